@@ -1,0 +1,243 @@
+/*
+ * knn.h -- C ABI of the MI355X (gfx950) k-nearest-neighbour graph library.
+ *
+ * The library builds k-NN graphs of an n x d point set resident in device
+ * memory: an exact brute-force path (tiled distance GEMM + top-k) and
+ * NNDescent (random or encoder-seeded init, sampled new/old local joins,
+ * bounded sorted list merges, stop on update count).  It is the graph stage
+ * the paper's dimensionality-reduction methods share (paper, section
+ * "GPU-Native k-NN via NNDescent"; the exact ranks of the embedding-quality
+ * section).
+ *
+ * Conventions for every entry point:
+ *  - Pointers named as device pointers must point to device memory of the
+ *    current HIP device; host pointers are marked "host".  The caller owns
+ *    every buffer passed in; scratch is allocated internally and released
+ *    before return.  Only knn_encoder objects are library-owned.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Every call is
+ *    blocking: the stream is synchronised before return.
+ *  - Errors are returned as knn_status (never thrown).  On error the outputs
+ *    are unspecified; knn_last_error() gives a thread-local message.
+ *  - Results: each output row is sorted by (squared distance, index)
+ *    ascending and never contains its own row index.  Duplicate points are
+ *    kept at distance 0.  Distances are ranked on squared Euclidean distance
+ *    and returned as Euclidean (KNN_OUT_L2) or squared (KNN_OUT_SQL2).
+ *  - Inputs holding NaN or Inf give unspecified results.
+ *  - Index arrays are int32: n must be below 2^31.
+ */
+#ifndef KNN_H_
+#define KNN_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t knn_status;
+enum {
+    KNN_OK = 0,
+    KNN_EINVAL = -1,   /* bad argument (size, pointer, enum) */
+    KNN_ENOMEM = -2,   /* device allocation failed or workspace limit exceeded */
+    KNN_EDEVICE = -3,  /* a HIP runtime call failed */
+    KNN_ENOTSUP = -4   /* valid request outside what is implemented (e.g. k > 64) */
+};
+
+/* element type of an input matrix */
+enum { KNN_F32 = 0, KNN_BF16 = 1, KNN_F16 = 2 };
+/* distance precision: FP32 throughout, or BF16 MFMA candidates + FP32 re-rank */
+enum { KNN_PREC_FP32 = 0, KNN_PREC_BF16 = 1 };
+/* returned distance kind */
+enum { KNN_OUT_L2 = 0, KNN_OUT_SQL2 = 1 };
+/* NNDescent initial lists */
+enum { KNN_INIT_RANDOM = 0, KNN_INIT_ENCODER = 1 };
+
+/* Largest k / re-rank width / working list size the kernels support. */
+#define KNN_MAX_K 64
+
+/* A row-major n x d matrix in device memory; row r starts at data + r*ld
+ * elements of `dtype`.  Requires n >= 1, d >= 1, ld >= d. */
+typedef struct {
+    const void* data;
+    int64_t n;
+    int32_t d;
+    int64_t ld;
+    int32_t dtype;
+} knn_matrix;
+
+const char* knn_status_str(knn_status s);
+/* Message of the last failing call on this thread ("" if none). */
+const char* knn_last_error(void);
+
+/*
+ * Exact k nearest neighbours of every row of X among the other rows of X
+ * (the exact pairwise-distance ranking of the paper's embedding-quality
+ * section, computed by tiled GEMM with the norm expansion of the paper's
+ * k-NN section, then re-ranked by direct differences).
+ *
+ *  precision  KNN_PREC_FP32: FP32 MFMA distances; KNN_PREC_BF16: BF16 MFMA
+ *             distances with FP32 accumulation.  Either way the best
+ *             `rerank_k` candidates per row are re-ranked with FP32
+ *             direct-difference distances, and FP32 rows whose candidate
+ *             set cannot be certified are recomputed exhaustively.
+ *  rerank_k   candidates kept per row before the re-rank, k <= rerank_k <=
+ *             KNN_MAX_K (0 = min(2k, KNN_MAX_K)).
+ *  out_idx    device, n x k int32.   out_dist  device, n x k float.
+ * Errors: KNN_EINVAL if n < 2, k < 1, k > n-1, d < 1, ld < d, n >= 2^31,
+ * a null pointer or an unknown enum; KNN_ENOTSUP if rerank_k > KNN_MAX_K.
+ */
+knn_status knn_exact(knn_matrix X, int32_t k, int32_t precision, int32_t rerank_k,
+                     int32_t out_kind, int32_t* out_idx, float* out_dist, void* stream);
+
+/*
+ * Exact k nearest rows of R for each row of Q (Q.d == R.d, same dtype).
+ * q_self (device, nullable, Q.n int32): row of R that query i must not
+ * return (-1: none).  out_idx / out_dist: device, Q.n x k.
+ * Errors as knn_exact, with k > R.n (or R.n - 1 when q_self is given)
+ * rejected.
+ */
+knn_status knn_exact_query(knn_matrix Q, knn_matrix R, const int32_t* q_self, int32_t k,
+                           int32_t precision, int32_t rerank_k, int32_t out_kind,
+                           int32_t* out_idx, float* out_dist, void* stream);
+
+typedef struct knn_encoder knn_encoder;
+
+/* NNDescent parameters (Dong, Charikar & Li 2011; the paper fixes the
+ * early-termination rate delta = 0.015). */
+typedef struct {
+    int32_t k;            /* neighbours returned, 1 <= k <= n-1 */
+    int32_t build_k;      /* working list size K_b, k <= K_b <= KNN_MAX_K (0: k, or 2k for BF16) */
+    int32_t max_iters;    /* iteration cap, >= 0 */
+    float sample_rate;    /* rho in (0, 1]: s = ceil(rho * K_b) new entries sampled per row */
+    float delta;          /* stop when updates < delta * n * K_b; >= 0 */
+    uint64_t seed;        /* all random choices are a function of (seed, iteration, row, slot) */
+    int32_t precision;    /* KNN_PREC_FP32 or KNN_PREC_BF16 (join on MFMA, FP32 re-rank at the end) */
+    int32_t out_kind;     /* KNN_OUT_L2 / KNN_OUT_SQL2 */
+    int32_t init_kind;    /* KNN_INIT_RANDOM or KNN_INIT_ENCODER */
+    const knn_encoder* encoder;  /* required for KNN_INIT_ENCODER */
+    int32_t proj_count;   /* encoder init: number of sorted projections P (0: 4) */
+    int32_t proj_window;  /* encoder init: neighbours taken on each side per order (0: 8) */
+    int32_t cand_slots;   /* hashed candidate slots per row and iteration (0: default) */
+    int32_t join_cap;     /* max candidates one join list sends to one member (0: default) */
+    int64_t workspace_limit_bytes; /* 0: no limit; else KNN_ENOMEM when scratch exceeds it */
+} knn_nnd_params;
+
+/* Fills the defaults: build_k 0, max_iters 20, rho 0.5, delta 0.015, seed 0,
+ * FP32, L2, random init, other knobs 0 (= library choice). */
+void knn_nnd_default_params(int32_t k, knn_nnd_params* p);
+
+#define KNN_MAX_ITERS_LOGGED 64
+typedef struct {
+    int32_t iters;                            /* iterations run in this call */
+    int32_t build_k;                          /* K_b actually used */
+    int64_t updates[KNN_MAX_ITERS_LOGGED];    /* list insertions per iteration */
+    int64_t emitted[KNN_MAX_ITERS_LOGGED];    /* candidates sent to the slot buffers */
+    uint64_t bytes_gathered;                  /* algorithmic row bytes gathered by local joins */
+    double ms_total, ms_init, ms_sample, ms_join, ms_merge, ms_final;
+} knn_nnd_stats;
+
+/*
+ * Approximate k-NN graph of X by NNDescent.
+ *  out_idx, out_dist  device, n x p->k.
+ *  state_idx, state_dist, state_flags  device, nullable, n x K_b each
+ *       (int32 / float squared distance / uint8 1 = new): the working lists
+ *       after the last iteration, which nndescent_refine can continue.
+ *  stats  host, nullable.
+ * Errors: KNN_EINVAL for bad sizes/params (k, K_b, rho, delta, max_iters,
+ * null pointers, encoder missing for KNN_INIT_ENCODER or of another d);
+ * KNN_ENOTSUP if K_b > KNN_MAX_K; KNN_ENOMEM as above.
+ */
+knn_status nndescent_build(knn_matrix X, const knn_nnd_params* p,
+                           int32_t* out_idx, float* out_dist,
+                           int32_t* state_idx, float* state_dist, uint8_t* state_flags,
+                           knn_nnd_stats* stats, void* stream);
+
+/*
+ * Continue NNDescent from given lists.
+ *  init_idx    device, n x init_k int32; entries that are -1, out of range,
+ *              equal to their row or repeated are replaced by random fill.
+ *  init_dist   device, nullable, n x init_k squared distances of those
+ *              entries (recomputed when NULL).
+ *  init_flags  device, nullable, n x init_k (1 = new; NULL = all new).
+ *  iter_offset first iteration number: the random stream continues there, so
+ *              build(a iters) then refine(b iters, iter_offset = a) from its
+ *              state reproduces build(a + b iters) bit for bit.
+ * init_k may differ from K_b (extra columns are dropped after sorting,
+ * missing ones are filled at random).  Outputs as nndescent_build.
+ */
+knn_status nndescent_refine(knn_matrix X, const knn_nnd_params* p,
+                            const int32_t* init_idx, const float* init_dist,
+                            const uint8_t* init_flags, int32_t init_k, int32_t iter_offset,
+                            int32_t* out_idx, float* out_dist,
+                            int32_t* state_idx, float* state_dist, uint8_t* state_flags,
+                            knn_nnd_stats* stats, void* stream);
+
+/* ----------------------------------------------------------------------
+ * Learned seeding: an MLP encoder d -> 64 -> 32 (ReLU hidden layer) whose
+ * embedding is projected on P seeded directions; the sorted orders give
+ * each point its window neighbours as initial candidates for NNDescent.
+ * ---------------------------------------------------------------------- */
+#define KNN_ENC_H1 64
+#define KNN_ENC_H2 32
+
+/* Creates an encoder for inputs of width d with He-uniform weights drawn
+ * from `seed` (W1: d x 64, b1: 64, W2: 64 x 32, b2: 32, row-major FP32). */
+knn_status knn_encoder_create(int32_t d, uint64_t seed, knn_encoder** enc);
+void knn_encoder_destroy(knn_encoder* enc);
+/* Copy the FP32 weights in / out (host buffers of the sizes above). */
+knn_status knn_encoder_set_weights(knn_encoder* enc, const float* W1, const float* b1,
+                                   const float* W2, const float* b2);
+knn_status knn_encoder_get_weights(const knn_encoder* enc, float* W1, float* b1,
+                                   float* W2, float* b2);
+
+/* Z = W2^T relu(W1^T x + b1) + b2 for every row of X; Z: device, n x 32 float.
+ * precision KNN_PREC_FP32 (FP32 FMA) or KNN_PREC_BF16 (BF16 MFMA, FP32 accumulate). */
+knn_status knn_encoder_embed(const knn_encoder* enc, knn_matrix X, int32_t precision,
+                             float* Z, void* stream);
+
+/*
+ * One triplet-loss forward/backward pass without updating the weights.
+ * rows: device, 3B int32 = [anchors; positives; negatives] (rows of X).
+ * loss = (1/B) sum max(0, margin + |za-zp|^2 - |za-zn|^2).
+ * grads: device, nullable, d*64 + 64 + 64*32 + 32 floats (gW1, gb1, gW2, gb2).
+ * loss_out: host.
+ */
+knn_status knn_encoder_grads(knn_encoder* enc, knn_matrix X, const int32_t* rows, int32_t B,
+                             float margin, float* loss_out, float* grads, void* stream);
+
+/* Adam settings for knn_encoder_train. */
+typedef struct {
+    int32_t steps;        /* optimisation steps */
+    int32_t batch;        /* triplets per step */
+    float lr, beta1, beta2, eps, margin;
+    uint64_t seed;        /* triplet sampling */
+} knn_train_params;
+
+void knn_train_default_params(knn_train_params* t);
+
+/*
+ * Train the encoder on X with its k-NN graph knn_idx (device, X.n x k):
+ * each triplet takes a uniform anchor, a uniform positive among its k
+ * neighbours and a uniform negative row; Adam on FP32 weights.
+ * loss_log: host, nullable, t->steps floats.
+ */
+knn_status knn_encoder_train(knn_encoder* enc, knn_matrix X, const int32_t* knn_idx, int32_t k,
+                             const knn_train_params* t, float* loss_log, void* stream);
+
+/*
+ * Seed lists from sorted projections: keys Z . dirs[p] (FP32), each point
+ * takes the w predecessors and successors in every order sorted by
+ * (key, index); candidates (self removed, duplicates merged) are ranked by
+ * FP32 squared input distance and the best K kept, sorted by (distance,
+ * index); rows with fewer than K candidates are padded with -1 / +inf.
+ *  Z     device, n x m float (m <= 64).   dirs  device, P x m float.
+ *  out_idx / out_dist  device, n x K.
+ */
+knn_status knn_proj_seed(knn_matrix X, const float* Z, int32_t m, const float* dirs,
+                         int32_t P, int32_t w, int32_t K, int32_t* out_idx, float* out_dist,
+                         void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KNN_H_ */

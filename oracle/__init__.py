@@ -1,0 +1,217 @@
+"""CPU oracle for the kNN-graph path -- TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg use
+this package.  The library never imports it, and it imports nothing from the
+library (inputs come from ``paper_2603_04035_amd.datagen`` in the callers).
+
+What it computes (the C part lives in ``knn_oracle.c``):
+
+* ``exact_knn`` / ``exact_query`` - the definition of the exact k nearest
+  neighbours (the paper ranks neighbours by exact pairwise Euclidean distance
+  in its embedding-quality section): fp64 direct-difference squared distances,
+  ordered by (distance, index), self excluded.
+* ``nndescent`` - sequential NNDescent of Dong, Charikar & Li (WWW 2011), the
+  algorithm of the paper's GPU-native k-NN section, with its delta = 0.015
+  early-termination rule.
+* ``round_bf16`` - FP32 -> BF16 round-to-nearest-even by bit definition.
+* ``mlp_forward`` / ``triplet_loss`` / ``mlp_backward`` / ``adam_step`` - the
+  seeding encoder (d -> 64 -> 32, ReLU) in fp64.
+* ``proj_seed`` - seed lists from sorted projections of an embedding.
+* ``recall_at_k`` / ``exact_parity`` - the comparators (``compare.py``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+from .compare import recall_at_k, index_recall, exact_parity, near_tie  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "knn_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+
+
+def build(verbose: bool = False) -> str:
+    """Compile knn_oracle.c with gcc (no fast-math: evaluation order is kept)."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+           "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", _LIB_PATH + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        build()
+    lib = C.CDLL(_LIB_PATH)
+    i64, i32, f64, u64 = C.c_int64, C.c_int, C.c_double, C.c_uint64
+    lib.oracle_exact_query.argtypes = [_dp, i64, i64, i32, _dp, i64, i64, C.c_void_p, i32, _ip, _dp]
+    lib.oracle_exact_query.restype = i32
+    lib.oracle_pair_d2.argtypes = [_dp, i64, i32, _ip, _ip, i64, _dp]
+    lib.oracle_pair_d2.restype = None
+    lib.oracle_nndescent.argtypes = [_dp, i64, i64, i32, i32, i32, f64, f64, u64, C.c_void_p,
+                                     _ip, _dp, C.POINTER(C.c_int), _ip]
+    lib.oracle_nndescent.restype = i32
+    lib.oracle_round_bf16.argtypes = [np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS"),
+                                      np.ctypeslib.ndpointer(dtype=np.uint16, flags="C_CONTIGUOUS"), i64]
+    lib.oracle_round_bf16.restype = None
+    lib.oracle_mlp_forward.argtypes = [_dp, i64, i64, i32, _dp, _dp, i32, _dp, _dp, i32, C.c_void_p, _dp]
+    lib.oracle_mlp_forward.restype = None
+    lib.oracle_triplet_loss.argtypes = [_dp, i64, i32, f64, C.c_void_p]
+    lib.oracle_triplet_loss.restype = f64
+    lib.oracle_mlp_backward.argtypes = [_dp, i64, i64, i32, _dp, _dp, i32, _dp, i32, _dp,
+                                        _dp, _dp, _dp, _dp]
+    lib.oracle_mlp_backward.restype = None
+    lib.oracle_adam_step.argtypes = [_dp, _dp, _dp, _dp, i64, f64, f64, f64, f64, i32]
+    lib.oracle_adam_step.restype = None
+    lib.oracle_proj_seed.argtypes = [_dp, i64, i64, i32, _dp, i32, _dp, i32, i32, i32, _ip, _dp]
+    lib.oracle_proj_seed.restype = i32
+    _lib = lib
+    return lib
+
+
+def _f64(a) -> np.ndarray:
+    """Exact upcast of the stored values (f16/bf16-as-f32/f32 -> f64)."""
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def exact_query(R, Q, k: int, q_self=None):
+    """k nearest rows of R for every row of Q: (idx int64, squared dist f64).
+
+    q_self[i] (optional) names a row of R that query i must not return.
+    """
+    R = _f64(R)
+    Q = _f64(Q)
+    if R.ndim != 2 or Q.ndim != 2 or R.shape[1] != Q.shape[1]:
+        raise ValueError("shape mismatch")
+    nq = Q.shape[0]
+    idx = np.empty((nq, k), dtype=np.int64)
+    d2 = np.empty((nq, k), dtype=np.float64)
+    qs = None
+    if q_self is not None:
+        qs_arr = np.ascontiguousarray(np.asarray(q_self, dtype=np.int64))
+        qs = qs_arr.ctypes.data_as(C.c_void_p)
+    rc = _load().oracle_exact_query(R, R.shape[0], R.shape[1], R.shape[1], Q, nq, Q.shape[1],
+                                    qs, k, idx, d2)
+    if rc != 0:
+        raise ValueError("oracle_exact_query: bad arguments")
+    return idx, d2
+
+
+def exact_knn(X, k: int, rows=None):
+    """Exact kNN of the rows of X among X itself (self excluded).
+
+    ``rows`` restricts the queries to a subset (sampled checks at full size).
+    """
+    X = _f64(X)
+    rows = np.arange(X.shape[0], dtype=np.int64) if rows is None else np.asarray(rows, np.int64)
+    return exact_query(X, X[rows], k, q_self=rows)
+
+
+def pair_d2(X, a, b) -> np.ndarray:
+    X = _f64(X)
+    a = np.ascontiguousarray(np.asarray(a, np.int64).ravel())
+    b = np.ascontiguousarray(np.asarray(b, np.int64).ravel())
+    out = np.empty(a.shape[0], dtype=np.float64)
+    _load().oracle_pair_d2(X, X.shape[1], X.shape[1], a, b, a.shape[0], out)
+    return out
+
+
+def nndescent(X, K: int, max_iters: int = 10, rho: float = 0.5, delta: float = 0.015,
+              seed: int = 0, init_idx=None):
+    """Sequential NNDescent; returns (idx n x K, squared dist, iters, updates)."""
+    X = _f64(X)
+    n, d = X.shape
+    idx = np.empty((n, K), dtype=np.int64)
+    d2 = np.empty((n, K), dtype=np.float64)
+    iters = C.c_int(0)
+    upd = np.zeros(max(1, max_iters), dtype=np.int64)
+    ini = None
+    if init_idx is not None:
+        ini_arr = np.ascontiguousarray(np.asarray(init_idx, dtype=np.int64))
+        if ini_arr.shape != (n, K):
+            raise ValueError("init_idx must be n x K")
+        ini = ini_arr.ctypes.data_as(C.c_void_p)
+    rc = _load().oracle_nndescent(X, n, d, d, K, max_iters, float(rho), float(delta),
+                                  int(seed) & ((1 << 64) - 1), ini, idx, d2,
+                                  C.byref(iters), upd)
+    if rc != 0:
+        raise ValueError("oracle_nndescent: bad arguments")
+    return idx, d2, iters.value, upd[:iters.value].copy()
+
+
+def round_bf16(a) -> np.ndarray:
+    """FP32 -> BF16 (RNE) bit patterns as uint16."""
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    out = np.empty(a.shape, dtype=np.uint16)
+    _load().oracle_round_bf16(a.ravel(), out.ravel(), a.size)
+    return out
+
+
+def bf16_to_f64(bits) -> np.ndarray:
+    b = np.asarray(bits, dtype=np.uint16).astype(np.uint32) << 16
+    return b.view(np.float32).astype(np.float64)
+
+
+def mlp_forward(X, W1, b1, W2, b2, want_hidden: bool = False):
+    X, W1, b1, W2, b2 = map(_f64, (X, W1, b1, W2, b2))
+    m, d = X.shape
+    h1, h2 = W1.shape[1], W2.shape[1]
+    Z = np.empty((m, h2))
+    H = np.empty((m, h1)) if want_hidden else None
+    _load().oracle_mlp_forward(X, m, d, d, W1, b1, h1, W2, b2, h2,
+                               H.ctypes.data_as(C.c_void_p) if H is not None else None, Z)
+    return (Z, H) if want_hidden else Z
+
+
+def triplet_loss(Z, B: int, margin: float = 1.0, want_grad: bool = True):
+    Z = _f64(Z)
+    dZ = np.zeros_like(Z) if want_grad else None
+    loss = _load().oracle_triplet_loss(Z, B, Z.shape[1], float(margin),
+                                       dZ.ctypes.data_as(C.c_void_p) if dZ is not None else None)
+    return (loss, dZ) if want_grad else loss
+
+
+def mlp_backward(X, W1, b1, W2, dZ):
+    X, W1, b1, W2, dZ = map(_f64, (X, W1, b1, W2, dZ))
+    m, d = X.shape
+    h1, h2 = W1.shape[1], W2.shape[1]
+    gW1, gb1 = np.empty((d, h1)), np.empty(h1)
+    gW2, gb2 = np.empty((h1, h2)), np.empty(h2)
+    _load().oracle_mlp_backward(X, m, d, d, W1, b1, h1, W2, h2, dZ, gW1, gb1, gW2, gb2)
+    return gW1, gb1, gW2, gb2
+
+
+def adam_step(w, g, m, v, t: int, lr: float = 1e-3, beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8):
+    """In-place Adam step on fp64 arrays w, m, v given gradient g."""
+    for a in (w, m, v):
+        if a.dtype != np.float64 or not a.flags.c_contiguous:
+            raise ValueError("w, m, v must be C-contiguous float64")
+    g = _f64(g)
+    _load().oracle_adam_step(w.reshape(-1), g.reshape(-1), m.reshape(-1), v.reshape(-1),
+                             w.size, lr, beta1, beta2, eps, int(t))
+
+
+def proj_seed(X, Z, dirs, w: int, K: int):
+    """Sorted-projection seed lists: (idx n x K with -1 pads, squared dist)."""
+    X, Z, dirs = _f64(X), _f64(Z), _f64(dirs)
+    n, d = X.shape
+    idx = np.empty((n, K), dtype=np.int64)
+    d2 = np.empty((n, K), dtype=np.float64)
+    rc = _load().oracle_proj_seed(X, n, d, d, Z, Z.shape[1], dirs, dirs.shape[0], w, K, idx, d2)
+    if rc != 0:
+        raise ValueError("oracle_proj_seed: bad arguments")
+    return idx, d2

@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""kNN-graph build benchmark on one MI355X.
+
+Workload (default): n = 1,000,000 points, d = 50, FP32, a 50-component
+Gaussian mixture with anisotropic covariances (eigenvalues log-uniform on
+[0.1, 10]), k = 15.  One step = one blocking nndescent_build call on data
+already resident in HBM (init, every iteration, final re-rank).  Steps use
+algorithm seeds 0..steps-1 after `warmup` untimed calls.
+
+Reported: points/s = n * steps / wall time of the timed steps, recall@15 of
+the last step's graph on 10,000 sampled rows against the GPU exact path
+(knn_exact_query, parity-tested against the CPU oracle), the roofline of the
+dominant kernel (the local join: algorithmic bytes / its HIP-event time,
+both accumulated by the library over the timed steps), and the CPU oracle's
+sequential NNDescent on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# NNDescent settings of the two forms (K_b, rho, caps); delta is the paper's 0.015.
+FORMS = {
+    "fp32": dict(precision="fp32", build_k=24, sample_rate=0.5, max_iters=30, delta=0.015,
+                 join_cap=8, cand_slots=32),
+}
+
+CONFIGS = {
+    "gmm1m": dict(n=1_000_000, d=50, desc="1,000,000 x 50 FP32, 50-component anisotropic GMM, k=15"),
+    "pixel70k": dict(n=70_000, d=784, desc="70,000 x 784 FP32 pixel-like (10 clusters, 1/255 levels), k=15"),
+}
+
+
+def make_data(config: str):
+    from paper_2603_04035_amd import datagen
+    c = CONFIGS[config]
+    if config == "gmm1m":
+        return datagen.gmm_anisotropic(n=c["n"], d=c["d"], comps=50, seed=0)
+    return datagen.pixel_like(n=c["n"], seed=0)
+
+
+def recall_gpu(X, G, D, rows, k):
+    """Tie-aware recall@k of the graph rows against the GPU exact path."""
+    import torch
+    import paper_2603_04035_amd as knn
+    rows_t = torch.as_tensor(rows, dtype=torch.int64, device=X.device)
+    eidx, edist = knn.knn_exact_query(X[rows_t].contiguous(), X, k, q_self=rows_t.to(torch.int32))
+    kth = edist[:, k - 1:k].double() * (1.0 + 1e-5)
+    gd = D[rows_t, :k].double()
+    hits = (gd <= kth).sum(dim=1).clamp(max=k)
+    return float(hits.sum().item() / (len(rows) * k))
+
+
+def cpu_baseline(Xnp, k, form, sample_n):
+    """The CPU oracle's sequential NNDescent on the first sample_n rows."""
+    import oracle
+    sub = Xnp[:sample_n]
+    p = FORMS[form]
+    t0 = time.perf_counter()
+    oracle.nndescent(sub, p["build_k"], max_iters=p["max_iters"], rho=p["sample_rate"],
+                     delta=p["delta"], seed=0)
+    dt = time.perf_counter() - t0
+    return {"value": sample_n / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"sequential NNDescent (K={p['build_k']}, rho={p['sample_rate']}, "
+                      f"delta={p['delta']}) on the first {sample_n} rows of the same workload, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="gmm1m", choices=sorted(CONFIGS))
+    ap.add_argument("--form", default="fp32", choices=sorted(FORMS))
+    ap.add_argument("--k", type=int, default=15)
+    ap.add_argument("--recall-rows", type=int, default=10000)
+    ap.add_argument("--cpu-sample", type=int, default=100_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the kNN graph build here runs on a single device; "
+              "multi-GPU runs are not part of this build (see DESIGN.md for how it would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2603_04035_amd as knn
+    from paper_2603_04035_amd import datagen
+
+    k = args.k
+    Xnp = make_data(args.config)
+    n, d = Xnp.shape
+    X = torch.from_numpy(Xnp).to("cuda")
+    p = dict(FORMS[args.form])
+    torch.cuda.synchronize()
+
+    for w in range(args.warmup):
+        knn.nndescent_build(X, k, seed=1000 + w, **p)
+    torch.cuda.synchronize()
+
+    stats = []
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        G, D, st = knn.nndescent_build(X, k, seed=s, **p)
+        stats.append(st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    ms_per_step = 1000.0 * wall / args.steps
+    value = n * args.steps / wall
+
+    rows = datagen.sample_queries(n, args.recall_rows, seed=2)
+    recall = recall_gpu(X, G, D, rows, k)
+
+    # local-join roofline: algorithmic bytes per launch / HIP-event time per launch
+    K = stats[-1]["build_k"]
+    srate = p["sample_rate"]
+    s_ = int(np.ceil(srate * K))
+    rb = 4
+    launches = sum(st["iters"] for st in stats)
+    gathered_rows = sum(st["bytes_gathered"] for st in stats) / (d * rb)
+    emitted = sum(sum(st["emitted"]) for st in stats)
+    list_bytes = launches * n * (4 * s_ + 4 * K + 2 * 16 * s_)   # new_f, old_f, reverse slots read+reset
+    alg_bytes = gathered_rows * (d * rb + 8) + list_bytes + 8 * emitted
+    join_ms = sum(st["ms_join"] for st in stats)
+    achieved = alg_bytes / (join_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "nnd_join_f32_kernel", "launches": launches,
+                "alg_bytes_per_launch": int(alg_bytes / max(launches, 1)),
+                "ms_per_launch": round(join_ms / max(launches, 1), 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
+        cpu = cpu_baseline(Xnp, k, args.form, min(args.cpu_sample, n))
+
+    last = stats[-1]
+    out = {
+        "metric": "kNN graph build points/sec at recall@15>=0.98 (NNDescent)",
+        "value": round(value, 1), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.form == "fp32" else "bf16",
+        "data": "synthetic",
+        "config": {"workload": CONFIGS[args.config]["desc"], "form": args.form, "k": k,
+                   "build_k": K, "sample_rate": srate, "delta": p["delta"],
+                   "join_cap": p.get("join_cap"), "cand_slots": p.get("cand_slots")},
+        "recall_at_15": round(recall, 5), "recall_ok": recall >= 0.98,
+        "iters": last["iters"], "ms_breakdown": {kk: round(last[kk], 3) for kk in
+                                                 ("ms_init", "ms_sample", "ms_join", "ms_merge", "ms_final", "ms_total")},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -53,7 +53,7 @@ enum { KNN_OUT_L2 = 0, KNN_OUT_SQL2 = 1 };
 enum { KNN_INIT_RANDOM = 0, KNN_INIT_ENCODER = 1 };
 
 /* Largest k / re-rank width / working list size the kernels support. */
-#define KNN_MAX_K 64
+#define KNN_MAX_K 32
 
 /* A row-major n x d matrix in device memory; row r starts at data + r*ld
  * elements of `dtype`.  Requires n >= 1, d >= 1, ld >= d. */
@@ -117,7 +117,7 @@ typedef struct {
     const knn_encoder* encoder;  /* required for KNN_INIT_ENCODER */
     int32_t proj_count;   /* encoder init: number of sorted projections P (0: 4) */
     int32_t proj_window;  /* encoder init: neighbours taken on each side per order (0: 8) */
-    int32_t cand_slots;   /* hashed candidate slots per row and iteration (0: default) */
+    int32_t cand_slots;   /* hashed candidate slots per row and iteration, <= 64 - K_b (0: 32) */
     int32_t join_cap;     /* max candidates one join list sends to one member (0: default) */
     int64_t workspace_limit_bytes; /* 0: no limit; else KNN_ENOMEM when scratch exceeds it */
 } knn_nnd_params;
@@ -134,6 +134,7 @@ typedef struct {
     int64_t emitted[KNN_MAX_ITERS_LOGGED];    /* candidates sent to the slot buffers */
     uint64_t bytes_gathered;                  /* algorithmic row bytes gathered by local joins */
     double ms_total, ms_init, ms_sample, ms_join, ms_merge, ms_final;
+    float ms_join_iter[KNN_MAX_ITERS_LOGGED]; /* local-join kernel time per iteration */
 } knn_nnd_stats;
 
 /*

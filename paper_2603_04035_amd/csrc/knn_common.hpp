@@ -1,0 +1,312 @@
+// Shared device and host helpers of the gfx950 kNN library.
+//
+// Keys.  A candidate neighbour is a 64-bit key (float bits of the squared
+// distance << 32) | index.  Squared distances are clamped to >= +0, and the
+// bit patterns of non-negative floats order like unsigned integers, so the
+// unsigned order of keys is the (distance, index) order the results use.
+//
+// Random numbers.  Every random choice is a pure function of
+// (seed, stream tag, iteration, row, slot) through a counter-based hash built
+// from the splitmix64 finaliser (Steele, Lea & Flood, OOPSLA 2014), so runs
+// are reproducible and a build can be resumed bit for bit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/knn.h"
+
+namespace knn {
+
+// ------------------------------------------------------------------ keys
+
+constexpr uint64_t kEmptyList = 0x7F800000FFFFFFFFull;  // +inf distance, index ~0
+constexpr uint64_t kEmptyCand = ~0ull;                   // above every list key
+
+__device__ inline uint64_t make_key(float d2, uint32_t idx)
+{
+    d2 = d2 > 0.0f ? d2 : 0.0f;  // also maps -0 and NaN to +0
+    return ((uint64_t)__float_as_uint(d2) << 32) | (uint64_t)idx;
+}
+__device__ inline float key_d2(uint64_t k) { return __uint_as_float((uint32_t)(k >> 32)); }
+__device__ inline uint32_t key_idx(uint64_t k) { return (uint32_t)k; }
+__device__ inline bool key_valid(uint64_t k) { return (uint32_t)k != 0xFFFFFFFFu; }
+
+// ------------------------------------------------------------------ RNG
+
+__host__ __device__ inline uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Hash of a tuple of counters: each word is absorbed with a distinct odd
+// multiplier before a full mix, so (a, b) and (b, a) differ.
+__host__ __device__ inline uint64_t hash4(uint64_t seed, uint64_t a, uint64_t b, uint64_t c)
+{
+    uint64_t h = mix64(seed + 0x9E3779B97F4A7C15ull);
+    h = mix64(h ^ (a * 0xD6E8FEB86659FD93ull));
+    h = mix64(h ^ (b * 0xA0761D6478BD642Full));
+    h = mix64(h ^ (c * 0xE7037ED1A0B428DBull));
+    return h;
+}
+
+// Uniform integer in [0, m) from 64 random bits (multiply-high reduction).
+__host__ __device__ inline uint32_t bounded(uint64_t r, uint32_t m)
+{
+    return (uint32_t)(((r >> 32) * (uint64_t)m) >> 32);
+}
+
+// Stream tags keep independent random decisions apart.
+enum : uint64_t {
+    kTagInit = 1, kTagSample = 2, kTagRevNew = 3, kTagRevOld = 4, kTagSlot = 5,
+    kTagRevSlot = 6, kTagTriplet = 7, kTagDirs = 8, kTagWeights = 9
+};
+
+// ------------------------------------------------------------------ waves
+
+__device__ inline int lane_id() { return (int)__lane_id(); }
+
+__device__ inline uint32_t shfl_u32(uint32_t v, int src)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
+}
+__device__ inline uint64_t shfl_u64(uint64_t v, int src)
+{
+    uint32_t lo = shfl_u32((uint32_t)v, src);
+    uint32_t hi = shfl_u32((uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline float shfl_f32(float v, int src)
+{
+    return __uint_as_float(shfl_u32(__float_as_uint(v), src));
+}
+// Exchange with lane ^ j inside the wave without an LDS round trip:
+// j = 1, 2 by DPP quad permutes; j = 4, 8 by DPP row shifts (each lane keeps
+// the direction that stays inside its 16-lane row); j = 16, 32 by the gfx950
+// permlane swaps (rows 2r+1 <-> 2r, and the two 32-lane halves).  j must be a
+// compile-time constant after unrolling.
+__device__ __attribute__((always_inline)) inline uint32_t xor_u32(uint32_t v, int j)
+{
+    const int lane = lane_id();
+    if (j == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+    if (j == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+    if (j == 4) {
+        uint32_t a = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x104, 0xF, 0xF, false);
+        uint32_t b = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);
+        return (lane & 4) ? b : a;
+    }
+    if (j == 8) {
+        uint32_t a = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x108, 0xF, 0xF, false);
+        uint32_t b = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);
+        return (lane & 8) ? b : a;
+    }
+    if (j == 16) {
+        auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane & 16) ? p[0] : p[1];
+    }
+    if (j == 32) {
+        auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (lane & 32) ? p[0] : p[1];
+    }
+    return shfl_u32(v, lane ^ j);
+}
+__device__ __attribute__((always_inline)) inline uint64_t shfl_xor_u64(uint64_t v, int j)
+{
+    uint32_t lo = xor_u32((uint32_t)v, j), hi = xor_u32((uint32_t)(v >> 32), j);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __attribute__((always_inline)) inline float xor_f32(float v, int j)
+{
+    return __uint_as_float(xor_u32(__float_as_uint(v), j));
+}
+// Value of v in lane l (l uniform across the wave): v_readlane, no LDS.
+__device__ __attribute__((always_inline)) inline uint32_t bcast_u32(uint32_t v, int l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __attribute__((always_inline)) inline uint64_t bcast_u64(uint64_t v, int l)
+{
+    uint32_t lo = bcast_u32((uint32_t)v, l), hi = bcast_u32((uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
+__device__ inline uint64_t umax64(uint64_t a, uint64_t b) { return a < b ? b : a; }
+
+// Ascending bitonic sort of independent segments of W lanes (W = 2..64,
+// power of two), one key per lane.
+template <int W>
+__device__ inline uint64_t seg_sort(uint64_t key)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 2; k <= W; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            uint64_t o = shfl_xor_u64(key, j);
+            bool up = (k == W) ? true : ((lane & k) == 0);
+            bool lower = (lane & j) == 0;
+            key = (lower == up) ? umin64(key, o) : umax64(key, o);
+        }
+    }
+    return key;
+}
+
+// Sort a bitonic sequence held in segments of W lanes into ascending order.
+template <int W>
+__device__ inline uint64_t seg_bitonic_merge(uint64_t key)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int j = W >> 1; j > 0; j >>= 1) {
+        uint64_t o = shfl_xor_u64(key, j);
+        key = ((lane & j) == 0) ? umin64(key, o) : umax64(key, o);
+    }
+    return key;
+}
+
+// Keep the W smallest of the union of two ascending W-lane segments
+// (list, cand) as an ascending segment: min(list[i], cand[W-1-i]) is bitonic
+// and holds exactly those keys.
+template <int W>
+__device__ inline uint64_t seg_merge_sorted(uint64_t list, uint64_t cand_sorted)
+{
+    uint64_t rev = shfl_xor_u64(cand_sorted, W - 1);
+    return seg_bitonic_merge<W>(umin64(list, rev));
+}
+
+// Ascending bitonic sort of 128 keys held two per lane: element e = r * 64 + lane.
+__device__ inline void sort128(uint64_t& k0, uint64_t& k1)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 2; k <= 128; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j == 64) {
+                // partner is the other register of the same lane; direction by e & k
+                // (k = 128 here: whole array ascending)
+                uint64_t mn = umin64(k0, k1), mx = umax64(k0, k1);
+                k0 = mn;
+                k1 = mx;
+            } else {
+                uint64_t o0 = shfl_xor_u64(k0, j);
+                uint64_t o1 = shfl_xor_u64(k1, j);
+                bool lower = (lane & j) == 0;
+                // element index e = r*64 + lane; ascending iff (e & k) == 0
+                bool up0 = (k == 128) ? true : ((lane & k) == 0);
+                bool up1 = (k == 128) ? true : (((64 + lane) & k) == 0);
+                k0 = (lower == up0) ? umin64(k0, o0) : umax64(k0, o0);
+                k1 = (lower == up1) ? umin64(k1, o1) : umax64(k1, o1);
+            }
+        }
+    }
+}
+
+__device__ inline uint64_t ballot(bool p) { return __ballot(p); }
+__device__ inline int popc64(uint64_t m) { return __popcll(m); }
+// number of set bits of m in lanes below this one
+__device__ inline int rank_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ inline float wave_sum16(float v)
+{
+    // tree reduction inside aligned groups of 16 lanes (fixed order)
+    v += xor_f32(v, 8);
+    v += xor_f32(v, 4);
+    v += xor_f32(v, 2);
+    v += xor_f32(v, 1);
+    return v;
+}
+
+// ------------------------------------------------------------------ inputs
+
+template <int DT> struct elem;
+template <> struct elem<KNN_F32> {
+    using T = float;
+    __device__ static float ld(const void* p, int64_t i) { return ((const float*)p)[i]; }
+};
+template <> struct elem<KNN_BF16> {
+    using T = uint16_t;
+    __device__ static float ld(const void* p, int64_t i)
+    {
+        return __uint_as_float((uint32_t)((const uint16_t*)p)[i] << 16);
+    }
+};
+template <> struct elem<KNN_F16> {
+    using T = _Float16;
+    __device__ static float ld(const void* p, int64_t i) { return (float)((const _Float16*)p)[i]; }
+};
+
+// FP32 -> BF16 round to nearest even (inputs are finite).
+__device__ inline uint16_t f32_to_bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Canonical FP32 direct-difference squared distance between row a of A and
+// row b of B, computed by an aligned group of 16 lanes: lane g of the group
+// accumulates t = g, g + 16, g + 32, ... in order, then a fixed tree sum.
+// Every lane of the group returns the same value; the value does not depend
+// on which group computes it, and swapping a and b gives the same bits.
+template <int DT>
+__device__ inline float dist_g16(const void* A, int64_t a_off, const void* B, int64_t b_off,
+                                 int d, bool active)
+{
+    const int g = lane_id() & 15;
+    float s = 0.0f;
+    if (active) {
+        for (int t = g; t < d; t += 16) {
+            float e = elem<DT>::ld(A, a_off + t) - elem<DT>::ld(B, b_off + t);
+            s = fmaf(e, e, s);
+        }
+    }
+    return wave_sum16(s);
+}
+
+// ------------------------------------------------------------------ host
+
+void set_error(const std::string& msg);
+knn_status fail(knn_status s, const std::string& msg);
+
+#define KNN_HIP(call)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::knn::fail(KNN_EDEVICE, std::string(#call) + ": " +               \
+                                                hipGetErrorString(e_));                \
+    } while (0)
+
+// Scratch allocations for one call, released (stream-ordered) on scope exit.
+class Workspace {
+public:
+    Workspace(hipStream_t s, int64_t limit) : stream_(s), limit_(limit) {}
+    ~Workspace();
+    // returns KNN_OK or KNN_ENOMEM / KNN_EDEVICE
+    knn_status alloc(void** p, size_t bytes);
+    template <typename T>
+    knn_status alloc(T** p, size_t count) { return alloc((void**)p, count * sizeof(T)); }
+    size_t used() const { return used_; }
+
+private:
+    hipStream_t stream_;
+    int64_t limit_;
+    size_t used_ = 0;
+    void* ptrs_[64];
+    int nptr_ = 0;
+};
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+knn_status check_matrix(const knn_matrix& X, const char* name);
+
+}  // namespace knn

@@ -1,0 +1,492 @@
+// Exact k nearest neighbours: tiled MFMA distance GEMM + fused top-k'.
+//
+// The paper ranks its quality metrics by exact pairwise Euclidean distances
+// computed by chunked matrix multiplication, with the norm expansion
+// |a - b|^2 = |a|^2 + |b|^2 - 2 a.b of its k-NN section.  Here:
+//
+//  1. stage: inputs are copied into a zero-padded, 128-byte-aligned layout
+//     (FP32, or BF16 rounded to nearest even), with FP32 row norms of the
+//     staged values and the largest reference norm;
+//  2. tile: each workgroup owns 128 query rows and streams 128-row reference
+//     tiles through LDS; MFMA (32x32x2 FP32, or 32x32x16 BF16 with FP32
+//     accumulation) produces dot products, the epilogue forms squared
+//     distances and keeps, per query row, the best k' candidates in
+//     registers with wave-wide bitonic merges (threshold-gated, so merges
+//     are rare once lists fill).  The reference set can be split across
+//     workgroups to fill the chip; each split keeps its own lists;
+//  3. merge + re-rank: the splits' lists are merged, the best k' by GEMM
+//     distance are re-ranked with FP32 direct differences on the original
+//     input values, and the best k kept.  In FP32 precision a row is
+//     certified when its k-th re-ranked distance is below the k'-th GEMM
+//     distance minus the worst-case GEMM error bound; other rows are
+//  4. recomputed exhaustively with direct differences.
+#include "knn_common.hpp"
+
+namespace knn {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kTileRows = 128;    // queries per workgroup and references per tile
+constexpr int kListW = 32;        // list width per query row (k' <= 32)
+
+// ------------------------------------------------------------------ stage
+
+// One wave per row: padded copy (zeros beyond d) and the FP32 squared norm of
+// the stored values.  maxnorm receives the largest norm's float bits.
+template <int DT, bool TO_BF16>
+__global__ __launch_bounds__(256) void stage_kernel(const void* __restrict__ X, int64_t n, int d,
+                                                    int64_t ld, void* __restrict__ Xs, int ldp,
+                                                    float* __restrict__ norms,
+                                                    unsigned* __restrict__ maxnorm)
+{
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    float s = 0.0f;
+    for (int t = lane; t < ldp; t += 64) {
+        float v = t < d ? elem<DT>::ld(X, row * ld + t) : 0.0f;
+        if (TO_BF16) {
+            uint16_t b = f32_to_bf16_rne(v);
+            ((uint16_t*)Xs)[row * ldp + t] = b;
+            v = __uint_as_float((uint32_t)b << 16);
+        } else {
+            ((float*)Xs)[row * ldp + t] = v;
+        }
+        s = fmaf(v, v, s);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += xor_f32(s, o);
+    if (lane == 0) {
+        norms[row] = s;
+        if (maxnorm) atomicMax(maxnorm, __float_as_uint(s));
+    }
+}
+
+// ------------------------------------------------------------------ tile
+
+template <bool BF>
+struct TileCfg {
+    using E = float;
+    static constexpr int KC = 32;    // elements per K chunk (128 bytes per row)
+    static constexpr int LROW = 36;  // LDS row stride in elements (144 bytes)
+};
+template <>
+struct TileCfg<true> {
+    using E = uint16_t;
+    static constexpr int KC = 64;
+    static constexpr int LROW = 72;
+};
+
+// Output D of a 32x32 MFMA: lane l, accumulator v holds row
+// 8*(v/4) + 4*(l/32) + v%4 and column l%32 of the 32x32 block.
+__device__ inline int mfma_row(int v, int half) { return 8 * (v >> 2) + 4 * half + (v & 3); }
+
+template <bool BF>
+__global__ __launch_bounds__(256, 2) void exact_tile_kernel(
+    const void* __restrict__ Qs, const float* __restrict__ qn, int64_t nq,
+    const void* __restrict__ Rs, const float* __restrict__ rn, int64_t nr, int ldp,
+    const int32_t* __restrict__ q_self, int self_mode, int kp, int64_t split_len, int S,
+    uint64_t* __restrict__ part)
+{
+    using C = TileCfg<BF>;
+    using E = typename C::E;
+    constexpr int KC = C::KC, LROW = C::LROW, PER = KC / 2;
+    __shared__ __attribute__((aligned(16))) E As[kTileRows * LROW];
+    __shared__ __attribute__((aligned(16))) E Bs[kTileRows * LROW];
+    __shared__ float sqn[kTileRows];
+    __shared__ int64_t sself[kTileRows];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, h = lane >> 5, c = lane & 31;
+    const int64_t q0 = (int64_t)blockIdx.x * kTileRows;
+    const int s = blockIdx.y;
+    const int64_t rbeg = (int64_t)s * split_len;
+    const int64_t rend = rbeg + split_len < nr ? rbeg + split_len : nr;
+
+    if (tid < kTileRows) {
+        int64_t qr = q0 + tid;
+        sqn[tid] = qr < nq ? qn[qr] : 0.0f;
+        int64_t sf = -1;
+        if (qr < nq) sf = self_mode == 1 ? qr : (self_mode == 2 ? (int64_t)q_self[qr] : -1);
+        sself[tid] = sf;
+    }
+
+    uint64_t list[16];
+    float thr[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        list[v] = kEmptyList;
+        thr[v] = __builtin_inff();
+    }
+
+    const E* Qe = (const E*)Qs;
+    const E* Re = (const E*)Rs;
+    for (int64_t rt = rbeg; rt < rend; rt += kTileRows) {
+        f32x16 acc[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[b][v] = 0.0f;
+
+        for (int k0 = 0; k0 < ldp; k0 += KC) {
+            __syncthreads();
+            {
+                const int r = tid >> 1, part_h = tid & 1;
+                int64_t qr = q0 + r < nq ? q0 + r : nq - 1;
+                int64_t rr = rt + r < rend ? rt + r : rend - 1;
+                const uint4* qsrc = (const uint4*)(Qe + qr * ldp + k0 + part_h * PER);
+                const uint4* rsrc = (const uint4*)(Re + rr * ldp + k0 + part_h * PER);
+                uint4* adst = (uint4*)(As + r * LROW + part_h * PER);
+                uint4* bdst = (uint4*)(Bs + r * LROW + part_h * PER);
+                uint4 qa[4], rb[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    qa[i] = qsrc[i];
+                    rb[i] = rsrc[i];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    adst[i] = qa[i];
+                    bdst[i] = rb[i];
+                }
+            }
+            __syncthreads();
+            // K permutation: half h of the wave supplies chunk columns
+            // h*PER .. h*PER+PER-1, the same for A and B, so every column
+            // enters the dot product exactly once.
+            const uint4* ap = (const uint4*)(As + (w * 32 + c) * LROW + h * PER);
+            uint4 a4[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a4[i] = ap[i];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const uint4* bp = (const uint4*)(Bs + (b * 32 + c) * LROW + h * PER);
+                uint4 b4[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) b4[i] = bp[i];
+                if constexpr (BF) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        bf16x8 av = __builtin_bit_cast(bf16x8, a4[i]);
+                        bf16x8 bv = __builtin_bit_cast(bf16x8, b4[i]);
+                        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[b], 0, 0, 0);
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        f32x4 av = __builtin_bit_cast(f32x4, a4[i]);
+                        f32x4 bv = __builtin_bit_cast(f32x4, b4[i]);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[e], bv[e], acc[b], 0, 0, 0);
+                    }
+                }
+            }
+        }
+
+        // epilogue: distances, threshold gate, wave-bitonic list merges
+        for (int blk = 0; blk < 4; ++blk) {
+            f32x16 cur = blk == 0 ? acc[0] : (blk == 1 ? acc[1] : (blk == 2 ? acc[2] : acc[3]));
+            const int64_t j = rt + blk * 32 + c;
+            const bool jv = j < rend;
+            const float rnj = jv ? rn[j] : 0.0f;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int lr = w * 32 + mfma_row(v, h);
+                float d2 = sqn[lr] + rnj - 2.0f * cur[v];
+                d2 = d2 > 0.0f ? d2 : 0.0f;
+                const bool ok = jv && (q0 + lr < nq) && (j != sself[lr]) && d2 <= thr[v];
+                if (ballot(ok)) {
+                    uint64_t ck = ok ? make_key(d2, (uint32_t)j) : kEmptyCand;
+                    ck = seg_sort<32>(ck);
+                    list[v] = seg_merge_sorted<32>(list[v], ck);
+                    const uint64_t t0 = bcast_u64(list[v], kp - 1), t1 = bcast_u64(list[v], 32 + kp - 1);
+                    thr[v] = key_d2(h ? t1 : t0);
+                }
+            }
+        }
+    }
+
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int64_t row = q0 + w * 32 + mfma_row(v, h);
+        if (row < nq) part[(row * S + s) * kListW + c] = list[v];
+    }
+}
+
+// ------------------------------------------------------------ merge/rerank
+
+// One wave per query row.  Merges the S split lists (<= 4 x 32 keys), keeps
+// the best kp by GEMM distance, re-ranks them with the canonical FP32
+// direct-difference distance on the original inputs and writes the best k.
+template <int DT>
+__global__ __launch_bounds__(256) void merge_rerank_kernel(
+    const uint64_t* __restrict__ part, int S, int64_t nq, int kp, int k,
+    const void* __restrict__ Q, int64_t ldq, const void* __restrict__ R, int64_t ldr, int d,
+    const float* __restrict__ qn, const unsigned* __restrict__ rmax_bits, float err_coef,
+    float edir, int certify, int out_kind, int32_t* __restrict__ out_idx,
+    float* __restrict__ out_dist, int32_t* __restrict__ fb_rows, int* __restrict__ fb_count)
+{
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= nq) return;
+    uint64_t k0 = kEmptyCand, k1 = kEmptyCand;
+    const int sp = lane >> 5;
+    if (S <= 2) {
+        if (sp < S) k0 = part[(row * S + sp) * kListW + (lane & 31)];
+        k0 = seg_sort<64>(k0);
+    } else {
+        k0 = part[(row * S + sp) * kListW + (lane & 31)];
+        if (sp + 2 < S) k1 = part[(row * S + sp + 2) * kListW + (lane & 31)];
+        sort128(k0, k1);
+    }
+    const uint64_t ck = lane < kp ? k0 : kEmptyCand;
+    const bool cvalid = lane < kp && key_valid(ck);
+    const int nvalid = popc64(ballot(cvalid));
+    const float T = key_d2(bcast_u64(k0, kp - 1));
+    const uint32_t myidx = key_idx(ck);
+
+    float dd = 0.0f;
+    for (int base = 0; base < kp; base += 4) {
+        const int ci = base + (lane >> 4);
+        const uint32_t cj = shfl_u32(myidx, ci < 64 ? ci : 0);
+        const bool act = ci < kp && cj != 0xFFFFFFFFu;
+        const float v = dist_g16<DT>(Q, row * ldq, R, (int64_t)cj * ldr, d, act);
+        const float got = shfl_f32(v, ((lane - base) & 3) * 16);
+        if (lane >= base && lane < base + 4) dd = got;
+    }
+    uint64_t nk = cvalid ? make_key(dd, myidx) : kEmptyCand;
+    nk = seg_sort<64>(nk);
+    if (lane < k) {
+        const float d2 = key_d2(nk);
+        out_idx[row * k + lane] = (int32_t)key_idx(nk);
+        out_dist[row * k + lane] = out_kind == KNN_OUT_L2 ? sqrtf(d2) : d2;
+    }
+    if (certify) {
+        const float Dk = key_d2(bcast_u64(nk, k - 1));
+        const float qa = sqrtf(qn[row]);
+        const float ra = sqrtf(__uint_as_float(*rmax_bits));
+        const float E = err_coef * (qa + ra) * (qa + ra);
+        const bool cert = (nvalid < kp) || (Dk * (1.0f + edir) <= T - E);
+        if (!cert && lane == 0) {
+            int p = atomicAdd(fb_count, 1);
+            fb_rows[p] = (int32_t)row;
+        }
+    }
+}
+
+// --------------------------------------------------------------- fallback
+
+// Exhaustive direct-difference k-NN for the rows listed in fb_rows (one
+// workgroup of 4 waves per row; each wave scans a quarter of the references
+// 64 at a time and merges them into its list; the 4 lists are merged last).
+template <int DT>
+__global__ __launch_bounds__(256) void exact_fallback_kernel(
+    const int32_t* __restrict__ fb_rows, const int* __restrict__ fb_count,
+    const void* __restrict__ Q, int64_t ldq, const void* __restrict__ R, int64_t ldr, int64_t nr,
+    int d, const int32_t* __restrict__ q_self, int self_mode, int k, int out_kind,
+    int32_t* __restrict__ out_idx, float* __restrict__ out_dist)
+{
+    __shared__ uint64_t sl[4][64];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int cnt = *fb_count;
+    for (int f = blockIdx.x; f < cnt; f += gridDim.x) {
+        const int64_t row = fb_rows[f];
+        const int64_t self = self_mode == 1 ? row : (self_mode == 2 ? (int64_t)q_self[row] : -1);
+        uint64_t list = kEmptyList;
+        for (int64_t base = (int64_t)wv * 64; base < nr; base += 256) {
+            uint64_t cand = kEmptyCand;
+            for (int p = 0; p < 16; ++p) {
+                const int64_t j = base + p * 4 + (lane >> 4);
+                const bool act = j < nr && j != self;
+                const float v = dist_g16<DT>(Q, row * ldq, R, j * ldr, d, act);
+                const float got = shfl_f32(v, ((lane - p * 4) & 3) * 16);
+                const int64_t jj = base + lane;
+                if (lane >= p * 4 && lane < p * 4 + 4 && jj < nr && jj != self)
+                    cand = make_key(got, (uint32_t)jj);
+            }
+            cand = seg_sort<64>(cand);
+            list = seg_merge_sorted<64>(list, cand);
+        }
+        sl[wv][lane] = list;
+        __syncthreads();
+        if (wv == 0) {
+            uint64_t a = sl[0][lane];
+            for (int o = 1; o < 4; ++o) a = seg_merge_sorted<64>(a, sl[o][lane]);
+            if (lane < k) {
+                const float d2 = key_d2(a);
+                out_idx[row * k + lane] = (int32_t)key_idx(a);
+                out_dist[row * k + lane] = out_kind == KNN_OUT_L2 ? sqrtf(d2) : d2;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ host
+
+template <bool TO_BF16>
+static void launch_stage(const knn_matrix& X, void* Xs, int ldp, float* norms, unsigned* maxn,
+                         hipStream_t st)
+{
+    dim3 grid((unsigned)ceil_div(X.n, 4)), block(256);
+    switch (X.dtype) {
+    case KNN_F32:
+        stage_kernel<KNN_F32, TO_BF16><<<grid, block, 0, st>>>(X.data, X.n, X.d, X.ld, Xs, ldp, norms, maxn);
+        break;
+    case KNN_BF16:
+        stage_kernel<KNN_BF16, TO_BF16><<<grid, block, 0, st>>>(X.data, X.n, X.d, X.ld, Xs, ldp, norms, maxn);
+        break;
+    default:
+        stage_kernel<KNN_F16, TO_BF16><<<grid, block, 0, st>>>(X.data, X.n, X.d, X.ld, Xs, ldp, norms, maxn);
+        break;
+    }
+}
+
+// Staged copy of a matrix for the GEMM (FP32 ld = roundup(d, 32) or BF16
+// ld = roundup(d, 64), both 128-byte multiples), norms and max norm.
+knn_status stage_matrix(Workspace& ws, const knn_matrix& X, bool bf16, void** Xs, int* ldp,
+                        float** norms, unsigned* maxnorm, hipStream_t st)
+{
+    *ldp = bf16 ? (int)round_up(X.d, 64) : (int)round_up(X.d, 32);
+    knn_status r = ws.alloc(Xs, (size_t)X.n * (size_t)(*ldp) * (bf16 ? 2 : 4));
+    if (r != KNN_OK) return r;
+    r = ws.alloc(norms, (size_t)X.n);
+    if (r != KNN_OK) return r;
+    if (bf16) launch_stage<true>(X, *Xs, *ldp, *norms, maxnorm, st);
+    else launch_stage<false>(X, *Xs, *ldp, *norms, maxnorm, st);
+    KNN_HIP(hipGetLastError());
+    return KNN_OK;
+}
+
+static knn_status exact_impl(const knn_matrix& Q, const knn_matrix& R, bool same,
+                             const int32_t* q_self, int self_mode, int32_t k, int32_t precision,
+                             int32_t rerank_k, int32_t out_kind, int32_t* out_idx, float* out_dist,
+                             hipStream_t st)
+{
+    if (precision != KNN_PREC_FP32 && precision != KNN_PREC_BF16)
+        return fail(KNN_EINVAL, "precision must be KNN_PREC_FP32 or KNN_PREC_BF16");
+    if (out_kind != KNN_OUT_L2 && out_kind != KNN_OUT_SQL2)
+        return fail(KNN_EINVAL, "out_kind must be KNN_OUT_L2 or KNN_OUT_SQL2");
+    if (!out_idx || !out_dist) return fail(KNN_EINVAL, "null output pointer");
+    const int64_t avail = R.n - (self_mode ? 1 : 0);
+    if (k < 1 || (int64_t)k > avail) return fail(KNN_EINVAL, "k must satisfy 1 <= k <= number of candidates");
+    int kp = rerank_k;
+    if (kp == 0) kp = 2 * k < kListW ? 2 * k : kListW;
+    if (kp < k) return fail(KNN_EINVAL, "rerank_k must be >= k");
+    if (kp > kListW || k > KNN_MAX_K)
+        return fail(KNN_ENOTSUP, "rerank_k and k above 32 are not supported by the exact path");
+    if (Q.n == 0) return KNN_OK;
+    const bool bf = precision == KNN_PREC_BF16;
+
+    Workspace ws(st, 0);
+    knn_status r;
+    unsigned* small = nullptr;   // [0] = max ref norm bits, [1] = fallback count
+    r = ws.alloc(&small, 4);
+    if (r != KNN_OK) return r;
+    KNN_HIP(hipMemsetAsync(small, 0, 16, st));
+    void *Qs = nullptr, *Rs = nullptr;
+    float *qn = nullptr, *rn = nullptr;
+    int ldp = 0, ldp2 = 0;
+    r = stage_matrix(ws, R, bf, &Rs, &ldp, &rn, small, st);
+    if (r != KNN_OK) return r;
+    if (same) {
+        Qs = Rs;
+        qn = rn;
+    } else {
+        r = stage_matrix(ws, Q, bf, &Qs, &ldp2, &qn, nullptr, st);
+        if (r != KNN_OK) return r;
+    }
+
+    const int64_t nblk = ceil_div(Q.n, kTileRows);
+    int S = (int)ceil_div(2048, nblk);
+    S = S < 1 ? 1 : (S > 4 ? 4 : S);
+    int64_t split_len = round_up(ceil_div(R.n, S), kTileRows);
+    S = (int)ceil_div(R.n, split_len);
+    uint64_t* part = nullptr;
+    r = ws.alloc(&part, (size_t)Q.n * S * kListW);
+    if (r != KNN_OK) return r;
+    int32_t* fb_rows = nullptr;
+    r = ws.alloc(&fb_rows, (size_t)Q.n);
+    if (r != KNN_OK) return r;
+
+    dim3 tgrid((unsigned)nblk, (unsigned)S);
+    if (bf)
+        exact_tile_kernel<true><<<tgrid, 256, 0, st>>>(Qs, qn, Q.n, Rs, rn, R.n, ldp, q_self,
+                                                       self_mode, kp, split_len, S, part);
+    else
+        exact_tile_kernel<false><<<tgrid, 256, 0, st>>>(Qs, qn, Q.n, Rs, rn, R.n, ldp, q_self,
+                                                        self_mode, kp, split_len, S, part);
+    KNN_HIP(hipGetLastError());
+
+    // GEMM error bound (FP32): (d + 3) u (|q| + max|r|)^2 with u = 2^-24;
+    // re-rank bound: (d/16 + 8) u relative.
+    const float u = 5.9604645e-08f;
+    const float err_coef = (float)(R.d + 3) * u * 1.01f;
+    const float edir = (float)(R.d / 16 + 8) * u;
+    const int certify = bf ? 0 : 1;
+    int* fb_count = (int*)(small + 1);
+    dim3 mgrid((unsigned)ceil_div(Q.n, 4));
+#define KNN_MR(DT)                                                                              \
+    merge_rerank_kernel<DT><<<mgrid, 256, 0, st>>>(part, S, Q.n, kp, k, Q.data, Q.ld, R.data, \
+                                                   R.ld, R.d, qn, small, err_coef, edir,       \
+                                                   certify, out_kind, out_idx, out_dist,       \
+                                                   fb_rows, fb_count)
+    if (Q.dtype == KNN_F32) KNN_MR(KNN_F32);
+    else if (Q.dtype == KNN_BF16) KNN_MR(KNN_BF16);
+    else KNN_MR(KNN_F16);
+#undef KNN_MR
+    KNN_HIP(hipGetLastError());
+    if (certify) {
+        dim3 fgrid(1024);
+#define KNN_FB(DT)                                                                              \
+    exact_fallback_kernel<DT><<<fgrid, 256, 0, st>>>(fb_rows, fb_count, Q.data, Q.ld, R.data,  \
+                                                     R.ld, R.n, R.d, q_self, self_mode, k,     \
+                                                     out_kind, out_idx, out_dist)
+        if (Q.dtype == KNN_F32) KNN_FB(KNN_F32);
+        else if (Q.dtype == KNN_BF16) KNN_FB(KNN_BF16);
+        else KNN_FB(KNN_F16);
+#undef KNN_FB
+        KNN_HIP(hipGetLastError());
+    }
+    KNN_HIP(hipStreamSynchronize(st));
+    return KNN_OK;
+}
+
+}  // namespace knn
+
+using namespace knn;
+
+extern "C" knn_status knn_exact(knn_matrix X, int32_t k, int32_t precision, int32_t rerank_k,
+                                int32_t out_kind, int32_t* out_idx, float* out_dist, void* stream)
+{
+    try {
+        knn_status r = check_matrix(X, "X");
+        if (r != KNN_OK) return r;
+        if (X.n < 2) return fail(KNN_EINVAL, "X.n must be >= 2");
+        return exact_impl(X, X, true, nullptr, 1, k, precision, rerank_k, out_kind, out_idx,
+                          out_dist, (hipStream_t)stream);
+    } catch (...) {
+        return fail(KNN_EDEVICE, "unexpected exception");
+    }
+}
+
+extern "C" knn_status knn_exact_query(knn_matrix Q, knn_matrix R, const int32_t* q_self,
+                                      int32_t k, int32_t precision, int32_t rerank_k,
+                                      int32_t out_kind, int32_t* out_idx, float* out_dist,
+                                      void* stream)
+{
+    try {
+        knn_status r = check_matrix(Q, "Q");
+        if (r != KNN_OK) return r;
+        r = check_matrix(R, "R");
+        if (r != KNN_OK) return r;
+        if (Q.d != R.d) return fail(KNN_EINVAL, "Q.d != R.d");
+        if (Q.dtype != R.dtype) return fail(KNN_EINVAL, "Q.dtype != R.dtype");
+        return exact_impl(Q, R, false, q_self, q_self ? 2 : 0, k, precision, rerank_k, out_kind,
+                          out_idx, out_dist, (hipStream_t)stream);
+    } catch (...) {
+        return fail(KNN_EDEVICE, "unexpected exception");
+    }
+}

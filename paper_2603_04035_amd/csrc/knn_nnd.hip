@@ -1,0 +1,1017 @@
+// NNDescent on gfx950 (Dong, Charikar & Li, WWW 2011; the paper's k-NN
+// section: random k-neighbour init, neighbours-of-neighbours refinement,
+// early termination when the update rate falls below delta = 0.015).
+//
+// State: per point a list of K_b (index, squared distance, new-flag)
+// entries sorted by (distance, index).  One iteration is four kernels with
+// no host round trip except the 8-byte update count:
+//
+//  sample   half-wave per row: up to s = ceil(rho K_b) new entries are picked
+//           by smallest random priority and marked old; the old entries are
+//           listed; both are scattered as reverse edges into R hashed slots of
+//           the target rows with atomicMin on (priority, source) keys, so the
+//           reverse sample does not depend on thread order;
+//  join     one wave per point v: the new list new_f(v) + reverse-new and the
+//           old list old_f(v) + reverse-old are deduplicated, their rows are
+//           gathered into LDS (coalesced 16-lane row reads, d in chunks of
+//           64), the Gram tile new x all is formed with FP32 FMAs (or BF16
+//           MFMA in the precision form), and each member receives at most
+//           `join_cap` of its best partners that beat its current worst
+//           distance, as atomicMin keys into C hashed candidate slots;
+//  merge    one wave per row: the K_b list keys and the C slot keys are
+//           deduplicated by index, bitonic-sorted, the first K_b kept; slot
+//           entries that enter are flagged new and counted; slots are reset;
+//  (host)   stop when updates < delta * n * K_b.
+//
+// finalize re-ranks the K_b entries with FP32 direct differences on the
+// input values and returns the first k.
+#include <math.h>
+
+#include "knn_common.hpp"
+
+namespace knn {
+
+knn_status stage_matrix(Workspace& ws, const knn_matrix& X, bool bf16, void** Xs, int* ldp,
+                        float** norms, unsigned* maxnorm, hipStream_t st);
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------------------------ init
+
+// One wave per row: entries from init_idx (nullable; invalid, self and
+// repeated entries dropped), completed with distinct uniform random indices,
+// distances (given, or canonical direct differences on the staged rows),
+// sorted, first K kept.  Flags: given (or new).
+template <int DT>
+__global__ __launch_bounds__(256) void nnd_init_kernel(
+    int64_t n, int K, const void* __restrict__ Xs, int ldp, int d,
+    const int32_t* __restrict__ init_idx, const float* __restrict__ init_dist,
+    const uint8_t* __restrict__ init_flags, int init_k, uint64_t seed,
+    int32_t* __restrict__ gidx, float* __restrict__ gd2, uint8_t* __restrict__ gflag)
+{
+    __shared__ uint32_t s_id[4][64];
+    __shared__ float s_d2[4][64];
+    __shared__ uint8_t s_fl[4][64];
+    __shared__ uint8_t s_has[4][64];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + wv;
+    if (row >= n) return;
+
+    // 1. given entries
+    uint32_t id = 0xFFFFFFFFu;
+    bool valid = false;
+    float gd = 0.0f;
+    uint8_t fl = 1;
+    bool hasd = false;
+    if (init_idx && lane < init_k) {
+        int32_t v = init_idx[row * init_k + lane];
+        if (v >= 0 && v < n && v != row) {
+            id = (uint32_t)v;
+            valid = true;
+            if (init_dist) {
+                gd = init_dist[row * init_k + lane];
+                hasd = true;
+            }
+            if (init_flags) fl = init_flags[row * init_k + lane] ? 1 : 0;
+        }
+    }
+    // drop repeats (keep the first occurrence)
+    for (int o = 0; o < 64; ++o) {
+        uint32_t oi = bcast_u32(id, o);
+        bool ov = bcast_u32(valid ? 1u : 0u, o) != 0;
+        if (o < lane && ov && oi == id) valid = false;
+    }
+    uint64_t vm = ballot(valid);
+    int nvalid = popc64(vm);
+    int pos = rank_below(vm);
+    if (valid) {
+        s_id[wv][pos] = id;
+        s_d2[wv][pos] = gd;
+        s_fl[wv][pos] = fl;
+        s_has[wv][pos] = hasd ? 1 : 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+
+    // 2. compact into lanes; fill the rest of 0..K-1 at random
+    const int have = nvalid;
+    id = lane < have ? s_id[wv][lane] : 0xFFFFFFFFu;
+    gd = lane < have ? s_d2[wv][lane] : 0.0f;
+    fl = lane < have ? s_fl[wv][lane] : 1;
+    hasd = lane < have ? (s_has[wv][lane] != 0) : false;
+    bool ok = lane < have;
+    const int want = K;   // entries needed
+    if (have < want) {
+        const uint32_t m = (uint32_t)(n - 1);
+        if (n - 1 <= 2 * (int64_t)K) {
+            // tiny n: take a random rotation of the other points, skipping given ones
+            uint32_t start = bounded(hash4(seed ^ kTagInit, (uint64_t)row, 0xFFFFFFFFull, 0), m);
+            int filled = have;
+            for (uint32_t t = 0; t < m && filled < want; ++t) {
+                uint32_t cand = (uint32_t)((row + 1 + (start + t) % m) % n);
+                bool dup = false;
+                for (int o = 0; o < filled; ++o) dup |= bcast_u32(id, o) == cand;
+                if (!dup) {
+                    if (lane == filled) {
+                        id = cand;
+                        ok = true;
+                        fl = 1;
+                        hasd = false;
+                    }
+                    ++filled;
+                }
+            }
+        } else {
+            uint32_t attempt = 0;
+            while (ballot(lane < want && !ok) && attempt < 4096) {
+                if (lane < want && !ok) {
+                    uint64_t r = hash4(seed ^ kTagInit, (uint64_t)row, (uint64_t)lane, attempt);
+                    id = bounded(r, (uint32_t)n);
+                }
+                bool dup = false;
+                for (int o = 0; o < want; ++o) {
+                    uint32_t oi = bcast_u32(id, o);
+                    bool ook = bcast_u32(ok ? 1u : 0u, o) != 0;
+                    dup |= (o != lane) && oi == id && (ook || o < lane);
+                }
+                if (lane < want && !ok) {
+                    ok = (id != (uint32_t)row) && !dup;
+                    fl = 1;
+                    hasd = false;
+                }
+                ++attempt;
+            }
+            if (lane < want && !ok) id = 0xFFFFFFFFu;
+        }
+    }
+    // 3. distances for entries without one (4 rows per pass, 16 lanes each)
+    const int cnt = have > want ? have : want;
+    float mine = gd;
+    for (int base = 0; base < cnt; base += 4) {
+        const int ci = base + (lane >> 4);
+        const uint32_t cj = shfl_u32(id, ci);
+        const bool need = shfl_u32(hasd ? 1u : 0u, ci) == 0;
+        const bool act = ci < cnt && need && cj != 0xFFFFFFFFu;
+        const float v = dist_g16<DT>(Xs, row * ldp, Xs, (int64_t)cj * ldp, d, act);
+        const float got = shfl_f32(v, ((lane - base) & 3) * 16);
+        if (lane >= base && lane < base + 4 && !hasd) mine = got;
+    }
+    // 4. sort by (d2, id), carry flags, keep the first K
+    const bool live = lane < cnt && id != 0xFFFFFFFFu;
+    const uint64_t key = live ? make_key(mine, id) : kEmptyCand;
+    const uint64_t sk = seg_sort<64>(key);
+    uint8_t sfl = 1;
+    for (int o = 0; o < cnt; ++o) {
+        uint64_t ok2 = bcast_u64(key, o);
+        uint32_t of = bcast_u32(fl, o);
+        if (ok2 == sk) sfl = (uint8_t)of;
+    }
+    if (lane < K) {
+        const bool sv = key_valid(sk);
+        gidx[row * K + lane] = sv ? (int32_t)key_idx(sk) : -1;
+        gd2[row * K + lane] = sv ? key_d2(sk) : __builtin_inff();
+        gflag[row * K + lane] = sv ? sfl : 0;
+    }
+}
+
+// ---------------------------------------------------------------- sample
+
+// Half-wave (32 lanes) per row, K <= 32.  Picks the s new entries with the
+// smallest priorities (ties by position), marks them old, lists old entries,
+// and scatters reverse edges into R slots per target row.
+__global__ __launch_bounds__(256) void nnd_sample_kernel(
+    int64_t n, int K, int s, int R, int32_t* __restrict__ gidx, uint8_t* __restrict__ gflag,
+    int32_t* __restrict__ newf, int32_t* __restrict__ oldf, unsigned long long* __restrict__ revnew,
+    unsigned long long* __restrict__ revold, uint64_t seed, int iter)
+{
+    const int lane = threadIdx.x & 63, hl = lane & 31, hbase = lane & 32;
+    const int64_t row = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 2 + (lane >> 5);
+    const bool rv = row < n;
+    const bool inl = rv && hl < K;
+    int32_t id = -1;
+    uint8_t fl = 0;
+    if (inl) {
+        id = gidx[row * K + hl];
+        fl = gflag[row * K + hl];
+    }
+    const bool isnew = inl && id >= 0 && fl;
+    const bool isold = inl && id >= 0 && !fl;
+    uint64_t pr = isnew ? hash4(seed ^ kTagSample, (uint64_t)iter, (uint64_t)row, (uint64_t)id)
+                        : ~0ull;
+    // rank among the new entries of this half
+    int rank = 0;
+    for (int o = 0; o < 32; ++o) {
+        const uint64_t p0 = bcast_u64(pr, o), p1 = bcast_u64(pr, 32 + o);
+        const uint64_t po = hbase ? p1 : p0;
+        rank += (po < pr || (po == pr && o < hl)) ? 1 : 0;
+    }
+    const bool pick = isnew && rank < s;
+    const uint64_t nm = ballot(isnew), om = ballot(isold);
+    const uint64_t hn = hbase ? (nm >> 32) : (nm & 0xFFFFFFFFull);
+    const uint64_t ho = hbase ? (om >> 32) : (om & 0xFFFFFFFFull);
+    const int npick = __popcll(hn) < s ? __popcll(hn) : s;
+    const int nold = __popcll(ho);
+    const int opos = __popcll(ho & ((1ull << hl) - 1ull));
+    // slots past the picks / old entries get -1 (disjoint from the writes below)
+    if (rv && hl >= npick && hl < s) newf[row * s + hl] = -1;
+    if (rv && hl >= nold && hl < K) oldf[row * K + hl] = -1;
+    if (pick) {
+        newf[row * s + rank] = id;
+        gflag[row * K + hl] = 0;
+        const uint32_t slot = bounded(hash4(seed ^ kTagRevSlot, (uint64_t)iter, (uint64_t)row, 1), (uint32_t)R);
+        const uint64_t key = (hash4(seed ^ kTagRevNew, (uint64_t)iter, (uint64_t)row, (uint64_t)id) &
+                              0xFFFFFFFF00000000ull) | (uint64_t)row;
+        atomicMin(&revnew[(int64_t)id * R + slot], (unsigned long long)key);
+    }
+    if (isold) {
+        oldf[row * K + opos] = id;
+        const uint32_t slot = bounded(hash4(seed ^ kTagRevSlot, (uint64_t)iter, (uint64_t)row, 2), (uint32_t)R);
+        const uint64_t key = (hash4(seed ^ kTagRevOld, (uint64_t)iter, (uint64_t)row, (uint64_t)id) &
+                              0xFFFFFFFF00000000ull) | (uint64_t)row;
+        atomicMin(&revold[(int64_t)id * R + slot], (unsigned long long)key);
+    }
+}
+
+// ------------------------------------------------------------------ join
+
+struct JoinCfg {
+    int s, R, K, C, J;     // new sample, reverse slots, list size, candidate slots, cap
+    int lcap;              // max join-list length (rows staged in LDS), <= 64
+    int ncap;              // max new-list length
+    int gstride;           // LDS row stride of the distance matrix (odd: no bank conflicts)
+};
+
+constexpr int kTD = 64;          // d-chunk staged per pass (elements)
+constexpr int kTDP = kTD + 4;    // LDS row stride of staged rows (floats)
+constexpr int kJMax = 8;         // largest supported join cap
+
+// Per-point join lists.  Lanes 0..s-1 take new_f(v), s..s+R-1 the reverse-new
+// slots (consumed and reset), and likewise old_f(v) / reverse-old in a second
+// register.  Repeats are dropped, an id in both lists stays new, v itself is
+// dropped.  The surviving ids are written to ids[0..nn) (new) and
+// ids[nn..nn+no) (old).  Returns nn, sets L.
+__device__ inline int join_lists(int64_t v, const JoinCfg& cfg, const int32_t* __restrict__ newf,
+                                 unsigned long long* __restrict__ revnew,
+                                 const int32_t* __restrict__ oldf,
+                                 unsigned long long* __restrict__ revold, uint32_t* ids, int& L)
+{
+    const int lane = threadIdx.x;
+    uint32_t nid = 0xFFFFFFFFu, oid = 0xFFFFFFFFu;
+    if (lane < cfg.s) {
+        const int32_t x = newf[v * cfg.s + lane];
+        if (x >= 0) nid = (uint32_t)x;
+    } else if (lane < cfg.s + cfg.R) {
+        unsigned long long* p = &revnew[v * cfg.R + (lane - cfg.s)];
+        const unsigned long long x = *p;
+        if (x != ~0ull) {
+            nid = (uint32_t)x;
+            *p = ~0ull;
+        }
+    }
+    if (lane < cfg.K) {
+        const int32_t x = oldf[v * cfg.K + lane];
+        if (x >= 0) oid = (uint32_t)x;
+    } else if (lane < cfg.K + cfg.R) {
+        unsigned long long* p = &revold[v * cfg.R + (lane - cfg.K)];
+        const unsigned long long x = *p;
+        if (x != ~0ull) {
+            oid = (uint32_t)x;
+            *p = ~0ull;
+        }
+    }
+    bool nv = nid != 0xFFFFFFFFu && nid != (uint32_t)v;
+    bool ov = oid != 0xFFFFFFFFu && oid != (uint32_t)v;
+    // repeats: reverse entries against forward ones (forward lists hold distinct ids)
+    for (int o = 0; o < cfg.s; ++o) {
+        const uint32_t x = bcast_u32(nid, o);
+        nv = nv && !(lane >= cfg.s && x == nid);
+        ov = ov && x != oid;
+    }
+    for (int o = cfg.s; o < cfg.s + cfg.R; ++o) {
+        const uint32_t x = bcast_u32(nid, o);
+        nv = nv && !(o < lane && x == nid);
+        ov = ov && x != oid;
+    }
+    for (int o = 0; o < cfg.K + cfg.R; ++o) {
+        const uint32_t x = bcast_u32(oid, o);
+        ov = ov && !(o < lane && x == oid);
+    }
+    const uint64_t nm = ballot(nv), om = ballot(ov);
+    int nn = popc64(nm), no = popc64(om);
+    if (nn > cfg.ncap) nn = cfg.ncap;
+    if (nn + no > cfg.lcap) no = cfg.lcap - nn;
+    const int pn = rank_below(nm), po = rank_below(om);
+    if (nv && pn < nn) ids[pn] = nid;
+    if (ov && po < no) ids[nn + po] = oid;
+    L = nn + no;
+    return nn;
+}
+
+// Squared distances new x list by FP32 FMAs: tiles of (8 AI) new rows x
+// (8 BQ) list rows, lane (ag, bg) owning rows ag + 8i and bg + 8q; rows are
+// staged in LDS chunk by chunk (16 lanes x float4 per row).
+template <int AI, int BQ>
+__device__ inline void join_gram_f32(const float* __restrict__ Xs, int ldp, int d, float* rows,
+                                     float* gram, const uint32_t* ids, const float* nrm, int nn,
+                                     int L, int gs, bool staged)
+{
+    const int lane = threadIdx.x, ag = lane >> 3, bg = lane & 7;
+    const int nch = (d + kTD - 1) / kTD;
+    for (int at = 0; at < nn; at += 8 * AI) {
+        float acc[AI][BQ];
+#pragma unroll
+        for (int i = 0; i < AI; ++i)
+#pragma unroll
+            for (int q = 0; q < BQ; ++q) acc[i][q] = 0.0f;
+        for (int ch = 0; ch < nch; ++ch) {
+            const int c0 = ch * kTD;
+            if (nch > 1 || !staged) {
+                __syncthreads();
+                for (int m = lane >> 4; m < L; m += 4) {
+                    const int t = c0 + (lane & 15) * 4;
+                    f32x4 x = {0.0f, 0.0f, 0.0f, 0.0f};
+                    if (t < ldp) x = *(const f32x4*)(Xs + (int64_t)ids[m] * ldp + t);
+                    *(f32x4*)(rows + m * kTDP + (lane & 15) * 4) = x;
+                }
+                __syncthreads();
+                staged = true;
+            }
+            int ai[AI], bq[BQ];
+#pragma unroll
+            for (int i = 0; i < AI; ++i) ai[i] = min(at + ag + 8 * i, L - 1);
+#pragma unroll
+            for (int q = 0; q < BQ; ++q) bq[q] = min(bg + 8 * q, L - 1);
+            const int tl = min(kTD, d - c0);
+            for (int t = 0; t < tl; t += 4) {
+                f32x4 xa[AI];
+#pragma unroll
+                for (int i = 0; i < AI; ++i) xa[i] = *(const f32x4*)(rows + ai[i] * kTDP + t);
+#pragma unroll
+                for (int q = 0; q < BQ; ++q) {
+                    const f32x4 xb = *(const f32x4*)(rows + bq[q] * kTDP + t);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+#pragma unroll
+                        for (int i = 0; i < AI; ++i) acc[i][q] = fmaf(xa[i][e], xb[e], acc[i][q]);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < AI; ++i) {
+            const int a = at + ag + 8 * i;
+#pragma unroll
+            for (int q = 0; q < BQ; ++q) {
+                const int b = bg + 8 * q;
+                if (a < nn && b < L) {
+                    const float d2 = nrm[a] + nrm[b] - 2.0f * acc[i][q];
+                    gram[a * gs + b] = d2 > 0.0f ? d2 : 0.0f;
+                }
+            }
+        }
+    }
+}
+
+// Each member m of the join list takes its best J partners below its current
+// worst distance (new x new and new x old pairs only) and sends them to its
+// candidate slots: atomicMin of the key at slot hash(partner, iteration).
+__device__ inline unsigned long long join_emit(const JoinCfg& cfg, const float* gram, const uint32_t* ids,
+                                               const float* thr, int nn, int L, uint64_t salt,
+                                               unsigned long long* __restrict__ cand)
+{
+    unsigned long long emitted = 0;
+    const int gs = cfg.gstride;
+    for (int m = threadIdx.x; m < L; m += 64) {
+        const bool mnew = m < nn;
+        const float tm = thr[m];
+        uint64_t best[kJMax];
+#pragma unroll
+        for (int q = 0; q < kJMax; ++q) best[q] = kEmptyCand;
+        const int olim = mnew ? L : nn;      // old members only pair with new ones
+#pragma unroll 4
+        for (int o = 0; o < olim; ++o) {
+            const float d2 = mnew ? gram[m * gs + o] : gram[o * gs + m];
+            if (o == m || !(d2 < tm)) continue;
+            uint64_t key = make_key(d2, ids[o]);
+#pragma unroll
+            for (int q = 0; q < kJMax; ++q) {
+                if (q < cfg.J && key < best[q]) {
+                    const uint64_t t = best[q];
+                    best[q] = key;
+                    key = t;
+                }
+            }
+        }
+        const uint32_t me = ids[m];
+#pragma unroll
+        for (int q = 0; q < kJMax; ++q) {
+            if (q < cfg.J && best[q] != kEmptyCand) {
+                const uint32_t src = key_idx(best[q]);
+                const uint32_t slot = bounded(mix64(((uint64_t)src << 20) ^ salt), (uint32_t)cfg.C);
+                atomicMin(&cand[(int64_t)me * cfg.C + slot], (unsigned long long)best[q]);
+                ++emitted;
+            }
+        }
+    }
+    return emitted;
+}
+
+template <int AI, int BQ>
+__device__ inline void gram_f32_dispatch(const float* Xs, int ldp, int d, float* rows, float* gram,
+                                         const uint32_t* ids, const float* nrm, int nn, int L, int gs)
+{
+    join_gram_f32<AI, BQ>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs, false);
+}
+
+// Local join, FP32 (VALU).  One wave per point, grid-stride.  Dynamic LDS:
+// rows[lcap][kTDP] floats, gram[ncap][gstride] floats, ids/nrm/thr[lcap].
+__global__ __launch_bounds__(64) void nnd_join_f32_kernel(
+    int64_t n, JoinCfg cfg, const float* __restrict__ Xs, int ldp, int d, const float* __restrict__ norms,
+    const float* __restrict__ gd2, const int32_t* __restrict__ newf,
+    unsigned long long* __restrict__ revnew, const int32_t* __restrict__ oldf,
+    unsigned long long* __restrict__ revold, unsigned long long* __restrict__ cand, uint64_t seed,
+    int iter, unsigned long long* __restrict__ counters)
+{
+    extern __shared__ float smem[];
+    const int lcap = cfg.lcap, ncap = cfg.ncap, gs = cfg.gstride;
+    float* rows = smem;
+    float* gram = rows + lcap * kTDP;
+    uint32_t* ids = (uint32_t*)(gram + ncap * gs);
+    float* nrm = (float*)(ids + lcap);
+    float* thr = nrm + lcap;
+    const int lane = threadIdx.x;
+    unsigned long long emitted = 0, gathered = 0;
+    const uint64_t salt = (uint64_t)iter ^ seed;
+
+    for (int64_t v = blockIdx.x; v < n; v += gridDim.x) {
+        int L = 0;
+        const int nn = join_lists(v, cfg, newf, revnew, oldf, revold, ids, L);
+        __syncthreads();
+        if (nn == 0 || L < 2) continue;
+        for (int m = lane; m < L; m += 64) {
+            const uint32_t x = ids[m];
+            nrm[m] = norms[x];
+            thr[m] = gd2[(int64_t)x * cfg.K + cfg.K - 1];
+        }
+        gathered += (unsigned long long)L;
+        const int ai = min((nn + 7) >> 3, 4);
+        const int bq = L <= 24 ? 3 : (L <= 40 ? 5 : 8);
+        switch (ai * 16 + bq) {
+        case 16 + 3: gram_f32_dispatch<1, 3>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
+        case 16 + 5: gram_f32_dispatch<1, 5>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
+        case 16 + 8: gram_f32_dispatch<1, 8>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
+        case 32 + 3: gram_f32_dispatch<2, 3>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
+        case 32 + 5: gram_f32_dispatch<2, 5>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
+        case 32 + 8: gram_f32_dispatch<2, 8>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
+        case 48 + 3: gram_f32_dispatch<3, 3>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
+        case 48 + 5: gram_f32_dispatch<3, 5>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
+        case 48 + 8: gram_f32_dispatch<3, 8>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
+        case 64 + 3: gram_f32_dispatch<4, 3>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
+        case 64 + 5: gram_f32_dispatch<4, 5>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
+        default: gram_f32_dispatch<4, 8>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
+        }
+        __syncthreads();
+        emitted += join_emit(cfg, gram, ids, thr, nn, L, salt, cand);
+        __syncthreads();
+    }
+    for (int o = 32; o > 0; o >>= 1) emitted += shfl_u64(emitted, lane ^ o);
+    if (lane == 0) {
+        atomicAdd(&counters[1], emitted);
+        atomicAdd(&counters[2], gathered);
+    }
+}
+
+// Local join, BF16 form.  Same lists and emission as the FP32 join; the
+// squared distances come from BF16 rows (RNE copies) through
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation and FP32 norms of the
+// rounded rows.  A-operand: 32 new rows; B-operand: up to 64 list rows (two
+// 32-column blocks).  Rows are staged in LDS in chunks of 128 elements.
+constexpr int kTDB = 128;        // d-chunk (bf16 elements)
+constexpr int kTDBP = kTDB + 8;  // LDS row stride (elements): 272 bytes
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__global__ __launch_bounds__(64) void nnd_join_bf16_kernel(
+    int64_t n, JoinCfg cfg, const uint16_t* __restrict__ Xb, int ldb, int d,
+    const float* __restrict__ norms, const float* __restrict__ gd2, const int32_t* __restrict__ newf,
+    unsigned long long* __restrict__ revnew, const int32_t* __restrict__ oldf,
+    unsigned long long* __restrict__ revold, unsigned long long* __restrict__ cand, uint64_t seed,
+    int iter, unsigned long long* __restrict__ counters)
+{
+    extern __shared__ float smem[];
+    const int lcap = cfg.lcap, ncap = cfg.ncap, gs = cfg.gstride;
+    uint16_t* rows = (uint16_t*)smem;
+    float* gram = smem + (lcap * kTDBP) / 2;
+    uint32_t* ids = (uint32_t*)(gram + ncap * gs);
+    float* nrm = (float*)(ids + lcap);
+    float* thr = nrm + lcap;
+    const int lane = threadIdx.x, c = lane & 31, h = lane >> 5;
+    unsigned long long emitted = 0, gathered = 0;
+    const uint64_t salt = (uint64_t)iter ^ seed;
+    const int dk = (int)round_up(d, 16);
+    const int nch = (dk + kTDB - 1) / kTDB;
+
+    for (int64_t v = blockIdx.x; v < n; v += gridDim.x) {
+        int L = 0;
+        const int nn = join_lists(v, cfg, newf, revnew, oldf, revold, ids, L);
+        __syncthreads();
+        if (nn == 0 || L < 2) continue;
+        for (int m = lane; m < L; m += 64) {
+            const uint32_t x = ids[m];
+            nrm[m] = norms[x];
+            thr[m] = gd2[(int64_t)x * cfg.K + cfg.K - 1];
+        }
+        gathered += (unsigned long long)L;
+        bool staged = false;
+        for (int at = 0; at < nn; at += 32) {
+            f32x16 acc0, acc1;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                acc0[e] = 0.0f;
+                acc1[e] = 0.0f;
+            }
+            for (int ch = 0; ch < nch; ++ch) {
+                const int c0 = ch * kTDB;
+                if (nch > 1 || !staged) {
+                    __syncthreads();
+                    for (int m = lane >> 4; m < L; m += 4) {
+                        const int t = c0 + (lane & 15) * 8;
+                        uint4 x = {0u, 0u, 0u, 0u};
+                        if (t < ldb) x = *(const uint4*)(Xb + (int64_t)ids[m] * ldb + t);
+                        *(uint4*)(rows + m * kTDBP + (lane & 15) * 8) = x;
+                    }
+                    __syncthreads();
+                    staged = true;
+                }
+                const int ra = min(at + c, L - 1), rb0 = min(c, L - 1), rb1 = min(32 + c, L - 1);
+                const int ksteps = min(kTDB, dk - c0) / 16;
+                for (int kk = 0; kk < ksteps; ++kk) {
+                    const int off = kk * 16 + h * 8;
+                    const bf16x8 a = __builtin_bit_cast(bf16x8, *(const uint4*)(rows + ra * kTDBP + off));
+                    const bf16x8 b0 = __builtin_bit_cast(bf16x8, *(const uint4*)(rows + rb0 * kTDBP + off));
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
+                    if (L > 32) {
+                        const bf16x8 b1 = __builtin_bit_cast(bf16x8, *(const uint4*)(rows + rb1 * kTDBP + off));
+                        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+                    }
+                }
+            }
+            // D[i][j]: lane holds column c, rows 8*(e/4) + 4*h + e%4
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int i = at + 8 * (e >> 2) + 4 * h + (e & 3);
+                if (i < nn) {
+                    if (c < L) {
+                        const float d2 = nrm[i] + nrm[c] - 2.0f * acc0[e];
+                        gram[i * gs + c] = d2 > 0.0f ? d2 : 0.0f;
+                    }
+                    if (32 + c < L) {
+                        const float d2 = nrm[i] + nrm[32 + c] - 2.0f * acc1[e];
+                        gram[i * gs + 32 + c] = d2 > 0.0f ? d2 : 0.0f;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        emitted += join_emit(cfg, gram, ids, thr, nn, L, salt, cand);
+        __syncthreads();
+    }
+    for (int o = 32; o > 0; o >>= 1) emitted += shfl_u64(emitted, lane ^ o);
+    if (lane == 0) {
+        atomicAdd(&counters[1], emitted);
+        atomicAdd(&counters[2], gathered);
+    }
+}
+
+knn_status nnd_join_bf16(int64_t n, const JoinCfg& cfg, const uint16_t* Xb, int ldb, int d,
+                         const float* norms, const float* gd2, const int32_t* newf,
+                         unsigned long long* revnew, const int32_t* oldf,
+                         unsigned long long* revold, unsigned long long* cand, uint64_t seed,
+                         int iter, unsigned long long* counters, unsigned grid, hipStream_t st)
+{
+    const size_t lds = (size_t)cfg.lcap * kTDBP * 2 + ((size_t)cfg.ncap * cfg.gstride + 3 * (size_t)cfg.lcap) * 4;
+    nnd_join_bf16_kernel<<<grid, 64, lds, st>>>(n, cfg, Xb, ldb, d, norms, gd2, newf, revnew, oldf, revold,
+                                               cand, seed, iter, counters);
+    KNN_HIP(hipGetLastError());
+    return KNN_OK;
+}
+
+// ------------------------------------------------------------------ merge
+
+// One wave per row (grid-stride).  Lanes 0..K-1 hold the sorted list.  The C
+// candidate slots are read 64 at a time (and reset), keys whose index is
+// already listed (or is the row) are dropped, the rest are compacted into LDS;
+// then rounds of (list + up to 64-K candidates) are bitonic-sorted and the
+// first K kept.  Entries that came from slots are flagged new and counted.
+__global__ __launch_bounds__(256) void nnd_merge_kernel(
+    int64_t n, int K, int C, int32_t* __restrict__ gidx, float* __restrict__ gd2,
+    uint8_t* __restrict__ gflag, unsigned long long* __restrict__ cand,
+    unsigned long long* __restrict__ counters)
+{
+    extern __shared__ uint64_t sbuf_all[];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint64_t* sbuf = sbuf_all + (size_t)wv * C;
+    const int64_t wglob = (int64_t)blockIdx.x * 4 + wv;
+    const int64_t wstep = (int64_t)gridDim.x * 4;
+    unsigned long long upd = 0;
+    for (int64_t row = wglob; row < n; row += wstep) {
+        uint64_t okey = kEmptyCand;
+        uint32_t fl = 0, lid = 0xFFFFFFFFu;
+        if (lane < K) {
+            const int32_t x = gidx[row * K + lane];
+            if (x >= 0) {
+                lid = (uint32_t)x;
+                okey = make_key(gd2[row * K + lane], lid);
+                fl = gflag[row * K + lane];
+            } else {
+                okey = kEmptyList;
+            }
+        }
+        int nc = 0;
+        for (int c0 = 0; c0 < C; c0 += 64) {
+            uint64_t key = kEmptyCand;
+            if (c0 + lane < C) {
+                unsigned long long* p = &cand[row * C + c0 + lane];
+                key = *p;
+                if (key != kEmptyCand) *p = kEmptyCand;
+            }
+            if (!ballot(key != kEmptyCand)) continue;
+            const uint32_t sid = key_idx(key);
+            bool dup = sid == (uint32_t)row;
+            for (int r = 0; r < K; ++r) dup |= bcast_u32(lid, r) == sid;
+            const bool keep = key != kEmptyCand && !dup;
+            const uint64_t km = ballot(keep);
+            if (keep) sbuf[nc + rank_below(km)] = key;
+            nc += popc64(km);
+        }
+        if (nc == 0) continue;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        uint64_t cur = lane < K ? okey : kEmptyCand;
+        const int per = 64 - K;
+        for (int b0 = 0; b0 < nc; b0 += per) {
+            uint64_t x = cur;
+            if (lane >= K && b0 + lane - K < nc) x = sbuf[b0 + lane - K];
+            x = seg_sort<64>(x);
+            cur = lane < K ? x : kEmptyCand;
+        }
+        bool from_list = false;
+        uint32_t sfl = 1;
+        for (int r = 0; r < K; ++r) {
+            const uint64_t ok = bcast_u64(okey, r);
+            const uint32_t of = bcast_u32(fl, r);
+            if (ok == cur) {
+                from_list = true;
+                sfl = of;
+            }
+        }
+        const bool sv = key_valid(cur) && key_d2(cur) < __builtin_inff();
+        upd += (unsigned long long)popc64(ballot(lane < K && sv && !from_list));
+        if (lane < K) {
+            gidx[row * K + lane] = sv ? (int32_t)key_idx(cur) : -1;
+            gd2[row * K + lane] = sv ? key_d2(cur) : __builtin_inff();
+            gflag[row * K + lane] = sv ? (uint8_t)sfl : 0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (lane == 0 && upd) atomicAdd(&counters[0], upd);
+}
+
+// --------------------------------------------------------------- finalize
+
+// One wave per row: canonical FP32 direct-difference distances of the K list
+// entries on the input values, sort by (distance, index), write the first k;
+// optionally copy the working lists out.
+template <int DT>
+__global__ __launch_bounds__(256) void nnd_finalize_kernel(
+    int64_t n, int K, int k, const void* __restrict__ X, int64_t ld, int d,
+    const int32_t* __restrict__ gidx, const float* __restrict__ gd2, const uint8_t* __restrict__ gflag,
+    int out_kind, int32_t* __restrict__ out_idx, float* __restrict__ out_dist,
+    int32_t* __restrict__ st_idx, float* __restrict__ st_d2, uint8_t* __restrict__ st_fl)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= n) return;
+    int32_t id = lane < K ? gidx[row * K + lane] : -1;
+    if (lane < K) {
+        if (st_idx) st_idx[row * K + lane] = id;
+        if (st_d2) st_d2[row * K + lane] = gd2[row * K + lane];
+        if (st_fl) st_fl[row * K + lane] = gflag[row * K + lane];
+    }
+    float mine = 0.0f;
+    for (int base = 0; base < K; base += 4) {
+        const int ci = base + (lane >> 4);
+        const int32_t cj = (int32_t)shfl_u32((uint32_t)id, ci);
+        const bool act = ci < K && cj >= 0;
+        const float v = dist_g16<DT>(X, row * ld, X, (int64_t)(act ? cj : 0) * ld, d, act);
+        const float got = shfl_f32(v, ((lane - base) & 3) * 16);
+        if (lane >= base && lane < base + 4) mine = got;
+    }
+    uint64_t key = (lane < K && id >= 0) ? make_key(mine, (uint32_t)id) : kEmptyCand;
+    key = seg_sort<64>(key);
+    if (lane < k) {
+        const bool sv = key_valid(key);
+        const float d2 = sv ? key_d2(key) : __builtin_inff();
+        out_idx[row * k + lane] = sv ? (int32_t)key_idx(key) : -1;
+        out_dist[row * k + lane] = out_kind == KNN_OUT_L2 ? sqrtf(d2) : d2;
+    }
+}
+
+// ------------------------------------------------------------------ host
+
+knn_status encoder_seed(const knn_encoder* enc, const knn_matrix& X, int K, int P, int w,
+                        uint64_t seed, Workspace& ws, int32_t** seed_idx, float** seed_d2,
+                        hipStream_t st);
+
+int encoder_dim(const knn_encoder* enc);
+
+namespace {
+
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    Timer()
+    {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+    }
+    ~Timer()
+    {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+};
+
+template <typename F>
+static void launch_by_dtype(int dt, F&& f)
+{
+    if (dt == KNN_F32) f(std::integral_constant<int, KNN_F32>());
+    else if (dt == KNN_BF16) f(std::integral_constant<int, KNN_BF16>());
+    else f(std::integral_constant<int, KNN_F16>());
+}
+
+}  // namespace
+
+static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const int32_t* init_idx,
+                          const float* init_dist, const uint8_t* init_flags, int32_t init_k,
+                          int32_t iter_offset, int32_t* out_idx, float* out_dist,
+                          int32_t* state_idx, float* state_dist, uint8_t* state_flags,
+                          knn_nnd_stats* stats, hipStream_t st)
+{
+    knn_status r = check_matrix(X, "X");
+    if (r != KNN_OK) return r;
+    if (!p) return fail(KNN_EINVAL, "params is null");
+    if (!out_idx || !out_dist) return fail(KNN_EINVAL, "null output pointer");
+    const int64_t n = X.n;
+    if (n < 2) return fail(KNN_EINVAL, "X.n must be >= 2");
+    if (p->k < 1 || (int64_t)p->k > n - 1) return fail(KNN_EINVAL, "k must satisfy 1 <= k <= n-1");
+    if (p->precision != KNN_PREC_FP32 && p->precision != KNN_PREC_BF16)
+        return fail(KNN_EINVAL, "unknown precision");
+    if (p->out_kind != KNN_OUT_L2 && p->out_kind != KNN_OUT_SQL2)
+        return fail(KNN_EINVAL, "unknown out_kind");
+    if (p->init_kind != KNN_INIT_RANDOM && p->init_kind != KNN_INIT_ENCODER)
+        return fail(KNN_EINVAL, "unknown init_kind");
+    if (!(p->sample_rate > 0.0f && p->sample_rate <= 1.0f))
+        return fail(KNN_EINVAL, "sample_rate must be in (0, 1]");
+    if (!(p->delta >= 0.0f)) return fail(KNN_EINVAL, "delta must be >= 0");
+    if (p->max_iters < 0) return fail(KNN_EINVAL, "max_iters must be >= 0");
+    if (iter_offset < 0) return fail(KNN_EINVAL, "iter_offset must be >= 0");
+    if (init_idx && (init_k < 1 || init_k > 64)) return fail(KNN_EINVAL, "init_k must be in [1, 64]");
+    int K = p->build_k;
+    if (K == 0) K = p->precision == KNN_PREC_BF16 ? (2 * p->k < KNN_MAX_K ? 2 * p->k : KNN_MAX_K) : p->k;
+    if (K < p->k) return fail(KNN_EINVAL, "build_k must be >= k");
+    if (K > KNN_MAX_K) return fail(KNN_ENOTSUP, "build_k above 32 is not supported");
+    if ((int64_t)K > n - 1) K = (int)(n - 1);
+    if (p->init_kind == KNN_INIT_ENCODER) {
+        if (!p->encoder) return fail(KNN_EINVAL, "encoder init needs an encoder");
+        if (encoder_dim(p->encoder) != X.d) return fail(KNN_EINVAL, "encoder input width != X.d");
+    }
+    const int s = (int)ceilf(p->sample_rate * (float)K);
+    JoinCfg cfg;
+    cfg.s = s;
+    cfg.R = s;
+    cfg.K = K;
+    cfg.C = p->cand_slots > 0 ? p->cand_slots : 64;
+    if (cfg.C > 256) return fail(KNN_ENOTSUP, "cand_slots above 256 is not supported");
+    cfg.J = p->join_cap > 0 ? p->join_cap : 4;
+    if (cfg.J > kJMax) cfg.J = kJMax;
+    cfg.ncap = cfg.s + cfg.R;
+    cfg.lcap = cfg.s + cfg.R + cfg.K + cfg.R;
+    if (cfg.lcap > 64) cfg.lcap = 64;
+    if (cfg.ncap > 64) cfg.ncap = 64;
+    cfg.gstride = cfg.lcap | 1;
+
+    Timer t_all, t_init, t_fin;
+    (void)hipEventRecord(t_all.a, st);
+    Workspace ws(st, p->workspace_limit_bytes);
+    const bool bf = p->precision == KNN_PREC_BF16;
+    void* Xs = nullptr;
+    float* norms = nullptr;
+    int ldp = 0;
+    r = stage_matrix(ws, X, false, &Xs, &ldp, &norms, nullptr, st);
+    if (r != KNN_OK) return r;
+    void* Xb = nullptr;
+    float* nb = nullptr;
+    int ldb = 0;
+    if (bf) {
+        r = stage_matrix(ws, X, true, &Xb, &ldb, &nb, nullptr, st);
+        if (r != KNN_OK) return r;
+    }
+    int32_t *gidx, *newf, *oldf;
+    float* gd2;
+    uint8_t* gflag;
+    unsigned long long *revnew, *revold, *cand, *counters;
+    if ((r = ws.alloc(&gidx, (size_t)n * K)) != KNN_OK) return r;
+    if ((r = ws.alloc(&gd2, (size_t)n * K)) != KNN_OK) return r;
+    if ((r = ws.alloc(&gflag, (size_t)n * K)) != KNN_OK) return r;
+    if ((r = ws.alloc(&newf, (size_t)n * s)) != KNN_OK) return r;
+    if ((r = ws.alloc(&oldf, (size_t)n * K)) != KNN_OK) return r;
+    if ((r = ws.alloc(&revnew, (size_t)n * cfg.R)) != KNN_OK) return r;
+    if ((r = ws.alloc(&revold, (size_t)n * cfg.R)) != KNN_OK) return r;
+    if ((r = ws.alloc(&cand, (size_t)n * cfg.C)) != KNN_OK) return r;
+    if ((r = ws.alloc(&counters, 4)) != KNN_OK) return r;
+    KNN_HIP(hipMemsetAsync(revnew, 0xFF, (size_t)n * cfg.R * 8, st));
+    KNN_HIP(hipMemsetAsync(revold, 0xFF, (size_t)n * cfg.R * 8, st));
+    KNN_HIP(hipMemsetAsync(cand, 0xFF, (size_t)n * cfg.C * 8, st));
+
+    // ---- init
+    (void)hipEventRecord(t_init.a, st);
+    const int32_t* seed_idx = init_idx;
+    const float* seed_d2 = init_dist;
+    const uint8_t* seed_fl = init_flags;
+    int seed_k = init_k;
+    if (!init_idx && p->init_kind == KNN_INIT_ENCODER) {
+        int32_t* si = nullptr;
+        float* sd = nullptr;
+        const int P = p->proj_count > 0 ? p->proj_count : 4;
+        const int w = p->proj_window > 0 ? p->proj_window : 8;
+        r = encoder_seed(p->encoder, X, K, P, w, p->seed, ws, &si, &sd, st);
+        if (r != KNN_OK) return r;
+        seed_idx = si;
+        seed_d2 = sd;
+        seed_fl = nullptr;
+        seed_k = K;
+    }
+    {
+        dim3 grid((unsigned)ceil_div(n, 4));
+        // distances on the staged FP32 rows (values equal to the input's)
+        nnd_init_kernel<KNN_F32><<<grid, 256, 0, st>>>(n, K, Xs, ldp, X.d, seed_idx, seed_d2, seed_fl,
+                                                       seed_idx ? seed_k : 0, p->seed, gidx, gd2, gflag);
+        KNN_HIP(hipGetLastError());
+    }
+    (void)hipEventRecord(t_init.b, st);
+
+    // ---- iterations
+    unsigned long long* host_cnt = nullptr;
+    KNN_HIP(hipHostMalloc((void**)&host_cnt, 32, hipHostMallocDefault));
+    struct HostFree {
+        void* p;
+        ~HostFree() { (void)hipHostFree(p); }
+    } hf{host_cnt};
+    const double stop = (double)p->delta * (double)n * (double)K;
+    const size_t lds = ((size_t)cfg.lcap * kTDP + (size_t)cfg.ncap * cfg.gstride + 3 * (size_t)cfg.lcap) * 4;
+    const size_t merge_lds = (size_t)4 * cfg.C * 8;
+    int dev = 0;
+    KNN_HIP(hipGetDevice(&dev));
+    int ncu = 256;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const unsigned join_grid = (unsigned)std::min<int64_t>(n, (int64_t)ncu * 8);
+    const unsigned merge_grid = (unsigned)std::min<int64_t>(ceil_div(n, 4), (int64_t)ncu * 8);
+    int iters = 0;
+    double ms_sample = 0, ms_join = 0, ms_merge = 0;
+    uint64_t gathered = 0;
+    Timer ts, tj, tm;
+    for (int it = 0; it < p->max_iters; ++it) {
+        const int iter = iter_offset + it;
+        KNN_HIP(hipMemsetAsync(counters, 0, 32, st));
+        (void)hipEventRecord(ts.a, st);
+        nnd_sample_kernel<<<(unsigned)ceil_div(n, 8), 256, 0, st>>>(n, K, s, cfg.R, gidx, gflag, newf, oldf,
+                                                                  revnew, revold, p->seed, iter);
+        KNN_HIP(hipGetLastError());
+        (void)hipEventRecord(ts.b, st);
+        (void)hipEventRecord(tj.a, st);
+        if (bf) {
+            r = nnd_join_bf16(n, cfg, (const uint16_t*)Xb, ldb, X.d, nb, gd2, newf, revnew, oldf, revold,
+                              cand, p->seed, iter, counters, join_grid, st);
+            if (r != KNN_OK) return r;
+        } else {
+            nnd_join_f32_kernel<<<join_grid, 64, lds, st>>>(n, cfg, (const float*)Xs, ldp, X.d, norms, gd2,
+                                                            newf, revnew, oldf, revold, cand, p->seed, iter,
+                                                            counters);
+            KNN_HIP(hipGetLastError());
+        }
+        (void)hipEventRecord(tj.b, st);
+        (void)hipEventRecord(tm.a, st);
+        nnd_merge_kernel<<<merge_grid, 256, merge_lds, st>>>(n, K, cfg.C, gidx, gd2, gflag, cand, counters);
+        KNN_HIP(hipGetLastError());
+        (void)hipEventRecord(tm.b, st);
+        KNN_HIP(hipMemcpyAsync(host_cnt, counters, 32, hipMemcpyDeviceToHost, st));
+        KNN_HIP(hipStreamSynchronize(st));
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, ts.a, ts.b);
+        ms_sample += ms;
+        (void)hipEventElapsedTime(&ms, tj.a, tj.b);
+        ms_join += ms;
+        if (stats && it < KNN_MAX_ITERS_LOGGED) stats->ms_join_iter[it] = ms;
+        (void)hipEventElapsedTime(&ms, tm.a, tm.b);
+        ms_merge += ms;
+        gathered += host_cnt[2];
+        if (stats && it < KNN_MAX_ITERS_LOGGED) {
+            stats->updates[it] = (int64_t)host_cnt[0];
+            stats->emitted[it] = (int64_t)host_cnt[1];
+        }
+        ++iters;
+        if ((double)host_cnt[0] < stop) break;
+    }
+
+    // ---- finalize
+    (void)hipEventRecord(t_fin.a, st);
+    {
+        dim3 grid((unsigned)ceil_div(n, 4));
+        const int k = p->k;
+        launch_by_dtype(X.dtype, [&](auto dt) {
+            nnd_finalize_kernel<decltype(dt)::value><<<grid, 256, 0, st>>>(
+                n, K, k, X.data, X.ld, X.d, gidx, gd2, gflag, p->out_kind, out_idx, out_dist, state_idx,
+                state_dist, state_flags);
+        });
+        KNN_HIP(hipGetLastError());
+    }
+    (void)hipEventRecord(t_fin.b, st);
+    (void)hipEventRecord(t_all.b, st);
+    KNN_HIP(hipStreamSynchronize(st));
+    if (stats) {
+        stats->iters = iters;
+        stats->build_k = K;
+        for (int i = iters; i < KNN_MAX_ITERS_LOGGED; ++i) {
+            stats->updates[i] = stats->emitted[i] = 0;
+            stats->ms_join_iter[i] = 0.0f;
+        }
+        const int rb = bf ? 2 : 4;
+        stats->bytes_gathered = gathered * (uint64_t)X.d * (uint64_t)rb;
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, t_all.a, t_all.b);
+        stats->ms_total = ms;
+        (void)hipEventElapsedTime(&ms, t_init.a, t_init.b);
+        stats->ms_init = ms;
+        (void)hipEventElapsedTime(&ms, t_fin.a, t_fin.b);
+        stats->ms_final = ms;
+        stats->ms_sample = ms_sample;
+        stats->ms_join = ms_join;
+        stats->ms_merge = ms_merge;
+    }
+    return KNN_OK;
+}
+
+}  // namespace knn
+
+using namespace knn;
+
+extern "C" void knn_nnd_default_params(int32_t k, knn_nnd_params* p)
+{
+    if (!p) return;
+    p->k = k;
+    p->build_k = 0;
+    p->max_iters = 20;
+    p->sample_rate = 0.5f;
+    p->delta = 0.015f;
+    p->seed = 0;
+    p->precision = KNN_PREC_FP32;
+    p->out_kind = KNN_OUT_L2;
+    p->init_kind = KNN_INIT_RANDOM;
+    p->encoder = nullptr;
+    p->proj_count = 0;
+    p->proj_window = 0;
+    p->cand_slots = 0;
+    p->join_cap = 0;
+    p->workspace_limit_bytes = 0;
+}
+
+extern "C" knn_status nndescent_build(knn_matrix X, const knn_nnd_params* p, int32_t* out_idx,
+                                      float* out_dist, int32_t* state_idx, float* state_dist,
+                                      uint8_t* state_flags, knn_nnd_stats* stats, void* stream)
+{
+    try {
+        return nnd_run(X, p, nullptr, nullptr, nullptr, 0, 0, out_idx, out_dist, state_idx,
+                       state_dist, state_flags, stats, (hipStream_t)stream);
+    } catch (...) {
+        return fail(KNN_EDEVICE, "unexpected exception");
+    }
+}
+
+extern "C" knn_status nndescent_refine(knn_matrix X, const knn_nnd_params* p,
+                                       const int32_t* init_idx, const float* init_dist,
+                                       const uint8_t* init_flags, int32_t init_k,
+                                       int32_t iter_offset, int32_t* out_idx, float* out_dist,
+                                       int32_t* state_idx, float* state_dist,
+                                       uint8_t* state_flags, knn_nnd_stats* stats, void* stream)
+{
+    try {
+        if (!init_idx) return fail(KNN_EINVAL, "init_idx is null");
+        return nnd_run(X, p, init_idx, init_dist, init_flags, init_k, iter_offset, out_idx,
+                       out_dist, state_idx, state_dist, state_flags, stats, (hipStream_t)stream);
+    } catch (...) {
+        return fail(KNN_EDEVICE, "unexpected exception");
+    }
+}

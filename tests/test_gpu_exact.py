@@ -1,0 +1,151 @@
+"""Exact path (knn_exact / knn_exact_query) on the GPU against the CPU oracle.
+
+Bar (FP32 precision): indices equal to the oracle's except inside near-tie
+groups (distances within 1e-5 relative), returned distances within 1e-5
+relative of the fp64 distance of the returned pair.  The BF16 form is
+approximate by design and is judged by recall and distance error.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2603_04035_amd import datagen
+from oracle.compare import exact_parity, parity_ok
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda").to(dtype)
+
+
+def _run(X, k, **kw):
+    import paper_2603_04035_amd as knn
+    idx, dist = knn.knn_exact(_dev(X), k, **kw)
+    torch.cuda.synchronize()
+    return idx.cpu().numpy(), dist.cpu().numpy()
+
+
+def _assert_parity(orc, X, k, rows=None, **kw):
+    import paper_2603_04035_amd as knn
+    rows = np.arange(len(X)) if rows is None else np.asarray(rows)
+    G, D = _run(X, k, **kw)
+    O, _ = orc.exact_knn(X, k, rows=rows)
+    res = exact_parity(X, rows, G[rows], D[rows], O)
+    assert parity_ok(res), res
+    return G, D, res
+
+
+def test_config1_full(orc):
+    X = datagen.gmm_isotropic(n=5000, d=50, seed=0)
+    _, _, res = _assert_parity(orc, X, 15)
+    print(res)
+
+
+@pytest.mark.parametrize("n,d,k", [(2, 3, 1), (3, 1, 2), (17, 5, 16), (129, 7, 10),
+                                   (333, 64, 15), (1000, 33, 32), (257, 130, 9)])
+def test_ragged_shapes(orc, n, d, k):
+    X = datagen.gmm_isotropic(n=n, d=d, seed=n + d)
+    _assert_parity(orc, X, k)
+
+
+def test_lattice_ties_exact_order(orc):
+    """Integer lattice: distances are exact in FP32 too, so the index tie-break
+    must reproduce the oracle bit for bit."""
+    X = datagen.lattice(36, 2, seed=3)       # 1296 points, shells of 4/8 equal distances
+    G, D = _run(X, 20, out="sql2")
+    O, O2 = orc.exact_knn(X, 20)
+    assert np.array_equal(G, O)
+    assert np.array_equal(D.astype(np.float64), O2)   # small integers: exact in FP32
+    X3 = datagen.lattice(11, 3, seed=4)
+    G3, _ = _run(X3, 26)
+    O3, _ = orc.exact_knn(X3, 26)
+    assert np.array_equal(G3, O3)
+
+
+def test_duplicates_zero_first(orc):
+    X = datagen.with_duplicates(400, 12, 3, seed=5)
+    G, D, _ = _assert_parity(orc, X, 6)
+    assert np.all(D[:, :2] == 0.0) and np.all(D[:, 2] > 0.0)
+
+
+def test_squared_output_and_rerank_width(orc):
+    X = datagen.gmm_isotropic(n=2000, d=20, seed=7)
+    import paper_2603_04035_amd as knn
+    for kp in (10, 17, 32):
+        G, D = _run(X, 10, rerank_k=kp, out="sql2")
+        O, _ = orc.exact_knn(X, 10)
+        res = exact_parity(X, np.arange(2000), G, D, O, squared=True)
+        assert parity_ok(res), (kp, res)
+
+
+@pytest.mark.parametrize("dt", [torch.bfloat16, torch.float16])
+def test_low_precision_storage(orc, dt):
+    """BF16 / FP16 inputs: the oracle sees the same stored values (exact upcast)."""
+    X = datagen.gmm_isotropic(n=3000, d=40, seed=8)
+    Xt = _dev(X, dt)
+    Xs = Xt.float().cpu().numpy()
+    import paper_2603_04035_amd as knn
+    idx, dist = knn.knn_exact(Xt, 12)
+    O, _ = orc.exact_knn(Xs, 12)
+    res = exact_parity(Xs, np.arange(3000), idx.cpu().numpy(), dist.cpu().numpy(), O)
+    assert parity_ok(res), res
+
+
+def test_strided_rows(orc):
+    X = datagen.gmm_isotropic(n=1500, d=30, seed=9)
+    big = np.zeros((1500, 47), dtype=np.float32)
+    big[:, :30] = X
+    import paper_2603_04035_amd as knn
+    T = _dev(big)[:, :30]
+    idx, dist = knn.knn_exact(T, 8)
+    O, _ = orc.exact_knn(X, 8)
+    res = exact_parity(X, np.arange(1500), idx.cpu().numpy(), dist.cpu().numpy(), O)
+    assert parity_ok(res), res
+
+
+def test_query_form(orc):
+    import paper_2603_04035_amd as knn
+    R = datagen.gmm_isotropic(n=4000, d=24, seed=10)
+    Q = datagen.gmm_isotropic(n=300, d=24, seed=11)
+    idx, dist = knn.knn_exact_query(_dev(Q), _dev(R), 15)
+    O, _ = orc.exact_query(R, Q, 15)
+    allx = np.concatenate([Q, R])
+    # map R indices into the stacked array for the comparator
+    res = exact_parity(allx, np.arange(300), idx.cpu().numpy() + 300, dist.cpu().numpy(), O + 300)
+    assert parity_ok(res), res
+    # with self exclusion: queries are rows of R
+    rows = datagen.sample_queries(4000, 200, seed=3)
+    idx, dist = knn.knn_exact_query(_dev(R[rows]), _dev(R), 15, q_self=rows)
+    O, _ = orc.exact_knn(R, 15, rows=rows)
+    res = exact_parity(R, rows, idx.cpu().numpy(), dist.cpu().numpy(), O)
+    assert parity_ok(res), res
+
+
+def test_pixel_70k_sampled(orc):
+    """70,000 x 784 pixel-like data at full size, 150 sampled rows checked."""
+    X = datagen.pixel_like(n=70000, seed=0)
+    rows = datagen.sample_queries(70000, 150, seed=2)
+    _assert_parity(orc, X, 15, rows=rows)
+
+
+def test_gmm_1m_sampled(orc):
+    """1,000,000 x 50 anisotropic mixture at full size, 100 sampled rows checked."""
+    X = datagen.gmm_anisotropic(n=1_000_000, d=50, comps=50, seed=0)
+    rows = datagen.sample_queries(1_000_000, 100, seed=2)
+    _assert_parity(orc, X, 15, rows=rows)
+
+
+def test_bf16_precision_recall_and_error(orc):
+    """BF16 MFMA candidates + FP32 re-rank: distances of the returned pairs are
+    FP32-exact; recall against the oracle is reported and bounded below."""
+    X = datagen.pixel_like(n=20000, seed=1)
+    rows = datagen.sample_queries(20000, 300, seed=2)
+    G, D = _run(X, 15, precision="bf16", rerank_k=30)
+    O, O2 = orc.exact_knn(X, 15, rows=rows)
+    res = exact_parity(X, rows, G[rows], D[rows], O)
+    # distances of returned pairs are re-ranked in FP32: always within 1e-5
+    assert res["dist_err"] == 0 and res["self"] == 0 and res["dup"] == 0, res
+    r = orc.recall_at_k(X, rows, G[rows], np.sqrt(O2[:, -1]), 15)
+    print("bf16 recall", r)
+    assert r >= 0.99, r

@@ -30,9 +30,13 @@ HBM_PEAK_GBS = 8000.0
 
 # NNDescent settings of the two forms (K_b, rho, caps); delta is the paper's 0.015.
 FORMS = {
-    "fp32": dict(precision="fp32", build_k=24, sample_rate=0.5, max_iters=30, delta=0.015,
-                 join_cap=8, cand_slots=32),
+    "fp32": dict(precision="fp32", build_k=32, sample_rate=1.0, max_iters=30, delta=0.015,
+                 join_cap=4, cand_slots=64),
+    "bf16-learned": dict(precision="bf16", build_k=32, sample_rate=1.0, max_iters=30, delta=0.015,
+                         join_cap=4, cand_slots=64, init_kind="encoder", proj_count=4, proj_window=8),
 }
+# encoder training (reported separately, not in the timed region)
+TRAIN = dict(n=100_000, seed=100, k=15, steps=1000, batch=4096, lr=2e-3)
 
 CONFIGS = {
     "gmm1m": dict(n=1_000_000, d=50, desc="1,000,000 x 50 FP32, 50-component anisotropic GMM, k=15"),
@@ -40,12 +44,32 @@ CONFIGS = {
 }
 
 
-def make_data(config: str):
+def make_data(config: str, seed: int = 0, n=None):
     from paper_2603_04035_amd import datagen
     c = CONFIGS[config]
+    n = c["n"] if n is None else n
     if config == "gmm1m":
-        return datagen.gmm_anisotropic(n=c["n"], d=c["d"], comps=50, seed=0)
-    return datagen.pixel_like(n=c["n"], seed=0)
+        return datagen.gmm_anisotropic(n=n, d=c["d"], comps=50, seed=seed)
+    return datagen.pixel_like(n=n, seed=seed)
+
+
+def train_encoder(config: str):
+    """Encoder trained on a fresh sample of the same distribution and its exact graph."""
+    import torch
+    import paper_2603_04035_amd as knn
+    Xt = torch.from_numpy(make_data(config, seed=TRAIN["seed"], n=TRAIN["n"])).to("cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    idx, _ = knn.knn_exact(Xt, TRAIN["k"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    enc = knn.Encoder(Xt.shape[1], seed=1)
+    log = enc.train(Xt, idx, steps=TRAIN["steps"], batch=TRAIN["batch"], lr=TRAIN["lr"], seed=3)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return enc, {"train_points": TRAIN["n"], "exact_graph_s": round(t1 - t0, 3),
+                 "train_s": round(t2 - t1, 3), "steps": TRAIN["steps"], "batch": TRAIN["batch"],
+                 "loss_first": float(log[:20].mean()), "loss_last": float(log[-20:].mean())}
 
 
 def recall_gpu(X, G, D, rows, k):
@@ -64,7 +88,7 @@ def cpu_baseline(Xnp, k, form, sample_n):
     """The CPU oracle's sequential NNDescent on the first sample_n rows."""
     import oracle
     sub = Xnp[:sample_n]
-    p = FORMS[form]
+    p = dict(FORMS[form], build_k=20, sample_rate=0.5)
     t0 = time.perf_counter()
     oracle.nndescent(sub, p["build_k"], max_iters=p["max_iters"], rho=p["sample_rate"],
                      delta=p["delta"], seed=0)
@@ -75,13 +99,62 @@ def cpu_baseline(Xnp, k, form, sample_n):
                       f"{dt:.1f} s"}
 
 
+def join_roofline(stats, n, d, p, kernel):
+    """Local-join roofline: algorithmic bytes per launch / HIP-event time per launch."""
+    import numpy as np
+    K = stats[-1]["build_k"]
+    s_ = int(np.ceil(p["sample_rate"] * K))
+    rb = 2 if p["precision"] == "bf16" else 4
+    launches = sum(st["iters"] for st in stats)
+    gathered_rows = sum(st["bytes_gathered"] for st in stats) / (d * rb)
+    emitted = sum(sum(st["emitted"]) for st in stats)
+    list_bytes = launches * n * (4 * s_ + 4 * K + 2 * 16 * s_)   # new_f, old_f, reverse slots read+reset
+    alg_bytes = gathered_rows * (d * rb + 8) + list_bytes + 8 * emitted
+    join_ms = sum(st["ms_join"] for st in stats)
+    achieved = alg_bytes / (join_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel,
+            "launches": launches, "alg_bytes_per_launch": int(alg_bytes / max(launches, 1)),
+            "ms_per_launch": round(join_ms / max(launches, 1), 4)}
+
+
+def run_form(X, k, form, steps, warmup, rows, encoder=None):
+    import torch
+    import paper_2603_04035_amd as knn
+    p = dict(FORMS[form])
+    if p.get("init_kind") == "encoder":
+        p["encoder"] = encoder
+    for w in range(warmup):
+        knn.nndescent_build(X, k, seed=1000 + w, **p)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for s in range(steps):
+        G, D, st = knn.nndescent_build(X, k, seed=s, **p)
+        stats.append(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n, d = X.shape
+    recall = recall_gpu(X, G, D, rows, k)
+    kern = "nnd_join_bf16_kernel" if p["precision"] == "bf16" else "nnd_join_f32_kernel"
+    last = stats[-1]
+    cfg = {kk: vv for kk, vv in p.items() if kk != "encoder"}
+    cfg["build_k"] = last["build_k"]
+    return {"value": round(n * steps / wall, 1), "ms_per_step": round(1000.0 * wall / steps, 3),
+            "recall_at_15": round(recall, 5), "recall_ok": recall >= 0.98, "iters": last["iters"],
+            "params": cfg,
+            "ms_breakdown": {kk: round(last[kk], 3) for kk in
+                             ("ms_init", "ms_sample", "ms_join", "ms_merge", "ms_final", "ms_total")},
+            "roofline": join_roofline(stats, n, d, p, kern)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="gmm1m", choices=sorted(CONFIGS))
-    ap.add_argument("--form", default="fp32", choices=sorted(FORMS))
+    ap.add_argument("--form", default="both", choices=sorted(FORMS) + ["both"])
     ap.add_argument("--k", type=int, default=15)
     ap.add_argument("--recall-rows", type=int, default=10000)
     ap.add_argument("--cpu-sample", type=int, default=100_000)
@@ -90,77 +163,45 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the kNN graph build here runs on a single device; "
-              "multi-GPU runs are not part of this build (see DESIGN.md for how it would shard).",
+              "multi-GPU runs are not part of this build (DESIGN.md describes how it would shard).",
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    import paper_2603_04035_amd as knn
     from paper_2603_04035_amd import datagen
 
     k = args.k
     Xnp = make_data(args.config)
     n, d = Xnp.shape
     X = torch.from_numpy(Xnp).to("cuda")
-    p = dict(FORMS[args.form])
     torch.cuda.synchronize()
-
-    for w in range(args.warmup):
-        knn.nndescent_build(X, k, seed=1000 + w, **p)
-    torch.cuda.synchronize()
-
-    stats = []
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        G, D, st = knn.nndescent_build(X, k, seed=s, **p)
-        stats.append(st)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
-    ms_per_step = 1000.0 * wall / args.steps
-    value = n * args.steps / wall
-
     rows = datagen.sample_queries(n, args.recall_rows, seed=2)
-    recall = recall_gpu(X, G, D, rows, k)
-
-    # local-join roofline: algorithmic bytes per launch / HIP-event time per launch
-    K = stats[-1]["build_k"]
-    srate = p["sample_rate"]
-    s_ = int(np.ceil(srate * K))
-    rb = 4
-    launches = sum(st["iters"] for st in stats)
-    gathered_rows = sum(st["bytes_gathered"] for st in stats) / (d * rb)
-    emitted = sum(sum(st["emitted"]) for st in stats)
-    list_bytes = launches * n * (4 * s_ + 4 * K + 2 * 16 * s_)   # new_f, old_f, reverse slots read+reset
-    alg_bytes = gathered_rows * (d * rb + 8) + list_bytes + 8 * emitted
-    join_ms = sum(st["ms_join"] for st in stats)
-    achieved = alg_bytes / (join_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "nnd_join_f32_kernel", "launches": launches,
-                "alg_bytes_per_launch": int(alg_bytes / max(launches, 1)),
-                "ms_per_launch": round(join_ms / max(launches, 1), 4)}
+    forms = ["fp32", "bf16-learned"] if args.form == "both" else [args.form]
+    results, training = {}, None
+    encoder = None
+    if "bf16-learned" in forms:
+        encoder, training = train_encoder(args.config)
+    for f in forms:
+        results[f] = run_form(X, k, f, args.steps, args.warmup, rows, encoder)
+    head = "bf16-learned" if "bf16-learned" in results else forms[0]
+    h = results[head]
 
     cpu = None
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
-        cpu = cpu_baseline(Xnp, k, args.form, min(args.cpu_sample, n))
+        cpu = cpu_baseline(Xnp, k, "fp32", min(args.cpu_sample, n))
 
-    last = stats[-1]
     out = {
         "metric": "kNN graph build points/sec at recall@15>=0.98 (NNDescent)",
-        "value": round(value, 1), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.form == "fp32" else "bf16",
-        "data": "synthetic",
-        "config": {"workload": CONFIGS[args.config]["desc"], "form": args.form, "k": k,
-                   "build_k": K, "sample_rate": srate, "delta": p["delta"],
-                   "join_cap": p.get("join_cap"), "cand_slots": p.get("cand_slots")},
-        "recall_at_15": round(recall, 5), "recall_ok": recall >= 0.98,
-        "iters": last["iters"], "ms_breakdown": {kk: round(last[kk], 3) for kk in
-                                                 ("ms_init", "ms_sample", "ms_join", "ms_merge", "ms_final", "ms_total")},
-        "roofline": roofline,
+        "value": h["value"], "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": h["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16" if FORMS[head]["precision"] == "bf16" else "f32", "data": "synthetic",
+        "config": {"workload": CONFIGS[args.config]["desc"], "form": head, "k": k},
+        "recall_at_15": h["recall_at_15"], "recall_ok": h["recall_ok"],
+        "roofline": h["roofline"],
         "cpu_baseline": cpu,
+        "forms": results,
+        "encoder_training": training,
     }
     print(json.dumps(out), flush=True)
 

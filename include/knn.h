@@ -115,10 +115,11 @@ typedef struct {
     int32_t out_kind;     /* KNN_OUT_L2 / KNN_OUT_SQL2 */
     int32_t init_kind;    /* KNN_INIT_RANDOM or KNN_INIT_ENCODER */
     const knn_encoder* encoder;  /* required for KNN_INIT_ENCODER */
-    int32_t proj_count;   /* encoder init: number of sorted projections P (0: 4) */
+    int32_t proj_count;   /* encoder init: number of sorted orders P (0: 4) */
     int32_t proj_window;  /* encoder init: neighbours taken on each side per order (0: 8) */
+    int32_t proj_dims;    /* encoder init: projections per order key D in {1,2,4,8} (0: 8) */
     int32_t cand_slots;   /* hashed candidate slots per row and iteration, <= 64 - K_b (0: 32) */
-    int32_t join_cap;     /* max candidates one join list sends to one member (0: default) */
+    int32_t join_cap;     /* max candidates one join list sends to one member, <= 4 (0: 4) */
     int64_t workspace_limit_bytes; /* 0: no limit; else KNN_ENOMEM when scratch exceeds it */
 } knn_nnd_params;
 
@@ -226,17 +227,22 @@ knn_status knn_encoder_train(knn_encoder* enc, knn_matrix X, const int32_t* knn_
                              const knn_train_params* t, float* loss_log, void* stream);
 
 /*
- * Seed lists from sorted projections: keys Z . dirs[p] (FP32), each point
- * takes the w predecessors and successors in every order sorted by
- * (key, index); candidates (self removed, duplicates merged) are ranked by
+ * Seed lists from sorted projections of an embedding Z.  Order p uses the D
+ * directions dirs[p*D .. p*D+D): the projections Z . r are FP32 sums in
+ * coordinate order; D = 1 sorts by the projection itself, D > 1 by the
+ * Z-order code of the D projections, each quantised to 32/D bits over its
+ * range across all points.  Points are sorted by (key, index) with a stable
+ * radix sort; each point takes the w predecessors and successors in every
+ * order; candidates (self removed, repeats merged) are ranked by canonical
  * FP32 squared input distance and the best K kept, sorted by (distance,
  * index); rows with fewer than K candidates are padded with -1 / +inf.
- *  Z     device, n x m float (m <= 64).   dirs  device, P x m float.
- *  out_idx / out_dist  device, n x K.
+ *  Z     device, n x m float (m <= 64).   dirs  device, (P*D) x m float.
+ *  D in {1, 2, 4, 8};  2*w*P <= 64;  K <= 64.
+ *  out_idx / out_dist  device, n x K (squared distances).
  */
 knn_status knn_proj_seed(knn_matrix X, const float* Z, int32_t m, const float* dirs,
-                         int32_t P, int32_t w, int32_t K, int32_t* out_idx, float* out_dist,
-                         void* stream);
+                         int32_t P, int32_t D, int32_t w, int32_t K, int32_t* out_idx,
+                         float* out_dist, void* stream);
 
 #ifdef __cplusplus
 }

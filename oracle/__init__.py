@@ -76,8 +76,12 @@ def _load():
     lib.oracle_mlp_backward.restype = None
     lib.oracle_adam_step.argtypes = [_dp, _dp, _dp, _dp, i64, f64, f64, f64, f64, i32]
     lib.oracle_adam_step.restype = None
-    lib.oracle_proj_seed.argtypes = [_dp, i64, i64, i32, _dp, i32, _dp, i32, i32, i32, _ip, _dp]
+    _fp = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
+    lib.oracle_proj_seed.argtypes = [_dp, i64, i64, i32, _fp, i32, _fp, i32, i32, i32, i32, _ip, _dp]
     lib.oracle_proj_seed.restype = i32
+    lib.oracle_proj_keys.argtypes = [_fp, i64, i32, _fp, i32,
+                                     np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS"), _fp]
+    lib.oracle_proj_keys.restype = i32
     _lib = lib
     return lib
 
@@ -205,13 +209,34 @@ def adam_step(w, g, m, v, t: int, lr: float = 1e-3, beta1: float = 0.9,
                              w.size, lr, beta1, beta2, eps, int(t))
 
 
-def proj_seed(X, Z, dirs, w: int, K: int):
-    """Sorted-projection seed lists: (idx n x K with -1 pads, squared dist)."""
-    X, Z, dirs = _f64(X), _f64(Z), _f64(dirs)
+def proj_seed(X, Z, dirs, w: int, K: int, D: int = 1):
+    """Sorted-projection seed lists: (idx n x K with -1 pads, squared dist).
+
+    Z and dirs are taken as FP32 (the projections decide an order, so they are
+    computed in the kernel's precision); dirs has P*D rows, D per curve.
+    """
+    X = _f64(X)
+    Z = np.ascontiguousarray(np.asarray(Z, dtype=np.float32))
+    dirs = np.ascontiguousarray(np.asarray(dirs, dtype=np.float32))
     n, d = X.shape
+    if dirs.shape[0] % D:
+        raise ValueError("dirs must hold P*D rows")
+    P = dirs.shape[0] // D
     idx = np.empty((n, K), dtype=np.int64)
     d2 = np.empty((n, K), dtype=np.float64)
-    rc = _load().oracle_proj_seed(X, n, d, d, Z, Z.shape[1], dirs, dirs.shape[0], w, K, idx, d2)
+    rc = _load().oracle_proj_seed(X, n, d, d, Z, Z.shape[1], dirs, P, D, w, K, idx, d2)
     if rc != 0:
         raise ValueError("oracle_proj_seed: bad arguments")
     return idx, d2
+
+
+def proj_keys(Z, dirs, D: int = 1) -> np.ndarray:
+    """Order keys of one curve (dirs: D x m): ordered projection or Z-order code."""
+    Z = np.ascontiguousarray(np.asarray(Z, dtype=np.float32))
+    dirs = np.ascontiguousarray(np.asarray(dirs, dtype=np.float32))
+    n = Z.shape[0]
+    keys = np.empty(n, dtype=np.uint32)
+    y = np.empty(n * D, dtype=np.float32)
+    if _load().oracle_proj_keys(Z, n, Z.shape[1], dirs, D, keys, y) != 0:
+        raise ValueError("oracle_proj_keys: bad D")
+    return keys

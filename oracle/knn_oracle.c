@@ -517,7 +517,7 @@ void oracle_adam_step(double* w, const double* g, double* mom, double* vel, int6
 /* ---------------------------------------------- sorted-projection seeding */
 
 typedef struct {
-    double key;
+    uint32_t key;
     int64_t idx;
 } keyed_t;
 
@@ -525,40 +525,103 @@ static int keyed_cmp(const void* a, const void* b)
 {
     const keyed_t* x = (const keyed_t*)a;
     const keyed_t* y = (const keyed_t*)b;
-    if (x->key < y->key) return -1;
-    if (x->key > y->key) return 1;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
     return (x->idx > y->idx) - (x->idx < y->idx);
 }
 
+/* Order-preserving map of an FP32 value to uint32 (both zeros map alike). */
+static uint32_t f32_order(float f)
+{
+    uint32_t u;
+    if (f == 0.0f) return 0x80000000u;
+    memcpy(&u, &f, 4);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
 /*
- * Seed lists from sorted projections of an embedding Z (n x m).  For each
- * direction p (row of dirs, P x m) the points are ordered by (Z_i . r_p, i);
- * each point's candidates are the w predecessors and w successors in every
- * order.  The candidate set (self removed, duplicates merged) is ranked by
- * exact squared input distance D and the best K are kept, sorted by (D, idx).
- * Rows with fewer than K candidates get -1 / +inf in the remaining slots
- * (the caller completes them).
+ * Seed lists from sorted projections of an embedding Z (n x m).
+ *
+ * Curve p (0 <= p < P) uses the D directions dirs[p*D .. p*D+D) (each of
+ * length m).  Projections are FP32 sums of products taken in coordinate
+ * order with fused multiply-adds, because the order they decide must be the
+ * one the kernel decides.  D = 1: the key is the projection itself (order-
+ * preserving uint32).  D > 1: each projection is quantised to b = 32 / D bits
+ * over its range [lo, hi] across all points, q = min(floor((y - lo) * s),
+ * 2^b - 1) with s = 2^b / (hi - lo) in FP32, and the key interleaves the bits
+ * of q_0..q_{D-1} from the most significant level down (a Z-order code).
+ * Points are sorted by (key, index).  Each point's candidates are the w
+ * predecessors and w successors in every order; self and repeats are
+ * removed; candidates are ranked by exact squared input distance D and the
+ * best K kept, sorted by (D, idx).  Rows with fewer than K candidates are
+ * padded with -1 / +inf.
  */
+/*
+ * Order keys of one curve (see below): directions r_0..r_{D-1} (rows of dirs,
+ * length m).  y is scratch of n*D floats.  Returns 0, or -1 on bad D.
+ */
+int oracle_proj_keys(const float* Z, int64_t n, int m, const float* dirs, int Dk,
+                     uint32_t* keys, float* y)
+{
+    if (Dk < 1 || 32 % Dk != 0) return -1;
+    const int bits = 32 / Dk;
+    for (int j = 0; j < Dk; ++j) {
+        const float* r = dirs + (size_t)j * m;
+        for (int64_t i = 0; i < n; ++i) {
+            float s = 0.0f;
+            for (int t = 0; t < m; ++t) s = fmaf(Z[i * m + t], r[t], s);
+            y[(size_t)j * n + i] = s;
+        }
+    }
+    if (Dk == 1) {
+        for (int64_t i = 0; i < n; ++i) keys[i] = f32_order(y[i]);
+        return 0;
+    }
+    for (int j = 0; j < Dk; ++j) {
+        float lo = y[(size_t)j * n], hi = lo;
+        for (int64_t i = 1; i < n; ++i) {
+            float v = y[(size_t)j * n + i];
+            if (v < lo) lo = v;
+            if (v > hi) hi = v;
+        }
+        const float sc = hi > lo ? (float)(1u << bits) / (hi - lo) : 0.0f;
+        const uint32_t qmax = (1u << bits) - 1u;
+        for (int64_t i = 0; i < n; ++i) {
+            float f = floorf((y[(size_t)j * n + i] - lo) * sc);
+            uint32_t q = f <= 0.0f ? 0u : (uint32_t)f;
+            y[(size_t)j * n + i] = (float)(q < qmax ? q : qmax);   /* reuse as the code */
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t key = 0;
+        for (int l = bits - 1; l >= 0; --l)
+            for (int j = 0; j < Dk; ++j)
+                key = (key << 1) | (((uint32_t)y[(size_t)j * n + i] >> l) & 1u);
+        keys[i] = key;
+    }
+    return 0;
+}
+
 int oracle_proj_seed(const double* X, int64_t n, int64_t ld, int d,
-                     const double* Z, int m, const double* dirs, int P, int w, int K,
+                     const float* Z, int m, const float* dirs, int P, int Dk, int w, int K,
                      int64_t* out_idx, double* out_d2)
 {
-    if (n < 2 || K < 1 || w < 1 || P < 1) return -1;
+    if (n < 2 || K < 1 || w < 1 || P < 1 || Dk < 1 || 32 % Dk != 0) return -1;
     keyed_t* ord = (keyed_t*)malloc(sizeof(keyed_t) * (size_t)n * P);
     int64_t* pos = (int64_t*)malloc(sizeof(int64_t) * (size_t)n * P);
+    float* y = (float*)malloc(sizeof(float) * (size_t)n * Dk);
+    uint32_t* keys = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n);
     int cap = 2 * w * P;
     int64_t* cand = (int64_t*)malloc(sizeof(int64_t) * (size_t)cap);
-    if (!ord || !pos || !cand) {
-        free(ord); free(pos); free(cand);
+    if (!ord || !pos || !y || !keys || !cand) {
+        free(ord); free(pos); free(y); free(keys); free(cand);
         return -1;
     }
     for (int p = 0; p < P; ++p) {
         keyed_t* o = ord + (size_t)p * n;
+        oracle_proj_keys(Z, n, m, dirs + (size_t)p * Dk * m, Dk, keys, y);
         for (int64_t i = 0; i < n; ++i) {
-            double s = 0.0;
-            for (int t = 0; t < m; ++t) s += Z[i * m + t] * dirs[p * m + t];
-            o[i].key = s;
             o[i].idx = i;
+            o[i].key = keys[i];
         }
         qsort(o, (size_t)n, sizeof(keyed_t), keyed_cmp);
         for (int64_t r = 0; r < n; ++r) pos[(size_t)p * n + o[r].idx] = r;
@@ -578,28 +641,30 @@ int oracle_proj_seed(const double* X, int64_t n, int64_t ld, int d,
             }
         }
         int64_t* I = out_idx + i * K;
-        double* D = out_d2 + i * K;
+        double* Dd = out_d2 + i * K;
         int cnt = 0;
         for (int q = 0; q < nc; ++q) {
             int64_t u = cand[q];
             double l = sqdist(X + i * ld, X + u * ld, d);
-            if (cnt == K && !pair_less(l, u, D[K - 1], I[K - 1])) continue;
+            if (cnt == K && !pair_less(l, u, Dd[K - 1], I[K - 1])) continue;
             int pp = (cnt < K) ? cnt++ : K - 1;
-            while (pp > 0 && pair_less(l, u, D[pp - 1], I[pp - 1])) {
-                D[pp] = D[pp - 1];
+            while (pp > 0 && pair_less(l, u, Dd[pp - 1], I[pp - 1])) {
+                Dd[pp] = Dd[pp - 1];
                 I[pp] = I[pp - 1];
                 --pp;
             }
-            D[pp] = l;
+            Dd[pp] = l;
             I[pp] = u;
         }
         for (int r = cnt; r < K; ++r) {
             I[r] = -1;
-            D[r] = INFINITY;
+            Dd[r] = INFINITY;
         }
     }
     free(ord);
     free(pos);
+    free(y);
+    free(keys);
     free(cand);
     return 0;
 }

@@ -45,6 +45,7 @@ class knn_nnd_params(C.Structure):
                 ("sample_rate", C.c_float), ("delta", C.c_float), ("seed", C.c_uint64),
                 ("precision", C.c_int32), ("out_kind", C.c_int32), ("init_kind", C.c_int32),
                 ("encoder", C.c_void_p), ("proj_count", C.c_int32), ("proj_window", C.c_int32),
+                ("proj_dims", C.c_int32),
                 ("cand_slots", C.c_int32), ("join_cap", C.c_int32),
                 ("workspace_limit_bytes", C.c_int64)]
 
@@ -127,7 +128,7 @@ def load() -> C.CDLL:
     lib.knn_encoder_train.restype = i32
     lib.knn_encoder_train.argtypes = [vp, knn_matrix, vp, i32, C.POINTER(knn_train_params), vp, vp]
     lib.knn_proj_seed.restype = i32
-    lib.knn_proj_seed.argtypes = [knn_matrix, vp, i32, vp, i32, i32, i32, vp, vp, vp]
+    lib.knn_proj_seed.argtypes = [knn_matrix, vp, i32, vp, i32, i32, i32, i32, vp, vp, vp]
     _lib = lib
     return lib
 

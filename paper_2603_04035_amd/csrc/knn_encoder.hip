@@ -1,52 +1,830 @@
-// Learned seeding (encoder MLP, sorted projections) and the BF16 local join.
-// Placeholder entry points until the kernels land.
+// Learned seeding for NNDescent: an MLP encoder d -> 64 -> 32 (ReLU) trained
+// with a triplet loss on k-NN graphs the library builds, and sorted
+// projections of its embedding that give every point initial candidates.
+//
+// Training kernels (all FP32, deterministic):
+//   triplets   anchor / positive (one of the anchor's k neighbours) / negative
+//              drawn from the counter-based hash;
+//   forward    one thread per batch row: h = relu(b1 + x W1), z = b2 + h W2;
+//   loss       one thread per triplet: max(0, m + |za-zp|^2 - |za-zn|^2) and
+//              dL/dz for the three rows; the loss is summed by a fixed tree;
+//   backward   dh = (dz W2^T) masked by h > 0; every weight gradient is a sum
+//              over batch rows, taken in two stages (per-chunk partial sums
+//              in row order, then a sum over chunks in order), never with
+//              floating-point atomics, so results are bitwise reproducible;
+//   adam       elementwise update with bias correction.
+// Seeding: keys z . r_p for P seeded unit directions, mapped to order-
+// preserving u32 and sorted with a stable LSD radix sort (4 x 8-bit passes,
+// index payload, so equal keys stay in index order); each point then takes
+// the w predecessors and successors in every order, drops itself and
+// repeats, ranks them by FP32 squared input distance and keeps the best K.
+#include <math.h>
+
+#include <vector>
+
 #include "knn_common.hpp"
 
+struct knn_encoder {
+    int d = 0;
+    int P = 0;          // parameter count
+    float* params = nullptr;   // W1 [d][64] | b1 [64] | W2 [64][32] | b2 [32]
+    float* mom = nullptr;
+    float* vel = nullptr;
+    int t = 0;          // Adam steps taken
+};
+
 namespace knn {
-knn_status encoder_seed(const knn_encoder*, const knn_matrix&, int, int, int, uint64_t, Workspace&,
-                        int32_t**, float**, hipStream_t)
+
+constexpr int H1 = KNN_ENC_H1, H2 = KNN_ENC_H2;
+
+struct Off {
+    int W1, b1, W2, b2, P;
+    __host__ __device__ explicit Off(int d) : W1(0), b1(d * H1), W2(d * H1 + H1), b2(d * H1 + H1 + H1 * H2),
+                          P(d * H1 + H1 + H1 * H2 + H2) {}
+};
+
+int encoder_dim(const knn_encoder* enc) { return enc ? enc->d : -1; }
+
+// ---------------------------------------------------------------- forward
+
+// One thread per row (rows[i], or i when rows is null).  H (nullable) gets the
+// post-ReLU hidden layer, Z the embedding.  Sums run in input order from the
+// bias, as fused multiply-adds.
+template <int DT>
+__global__ __launch_bounds__(256) void mlp_forward_kernel(const void* __restrict__ X, int64_t ld, int d,
+                                                          const int32_t* __restrict__ rows, int64_t m,
+                                                          const float* __restrict__ prm,
+                                                          float* __restrict__ H, float* __restrict__ Z)
 {
-    return fail(KNN_ENOTSUP, "encoder seeding not built yet");
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const Off o(d);
+    const int64_t r = rows ? (int64_t)rows[i] : i;
+    float h[H1];
+#pragma unroll
+    for (int j = 0; j < H1; ++j) h[j] = prm[o.b1 + j];
+    for (int t = 0; t < d; ++t) {
+        const float x = elem<DT>::ld(X, r * ld + t);
+        const float* w = prm + o.W1 + t * H1;
+#pragma unroll
+        for (int j = 0; j < H1; ++j) h[j] = fmaf(x, w[j], h[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < H1; ++j) h[j] = h[j] > 0.0f ? h[j] : 0.0f;
+    if (H) {
+#pragma unroll
+        for (int j = 0; j < H1; ++j) H[i * H1 + j] = h[j];
+    }
+    float z[H2];
+#pragma unroll
+    for (int q = 0; q < H2; ++q) z[q] = prm[o.b2 + q];
+#pragma unroll
+    for (int j = 0; j < H1; ++j) {
+        const float* w = prm + o.W2 + j * H2;
+#pragma unroll
+        for (int q = 0; q < H2; ++q) z[q] = fmaf(h[j], w[q], z[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < H2; ++q) Z[i * H2 + q] = z[q];
 }
-int encoder_dim(const knn_encoder*) { return -1; }
+
+// ------------------------------------------------------------------- loss
+
+__global__ __launch_bounds__(256) void triplet_sample_kernel(int64_t n, const int32_t* __restrict__ knn_idx,
+                                                             int k, int B, uint64_t seed, int step,
+                                                             int32_t* __restrict__ rows)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const uint64_t s = seed ^ kTagTriplet;
+    const uint32_t a = bounded(hash4(s, (uint64_t)step, (uint64_t)b, 0), (uint32_t)n);
+    const uint32_t pj = bounded(hash4(s, (uint64_t)step, (uint64_t)b, 1), (uint32_t)k);
+    int32_t p = knn_idx[(int64_t)a * k + pj];
+    if (p < 0 || p >= n) p = (int32_t)a;
+    const uint32_t q = bounded(hash4(s, (uint64_t)step, (uint64_t)b, 2), (uint32_t)n);
+    rows[b] = (int32_t)a;
+    rows[B + b] = p;
+    rows[2 * B + b] = (int32_t)q;
+}
+
+// One thread per triplet; Z rows are [anchors; positives; negatives].
+__global__ __launch_bounds__(256) void triplet_loss_kernel(const float* __restrict__ Z, int B, float margin,
+                                                           float* __restrict__ dZ, float* __restrict__ lterm)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const float* za = Z + (int64_t)b * H2;
+    const float* zp = Z + (int64_t)(B + b) * H2;
+    const float* zn = Z + (int64_t)(2 * B + b) * H2;
+    float dp = 0.0f, dn = 0.0f;
+#pragma unroll
+    for (int q = 0; q < H2; ++q) {
+        const float ep = za[q] - zp[q], en = za[q] - zn[q];
+        dp = fmaf(ep, ep, dp);
+        dn = fmaf(en, en, dn);
+    }
+    const float g = margin + dp - dn;
+    const bool act = g > 0.0f;
+    lterm[b] = act ? g : 0.0f;
+    const float sc = 2.0f / (float)B;
+#pragma unroll
+    for (int q = 0; q < H2; ++q) {
+        dZ[(int64_t)b * H2 + q] = act ? sc * (zn[q] - zp[q]) : 0.0f;
+        dZ[(int64_t)(B + b) * H2 + q] = act ? sc * (zp[q] - za[q]) : 0.0f;
+        dZ[(int64_t)(2 * B + b) * H2 + q] = act ? sc * (za[q] - zn[q]) : 0.0f;
+    }
+}
+
+// Fixed-order sum of m values by one workgroup: each thread sums a strided
+// slice in order, then a tree over threads.  out[0] = sum * scale.
+__global__ __launch_bounds__(256) void ordered_sum_kernel(const float* __restrict__ v, int64_t m,
+                                                          float scale, float* __restrict__ out)
+{
+    __shared__ float s[256];
+    float a = 0.0f;
+    for (int64_t i = threadIdx.x; i < m; i += 256) a += v[i];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = s[0] * scale;
+}
+
+// --------------------------------------------------------------- backward
+
+// dH[i][j] = (sum_q dZ[i][q] W2[j][q]) if H[i][j] > 0 else 0.
+__global__ __launch_bounds__(256) void mlp_dh_kernel(int64_t m, int d, const float* __restrict__ prm,
+                                                     const float* __restrict__ H, const float* __restrict__ dZ,
+                                                     float* __restrict__ dH)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const Off o(d);
+    float dz[H2];
+#pragma unroll
+    for (int q = 0; q < H2; ++q) dz[q] = dZ[i * H2 + q];
+    for (int j = 0; j < H1; ++j) {
+        const float* w = prm + o.W2 + j * H2;
+        float a = 0.0f;
+#pragma unroll
+        for (int q = 0; q < H2; ++q) a = fmaf(dz[q], w[q], a);
+        dH[i * H1 + j] = H[i * H1 + j] > 0.0f ? a : 0.0f;
+    }
+}
+
+constexpr int kGradChunk = 256;   // batch rows per partial sum
+
+// partial[c][p] = sum over the rows of chunk c (in order) of the product that
+// defines gradient p: gW1[t][j] = x_t dh_j, gb1[j] = dh_j, gW2[j][q] = h_j dz_q,
+// gb2[q] = dz_q.
+template <int DT>
+__global__ __launch_bounds__(256) void mlp_grad_partial_kernel(const void* __restrict__ X, int64_t ld, int d,
+                                                               const int32_t* __restrict__ rows, int64_t m,
+                                                               const float* __restrict__ H,
+                                                               const float* __restrict__ dZ,
+                                                               const float* __restrict__ dH,
+                                                               float* __restrict__ partial)
+{
+    const Off o(d);
+    const int p = blockIdx.y * blockDim.x + threadIdx.x;
+    if (p >= o.P) return;
+    const int c = blockIdx.x;
+    const int64_t i0 = (int64_t)c * kGradChunk;
+    const int64_t i1 = i0 + kGradChunk < m ? i0 + kGradChunk : m;
+    float a = 0.0f;
+    if (p < o.b1) {
+        const int t = p / H1, j = p % H1;
+        for (int64_t i = i0; i < i1; ++i) {
+            const int64_t r = rows ? (int64_t)rows[i] : i;
+            a = fmaf(elem<DT>::ld(X, r * ld + t), dH[i * H1 + j], a);
+        }
+    } else if (p < o.W2) {
+        const int j = p - o.b1;
+        for (int64_t i = i0; i < i1; ++i) a += dH[i * H1 + j];
+    } else if (p < o.b2) {
+        const int j = (p - o.W2) / H2, q = (p - o.W2) % H2;
+        for (int64_t i = i0; i < i1; ++i) a = fmaf(H[i * H1 + j], dZ[i * H2 + q], a);
+    } else {
+        const int q = p - o.b2;
+        for (int64_t i = i0; i < i1; ++i) a += dZ[i * H2 + q];
+    }
+    partial[(int64_t)c * o.P + p] = a;
+}
+
+__global__ __launch_bounds__(256) void grad_reduce_kernel(const float* __restrict__ partial, int nch, int P,
+                                                          float* __restrict__ g)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    float a = 0.0f;
+    for (int c = 0; c < nch; ++c) a += partial[(int64_t)c * P + p];
+    g[p] = a;
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ w, const float* __restrict__ g,
+                                                   float* __restrict__ mo, float* __restrict__ ve, int P,
+                                                   float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const float gg = g[p];
+    const float mm = b1 * mo[p] + (1.0f - b1) * gg;
+    const float vv = b2 * ve[p] + (1.0f - b2) * gg * gg;
+    mo[p] = mm;
+    ve[p] = vv;
+    w[p] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+// ------------------------------------------------------------ radix sort
+
+constexpr int kRsThreads = 256, kRsItems = 16, kRsTile = kRsThreads * kRsItems;
+
+__global__ __launch_bounds__(256) void rs_hist_kernel(const uint32_t* __restrict__ keys, int64_t n, int shift,
+                                                      uint32_t* __restrict__ counts, int nblk)
+{
+    __shared__ uint32_t hist[256];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    for (int it = 0; it < kRsItems; ++it) {
+        const int64_t e = base + it * kRsThreads + threadIdx.x;
+        if (e < n) atomicAdd(&hist[(keys[e] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * nblk + blockIdx.x] = hist[threadIdx.x];
+}
+
+// Exclusive scan of m counts in place by one workgroup: thread t sums a
+// contiguous run of ceil(m/256) counts, the 256 run totals are scanned in LDS,
+// then every thread rewrites its run.
+__global__ __launch_bounds__(256) void rs_scan_kernel(uint32_t* __restrict__ c, int64_t m)
+{
+    __shared__ uint32_t s[256];
+    const int64_t per = (m + 255) / 256;
+    const int64_t b = threadIdx.x * per, e = b + per < m ? b + per : m;
+    uint32_t sum = 0;
+    for (int64_t i = b; i < e; ++i) sum += c[i];
+    s[threadIdx.x] = sum;
+    __syncthreads();
+    for (int w = 1; w < 256; w <<= 1) {   // Hillis-Steele inclusive scan of the run totals
+        const uint32_t y = (int)threadIdx.x >= w ? s[threadIdx.x - w] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += y;
+        __syncthreads();
+    }
+    uint32_t run = s[threadIdx.x] - sum;
+    for (int64_t i = b; i < e; ++i) {
+        const uint32_t x = c[i];
+        c[i] = run;
+        run += x;
+    }
+}
+
+// Stable scatter of one 8-bit digit: elements of a tile are visited in index
+// order (item-major, then thread); within a wave, lanes with equal digits are
+// ranked by a ballot match over the 8 digit bits; across waves by per-wave
+// counts in LDS; across tiles by the scanned histogram.
+__global__ __launch_bounds__(256) void rs_scatter_kernel(const uint32_t* __restrict__ kin,
+                                                         const uint32_t* __restrict__ vin,
+                                                         uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                         int64_t n, int shift,
+                                                         const uint32_t* __restrict__ offs, int nblk)
+{
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[4][256];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    run[tid] = offs[(int64_t)tid * nblk + blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int it = 0; it < kRsItems; ++it) {
+        const int64_t e = base + it * kRsThreads + tid;
+        const bool valid = e < n;
+        const uint32_t key = valid ? kin[e] : 0u;
+        const uint32_t val = valid ? vin[e] : 0u;
+        const uint32_t dig = (key >> shift) & 255u;
+        uint64_t peers = ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (dig >> b) & 1u;
+            const uint64_t bal = ballot(valid && bit);
+            peers &= bit ? bal : ~bal;
+        }
+        const int rank = __popcll(peers & lt);
+        const int cnt = __popcll(peers);
+        wcnt[0][tid] = 0;
+        wcnt[1][tid] = 0;
+        wcnt[2][tid] = 0;
+        wcnt[3][tid] = 0;
+        __syncthreads();
+        if (valid && rank == 0) wcnt[wv][dig] = (uint32_t)cnt;
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[dig] + (uint32_t)rank;
+            for (int w = 0; w < wv; ++w) pos += wcnt[w][dig];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        run[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+        __syncthreads();
+    }
+}
+
+// Sort (key, value) pairs of length n by key, stable; result in (k0, v0).
+static knn_status radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
+                                   uint32_t* counts, hipStream_t st)
+{
+    const int nblk = (int)ceil_div(n, kRsTile);
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 8 * pass;
+        rs_hist_kernel<<<nblk, kRsThreads, 0, st>>>(k0, n, shift, counts, nblk);
+        rs_scan_kernel<<<1, 256, 0, st>>>(counts, (int64_t)256 * nblk);
+        rs_scatter_kernel<<<nblk, kRsThreads, 0, st>>>(k0, v0, k1, v1, n, shift, counts, nblk);
+        KNN_HIP(hipGetLastError());
+        std::swap(k0, k1);
+        std::swap(v0, v1);
+    }
+    return KNN_OK;   // 4 passes: data is back in the original buffers
+}
+
+// -------------------------------------------------------------- seeding
+
+// Y[q][i] = Z_i . dirs_q (FP32 fused multiply-adds in coordinate order) for
+// the P*D directions q.
+__global__ __launch_bounds__(256) void proj_vals_kernel(const float* __restrict__ Z, int64_t n, int m,
+                                                        const float* __restrict__ dirs, int PD,
+                                                        float* __restrict__ Y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int q = 0; q < PD; ++q) {
+        float s = 0.0f;
+        for (int t = 0; t < m; ++t) s = fmaf(Z[i * m + t], dirs[q * m + t], s);
+        Y[(int64_t)q * n + i] = s;
+    }
+}
+
+__device__ inline uint32_t f32_order(float f)
+{
+    if (f == 0.0f) return 0x80000000u;
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float f32_unorder(uint32_t u)
+{
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
+}
+
+// Per direction q: lohi[2q] = min, lohi[2q+1] = max of Y[q][*] as ordered
+// uint32 (integer atomics: exact and order-free).  lohi starts at (~0, 0).
+__global__ __launch_bounds__(256) void minmax_kernel(const float* __restrict__ Y, int64_t n,
+                                                     unsigned* __restrict__ lohi)
+{
+    const int q = blockIdx.y;
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t u = f32_order(Y[(int64_t)q * n + i]);
+        lo = u < lo ? u : lo;
+        hi = u > hi ? u : hi;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t a = xor_u32(lo, o), b = xor_u32(hi, o);
+        lo = a < lo ? a : lo;
+        hi = b > hi ? b : hi;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&lohi[2 * q], lo);
+        atomicMax(&lohi[2 * q + 1], hi);
+    }
+}
+
+// keys[p][i]: D = 1 -> the ordered projection; D > 1 -> Z-order code of the D
+// projections, each quantised to b = 32/D bits over [lo, hi]:
+// q = min(floor((y - lo) * (2^b / (hi - lo))), 2^b - 1), bits interleaved
+// from the most significant level down.
+__global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ Y, int64_t n, int P, int D,
+                                                     const unsigned* __restrict__ lohi,
+                                                     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int bits = 32 / D;
+    for (int p = 0; p < P; ++p) {
+        uint32_t key;
+        if (D == 1) {
+            key = f32_order(Y[(int64_t)p * n + i]);
+        } else {
+            uint32_t code[8];
+            const uint32_t qmax = (1u << bits) - 1u;
+            for (int j = 0; j < D; ++j) {
+                const int q = p * D + j;
+                const float lo = f32_unorder(lohi[2 * q]), hi = f32_unorder(lohi[2 * q + 1]);
+                const float sc = hi > lo ? (float)(1u << bits) / (hi - lo) : 0.0f;
+                const float f = floorf((Y[(int64_t)q * n + i] - lo) * sc);
+                const uint32_t c = f <= 0.0f ? 0u : (uint32_t)f;
+                code[j] = c < qmax ? c : qmax;
+            }
+            key = 0;
+            for (int l = bits - 1; l >= 0; --l)
+                for (int j = 0; j < D; ++j) key = (key << 1) | ((code[j] >> l) & 1u);
+        }
+        keys[(int64_t)p * n + i] = key;
+        vals[(int64_t)p * n + i] = (uint32_t)i;
+    }
+}
+
+__global__ __launch_bounds__(256) void inverse_perm_kernel(const uint32_t* __restrict__ order, int64_t n,
+                                                           uint32_t* __restrict__ pos)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) pos[order[r]] = (uint32_t)r;
+}
+
+// One wave per point: window candidates from every order (lane = (p, side,
+// offset)), repeats and self dropped, canonical FP32 distances, best K sorted.
+template <int DT>
+__global__ __launch_bounds__(256) void proj_seed_kernel(const void* __restrict__ X, int64_t ld, int d, int64_t n,
+                                                        const uint32_t* __restrict__ order,
+                                                        const uint32_t* __restrict__ pos, int P, int w, int K,
+                                                        int32_t* __restrict__ out_idx, float* __restrict__ out_d2)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    uint32_t cand = 0xFFFFFFFFu;
+    const int per = 2 * w;
+    if (lane < per * P) {
+        const int p = lane / per, o = lane % per;
+        const int64_t r0 = pos[(int64_t)p * n + i];
+        const int64_t r = o < w ? r0 - (o + 1) : r0 + (o - w + 1);
+        if (r >= 0 && r < n) cand = order[(int64_t)p * n + r];
+    }
+    bool ok = cand != 0xFFFFFFFFu && cand != (uint32_t)i;
+    for (int o = 0; o < per * P; ++o) {
+        const uint32_t x = bcast_u32(cand, o);
+        ok = ok && !(o < lane && x == cand);
+    }
+    // compact, then 4 candidates per pass through the 16-lane distance groups
+    const uint64_t mk = ballot(ok);
+    const int cnt = popc64(mk);
+    __shared__ uint32_t sc[4][64];
+    const int wv = threadIdx.x >> 6;
+    if (ok) sc[wv][rank_below(mk)] = cand;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const uint32_t mine = lane < cnt ? sc[wv][lane] : 0xFFFFFFFFu;
+    float dd = 0.0f;
+    for (int base = 0; base < cnt; base += 4) {
+        const int ci = base + (lane >> 4);
+        const uint32_t cj = shfl_u32(mine, ci);
+        const bool act = ci < cnt;
+        const float v = dist_g16<DT>(X, i * ld, X, (int64_t)(act ? cj : 0) * ld, d, act);
+        const float got = shfl_f32(v, ((lane - base) & 3) * 16);
+        if (lane >= base && lane < base + 4) dd = got;
+    }
+    uint64_t key = lane < cnt ? make_key(dd, mine) : kEmptyCand;
+    key = seg_sort<64>(key);
+    if (lane < K) {
+        const bool v = key_valid(key);
+        out_idx[i * K + lane] = v ? (int32_t)key_idx(key) : -1;
+        out_d2[i * K + lane] = v ? key_d2(key) : __builtin_inff();
+    }
+}
+
+template <typename F>
+static void by_dtype(int dt, F&& f)
+{
+    if (dt == KNN_F32) f(std::integral_constant<int, KNN_F32>());
+    else if (dt == KNN_BF16) f(std::integral_constant<int, KNN_BF16>());
+    else f(std::integral_constant<int, KNN_F16>());
+}
+
+static knn_status proj_seed_impl(const knn_matrix& X, const float* Z, int m, const float* dirs, int P, int D,
+                                 int w, int K, int32_t* out_idx, float* out_d2, Workspace& ws, hipStream_t st)
+{
+    const int64_t n = X.n;
+    uint32_t *keys, *vals, *k1, *v1, *pos, *counts, *lohi;
+    float* Y;
+    knn_status r;
+    if ((r = ws.alloc(&Y, (size_t)n * P * D)) != KNN_OK) return r;
+    if ((r = ws.alloc(&lohi, (size_t)2 * P * D)) != KNN_OK) return r;
+    if ((r = ws.alloc(&keys, (size_t)n * P)) != KNN_OK) return r;
+    if ((r = ws.alloc(&vals, (size_t)n * P)) != KNN_OK) return r;
+    if ((r = ws.alloc(&k1, (size_t)n)) != KNN_OK) return r;
+    if ((r = ws.alloc(&v1, (size_t)n)) != KNN_OK) return r;
+    if ((r = ws.alloc(&pos, (size_t)n * P)) != KNN_OK) return r;
+    if ((r = ws.alloc(&counts, (size_t)256 * ceil_div(n, kRsTile))) != KNN_OK) return r;
+    const unsigned g = (unsigned)ceil_div(n, 256);
+    proj_vals_kernel<<<g, 256, 0, st>>>(Z, n, m, dirs, P * D, Y);
+    if (D > 1) {
+        std::vector<uint32_t> init((size_t)2 * P * D);
+        for (size_t q = 0; q < init.size(); ++q) init[q] = (q & 1) ? 0u : 0xFFFFFFFFu;
+        KNN_HIP(hipMemcpyAsync(lohi, init.data(), init.size() * 4, hipMemcpyHostToDevice, st));
+        dim3 mg((unsigned)std::min<int64_t>(ceil_div(n, 256), 1024), (unsigned)(P * D));
+        minmax_kernel<<<mg, 256, 0, st>>>(Y, n, lohi);
+        KNN_HIP(hipStreamSynchronize(st));   // the host init vector must outlive the copy
+    }
+    morton_kernel<<<g, 256, 0, st>>>(Y, n, P, D, lohi, keys, vals);
+    KNN_HIP(hipGetLastError());
+    for (int p = 0; p < P; ++p) {
+        r = radix_sort_pairs(keys + (int64_t)p * n, vals + (int64_t)p * n, k1, v1, n, counts, st);
+        if (r != KNN_OK) return r;
+        inverse_perm_kernel<<<g, 256, 0, st>>>(vals + (int64_t)p * n, n, pos + (int64_t)p * n);
+        KNN_HIP(hipGetLastError());
+    }
+    by_dtype(X.dtype, [&](auto dt) {
+        proj_seed_kernel<decltype(dt)::value><<<(unsigned)ceil_div(n, 4), 256, 0, st>>>(
+            X.data, X.ld, X.d, n, vals, pos, P, w, K, out_idx, out_d2);
+    });
+    KNN_HIP(hipGetLastError());
+    return KNN_OK;
+}
+
+static knn_status embed_impl(const knn_encoder* enc, const knn_matrix& X, float* Z, hipStream_t st)
+{
+    by_dtype(X.dtype, [&](auto dt) {
+        mlp_forward_kernel<decltype(dt)::value><<<(unsigned)ceil_div(X.n, 256), 256, 0, st>>>(
+            X.data, X.ld, X.d, nullptr, X.n, enc->params, nullptr, Z);
+    });
+    KNN_HIP(hipGetLastError());
+    return KNN_OK;
+}
+
+// P seeded directions on the unit sphere in R^m (normalised Gaussians via
+// the Box-Muller transform of the counter-based hash).
+static std::vector<float> seeded_dirs(int P, int m, uint64_t seed)
+{
+    std::vector<float> v((size_t)P * m);
+    for (int p = 0; p < P; ++p) {
+        double nrm = 0.0;
+        for (int t = 0; t < m; ++t) {
+            const uint64_t h = hash4(seed ^ kTagDirs, (uint64_t)p, (uint64_t)t, 0);
+            const double u1 = ((h >> 11) + 1.0) * (1.0 / 9007199254740993.0);
+            const double u2 = (double)(hash4(seed ^ kTagDirs, (uint64_t)p, (uint64_t)t, 1) >> 11) *
+                              (1.0 / 9007199254740992.0);
+            const double g = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+            v[(size_t)p * m + t] = (float)g;
+            nrm += g * g;
+        }
+        nrm = sqrt(nrm);
+        for (int t = 0; t < m; ++t) v[(size_t)p * m + t] = (float)(v[(size_t)p * m + t] / nrm);
+    }
+    return v;
+}
+
+knn_status encoder_seed(const knn_encoder* enc, const knn_matrix& X, int K, int P, int D, int w, uint64_t seed,
+                        Workspace& ws, int32_t** seed_idx, float** seed_d2, hipStream_t st)
+{
+    if (2 * w * P > 64) return fail(KNN_EINVAL, "2 * proj_window * proj_count must be <= 64");
+    if (D < 1 || D > 8 || 32 % D) return fail(KNN_EINVAL, "proj_dims must be 1, 2, 4 or 8");
+    knn_status r;
+    float *Z, *dirs;
+    if ((r = ws.alloc(&Z, (size_t)X.n * H2)) != KNN_OK) return r;
+    if ((r = ws.alloc(&dirs, (size_t)P * D * H2)) != KNN_OK) return r;
+    if ((r = ws.alloc(seed_idx, (size_t)X.n * K)) != KNN_OK) return r;
+    if ((r = ws.alloc(seed_d2, (size_t)X.n * K)) != KNN_OK) return r;
+    std::vector<float> hd = seeded_dirs(P * D, H2, seed);
+    KNN_HIP(hipMemcpyAsync(dirs, hd.data(), hd.size() * 4, hipMemcpyHostToDevice, st));
+    if ((r = embed_impl(enc, X, Z, st)) != KNN_OK) return r;
+    r = proj_seed_impl(X, Z, H2, dirs, P, D, w, K, *seed_idx, *seed_d2, ws, st);
+    if (r != KNN_OK) return r;
+    KNN_HIP(hipStreamSynchronize(st));   // host vector hd must outlive the copy
+    return KNN_OK;
+}
+
+// Forward + loss + backward of one batch (rows: 3B device ints).  Leaves the
+// loss sum in loss_dev[0] (already divided by B) and the gradient in grad.
+static knn_status batch_grads(const knn_encoder* enc, const knn_matrix& X, const int32_t* rows, int B,
+                              float margin, float* H, float* Z, float* dZ, float* dH, float* lterm,
+                              float* partial, float* grad, float* loss_dev, hipStream_t st)
+{
+    const int64_t m = 3 * (int64_t)B;
+    const Off o(enc->d);
+    by_dtype(X.dtype, [&](auto dt) {
+        mlp_forward_kernel<decltype(dt)::value><<<(unsigned)ceil_div(m, 256), 256, 0, st>>>(
+            X.data, X.ld, X.d, rows, m, enc->params, H, Z);
+    });
+    triplet_loss_kernel<<<(unsigned)ceil_div(B, 256), 256, 0, st>>>(Z, B, margin, dZ, lterm);
+    ordered_sum_kernel<<<1, 256, 0, st>>>(lterm, B, 1.0f / (float)B, loss_dev);
+    mlp_dh_kernel<<<(unsigned)ceil_div(m, 256), 256, 0, st>>>(m, enc->d, enc->params, H, dZ, dH);
+    const int nch = (int)ceil_div(m, kGradChunk);
+    dim3 g((unsigned)nch, (unsigned)ceil_div(o.P, 256));
+    by_dtype(X.dtype, [&](auto dt) {
+        mlp_grad_partial_kernel<decltype(dt)::value><<<g, 256, 0, st>>>(X.data, X.ld, X.d, rows, m, H, dZ, dH,
+                                                                        partial);
+    });
+    grad_reduce_kernel<<<(unsigned)ceil_div(o.P, 256), 256, 0, st>>>(partial, nch, o.P, grad);
+    KNN_HIP(hipGetLastError());
+    return KNN_OK;
+}
+
 }  // namespace knn
 
 using namespace knn;
-extern "C" {
-knn_status knn_encoder_create(int32_t, uint64_t, knn_encoder** enc)
+
+extern "C" knn_status knn_encoder_create(int32_t d, uint64_t seed, knn_encoder** enc)
 {
-    if (enc) *enc = nullptr;
-    return fail(KNN_ENOTSUP, "encoder not built yet");
+    try {
+        if (!enc) return fail(KNN_EINVAL, "enc is null");
+        *enc = nullptr;
+        if (d < 1) return fail(KNN_EINVAL, "d must be >= 1");
+        const Off o(d);
+        knn_encoder* e = new knn_encoder();
+        e->d = d;
+        e->P = o.P;
+        if (hipMalloc(&e->params, (size_t)o.P * 4) != hipSuccess || hipMalloc(&e->mom, (size_t)o.P * 4) != hipSuccess ||
+            hipMalloc(&e->vel, (size_t)o.P * 4) != hipSuccess) {
+            (void)hipGetLastError();
+            knn_encoder_destroy(e);
+            return fail(KNN_ENOMEM, "encoder allocation failed");
+        }
+        // He-uniform weights, zero biases
+        std::vector<float> h((size_t)o.P, 0.0f);
+        const double a1 = sqrt(6.0 / d), a2 = sqrt(6.0 / H1);
+        for (int p = 0; p < o.b1; ++p)
+            h[p] = (float)(a1 * (2.0 * ((hash4(seed ^ kTagWeights, 1, (uint64_t)p, 0) >> 11) * (1.0 / 9007199254740992.0)) - 1.0));
+        for (int p = o.W2; p < o.b2; ++p)
+            h[p] = (float)(a2 * (2.0 * ((hash4(seed ^ kTagWeights, 2, (uint64_t)p, 0) >> 11) * (1.0 / 9007199254740992.0)) - 1.0));
+        if (hipMemcpy(e->params, h.data(), (size_t)o.P * 4, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemset(e->mom, 0, (size_t)o.P * 4) != hipSuccess || hipMemset(e->vel, 0, (size_t)o.P * 4) != hipSuccess) {
+            (void)hipGetLastError();
+            knn_encoder_destroy(e);
+            return fail(KNN_EDEVICE, "encoder initialisation failed");
+        }
+        *enc = e;
+        return KNN_OK;
+    } catch (...) {
+        return fail(KNN_EDEVICE, "unexpected exception");
+    }
 }
-void knn_encoder_destroy(knn_encoder*) {}
-knn_status knn_encoder_set_weights(knn_encoder*, const float*, const float*, const float*, const float*)
+
+extern "C" void knn_encoder_destroy(knn_encoder* enc)
 {
-    return fail(KNN_ENOTSUP, "encoder not built yet");
+    if (!enc) return;
+    if (enc->params) (void)hipFree(enc->params);
+    if (enc->mom) (void)hipFree(enc->mom);
+    if (enc->vel) (void)hipFree(enc->vel);
+    delete enc;
 }
-knn_status knn_encoder_get_weights(const knn_encoder*, float*, float*, float*, float*)
+
+extern "C" knn_status knn_encoder_set_weights(knn_encoder* enc, const float* W1, const float* b1,
+                                              const float* W2, const float* b2)
 {
-    return fail(KNN_ENOTSUP, "encoder not built yet");
+    if (!enc || !W1 || !b1 || !W2 || !b2) return fail(KNN_EINVAL, "null argument");
+    const Off o(enc->d);
+    KNN_HIP(hipMemcpy(enc->params + o.W1, W1, (size_t)enc->d * H1 * 4, hipMemcpyHostToDevice));
+    KNN_HIP(hipMemcpy(enc->params + o.b1, b1, (size_t)H1 * 4, hipMemcpyHostToDevice));
+    KNN_HIP(hipMemcpy(enc->params + o.W2, W2, (size_t)H1 * H2 * 4, hipMemcpyHostToDevice));
+    KNN_HIP(hipMemcpy(enc->params + o.b2, b2, (size_t)H2 * 4, hipMemcpyHostToDevice));
+    KNN_HIP(hipMemset(enc->mom, 0, (size_t)o.P * 4));
+    KNN_HIP(hipMemset(enc->vel, 0, (size_t)o.P * 4));
+    enc->t = 0;
+    return KNN_OK;
 }
-knn_status knn_encoder_embed(const knn_encoder*, knn_matrix, int32_t, float*, void*)
+
+extern "C" knn_status knn_encoder_get_weights(const knn_encoder* enc, float* W1, float* b1, float* W2, float* b2)
 {
-    return fail(KNN_ENOTSUP, "encoder not built yet");
+    if (!enc || !W1 || !b1 || !W2 || !b2) return fail(KNN_EINVAL, "null argument");
+    const Off o(enc->d);
+    KNN_HIP(hipMemcpy(W1, enc->params + o.W1, (size_t)enc->d * H1 * 4, hipMemcpyDeviceToHost));
+    KNN_HIP(hipMemcpy(b1, enc->params + o.b1, (size_t)H1 * 4, hipMemcpyDeviceToHost));
+    KNN_HIP(hipMemcpy(W2, enc->params + o.W2, (size_t)H1 * H2 * 4, hipMemcpyDeviceToHost));
+    KNN_HIP(hipMemcpy(b2, enc->params + o.b2, (size_t)H2 * 4, hipMemcpyDeviceToHost));
+    return KNN_OK;
 }
-knn_status knn_encoder_grads(knn_encoder*, knn_matrix, const int32_t*, int32_t, float, float*, float*, void*)
+
+extern "C" knn_status knn_encoder_embed(const knn_encoder* enc, knn_matrix X, int32_t precision, float* Z,
+                                        void* stream)
 {
-    return fail(KNN_ENOTSUP, "encoder not built yet");
+    try {
+        if (!enc || !Z) return fail(KNN_EINVAL, "null argument");
+        knn_status r = check_matrix(X, "X");
+        if (r != KNN_OK) return r;
+        if (X.d != enc->d) return fail(KNN_EINVAL, "X.d != encoder input width");
+        if (precision != KNN_PREC_FP32) return fail(KNN_ENOTSUP, "only the FP32 embedding is implemented");
+        hipStream_t st = (hipStream_t)stream;
+        if ((r = embed_impl(enc, X, Z, st)) != KNN_OK) return r;
+        KNN_HIP(hipStreamSynchronize(st));
+        return KNN_OK;
+    } catch (...) {
+        return fail(KNN_EDEVICE, "unexpected exception");
+    }
 }
-void knn_train_default_params(knn_train_params* t)
+
+extern "C" knn_status knn_encoder_grads(knn_encoder* enc, knn_matrix X, const int32_t* rows, int32_t B,
+                                        float margin, float* loss_out, float* grads, void* stream)
+{
+    try {
+        if (!enc || !rows || !loss_out) return fail(KNN_EINVAL, "null argument");
+        knn_status r = check_matrix(X, "X");
+        if (r != KNN_OK) return r;
+        if (X.d != enc->d) return fail(KNN_EINVAL, "X.d != encoder input width");
+        if (B < 1) return fail(KNN_EINVAL, "B must be >= 1");
+        hipStream_t st = (hipStream_t)stream;
+        Workspace ws(st, 0);
+        const int64_t m = 3 * (int64_t)B;
+        const Off o(enc->d);
+        float *H, *Z, *dZ, *dH, *lterm, *partial, *grad, *loss_dev;
+        if ((r = ws.alloc(&H, (size_t)m * H1)) != KNN_OK) return r;
+        if ((r = ws.alloc(&Z, (size_t)m * H2)) != KNN_OK) return r;
+        if ((r = ws.alloc(&dZ, (size_t)m * H2)) != KNN_OK) return r;
+        if ((r = ws.alloc(&dH, (size_t)m * H1)) != KNN_OK) return r;
+        if ((r = ws.alloc(&lterm, (size_t)B)) != KNN_OK) return r;
+        if ((r = ws.alloc(&partial, (size_t)ceil_div(m, kGradChunk) * o.P)) != KNN_OK) return r;
+        grad = grads;
+        if (!grad && (r = ws.alloc(&grad, (size_t)o.P)) != KNN_OK) return r;
+        if ((r = ws.alloc(&loss_dev, 1)) != KNN_OK) return r;
+        r = batch_grads(enc, X, rows, B, margin, H, Z, dZ, dH, lterm, partial, grad, loss_dev, st);
+        if (r != KNN_OK) return r;
+        KNN_HIP(hipMemcpyAsync(loss_out, loss_dev, 4, hipMemcpyDeviceToHost, st));
+        KNN_HIP(hipStreamSynchronize(st));
+        return KNN_OK;
+    } catch (...) {
+        return fail(KNN_EDEVICE, "unexpected exception");
+    }
+}
+
+extern "C" void knn_train_default_params(knn_train_params* t)
 {
     if (!t) return;
-    t->steps = 2000; t->batch = 4096; t->lr = 1e-3f; t->beta1 = 0.9f; t->beta2 = 0.999f;
-    t->eps = 1e-8f; t->margin = 1.0f; t->seed = 0;
+    t->steps = 2000;
+    t->batch = 4096;
+    t->lr = 1e-3f;
+    t->beta1 = 0.9f;
+    t->beta2 = 0.999f;
+    t->eps = 1e-8f;
+    t->margin = 1.0f;
+    t->seed = 0;
 }
-knn_status knn_encoder_train(knn_encoder*, knn_matrix, const int32_t*, int32_t, const knn_train_params*, float*, void*)
+
+extern "C" knn_status knn_encoder_train(knn_encoder* enc, knn_matrix X, const int32_t* knn_idx, int32_t k,
+                                        const knn_train_params* tp, float* loss_log, void* stream)
 {
-    return fail(KNN_ENOTSUP, "encoder not built yet");
+    try {
+        if (!enc || !knn_idx || !tp) return fail(KNN_EINVAL, "null argument");
+        knn_status r = check_matrix(X, "X");
+        if (r != KNN_OK) return r;
+        if (X.d != enc->d) return fail(KNN_EINVAL, "X.d != encoder input width");
+        if (k < 1 || tp->steps < 0 || tp->batch < 1) return fail(KNN_EINVAL, "bad training parameters");
+        hipStream_t st = (hipStream_t)stream;
+        Workspace ws(st, 0);
+        const int B = tp->batch;
+        const int64_t m = 3 * (int64_t)B;
+        const Off o(enc->d);
+        int32_t* rows;
+        float *H, *Z, *dZ, *dH, *lterm, *partial, *grad, *losses;
+        if ((r = ws.alloc(&rows, (size_t)m)) != KNN_OK) return r;
+        if ((r = ws.alloc(&H, (size_t)m * H1)) != KNN_OK) return r;
+        if ((r = ws.alloc(&Z, (size_t)m * H2)) != KNN_OK) return r;
+        if ((r = ws.alloc(&dZ, (size_t)m * H2)) != KNN_OK) return r;
+        if ((r = ws.alloc(&dH, (size_t)m * H1)) != KNN_OK) return r;
+        if ((r = ws.alloc(&lterm, (size_t)B)) != KNN_OK) return r;
+        if ((r = ws.alloc(&partial, (size_t)ceil_div(m, kGradChunk) * o.P)) != KNN_OK) return r;
+        if ((r = ws.alloc(&grad, (size_t)o.P)) != KNN_OK) return r;
+        if ((r = ws.alloc(&losses, (size_t)(tp->steps > 0 ? tp->steps : 1))) != KNN_OK) return r;
+        for (int s = 0; s < tp->steps; ++s) {
+            triplet_sample_kernel<<<(unsigned)ceil_div(B, 256), 256, 0, st>>>(X.n, knn_idx, k, B, tp->seed,
+                                                                              enc->t + s, rows);
+            r = batch_grads(enc, X, rows, B, tp->margin, H, Z, dZ, dH, lterm, partial, grad, losses + s, st);
+            if (r != KNN_OK) return r;
+            const int t = enc->t + s + 1;
+            const float c1 = 1.0f - powf(tp->beta1, (float)t), c2 = 1.0f - powf(tp->beta2, (float)t);
+            adam_kernel<<<(unsigned)ceil_div(o.P, 256), 256, 0, st>>>(enc->params, grad, enc->mom, enc->vel, o.P,
+                                                                      tp->lr, tp->beta1, tp->beta2, tp->eps, c1, c2);
+            KNN_HIP(hipGetLastError());
+        }
+        enc->t += tp->steps;
+        if (loss_log && tp->steps > 0)
+            KNN_HIP(hipMemcpyAsync(loss_log, losses, (size_t)tp->steps * 4, hipMemcpyDeviceToHost, st));
+        KNN_HIP(hipStreamSynchronize(st));
+        return KNN_OK;
+    } catch (...) {
+        return fail(KNN_EDEVICE, "unexpected exception");
+    }
 }
-knn_status knn_proj_seed(knn_matrix, const float*, int32_t, const float*, int32_t, int32_t, int32_t, int32_t*, float*, void*)
+
+extern "C" knn_status knn_proj_seed(knn_matrix X, const float* Z, int32_t m, const float* dirs, int32_t P,
+                                    int32_t D, int32_t w, int32_t K, int32_t* out_idx, float* out_dist,
+                                    void* stream)
 {
-    return fail(KNN_ENOTSUP, "projection seeding not built yet");
-}
+    try {
+        knn_status r = check_matrix(X, "X");
+        if (r != KNN_OK) return r;
+        if (!Z || !dirs || !out_idx || !out_dist) return fail(KNN_EINVAL, "null argument");
+        if (X.n < 2 || m < 1 || m > 64 || P < 1 || w < 1 || K < 1 || K > 64)
+            return fail(KNN_EINVAL, "bad sizes (need n >= 2, 1 <= m <= 64, P >= 1, w >= 1, 1 <= K <= 64)");
+        if (D < 1 || D > 8 || 32 % D) return fail(KNN_EINVAL, "D must be 1, 2, 4 or 8");
+        if (2 * w * P > 64) return fail(KNN_EINVAL, "2 * w * P must be <= 64");
+        hipStream_t st = (hipStream_t)stream;
+        Workspace ws(st, 0);
+        r = proj_seed_impl(X, Z, m, dirs, P, D, w, K, out_idx, out_dist, ws, st);
+        if (r != KNN_OK) return r;
+        KNN_HIP(hipStreamSynchronize(st));
+        return KNN_OK;
+    } catch (...) {
+        return fail(KNN_EDEVICE, "unexpected exception");
+    }
 }

@@ -45,7 +45,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // sorted, first K kept.  Flags: given (or new).
 template <int DT>
 __global__ __launch_bounds__(256) void nnd_init_kernel(
-    int64_t n, int K, const void* __restrict__ Xs, int ldp, int d,
+    int64_t n, int K, const void* __restrict__ Xs, int64_t ldp, int d,
     const int32_t* __restrict__ init_idx, const float* __restrict__ init_dist,
     const uint8_t* __restrict__ init_flags, int init_k, uint64_t seed,
     int32_t* __restrict__ gidx, float* __restrict__ gd2, uint8_t* __restrict__ gflag)
@@ -240,12 +240,11 @@ struct JoinCfg {
     int s, R, K, C, J;     // new sample, reverse slots, list size, candidate slots, cap
     int lcap;              // max join-list length (rows staged in LDS), <= 64
     int ncap;              // max new-list length
-    int gstride;           // LDS row stride of the distance matrix (odd: no bank conflicts)
+    int gstride;           // (unused)
+    int chunk, tdp;        // FP32 join: d-chunk staged per pass and its LDS row stride (floats)
 };
 
-constexpr int kTD = 64;          // d-chunk staged per pass (elements)
-constexpr int kTDP = kTD + 4;    // LDS row stride of staged rows (floats)
-constexpr int kJMax = 8;         // largest supported join cap
+constexpr int kJMax = 4;         // largest supported join cap
 
 // Per-point join lists.  Lanes 0..s-1 take new_f(v), s..s+R-1 the reverse-new
 // slots (consumed and reset), and likewise old_f(v) / reverse-old in a second
@@ -309,107 +308,44 @@ __device__ inline int join_lists(int64_t v, const JoinCfg& cfg, const int32_t* _
     return nn;
 }
 
-// Squared distances new x list by FP32 FMAs: tiles of (8 AI) new rows x
-// (8 BQ) list rows, lane (ag, bg) owning rows ag + 8i and bg + 8q; rows are
-// staged in LDS chunk by chunk (16 lanes x float4 per row).
-template <int AI, int BQ>
-__device__ inline void join_gram_f32(const float* __restrict__ Xs, int ldp, int d, float* rows,
-                                     float* gram, const uint32_t* ids, const float* nrm, int nn,
-                                     int L, int gs, bool staged)
+// Keep the J smallest keys (ascending) of a stream: insertion from the back.
+__device__ inline void topj_insert(uint64_t (&best)[kJMax], int J, uint64_t key)
 {
-    const int lane = threadIdx.x, ag = lane >> 3, bg = lane & 7;
-    const int nch = (d + kTD - 1) / kTD;
-    for (int at = 0; at < nn; at += 8 * AI) {
-        float acc[AI][BQ];
 #pragma unroll
-        for (int i = 0; i < AI; ++i)
-#pragma unroll
-            for (int q = 0; q < BQ; ++q) acc[i][q] = 0.0f;
-        for (int ch = 0; ch < nch; ++ch) {
-            const int c0 = ch * kTD;
-            if (nch > 1 || !staged) {
-                __syncthreads();
-                for (int m = lane >> 4; m < L; m += 4) {
-                    const int t = c0 + (lane & 15) * 4;
-                    f32x4 x = {0.0f, 0.0f, 0.0f, 0.0f};
-                    if (t < ldp) x = *(const f32x4*)(Xs + (int64_t)ids[m] * ldp + t);
-                    *(f32x4*)(rows + m * kTDP + (lane & 15) * 4) = x;
-                }
-                __syncthreads();
-                staged = true;
-            }
-            int ai[AI], bq[BQ];
-#pragma unroll
-            for (int i = 0; i < AI; ++i) ai[i] = min(at + ag + 8 * i, L - 1);
-#pragma unroll
-            for (int q = 0; q < BQ; ++q) bq[q] = min(bg + 8 * q, L - 1);
-            const int tl = min(kTD, d - c0);
-            for (int t = 0; t < tl; t += 4) {
-                f32x4 xa[AI];
-#pragma unroll
-                for (int i = 0; i < AI; ++i) xa[i] = *(const f32x4*)(rows + ai[i] * kTDP + t);
-#pragma unroll
-                for (int q = 0; q < BQ; ++q) {
-                    const f32x4 xb = *(const f32x4*)(rows + bq[q] * kTDP + t);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-#pragma unroll
-                        for (int i = 0; i < AI; ++i) acc[i][q] = fmaf(xa[i][e], xb[e], acc[i][q]);
-                }
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < AI; ++i) {
-            const int a = at + ag + 8 * i;
-#pragma unroll
-            for (int q = 0; q < BQ; ++q) {
-                const int b = bg + 8 * q;
-                if (a < nn && b < L) {
-                    const float d2 = nrm[a] + nrm[b] - 2.0f * acc[i][q];
-                    gram[a * gs + b] = d2 > 0.0f ? d2 : 0.0f;
-                }
-            }
+    for (int q = 0; q < kJMax; ++q) {
+        if (q < J && key < best[q]) {
+            const uint64_t t = best[q];
+            best[q] = key;
+            key = t;
         }
     }
 }
 
-// Each member m of the join list takes its best J partners below its current
-// worst distance (new x new and new x old pairs only) and sends them to its
-// candidate slots: atomicMin of the key at slot hash(partner, iteration).
-__device__ inline unsigned long long join_emit(const JoinCfg& cfg, const float* gram, const uint32_t* ids,
-                                               const float* thr, int nn, int L, uint64_t salt,
-                                               unsigned long long* __restrict__ cand)
+__device__ inline float topj_cut(const uint64_t (&best)[kJMax], int J, float thr)
+{
+    uint64_t last = kEmptyCand;
+#pragma unroll
+    for (int q = 0; q < kJMax; ++q)
+        if (q == J - 1) last = best[q];
+    return last != kEmptyCand ? fminf(thr, key_d2(last)) : thr;
+}
+
+// Offer member `me` its kept partners: atomicMin of each key into slot
+// hash(partner, iteration) of me's candidate row.  Slots only decrease
+// during a launch, so a plain read that already shows a key at most as
+// large makes the atomic a no-op and it is skipped.
+__device__ inline unsigned long long emit_best(const uint64_t (&best)[kJMax], int J, uint32_t me, int C,
+                                               uint64_t salt, unsigned long long* __restrict__ cand)
 {
     unsigned long long emitted = 0;
-    const int gs = cfg.gstride;
-    for (int m = threadIdx.x; m < L; m += 64) {
-        const bool mnew = m < nn;
-        const float tm = thr[m];
-        uint64_t best[kJMax];
 #pragma unroll
-        for (int q = 0; q < kJMax; ++q) best[q] = kEmptyCand;
-        const int olim = mnew ? L : nn;      // old members only pair with new ones
-#pragma unroll 4
-        for (int o = 0; o < olim; ++o) {
-            const float d2 = mnew ? gram[m * gs + o] : gram[o * gs + m];
-            if (o == m || !(d2 < tm)) continue;
-            uint64_t key = make_key(d2, ids[o]);
-#pragma unroll
-            for (int q = 0; q < kJMax; ++q) {
-                if (q < cfg.J && key < best[q]) {
-                    const uint64_t t = best[q];
-                    best[q] = key;
-                    key = t;
-                }
-            }
-        }
-        const uint32_t me = ids[m];
-#pragma unroll
-        for (int q = 0; q < kJMax; ++q) {
-            if (q < cfg.J && best[q] != kEmptyCand) {
-                const uint32_t src = key_idx(best[q]);
-                const uint32_t slot = bounded(mix64(((uint64_t)src << 20) ^ salt), (uint32_t)cfg.C);
-                atomicMin(&cand[(int64_t)me * cfg.C + slot], (unsigned long long)best[q]);
+    for (int q = 0; q < kJMax; ++q) {
+        if (q < J && best[q] != kEmptyCand) {
+            const uint32_t src = key_idx(best[q]);
+            const uint32_t slot = bounded(mix64(((uint64_t)src << 20) ^ salt), (uint32_t)C);
+            unsigned long long* p = &cand[(int64_t)me * C + slot];
+            if (*p > (unsigned long long)best[q]) {
+                atomicMin(p, (unsigned long long)best[q]);
                 ++emitted;
             }
         }
@@ -417,15 +353,12 @@ __device__ inline unsigned long long join_emit(const JoinCfg& cfg, const float* 
     return emitted;
 }
 
-template <int AI, int BQ>
-__device__ inline void gram_f32_dispatch(const float* Xs, int ldp, int d, float* rows, float* gram,
-                                         const uint32_t* ids, const float* nrm, int nn, int L, int gs)
-{
-    join_gram_f32<AI, BQ>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs, false);
-}
-
-// Local join, FP32 (VALU).  One wave per point, grid-stride.  Dynamic LDS:
-// rows[lcap][kTDP] floats, gram[ncap][gstride] floats, ids/nrm/thr[lcap].
+// Local join, FP32 (VALU).  One wave per point v, grid-stride.  Lane m owns
+// list member m: its column of squared distances to every list member is
+// accumulated in 64 registers (broadcast LDS reads of the other rows, d in
+// chunks), then the member keeps its best J partners below its current worst
+// distance -- new x new and new x old pairs only -- and offers them.
+// Dynamic LDS: rows[64][tdp] floats, ids[64], nrm[64].
 __global__ __launch_bounds__(64) void nnd_join_f32_kernel(
     int64_t n, JoinCfg cfg, const float* __restrict__ Xs, int ldp, int d, const float* __restrict__ norms,
     const float* __restrict__ gd2, const int32_t* __restrict__ newf,
@@ -434,12 +367,10 @@ __global__ __launch_bounds__(64) void nnd_join_f32_kernel(
     int iter, unsigned long long* __restrict__ counters)
 {
     extern __shared__ float smem[];
-    const int lcap = cfg.lcap, ncap = cfg.ncap, gs = cfg.gstride;
+    const int tdp = cfg.tdp, chunk = cfg.chunk;
     float* rows = smem;
-    float* gram = rows + lcap * kTDP;
-    uint32_t* ids = (uint32_t*)(gram + ncap * gs);
-    float* nrm = (float*)(ids + lcap);
-    float* thr = nrm + lcap;
+    uint32_t* ids = (uint32_t*)(rows + 64 * tdp);
+    float* nrm = (float*)(ids + 64);
     const int lane = threadIdx.x;
     unsigned long long emitted = 0, gathered = 0;
     const uint64_t salt = (uint64_t)iter ^ seed;
@@ -449,31 +380,64 @@ __global__ __launch_bounds__(64) void nnd_join_f32_kernel(
         const int nn = join_lists(v, cfg, newf, revnew, oldf, revold, ids, L);
         __syncthreads();
         if (nn == 0 || L < 2) continue;
-        for (int m = lane; m < L; m += 64) {
-            const uint32_t x = ids[m];
-            nrm[m] = norms[x];
-            thr[m] = gd2[(int64_t)x * cfg.K + cfg.K - 1];
+        float tme = 0.0f;
+        if (lane < L) {
+            const uint32_t x = ids[lane];
+            nrm[lane] = norms[x];
+            tme = gd2[(int64_t)x * cfg.K + cfg.K - 1];
         }
         gathered += (unsigned long long)L;
-        const int ai = min((nn + 7) >> 3, 4);
-        const int bq = L <= 24 ? 3 : (L <= 40 ? 5 : 8);
-        switch (ai * 16 + bq) {
-        case 16 + 3: gram_f32_dispatch<1, 3>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
-        case 16 + 5: gram_f32_dispatch<1, 5>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
-        case 16 + 8: gram_f32_dispatch<1, 8>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
-        case 32 + 3: gram_f32_dispatch<2, 3>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
-        case 32 + 5: gram_f32_dispatch<2, 5>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
-        case 32 + 8: gram_f32_dispatch<2, 8>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
-        case 48 + 3: gram_f32_dispatch<3, 3>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
-        case 48 + 5: gram_f32_dispatch<3, 5>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
-        case 48 + 8: gram_f32_dispatch<3, 8>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
-        case 64 + 3: gram_f32_dispatch<4, 3>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
-        case 64 + 5: gram_f32_dispatch<4, 5>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
-        default: gram_f32_dispatch<4, 8>(Xs, ldp, d, rows, gram, ids, nrm, nn, L, gs); break;
+        const int me = lane < L ? lane : L - 1;
+        float acc[64];
+#pragma unroll
+        for (int r = 0; r < 64; ++r) acc[r] = 0.0f;
+        for (int c0 = 0; c0 < d; c0 += chunk) {
+            __syncthreads();
+            const int col = (lane & 15) * 4;
+            if (col < chunk) {
+                for (int m = lane >> 4; m < L; m += 4) {
+                    const int t = c0 + col;
+                    f32x4 x = {0.0f, 0.0f, 0.0f, 0.0f};
+                    if (t < ldp) x = *(const f32x4*)(Xs + (int64_t)ids[m] * ldp + t);
+                    *(f32x4*)(rows + m * tdp + col) = x;
+                }
+            }
+            __syncthreads();
+            const int tl = min(chunk, d - c0);
+            for (int t = 0; t < tl; t += 4) {
+                const f32x4 xc = *(const f32x4*)(rows + me * tdp + t);
+#pragma unroll
+                for (int r = 0; r < 64; ++r) {
+                    if (r < L) {
+                        const f32x4 xr = *(const f32x4*)(rows + r * tdp + t);
+                        acc[r] = fmaf(xr[0], xc[0], acc[r]);
+                        acc[r] = fmaf(xr[1], xc[1], acc[r]);
+                        acc[r] = fmaf(xr[2], xc[2], acc[r]);
+                        acc[r] = fmaf(xr[3], xc[3], acc[r]);
+                    }
+                }
+            }
         }
-        __syncthreads();
-        emitted += join_emit(cfg, gram, ids, thr, nn, L, salt, cand);
-        __syncthreads();
+        if (lane < L) {
+            const bool mnew = lane < nn;
+            const float nme = nrm[lane];
+            uint64_t best[kJMax];
+#pragma unroll
+            for (int q = 0; q < kJMax; ++q) best[q] = kEmptyCand;
+            float cut = tme;
+#pragma unroll
+            for (int r = 0; r < 64; ++r) {
+                if (r < L && r != lane && (mnew || r < nn)) {
+                    float d2 = nrm[r] + nme - 2.0f * acc[r];
+                    d2 = d2 > 0.0f ? d2 : 0.0f;
+                    if (d2 < cut) {
+                        topj_insert(best, cfg.J, make_key(d2, ids[r]));
+                        cut = topj_cut(best, cfg.J, cut);
+                    }
+                }
+            }
+            emitted += emit_best(best, cfg.J, ids[lane], cfg.C, salt, cand);
+        }
     }
     for (int o = 32; o > 0; o >>= 1) emitted += shfl_u64(emitted, lane ^ o);
     if (lane == 0) {
@@ -482,13 +446,15 @@ __global__ __launch_bounds__(64) void nnd_join_f32_kernel(
     }
 }
 
-// Local join, BF16 form.  Same lists and emission as the FP32 join; the
-// squared distances come from BF16 rows (RNE copies) through
-// v_mfma_f32_32x32x16_bf16 with FP32 accumulation and FP32 norms of the
-// rounded rows.  A-operand: 32 new rows; B-operand: up to 64 list rows (two
-// 32-column blocks).  Rows are staged in LDS in chunks of 128 elements.
-constexpr int kTDB = 128;        // d-chunk (bf16 elements)
-constexpr int kTDBP = kTDB + 8;  // LDS row stride (elements): 272 bytes
+// Local join, BF16 form.  Same lists and offers; the L x L Gram of the list
+// rows (BF16 copies, RNE) comes from v_mfma_f32_32x32x16_bf16 with FP32
+// accumulation: four 32 x 32 tiles whose A and B operands are the same two
+// LDS vectors.  Lane (h, c) holds columns c and 32 + c (two members) and 16
+// rows of each tile; it keeps a partial best-J per column over its 32 rows,
+// swaps the partial list of one column with its partner lane (the other h)
+// and finalises the other.  Norms are FP32 norms of the rounded rows.
+constexpr int kTDB = 64;         // d-chunk (bf16 elements)
+constexpr int kTDBP = kTDB + 8;  // LDS row stride (elements): 144 bytes
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -499,83 +465,111 @@ __global__ __launch_bounds__(64) void nnd_join_bf16_kernel(
     unsigned long long* __restrict__ revold, unsigned long long* __restrict__ cand, uint64_t seed,
     int iter, unsigned long long* __restrict__ counters)
 {
-    extern __shared__ float smem[];
-    const int lcap = cfg.lcap, ncap = cfg.ncap, gs = cfg.gstride;
-    uint16_t* rows = (uint16_t*)smem;
-    float* gram = smem + (lcap * kTDBP) / 2;
-    uint32_t* ids = (uint32_t*)(gram + ncap * gs);
-    float* nrm = (float*)(ids + lcap);
-    float* thr = nrm + lcap;
+    __shared__ __attribute__((aligned(16))) uint16_t rows[64 * kTDBP];
+    __shared__ uint32_t ids[64];
+    __shared__ float nrm[64];
+    __shared__ float thr[64];
     const int lane = threadIdx.x, c = lane & 31, h = lane >> 5;
     unsigned long long emitted = 0, gathered = 0;
     const uint64_t salt = (uint64_t)iter ^ seed;
     const int dk = (int)round_up(d, 16);
-    const int nch = (dk + kTDB - 1) / kTDB;
+    const int J = cfg.J;
 
     for (int64_t v = blockIdx.x; v < n; v += gridDim.x) {
         int L = 0;
         const int nn = join_lists(v, cfg, newf, revnew, oldf, revold, ids, L);
         __syncthreads();
         if (nn == 0 || L < 2) continue;
-        for (int m = lane; m < L; m += 64) {
-            const uint32_t x = ids[m];
-            nrm[m] = norms[x];
-            thr[m] = gd2[(int64_t)x * cfg.K + cfg.K - 1];
+        if (lane < L) {
+            const uint32_t x = ids[lane];
+            nrm[lane] = norms[x];
+            thr[lane] = gd2[(int64_t)x * cfg.K + cfg.K - 1];
         }
         gathered += (unsigned long long)L;
-        bool staged = false;
-        for (int at = 0; at < nn; at += 32) {
-            f32x16 acc0, acc1;
+        const bool two = L > 32;
+        f32x16 a00, a01, a10, a11;
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                acc0[e] = 0.0f;
-                acc1[e] = 0.0f;
+        for (int e = 0; e < 16; ++e) {
+            a00[e] = 0.0f;
+            a01[e] = 0.0f;
+            a10[e] = 0.0f;
+            a11[e] = 0.0f;
+        }
+        for (int c0 = 0; c0 < dk; c0 += kTDB) {
+            __syncthreads();
+            // 8 lanes x 16 bytes per row; rows past L are zero
+            for (int m = lane >> 3; m < (two ? 64 : 32); m += 8) {
+                const int t = c0 + (lane & 7) * 8;
+                uint4 x = {0u, 0u, 0u, 0u};
+                if (m < L && t < ldb) x = *(const uint4*)(Xb + (int64_t)ids[m] * ldb + t);
+                *(uint4*)(rows + m * kTDBP + (lane & 7) * 8) = x;
             }
-            for (int ch = 0; ch < nch; ++ch) {
-                const int c0 = ch * kTDB;
-                if (nch > 1 || !staged) {
-                    __syncthreads();
-                    for (int m = lane >> 4; m < L; m += 4) {
-                        const int t = c0 + (lane & 15) * 8;
-                        uint4 x = {0u, 0u, 0u, 0u};
-                        if (t < ldb) x = *(const uint4*)(Xb + (int64_t)ids[m] * ldb + t);
-                        *(uint4*)(rows + m * kTDBP + (lane & 15) * 8) = x;
-                    }
-                    __syncthreads();
-                    staged = true;
-                }
-                const int ra = min(at + c, L - 1), rb0 = min(c, L - 1), rb1 = min(32 + c, L - 1);
-                const int ksteps = min(kTDB, dk - c0) / 16;
-                for (int kk = 0; kk < ksteps; ++kk) {
-                    const int off = kk * 16 + h * 8;
-                    const bf16x8 a = __builtin_bit_cast(bf16x8, *(const uint4*)(rows + ra * kTDBP + off));
-                    const bf16x8 b0 = __builtin_bit_cast(bf16x8, *(const uint4*)(rows + rb0 * kTDBP + off));
-                    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
-                    if (L > 32) {
-                        const bf16x8 b1 = __builtin_bit_cast(bf16x8, *(const uint4*)(rows + rb1 * kTDBP + off));
-                        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
-                    }
+            __syncthreads();
+            const int ks = min(kTDB, dk - c0) / 16;
+            for (int kk = 0; kk < ks; ++kk) {
+                const int off = kk * 16 + h * 8;
+                const bf16x8 r0 = __builtin_bit_cast(bf16x8, *(const uint4*)(rows + c * kTDBP + off));
+                a00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r0, r0, a00, 0, 0, 0);
+                if (two) {
+                    const bf16x8 r1 = __builtin_bit_cast(bf16x8, *(const uint4*)(rows + (32 + c) * kTDBP + off));
+                    a01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r0, r1, a01, 0, 0, 0);
+                    a10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r1, r0, a10, 0, 0, 0);
+                    a11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r1, r1, a11, 0, 0, 0);
                 }
             }
-            // D[i][j]: lane holds column c, rows 8*(e/4) + 4*h + e%4
+        }
+        // tile (rb, cb): lane holds column cb*32 + c, rows rb*32 + 8(e/4) + 4h + e%4
+        uint64_t p0[kJMax], p1[kJMax];
+#pragma unroll
+        for (int q = 0; q < kJMax; ++q) {
+            p0[q] = kEmptyCand;
+            p1[q] = kEmptyCand;
+        }
+        const int m0 = c, m1 = 32 + c;
+        float cut0 = m0 < L ? thr[m0] : -1.0f, cut1 = m1 < L ? thr[m1] : -1.0f;
+        const bool new0 = m0 < nn, new1 = m1 < nn;
+        const float n0 = nrm[m0 < L ? m0 : 0], n1 = nrm[m1 < L ? m1 : 0];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
-                const int i = at + 8 * (e >> 2) + 4 * h + (e & 3);
-                if (i < nn) {
-                    if (c < L) {
-                        const float d2 = nrm[i] + nrm[c] - 2.0f * acc0[e];
-                        gram[i * gs + c] = d2 > 0.0f ? d2 : 0.0f;
+                const int i = rb * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+                if (i >= L) continue;
+                const float ni = nrm[i];
+                const bool inew = i < nn;
+                const float g0 = rb == 0 ? a00[e] : a10[e];
+                const float g1 = rb == 0 ? a01[e] : a11[e];
+                if (i != m0 && (new0 || inew)) {
+                    float d2 = ni + n0 - 2.0f * g0;
+                    d2 = d2 > 0.0f ? d2 : 0.0f;
+                    if (d2 < cut0) {
+                        topj_insert(p0, J, make_key(d2, ids[i]));
+                        cut0 = topj_cut(p0, J, cut0);
                     }
-                    if (32 + c < L) {
-                        const float d2 = nrm[i] + nrm[32 + c] - 2.0f * acc1[e];
-                        gram[i * gs + 32 + c] = d2 > 0.0f ? d2 : 0.0f;
+                }
+                if (two && i != m1 && (new1 || inew)) {
+                    float d2 = ni + n1 - 2.0f * g1;
+                    d2 = d2 > 0.0f ? d2 : 0.0f;
+                    if (d2 < cut1) {
+                        topj_insert(p1, J, make_key(d2, ids[i]));
+                        cut1 = topj_cut(p1, J, cut1);
                     }
                 }
             }
         }
-        __syncthreads();
-        emitted += join_emit(cfg, gram, ids, thr, nn, L, salt, cand);
-        __syncthreads();
+        // lane h = 0 finalises column m0, lane h = 1 column m1
+        uint64_t fin[kJMax];
+        uint64_t recv[kJMax];
+#pragma unroll
+        for (int q = 0; q < kJMax; ++q) {
+            recv[q] = shfl_xor_u64(h == 0 ? p1[q] : p0[q], 32);
+            fin[q] = h == 0 ? p0[q] : p1[q];
+        }
+#pragma unroll
+        for (int q = 0; q < kJMax; ++q)
+            if (q < J) topj_insert(fin, J, recv[q]);
+        const int mm = h == 0 ? m0 : m1;
+        if (mm < L) emitted += emit_best(fin, J, ids[mm], cfg.C, salt, cand);
     }
     for (int o = 32; o > 0; o >>= 1) emitted += shfl_u64(emitted, lane ^ o);
     if (lane == 0) {
@@ -590,9 +584,8 @@ knn_status nnd_join_bf16(int64_t n, const JoinCfg& cfg, const uint16_t* Xb, int 
                          unsigned long long* revold, unsigned long long* cand, uint64_t seed,
                          int iter, unsigned long long* counters, unsigned grid, hipStream_t st)
 {
-    const size_t lds = (size_t)cfg.lcap * kTDBP * 2 + ((size_t)cfg.ncap * cfg.gstride + 3 * (size_t)cfg.lcap) * 4;
-    nnd_join_bf16_kernel<<<grid, 64, lds, st>>>(n, cfg, Xb, ldb, d, norms, gd2, newf, revnew, oldf, revold,
-                                               cand, seed, iter, counters);
+    nnd_join_bf16_kernel<<<grid, 64, 0, st>>>(n, cfg, Xb, ldb, d, norms, gd2, newf, revnew, oldf, revold,
+                                             cand, seed, iter, counters);
     KNN_HIP(hipGetLastError());
     return KNN_OK;
 }
@@ -722,7 +715,7 @@ __global__ __launch_bounds__(256) void nnd_finalize_kernel(
 
 // ------------------------------------------------------------------ host
 
-knn_status encoder_seed(const knn_encoder* enc, const knn_matrix& X, int K, int P, int w,
+knn_status encoder_seed(const knn_encoder* enc, const knn_matrix& X, int K, int P, int D, int w,
                         uint64_t seed, Workspace& ws, int32_t** seed_idx, float** seed_d2,
                         hipStream_t st);
 
@@ -802,6 +795,8 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     if (cfg.lcap > 64) cfg.lcap = 64;
     if (cfg.ncap > 64) cfg.ncap = 64;
     cfg.gstride = cfg.lcap | 1;
+    cfg.chunk = (int)std::min<int64_t>(64, round_up(X.d, 4));
+    cfg.tdp = cfg.chunk + 4;
 
     Timer t_all, t_init, t_fin;
     (void)hipEventRecord(t_all.a, st);
@@ -810,8 +805,10 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     void* Xs = nullptr;
     float* norms = nullptr;
     int ldp = 0;
-    r = stage_matrix(ws, X, false, &Xs, &ldp, &norms, nullptr, st);
-    if (r != KNN_OK) return r;
+    if (!bf) {
+        r = stage_matrix(ws, X, false, &Xs, &ldp, &norms, nullptr, st);
+        if (r != KNN_OK) return r;
+    }
     void* Xb = nullptr;
     float* nb = nullptr;
     int ldb = 0;
@@ -847,7 +844,8 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         float* sd = nullptr;
         const int P = p->proj_count > 0 ? p->proj_count : 4;
         const int w = p->proj_window > 0 ? p->proj_window : 8;
-        r = encoder_seed(p->encoder, X, K, P, w, p->seed, ws, &si, &sd, st);
+        const int D = p->proj_dims > 0 ? p->proj_dims : 8;
+        r = encoder_seed(p->encoder, X, K, P, D, w, p->seed, ws, &si, &sd, st);
         if (r != KNN_OK) return r;
         seed_idx = si;
         seed_d2 = sd;
@@ -856,9 +854,12 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     }
     {
         dim3 grid((unsigned)ceil_div(n, 4));
-        // distances on the staged FP32 rows (values equal to the input's)
-        nnd_init_kernel<KNN_F32><<<grid, 256, 0, st>>>(n, K, Xs, ldp, X.d, seed_idx, seed_d2, seed_fl,
-                                                       seed_idx ? seed_k : 0, p->seed, gidx, gd2, gflag);
+        // canonical FP32 direct-difference distances on the input values
+        const int sk = seed_idx ? seed_k : 0;
+        launch_by_dtype(X.dtype, [&](auto dt) {
+            nnd_init_kernel<decltype(dt)::value><<<grid, 256, 0, st>>>(n, K, X.data, X.ld, X.d, seed_idx, seed_d2,
+                                                                      seed_fl, sk, p->seed, gidx, gd2, gflag);
+        });
         KNN_HIP(hipGetLastError());
     }
     (void)hipEventRecord(t_init.b, st);
@@ -871,7 +872,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         ~HostFree() { (void)hipHostFree(p); }
     } hf{host_cnt};
     const double stop = (double)p->delta * (double)n * (double)K;
-    const size_t lds = ((size_t)cfg.lcap * kTDP + (size_t)cfg.ncap * cfg.gstride + 3 * (size_t)cfg.lcap) * 4;
+    const size_t lds = ((size_t)64 * cfg.tdp + 128) * 4;
     const size_t merge_lds = (size_t)4 * cfg.C * 8;
     int dev = 0;
     KNN_HIP(hipGetDevice(&dev));
@@ -983,6 +984,7 @@ extern "C" void knn_nnd_default_params(int32_t k, knn_nnd_params* p)
     p->encoder = nullptr;
     p->proj_count = 0;
     p->proj_window = 0;
+    p->proj_dims = 0;
     p->cand_slots = 0;
     p->join_cap = 0;
     p->workspace_limit_bytes = 0;

@@ -1,0 +1,142 @@
+"""Learned seeding on the GPU: encoder forward/backward against the FP64 CPU
+oracle, the stable radix sort + window seeding against the oracle's
+sorted-projection seeding, and the gain of a trained encoder over random
+init (recall after the same number of NNDescent iterations)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2603_04035_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda").to(dtype)
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def test_embed_matches_oracle(orc):
+    from paper_2603_04035_amd import Encoder
+    X = datagen.gmm_isotropic(n=3000, d=50, seed=1)
+    enc = Encoder(50, seed=3)
+    W1, b1, W2, b2 = enc.get_weights()
+    assert np.abs(b1).max() == 0 and np.abs(W1).max() <= np.sqrt(6 / 50) + 1e-6
+    Z = enc.embed(_dev(X)).cpu().numpy()
+    Zo = orc.mlp_forward(X, W1, b1, W2, b2)
+    assert _rel(Z, Zo) < 1e-5, _rel(Z, Zo)
+
+
+@pytest.mark.parametrize("B", [1, 37, 4096])
+def test_gradients_match_oracle(orc, B):
+    from paper_2603_04035_amd import Encoder
+    d = 50
+    X = datagen.gmm_isotropic(n=5000, d=d, seed=2)
+    rng = np.random.default_rng(B)
+    rows = rng.integers(0, 5000, size=3 * B)
+    enc = Encoder(d, seed=4)
+    W1, b1, W2, b2 = enc.get_weights()
+    b1 = rng.normal(0, 0.1, size=64).astype(np.float32)   # non-zero biases exercise gb1/gb2 paths
+    b2 = rng.normal(0, 0.1, size=32).astype(np.float32)
+    enc.set_weights(W1, b1, W2, b2)
+    loss, g = enc.grads(_dev(X), torch.from_numpy(rows), B, margin=1.0)
+    g = g.cpu().numpy()
+    Zo = orc.mlp_forward(X[rows], W1, b1, W2, b2)
+    lo, dZ = orc.triplet_loss(Zo, B, 1.0)
+    gW1, gb1, gW2, gb2 = orc.mlp_backward(X[rows], W1, b1, W2, dZ)
+    assert abs(loss - lo) <= 1e-5 * max(abs(lo), 1e-6), (loss, lo)
+    o = 0
+    for ref in (gW1, gb1, gW2):
+        part = g[o:o + ref.size]
+        assert _rel(part, ref) < 1e-5, _rel(part, ref)
+        o += ref.size
+    # gb2 is zero up to rounding (translation invariance of the loss)
+    assert np.abs(g[o:]).max() < 1e-5 * max(np.abs(g[:o]).max(), 1e-6) + 1e-6
+
+
+def test_training_lowers_loss_and_is_deterministic():
+    from paper_2603_04035_amd import Encoder
+    import paper_2603_04035_amd as knn
+    X = _dev(datagen.gmm_anisotropic(n=20000, d=50, comps=20, seed=5))
+    idx, _ = knn.knn_exact(X, 15)
+    runs = []
+    for _ in range(2):
+        enc = Encoder(50, seed=1)
+        log = enc.train(X, idx, steps=300, batch=1024, lr=1e-3, seed=7)
+        runs.append((log, enc.get_weights()))
+    log = runs[0][0]
+    assert log[-20:].mean() < 0.5 * log[:20].mean(), (log[:5], log[-5:])
+    assert np.array_equal(runs[0][0], runs[1][0])
+    for a, b in zip(runs[0][1], runs[1][1]):
+        assert np.array_equal(a, b)
+
+
+def test_proj_seed_matches_oracle(orc):
+    """Both sides decide the orders with the same FP32 arithmetic (sequential
+    fused multiply-adds, the same quantisation), so the sorted orders and the
+    candidate windows coincide; the best K follow the exact-path rule
+    (near-ties within 1e-5 may swap)."""
+    from paper_2603_04035_amd import knn_proj_seed
+    from oracle.compare import exact_parity, parity_ok
+    n = 6000
+    X = datagen.gmm_isotropic(n=n, d=20, seed=6)
+    rng = np.random.default_rng(0)
+    Zi = rng.integers(-50, 50, size=(n, 8)).astype(np.float32)
+    Zr = rng.normal(size=(n, 32)).astype(np.float32)
+    cases = [(Zi, rng.integers(-3, 4, size=(3, 8)).astype(np.float32), 1, 2, 5),
+             (Zi, rng.integers(-3, 4, size=(3, 8)).astype(np.float32), 1, 8, 16),
+             (Zr, rng.normal(size=(2, 32)).astype(np.float32), 1, 10, 32),
+             (Zr, rng.normal(size=(4 * 8, 32)).astype(np.float32), 8, 8, 32),
+             (Zr, rng.normal(size=(2 * 4, 32)).astype(np.float32), 4, 16, 20),
+             (Zr, rng.normal(size=(1 * 2, 32)).astype(np.float32), 2, 30, 24)]
+    for Z, dirs, D, w, K in cases:
+        idx, d2 = knn_proj_seed(_dev(X), _dev(Z), _dev(dirs), w=w, K=K, D=D)
+        idx, d2 = idx.cpu().numpy(), d2.cpu().numpy()
+        oi, od2 = orc.proj_seed(X, Z, dirs, w=w, K=K, D=D)
+        assert np.array_equal(idx < 0, oi < 0), (D, w, K)
+        full = oi.min(axis=1) >= 0
+        res = exact_parity(X, np.arange(n)[full], idx[full], np.sqrt(d2[full]), oi[full])
+        assert parity_ok(res), (D, w, K, res)
+
+
+def test_proj_seed_line_is_exact(orc):
+    """d = 1, identity embedding, one projection, w >= k: seeds equal the exact kNN."""
+    from paper_2603_04035_amd import knn_proj_seed
+    X = datagen.line_1d(5000, seed=3)
+    idx, d2 = knn_proj_seed(_dev(X), _dev(X), _dev(np.ones((1, 1), np.float32)), w=15, K=15)
+    oi, _ = orc.exact_knn(X, 15)
+    assert np.array_equal(idx.cpu().numpy(), oi)
+
+
+def test_learned_init_vs_random(orc):
+    """Train on a 20K sample of the mixture (exact graph from knn_exact), seed a
+    held-out 100K set through Z-order windows of the embedding, and compare
+    recall after 0, 1 and 2 NNDescent iterations with random init and with an
+    untrained encoder (same settings).  The seeds must beat random lists."""
+    import paper_2603_04035_amd as knn
+    from paper_2603_04035_amd import Encoder
+    Xt = _dev(datagen.gmm_anisotropic(n=20000, d=50, comps=50, seed=0 + 100))
+    Xe_np = datagen.gmm_anisotropic(n=100000, d=50, comps=50, seed=0)
+    Xe = _dev(Xe_np)
+    ti, _ = knn.knn_exact(Xt, 15)
+    trained = Encoder(50, seed=1)
+    trained.train(Xt, ti, steps=500, batch=2048, lr=2e-3, seed=3)
+    untrained = Encoder(50, seed=1)
+    rows = datagen.sample_queries(100000, 2000, seed=2)
+    _, O2 = orc.exact_knn(Xe_np, 15, rows=rows)
+    res = {}
+    for name, kw in (("random", {}), ("untrained", {"init_kind": "encoder", "encoder": untrained}),
+                     ("trained", {"init_kind": "encoder", "encoder": trained})):
+        res[name] = []
+        for it in (0, 1, 2):
+            G, D, st = knn.nndescent_build(Xe, 15, build_k=20, max_iters=it, delta=0.0, **kw)
+            res[name].append(round(orc.recall_at_k(Xe_np, rows, G.cpu().numpy()[rows],
+                                                   np.sqrt(O2[:, -1]), 15), 4))
+    print("recall after 0/1/2 iterations", res)
+    assert res["trained"][0] > 5 * max(res["random"][0], 1e-3), res
+    assert res["trained"][2] > res["random"][2], res

@@ -149,16 +149,16 @@ def test_workspace_limit_is_enomem():
 
 
 def test_gmm_1m_recall_sampled(orc):
-    """1,000,000 x 50 anisotropic mixture (50 components), k = 15, random init:
-    recall@15 on 1,000 sampled rows against the oracle."""
+    """1,000,000 x 50 anisotropic mixture (50 components), k = 15, random init,
+    K_b = 32, rho = 1: recall@15 >= 0.98 on 1,000 rows sampled against the oracle."""
     X = datagen.gmm_anisotropic(n=1_000_000, d=50, comps=50, seed=0)
     rows = datagen.sample_queries(1_000_000, 1000, seed=2)
-    G, D, st = _build(X, 15, build_k=20, max_iters=20)
+    G, D, st = _build(X, 15, build_k=32, sample_rate=1.0, max_iters=30)
     G = G.cpu().numpy()
     _, O2 = orc.exact_knn(X, 15, rows=rows)
     r = orc.recall_at_k(X, rows, G[rows], np.sqrt(O2[:, -1]), 15)
     print("1M recall", r, st)
-    assert r >= 0.9, (r, st)
+    assert r >= 0.98, (r, st)
 
 
 def test_bf16_form_recall_and_exact_distances(orc):
@@ -177,14 +177,19 @@ def test_bf16_form_recall_and_exact_distances(orc):
 
 @pytest.mark.parametrize("C", [8, 64, 200])
 def test_slot_counts(orc, C):
-    """Candidate slot counts below, at and above one wave (chunked merges)."""
+    """Candidate slot counts below, at and above one wave (chunked merges).
+    Bar: the sequential oracle's recall at the same K, rho and iteration count
+    (minus 0.03), except for 8 slots, which must still beat random lists."""
     X = datagen.gmm_isotropic(n=4000, d=24, seed=11)
-    G, D, st = _build(X, 10, cand_slots=C, max_iters=10)
+    G, D, st = _build(X, 10, cand_slots=C, max_iters=10, delta=0.0)
     G, D = G.cpu().numpy(), D.cpu().numpy()
     _check_rows(orc, X, G, D)
     _, O2 = orc.exact_knn(X, 10)
     r = orc.recall_at_k(X, np.arange(4000), G, np.sqrt(O2[:, -1]), 10)
-    assert r >= (0.6 if C == 8 else 0.9), (C, r)
+    oi, od2, _, _ = orc.nndescent(X, 10, max_iters=10, rho=0.5, delta=0.0, seed=0)
+    ro = orc.recall_at_k(X, np.arange(4000), oi, np.sqrt(O2[:, -1]), 10)
+    print("slots", C, "gpu", r, "oracle", ro)
+    assert r >= (0.6 if C == 8 else ro - 0.03), (C, r, ro)
 
 
 def test_pixel_like_high_dim(orc):

@@ -164,3 +164,47 @@ def test_proj_seed_invariants(orc):
         for i in range(0, n, 50):
             win = set(order[max(0, rank[i] - 2): rank[i] + 3]) - {i}
             assert win <= set(idx[i][valid[i]]) or len(win | set(idx[i][valid[i]])) > 0
+
+
+def test_zorder_keys_visit_quadrants_recursively(orc):
+    """Z-order (D = 2): on a 16 x 16 grid whose coordinate range is exactly 16
+    (one extra point at (16, 16) makes (hi - lo) * scale exact), the sorted
+    order visits aligned 2^l x 2^l squares one after another at every level,
+    the defining property of the curve."""
+    g = np.array([(x, y) for x in range(16) for y in range(16)] + [(16, 16)], dtype=np.float32)
+    keys = orc.proj_keys(g, np.eye(2, dtype=np.float32), D=2)
+    order = np.lexsort((np.arange(len(g)), keys))[:256]
+    pts = g[order].astype(int)
+    assert sorted(map(tuple, pts)) == [(x, y) for x in range(16) for y in range(16)]
+    for lvl in (1, 2, 3):
+        side = 2 ** lvl
+        blocks = pts.reshape(-1, side * side, 2)
+        for b in blocks:
+            assert (b[:, 0] // side).min() == (b[:, 0] // side).max()
+            assert (b[:, 1] // side).min() == (b[:, 1] // side).max()
+    # D = 1: keys order like the projections themselves
+    z = np.random.default_rng(0).normal(size=(1000, 3)).astype(np.float32)
+    k1 = orc.proj_keys(z, np.array([[1.0, 0.0, 0.0]], np.float32), D=1)
+    assert np.array_equal(np.argsort(k1, kind="stable"), np.argsort(z[:, 0], kind="stable"))
+
+
+def test_proj_seed_zorder_windows(orc):
+    """Seeds from Z-order windows contain only window members and the best
+    of them by true distance."""
+    rng = np.random.default_rng(1)
+    X = rng.normal(size=(400, 6))
+    Z = X[:, :4].astype(np.float32)
+    dirs = rng.normal(size=(2 * 4, 4)).astype(np.float32)     # P = 2 curves, D = 4
+    idx, d2 = orc.proj_seed(X, Z, dirs, w=3, K=12, D=4)
+    members = [set() for _ in range(400)]
+    for p in range(2):
+        keys = orc.proj_keys(Z, dirs[4 * p:4 * p + 4], D=4)
+        order = np.lexsort((np.arange(400), keys))
+        rank = np.empty(400, np.int64)
+        rank[order] = np.arange(400)
+        for i in range(400):
+            members[i] |= set(order[max(0, rank[i] - 3): rank[i] + 4].tolist()) - {i}
+    for i in range(400):
+        cand = sorted(members[i], key=lambda j: (((X[i] - X[j]) ** 2).sum(), j))
+        got = [j for j in idx[i] if j >= 0]
+        assert got == cand[:12]

@@ -352,17 +352,32 @@ static knn_status radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uin
 // -------------------------------------------------------------- seeding
 
 // Y[q][i] = Z_i . dirs_q (FP32 fused multiply-adds in coordinate order) for
-// the P*D directions q.
+// the P*D directions q.  The row of Z is read once into registers (M = m when
+// m <= 32, else a strided fallback).
+template <int M>
 __global__ __launch_bounds__(256) void proj_vals_kernel(const float* __restrict__ Z, int64_t n, int m,
                                                         const float* __restrict__ dirs, int PD,
                                                         float* __restrict__ Y)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    for (int q = 0; q < PD; ++q) {
-        float s = 0.0f;
-        for (int t = 0; t < m; ++t) s = fmaf(Z[i * m + t], dirs[q * m + t], s);
-        Y[(int64_t)q * n + i] = s;
+    if constexpr (M > 0) {
+        float z[M];
+#pragma unroll
+        for (int t = 0; t < M; ++t) z[t] = t < m ? Z[i * m + t] : 0.0f;
+        for (int q = 0; q < PD; ++q) {
+            float s = 0.0f;
+#pragma unroll
+            for (int t = 0; t < M; ++t)
+                if (t < m) s = fmaf(z[t], dirs[q * m + t], s);
+            Y[(int64_t)q * n + i] = s;
+        }
+    } else {
+        for (int q = 0; q < PD; ++q) {
+            float s = 0.0f;
+            for (int t = 0; t < m; ++t) s = fmaf(Z[i * m + t], dirs[q * m + t], s);
+            Y[(int64_t)q * n + i] = s;
+        }
     }
 }
 
@@ -442,6 +457,29 @@ __global__ __launch_bounds__(256) void inverse_perm_kernel(const uint32_t* __res
     if (r < n) pos[order[r]] = (uint32_t)r;
 }
 
+// Y[j][i] = X_i . dirs_j over the d input coordinates (FP32 fused
+// multiply-adds in coordinate order), D directions.
+template <int DT>
+__global__ __launch_bounds__(256) void xproj_kernel(const void* __restrict__ X, int64_t ld, int d, int64_t n,
+                                                    const float* __restrict__ dirs, int D,
+                                                    float* __restrict__ Y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float y[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) y[j] = 0.0f;
+    for (int t = 0; t < d; ++t) {
+        const float x = elem<DT>::ld(X, i * ld + t);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (j < D) y[j] = fmaf(x, dirs[j * d + t], y[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (j < D) Y[(int64_t)j * n + i] = y[j];
+}
+
 // One wave per point: window candidates from every order (lane = (p, side,
 // offset)), repeats and self dropped, canonical FP32 distances, best K sorted.
 template <int DT>
@@ -518,7 +556,8 @@ static knn_status proj_seed_impl(const knn_matrix& X, const float* Z, int m, con
     if ((r = ws.alloc(&pos, (size_t)n * P)) != KNN_OK) return r;
     if ((r = ws.alloc(&counts, (size_t)256 * ceil_div(n, kRsTile))) != KNN_OK) return r;
     const unsigned g = (unsigned)ceil_div(n, 256);
-    proj_vals_kernel<<<g, 256, 0, st>>>(Z, n, m, dirs, P * D, Y);
+    if (m <= 32) proj_vals_kernel<32><<<g, 256, 0, st>>>(Z, n, m, dirs, P * D, Y);
+    else proj_vals_kernel<0><<<g, 256, 0, st>>>(Z, n, m, dirs, P * D, Y);
     if (D > 1) {
         std::vector<uint32_t> init((size_t)2 * P * D);
         for (size_t q = 0; q < init.size(); ++q) init[q] = (q & 1) ? 0u : 0xFFFFFFFFu;
@@ -540,6 +579,48 @@ static knn_status proj_seed_impl(const knn_matrix& X, const float* Z, int m, con
             X.data, X.ld, X.d, n, vals, pos, P, w, K, out_idx, out_d2);
     });
     KNN_HIP(hipGetLastError());
+    return KNN_OK;
+}
+
+static std::vector<float> seeded_dirs(int P, int m, uint64_t seed);
+
+// Internal processing order of the points: the Z-order curve of D seeded
+// random projections of X (4-bit codes for D = 8), ties by index.  Points
+// that are close get close positions, so rows and candidate slots touched
+// together share cache lines.  perm[new] = old, inv[old] = new.
+knn_status morton_order(const knn_matrix& X, int D, uint64_t seed, Workspace& ws, uint32_t** perm,
+                        uint32_t** inv, hipStream_t st)
+{
+    const int64_t n = X.n;
+    knn_status r;
+    float *Y, *dirs;
+    uint32_t *keys, *k1, *v1, *lohi, *counts;
+    if ((r = ws.alloc(&Y, (size_t)n * D)) != KNN_OK) return r;
+    if ((r = ws.alloc(&dirs, (size_t)D * X.d)) != KNN_OK) return r;
+    if ((r = ws.alloc(&keys, (size_t)n)) != KNN_OK) return r;
+    if ((r = ws.alloc(perm, (size_t)n)) != KNN_OK) return r;
+    if ((r = ws.alloc(inv, (size_t)n)) != KNN_OK) return r;
+    if ((r = ws.alloc(&k1, (size_t)n)) != KNN_OK) return r;
+    if ((r = ws.alloc(&v1, (size_t)n)) != KNN_OK) return r;
+    if ((r = ws.alloc(&lohi, (size_t)2 * D)) != KNN_OK) return r;
+    if ((r = ws.alloc(&counts, (size_t)256 * ceil_div(n, kRsTile))) != KNN_OK) return r;
+    std::vector<float> hd = seeded_dirs(D, X.d, seed ^ 0x5DEECE66Dull);
+    std::vector<uint32_t> init((size_t)2 * D);
+    for (size_t q = 0; q < init.size(); ++q) init[q] = (q & 1) ? 0u : 0xFFFFFFFFu;
+    KNN_HIP(hipMemcpyAsync(dirs, hd.data(), hd.size() * 4, hipMemcpyHostToDevice, st));
+    KNN_HIP(hipMemcpyAsync(lohi, init.data(), init.size() * 4, hipMemcpyHostToDevice, st));
+    const unsigned g = (unsigned)ceil_div(n, 256);
+    by_dtype(X.dtype, [&](auto dt) {
+        xproj_kernel<decltype(dt)::value><<<g, 256, 0, st>>>(X.data, X.ld, X.d, n, dirs, D, Y);
+    });
+    dim3 mg((unsigned)std::min<int64_t>(ceil_div(n, 256), 1024), (unsigned)D);
+    minmax_kernel<<<mg, 256, 0, st>>>(Y, n, lohi);
+    morton_kernel<<<g, 256, 0, st>>>(Y, n, 1, D, lohi, keys, *perm);
+    KNN_HIP(hipGetLastError());
+    if ((r = radix_sort_pairs(keys, *perm, k1, v1, n, counts, st)) != KNN_OK) return r;
+    inverse_perm_kernel<<<g, 256, 0, st>>>(*perm, n, *inv);
+    KNN_HIP(hipGetLastError());
+    KNN_HIP(hipStreamSynchronize(st));   // host vectors must outlive the copies
     return KNN_OK;
 }
 

@@ -32,7 +32,9 @@
 namespace knn {
 
 knn_status stage_matrix(Workspace& ws, const knn_matrix& X, bool bf16, void** Xs, int* ldp,
-                        float** norms, unsigned* maxnorm, hipStream_t st);
+                        float** norms, unsigned* maxnorm, hipStream_t st, const uint32_t* rowmap);
+knn_status morton_order(const knn_matrix& X, int D, uint64_t seed, Workspace& ws, uint32_t** perm,
+                        uint32_t** inv, hipStream_t st);
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -48,7 +50,8 @@ __global__ __launch_bounds__(256) void nnd_init_kernel(
     int64_t n, int K, const void* __restrict__ Xs, int64_t ldp, int d,
     const int32_t* __restrict__ init_idx, const float* __restrict__ init_dist,
     const uint8_t* __restrict__ init_flags, int init_k, uint64_t seed,
-    int32_t* __restrict__ gidx, float* __restrict__ gd2, uint8_t* __restrict__ gflag)
+    int32_t* __restrict__ gidx, float* __restrict__ gd2, uint8_t* __restrict__ gflag,
+    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ inv)
 {
     __shared__ uint32_t s_id[4][64];
     __shared__ float s_d2[4][64];
@@ -64,16 +67,19 @@ __global__ __launch_bounds__(256) void nnd_init_kernel(
     float gd = 0.0f;
     uint8_t fl = 1;
     bool hasd = false;
+    // lists given in input order are read at the row's input position and
+    // their entries mapped to processing order
+    const int64_t grow = perm ? (int64_t)perm[row] : row;
     if (init_idx && lane < init_k) {
-        int32_t v = init_idx[row * init_k + lane];
-        if (v >= 0 && v < n && v != row) {
-            id = (uint32_t)v;
+        int32_t v = init_idx[grow * init_k + lane];
+        if (v >= 0 && v < n && v != grow) {
+            id = inv ? inv[v] : (uint32_t)v;
             valid = true;
             if (init_dist) {
-                gd = init_dist[row * init_k + lane];
+                gd = init_dist[grow * init_k + lane];
                 hasd = true;
             }
-            if (init_flags) fl = init_flags[row * init_k + lane] ? 1 : 0;
+            if (init_flags) fl = init_flags[grow * init_k + lane] ? 1 : 0;
         }
     }
     // drop repeats (keep the first occurrence)
@@ -353,12 +359,75 @@ __device__ inline unsigned long long emit_best(const uint64_t (&best)[kJMax], in
     return emitted;
 }
 
-// Local join, FP32 (VALU).  One wave per point v, grid-stride.  Lane m owns
-// list member m: its column of squared distances to every list member is
-// accumulated in 64 registers (broadcast LDS reads of the other rows, d in
-// chunks), then the member keeps its best J partners below its current worst
-// distance -- new x new and new x old pairs only -- and offers them.
-// Dynamic LDS: rows[64][tdp] floats, ids[64], nrm[64].
+// Local join, FP32 (VALU).  One wave per point v, grid-stride.
+//  1. the join lists are built (join_lists) and their rows staged in LDS in
+//     d-chunks (16 lanes x float4 per row);
+//  2. the Gram block new x list is accumulated with FP32 FMAs, register-
+//     blocked: lane (ag, bg) owns new rows ag + 8i (i < NI) and list rows
+//     bg + 8q (q < NQ), i.e. 4 NI NQ FMAs per NI + NQ LDS reads;
+//  3. the squared distances overwrite the staged rows in LDS (odd row stride);
+//  4. lane m scans member m's partners -- its row if it is new, its column
+//     over the new rows if it is old -- keeps the best J below its current
+//     worst distance and offers them.
+// Dynamic LDS: max(64 * tdp, 64 * 65) floats, ids[64], nrm[64].
+template <int NI, int NQ>
+__device__ inline void gram_f32(const float* __restrict__ Xs, int ldp, int d, int chunk, int tdp,
+                                float* buf, const uint32_t* ids, const float* nrm, int nn, int L)
+{
+    const int lane = threadIdx.x, ag = lane >> 3, bg = lane & 7;
+    float acc[NI][NQ];
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[i][q] = 0.0f;
+    int ra[NI], rb[NQ];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) ra[i] = min(ag + 8 * i, L - 1);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) rb[q] = min(bg + 8 * q, L - 1);
+    for (int c0 = 0; c0 < d; c0 += chunk) {
+        __syncthreads();
+        const int col = (lane & 15) * 4;
+        if (col < chunk) {
+            for (int m = lane >> 4; m < L; m += 4) {
+                const int t = c0 + col;
+                f32x4 x = {0.0f, 0.0f, 0.0f, 0.0f};
+                if (t < ldp) x = *(const f32x4*)(Xs + (int64_t)ids[m] * ldp + t);
+                *(f32x4*)(buf + m * tdp + col) = x;
+            }
+        }
+        __syncthreads();
+        const int tl = min(chunk, d - c0);
+        for (int t = 0; t < tl; t += 4) {
+            f32x4 xa[NI];
+#pragma unroll
+            for (int i = 0; i < NI; ++i) xa[i] = *(const f32x4*)(buf + ra[i] * tdp + t);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const f32x4 xb = *(const f32x4*)(buf + rb[q] * tdp + t);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int i = 0; i < NI; ++i) acc[i][q] = fmaf(xa[i][e], xb[e], acc[i][q]);
+            }
+        }
+    }
+    __syncthreads();   // every lane is done with the staged rows
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int a = ag + 8 * i;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int b = bg + 8 * q;
+            if (a < nn && b < L) {
+                const float d2 = nrm[a] + nrm[b] - 2.0f * acc[i][q];
+                buf[a * 65 + b] = d2 > 0.0f ? d2 : 0.0f;
+            }
+        }
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(64) void nnd_join_f32_kernel(
     int64_t n, JoinCfg cfg, const float* __restrict__ Xs, int ldp, int d, const float* __restrict__ norms,
     const float* __restrict__ gd2, const int32_t* __restrict__ newf,
@@ -368,8 +437,9 @@ __global__ __launch_bounds__(64) void nnd_join_f32_kernel(
 {
     extern __shared__ float smem[];
     const int tdp = cfg.tdp, chunk = cfg.chunk;
-    float* rows = smem;
-    uint32_t* ids = (uint32_t*)(rows + 64 * tdp);
+    const int bufsz = 64 * tdp > 64 * 65 ? 64 * tdp : 64 * 65;
+    float* buf = smem;
+    uint32_t* ids = (uint32_t*)(buf + bufsz);
     float* nrm = (float*)(ids + 64);
     const int lane = threadIdx.x;
     unsigned long long emitted = 0, gathered = 0;
@@ -387,53 +457,34 @@ __global__ __launch_bounds__(64) void nnd_join_f32_kernel(
             tme = gd2[(int64_t)x * cfg.K + cfg.K - 1];
         }
         gathered += (unsigned long long)L;
-        const int me = lane < L ? lane : L - 1;
-        float acc[64];
-#pragma unroll
-        for (int r = 0; r < 64; ++r) acc[r] = 0.0f;
-        for (int c0 = 0; c0 < d; c0 += chunk) {
-            __syncthreads();
-            const int col = (lane & 15) * 4;
-            if (col < chunk) {
-                for (int m = lane >> 4; m < L; m += 4) {
-                    const int t = c0 + col;
-                    f32x4 x = {0.0f, 0.0f, 0.0f, 0.0f};
-                    if (t < ldp) x = *(const f32x4*)(Xs + (int64_t)ids[m] * ldp + t);
-                    *(f32x4*)(rows + m * tdp + col) = x;
-                }
-            }
-            __syncthreads();
-            const int tl = min(chunk, d - c0);
-            for (int t = 0; t < tl; t += 4) {
-                const f32x4 xc = *(const f32x4*)(rows + me * tdp + t);
-#pragma unroll
-                for (int r = 0; r < 64; ++r) {
-                    if (r < L) {
-                        const f32x4 xr = *(const f32x4*)(rows + r * tdp + t);
-                        acc[r] = fmaf(xr[0], xc[0], acc[r]);
-                        acc[r] = fmaf(xr[1], xc[1], acc[r]);
-                        acc[r] = fmaf(xr[2], xc[2], acc[r]);
-                        acc[r] = fmaf(xr[3], xc[3], acc[r]);
-                    }
-                }
-            }
+        const int ni = (nn + 15) >> 4;        // pairs of 8-row groups: 1..4
+        const int nq = L <= 32 ? 0 : (L <= 48 ? 1 : 2);
+        switch (ni * 4 + nq) {
+        case 4: gram_f32<2, 4>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
+        case 5: gram_f32<2, 6>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
+        case 6: gram_f32<2, 8>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
+        case 8: gram_f32<4, 4>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
+        case 9: gram_f32<4, 6>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
+        case 10: gram_f32<4, 8>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
+        case 12: gram_f32<6, 4>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
+        case 13: gram_f32<6, 6>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
+        case 14: gram_f32<6, 8>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
+        case 16: gram_f32<8, 4>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
+        case 17: gram_f32<8, 6>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
+        default: gram_f32<8, 8>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
         }
         if (lane < L) {
             const bool mnew = lane < nn;
-            const float nme = nrm[lane];
             uint64_t best[kJMax];
 #pragma unroll
             for (int q = 0; q < kJMax; ++q) best[q] = kEmptyCand;
             float cut = tme;
-#pragma unroll
-            for (int r = 0; r < 64; ++r) {
-                if (r < L && r != lane && (mnew || r < nn)) {
-                    float d2 = nrm[r] + nme - 2.0f * acc[r];
-                    d2 = d2 > 0.0f ? d2 : 0.0f;
-                    if (d2 < cut) {
-                        topj_insert(best, cfg.J, make_key(d2, ids[r]));
-                        cut = topj_cut(best, cfg.J, cut);
-                    }
+            const int olim = mnew ? L : nn;
+            for (int o = 0; o < olim; ++o) {
+                const float d2 = mnew ? buf[lane * 65 + o] : buf[o * 65 + lane];
+                if (o != lane && d2 < cut) {
+                    topj_insert(best, cfg.J, make_key(d2, ids[o]));
+                    cut = topj_cut(best, cfg.J, cut);
                 }
             }
             emitted += emit_best(best, cfg.J, ids[lane], cfg.C, salt, cand);
@@ -675,41 +726,44 @@ __global__ __launch_bounds__(256) void nnd_merge_kernel(
 
 // --------------------------------------------------------------- finalize
 
-// One wave per row: canonical FP32 direct-difference distances of the K list
-// entries on the input values, sort by (distance, index), write the first k;
-// optionally copy the working lists out.
-template <int DT>
+// One wave per processing-order row i: canonical FP32 direct-difference
+// distances of the K list entries (on the staged rows, whose values are the
+// input's), sorted by (distance, input index); the first k are written to
+// input row perm[i] with input indices; optionally the working lists too.
 __global__ __launch_bounds__(256) void nnd_finalize_kernel(
-    int64_t n, int K, int k, const void* __restrict__ X, int64_t ld, int d,
+    int64_t n, int K, int k, const float* __restrict__ Xs, int64_t ldp, int d,
     const int32_t* __restrict__ gidx, const float* __restrict__ gd2, const uint8_t* __restrict__ gflag,
     int out_kind, int32_t* __restrict__ out_idx, float* __restrict__ out_dist,
-    int32_t* __restrict__ st_idx, float* __restrict__ st_d2, uint8_t* __restrict__ st_fl)
+    int32_t* __restrict__ st_idx, float* __restrict__ st_d2, uint8_t* __restrict__ st_fl,
+    const uint32_t* __restrict__ perm)
 {
     const int lane = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= n) return;
-    int32_t id = lane < K ? gidx[row * K + lane] : -1;
+    const int64_t orow = perm[row];
+    const int32_t id = lane < K ? gidx[row * K + lane] : -1;
+    const int32_t oid = id >= 0 ? (int32_t)perm[id] : -1;
     if (lane < K) {
-        if (st_idx) st_idx[row * K + lane] = id;
-        if (st_d2) st_d2[row * K + lane] = gd2[row * K + lane];
-        if (st_fl) st_fl[row * K + lane] = gflag[row * K + lane];
+        if (st_idx) st_idx[orow * K + lane] = oid;
+        if (st_d2) st_d2[orow * K + lane] = gd2[row * K + lane];
+        if (st_fl) st_fl[orow * K + lane] = gflag[row * K + lane];
     }
     float mine = 0.0f;
     for (int base = 0; base < K; base += 4) {
         const int ci = base + (lane >> 4);
         const int32_t cj = (int32_t)shfl_u32((uint32_t)id, ci);
         const bool act = ci < K && cj >= 0;
-        const float v = dist_g16<DT>(X, row * ld, X, (int64_t)(act ? cj : 0) * ld, d, act);
+        const float v = dist_g16<KNN_F32>(Xs, row * ldp, Xs, (int64_t)(act ? cj : 0) * ldp, d, act);
         const float got = shfl_f32(v, ((lane - base) & 3) * 16);
         if (lane >= base && lane < base + 4) mine = got;
     }
-    uint64_t key = (lane < K && id >= 0) ? make_key(mine, (uint32_t)id) : kEmptyCand;
+    uint64_t key = (lane < K && id >= 0) ? make_key(mine, (uint32_t)oid) : kEmptyCand;
     key = seg_sort<64>(key);
     if (lane < k) {
         const bool sv = key_valid(key);
         const float d2 = sv ? key_d2(key) : __builtin_inff();
-        out_idx[row * k + lane] = sv ? (int32_t)key_idx(key) : -1;
-        out_dist[row * k + lane] = out_kind == KNN_OUT_L2 ? sqrtf(d2) : d2;
+        out_idx[orow * k + lane] = sv ? (int32_t)key_idx(key) : -1;
+        out_dist[orow * k + lane] = out_kind == KNN_OUT_L2 ? sqrtf(d2) : d2;
     }
 }
 
@@ -802,20 +856,24 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     (void)hipEventRecord(t_all.a, st);
     Workspace ws(st, p->workspace_limit_bytes);
     const bool bf = p->precision == KNN_PREC_BF16;
+    // processing order: Z-order curve of X (see morton_order); every staged
+    // copy and every list below is indexed in that order
+    uint32_t *perm = nullptr, *inv = nullptr;
+    r = morton_order(X, 8, p->seed, ws, &perm, &inv, st);
+    if (r != KNN_OK) return r;
     void* Xs = nullptr;
     float* norms = nullptr;
     int ldp = 0;
-    if (!bf) {
-        r = stage_matrix(ws, X, false, &Xs, &ldp, &norms, nullptr, st);
-        if (r != KNN_OK) return r;
-    }
+    r = stage_matrix(ws, X, false, &Xs, &ldp, &norms, nullptr, st, perm);
+    if (r != KNN_OK) return r;
     void* Xb = nullptr;
     float* nb = nullptr;
     int ldb = 0;
     if (bf) {
-        r = stage_matrix(ws, X, true, &Xb, &ldb, &nb, nullptr, st);
+        r = stage_matrix(ws, X, true, &Xb, &ldb, &nb, nullptr, st, perm);
         if (r != KNN_OK) return r;
     }
+    const knn_matrix Xp = {Xs, X.n, X.d, ldp, KNN_F32};   // input values in processing order
     int32_t *gidx, *newf, *oldf;
     float* gd2;
     uint8_t* gflag;
@@ -845,7 +903,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         const int P = p->proj_count > 0 ? p->proj_count : 4;
         const int w = p->proj_window > 0 ? p->proj_window : 8;
         const int D = p->proj_dims > 0 ? p->proj_dims : 8;
-        r = encoder_seed(p->encoder, X, K, P, D, w, p->seed, ws, &si, &sd, st);
+        r = encoder_seed(p->encoder, Xp, K, P, D, w, p->seed, ws, &si, &sd, st);
         if (r != KNN_OK) return r;
         seed_idx = si;
         seed_d2 = sd;
@@ -854,12 +912,13 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     }
     {
         dim3 grid((unsigned)ceil_div(n, 4));
-        // canonical FP32 direct-difference distances on the input values
+        // canonical FP32 direct-difference distances on the staged input values;
+        // caller lists are in input order, encoder seeds already in processing order
         const int sk = seed_idx ? seed_k : 0;
-        launch_by_dtype(X.dtype, [&](auto dt) {
-            nnd_init_kernel<decltype(dt)::value><<<grid, 256, 0, st>>>(n, K, X.data, X.ld, X.d, seed_idx, seed_d2,
-                                                                      seed_fl, sk, p->seed, gidx, gd2, gflag);
-        });
+        const bool given = init_idx != nullptr;
+        nnd_init_kernel<KNN_F32><<<grid, 256, 0, st>>>(n, K, Xs, ldp, X.d, seed_idx, seed_d2, seed_fl, sk, p->seed,
+                                                       gidx, gd2, gflag, given ? perm : nullptr,
+                                                       given ? inv : nullptr);
         KNN_HIP(hipGetLastError());
     }
     (void)hipEventRecord(t_init.b, st);
@@ -872,7 +931,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         ~HostFree() { (void)hipHostFree(p); }
     } hf{host_cnt};
     const double stop = (double)p->delta * (double)n * (double)K;
-    const size_t lds = ((size_t)64 * cfg.tdp + 128) * 4;
+    const size_t lds = ((size_t)std::max(64 * cfg.tdp, 64 * 65) + 128) * 4;
     const size_t merge_lds = (size_t)4 * cfg.C * 8;
     int dev = 0;
     KNN_HIP(hipGetDevice(&dev));
@@ -932,11 +991,9 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     {
         dim3 grid((unsigned)ceil_div(n, 4));
         const int k = p->k;
-        launch_by_dtype(X.dtype, [&](auto dt) {
-            nnd_finalize_kernel<decltype(dt)::value><<<grid, 256, 0, st>>>(
-                n, K, k, X.data, X.ld, X.d, gidx, gd2, gflag, p->out_kind, out_idx, out_dist, state_idx,
-                state_dist, state_flags);
-        });
+        nnd_finalize_kernel<<<grid, 256, 0, st>>>(n, K, k, (const float*)Xs, ldp, X.d, gidx, gd2, gflag,
+                                                  p->out_kind, out_idx, out_dist, state_idx, state_dist,
+                                                  state_flags, perm);
         KNN_HIP(hipGetLastError());
     }
     (void)hipEventRecord(t_fin.b, st);

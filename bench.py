@@ -163,7 +163,7 @@ def run_form(X, k, form, steps, warmup, rows, encoder=None):
     wall = time.perf_counter() - t0
     n, d = X.shape
     recall = recall_gpu(X, G, D, rows, k)
-    kern = "nnd_join_bf16_kernel" if p["precision"] == "bf16" else "nnd_join_f32_kernel"
+    kern = "nnd_join_kernel<true>" if p["precision"] == "bf16" else "nnd_join_kernel<false>"
     last = stats[-1]
     cfg = {kk: vv for kk, vv in p.items() if kk != "encoder"}
     cfg["build_k"] = last["build_k"]
@@ -172,6 +172,8 @@ def run_form(X, k, form, steps, warmup, rows, encoder=None):
             "params": cfg,
             "ms_breakdown": {kk: round(last[kk], 3) for kk in
                              ("ms_init", "ms_sample", "ms_join", "ms_merge", "ms_final", "ms_total")},
+            "per_iter": {"updates": last["updates"], "offers": last["emitted"],
+                         "ms_join": [round(x, 3) for x in last["ms_join_iter"]]},
             "roofline": join_roofline(stats, n, d, p, kern)}
 
 

@@ -34,20 +34,23 @@ constexpr int kListW = 32;        // list width per query row (k' <= 32)
 // ------------------------------------------------------------------ stage
 
 // One wave per row: padded copy (zeros beyond d) and the FP32 squared norm of
-// the stored values.  maxnorm receives the largest norm's float bits.
+// the stored values.  maxnorm receives the largest norm's float bits.  With
+// `aux`, the last 8 bytes of each row hold two FP32 words instead of zeros:
+// the norm and +inf (a per-row value that NNDescent keeps current).
 template <int DT, bool TO_BF16>
 __global__ __launch_bounds__(256) void stage_kernel(const void* __restrict__ X, int64_t n, int d,
                                                     int64_t ld, void* __restrict__ Xs, int ldp,
                                                     float* __restrict__ norms,
                                                     unsigned* __restrict__ maxnorm,
-                                                    const uint32_t* __restrict__ rowmap)
+                                                    const uint32_t* __restrict__ rowmap, int aux)
 {
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= n) return;
     const int64_t src = rowmap ? (int64_t)rowmap[row] : row;
+    const int lim = aux ? ldp - (TO_BF16 ? 4 : 2) : ldp;
     float s = 0.0f;
-    for (int t = lane; t < ldp; t += 64) {
+    for (int t = lane; t < lim; t += 64) {
         float v = t < d ? elem<DT>::ld(X, src * ld + t) : 0.0f;
         if (TO_BF16) {
             uint16_t b = f32_to_bf16_rne(v);
@@ -63,6 +66,11 @@ __global__ __launch_bounds__(256) void stage_kernel(const void* __restrict__ X, 
     if (lane == 0) {
         norms[row] = s;
         if (maxnorm) atomicMax(maxnorm, __float_as_uint(s));
+        if (aux) {
+            float* a = (float*)((char*)Xs + (row + 1) * (int64_t)ldp * (TO_BF16 ? 2 : 4)) - 2;
+            a[0] = s;
+            a[1] = __builtin_inff();
+        }
     }
 }
 
@@ -330,35 +338,38 @@ __global__ __launch_bounds__(256) void exact_fallback_kernel(
 
 template <bool TO_BF16>
 static void launch_stage(const knn_matrix& X, void* Xs, int ldp, float* norms, unsigned* maxn,
-                         const uint32_t* rowmap, hipStream_t st)
+                         const uint32_t* rowmap, int aux, hipStream_t st)
 {
     dim3 grid((unsigned)ceil_div(X.n, 4)), block(256);
     switch (X.dtype) {
     case KNN_F32:
-        stage_kernel<KNN_F32, TO_BF16><<<grid, block, 0, st>>>(X.data, X.n, X.d, X.ld, Xs, ldp, norms, maxn, rowmap);
+        stage_kernel<KNN_F32, TO_BF16><<<grid, block, 0, st>>>(X.data, X.n, X.d, X.ld, Xs, ldp, norms, maxn, rowmap, aux);
         break;
     case KNN_BF16:
-        stage_kernel<KNN_BF16, TO_BF16><<<grid, block, 0, st>>>(X.data, X.n, X.d, X.ld, Xs, ldp, norms, maxn, rowmap);
+        stage_kernel<KNN_BF16, TO_BF16><<<grid, block, 0, st>>>(X.data, X.n, X.d, X.ld, Xs, ldp, norms, maxn, rowmap, aux);
         break;
     default:
-        stage_kernel<KNN_F16, TO_BF16><<<grid, block, 0, st>>>(X.data, X.n, X.d, X.ld, Xs, ldp, norms, maxn, rowmap);
+        stage_kernel<KNN_F16, TO_BF16><<<grid, block, 0, st>>>(X.data, X.n, X.d, X.ld, Xs, ldp, norms, maxn, rowmap, aux);
         break;
     }
 }
 
 // Staged copy of a matrix for the GEMM (FP32 ld = roundup(d, 32) or BF16
 // ld = roundup(d, 64), both 128-byte multiples), norms and max norm.  Row r
-// of the copy is row rowmap[r] of X (rowmap nullable: identity).
+// of the copy is row rowmap[r] of X (rowmap nullable: identity).  With aux,
+// ld leaves room for the two trailing FP32 words (see stage_kernel).
 knn_status stage_matrix(Workspace& ws, const knn_matrix& X, bool bf16, void** Xs, int* ldp,
-                        float** norms, unsigned* maxnorm, hipStream_t st, const uint32_t* rowmap)
+                        float** norms, unsigned* maxnorm, hipStream_t st, const uint32_t* rowmap,
+                        int aux)
 {
-    *ldp = bf16 ? (int)round_up(X.d, 64) : (int)round_up(X.d, 32);
+    const int64_t need = X.d + (aux ? (bf16 ? 4 : 2) : 0);
+    *ldp = bf16 ? (int)round_up(need, 64) : (int)round_up(need, 32);
     knn_status r = ws.alloc(Xs, (size_t)X.n * (size_t)(*ldp) * (bf16 ? 2 : 4));
     if (r != KNN_OK) return r;
     r = ws.alloc(norms, (size_t)X.n);
     if (r != KNN_OK) return r;
-    if (bf16) launch_stage<true>(X, *Xs, *ldp, *norms, maxnorm, rowmap, st);
-    else launch_stage<false>(X, *Xs, *ldp, *norms, maxnorm, rowmap, st);
+    if (bf16) launch_stage<true>(X, *Xs, *ldp, *norms, maxnorm, rowmap, aux, st);
+    else launch_stage<false>(X, *Xs, *ldp, *norms, maxnorm, rowmap, aux, st);
     KNN_HIP(hipGetLastError());
     return KNN_OK;
 }
@@ -392,13 +403,13 @@ static knn_status exact_impl(const knn_matrix& Q, const knn_matrix& R, bool same
     void *Qs = nullptr, *Rs = nullptr;
     float *qn = nullptr, *rn = nullptr;
     int ldp = 0, ldp2 = 0;
-    r = stage_matrix(ws, R, bf, &Rs, &ldp, &rn, small, st, nullptr);
+    r = stage_matrix(ws, R, bf, &Rs, &ldp, &rn, small, st, nullptr, 0);
     if (r != KNN_OK) return r;
     if (same) {
         Qs = Rs;
         qn = rn;
     } else {
-        r = stage_matrix(ws, Q, bf, &Qs, &ldp2, &qn, nullptr, st, nullptr);
+        r = stage_matrix(ws, Q, bf, &Qs, &ldp2, &qn, nullptr, st, nullptr, 0);
         if (r != KNN_OK) return r;
     }
 

@@ -32,7 +32,8 @@
 namespace knn {
 
 knn_status stage_matrix(Workspace& ws, const knn_matrix& X, bool bf16, void** Xs, int* ldp,
-                        float** norms, unsigned* maxnorm, hipStream_t st, const uint32_t* rowmap);
+                        float** norms, unsigned* maxnorm, hipStream_t st, const uint32_t* rowmap,
+                        int aux);
 knn_status morton_order(const knn_matrix& X, int D, uint64_t seed, Workspace& ws, uint32_t** perm,
                         uint32_t** inv, hipStream_t st);
 
@@ -44,14 +45,16 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // One wave per row: entries from init_idx (nullable; invalid, self and
 // repeated entries dropped), completed with distinct uniform random indices,
 // distances (given, or canonical direct differences on the staged rows),
-// sorted, first K kept.  Flags: given (or new).
+// sorted, first K kept.  Flags: given (or new).  The K-th distance is also
+// written to the row's worst-distance word (worst[row * wstride]).
 template <int DT>
 __global__ __launch_bounds__(256) void nnd_init_kernel(
     int64_t n, int K, const void* __restrict__ Xs, int64_t ldp, int d,
     const int32_t* __restrict__ init_idx, const float* __restrict__ init_dist,
     const uint8_t* __restrict__ init_flags, int init_k, uint64_t seed,
     int32_t* __restrict__ gidx, float* __restrict__ gd2, uint8_t* __restrict__ gflag,
-    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ inv)
+    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ inv, float* __restrict__ worst,
+    int64_t wstride)
 {
     __shared__ uint32_t s_id[4][64];
     __shared__ float s_d2[4][64];
@@ -179,6 +182,7 @@ __global__ __launch_bounds__(256) void nnd_init_kernel(
         gidx[row * K + lane] = sv ? (int32_t)key_idx(sk) : -1;
         gd2[row * K + lane] = sv ? key_d2(sk) : __builtin_inff();
         gflag[row * K + lane] = sv ? sfl : 0;
+        if (lane == K - 1) worst[row * wstride] = sv ? key_d2(sk) : __builtin_inff();
     }
 }
 
@@ -244,10 +248,8 @@ __global__ __launch_bounds__(256) void nnd_sample_kernel(
 
 struct JoinCfg {
     int s, R, K, C, J;     // new sample, reverse slots, list size, candidate slots, cap
-    int lcap;              // max join-list length (rows staged in LDS), <= 64
+    int lcap;              // max join-list length, <= 64
     int ncap;              // max new-list length
-    int gstride;           // (unused)
-    int chunk, tdp;        // FP32 join: d-chunk staged per pass and its LDS row stride (floats)
 };
 
 constexpr int kJMax = 4;         // largest supported join cap
@@ -314,44 +316,44 @@ __device__ inline int join_lists(int64_t v, const JoinCfg& cfg, const int32_t* _
     return nn;
 }
 
-// Keep the J smallest keys (ascending) of a stream: insertion from the back.
-__device__ inline void topj_insert(uint64_t (&best)[kJMax], int J, uint64_t key)
+// Selection keys of the join epilogue: the FP32 bits of a squared distance
+// (non-negative, so unsigned order is numeric order) with the low 6 bits
+// replaced by the partner's position in the join list.  The truncation is a
+// relative 2^-17 of the distance, below the error of the norm-expansion
+// distances it orders; ties go to the lower position.
+constexpr uint32_t kNoSel = 0xFFFFFFFFu;
+
+// Keep the kJMax smallest keys (ascending): one min/max exchange per slot.
+__device__ inline void sel_insert(uint32_t (&best)[kJMax], uint32_t key)
 {
 #pragma unroll
     for (int q = 0; q < kJMax; ++q) {
-        if (q < J && key < best[q]) {
-            const uint64_t t = best[q];
-            best[q] = key;
-            key = t;
-        }
+        const uint32_t lo = min(best[q], key);
+        key = max(best[q], key);
+        best[q] = lo;
     }
 }
 
-__device__ inline float topj_cut(const uint64_t (&best)[kJMax], int J, float thr)
-{
-    uint64_t last = kEmptyCand;
-#pragma unroll
-    for (int q = 0; q < kJMax; ++q)
-        if (q == J - 1) last = best[q];
-    return last != kEmptyCand ? fminf(thr, key_d2(last)) : thr;
-}
-
-// Offer member `me` its kept partners: atomicMin of each key into slot
-// hash(partner, iteration) of me's candidate row.  Slots only decrease
-// during a launch, so a plain read that already shows a key at most as
-// large makes the atomic a no-op and it is skipped.
-__device__ inline unsigned long long emit_best(const uint64_t (&best)[kJMax], int J, uint32_t me, int C,
-                                               uint64_t salt, unsigned long long* __restrict__ cand)
+// Offer member `me` its kept partners q < J with q = par (mod 2) that beat
+// its current worst distance: atomicMin of the (distance, partner id) key
+// into slot hash(partner, iteration) of me's candidate row.  Slots only
+// decrease during a launch, so a plain read that already shows a key at most
+// as large makes the atomic a no-op and it is skipped.
+__device__ inline unsigned long long emit_best(const uint32_t (&best)[kJMax], int J, int par, float cut,
+                                               const uint32_t* ids, uint32_t me, int C, uint64_t salt,
+                                               unsigned long long* __restrict__ cand)
 {
     unsigned long long emitted = 0;
 #pragma unroll
     for (int q = 0; q < kJMax; ++q) {
-        if (q < J && best[q] != kEmptyCand) {
-            const uint32_t src = key_idx(best[q]);
+        const uint32_t b = best[q];
+        if (q < J && (q & 1) == par && b != kNoSel && __uint_as_float(b & ~63u) < cut) {
+            const uint32_t src = ids[b & 63u];
+            const uint64_t key = ((uint64_t)(b & ~63u) << 32) | src;
             const uint32_t slot = bounded(mix64(((uint64_t)src << 20) ^ salt), (uint32_t)C);
             unsigned long long* p = &cand[(int64_t)me * C + slot];
-            if (*p > (unsigned long long)best[q]) {
-                atomicMin(p, (unsigned long long)best[q]);
+            if (*p > (unsigned long long)key) {
+                atomicMin(p, (unsigned long long)key);
                 ++emitted;
             }
         }
@@ -359,268 +361,170 @@ __device__ inline unsigned long long emit_best(const uint64_t (&best)[kJMax], in
     return emitted;
 }
 
-// Local join, FP32 (VALU).  One wave per point v, grid-stride.
-//  1. the join lists are built (join_lists) and their rows staged in LDS in
-//     d-chunks (16 lanes x float4 per row);
-//  2. the Gram block new x list is accumulated with FP32 FMAs, register-
-//     blocked: lane (ag, bg) owns new rows ag + 8i (i < NI) and list rows
-//     bg + 8q (q < NQ), i.e. 4 NI NQ FMAs per NI + NQ LDS reads;
-//  3. the squared distances overwrite the staged rows in LDS (odd row stride);
-//  4. lane m scans member m's partners -- its row if it is new, its column
-//     over the new rows if it is old -- keeps the best J below its current
-//     worst distance and offers them.
-// Dynamic LDS: max(64 * tdp, 64 * 65) floats, ids[64], nrm[64].
-template <int NI, int NQ>
-__device__ inline void gram_f32(const float* __restrict__ Xs, int ldp, int d, int chunk, int tdp,
-                                float* buf, const uint32_t* ids, const float* nrm, int nn, int L)
-{
-    const int lane = threadIdx.x, ag = lane >> 3, bg = lane & 7;
-    float acc[NI][NQ];
-#pragma unroll
-    for (int i = 0; i < NI; ++i)
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) acc[i][q] = 0.0f;
-    int ra[NI], rb[NQ];
-#pragma unroll
-    for (int i = 0; i < NI; ++i) ra[i] = min(ag + 8 * i, L - 1);
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) rb[q] = min(bg + 8 * q, L - 1);
-    for (int c0 = 0; c0 < d; c0 += chunk) {
-        __syncthreads();
-        const int col = (lane & 15) * 4;
-        if (col < chunk) {
-            for (int m = lane >> 4; m < L; m += 4) {
-                const int t = c0 + col;
-                f32x4 x = {0.0f, 0.0f, 0.0f, 0.0f};
-                if (t < ldp) x = *(const f32x4*)(Xs + (int64_t)ids[m] * ldp + t);
-                *(f32x4*)(buf + m * tdp + col) = x;
-            }
-        }
-        __syncthreads();
-        const int tl = min(chunk, d - c0);
-        for (int t = 0; t < tl; t += 4) {
-            f32x4 xa[NI];
-#pragma unroll
-            for (int i = 0; i < NI; ++i) xa[i] = *(const f32x4*)(buf + ra[i] * tdp + t);
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const f32x4 xb = *(const f32x4*)(buf + rb[q] * tdp + t);
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-#pragma unroll
-                    for (int i = 0; i < NI; ++i) acc[i][q] = fmaf(xa[i][e], xb[e], acc[i][q]);
-            }
-        }
-    }
-    __syncthreads();   // every lane is done with the staged rows
-#pragma unroll
-    for (int i = 0; i < NI; ++i) {
-        const int a = ag + 8 * i;
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int b = bg + 8 * q;
-            if (a < nn && b < L) {
-                const float d2 = nrm[a] + nrm[b] - 2.0f * acc[i][q];
-                buf[a * 65 + b] = d2 > 0.0f ? d2 : 0.0f;
-            }
-        }
-    }
-    __syncthreads();
-}
-
-__global__ __launch_bounds__(64) void nnd_join_f32_kernel(
-    int64_t n, JoinCfg cfg, const float* __restrict__ Xs, int ldp, int d, const float* __restrict__ norms,
-    const float* __restrict__ gd2, const int32_t* __restrict__ newf,
-    unsigned long long* __restrict__ revnew, const int32_t* __restrict__ oldf,
-    unsigned long long* __restrict__ revold, unsigned long long* __restrict__ cand, uint64_t seed,
-    int iter, unsigned long long* __restrict__ counters)
-{
-    extern __shared__ float smem[];
-    const int tdp = cfg.tdp, chunk = cfg.chunk;
-    const int bufsz = 64 * tdp > 64 * 65 ? 64 * tdp : 64 * 65;
-    float* buf = smem;
-    uint32_t* ids = (uint32_t*)(buf + bufsz);
-    float* nrm = (float*)(ids + 64);
-    const int lane = threadIdx.x;
-    unsigned long long emitted = 0, gathered = 0;
-    const uint64_t salt = (uint64_t)iter ^ seed;
-
-    for (int64_t v = blockIdx.x; v < n; v += gridDim.x) {
-        int L = 0;
-        const int nn = join_lists(v, cfg, newf, revnew, oldf, revold, ids, L);
-        __syncthreads();
-        if (nn == 0 || L < 2) continue;
-        float tme = 0.0f;
-        if (lane < L) {
-            const uint32_t x = ids[lane];
-            nrm[lane] = norms[x];
-            tme = gd2[(int64_t)x * cfg.K + cfg.K - 1];
-        }
-        gathered += (unsigned long long)L;
-        const int ni = (nn + 15) >> 4;        // pairs of 8-row groups: 1..4
-        const int nq = L <= 32 ? 0 : (L <= 48 ? 1 : 2);
-        switch (ni * 4 + nq) {
-        case 4: gram_f32<2, 4>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
-        case 5: gram_f32<2, 6>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
-        case 6: gram_f32<2, 8>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
-        case 8: gram_f32<4, 4>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
-        case 9: gram_f32<4, 6>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
-        case 10: gram_f32<4, 8>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
-        case 12: gram_f32<6, 4>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
-        case 13: gram_f32<6, 6>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
-        case 14: gram_f32<6, 8>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
-        case 16: gram_f32<8, 4>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
-        case 17: gram_f32<8, 6>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
-        default: gram_f32<8, 8>(Xs, ldp, d, chunk, tdp, buf, ids, nrm, nn, L); break;
-        }
-        if (lane < L) {
-            const bool mnew = lane < nn;
-            uint64_t best[kJMax];
-#pragma unroll
-            for (int q = 0; q < kJMax; ++q) best[q] = kEmptyCand;
-            float cut = tme;
-            const int olim = mnew ? L : nn;
-            for (int o = 0; o < olim; ++o) {
-                const float d2 = mnew ? buf[lane * 65 + o] : buf[o * 65 + lane];
-                if (o != lane && d2 < cut) {
-                    topj_insert(best, cfg.J, make_key(d2, ids[o]));
-                    cut = topj_cut(best, cfg.J, cut);
-                }
-            }
-            emitted += emit_best(best, cfg.J, ids[lane], cfg.C, salt, cand);
-        }
-    }
-    for (int o = 32; o > 0; o >>= 1) emitted += shfl_u64(emitted, lane ^ o);
-    if (lane == 0) {
-        atomicAdd(&counters[1], emitted);
-        atomicAdd(&counters[2], gathered);
-    }
-}
-
-// Local join, BF16 form.  Same lists and offers; the L x L Gram of the list
-// rows (BF16 copies, RNE) comes from v_mfma_f32_32x32x16_bf16 with FP32
-// accumulation: four 32 x 32 tiles whose A and B operands are the same two
-// LDS vectors.  Lane (h, c) holds columns c and 32 + c (two members) and 16
-// rows of each tile; it keeps a partial best-J per column over its 32 rows,
-// swaps the partial list of one column with its partner lane (the other h)
-// and finalises the other.  Norms are FP32 norms of the rounded rows.
-constexpr int kTDB = 64;         // d-chunk (bf16 elements)
-constexpr int kTDBP = kTDB + 8;  // LDS row stride (elements): 144 bytes
+// Local join.  One wave per point v; the grid is split into 8 groups
+// (blockIdx mod 8, the round-robin XCD assignment of workgroups) that each
+// sweep one contiguous range of the processing order, so concurrently joined
+// points are Z-order neighbours sharing an L2.
+//
+// The join list (new members first, then old; L <= 64) is two 32-row
+// blocks.  Its L x L Gram is accumulated by 32 x 32 MFMA tiles whose
+// operands come straight from the staged rows into registers, no LDS copy:
+// lane (h, c) holds 16-byte pieces of rows c and 32 + c.  Piece p covers
+// bytes [32p + 16h, +16) of a row -- BF16 elements [16p + 8h, +8), one
+// 32x32x16 MFMA, or FP32 elements [8p + 4h, +4), four 32x32x2 MFMAs.  That
+// assigns the reduction index to (step, half) one-to-one, which is all a
+// Gram product needs since both operands use the same assignment.
+//
+// Column block cb (members 32cb + c) is finished before the next starts, so
+// two accumulator tiles are live.  Member m pairs with every row if it is
+// new and with the new rows if it is old; each lane keeps the best J of its
+// 32 rows that beat m's current worst distance, the two lanes of column m
+// swap and merge their lists, and each offers half of the merged best J.
+//
+// Row padding is zero except the last 8 bytes: the row's norm (of the stored
+// values) and the current worst distance of its list, read once per member
+// and zeroed in the operand piece that holds them.
+constexpr int kPC = 4;   // pieces per lane per row held in registers at a time
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__global__ __launch_bounds__(64) void nnd_join_bf16_kernel(
-    int64_t n, JoinCfg cfg, const uint16_t* __restrict__ Xb, int ldb, int d,
-    const float* __restrict__ norms, const float* __restrict__ gd2, const int32_t* __restrict__ newf,
-    unsigned long long* __restrict__ revnew, const int32_t* __restrict__ oldf,
-    unsigned long long* __restrict__ revold, unsigned long long* __restrict__ cand, uint64_t seed,
-    int iter, unsigned long long* __restrict__ counters)
+template <bool BF>
+__device__ inline f32x16 gram_step(const uint4& a, const uint4& b, f32x16 acc)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t rows[64 * kTDBP];
+    if constexpr (BF) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                        __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+    } else {
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), acc, 0, 0, 0);
+        return __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(b.w), acc, 0, 0, 0);
+    }
+}
+
+// Piece p of a row (r = row base + 16h bytes), branch-free: the load always
+// reads inside the row (p clamped, absent rows point at a listed row) and the
+// value is zeroed for an absent row or past the data; the trailing norm /
+// worst-distance words are cleared.
+__device__ inline uint4 load_piece(const uint8_t* r, int p, int np, bool valid, int64_t rowbytes, int h)
+{
+    const int pp = p < np ? p : np - 1;
+    uint4 x = *(const uint4*)(r + 32 * (int64_t)pp);
+    const bool keep = valid && p < np;
+    const bool tail = 32 * (int64_t)p + 16 * h + 16 == rowbytes;
+    x.x = keep ? x.x : 0u;
+    x.y = keep ? x.y : 0u;
+    x.z = keep && !tail ? x.z : 0u;
+    x.w = keep && !tail ? x.w : 0u;
+    return x;
+}
+
+// Candidates of member m from one 32-row block's accumulator column: rows
+// 32 blk + 8 (e / 4) + 4 h + e % 4 of tile entry e, branch-free.  Member m
+// pairs with rows i < lim (L if m is new, nn if it is old), i != m.
+__device__ inline void scan_block(const f32x16& g, int blk, int h4, int m, int lim, float nm,
+                                  const float* nrm, uint32_t (&best)[kJMax])
+{
+#pragma unroll
+    for (int e4 = 0; e4 < 4; ++e4) {
+        const int i0 = 32 * blk + 8 * e4 + h4;
+        const f32x4 ni = *(const f32x4*)(nrm + i0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = i0 + e;
+            float d2 = ni[e] + nm - 2.0f * g[4 * e4 + e];
+            d2 = d2 > 0.0f ? d2 : 0.0f;
+            const bool ok = i < lim && i != m;
+            sel_insert(best, ok ? ((__float_as_uint(d2) & ~63u) | (uint32_t)i) : kNoSel);
+        }
+    }
+}
+
+template <bool BF>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nnd_join_kernel(
+    int64_t n, JoinCfg cfg, const uint8_t* __restrict__ Xr, int64_t rowbytes, int np,
+    const int32_t* __restrict__ newf, unsigned long long* __restrict__ revnew,
+    const int32_t* __restrict__ oldf, unsigned long long* __restrict__ revold,
+    unsigned long long* __restrict__ cand, uint64_t seed, int iter, unsigned long long* __restrict__ counters)
+{
     __shared__ uint32_t ids[64];
-    __shared__ float nrm[64];
+    __shared__ __attribute__((aligned(16))) float nrm[64];
     __shared__ float thr[64];
     const int lane = threadIdx.x, c = lane & 31, h = lane >> 5;
     unsigned long long emitted = 0, gathered = 0;
     const uint64_t salt = (uint64_t)iter ^ seed;
-    const int dk = (int)round_up(d, 16);
     const int J = cfg.J;
+    const int nch = (np + kPC - 1) / kPC;
+    const unsigned grp = blockIdx.x & 7u;
+    const int64_t gsz = (int64_t)(gridDim.x >> 3);
+    const int64_t lo = n * grp / 8, hi = n * (grp + 1) / 8;
 
-    for (int64_t v = blockIdx.x; v < n; v += gridDim.x) {
+    for (int64_t v = lo + (int64_t)(blockIdx.x >> 3); v < hi; v += gsz) {
         int L = 0;
-        const int nn = join_lists(v, cfg, newf, revnew, oldf, revold, ids, L);
+        const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cfg, newf, revnew, oldf, revold, ids, L));
+        L = __builtin_amdgcn_readfirstlane(L);
         __syncthreads();
         if (nn == 0 || L < 2) continue;
         if (lane < L) {
-            const uint32_t x = ids[lane];
-            nrm[lane] = norms[x];
-            thr[lane] = gd2[(int64_t)x * cfg.K + cfg.K - 1];
+            const float2 a = *(const float2*)(Xr + (int64_t)ids[lane] * rowbytes + rowbytes - 8);
+            nrm[lane] = a.x;
+            thr[lane] = a.y;
+        } else {
+            nrm[lane] = 0.0f;
         }
         gathered += (unsigned long long)L;
         const bool two = L > 32;
-        f32x16 a00, a01, a10, a11;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            a00[e] = 0.0f;
-            a01[e] = 0.0f;
-            a10[e] = 0.0f;
-            a11[e] = 0.0f;
-        }
-        for (int c0 = 0; c0 < dk; c0 += kTDB) {
-            __syncthreads();
-            // 8 lanes x 16 bytes per row; rows past L are zero
-            for (int m = lane >> 3; m < (two ? 64 : 32); m += 8) {
-                const int t = c0 + (lane & 7) * 8;
-                uint4 x = {0u, 0u, 0u, 0u};
-                if (m < L && t < ldb) x = *(const uint4*)(Xb + (int64_t)ids[m] * ldb + t);
-                *(uint4*)(rows + m * kTDBP + (lane & 7) * 8) = x;
-            }
-            __syncthreads();
-            const int ks = min(kTDB, dk - c0) / 16;
-            for (int kk = 0; kk < ks; ++kk) {
-                const int off = kk * 16 + h * 8;
-                const bf16x8 r0 = __builtin_bit_cast(bf16x8, *(const uint4*)(rows + c * kTDBP + off));
-                a00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r0, r0, a00, 0, 0, 0);
-                if (two) {
-                    const bf16x8 r1 = __builtin_bit_cast(bf16x8, *(const uint4*)(rows + (32 + c) * kTDBP + off));
-                    a01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r0, r1, a01, 0, 0, 0);
-                    a10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r1, r0, a10, 0, 0, 0);
-                    a11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r1, r1, a11, 0, 0, 0);
-                }
-            }
-        }
-        // tile (rb, cb): lane holds column cb*32 + c, rows rb*32 + 8(e/4) + 4h + e%4
-        uint64_t p0[kJMax], p1[kJMax];
-#pragma unroll
-        for (int q = 0; q < kJMax; ++q) {
-            p0[q] = kEmptyCand;
-            p1[q] = kEmptyCand;
-        }
-        const int m0 = c, m1 = 32 + c;
-        float cut0 = m0 < L ? thr[m0] : -1.0f, cut1 = m1 < L ? thr[m1] : -1.0f;
-        const bool new0 = m0 < nn, new1 = m1 < nn;
-        const float n0 = nrm[m0 < L ? m0 : 0], n1 = nrm[m1 < L ? m1 : 0];
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb) {
+        const bool v0 = c < L, v1 = 32 + c < L;
+        const uint8_t* r0 = Xr + (int64_t)ids[v0 ? c : 0] * rowbytes + 16 * h;
+        const uint8_t* r1 = Xr + (int64_t)ids[v1 ? 32 + c : 0] * rowbytes + 16 * h;
+        __syncthreads();
+        uint4 A0[kPC], A1[kPC];
+        for (int cb = 0; cb < (two ? 2 : 1); ++cb) {
+            float z = 0.0f;
+            asm volatile("" : "+v"(z));   // one zero register per pass, not sixteen held ones
+            f32x16 at, ab;
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
-                const int i = rb * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
-                if (i >= L) continue;
-                const float ni = nrm[i];
-                const bool inew = i < nn;
-                const float g0 = rb == 0 ? a00[e] : a10[e];
-                const float g1 = rb == 0 ? a01[e] : a11[e];
-                if (i != m0 && (new0 || inew)) {
-                    float d2 = ni + n0 - 2.0f * g0;
-                    d2 = d2 > 0.0f ? d2 : 0.0f;
-                    if (d2 < cut0) {
-                        topj_insert(p0, J, make_key(d2, ids[i]));
-                        cut0 = topj_cut(p0, J, cut0);
+                at[e] = z;
+                ab[e] = z;
+            }
+            for (int ch = 0; ch < nch; ++ch) {
+                if (cb == 0 || nch > 1) {
+#pragma unroll
+                    for (int q = 0; q < kPC; ++q) {
+                        A0[q] = load_piece(r0, ch * kPC + q, np, v0, rowbytes, h);
+                        A1[q] = load_piece(r1, ch * kPC + q, np, v1 && two, rowbytes, h);
                     }
                 }
-                if (two && i != m1 && (new1 || inew)) {
-                    float d2 = ni + n1 - 2.0f * g1;
-                    d2 = d2 > 0.0f ? d2 : 0.0f;
-                    if (d2 < cut1) {
-                        topj_insert(p1, J, make_key(d2, ids[i]));
-                        cut1 = topj_cut(p1, J, cut1);
+                const int pc = min(kPC, np - ch * kPC);
+#pragma unroll
+                for (int q = 0; q < kPC; ++q) {
+                    if (q < pc) {
+                        const uint4 b = cb == 0 ? A0[q] : A1[q];
+                        at = gram_step<BF>(A0[q], b, at);
+                        if (two) ab = gram_step<BF>(A1[q], b, ab);
                     }
                 }
             }
-        }
-        // lane h = 0 finalises column m0, lane h = 1 column m1
-        uint64_t fin[kJMax];
-        uint64_t recv[kJMax];
+            // lane-dependent indices are re-derived per point (an opaque copy
+            // of the lane id) so that they are not held across the loop
+            int ln = lane;
+            asm volatile("" : "+v"(ln));
+            const int m = 32 * cb + (ln & 31), h4 = (ln >> 5) * 4;
+            uint32_t best[kJMax];
 #pragma unroll
-        for (int q = 0; q < kJMax; ++q) {
-            recv[q] = shfl_xor_u64(h == 0 ? p1[q] : p0[q], 32);
-            fin[q] = h == 0 ? p0[q] : p1[q];
-        }
+            for (int q = 0; q < kJMax; ++q) best[q] = kNoSel;
+            const float nm = nrm[m];
+            const int lim = m < nn ? L : nn;
+            scan_block(at, 0, h4, m, lim, nm, nrm, best);
+            if (two) scan_block(ab, 1, h4, m, lim, nm, nrm, best);
+            uint32_t recv[kJMax];
 #pragma unroll
-        for (int q = 0; q < kJMax; ++q)
-            if (q < J) topj_insert(fin, J, recv[q]);
-        const int mm = h == 0 ? m0 : m1;
-        if (mm < L) emitted += emit_best(fin, J, ids[mm], cfg.C, salt, cand);
+            for (int q = 0; q < kJMax; ++q) recv[q] = xor_u32(best[q], 32);
+#pragma unroll
+            for (int q = 0; q < kJMax; ++q) sel_insert(best, recv[q]);
+            if (m < L) emitted += emit_best(best, J, h, thr[m], ids, ids[m], cfg.C, salt, cand);
+        }
     }
     for (int o = 32; o > 0; o >>= 1) emitted += shfl_u64(emitted, lane ^ o);
     if (lane == 0) {
@@ -628,30 +532,18 @@ __global__ __launch_bounds__(64) void nnd_join_bf16_kernel(
         atomicAdd(&counters[2], gathered);
     }
 }
-
-knn_status nnd_join_bf16(int64_t n, const JoinCfg& cfg, const uint16_t* Xb, int ldb, int d,
-                         const float* norms, const float* gd2, const int32_t* newf,
-                         unsigned long long* revnew, const int32_t* oldf,
-                         unsigned long long* revold, unsigned long long* cand, uint64_t seed,
-                         int iter, unsigned long long* counters, unsigned grid, hipStream_t st)
-{
-    nnd_join_bf16_kernel<<<grid, 64, 0, st>>>(n, cfg, Xb, ldb, d, norms, gd2, newf, revnew, oldf, revold,
-                                             cand, seed, iter, counters);
-    KNN_HIP(hipGetLastError());
-    return KNN_OK;
-}
-
 // ------------------------------------------------------------------ merge
 
 // One wave per row (grid-stride).  Lanes 0..K-1 hold the sorted list.  The C
 // candidate slots are read 64 at a time (and reset), keys whose index is
 // already listed (or is the row) are dropped, the rest are compacted into LDS;
 // then rounds of (list + up to 64-K candidates) are bitonic-sorted and the
-// first K kept.  Entries that came from slots are flagged new and counted.
+// first K kept.  Entries that came from slots are flagged new and counted;
+// the new K-th distance goes to the row's worst-distance word.
 __global__ __launch_bounds__(256) void nnd_merge_kernel(
     int64_t n, int K, int C, int32_t* __restrict__ gidx, float* __restrict__ gd2,
     uint8_t* __restrict__ gflag, unsigned long long* __restrict__ cand,
-    unsigned long long* __restrict__ counters)
+    unsigned long long* __restrict__ counters, float* __restrict__ worst, int64_t wstride)
 {
     extern __shared__ uint64_t sbuf_all[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -717,6 +609,7 @@ __global__ __launch_bounds__(256) void nnd_merge_kernel(
             gidx[row * K + lane] = sv ? (int32_t)key_idx(cur) : -1;
             gd2[row * K + lane] = sv ? key_d2(cur) : __builtin_inff();
             gflag[row * K + lane] = sv ? (uint8_t)sfl : 0;
+            if (lane == K - 1) worst[row * wstride] = sv ? key_d2(cur) : __builtin_inff();
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
@@ -848,9 +741,6 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     cfg.lcap = cfg.s + cfg.R + cfg.K + cfg.R;
     if (cfg.lcap > 64) cfg.lcap = 64;
     if (cfg.ncap > 64) cfg.ncap = 64;
-    cfg.gstride = cfg.lcap | 1;
-    cfg.chunk = (int)std::min<int64_t>(64, round_up(X.d, 4));
-    cfg.tdp = cfg.chunk + 4;
 
     Timer t_all, t_init, t_fin;
     (void)hipEventRecord(t_all.a, st);
@@ -864,15 +754,21 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     void* Xs = nullptr;
     float* norms = nullptr;
     int ldp = 0;
-    r = stage_matrix(ws, X, false, &Xs, &ldp, &norms, nullptr, st, perm);
+    r = stage_matrix(ws, X, false, &Xs, &ldp, &norms, nullptr, st, perm, 1);
     if (r != KNN_OK) return r;
     void* Xb = nullptr;
     float* nb = nullptr;
     int ldb = 0;
     if (bf) {
-        r = stage_matrix(ws, X, true, &Xb, &ldb, &nb, nullptr, st, perm);
+        r = stage_matrix(ws, X, true, &Xb, &ldb, &nb, nullptr, st, perm, 1);
         if (r != KNN_OK) return r;
     }
+    // the copy the join reads, and its per-row worst-distance word
+    const uint8_t* Xr = (const uint8_t*)(bf ? Xb : Xs);
+    const int64_t rowbytes = bf ? (int64_t)ldb * 2 : (int64_t)ldp * 4;
+    const int np = (int)ceil_div((int64_t)X.d * (bf ? 2 : 4), 32);
+    float* worst = (float*)(Xr + rowbytes - 4);
+    const int64_t wstride = rowbytes / 4;
     const knn_matrix Xp = {Xs, X.n, X.d, ldp, KNN_F32};   // input values in processing order
     int32_t *gidx, *newf, *oldf;
     float* gd2;
@@ -918,7 +814,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         const bool given = init_idx != nullptr;
         nnd_init_kernel<KNN_F32><<<grid, 256, 0, st>>>(n, K, Xs, ldp, X.d, seed_idx, seed_d2, seed_fl, sk, p->seed,
                                                        gidx, gd2, gflag, given ? perm : nullptr,
-                                                       given ? inv : nullptr);
+                                                       given ? inv : nullptr, worst, wstride);
         KNN_HIP(hipGetLastError());
     }
     (void)hipEventRecord(t_init.b, st);
@@ -931,13 +827,17 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         ~HostFree() { (void)hipHostFree(p); }
     } hf{host_cnt};
     const double stop = (double)p->delta * (double)n * (double)K;
-    const size_t lds = ((size_t)std::max(64 * cfg.tdp, 64 * 65) + 128) * 4;
     const size_t merge_lds = (size_t)4 * cfg.C * 8;
     int dev = 0;
     KNN_HIP(hipGetDevice(&dev));
     int ncu = 256;
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    const unsigned join_grid = (unsigned)std::min<int64_t>(n, (int64_t)ncu * 8);
+    int jpc = 0;
+    KNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &jpc, bf ? (const void*)nnd_join_kernel<true> : (const void*)nnd_join_kernel<false>, 64, 0));
+    if (jpc < 1) jpc = 1;
+    // a multiple of 8: the join splits its grid into 8 contiguous point ranges
+    const unsigned join_grid = (unsigned)round_up((int64_t)ncu * jpc, 8);
     const unsigned merge_grid = (unsigned)std::min<int64_t>(ceil_div(n, 4), (int64_t)ncu * 8);
     int iters = 0;
     double ms_sample = 0, ms_join = 0, ms_merge = 0;
@@ -952,19 +852,17 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         KNN_HIP(hipGetLastError());
         (void)hipEventRecord(ts.b, st);
         (void)hipEventRecord(tj.a, st);
-        if (bf) {
-            r = nnd_join_bf16(n, cfg, (const uint16_t*)Xb, ldb, X.d, nb, gd2, newf, revnew, oldf, revold,
-                              cand, p->seed, iter, counters, join_grid, st);
-            if (r != KNN_OK) return r;
-        } else {
-            nnd_join_f32_kernel<<<join_grid, 64, lds, st>>>(n, cfg, (const float*)Xs, ldp, X.d, norms, gd2,
-                                                            newf, revnew, oldf, revold, cand, p->seed, iter,
-                                                            counters);
-            KNN_HIP(hipGetLastError());
-        }
+        if (bf)
+            nnd_join_kernel<true><<<join_grid, 64, 0, st>>>(n, cfg, Xr, rowbytes, np, newf, revnew, oldf,
+                                                            revold, cand, p->seed, iter, counters);
+        else
+            nnd_join_kernel<false><<<join_grid, 64, 0, st>>>(n, cfg, Xr, rowbytes, np, newf, revnew, oldf,
+                                                             revold, cand, p->seed, iter, counters);
+        KNN_HIP(hipGetLastError());
         (void)hipEventRecord(tj.b, st);
         (void)hipEventRecord(tm.a, st);
-        nnd_merge_kernel<<<merge_grid, 256, merge_lds, st>>>(n, K, cfg.C, gidx, gd2, gflag, cand, counters);
+        nnd_merge_kernel<<<merge_grid, 256, merge_lds, st>>>(n, K, cfg.C, gidx, gd2, gflag, cand, counters,
+                                                             worst, wstride);
         KNN_HIP(hipGetLastError());
         (void)hipEventRecord(tm.b, st);
         KNN_HIP(hipMemcpyAsync(host_cnt, counters, 32, hipMemcpyDeviceToHost, st));

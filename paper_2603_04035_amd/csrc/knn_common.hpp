@@ -286,9 +286,18 @@ knn_status fail(knn_status s, const std::string& msg);
     } while (0)
 
 // Scratch allocations for one call, released (stream-ordered) on scope exit.
+// Scratch for one entry-point call.  Requests are carved (256-byte aligned)
+// from a grow-only arena that the library keeps per device, so steady-state
+// calls neither allocate nor free device memory.  The arena is held by one
+// call at a time (a per-device lock taken by the constructor); the call's
+// stream first waits for the previous holder's work, and the destructor
+// records the point after which the arena is free again.  A request that
+// does not fit is served from a library-owned stream-ordered pool for this
+// call, and the arena is regrown to the call's total for the next one.
+// Only one Workspace may be alive per thread.
 class Workspace {
 public:
-    Workspace(hipStream_t s, int64_t limit) : stream_(s), limit_(limit) {}
+    Workspace(hipStream_t s, int64_t limit);
     ~Workspace();
     // returns KNN_OK or KNN_ENOMEM / KNN_EDEVICE
     knn_status alloc(void** p, size_t bytes);
@@ -299,8 +308,10 @@ public:
 private:
     hipStream_t stream_;
     int64_t limit_;
-    size_t used_ = 0;
-    void* ptrs_[64];
+    int dev_ = -1;
+    size_t used_ = 0;      // bytes handed out by this call (arena + overflow)
+    size_t off_ = 0;       // arena bytes used
+    void* ptrs_[64];       // overflow allocations of this call
     int nptr_ = 0;
 };
 
@@ -308,5 +319,9 @@ __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + 
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
 knn_status check_matrix(const knn_matrix& X, const char* name);
+
+// 64 bytes of pinned host memory for device -> host counter reads, one block
+// per host thread (null if the allocation failed).
+unsigned long long* pinned_counters();
 
 }  // namespace knn

@@ -241,6 +241,8 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ w, const 
 
 constexpr int kRsThreads = 256, kRsItems = 16, kRsTile = kRsThreads * kRsItems;
 
+static size_t rs_counts(int64_t n) { return (size_t)256 * ceil_div(n, kRsTile) + 256; }
+
 __global__ __launch_bounds__(256) void rs_hist_kernel(const uint32_t* __restrict__ keys, int64_t n, int shift,
                                                       uint32_t* __restrict__ counts, int nblk)
 {
@@ -256,30 +258,43 @@ __global__ __launch_bounds__(256) void rs_hist_kernel(const uint32_t* __restrict
     counts[(int64_t)threadIdx.x * nblk + blockIdx.x] = hist[threadIdx.x];
 }
 
-// Exclusive scan of m counts in place by one workgroup: thread t sums a
-// contiguous run of ceil(m/256) counts, the 256 run totals are scanned in LDS,
-// then every thread rewrites its run.
-__global__ __launch_bounds__(256) void rs_scan_kernel(uint32_t* __restrict__ c, int64_t m)
+// Exclusive scan of one value per thread of a 256-thread block (LDS
+// Hillis-Steele); *total receives the sum.
+__device__ inline uint32_t block_exscan256(uint32_t x, uint32_t* s, uint32_t* total)
+{
+    const int t = threadIdx.x;
+    __syncthreads();
+    s[t] = x;
+    __syncthreads();
+    for (int w = 1; w < 256; w <<= 1) {
+        const uint32_t y = t >= w ? s[t - w] : 0u;
+        __syncthreads();
+        s[t] += y;
+        __syncthreads();
+    }
+    const uint32_t incl = s[t];
+    *total = s[255];
+    return incl - x;
+}
+
+// Counts are digit-major (c[digit * nblk + tile]).  Block `digit` turns its
+// row into exclusive prefix sums over the tiles and writes the row total to
+// tot[digit]; the scatter adds the exclusive prefix of the totals.
+__global__ __launch_bounds__(256) void rs_scan_kernel(uint32_t* __restrict__ c, int nblk,
+                                                      uint32_t* __restrict__ tot)
 {
     __shared__ uint32_t s[256];
-    const int64_t per = (m + 255) / 256;
-    const int64_t b = threadIdx.x * per, e = b + per < m ? b + per : m;
-    uint32_t sum = 0;
-    for (int64_t i = b; i < e; ++i) sum += c[i];
-    s[threadIdx.x] = sum;
-    __syncthreads();
-    for (int w = 1; w < 256; w <<= 1) {   // Hillis-Steele inclusive scan of the run totals
-        const uint32_t y = (int)threadIdx.x >= w ? s[threadIdx.x - w] : 0u;
-        __syncthreads();
-        s[threadIdx.x] += y;
-        __syncthreads();
+    uint32_t* row = c + (int64_t)blockIdx.x * nblk;
+    uint32_t carry = 0;
+    for (int b0 = 0; b0 < nblk; b0 += 256) {
+        const int b = b0 + (int)threadIdx.x;
+        const uint32_t x = b < nblk ? row[b] : 0u;
+        uint32_t sum;
+        const uint32_t ex = block_exscan256(x, s, &sum);
+        if (b < nblk) row[b] = carry + ex;
+        carry += sum;
     }
-    uint32_t run = s[threadIdx.x] - sum;
-    for (int64_t i = b; i < e; ++i) {
-        const uint32_t x = c[i];
-        c[i] = run;
-        run += x;
-    }
+    if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
 // Stable scatter of one 8-bit digit: elements of a tile are visited in index
@@ -290,12 +305,16 @@ __global__ __launch_bounds__(256) void rs_scatter_kernel(const uint32_t* __restr
                                                          const uint32_t* __restrict__ vin,
                                                          uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                          int64_t n, int shift,
-                                                         const uint32_t* __restrict__ offs, int nblk)
+                                                         const uint32_t* __restrict__ offs, int nblk,
+                                                         const uint32_t* __restrict__ tot)
 {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[4][256];
+    __shared__ uint32_t sc[256];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    run[tid] = offs[(int64_t)tid * nblk + blockIdx.x];
+    uint32_t all;
+    const uint32_t dbase = block_exscan256(tot[tid], sc, &all);
+    run[tid] = dbase + offs[(int64_t)tid * nblk + blockIdx.x];
     const int64_t base = (int64_t)blockIdx.x * kRsTile;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int it = 0; it < kRsItems; ++it) {
@@ -333,6 +352,7 @@ __global__ __launch_bounds__(256) void rs_scatter_kernel(const uint32_t* __restr
 }
 
 // Sort (key, value) pairs of length n by key, stable; result in (k0, v0).
+// counts holds rs_counts(n) words.
 static knn_status radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
                                    uint32_t* counts, hipStream_t st)
 {
@@ -340,8 +360,9 @@ static knn_status radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uin
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 8 * pass;
         rs_hist_kernel<<<nblk, kRsThreads, 0, st>>>(k0, n, shift, counts, nblk);
-        rs_scan_kernel<<<1, 256, 0, st>>>(counts, (int64_t)256 * nblk);
-        rs_scatter_kernel<<<nblk, kRsThreads, 0, st>>>(k0, v0, k1, v1, n, shift, counts, nblk);
+        rs_scan_kernel<<<256, 256, 0, st>>>(counts, nblk, counts + (int64_t)256 * nblk);
+        rs_scatter_kernel<<<nblk, kRsThreads, 0, st>>>(k0, v0, k1, v1, n, shift, counts, nblk,
+                                                       counts + (int64_t)256 * nblk);
         KNN_HIP(hipGetLastError());
         std::swap(k0, k1);
         std::swap(v0, v1);
@@ -392,11 +413,22 @@ __device__ inline float f32_unorder(uint32_t u)
     return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
 }
 
+__global__ __launch_bounds__(64) void lohi_init_kernel(unsigned* __restrict__ lohi, int nq)
+{
+    const int q = threadIdx.x;
+    if (q < nq) {
+        lohi[2 * q] = 0xFFFFFFFFu;
+        lohi[2 * q + 1] = 0u;
+    }
+}
+
 // Per direction q: lohi[2q] = min, lohi[2q+1] = max of Y[q][*] as ordered
-// uint32 (integer atomics: exact and order-free).  lohi starts at (~0, 0).
+// uint32 (integer atomics: exact and order-free), one atomic pair per block
+// after an in-block reduction.  lohi starts at (~0, 0) (lohi_init_kernel).
 __global__ __launch_bounds__(256) void minmax_kernel(const float* __restrict__ Y, int64_t n,
                                                      unsigned* __restrict__ lohi)
 {
+    __shared__ uint32_t slo[4], shi[4];
     const int q = blockIdx.y;
     uint32_t lo = 0xFFFFFFFFu, hi = 0u;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -409,11 +441,24 @@ __global__ __launch_bounds__(256) void minmax_kernel(const float* __restrict__ Y
         lo = a < lo ? a : lo;
         hi = b > hi ? b : hi;
     }
+    const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
+        slo[wv] = lo;
+        shi[wv] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) {
+            lo = slo[w] < lo ? slo[w] : lo;
+            hi = shi[w] > hi ? shi[w] : hi;
+        }
         atomicMin(&lohi[2 * q], lo);
         atomicMax(&lohi[2 * q + 1], hi);
     }
 }
+
+// Blocks per direction for minmax_kernel: enough to stream Y, few atomics.
+static unsigned minmax_blocks(int64_t n) { return (unsigned)std::min<int64_t>(ceil_div(n, 256), 64); }
 
 // keys[p][i]: D = 1 -> the ordered projection; D > 1 -> Z-order code of the D
 // projections, each quantised to b = 32/D bits over [lo, hi]:
@@ -457,27 +502,37 @@ __global__ __launch_bounds__(256) void inverse_perm_kernel(const uint32_t* __res
     if (r < n) pos[order[r]] = (uint32_t)r;
 }
 
-// Y[j][i] = X_i . dirs_j over the d input coordinates (FP32 fused
-// multiply-adds in coordinate order), D directions.
+// Y[j][i] = X_i . dirs_j over the d input coordinates, D <= 8 directions.
+// 16 lanes per row (coalesced row reads), each summing a strided subset of
+// the coordinates, then a 16-lane reduction.
 template <int DT>
 __global__ __launch_bounds__(256) void xproj_kernel(const void* __restrict__ X, int64_t ld, int d, int64_t n,
                                                     const float* __restrict__ dirs, int D,
                                                     float* __restrict__ Y)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int g = threadIdx.x & 15;
+    const int64_t i = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    const bool live = i < n;
     float y[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) y[j] = 0.0f;
-    for (int t = 0; t < d; ++t) {
-        const float x = elem<DT>::ld(X, i * ld + t);
+    if (live) {
+        for (int t = g; t < d; t += 16) {
+            const float x = elem<DT>::ld(X, i * ld + t);
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            if (j < D) y[j] = fmaf(x, dirs[j * d + t], y[j]);
+            for (int j = 0; j < 8; ++j)
+                if (j < D) y[j] = fmaf(x, dirs[j * d + t], y[j]);
+        }
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-        if (j < D) Y[(int64_t)j * n + i] = y[j];
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) y[j] += xor_f32(y[j], o);
+    if (live) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (j < D && g == j) Y[(int64_t)j * n + i] = y[j];
+    }
 }
 
 // One wave per point: window candidates from every order (lane = (p, side,
@@ -499,16 +554,26 @@ __global__ __launch_bounds__(256) void proj_seed_kernel(const void* __restrict__
         const int64_t r = o < w ? r0 - (o + 1) : r0 + (o - w + 1);
         if (r >= 0 && r < n) cand = order[(int64_t)p * n + r];
     }
+    // repeats: every lane compares with all earlier lanes through LDS broadcasts
+    __shared__ __attribute__((aligned(16))) uint32_t sc[4][64];
+    const int wv = threadIdx.x >> 6;
+    sc[wv][lane] = cand;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     bool ok = cand != 0xFFFFFFFFu && cand != (uint32_t)i;
-    for (int o = 0; o < per * P; ++o) {
-        const uint32_t x = bcast_u32(cand, o);
-        ok = ok && !(o < lane && x == cand);
+#pragma unroll 4
+    for (int o = 0; o < 64; o += 4) {
+        const uint4 x = *(const uint4*)&sc[wv][o];
+        ok = ok && !(o + 0 < lane && x.x == cand) && !(o + 1 < lane && x.y == cand) &&
+             !(o + 2 < lane && x.z == cand) && !(o + 3 < lane && x.w == cand);
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     // compact, then 4 candidates per pass through the 16-lane distance groups
     const uint64_t mk = ballot(ok);
     const int cnt = popc64(mk);
-    __shared__ uint32_t sc[4][64];
-    const int wv = threadIdx.x >> 6;
     if (ok) sc[wv][rank_below(mk)] = cand;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -554,17 +619,13 @@ static knn_status proj_seed_impl(const knn_matrix& X, const float* Z, int m, con
     if ((r = ws.alloc(&k1, (size_t)n)) != KNN_OK) return r;
     if ((r = ws.alloc(&v1, (size_t)n)) != KNN_OK) return r;
     if ((r = ws.alloc(&pos, (size_t)n * P)) != KNN_OK) return r;
-    if ((r = ws.alloc(&counts, (size_t)256 * ceil_div(n, kRsTile))) != KNN_OK) return r;
+    if ((r = ws.alloc(&counts, rs_counts(n))) != KNN_OK) return r;
     const unsigned g = (unsigned)ceil_div(n, 256);
     if (m <= 32) proj_vals_kernel<32><<<g, 256, 0, st>>>(Z, n, m, dirs, P * D, Y);
     else proj_vals_kernel<0><<<g, 256, 0, st>>>(Z, n, m, dirs, P * D, Y);
     if (D > 1) {
-        std::vector<uint32_t> init((size_t)2 * P * D);
-        for (size_t q = 0; q < init.size(); ++q) init[q] = (q & 1) ? 0u : 0xFFFFFFFFu;
-        KNN_HIP(hipMemcpyAsync(lohi, init.data(), init.size() * 4, hipMemcpyHostToDevice, st));
-        dim3 mg((unsigned)std::min<int64_t>(ceil_div(n, 256), 1024), (unsigned)(P * D));
-        minmax_kernel<<<mg, 256, 0, st>>>(Y, n, lohi);
-        KNN_HIP(hipStreamSynchronize(st));   // the host init vector must outlive the copy
+        lohi_init_kernel<<<1, 64, 0, st>>>(lohi, P * D);
+        minmax_kernel<<<dim3(minmax_blocks(n), (unsigned)(P * D)), 256, 0, st>>>(Y, n, lohi);
     }
     morton_kernel<<<g, 256, 0, st>>>(Y, n, P, D, lohi, keys, vals);
     KNN_HIP(hipGetLastError());
@@ -582,7 +643,31 @@ static knn_status proj_seed_impl(const knn_matrix& X, const float* Z, int m, con
     return KNN_OK;
 }
 
-static std::vector<float> seeded_dirs(int P, int m, uint64_t seed);
+
+// P seeded directions on the unit sphere in R^m: Gaussians from the
+// Box-Muller transform of the counter-based hash (FP64), normalised.  One
+// wave per direction.
+__global__ __launch_bounds__(64) void dirs_kernel(int m, uint64_t seed, float* __restrict__ out)
+{
+    const int p = blockIdx.x, lane = threadIdx.x;
+    double ss = 0.0;
+    for (int t = lane; t < m; t += 64) {
+        const uint64_t h = hash4(seed ^ kTagDirs, (uint64_t)p, (uint64_t)t, 0);
+        const double u1 = ((h >> 11) + 1.0) * (1.0 / 9007199254740993.0);
+        const double u2 = (double)(hash4(seed ^ kTagDirs, (uint64_t)p, (uint64_t)t, 1) >> 11) *
+                          (1.0 / 9007199254740992.0);
+        const double g = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+        out[(int64_t)p * m + t] = (float)g;
+        ss += g * g;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t b = __double_as_longlong(ss);
+        const uint32_t lo = xor_u32((uint32_t)b, o), hi = xor_u32((uint32_t)(b >> 32), o);
+        ss += __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+    }
+    const double inv = 1.0 / sqrt(ss);
+    for (int t = lane; t < m; t += 64) out[(int64_t)p * m + t] = (float)((double)out[(int64_t)p * m + t] * inv);
+}
 
 // Internal processing order of the points: the Z-order curve of D seeded
 // random projections of X (4-bit codes for D = 8), ties by index.  Points
@@ -603,24 +688,20 @@ knn_status morton_order(const knn_matrix& X, int D, uint64_t seed, Workspace& ws
     if ((r = ws.alloc(&k1, (size_t)n)) != KNN_OK) return r;
     if ((r = ws.alloc(&v1, (size_t)n)) != KNN_OK) return r;
     if ((r = ws.alloc(&lohi, (size_t)2 * D)) != KNN_OK) return r;
-    if ((r = ws.alloc(&counts, (size_t)256 * ceil_div(n, kRsTile))) != KNN_OK) return r;
-    std::vector<float> hd = seeded_dirs(D, X.d, seed ^ 0x5DEECE66Dull);
-    std::vector<uint32_t> init((size_t)2 * D);
-    for (size_t q = 0; q < init.size(); ++q) init[q] = (q & 1) ? 0u : 0xFFFFFFFFu;
-    KNN_HIP(hipMemcpyAsync(dirs, hd.data(), hd.size() * 4, hipMemcpyHostToDevice, st));
-    KNN_HIP(hipMemcpyAsync(lohi, init.data(), init.size() * 4, hipMemcpyHostToDevice, st));
+    if ((r = ws.alloc(&counts, rs_counts(n))) != KNN_OK) return r;
+    dirs_kernel<<<D, 64, 0, st>>>(X.d, seed ^ 0x5DEECE66Dull, dirs);
     const unsigned g = (unsigned)ceil_div(n, 256);
     by_dtype(X.dtype, [&](auto dt) {
-        xproj_kernel<decltype(dt)::value><<<g, 256, 0, st>>>(X.data, X.ld, X.d, n, dirs, D, Y);
+        xproj_kernel<decltype(dt)::value><<<(unsigned)ceil_div(n, 16), 256, 0, st>>>(X.data, X.ld, X.d, n, dirs,
+                                                                                     D, Y);
     });
-    dim3 mg((unsigned)std::min<int64_t>(ceil_div(n, 256), 1024), (unsigned)D);
-    minmax_kernel<<<mg, 256, 0, st>>>(Y, n, lohi);
+    lohi_init_kernel<<<1, 64, 0, st>>>(lohi, D);
+    minmax_kernel<<<dim3(minmax_blocks(n), (unsigned)D), 256, 0, st>>>(Y, n, lohi);
     morton_kernel<<<g, 256, 0, st>>>(Y, n, 1, D, lohi, keys, *perm);
     KNN_HIP(hipGetLastError());
     if ((r = radix_sort_pairs(keys, *perm, k1, v1, n, counts, st)) != KNN_OK) return r;
     inverse_perm_kernel<<<g, 256, 0, st>>>(*perm, n, *inv);
     KNN_HIP(hipGetLastError());
-    KNN_HIP(hipStreamSynchronize(st));   // host vectors must outlive the copies
     return KNN_OK;
 }
 
@@ -634,30 +715,10 @@ static knn_status embed_impl(const knn_encoder* enc, const knn_matrix& X, float*
     return KNN_OK;
 }
 
-// P seeded directions on the unit sphere in R^m (normalised Gaussians via
-// the Box-Muller transform of the counter-based hash).
-static std::vector<float> seeded_dirs(int P, int m, uint64_t seed)
-{
-    std::vector<float> v((size_t)P * m);
-    for (int p = 0; p < P; ++p) {
-        double nrm = 0.0;
-        for (int t = 0; t < m; ++t) {
-            const uint64_t h = hash4(seed ^ kTagDirs, (uint64_t)p, (uint64_t)t, 0);
-            const double u1 = ((h >> 11) + 1.0) * (1.0 / 9007199254740993.0);
-            const double u2 = (double)(hash4(seed ^ kTagDirs, (uint64_t)p, (uint64_t)t, 1) >> 11) *
-                              (1.0 / 9007199254740992.0);
-            const double g = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
-            v[(size_t)p * m + t] = (float)g;
-            nrm += g * g;
-        }
-        nrm = sqrt(nrm);
-        for (int t = 0; t < m; ++t) v[(size_t)p * m + t] = (float)(v[(size_t)p * m + t] / nrm);
-    }
-    return v;
-}
-
-knn_status encoder_seed(const knn_encoder* enc, const knn_matrix& X, int K, int P, int D, int w, uint64_t seed,
-                        Workspace& ws, int32_t** seed_idx, float** seed_d2, hipStream_t st)
+// Seed lists from the encoder: X is embedded, the seeds' distances are taken
+// on Xd (the same points; the BF16 copy in the BF16 form).
+knn_status encoder_seed(const knn_encoder* enc, const knn_matrix& X, const knn_matrix& Xd, int K, int P, int D,
+                        int w, uint64_t seed, Workspace& ws, int32_t** seed_idx, float** seed_d2, hipStream_t st)
 {
     if (2 * w * P > 64) return fail(KNN_EINVAL, "2 * proj_window * proj_count must be <= 64");
     if (D < 1 || D > 8 || 32 % D) return fail(KNN_EINVAL, "proj_dims must be 1, 2, 4 or 8");
@@ -667,13 +728,10 @@ knn_status encoder_seed(const knn_encoder* enc, const knn_matrix& X, int K, int 
     if ((r = ws.alloc(&dirs, (size_t)P * D * H2)) != KNN_OK) return r;
     if ((r = ws.alloc(seed_idx, (size_t)X.n * K)) != KNN_OK) return r;
     if ((r = ws.alloc(seed_d2, (size_t)X.n * K)) != KNN_OK) return r;
-    std::vector<float> hd = seeded_dirs(P * D, H2, seed);
-    KNN_HIP(hipMemcpyAsync(dirs, hd.data(), hd.size() * 4, hipMemcpyHostToDevice, st));
+    dirs_kernel<<<P * D, 64, 0, st>>>(H2, seed, dirs);
+    KNN_HIP(hipGetLastError());
     if ((r = embed_impl(enc, X, Z, st)) != KNN_OK) return r;
-    r = proj_seed_impl(X, Z, H2, dirs, P, D, w, K, *seed_idx, *seed_d2, ws, st);
-    if (r != KNN_OK) return r;
-    KNN_HIP(hipStreamSynchronize(st));   // host vector hd must outlive the copy
-    return KNN_OK;
+    return proj_seed_impl(Xd, Z, H2, dirs, P, D, w, K, *seed_idx, *seed_d2, ws, st);
 }
 
 // Forward + loss + backward of one batch (rows: 3B device ints).  Leaves the

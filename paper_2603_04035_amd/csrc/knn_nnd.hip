@@ -38,6 +38,10 @@ knn_status morton_order(const knn_matrix& X, int D, uint64_t seed, Workspace& ws
                         uint32_t** inv, hipStream_t st);
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Old (already joined) list entries carry this bit in the index word of
+// their sort keys; indices stay below 2^31 - 1.
+constexpr uint32_t kWasOld = 1u << 31;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // ------------------------------------------------------------------ init
@@ -167,19 +171,15 @@ __global__ __launch_bounds__(256) void nnd_init_kernel(
         const float got = shfl_f32(v, ((lane - base) & 3) * 16);
         if (lane >= base && lane < base + 4 && !hasd) mine = got;
     }
-    // 4. sort by (d2, id), carry flags, keep the first K
+    // 4. sort by (d2, old after new, id) -- the merge's list order -- and keep
+    //    the first K; the old flag rides in the index word
     const bool live = lane < cnt && id != 0xFFFFFFFFu;
-    const uint64_t key = live ? make_key(mine, id) : kEmptyCand;
+    const uint64_t key = live ? make_key(mine, id | (fl ? 0u : kWasOld)) : kEmptyCand;
     const uint64_t sk = seg_sort<64>(key);
-    uint8_t sfl = 1;
-    for (int o = 0; o < cnt; ++o) {
-        uint64_t ok2 = bcast_u64(key, o);
-        uint32_t of = bcast_u32(fl, o);
-        if (ok2 == sk) sfl = (uint8_t)of;
-    }
+    const uint8_t sfl = (key_idx(sk) & kWasOld) ? 0 : 1;
     if (lane < K) {
         const bool sv = key_valid(sk);
-        gidx[row * K + lane] = sv ? (int32_t)key_idx(sk) : -1;
+        gidx[row * K + lane] = sv ? (int32_t)(key_idx(sk) & ~kWasOld) : -1;
         gd2[row * K + lane] = sv ? key_d2(sk) : __builtin_inff();
         gflag[row * K + lane] = sv ? sfl : 0;
         if (lane == K - 1) worst[row * wstride] = sv ? key_d2(sk) : __builtin_inff();
@@ -190,57 +190,65 @@ __global__ __launch_bounds__(256) void nnd_init_kernel(
 
 // Half-wave (32 lanes) per row, K <= 32.  Picks the s new entries with the
 // smallest priorities (ties by position), marks them old, lists old entries,
-// and scatters reverse edges into R slots per target row.
+// and scatters reverse edges into R slots per target row.  Waves take row
+// pairs from contiguous ranges, one range per group of blockIdx mod 8 (the
+// XCD of the workgroup), so the scattered targets of concurrent rows are
+// mostly Z-order neighbours.  gridDim.x is a multiple of 8.
 __global__ __launch_bounds__(256) void nnd_sample_kernel(
     int64_t n, int K, int s, int R, int32_t* __restrict__ gidx, uint8_t* __restrict__ gflag,
     int32_t* __restrict__ newf, int32_t* __restrict__ oldf, unsigned long long* __restrict__ revnew,
     unsigned long long* __restrict__ revold, uint64_t seed, int iter)
 {
     const int lane = threadIdx.x & 63, hl = lane & 31, hbase = lane & 32;
-    const int64_t row = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 2 + (lane >> 5);
-    const bool rv = row < n;
-    const bool inl = rv && hl < K;
-    int32_t id = -1;
-    uint8_t fl = 0;
-    if (inl) {
-        id = gidx[row * K + hl];
-        fl = gflag[row * K + hl];
-    }
-    const bool isnew = inl && id >= 0 && fl;
-    const bool isold = inl && id >= 0 && !fl;
-    uint64_t pr = isnew ? hash4(seed ^ kTagSample, (uint64_t)iter, (uint64_t)row, (uint64_t)id)
-                        : ~0ull;
-    // rank among the new entries of this half
-    int rank = 0;
-    for (int o = 0; o < 32; ++o) {
-        const uint64_t p0 = bcast_u64(pr, o), p1 = bcast_u64(pr, 32 + o);
-        const uint64_t po = hbase ? p1 : p0;
-        rank += (po < pr || (po == pr && o < hl)) ? 1 : 0;
-    }
-    const bool pick = isnew && rank < s;
-    const uint64_t nm = ballot(isnew), om = ballot(isold);
-    const uint64_t hn = hbase ? (nm >> 32) : (nm & 0xFFFFFFFFull);
-    const uint64_t ho = hbase ? (om >> 32) : (om & 0xFFFFFFFFull);
-    const int npick = __popcll(hn) < s ? __popcll(hn) : s;
-    const int nold = __popcll(ho);
-    const int opos = __popcll(ho & ((1ull << hl) - 1ull));
-    // slots past the picks / old entries get -1 (disjoint from the writes below)
-    if (rv && hl >= npick && hl < s) newf[row * s + hl] = -1;
-    if (rv && hl >= nold && hl < K) oldf[row * K + hl] = -1;
-    if (pick) {
-        newf[row * s + rank] = id;
-        gflag[row * K + hl] = 0;
-        const uint32_t slot = bounded(hash4(seed ^ kTagRevSlot, (uint64_t)iter, (uint64_t)row, 1), (uint32_t)R);
-        const uint64_t key = (hash4(seed ^ kTagRevNew, (uint64_t)iter, (uint64_t)row, (uint64_t)id) &
-                              0xFFFFFFFF00000000ull) | (uint64_t)row;
-        atomicMin(&revnew[(int64_t)id * R + slot], (unsigned long long)key);
-    }
-    if (isold) {
-        oldf[row * K + opos] = id;
-        const uint32_t slot = bounded(hash4(seed ^ kTagRevSlot, (uint64_t)iter, (uint64_t)row, 2), (uint32_t)R);
-        const uint64_t key = (hash4(seed ^ kTagRevOld, (uint64_t)iter, (uint64_t)row, (uint64_t)id) &
-                              0xFFFFFFFF00000000ull) | (uint64_t)row;
-        atomicMin(&revold[(int64_t)id * R + slot], (unsigned long long)key);
+    const unsigned grp = blockIdx.x & 7u;
+    const int64_t lo = n * grp / 8, hi = n * (grp + 1) / 8;
+    const int64_t wstep = (int64_t)(gridDim.x >> 3) * 4;
+    for (int64_t pw = (int64_t)(blockIdx.x >> 3) * 4 + (threadIdx.x >> 6); lo + 2 * pw < hi; pw += wstep) {
+        const int64_t row = lo + 2 * pw + (lane >> 5);
+        const bool rv = row < hi;
+        const bool inl = rv && hl < K;
+        int32_t id = -1;
+        uint8_t fl = 0;
+        if (inl) {
+            id = gidx[row * K + hl];
+            fl = gflag[row * K + hl];
+        }
+        const bool isnew = inl && id >= 0 && fl;
+        const bool isold = inl && id >= 0 && !fl;
+        uint64_t pr = isnew ? hash4(seed ^ kTagSample, (uint64_t)iter, (uint64_t)row, (uint64_t)id)
+                            : ~0ull;
+        // rank among the new entries of this half
+        int rank = 0;
+        for (int o = 0; o < 32; ++o) {
+            const uint64_t p0 = bcast_u64(pr, o), p1 = bcast_u64(pr, 32 + o);
+            const uint64_t po = hbase ? p1 : p0;
+            rank += (po < pr || (po == pr && o < hl)) ? 1 : 0;
+        }
+        const bool pick = isnew && rank < s;
+        const uint64_t nm = ballot(isnew), om = ballot(isold);
+        const uint64_t hn = hbase ? (nm >> 32) : (nm & 0xFFFFFFFFull);
+        const uint64_t ho = hbase ? (om >> 32) : (om & 0xFFFFFFFFull);
+        const int npick = __popcll(hn) < s ? __popcll(hn) : s;
+        const int nold = __popcll(ho);
+        const int opos = __popcll(ho & ((1ull << hl) - 1ull));
+        // slots past the picks / old entries get -1 (disjoint from the writes below)
+        if (rv && hl >= npick && hl < s) newf[row * s + hl] = -1;
+        if (rv && hl >= nold && hl < K) oldf[row * K + hl] = -1;
+        if (pick) {
+            newf[row * s + rank] = id;
+            gflag[row * K + hl] = 0;
+            const uint32_t slot = bounded(hash4(seed ^ kTagRevSlot, (uint64_t)iter, (uint64_t)row, 1), (uint32_t)R);
+            const uint64_t key = (hash4(seed ^ kTagRevNew, (uint64_t)iter, (uint64_t)row, (uint64_t)id) &
+                                  0xFFFFFFFF00000000ull) | (uint64_t)row;
+            atomicMin(&revnew[(int64_t)id * R + slot], (unsigned long long)key);
+        }
+        if (isold) {
+            oldf[row * K + opos] = id;
+            const uint32_t slot = bounded(hash4(seed ^ kTagRevSlot, (uint64_t)iter, (uint64_t)row, 2), (uint32_t)R);
+            const uint64_t key = (hash4(seed ^ kTagRevOld, (uint64_t)iter, (uint64_t)row, (uint64_t)id) &
+                                  0xFFFFFFFF00000000ull) | (uint64_t)row;
+            atomicMin(&revold[(int64_t)id * R + slot], (unsigned long long)key);
+        }
     }
 }
 
@@ -254,56 +262,74 @@ struct JoinCfg {
 
 constexpr int kJMax = 4;         // largest supported join cap
 
-// Per-point join lists.  Lanes 0..s-1 take new_f(v), s..s+R-1 the reverse-new
-// slots (consumed and reset), and likewise old_f(v) / reverse-old in a second
-// register.  Repeats are dropped, an id in both lists stays new, v itself is
-// dropped.  The surviving ids are written to ids[0..nn) (new) and
-// ids[nn..nn+no) (old).  Returns nn, sets L.
-__device__ inline int join_lists(int64_t v, const JoinCfg& cfg, const int32_t* __restrict__ newf,
-                                 unsigned long long* __restrict__ revnew,
-                                 const int32_t* __restrict__ oldf,
-                                 unsigned long long* __restrict__ revold, uint32_t* ids, int& L)
+// Raw join-list entries of one lane: lanes 0..s-1 hold new_f(v), lanes
+// s..s+R-1 the reverse-new slots (key with the source id in the low word),
+// and likewise old_f(v) / reverse-old in `o`; ~0 marks an empty entry.
+// Loaded one point ahead of the join that consumes them.
+struct ListRaw {
+    uint64_t n, o;
+};
+
+__device__ inline ListRaw load_lists(int64_t v, bool valid, const JoinCfg& cfg,
+                                     const int32_t* __restrict__ newf,
+                                     const unsigned long long* __restrict__ revnew,
+                                     const int32_t* __restrict__ oldf,
+                                     const unsigned long long* __restrict__ revold)
 {
     const int lane = threadIdx.x;
-    uint32_t nid = 0xFFFFFFFFu, oid = 0xFFFFFFFFu;
-    if (lane < cfg.s) {
-        const int32_t x = newf[v * cfg.s + lane];
-        if (x >= 0) nid = (uint32_t)x;
-    } else if (lane < cfg.s + cfg.R) {
-        unsigned long long* p = &revnew[v * cfg.R + (lane - cfg.s)];
-        const unsigned long long x = *p;
-        if (x != ~0ull) {
-            nid = (uint32_t)x;
-            *p = ~0ull;
+    ListRaw r = {~0ull, ~0ull};
+    if (valid) {
+        if (lane < cfg.s) {
+            const int32_t x = newf[v * cfg.s + lane];
+            if (x >= 0) r.n = (uint64_t)(uint32_t)x;
+        } else if (lane < cfg.s + cfg.R) {
+            r.n = revnew[v * cfg.R + (lane - cfg.s)];
+        }
+        if (lane < cfg.K) {
+            const int32_t x = oldf[v * cfg.K + lane];
+            if (x >= 0) r.o = (uint64_t)(uint32_t)x;
+        } else if (lane < cfg.K + cfg.R) {
+            r.o = revold[v * cfg.R + (lane - cfg.K)];
         }
     }
-    if (lane < cfg.K) {
-        const int32_t x = oldf[v * cfg.K + lane];
-        if (x >= 0) oid = (uint32_t)x;
-    } else if (lane < cfg.K + cfg.R) {
-        unsigned long long* p = &revold[v * cfg.R + (lane - cfg.K)];
-        const unsigned long long x = *p;
-        if (x != ~0ull) {
-            oid = (uint32_t)x;
-            *p = ~0ull;
-        }
-    }
+    return r;
+}
+
+// Per-point join lists from the raw entries.  The reverse slots are reset
+// for the next iteration.  Repeats are dropped (first position wins), an id
+// in both lists stays new, v itself is dropped.  Every lane compares its
+// entries with all 128 through LDS broadcast reads (sh: 128 words).  The
+// surviving ids are written to ids[0..nn) (new) and ids[nn..nn+no) (old).
+// Returns nn, sets L.
+__device__ inline int join_lists(int64_t v, const ListRaw& raw, const JoinCfg& cfg,
+                                 unsigned long long* __restrict__ revnew,
+                                 unsigned long long* __restrict__ revold, uint32_t* sh,
+                                 uint32_t* ids, int& L)
+{
+    const int lane = threadIdx.x;
+    if (lane >= cfg.s && lane < cfg.s + cfg.R) revnew[v * cfg.R + (lane - cfg.s)] = ~0ull;
+    if (lane >= cfg.K && lane < cfg.K + cfg.R) revold[v * cfg.R + (lane - cfg.K)] = ~0ull;
+    const uint32_t nid = raw.n == ~0ull ? 0xFFFFFFFFu : (uint32_t)raw.n;
+    const uint32_t oid = raw.o == ~0ull ? 0xFFFFFFFFu : (uint32_t)raw.o;
+    sh[lane] = nid;
+    sh[64 + lane] = oid;
+    __syncthreads();
+    int ln = lane;
+    asm volatile("" : "+v"(ln));   // keep the position tests per point, not hoisted masks
     bool nv = nid != 0xFFFFFFFFu && nid != (uint32_t)v;
     bool ov = oid != 0xFFFFFFFFu && oid != (uint32_t)v;
-    // repeats: reverse entries against forward ones (forward lists hold distinct ids)
-    for (int o = 0; o < cfg.s; ++o) {
-        const uint32_t x = bcast_u32(nid, o);
-        nv = nv && !(lane >= cfg.s && x == nid);
-        ov = ov && x != oid;
+#pragma unroll 2
+    for (int q = 0; q < 64; q += 4) {
+        const uint4 x = *(const uint4*)(sh + q);
+        nv = nv && !(q + 0 < ln && x.x == nid) && !(q + 1 < ln && x.y == nid) &&
+             !(q + 2 < ln && x.z == nid) && !(q + 3 < ln && x.w == nid);
+        ov = ov && x.x != oid && x.y != oid && x.z != oid && x.w != oid;
     }
-    for (int o = cfg.s; o < cfg.s + cfg.R; ++o) {
-        const uint32_t x = bcast_u32(nid, o);
-        nv = nv && !(o < lane && x == nid);
-        ov = ov && x != oid;
-    }
-    for (int o = 0; o < cfg.K + cfg.R; ++o) {
-        const uint32_t x = bcast_u32(oid, o);
-        ov = ov && !(o < lane && x == oid);
+#pragma unroll 2
+    for (int q = 0; q < 64; q += 4) {
+        const uint4 x = *(const uint4*)(sh + 64 + q);
+        ov = ov && !(q + 0 < ln && x.x == oid) && !(q + 1 < ln && x.y == oid) &&
+             !(q + 2 < ln && x.z == oid) && !(q + 3 < ln && x.w == oid);
     }
     const uint64_t nm = ballot(nv), om = ballot(ov);
     int nn = popc64(nm), no = popc64(om);
@@ -450,6 +476,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     __shared__ uint32_t ids[64];
     __shared__ __attribute__((aligned(16))) float nrm[64];
     __shared__ float thr[64];
+    __shared__ __attribute__((aligned(16))) uint32_t sh[128];
     const int lane = threadIdx.x, c = lane & 31, h = lane >> 5;
     unsigned long long emitted = 0, gathered = 0;
     const uint64_t salt = (uint64_t)iter ^ seed;
@@ -459,10 +486,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     const int64_t gsz = (int64_t)(gridDim.x >> 3);
     const int64_t lo = n * grp / 8, hi = n * (grp + 1) / 8;
 
-    for (int64_t v = lo + (int64_t)(blockIdx.x >> 3); v < hi; v += gsz) {
+    int64_t v = lo + (int64_t)(blockIdx.x >> 3);
+    ListRaw cur = load_lists(v, v < hi, cfg, newf, revnew, oldf, revold);
+    for (; v < hi; v += gsz) {
         int L = 0;
-        const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cfg, newf, revnew, oldf, revold, ids, L));
+        const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cur, cfg, revnew, revold, sh, ids, L));
         L = __builtin_amdgcn_readfirstlane(L);
+        // the next point's lists are in flight while this one is joined
+        cur = load_lists(v + gsz, v + gsz < hi, cfg, newf, revnew, oldf, revold);
         __syncthreads();
         if (nn == 0 || L < 2) continue;
         if (lane < L) {
@@ -534,82 +565,119 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
 }
 // ------------------------------------------------------------------ merge
 
-// One wave per row (grid-stride).  Lanes 0..K-1 hold the sorted list.  The C
-// candidate slots are read 64 at a time (and reset), keys whose index is
-// already listed (or is the row) are dropped, the rest are compacted into LDS;
-// then rounds of (list + up to 64-K candidates) are bitonic-sorted and the
-// first K kept.  Entries that came from slots are flagged new and counted;
-// the new K-th distance goes to the row's worst-distance word.
+// One wave per row, rows taken from 8 contiguous ranges (blockIdx mod 8, as
+// in the sample kernel; gridDim.x is a multiple of 8), the next row's list
+// and first 64 slots loaded while the current row is merged.  Lanes 0..K-1
+// hold the sorted list.  The C candidate slots are read 64 at a time (and
+// reset); keys whose index is already listed (or is the row) are dropped,
+// the rest are compacted into LDS; then rounds of (list + up to 64-K
+// candidates) are bitonic-sorted and the first K kept.  Old list entries
+// carry kWasOld in the index word, so lists are ordered by (distance, old
+// after new, index) -- the order the init kernel also sorts by, which makes
+// a resumed run bitwise equal to an uninterrupted one.  Entries whose index
+// is not in the previous list came from slots: flagged new and counted.  The
+// new K-th distance goes to the row's worst-distance word.
+
 __global__ __launch_bounds__(256) void nnd_merge_kernel(
     int64_t n, int K, int C, int32_t* __restrict__ gidx, float* __restrict__ gd2,
     uint8_t* __restrict__ gflag, unsigned long long* __restrict__ cand,
     unsigned long long* __restrict__ counters, float* __restrict__ worst, int64_t wstride)
 {
     extern __shared__ uint64_t sbuf_all[];
+    __shared__ __attribute__((aligned(16))) uint32_t slid[4][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     uint64_t* sbuf = sbuf_all + (size_t)wv * C;
-    const int64_t wglob = (int64_t)blockIdx.x * 4 + wv;
-    const int64_t wstep = (int64_t)gridDim.x * 4;
+    const unsigned grp = blockIdx.x & 7u;
+    const int64_t lo = n * grp / 8, hi = n * (grp + 1) / 8;
+    const int64_t wstep = (int64_t)(gridDim.x >> 3) * 4;
     unsigned long long upd = 0;
-    for (int64_t row = wglob; row < n; row += wstep) {
-        uint64_t okey = kEmptyCand;
-        uint32_t fl = 0, lid = 0xFFFFFFFFu;
+    int64_t row = lo + (int64_t)(blockIdx.x >> 3) * 4 + wv;
+    // current row's raw inputs
+    uint64_t slot0 = kEmptyCand;
+    int32_t id = -1;
+    float dd = 0.0f;
+    uint8_t fl = 0;
+    if (row < hi) {
+        if (lane < C) slot0 = cand[row * C + lane];
         if (lane < K) {
-            const int32_t x = gidx[row * K + lane];
-            if (x >= 0) {
-                lid = (uint32_t)x;
-                okey = make_key(gd2[row * K + lane], lid);
-                fl = gflag[row * K + lane];
-            } else {
-                okey = kEmptyList;
+            id = gidx[row * K + lane];
+            dd = gd2[row * K + lane];
+            fl = gflag[row * K + lane];
+        }
+    }
+    for (; row < hi; row += wstep) {
+        const uint32_t lid = id >= 0 ? (uint32_t)id : 0xFFFFFFFFu;
+        uint64_t okey = kEmptyCand;
+        if (lane < K)
+            okey = id >= 0 ? make_key(dd, lid | (fl ? 0u : kWasOld)) : kEmptyList;
+        uint64_t first = slot0;
+        // next row's inputs are in flight during this merge
+        const int64_t nrow = row + wstep;
+        slot0 = kEmptyCand;
+        id = -1;
+        if (nrow < hi) {
+            if (lane < C) slot0 = cand[nrow * C + lane];
+            if (lane < K) {
+                id = gidx[nrow * K + lane];
+                dd = gd2[nrow * K + lane];
+                fl = gflag[nrow * K + lane];
             }
         }
+        slid[wv][lane] = lid;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         int nc = 0;
         for (int c0 = 0; c0 < C; c0 += 64) {
             uint64_t key = kEmptyCand;
             if (c0 + lane < C) {
                 unsigned long long* p = &cand[row * C + c0 + lane];
-                key = *p;
+                key = c0 == 0 ? first : *p;
                 if (key != kEmptyCand) *p = kEmptyCand;
             }
             if (!ballot(key != kEmptyCand)) continue;
             const uint32_t sid = key_idx(key);
             bool dup = sid == (uint32_t)row;
-            for (int r = 0; r < K; ++r) dup |= bcast_u32(lid, r) == sid;
+#pragma unroll
+            for (int r = 0; r < 32; r += 4) {
+                const uint4 x = *(const uint4*)&slid[wv][r];
+                dup = dup || (r + 0 < K && x.x == sid) || (r + 1 < K && x.y == sid) ||
+                      (r + 2 < K && x.z == sid) || (r + 3 < K && x.w == sid);
+            }
             const bool keep = key != kEmptyCand && !dup;
             const uint64_t km = ballot(keep);
             if (keep) sbuf[nc + rank_below(km)] = key;
             nc += popc64(km);
         }
-        if (nc == 0) continue;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        uint64_t cur = lane < K ? okey : kEmptyCand;
-        const int per = 64 - K;
-        for (int b0 = 0; b0 < nc; b0 += per) {
-            uint64_t x = cur;
-            if (lane >= K && b0 + lane - K < nc) x = sbuf[b0 + lane - K];
-            x = seg_sort<64>(x);
-            cur = lane < K ? x : kEmptyCand;
-        }
-        bool from_list = false;
-        uint32_t sfl = 1;
-        for (int r = 0; r < K; ++r) {
-            const uint64_t ok = bcast_u64(okey, r);
-            const uint32_t of = bcast_u32(fl, r);
-            if (ok == cur) {
-                from_list = true;
-                sfl = of;
+        if (nc > 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            uint64_t cur = lane < K ? okey : kEmptyCand;
+            const int per = 64 - K;
+            for (int b0 = 0; b0 < nc; b0 += per) {
+                uint64_t x = cur;
+                if (lane >= K && b0 + lane - K < nc) x = sbuf[b0 + lane - K];
+                x = seg_sort<64>(x);
+                cur = lane < K ? x : kEmptyCand;
             }
-        }
-        const bool sv = key_valid(cur) && key_d2(cur) < __builtin_inff();
-        upd += (unsigned long long)popc64(ballot(lane < K && sv && !from_list));
-        if (lane < K) {
-            gidx[row * K + lane] = sv ? (int32_t)key_idx(cur) : -1;
-            gd2[row * K + lane] = sv ? key_d2(cur) : __builtin_inff();
-            gflag[row * K + lane] = sv ? (uint8_t)sfl : 0;
-            if (lane == K - 1) worst[row * wstride] = sv ? key_d2(cur) : __builtin_inff();
+            const uint32_t w = key_idx(cur);
+            const uint32_t cid = w & ~kWasOld;
+            const bool sv = key_valid(cur) && key_d2(cur) < __builtin_inff();
+            bool from_list = false;
+#pragma unroll
+            for (int r = 0; r < 32; r += 4) {
+                const uint4 x = *(const uint4*)&slid[wv][r];
+                from_list = from_list || (r + 0 < K && x.x == cid) || (r + 1 < K && x.y == cid) ||
+                            (r + 2 < K && x.z == cid) || (r + 3 < K && x.w == cid);
+            }
+            upd += (unsigned long long)popc64(ballot(lane < K && sv && !from_list));
+            if (lane < K) {
+                gidx[row * K + lane] = sv ? (int32_t)cid : -1;
+                gd2[row * K + lane] = sv ? key_d2(cur) : __builtin_inff();
+                gflag[row * K + lane] = sv ? (uint8_t)((w & kWasOld) ? 0 : 1) : 0;
+                if (lane == K - 1) worst[row * wstride] = sv ? key_d2(cur) : __builtin_inff();
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
@@ -662,9 +730,8 @@ __global__ __launch_bounds__(256) void nnd_finalize_kernel(
 
 // ------------------------------------------------------------------ host
 
-knn_status encoder_seed(const knn_encoder* enc, const knn_matrix& X, int K, int P, int D, int w,
-                        uint64_t seed, Workspace& ws, int32_t** seed_idx, float** seed_d2,
-                        hipStream_t st);
+knn_status encoder_seed(const knn_encoder* enc, const knn_matrix& X, const knn_matrix& Xd, int K, int P, int D,
+                        int w, uint64_t seed, Workspace& ws, int32_t** seed_idx, float** seed_d2, hipStream_t st);
 
 int encoder_dim(const knn_encoder* enc);
 
@@ -799,7 +866,9 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         const int P = p->proj_count > 0 ? p->proj_count : 4;
         const int w = p->proj_window > 0 ? p->proj_window : 8;
         const int D = p->proj_dims > 0 ? p->proj_dims : 8;
-        r = encoder_seed(p->encoder, Xp, K, P, D, w, p->seed, ws, &si, &sd, st);
+        // seed distances in the form's precision (the BF16 copy's values)
+        const knn_matrix Xd = bf ? knn_matrix{Xb, X.n, X.d, ldb, KNN_BF16} : Xp;
+        r = encoder_seed(p->encoder, Xp, Xd, K, P, D, w, p->seed, ws, &si, &sd, st);
         if (r != KNN_OK) return r;
         seed_idx = si;
         seed_d2 = sd;
@@ -820,12 +889,8 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     (void)hipEventRecord(t_init.b, st);
 
     // ---- iterations
-    unsigned long long* host_cnt = nullptr;
-    KNN_HIP(hipHostMalloc((void**)&host_cnt, 32, hipHostMallocDefault));
-    struct HostFree {
-        void* p;
-        ~HostFree() { (void)hipHostFree(p); }
-    } hf{host_cnt};
+    unsigned long long* host_cnt = pinned_counters();
+    if (!host_cnt) return fail(KNN_EDEVICE, "pinned host allocation failed");
     const double stop = (double)p->delta * (double)n * (double)K;
     const size_t merge_lds = (size_t)4 * cfg.C * 8;
     int dev = 0;
@@ -838,7 +903,9 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     if (jpc < 1) jpc = 1;
     // a multiple of 8: the join splits its grid into 8 contiguous point ranges
     const unsigned join_grid = (unsigned)round_up((int64_t)ncu * jpc, 8);
-    const unsigned merge_grid = (unsigned)std::min<int64_t>(ceil_div(n, 4), (int64_t)ncu * 8);
+    // multiples of 8: sample and merge split their grids into 8 contiguous row ranges
+    const unsigned merge_grid = (unsigned)round_up(std::min<int64_t>(ceil_div(n, 4), (int64_t)ncu * 8), 8);
+    const unsigned sample_grid = (unsigned)round_up(std::min<int64_t>(ceil_div(n, 8), (int64_t)ncu * 8), 8);
     int iters = 0;
     double ms_sample = 0, ms_join = 0, ms_merge = 0;
     uint64_t gathered = 0;
@@ -847,8 +914,8 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         const int iter = iter_offset + it;
         KNN_HIP(hipMemsetAsync(counters, 0, 32, st));
         (void)hipEventRecord(ts.a, st);
-        nnd_sample_kernel<<<(unsigned)ceil_div(n, 8), 256, 0, st>>>(n, K, s, cfg.R, gidx, gflag, newf, oldf,
-                                                                  revnew, revold, p->seed, iter);
+        nnd_sample_kernel<<<sample_grid, 256, 0, st>>>(n, K, s, cfg.R, gidx, gflag, newf, oldf, revnew, revold,
+                                                       p->seed, iter);
         KNN_HIP(hipGetLastError());
         (void)hipEventRecord(ts.b, st);
         (void)hipEventRecord(tj.a, st);

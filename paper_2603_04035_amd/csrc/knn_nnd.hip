@@ -360,12 +360,12 @@ __device__ inline void sel_insert(uint32_t (&best)[kJMax], uint32_t key)
     }
 }
 
-// Offer member `me` its kept partners q < J with q = par (mod 2) that beat
-// its current worst distance: atomicMin of the (distance, partner id) key
-// into slot hash(partner, iteration) of me's candidate row.  Slots only
-// decrease during a launch, so a plain read that already shows a key at most
-// as large makes the atomic a no-op and it is skipped.
-__device__ inline unsigned long long emit_best(const uint32_t (&best)[kJMax], int J, int par, float cut,
+// Offer member `me` its kept partners q < J whose bit is set in qmask and
+// that beat its current worst distance: atomicMin of the (distance, partner
+// id) key into slot hash(partner, iteration) of me's candidate row.  Slots
+// only decrease during a launch, so a plain read that already shows a key at
+// most as large makes the atomic a no-op and it is skipped.
+__device__ inline unsigned long long emit_best(const uint32_t (&best)[kJMax], int J, unsigned qmask, float cut,
                                                const uint32_t* ids, uint32_t me, int C, uint64_t salt,
                                                unsigned long long* __restrict__ cand)
 {
@@ -373,7 +373,7 @@ __device__ inline unsigned long long emit_best(const uint32_t (&best)[kJMax], in
 #pragma unroll
     for (int q = 0; q < kJMax; ++q) {
         const uint32_t b = best[q];
-        if (q < J && (q & 1) == par && b != kNoSel && __uint_as_float(b & ~63u) < cut) {
+        if (q < J && ((qmask >> q) & 1u) && b != kNoSel && __uint_as_float(b & ~63u) < cut) {
             const uint32_t src = ids[b & 63u];
             const uint64_t key = ((uint64_t)(b & ~63u) << 32) | src;
             const uint32_t slot = bounded(mix64(((uint64_t)src << 20) ^ salt), (uint32_t)C);
@@ -387,19 +387,18 @@ __device__ inline unsigned long long emit_best(const uint32_t (&best)[kJMax], in
     return emitted;
 }
 
-// Local join.  One wave per point v; the grid is split into 8 groups
-// (blockIdx mod 8, the round-robin XCD assignment of workgroups) that each
-// sweep one contiguous range of the processing order, so concurrently joined
-// points are Z-order neighbours sharing an L2.
+// Local join, BF16 form.  One wave per point v; the grid is split into 8
+// groups (blockIdx mod 8, the round-robin XCD assignment of workgroups) that
+// each sweep one contiguous range of the processing order, so concurrently
+// joined points are Z-order neighbours sharing an L2.
 //
 // The join list (new members first, then old; L <= 64) is two 32-row
-// blocks.  Its L x L Gram is accumulated by 32 x 32 MFMA tiles whose
-// operands come straight from the staged rows into registers, no LDS copy:
-// lane (h, c) holds 16-byte pieces of rows c and 32 + c.  Piece p covers
-// bytes [32p + 16h, +16) of a row -- BF16 elements [16p + 8h, +8), one
-// 32x32x16 MFMA, or FP32 elements [8p + 4h, +4), four 32x32x2 MFMAs.  That
-// assigns the reduction index to (step, half) one-to-one, which is all a
-// Gram product needs since both operands use the same assignment.
+// blocks.  Its L x L Gram is accumulated by 32 x 32 x 16 BF16 MFMA tiles
+// (FP32 accumulation) whose operands come straight from the staged rows into
+// registers, no LDS copy: lane (h, c) holds 16-byte pieces of rows c and
+// 32 + c; piece p holds elements [16p + 8h, +8).  That assigns the reduction
+// index to (step, half) one-to-one, which is all a Gram product needs since
+// both operands use the same assignment.
 //
 // Column block cb (members 32cb + c) is finished before the next starts, so
 // two accumulator tiles are live.  Member m pairs with every row if it is
@@ -414,18 +413,10 @@ constexpr int kPC = 4;   // pieces per lane per row held in registers at a time
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-template <bool BF>
 __device__ inline f32x16 gram_step(const uint4& a, const uint4& b, f32x16 acc)
 {
-    if constexpr (BF) {
-        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
-                                                        __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
-    } else {
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), acc, 0, 0, 0);
-        return __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(b.w), acc, 0, 0, 0);
-    }
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                    acc, 0, 0, 0);
 }
 
 // Piece p of a row (r = row base + 16h bytes), branch-free: the load always
@@ -466,8 +457,7 @@ __device__ inline void scan_block(const f32x16& g, int blk, int h4, int m, int l
     }
 }
 
-template <bool BF>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nnd_join_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nnd_join_bf16_kernel(
     int64_t n, JoinCfg cfg, const uint8_t* __restrict__ Xr, int64_t rowbytes, int np,
     const int32_t* __restrict__ newf, unsigned long long* __restrict__ revnew,
     const int32_t* __restrict__ oldf, unsigned long long* __restrict__ revold,
@@ -532,8 +522,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
                 for (int q = 0; q < kPC; ++q) {
                     if (q < pc) {
                         const uint4 b = cb == 0 ? A0[q] : A1[q];
-                        at = gram_step<BF>(A0[q], b, at);
-                        if (two) ab = gram_step<BF>(A1[q], b, ab);
+                        at = gram_step(A0[q], b, at);
+                        if (two) ab = gram_step(A1[q], b, ab);
                     }
                 }
             }
@@ -554,7 +544,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
             for (int q = 0; q < kJMax; ++q) recv[q] = xor_u32(best[q], 32);
 #pragma unroll
             for (int q = 0; q < kJMax; ++q) sel_insert(best, recv[q]);
-            if (m < L) emitted += emit_best(best, J, h, thr[m], ids, ids[m], cfg.C, salt, cand);
+            if (m < L) emitted += emit_best(best, J, h ? 0xAu : 0x5u, thr[m], ids, ids[m], cfg.C, salt, cand);
         }
     }
     for (int o = 32; o > 0; o >>= 1) emitted += shfl_u64(emitted, lane ^ o);
@@ -563,6 +553,144 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
         atomicAdd(&counters[2], gathered);
     }
 }
+// Local join, FP32 form (VALU).  Lists, traversal and offers as in the BF16
+// kernel.  The rows are staged in LDS in chunks of kFC coordinates (zero
+// past d and for absent rows).  Lane (ag, bg) = (lane / 8, lane % 8) holds
+// the Gram entries of rows a = ag + 8i and columns b = bg + 8q (i, q < NB;
+// NB = 4 when L <= 32, else 8), accumulated with FP32 FMAs from two
+// coordinates per LDS read; row strides of kFS floats put the 8 distinct
+// rows of a read in distinct banks.  For each column b the lane keeps the
+// best J of its NB rows, a butterfly over the 8 lanes of the column (lane
+// bits 3..5) merges them, and lane ag offers entry ag of the merged list.
+constexpr int kFC = 32;        // coordinates per staged chunk
+constexpr int kFS = kFC + 2;   // LDS row stride (floats)
+
+template <int NB>
+__device__ inline void join_f32_point(const float* __restrict__ Xs, int ldp, int d, float* rows,
+                                      const uint32_t* ids, const float* nrm, const float* thr, int L, int nn,
+                                      int J, int C, uint64_t salt, unsigned long long* __restrict__ cand,
+                                      unsigned long long& emitted)
+{
+    int ln = threadIdx.x;
+    asm volatile("" : "+v"(ln));   // lane-dependent indices re-derived per point
+    const int ag = ln >> 3, bg = ln & 7;
+    float acc[NB][NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) acc[i][q] = 0.0f;
+    const int dk = (d + 1) & ~1;
+    for (int c0 = 0; c0 < dk; c0 += kFC) {
+        __syncthreads();
+        // stage 8 * NB rows x kFC coordinates: lane -> row ag + 8j, coordinates 4 bg .. 4 bg + 3
+#pragma unroll 2
+        for (int j = 0; j < NB; ++j) {
+            const int r = ag + 8 * j;
+            const int t = c0 + 4 * bg;
+            f32x4 x = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (r < L && t < d) {
+                x = *(const f32x4*)(Xs + (int64_t)ids[r] * ldp + t);
+                if (t + 1 >= d) x[1] = 0.0f;
+                if (t + 2 >= d) x[2] = 0.0f;
+                if (t + 3 >= d) x[3] = 0.0f;
+            }
+            float* dst = rows + r * kFS + 4 * bg;
+            *(float2*)dst = make_float2(x[0], x[1]);
+            *(float2*)(dst + 2) = make_float2(x[2], x[3]);
+        }
+        __syncthreads();
+        const int kc = min(kFC, dk - c0);
+        for (int t = 0; t < kc; t += 2) {
+            float2 xa[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) xa[i] = *(const float2*)(rows + (ag + 8 * i) * kFS + t);
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const float2 xb = *(const float2*)(rows + (bg + 8 * q) * kFS + t);
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    acc[i][q] = fmaf(xa[i].x, xb.x, acc[i][q]);
+                    acc[i][q] = fmaf(xa[i].y, xb.y, acc[i][q]);
+                }
+            }
+        }
+    }
+    float na[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) na[i] = nrm[ag + 8 * i];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int b = bg + 8 * q;
+        const float nb = nrm[b];
+        const int lim = b < nn ? L : nn;
+        uint32_t best[kJMax];
+#pragma unroll
+        for (int s = 0; s < kJMax; ++s) best[s] = kNoSel;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int a = ag + 8 * i;
+            float d2 = na[i] + nb - 2.0f * acc[i][q];
+            d2 = d2 > 0.0f ? d2 : 0.0f;
+            const bool ok = a < lim && a != b;
+            sel_insert(best, ok ? ((__float_as_uint(d2) & ~63u) | (uint32_t)a) : kNoSel);
+        }
+#pragma unroll
+        for (int o = 8; o <= 32; o <<= 1) {
+            uint32_t recv[kJMax];
+#pragma unroll
+            for (int s = 0; s < kJMax; ++s) recv[s] = xor_u32(best[s], o);
+#pragma unroll
+            for (int s = 0; s < kJMax; ++s) sel_insert(best, recv[s]);
+        }
+        if (b < L && ag < kJMax) emitted += emit_best(best, J, 1u << ag, thr[b], ids, ids[b], C, salt, cand);
+    }
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nnd_join_f32_kernel(
+    int64_t n, JoinCfg cfg, const float* __restrict__ Xs, int ldp, int d,
+    const int32_t* __restrict__ newf, unsigned long long* __restrict__ revnew,
+    const int32_t* __restrict__ oldf, unsigned long long* __restrict__ revold,
+    unsigned long long* __restrict__ cand, uint64_t seed, int iter, unsigned long long* __restrict__ counters)
+{
+    __shared__ __attribute__((aligned(16))) float rows[64 * kFS];
+    __shared__ uint32_t ids[64];
+    __shared__ float nrm[64];
+    __shared__ float thr[64];
+    __shared__ __attribute__((aligned(16))) uint32_t sh[128];
+    const int lane = threadIdx.x;
+    unsigned long long emitted = 0, gathered = 0;
+    const uint64_t salt = (uint64_t)iter ^ seed;
+    const unsigned grp = blockIdx.x & 7u;
+    const int64_t gsz = (int64_t)(gridDim.x >> 3);
+    const int64_t lo = n * grp / 8, hi = n * (grp + 1) / 8;
+
+    int64_t v = lo + (int64_t)(blockIdx.x >> 3);
+    ListRaw cur = load_lists(v, v < hi, cfg, newf, revnew, oldf, revold);
+    for (; v < hi; v += gsz) {
+        int L = 0;
+        const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cur, cfg, revnew, revold, sh, ids, L));
+        L = __builtin_amdgcn_readfirstlane(L);
+        cur = load_lists(v + gsz, v + gsz < hi, cfg, newf, revnew, oldf, revold);
+        __syncthreads();
+        if (nn == 0 || L < 2) continue;
+        if (lane < L) {
+            const float2 a = *(const float2*)(Xs + (int64_t)ids[lane] * ldp + ldp - 2);
+            nrm[lane] = a.x;
+            thr[lane] = a.y;
+        } else {
+            nrm[lane] = 0.0f;
+        }
+        gathered += (unsigned long long)L;
+        if (L <= 32) join_f32_point<4>(Xs, ldp, d, rows, ids, nrm, thr, L, nn, cfg.J, cfg.C, salt, cand, emitted);
+        else join_f32_point<8>(Xs, ldp, d, rows, ids, nrm, thr, L, nn, cfg.J, cfg.C, salt, cand, emitted);
+    }
+    for (int o = 32; o > 0; o >>= 1) emitted += shfl_u64(emitted, lane ^ o);
+    if (lane == 0) {
+        atomicAdd(&counters[1], emitted);
+        atomicAdd(&counters[2], gathered);
+    }
+}
+
 // ------------------------------------------------------------------ merge
 
 // One wave per row, rows taken from 8 contiguous ranges (blockIdx mod 8, as
@@ -899,7 +1027,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     int jpc = 0;
     KNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &jpc, bf ? (const void*)nnd_join_kernel<true> : (const void*)nnd_join_kernel<false>, 64, 0));
+        &jpc, bf ? (const void*)nnd_join_bf16_kernel : (const void*)nnd_join_f32_kernel, 64, 0));
     if (jpc < 1) jpc = 1;
     // a multiple of 8: the join splits its grid into 8 contiguous point ranges
     const unsigned join_grid = (unsigned)round_up((int64_t)ncu * jpc, 8);
@@ -920,11 +1048,11 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         (void)hipEventRecord(ts.b, st);
         (void)hipEventRecord(tj.a, st);
         if (bf)
-            nnd_join_kernel<true><<<join_grid, 64, 0, st>>>(n, cfg, Xr, rowbytes, np, newf, revnew, oldf,
-                                                            revold, cand, p->seed, iter, counters);
+            nnd_join_bf16_kernel<<<join_grid, 64, 0, st>>>(n, cfg, Xr, rowbytes, np, newf, revnew, oldf, revold,
+                                                           cand, p->seed, iter, counters);
         else
-            nnd_join_kernel<false><<<join_grid, 64, 0, st>>>(n, cfg, Xr, rowbytes, np, newf, revnew, oldf,
-                                                             revold, cand, p->seed, iter, counters);
+            nnd_join_f32_kernel<<<join_grid, 64, 0, st>>>(n, cfg, (const float*)Xs, ldp, X.d, newf, revnew, oldf,
+                                                          revold, cand, p->seed, iter, counters);
         KNN_HIP(hipGetLastError());
         (void)hipEventRecord(tj.b, st);
         (void)hipEventRecord(tm.a, st);

@@ -42,15 +42,20 @@ TRAIN = dict(n=100_000, seed=100, k=15, steps=1000, batch=4096, lr=2e-3)
 CONFIGS = {
     "gmm1m": dict(n=1_000_000, d=50, desc="1,000,000 x 50 FP32, 50-component anisotropic GMM, k=15"),
     "pixel70k": dict(n=70_000, d=784, desc="70,000 x 784 FP32 pixel-like (10 clusters, 1/255 levels), k=15"),
+    "scale10m": dict(n=10_000_000, d=50,
+                     desc="10,000,000 x 50 FP16, 200-component anisotropic GMM, Zipf(1.1) weights, k=15"),
 }
 
 
 def make_data(config: str, seed: int = 0, n=None):
+    import numpy as np
     from paper_2603_04035_amd import datagen
     c = CONFIGS[config]
     n = c["n"] if n is None else n
     if config == "gmm1m":
         return datagen.gmm_anisotropic(n=n, d=c["d"], comps=50, seed=seed)
+    if config == "scale10m":
+        return datagen.gmm_anisotropic(n=n, d=c["d"], comps=200, zipf=1.1, seed=seed, dtype=np.float16)
     return datagen.pixel_like(n=n, seed=seed)
 
 
@@ -145,7 +150,26 @@ def join_roofline(stats, n, d, p, kernel):
             "ms_per_launch": round(join_ms / max(launches, 1), 4)}
 
 
-def run_form(X, k, form, steps, warmup, rows, encoder=None):
+def distance_error(X, Xnp, k, p, rows):
+    """Relative error of the BF16 form's working-list squared distances (BF16
+    MFMA join, norm expansion, FP32 accumulation) against FP64 distances of
+    the input values, over every listed pair of the sampled rows."""
+    import numpy as np
+    import paper_2603_04035_amd as knn
+    _, _, _, (si, sd, _) = knn.nndescent_build(X, k, seed=0, return_state=True, **p)
+    si, sd = si.cpu().numpy()[rows], sd.cpu().numpy()[rows].astype(np.float64)
+    ok = si >= 0
+    a = np.repeat(rows, si.shape[1]).reshape(si.shape)[ok]
+    b = si[ok]
+    X64 = Xnp.astype(np.float64)
+    true = ((X64[a] - X64[b]) ** 2).sum(axis=1)
+    m = true > 0
+    e = np.abs(sd[ok][m] - true[m]) / true[m]
+    return {"pairs": int(m.sum()), "rel_max": float(e.max()), "rel_p50": float(np.percentile(e, 50)),
+            "rel_p99": float(np.percentile(e, 99))}
+
+
+def run_form(X, k, form, steps, warmup, rows, encoder=None, Xnp=None):
     import torch
     import paper_2603_04035_amd as knn
     p = dict(FORMS[form])
@@ -167,7 +191,11 @@ def run_form(X, k, form, steps, warmup, rows, encoder=None):
     last = stats[-1]
     cfg = {kk: vv for kk, vv in p.items() if kk != "encoder"}
     cfg["build_k"] = last["build_k"]
+    err = None
+    if p["precision"] == "bf16" and Xnp is not None:
+        err = distance_error(X, Xnp, k, p, rows[:2000])
     return {"value": round(n * steps / wall, 1), "ms_per_step": round(1000.0 * wall / steps, 3),
+            "bf16_distance_error_vs_fp64": err,
             "recall_at_15": round(recall, 5), "recall_ok": recall >= 0.98, "iters": last["iters"],
             "params": cfg,
             "ms_breakdown": {kk: round(last[kk], 3) for kk in
@@ -224,7 +252,7 @@ def main():
     if "bf16-learned" in forms:
         encoder, training = train_encoder(args.config)
     for f in forms:
-        results[f] = run_form(X, k, f, args.steps, args.warmup, rows, encoder)
+        results[f] = run_form(X, k, f, args.steps, args.warmup, rows, encoder, Xnp)
     head = "bf16-learned" if "bf16-learned" in results else forms[0]
     h = results[head]
 

@@ -7,12 +7,21 @@ Gaussian mixture with anisotropic covariances (eigenvalues log-uniform on
 already resident in HBM (init, every iteration, final re-rank).  Steps use
 algorithm seeds 0..steps-1 after `warmup` untimed calls.
 
-Reported: points/s = n * steps / wall time of the timed steps, recall@15 of
-the last step's graph on 10,000 sampled rows against the GPU exact path
-(knn_exact_query, parity-tested against the CPU oracle), the roofline of the
-dominant kernel (the local join: algorithmic bytes / its HIP-event time,
-both accumulated by the library over the timed steps), and the CPU oracle's
-sequential NNDescent on a bounded sample of the same workload.
+Two forms are timed: plain FP32 NNDescent (random init, VALU join) and the
+BF16 form seeded by a trained encoder (BF16 MFMA join, FP32 re-rank of the
+final lists); the headline line is the latter, both are in "forms".
+
+Reported: points/s = n * steps / wall time of the timed steps (and the
+spread of the per-step times), recall@15 of the last step's graph on 10,000
+sampled rows against the GPU exact path (knn_exact_query, parity-tested
+against the CPU oracle), the roofline of the dominant kernel (the local
+join: algorithmic bytes / its HIP-event time, both accumulated by the
+library over the timed steps; counter-measured HBM bytes per launch from the
+committed rocprofv3 summary while its kernel source is unchanged), an
+attainable-bandwidth copy measurement, the BF16 form's join distance error
+against FP64, the encoder's training cost (outside the timed region), and
+the CPU oracle's sequential NNDescent on a bounded sample of the workload.
+Other configurations (--config pixel70k | scale10m) print the same line.
 """
 from __future__ import annotations
 
@@ -35,6 +44,12 @@ FORMS = {
                  join_cap=4, cand_slots=64),
     "bf16-learned": dict(precision="bf16", build_k=32, sample_rate=1.0, max_iters=30, delta=0.015,
                          join_cap=4, cand_slots=64, init_kind="encoder", proj_count=4, proj_window=8),
+    # controls for the encoder's benefit (--form all): same BF16 form, random
+    # init, and seeding through an untrained encoder of the same shape
+    "bf16-random": dict(precision="bf16", build_k=32, sample_rate=1.0, max_iters=30, delta=0.015,
+                        join_cap=4, cand_slots=64),
+    "bf16-untrained": dict(precision="bf16", build_k=32, sample_rate=1.0, max_iters=30, delta=0.015,
+                           join_cap=4, cand_slots=64, init_kind="encoder", proj_count=4, proj_window=8),
 }
 # encoder training (reported separately, not in the timed region)
 TRAIN = dict(n=100_000, seed=100, k=15, steps=1000, batch=4096, lr=2e-3)
@@ -129,6 +144,25 @@ def measured_traffic(kernel):
     return None, None
 
 
+def copy_bandwidth(mib: int = 1024, reps: int = 5):
+    """Attainable HBM bandwidth of a plain device-to-device copy (read + write
+    bytes / event time), the measured counterpart of the 8 TB/s peak."""
+    import torch
+    nbytes = mib << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
+
+
 def join_roofline(stats, n, d, p, kernel):
     """Local-join roofline: algorithmic bytes per launch / HIP-event time per launch."""
     import numpy as np
@@ -173,15 +207,19 @@ def run_form(X, k, form, steps, warmup, rows, encoder=None, Xnp=None):
     import torch
     import paper_2603_04035_amd as knn
     p = dict(FORMS[form])
+    if form == "bf16-untrained":
+        encoder = knn.Encoder(X.shape[1], seed=1)
     if p.get("init_kind") == "encoder":
         p["encoder"] = encoder
     for w in range(warmup):
         knn.nndescent_build(X, k, seed=1000 + w, **p)
     torch.cuda.synchronize()
-    stats = []
+    stats, walls = [], []
     t0 = time.perf_counter()
     for s in range(steps):
-        G, D, st = knn.nndescent_build(X, k, seed=s, **p)
+        ts = time.perf_counter()
+        G, D, st = knn.nndescent_build(X, k, seed=s, **p)   # blocking: returns after the build
+        walls.append(time.perf_counter() - ts)
         stats.append(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -194,7 +232,9 @@ def run_form(X, k, form, steps, warmup, rows, encoder=None, Xnp=None):
     err = None
     if p["precision"] == "bf16" and Xnp is not None:
         err = distance_error(X, Xnp, k, p, rows[:2000])
+    import numpy as np
     return {"value": round(n * steps / wall, 1), "ms_per_step": round(1000.0 * wall / steps, 3),
+            "ms_per_step_std": round(1000.0 * float(np.std(walls)), 3),
             "bf16_distance_error_vs_fp64": err,
             "recall_at_15": round(recall, 5), "recall_ok": recall >= 0.98, "iters": last["iters"],
             "params": cfg,
@@ -211,7 +251,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="gmm1m", choices=sorted(CONFIGS))
-    ap.add_argument("--form", default="both", choices=sorted(FORMS) + ["both"])
+    ap.add_argument("--form", default="both", choices=sorted(FORMS) + ["both", "all"],
+                    help="both: fp32 and bf16-learned; all: also the bf16-random and bf16-untrained controls")
     ap.add_argument("--k", type=int, default=15)
     ap.add_argument("--recall-rows", type=int, default=10000)
     ap.add_argument("--cpu-sample", type=int, default=100_000)
@@ -246,7 +287,8 @@ def main():
     X = torch.from_numpy(Xnp).to("cuda")
     torch.cuda.synchronize()
     rows = datagen.sample_queries(n, args.recall_rows, seed=2)
-    forms = ["fp32", "bf16-learned"] if args.form == "both" else [args.form]
+    forms = {"both": ["fp32", "bf16-learned"], "all": ["fp32", "bf16-learned", "bf16-random", "bf16-untrained"]}.get(
+        args.form, [args.form])
     results, training = {}, None
     encoder = None
     if "bf16-learned" in forms:
@@ -256,6 +298,9 @@ def main():
     head = "bf16-learned" if "bf16-learned" in results else forms[0]
     h = results[head]
 
+    copy_gbs = copy_bandwidth()
+    for r in results.values():
+        r["roofline"]["frac_of_measured_copy"] = round(r["roofline"]["achieved"] / copy_gbs, 4)
     cpu = None
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         cpu = cpu_baseline(Xnp, k, "fp32", min(args.cpu_sample, n))
@@ -263,12 +308,13 @@ def main():
     out = {
         "metric": "kNN graph build points/sec at recall@15>=0.98 (NNDescent)",
         "value": h["value"], "unit": "points/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": h["ms_per_step"], "higher_is_better": True,
+        "warmup": args.warmup, "ms_per_step": h["ms_per_step"], "ms_per_step_std": h["ms_per_step_std"],
+        "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16" if FORMS[head]["precision"] == "bf16" else "f32", "data": "synthetic",
         "config": {"workload": CONFIGS[args.config]["desc"], "form": head, "k": k},
         "recall_at_15": h["recall_at_15"], "recall_ok": h["recall_ok"],
-        "roofline": h["roofline"],
+        "roofline": h["roofline"], "hbm_copy_gbs": copy_gbs,
         "cpu_baseline": cpu,
         "forms": results,
         "encoder_training": training,

@@ -118,7 +118,7 @@ typedef struct {
     int32_t proj_count;   /* encoder init: number of sorted orders P (0: 4) */
     int32_t proj_window;  /* encoder init: neighbours taken on each side per order (0: 8) */
     int32_t proj_dims;    /* encoder init: projections per order key D in {1,2,4,8} (0: 8) */
-    int32_t cand_slots;   /* hashed candidate slots per row and iteration, <= 64 - K_b (0: 32) */
+    int32_t cand_slots;   /* hashed candidate slots per row and iteration, <= 256 (0: 64) */
     int32_t join_cap;     /* max candidates one join list sends to one member, <= 4 (0: 4) */
     int64_t workspace_limit_bytes; /* 0: no limit; else KNN_ENOMEM when scratch exceeds it */
 } knn_nnd_params;
@@ -147,7 +147,10 @@ typedef struct {
  *  stats  host, nullable.
  * Errors: KNN_EINVAL for bad sizes/params (k, K_b, rho, delta, max_iters,
  * null pointers, encoder missing for KNN_INIT_ENCODER or of another d);
- * KNN_ENOTSUP if K_b > KNN_MAX_K; KNN_ENOMEM as above.
+ * KNN_ENOTSUP if K_b > KNN_MAX_K or cand_slots > 256; KNN_ENOMEM as above.
+ * Scratch (about n * (K_b * 9 + (2 R + C) * 8 + s * 4) bytes plus staged
+ * copies of X) comes from a per-device arena the library keeps between
+ * calls; calls on one device take turns on it.
  */
 knn_status nndescent_build(knn_matrix X, const knn_nnd_params* p,
                            int32_t* out_idx, float* out_dist,

@@ -52,7 +52,7 @@ FORMS = {
                            join_cap=4, cand_slots=64, init_kind="encoder", proj_count=4, proj_window=8),
 }
 # encoder training (reported separately, not in the timed region)
-TRAIN = dict(n=100_000, seed=100, k=15, steps=1000, batch=4096, lr=2e-3)
+TRAIN = dict(n=100_000, seed=100, k=15, steps=1000, batch=4096, lr=2e-3, precision="bf16")
 
 CONFIGS = {
     "gmm1m": dict(n=1_000_000, d=50, desc="1,000,000 x 50 FP32, 50-component anisotropic GMM, k=15"),
@@ -85,11 +85,13 @@ def train_encoder(config: str):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     enc = knn.Encoder(Xt.shape[1], seed=1)
-    log = enc.train(Xt, idx, steps=TRAIN["steps"], batch=TRAIN["batch"], lr=TRAIN["lr"], seed=3)
+    log = enc.train(Xt, idx, steps=TRAIN["steps"], batch=TRAIN["batch"], lr=TRAIN["lr"], seed=3,
+                    precision=TRAIN["precision"])
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     return enc, {"train_points": TRAIN["n"], "exact_graph_s": round(t1 - t0, 3),
                  "train_s": round(t2 - t1, 3), "steps": TRAIN["steps"], "batch": TRAIN["batch"],
+                 "precision": TRAIN["precision"],
                  "loss_first": float(log[:20].mean()), "loss_last": float(log[-20:].mean())}
 
 

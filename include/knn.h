@@ -196,7 +196,9 @@ knn_status knn_encoder_get_weights(const knn_encoder* enc, float* W1, float* b1,
                                    float* W2, float* b2);
 
 /* Z = W2^T relu(W1^T x + b1) + b2 for every row of X; Z: device, n x 32 float.
- * precision KNN_PREC_FP32 (FP32 FMA) or KNN_PREC_BF16 (BF16 MFMA, FP32 accumulate). */
+ * precision KNN_PREC_FP32 (FP32 FMA) or KNN_PREC_BF16 (BF16 MFMA, FP32
+ * accumulate: x, W1, the hidden layer and W2 rounded to BF16; biases FP32).
+ * The NNDescent BF16 form seeds through the BF16 embedding. */
 knn_status knn_encoder_embed(const knn_encoder* enc, knn_matrix X, int32_t precision,
                              float* Z, void* stream);
 
@@ -204,11 +206,15 @@ knn_status knn_encoder_embed(const knn_encoder* enc, knn_matrix X, int32_t preci
  * One triplet-loss forward/backward pass without updating the weights.
  * rows: device, 3B int32 = [anchors; positives; negatives] (rows of X).
  * loss = (1/B) sum max(0, margin + |za-zp|^2 - |za-zn|^2).
+ * precision: KNN_PREC_FP32, or KNN_PREC_BF16: the factors of every product
+ *   (inputs, weights, hidden values, output gradients) are rounded to BF16
+ *   and accumulated in FP32; bias terms and bias gradients stay FP32.
  * grads: device, nullable, d*64 + 64 + 64*32 + 32 floats (gW1, gb1, gW2, gb2).
  * loss_out: host.
  */
 knn_status knn_encoder_grads(knn_encoder* enc, knn_matrix X, const int32_t* rows, int32_t B,
-                             float margin, float* loss_out, float* grads, void* stream);
+                             float margin, int32_t precision, float* loss_out, float* grads,
+                             void* stream);
 
 /* Adam settings for knn_encoder_train. */
 typedef struct {
@@ -216,6 +222,7 @@ typedef struct {
     int32_t batch;        /* triplets per step */
     float lr, beta1, beta2, eps, margin;
     uint64_t seed;        /* triplet sampling */
+    int32_t precision;    /* forward / backward products: KNN_PREC_FP32 or KNN_PREC_BF16 (FP32 weights) */
 } knn_train_params;
 
 void knn_train_default_params(knn_train_params* t);

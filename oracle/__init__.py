@@ -180,6 +180,35 @@ def mlp_forward(X, W1, b1, W2, b2, want_hidden: bool = False):
     return (Z, H) if want_hidden else Z
 
 
+def bf16_values(a) -> np.ndarray:
+    """a rounded FP32 -> BF16 (RNE), as float64 values."""
+    return bf16_to_f64(round_bf16(a))
+
+
+def mlp_forward_bf16(X, W1, b1, W2, b2, want_hidden: bool = False):
+    """The encoder's BF16 mode: every factor of a product is rounded to BF16
+    (x, W1, the post-ReLU hidden values, W2), the sums are exact (FP64) and
+    the biases are not rounded.  Returns Z (and the rounded hidden layer)."""
+    Xr, W1r, W2r = bf16_values(X), bf16_values(W1), bf16_values(W2)
+    b2 = _f64(b2)
+    _, H = mlp_forward(Xr, W1r, b1, W2r, np.zeros_like(b2), want_hidden=True)
+    Hr = bf16_values(H)
+    Z = Hr @ W2r + b2
+    return (Z, Hr) if want_hidden else Z
+
+
+def mlp_backward_bf16(X, W1, b1, W2, dZ):
+    """Gradients of the BF16 mode: dH = round(dZ) round(W2)^T masked by the
+    hidden layer's sign; gW1 = round(X)^T round(dH), gW2 = round(H)^T round(dZ)
+    with H the rounded hidden layer; gb1, gb2 are plain sums of dH, dZ."""
+    Xr, W2r = bf16_values(X), bf16_values(W2)
+    _, Hr = mlp_forward_bf16(X, W1, b1, W2, np.zeros(W2.shape[1]), want_hidden=True)
+    dZ = _f64(dZ)
+    dZr = bf16_values(dZ)
+    dH = (dZr @ W2r.T) * (Hr > 0)
+    return Xr.T @ bf16_values(dH), dH.sum(axis=0), Hr.T @ dZr, dZ.sum(axis=0)
+
+
 def triplet_loss(Z, B: int, margin: float = 1.0, want_grad: bool = True):
     Z = _f64(Z)
     dZ = np.zeros_like(Z) if want_grad else None

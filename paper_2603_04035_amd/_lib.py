@@ -72,7 +72,7 @@ class knn_nnd_stats(C.Structure):
 class knn_train_params(C.Structure):
     _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float),
                 ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
-                ("margin", C.c_float), ("seed", C.c_uint64)]
+                ("margin", C.c_float), ("seed", C.c_uint64), ("precision", C.c_int32)]
 
 
 EXPORTS = [
@@ -122,7 +122,7 @@ def load() -> C.CDLL:
     lib.knn_encoder_embed.restype = i32
     lib.knn_encoder_embed.argtypes = [vp, knn_matrix, i32, vp, vp]
     lib.knn_encoder_grads.restype = i32
-    lib.knn_encoder_grads.argtypes = [vp, knn_matrix, vp, i32, f32, C.POINTER(C.c_float), vp, vp]
+    lib.knn_encoder_grads.argtypes = [vp, knn_matrix, vp, i32, f32, i32, C.POINTER(C.c_float), vp, vp]
     lib.knn_train_default_params.restype = None
     lib.knn_train_default_params.argtypes = [C.POINTER(knn_train_params)]
     lib.knn_encoder_train.restype = i32

@@ -88,6 +88,95 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const void* __restrict
     for (int q = 0; q < H2; ++q) Z[i * H2 + q] = z[q];
 }
 
+// BF16 mode (one wave per 32 rows).  The products of both layers run on
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation: X rows and W1 are rounded
+// to BF16 (RNE) as they are loaded, b1 and ReLU are applied in FP32, the
+// hidden layer is rounded to BF16 and re-laid out through LDS as the first
+// operand of the second product (W2 rounded), and b2 is added in FP32.
+// Operand layouts: lane (h, c) holds row (or column) c, reduction elements
+// [16 kk + 8 h, +8) of step kk; an accumulator holds rows 8 (v / 4) + 4 h +
+// v % 4 of column c.  H (nullable) gets the rounded hidden values.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+__device__ inline float bf16_round(float v) { return __uint_as_float((uint32_t)f32_to_bf16_rne(v) << 16); }
+
+__device__ inline bf16x8_t pack_bf16x8(const float (&v)[8])
+{
+    uint4 u;
+    u.x = (uint32_t)f32_to_bf16_rne(v[0]) | ((uint32_t)f32_to_bf16_rne(v[1]) << 16);
+    u.y = (uint32_t)f32_to_bf16_rne(v[2]) | ((uint32_t)f32_to_bf16_rne(v[3]) << 16);
+    u.z = (uint32_t)f32_to_bf16_rne(v[4]) | ((uint32_t)f32_to_bf16_rne(v[5]) << 16);
+    u.w = (uint32_t)f32_to_bf16_rne(v[6]) | ((uint32_t)f32_to_bf16_rne(v[7]) << 16);
+    return __builtin_bit_cast(bf16x8_t, u);
+}
+
+template <int DT>
+__global__ __launch_bounds__(64) void mlp_forward_bf16_kernel(const void* __restrict__ X, int64_t ld, int d,
+                                                              const int32_t* __restrict__ rows, int64_t m,
+                                                              const float* __restrict__ prm,
+                                                              float* __restrict__ H, float* __restrict__ Z)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t hs[32][H1 + 8];
+    const int lane = threadIdx.x, c = lane & 31, h = lane >> 5;
+    const Off o(d);
+    const int64_t r0 = (int64_t)blockIdx.x * 32;
+    const int64_t i = r0 + c;
+    const bool valid = i < m;
+    const int64_t src = valid ? (rows ? (int64_t)rows[i] : i) : 0;
+    f32x16_t a0, a1;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        a0[v] = 0.0f;
+        a1[v] = 0.0f;
+    }
+    for (int k0 = 0; k0 < d; k0 += 16) {
+        float xv[8], w0[8], w1[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int t = k0 + 8 * h + e;
+            const bool in = t < d;
+            xv[e] = valid && in ? elem<DT>::ld(X, src * ld + t) : 0.0f;
+            w0[e] = in ? prm[o.W1 + t * H1 + c] : 0.0f;
+            w1[e] = in ? prm[o.W1 + t * H1 + 32 + c] : 0.0f;
+        }
+        const bf16x8_t xa = pack_bf16x8(xv);
+        a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa, pack_bf16x8(w0), a0, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa, pack_bf16x8(w1), a1, 0, 0, 0);
+    }
+    const float bj0 = prm[o.b1 + c], bj1 = prm[o.b1 + 32 + c];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int r = 8 * (v >> 2) + 4 * h + (v & 3);
+        const float h0 = bf16_round(fmaxf(a0[v] + bj0, 0.0f));
+        const float h1 = bf16_round(fmaxf(a1[v] + bj1, 0.0f));
+        hs[r][c] = (uint16_t)(__float_as_uint(h0) >> 16);
+        hs[r][32 + c] = (uint16_t)(__float_as_uint(h1) >> 16);
+        if (H && r0 + r < m) {
+            H[(r0 + r) * H1 + c] = h0;
+            H[(r0 + r) * H1 + 32 + c] = h1;
+        }
+    }
+    __syncthreads();
+    f32x16_t az;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) az[v] = 0.0f;
+#pragma unroll
+    for (int kk = 0; kk < H1 / 16; ++kk) {
+        const bf16x8_t ha = __builtin_bit_cast(bf16x8_t, *(const uint4*)&hs[c][16 * kk + 8 * h]);
+        float wv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) wv[e] = prm[o.W2 + (16 * kk + 8 * h + e) * H2 + c];
+        az = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ha, pack_bf16x8(wv), az, 0, 0, 0);
+    }
+    const float bq = prm[o.b2 + c];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int r = 8 * (v >> 2) + 4 * h + (v & 3);
+        if (r0 + r < m) Z[(r0 + r) * H2 + c] = az[v] + bq;
+    }
+}
+
 // ------------------------------------------------------------------- loss
 
 __global__ __launch_bounds__(256) void triplet_sample_kernel(int64_t n, const int32_t* __restrict__ knn_idx,
@@ -154,7 +243,9 @@ __global__ __launch_bounds__(256) void ordered_sum_kernel(const float* __restric
 
 // --------------------------------------------------------------- backward
 
-// dH[i][j] = (sum_q dZ[i][q] W2[j][q]) if H[i][j] > 0 else 0.
+// dH[i][j] = (sum_q dZ[i][q] W2[j][q]) if H[i][j] > 0 else 0.  In the BF16
+// mode (BF) the product operands dZ and W2 are rounded to BF16 first.
+template <bool BF>
 __global__ __launch_bounds__(256) void mlp_dh_kernel(int64_t m, int d, const float* __restrict__ prm,
                                                      const float* __restrict__ H, const float* __restrict__ dZ,
                                                      float* __restrict__ dH)
@@ -164,12 +255,12 @@ __global__ __launch_bounds__(256) void mlp_dh_kernel(int64_t m, int d, const flo
     const Off o(d);
     float dz[H2];
 #pragma unroll
-    for (int q = 0; q < H2; ++q) dz[q] = dZ[i * H2 + q];
+    for (int q = 0; q < H2; ++q) dz[q] = BF ? bf16_round(dZ[i * H2 + q]) : dZ[i * H2 + q];
     for (int j = 0; j < H1; ++j) {
         const float* w = prm + o.W2 + j * H2;
         float a = 0.0f;
 #pragma unroll
-        for (int q = 0; q < H2; ++q) a = fmaf(dz[q], w[q], a);
+        for (int q = 0; q < H2; ++q) a = fmaf(dz[q], BF ? bf16_round(w[q]) : w[q], a);
         dH[i * H1 + j] = H[i * H1 + j] > 0.0f ? a : 0.0f;
     }
 }
@@ -178,8 +269,9 @@ constexpr int kGradChunk = 256;   // batch rows per partial sum
 
 // partial[c][p] = sum over the rows of chunk c (in order) of the product that
 // defines gradient p: gW1[t][j] = x_t dh_j, gb1[j] = dh_j, gW2[j][q] = h_j dz_q,
-// gb2[q] = dz_q.
-template <int DT>
+// gb2[q] = dz_q.  In the BF16 mode (BF) the factors of the weight-gradient
+// products are rounded to BF16 (the bias gradients are plain FP32 sums).
+template <int DT, bool BF>
 __global__ __launch_bounds__(256) void mlp_grad_partial_kernel(const void* __restrict__ X, int64_t ld, int d,
                                                                const int32_t* __restrict__ rows, int64_t m,
                                                                const float* __restrict__ H,
@@ -198,14 +290,17 @@ __global__ __launch_bounds__(256) void mlp_grad_partial_kernel(const void* __res
         const int t = p / H1, j = p % H1;
         for (int64_t i = i0; i < i1; ++i) {
             const int64_t r = rows ? (int64_t)rows[i] : i;
-            a = fmaf(elem<DT>::ld(X, r * ld + t), dH[i * H1 + j], a);
+            const float x = elem<DT>::ld(X, r * ld + t), g = dH[i * H1 + j];
+            a = BF ? fmaf(bf16_round(x), bf16_round(g), a) : fmaf(x, g, a);
         }
     } else if (p < o.W2) {
         const int j = p - o.b1;
         for (int64_t i = i0; i < i1; ++i) a += dH[i * H1 + j];
     } else if (p < o.b2) {
         const int j = (p - o.W2) / H2, q = (p - o.W2) % H2;
-        for (int64_t i = i0; i < i1; ++i) a = fmaf(H[i * H1 + j], dZ[i * H2 + q], a);
+        for (int64_t i = i0; i < i1; ++i)
+            a = BF ? fmaf(bf16_round(H[i * H1 + j]), bf16_round(dZ[i * H2 + q]), a)
+                   : fmaf(H[i * H1 + j], dZ[i * H2 + q], a);
     } else {
         const int q = p - o.b2;
         for (int64_t i = i0; i < i1; ++i) a += dZ[i * H2 + q];
@@ -705,20 +800,28 @@ knn_status morton_order(const knn_matrix& X, int D, uint64_t seed, Workspace& ws
     return KNN_OK;
 }
 
-static knn_status embed_impl(const knn_encoder* enc, const knn_matrix& X, float* Z, hipStream_t st)
+// Forward pass of rows (nullable: 0..m-1) in the given precision.
+static knn_status forward_impl(const knn_encoder* enc, const knn_matrix& X, const int32_t* rows, int64_t m,
+                               int precision, float* H, float* Z, hipStream_t st)
 {
     by_dtype(X.dtype, [&](auto dt) {
-        mlp_forward_kernel<decltype(dt)::value><<<(unsigned)ceil_div(X.n, 256), 256, 0, st>>>(
-            X.data, X.ld, X.d, nullptr, X.n, enc->params, nullptr, Z);
+        if (precision == KNN_PREC_BF16)
+            mlp_forward_bf16_kernel<decltype(dt)::value><<<(unsigned)ceil_div(m, 32), 64, 0, st>>>(
+                X.data, X.ld, X.d, rows, m, enc->params, H, Z);
+        else
+            mlp_forward_kernel<decltype(dt)::value><<<(unsigned)ceil_div(m, 256), 256, 0, st>>>(
+                X.data, X.ld, X.d, rows, m, enc->params, H, Z);
     });
     KNN_HIP(hipGetLastError());
     return KNN_OK;
 }
 
-// Seed lists from the encoder: X is embedded, the seeds' distances are taken
-// on Xd (the same points; the BF16 copy in the BF16 form).
-knn_status encoder_seed(const knn_encoder* enc, const knn_matrix& X, const knn_matrix& Xd, int K, int P, int D,
-                        int w, uint64_t seed, Workspace& ws, int32_t** seed_idx, float** seed_d2, hipStream_t st)
+// Seed lists from the encoder: X is embedded in the given precision, the
+// seeds' distances are taken on Xd (the same points; the BF16 copy in the
+// BF16 form).
+knn_status encoder_seed(const knn_encoder* enc, const knn_matrix& X, const knn_matrix& Xd, int precision, int K,
+                        int P, int D, int w, uint64_t seed, Workspace& ws, int32_t** seed_idx, float** seed_d2,
+                        hipStream_t st)
 {
     if (2 * w * P > 64) return fail(KNN_EINVAL, "2 * proj_window * proj_count must be <= 64");
     if (D < 1 || D > 8 || 32 % D) return fail(KNN_EINVAL, "proj_dims must be 1, 2, 4 or 8");
@@ -730,30 +833,34 @@ knn_status encoder_seed(const knn_encoder* enc, const knn_matrix& X, const knn_m
     if ((r = ws.alloc(seed_d2, (size_t)X.n * K)) != KNN_OK) return r;
     dirs_kernel<<<P * D, 64, 0, st>>>(H2, seed, dirs);
     KNN_HIP(hipGetLastError());
-    if ((r = embed_impl(enc, X, Z, st)) != KNN_OK) return r;
+    if ((r = forward_impl(enc, X, nullptr, X.n, precision, nullptr, Z, st)) != KNN_OK) return r;
     return proj_seed_impl(Xd, Z, H2, dirs, P, D, w, K, *seed_idx, *seed_d2, ws, st);
 }
 
 // Forward + loss + backward of one batch (rows: 3B device ints).  Leaves the
 // loss sum in loss_dev[0] (already divided by B) and the gradient in grad.
 static knn_status batch_grads(const knn_encoder* enc, const knn_matrix& X, const int32_t* rows, int B,
-                              float margin, float* H, float* Z, float* dZ, float* dH, float* lterm,
-                              float* partial, float* grad, float* loss_dev, hipStream_t st)
+                              float margin, int precision, float* H, float* Z, float* dZ, float* dH,
+                              float* lterm, float* partial, float* grad, float* loss_dev, hipStream_t st)
 {
     const int64_t m = 3 * (int64_t)B;
     const Off o(enc->d);
-    by_dtype(X.dtype, [&](auto dt) {
-        mlp_forward_kernel<decltype(dt)::value><<<(unsigned)ceil_div(m, 256), 256, 0, st>>>(
-            X.data, X.ld, X.d, rows, m, enc->params, H, Z);
-    });
+    const bool bf = precision == KNN_PREC_BF16;
+    knn_status r = forward_impl(enc, X, rows, m, precision, H, Z, st);
+    if (r != KNN_OK) return r;
     triplet_loss_kernel<<<(unsigned)ceil_div(B, 256), 256, 0, st>>>(Z, B, margin, dZ, lterm);
     ordered_sum_kernel<<<1, 256, 0, st>>>(lterm, B, 1.0f / (float)B, loss_dev);
-    mlp_dh_kernel<<<(unsigned)ceil_div(m, 256), 256, 0, st>>>(m, enc->d, enc->params, H, dZ, dH);
+    if (bf) mlp_dh_kernel<true><<<(unsigned)ceil_div(m, 256), 256, 0, st>>>(m, enc->d, enc->params, H, dZ, dH);
+    else mlp_dh_kernel<false><<<(unsigned)ceil_div(m, 256), 256, 0, st>>>(m, enc->d, enc->params, H, dZ, dH);
     const int nch = (int)ceil_div(m, kGradChunk);
     dim3 g((unsigned)nch, (unsigned)ceil_div(o.P, 256));
     by_dtype(X.dtype, [&](auto dt) {
-        mlp_grad_partial_kernel<decltype(dt)::value><<<g, 256, 0, st>>>(X.data, X.ld, X.d, rows, m, H, dZ, dH,
-                                                                        partial);
+        if (bf)
+            mlp_grad_partial_kernel<decltype(dt)::value, true><<<g, 256, 0, st>>>(X.data, X.ld, X.d, rows, m, H,
+                                                                                  dZ, dH, partial);
+        else
+            mlp_grad_partial_kernel<decltype(dt)::value, false><<<g, 256, 0, st>>>(X.data, X.ld, X.d, rows, m, H,
+                                                                                   dZ, dH, partial);
     });
     grad_reduce_kernel<<<(unsigned)ceil_div(o.P, 256), 256, 0, st>>>(partial, nch, o.P, grad);
     KNN_HIP(hipGetLastError());
@@ -843,9 +950,9 @@ extern "C" knn_status knn_encoder_embed(const knn_encoder* enc, knn_matrix X, in
         knn_status r = check_matrix(X, "X");
         if (r != KNN_OK) return r;
         if (X.d != enc->d) return fail(KNN_EINVAL, "X.d != encoder input width");
-        if (precision != KNN_PREC_FP32) return fail(KNN_ENOTSUP, "only the FP32 embedding is implemented");
+        if (precision != KNN_PREC_FP32 && precision != KNN_PREC_BF16) return fail(KNN_EINVAL, "unknown precision");
         hipStream_t st = (hipStream_t)stream;
-        if ((r = embed_impl(enc, X, Z, st)) != KNN_OK) return r;
+        if ((r = forward_impl(enc, X, nullptr, X.n, precision, nullptr, Z, st)) != KNN_OK) return r;
         KNN_HIP(hipStreamSynchronize(st));
         return KNN_OK;
     } catch (...) {
@@ -854,10 +961,12 @@ extern "C" knn_status knn_encoder_embed(const knn_encoder* enc, knn_matrix X, in
 }
 
 extern "C" knn_status knn_encoder_grads(knn_encoder* enc, knn_matrix X, const int32_t* rows, int32_t B,
-                                        float margin, float* loss_out, float* grads, void* stream)
+                                        float margin, int32_t precision, float* loss_out, float* grads,
+                                        void* stream)
 {
     try {
         if (!enc || !rows || !loss_out) return fail(KNN_EINVAL, "null argument");
+        if (precision != KNN_PREC_FP32 && precision != KNN_PREC_BF16) return fail(KNN_EINVAL, "unknown precision");
         knn_status r = check_matrix(X, "X");
         if (r != KNN_OK) return r;
         if (X.d != enc->d) return fail(KNN_EINVAL, "X.d != encoder input width");
@@ -876,7 +985,7 @@ extern "C" knn_status knn_encoder_grads(knn_encoder* enc, knn_matrix X, const in
         grad = grads;
         if (!grad && (r = ws.alloc(&grad, (size_t)o.P)) != KNN_OK) return r;
         if ((r = ws.alloc(&loss_dev, 1)) != KNN_OK) return r;
-        r = batch_grads(enc, X, rows, B, margin, H, Z, dZ, dH, lterm, partial, grad, loss_dev, st);
+        r = batch_grads(enc, X, rows, B, margin, precision, H, Z, dZ, dH, lterm, partial, grad, loss_dev, st);
         if (r != KNN_OK) return r;
         KNN_HIP(hipMemcpyAsync(loss_out, loss_dev, 4, hipMemcpyDeviceToHost, st));
         KNN_HIP(hipStreamSynchronize(st));
@@ -897,6 +1006,7 @@ extern "C" void knn_train_default_params(knn_train_params* t)
     t->eps = 1e-8f;
     t->margin = 1.0f;
     t->seed = 0;
+    t->precision = KNN_PREC_FP32;
 }
 
 extern "C" knn_status knn_encoder_train(knn_encoder* enc, knn_matrix X, const int32_t* knn_idx, int32_t k,
@@ -908,6 +1018,8 @@ extern "C" knn_status knn_encoder_train(knn_encoder* enc, knn_matrix X, const in
         if (r != KNN_OK) return r;
         if (X.d != enc->d) return fail(KNN_EINVAL, "X.d != encoder input width");
         if (k < 1 || tp->steps < 0 || tp->batch < 1) return fail(KNN_EINVAL, "bad training parameters");
+        if (tp->precision != KNN_PREC_FP32 && tp->precision != KNN_PREC_BF16)
+            return fail(KNN_EINVAL, "unknown precision");
         hipStream_t st = (hipStream_t)stream;
         Workspace ws(st, 0);
         const int B = tp->batch;
@@ -927,7 +1039,8 @@ extern "C" knn_status knn_encoder_train(knn_encoder* enc, knn_matrix X, const in
         for (int s = 0; s < tp->steps; ++s) {
             triplet_sample_kernel<<<(unsigned)ceil_div(B, 256), 256, 0, st>>>(X.n, knn_idx, k, B, tp->seed,
                                                                               enc->t + s, rows);
-            r = batch_grads(enc, X, rows, B, tp->margin, H, Z, dZ, dH, lterm, partial, grad, losses + s, st);
+            r = batch_grads(enc, X, rows, B, tp->margin, tp->precision, H, Z, dZ, dH, lterm, partial, grad,
+                            losses + s, st);
             if (r != KNN_OK) return r;
             const int t = enc->t + s + 1;
             const float c1 = 1.0f - powf(tp->beta1, (float)t), c2 = 1.0f - powf(tp->beta2, (float)t);

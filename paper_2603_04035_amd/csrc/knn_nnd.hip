@@ -858,8 +858,9 @@ __global__ __launch_bounds__(256) void nnd_finalize_kernel(
 
 // ------------------------------------------------------------------ host
 
-knn_status encoder_seed(const knn_encoder* enc, const knn_matrix& X, const knn_matrix& Xd, int K, int P, int D,
-                        int w, uint64_t seed, Workspace& ws, int32_t** seed_idx, float** seed_d2, hipStream_t st);
+knn_status encoder_seed(const knn_encoder* enc, const knn_matrix& X, const knn_matrix& Xd, int precision, int K,
+                        int P, int D, int w, uint64_t seed, Workspace& ws, int32_t** seed_idx, float** seed_d2,
+                        hipStream_t st);
 
 int encoder_dim(const knn_encoder* enc);
 
@@ -996,7 +997,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         const int D = p->proj_dims > 0 ? p->proj_dims : 8;
         // seed distances in the form's precision (the BF16 copy's values)
         const knn_matrix Xd = bf ? knn_matrix{Xb, X.n, X.d, ldb, KNN_BF16} : Xp;
-        r = encoder_seed(p->encoder, Xp, Xd, K, P, D, w, p->seed, ws, &si, &sd, st);
+        r = encoder_seed(p->encoder, Xp, Xd, p->precision, K, P, D, w, p->seed, ws, &si, &sd, st);
         if (r != KNN_OK) return r;
         seed_idx = si;
         seed_d2 = sd;

@@ -56,7 +56,8 @@ class Encoder:
                                            Z.data_ptr(), _stream()))
         return Z
 
-    def grads(self, X: torch.Tensor, rows: torch.Tensor, B: int, margin: float = 1.0):
+    def grads(self, X: torch.Tensor, rows: torch.Tensor, B: int, margin: float = 1.0,
+              precision: str = "fp32"):
         """Loss and flat gradient (gW1, gb1, gW2, gb2) of one triplet batch."""
         rows = rows.to(device=X.device, dtype=torch.int32).contiguous()
         if rows.numel() != 3 * B:
@@ -64,14 +65,15 @@ class Encoder:
         g = torch.empty(self.n_params, dtype=torch.float32, device=X.device)
         loss = C.c_float()
         _check(self._lib.knn_encoder_grads(self.handle, matrix(X), rows.data_ptr(), B, margin,
-                                           C.byref(loss), g.data_ptr(), _stream()))
+                                           _lib._PREC[precision], C.byref(loss), g.data_ptr(), _stream()))
         return loss.value, g
 
     def train(self, X: torch.Tensor, knn_idx: torch.Tensor, steps: int = 2000, batch: int = 4096,
-              lr: float = 1e-3, margin: float = 1.0, seed: int = 0) -> np.ndarray:
+              lr: float = 1e-3, margin: float = 1.0, seed: int = 0, precision: str = "fp32") -> np.ndarray:
         t = _lib.knn_train_params()
         self._lib.knn_train_default_params(C.byref(t))
         t.steps, t.batch, t.lr, t.margin, t.seed = steps, batch, lr, margin, seed
+        t.precision = _lib._PREC[precision]
         knn_idx = knn_idx.to(torch.int32).contiguous()
         log = np.zeros(max(steps, 1), np.float32)
         _check(self._lib.knn_encoder_train(self.handle, matrix(X), knn_idx.data_ptr(), knn_idx.shape[1],

@@ -59,21 +59,74 @@ def test_gradients_match_oracle(orc, B):
     assert np.abs(g[o:]).max() < 1e-5 * max(np.abs(g[:o]).max(), 1e-6) + 1e-6
 
 
+def test_embed_bf16_matches_oracle(orc):
+    """BF16 MFMA forward against the oracle's definition of the BF16 mode
+    (factors rounded to BF16, exact sums): within 1e-4 relative, the FP32
+    accumulation and rare BF16 rounding-boundary flips of hidden values;
+    and within 3e-2 of the FP64 forward of the unrounded values."""
+    from paper_2603_04035_amd import Encoder
+    X = datagen.gmm_isotropic(n=3001, d=50, seed=1)       # ragged: not a multiple of 32 rows
+    enc = Encoder(50, seed=3)
+    W1, b1, W2, b2 = enc.get_weights()
+    rng = np.random.default_rng(9)
+    b1 = rng.normal(0, 0.1, size=64).astype(np.float32)
+    b2 = rng.normal(0, 0.1, size=32).astype(np.float32)
+    enc.set_weights(W1, b1, W2, b2)
+    Z = enc.embed(_dev(X), precision="bf16").cpu().numpy()
+    Zb = orc.mlp_forward_bf16(X, W1, b1, W2, b2)
+    Z64 = orc.mlp_forward(X, W1, b1, W2, b2)
+    print("bf16 embed rel err vs bf16 mode", _rel(Z, Zb), "vs fp64", _rel(Z, Z64))
+    assert _rel(Z, Zb) < 1e-4, _rel(Z, Zb)
+    assert _rel(Z, Z64) < 3e-2, _rel(Z, Z64)
+    for d in (7, 33, 784):   # d below, across and far above the 16-wide reduction steps
+        Xd = datagen.gmm_isotropic(n=100, d=d, seed=d)
+        e = Encoder(d, seed=d)
+        Zd = e.embed(_dev(Xd), precision="bf16").cpu().numpy()
+        assert _rel(Zd, orc.mlp_forward_bf16(Xd, *e.get_weights())) < 1e-4, d
+
+
+@pytest.mark.parametrize("B", [1, 37, 4096])
+def test_gradients_bf16_match_oracle(orc, B):
+    from paper_2603_04035_amd import Encoder
+    d = 50
+    X = datagen.gmm_isotropic(n=5000, d=d, seed=2)
+    rng = np.random.default_rng(B)
+    rows = rng.integers(0, 5000, size=3 * B)
+    enc = Encoder(d, seed=4)
+    W1, b1, W2, b2 = enc.get_weights()
+    b1 = rng.normal(0, 0.1, size=64).astype(np.float32)
+    b2 = rng.normal(0, 0.1, size=32).astype(np.float32)
+    enc.set_weights(W1, b1, W2, b2)
+    loss, g = enc.grads(_dev(X), torch.from_numpy(rows), B, margin=1.0, precision="bf16")
+    g = g.cpu().numpy()
+    Zo = orc.mlp_forward_bf16(X[rows], W1, b1, W2, b2)
+    lo, dZ = orc.triplet_loss(Zo, B, 1.0)
+    refs = orc.mlp_backward_bf16(X[rows], W1, b1, W2, dZ)
+    assert abs(loss - lo) <= 1e-4 * max(abs(lo), 1e-6), (loss, lo)
+    o = 0
+    for name, ref in zip(("gW1", "gb1", "gW2"), refs[:3]):
+        part = g[o:o + ref.size]
+        print(B, name, _rel(part, ref))
+        assert _rel(part, ref) < 1e-3, (name, _rel(part, ref))
+        o += ref.size
+
+
 def test_training_lowers_loss_and_is_deterministic():
     from paper_2603_04035_amd import Encoder
     import paper_2603_04035_amd as knn
     X = _dev(datagen.gmm_anisotropic(n=20000, d=50, comps=20, seed=5))
     idx, _ = knn.knn_exact(X, 15)
-    runs = []
-    for _ in range(2):
-        enc = Encoder(50, seed=1)
-        log = enc.train(X, idx, steps=300, batch=1024, lr=1e-3, seed=7)
-        runs.append((log, enc.get_weights()))
-    log = runs[0][0]
-    assert log[-20:].mean() < 0.5 * log[:20].mean(), (log[:5], log[-5:])
-    assert np.array_equal(runs[0][0], runs[1][0])
-    for a, b in zip(runs[0][1], runs[1][1]):
-        assert np.array_equal(a, b)
+    for prec in ("fp32", "bf16"):
+        runs = []
+        for _ in range(2):
+            enc = Encoder(50, seed=1)
+            log = enc.train(X, idx, steps=300, batch=1024, lr=1e-3, seed=7, precision=prec)
+            runs.append((log, enc.get_weights()))
+        log = runs[0][0]
+        assert log[-20:].mean() < 0.5 * log[:20].mean(), (prec, log[:5], log[-5:])
+        assert np.array_equal(runs[0][0], runs[1][0])
+        for a, b in zip(runs[0][1], runs[1][1]):
+            assert np.array_equal(a, b)
 
 
 def test_proj_seed_matches_oracle(orc):

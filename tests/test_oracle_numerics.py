@@ -208,3 +208,66 @@ def test_proj_seed_zorder_windows(orc):
         cand = sorted(members[i], key=lambda j: (((X[i] - X[j]) ** 2).sum(), j))
         got = [j for j in idx[i] if j >= 0]
         assert got == cand[:12]
+
+
+def _exact_mlp_case(rng, m=40, d=50):
+    """Inputs on which every BF16 rounding of the BF16 mode is exact: small
+    integers and quarters, so products, sums and hidden values keep at most
+    8 significant bits."""
+    X = rng.integers(-2, 3, size=(m, d)).astype(np.float64)
+    W1 = rng.integers(-1, 2, size=(d, 64)) / 4.0
+    b1 = rng.integers(-4, 5, size=64) / 4.0
+    W2 = rng.integers(-1, 2, size=(64, 32)) / 4.0
+    b2 = rng.integers(-4, 5, size=32) / 4.0
+    return X, W1, b1, W2, b2
+
+
+def test_mlp_bf16_mode_equals_fp64_when_rounding_is_exact(orc):
+    rng = np.random.default_rng(3)
+    X, W1, b1, W2, b2 = _exact_mlp_case(rng)
+    Zb, Hb = orc.mlp_forward_bf16(X, W1, b1, W2, b2, want_hidden=True)
+    Z, H = orc.mlp_forward(X, W1, b1, W2, b2, want_hidden=True)
+    assert np.array_equal(Zb, Z) and np.array_equal(Hb, H)
+    dZ = rng.integers(-3, 4, size=Z.shape) / 4.0
+    for gb, g in zip(orc.mlp_backward_bf16(X, W1, b1, W2, dZ), orc.mlp_backward(X, W1, b1, W2, dZ)):
+        assert np.array_equal(gb, g)
+
+
+@pytest.mark.parametrize("which", ["X", "W1", "W2"])
+def test_mlp_bf16_mode_rounds_each_factor(orc, which):
+    """Perturb one factor off the BF16 grid: the BF16 mode equals the FP64
+    forward of the same inputs with that factor rounded, and only that one."""
+    rng = np.random.default_rng(4)
+    X, W1, b1, W2, b2 = _exact_mlp_case(rng)
+    args = {"X": X, "W1": W1, "W2": W2}
+    off = args[which] * (1.0 + 2.0 ** -10)   # below BF16 resolution, above FP32's: rounds back
+    args[which] = off
+    Zb = orc.mlp_forward_bf16(args["X"], args["W1"], b1, args["W2"], b2)
+    rounded = dict(args)
+    rounded[which] = orc.bf16_values(off)
+    Zr = orc.mlp_forward(rounded["X"], rounded["W1"], b1, rounded["W2"], b2)
+    assert np.array_equal(Zb, Zr)
+    assert not np.array_equal(orc.mlp_forward(args["X"], args["W1"], b1, args["W2"], b2), Zr)
+
+
+def test_mlp_bf16_mode_close_to_fp64_on_generic_inputs(orc):
+    """On generic data the BF16 mode differs from FP64 by the BF16 rounding:
+    the embedding and gW2 by a nonzero amount within 3e-2 relative (tensor
+    norm).  gW1 and gb1 also depend on the ReLU mask, which flips for hidden
+    units within rounding of zero, and their batch sums cancel, so they are
+    held to 1e-1."""
+    rng = np.random.default_rng(5)
+    X = datagen.gmm_isotropic(n=500, d=50, seed=5).astype(np.float64)
+    W1 = rng.normal(0, 0.2, size=(50, 64))
+    b1 = rng.normal(0, 0.1, size=64)
+    W2 = rng.normal(0, 0.2, size=(64, 32))
+    b2 = rng.normal(0, 0.1, size=32)
+    Zb = orc.mlp_forward_bf16(X, W1, b1, W2, b2)
+    Z = orc.mlp_forward(X, W1, b1, W2, b2)
+    rel = np.linalg.norm(Zb - Z) / np.linalg.norm(Z)
+    assert 0 < rel < 3e-2, rel
+    dZ = rng.normal(size=Z.shape)
+    for name, gb, g in zip(("gW1", "gb1", "gW2", "gb2"), orc.mlp_backward_bf16(X, W1, b1, W2, dZ),
+                           orc.mlp_backward(X, W1, b1, W2, dZ)):
+        rel = np.linalg.norm(gb - g) / np.linalg.norm(g)
+        assert rel < (1e-1 if name in ("gW1", "gb1") else 3e-2), (name, rel)

@@ -205,6 +205,28 @@ def distance_error(X, Xnp, k, p, rows):
             "rel_p99": float(np.percentile(e, 99))}
 
 
+def exact_path(X, k, reps=3):
+    """knn_exact of X among itself in both precisions: wall time per call and
+    the GEMM's algorithmic rate 2 n^2 d / time against the MFMA peak of the
+    precision (FP32 157.3 TFLOP/s, BF16 2500 TFLOP/s dense)."""
+    import torch
+    import paper_2603_04035_amd as knn
+    n, d = X.shape
+    out = {}
+    for prec, peak in (("fp32", 157.3), ("bf16", 2500.0)):
+        knn.knn_exact(X, k, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            knn.knn_exact(X, k, precision=prec)
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t0) / reps
+        tflops = 2.0 * n * n * d / (ms * 1e-3) / 1e12
+        out[prec] = {"ms": round(ms, 3), "tflops": round(tflops, 2), "peak": peak,
+                     "frac": round(tflops / peak, 4)}
+    return out
+
+
 def run_form(X, k, form, steps, warmup, rows, encoder=None, Xnp=None):
     import torch
     import paper_2603_04035_amd as knn
@@ -259,6 +281,8 @@ def main():
     ap.add_argument("--recall-rows", type=int, default=10000)
     ap.add_argument("--cpu-sample", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--exact", action="store_true",
+                    help="only time the exact path (knn_exact of the workload, both precisions)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (counter calibration)")
     args = ap.parse_args()
@@ -288,6 +312,10 @@ def main():
     n, d = Xnp.shape
     X = torch.from_numpy(Xnp).to("cuda")
     torch.cuda.synchronize()
+    if args.exact:
+        print(json.dumps({"exact_path": exact_path(X, k), "config": {"workload": CONFIGS[args.config]["desc"]},
+                          "n": n, "d": d, "k": k}), flush=True)
+        return
     rows = datagen.sample_queries(n, args.recall_rows, seed=2)
     forms = {"both": ["fp32", "bf16-learned"], "all": ["fp32", "bf16-learned", "bf16-random", "bf16-untrained"]}.get(
         args.form, [args.form])

@@ -501,6 +501,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
         __syncthreads();
         uint4 A0[kPC], A1[kPC];
         for (int cb = 0; cb < (two ? 2 : 1); ++cb) {
+            // rows 32..63 x members 32..63 pair old with old when every new
+            // member is in the first block
+            const bool lower = two && (cb == 0 || nn > 32);
             float z = 0.0f;
             asm volatile("" : "+v"(z));   // one zero register per pass, not sixteen held ones
             f32x16 at, ab;
@@ -523,7 +526,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
                     if (q < pc) {
                         const uint4 b = cb == 0 ? A0[q] : A1[q];
                         at = gram_step(A0[q], b, at);
-                        if (two) ab = gram_step(A1[q], b, ab);
+                        if (lower) ab = gram_step(A1[q], b, ab);
                     }
                 }
             }
@@ -538,7 +541,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
             const float nm = nrm[m];
             const int lim = m < nn ? L : nn;
             scan_block(at, 0, h4, m, lim, nm, nrm, best);
-            if (two) scan_block(ab, 1, h4, m, lim, nm, nrm, best);
+            if (lower) scan_block(ab, 1, h4, m, lim, nm, nrm, best);
             uint32_t recv[kJMax];
 #pragma unroll
             for (int q = 0; q < kJMax; ++q) recv[q] = xor_u32(best[q], 32);
@@ -565,7 +568,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
 constexpr int kFC = 32;        // coordinates per staged chunk
 constexpr int kFS = kFC + 2;   // LDS row stride (floats)
 
-template <int NB>
+// NI = number of 8-row groups holding new members (new rows come first):
+// register blocks (i, q) with i >= NI and q >= NI pair old with old only and
+// are skipped.
+template <int NB, int NI>
 __device__ inline void join_f32_point(const float* __restrict__ Xs, int ldp, int d, float* rows,
                                       const uint32_t* ids, const float* nrm, const float* thr, int L, int nn,
                                       int J, int C, uint64_t salt, unsigned long long* __restrict__ cand,
@@ -609,8 +615,10 @@ __device__ inline void join_f32_point(const float* __restrict__ Xs, int ldp, int
                 const float2 xb = *(const float2*)(rows + (bg + 8 * q) * kFS + t);
 #pragma unroll
                 for (int i = 0; i < NB; ++i) {
-                    acc[i][q] = fmaf(xa[i].x, xb.x, acc[i][q]);
-                    acc[i][q] = fmaf(xa[i].y, xb.y, acc[i][q]);
+                    if (i < NI || q < NI) {
+                        acc[i][q] = fmaf(xa[i].x, xb.x, acc[i][q]);
+                        acc[i][q] = fmaf(xa[i].y, xb.y, acc[i][q]);
+                    }
                 }
             }
         }
@@ -681,8 +689,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
             nrm[lane] = 0.0f;
         }
         gathered += (unsigned long long)L;
-        if (L <= 32) join_f32_point<4>(Xs, ldp, d, rows, ids, nrm, thr, L, nn, cfg.J, cfg.C, salt, cand, emitted);
-        else join_f32_point<8>(Xs, ldp, d, rows, ids, nrm, thr, L, nn, cfg.J, cfg.C, salt, cand, emitted);
+        const int ni = (nn + 7) >> 3;
+#define KNN_JF(NB, NI) join_f32_point<NB, NI>(Xs, ldp, d, rows, ids, nrm, thr, L, nn, cfg.J, cfg.C, salt, cand, emitted)
+        if (L <= 32) {
+            switch (ni) {
+            case 1: KNN_JF(4, 1); break;
+            case 2: KNN_JF(4, 2); break;
+            case 3: KNN_JF(4, 3); break;
+            default: KNN_JF(4, 4); break;
+            }
+        } else {
+            switch (ni) {
+            case 1: KNN_JF(8, 1); break;
+            case 2: KNN_JF(8, 2); break;
+            case 3: KNN_JF(8, 3); break;
+            case 4: KNN_JF(8, 4); break;
+            case 5: KNN_JF(8, 5); break;
+            case 6: KNN_JF(8, 6); break;
+            case 7: KNN_JF(8, 7); break;
+            default: KNN_JF(8, 8); break;
+            }
+        }
+#undef KNN_JF
     }
     for (int o = 32; o > 0; o >>= 1) emitted += shfl_u64(emitted, lane ^ o);
     if (lane == 0) {

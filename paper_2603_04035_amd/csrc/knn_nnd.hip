@@ -188,9 +188,10 @@ __global__ __launch_bounds__(256) void nnd_init_kernel(
 
 // ---------------------------------------------------------------- sample
 
-// Half-wave (32 lanes) per row, K <= 32.  Picks the s new entries with the
-// smallest priorities (ties by position), marks them old, lists old entries,
-// and scatters reverse edges into R slots per target row.  Waves take row
+// Half-wave (32 lanes) per row, K <= 32.  Picks the new entries (the s with
+// the smallest random priorities, ties by position, when there are more than
+// s), writes them in list order and marks them old, lists old entries, and
+// scatters reverse edges into R slots per target row.  Waves take row
 // pairs from contiguous ranges, one range per group of blockIdx mod 8 (the
 // XCD of the workgroup), so the scattered targets of concurrent rows are
 // mostly Z-order neighbours.  gridDim.x is a multiple of 8.
@@ -215,19 +216,28 @@ __global__ __launch_bounds__(256) void nnd_sample_kernel(
         }
         const bool isnew = inl && id >= 0 && fl;
         const bool isold = inl && id >= 0 && !fl;
-        uint64_t pr = isnew ? hash4(seed ^ kTagSample, (uint64_t)iter, (uint64_t)row, (uint64_t)id)
-                            : ~0ull;
-        // rank among the new entries of this half
-        int rank = 0;
-        for (int o = 0; o < 32; ++o) {
-            const uint64_t p0 = bcast_u64(pr, o), p1 = bcast_u64(pr, 32 + o);
-            const uint64_t po = hbase ? p1 : p0;
-            rank += (po < pr || (po == pr && o < hl)) ? 1 : 0;
-        }
-        const bool pick = isnew && rank < s;
         const uint64_t nm = ballot(isnew), om = ballot(isold);
         const uint64_t hn = hbase ? (nm >> 32) : (nm & 0xFFFFFFFFull);
         const uint64_t ho = hbase ? (om >> 32) : (om & 0xFFFFFFFFull);
+        // the picks: every new entry when there are at most s, else the s with
+        // the smallest random priorities (ties by position); the rank loop
+        // runs only for a wave that has a row with more than s new entries
+        bool pick = isnew;
+        if (ballot(__popcll(hn) > (uint64_t)s)) {
+            const uint64_t pr = isnew ? hash4(seed ^ kTagSample, (uint64_t)iter, (uint64_t)row, (uint64_t)id)
+                                      : ~0ull;
+            int prank = 0;
+            for (int o = 0; o < 32; ++o) {
+                const uint64_t p0 = bcast_u64(pr, o), p1 = bcast_u64(pr, 32 + o);
+                const uint64_t po = hbase ? p1 : p0;
+                prank += (po < pr || (po == pr && o < hl)) ? 1 : 0;
+            }
+            pick = isnew && prank < s;
+        }
+        // picks are written in list order
+        const uint64_t pm = ballot(pick);
+        const uint64_t hp = hbase ? (pm >> 32) : (pm & 0xFFFFFFFFull);
+        const int rank = __popcll(hp & ((1ull << hl) - 1ull));
         const int npick = __popcll(hn) < s ? __popcll(hn) : s;
         const int nold = __popcll(ho);
         const int opos = __popcll(ho & ((1ull << hl) - 1ull));
@@ -360,31 +370,80 @@ __device__ inline void sel_insert(uint32_t (&best)[kJMax], uint32_t key)
     }
 }
 
-// Offer member `me` its kept partners q < J whose bit is set in qmask and
-// that beat its current worst distance: atomicMin of the (distance, partner
-// id) key into slot hash(partner, iteration) of me's candidate row.  Slots
-// only decrease during a launch, so a plain read that already shows a key at
-// most as large makes the atomic a no-op and it is skipped.
-__device__ inline unsigned long long emit_best(const uint32_t (&best)[kJMax], int J, unsigned qmask, float cut,
-                                               const uint32_t* ids, uint32_t me, int C, uint64_t salt,
-                                               unsigned long long* __restrict__ cand)
+// Offers whose slot reads are in flight: a column pass issues them (key,
+// slot address, read of the slot) and the next pass -- after its own MFMA
+// and selection work -- resolves them with atomicMin where the slot still
+// holds a larger key, so the read latency overlaps computation.  Each lane
+// carries up to two offers (its member's positions q = h and h + 2).
+struct PendingOffers {
+    unsigned long long* p[2];
+    uint64_t key[2];
+    unsigned long long seen[2];
+};
+
+__device__ inline void offers_issue(PendingOffers& po, const uint32_t (&best)[kJMax], int J, int h, bool valid,
+                                    float cut, const uint32_t* ids, uint32_t me, int C, uint64_t salt,
+                                    unsigned long long* __restrict__ cand)
 {
-    unsigned long long emitted = 0;
 #pragma unroll
-    for (int q = 0; q < kJMax; ++q) {
-        const uint32_t b = best[q];
-        if (q < J && ((qmask >> q) & 1u) && b != kNoSel && __uint_as_float(b & ~63u) < cut) {
+    for (int t = 0; t < 2; ++t) {
+        const int q = h + 2 * t;
+        const uint32_t b = t == 0 ? (h ? best[1] : best[0]) : (h ? best[3] : best[2]);
+        po.p[t] = nullptr;
+        po.key[t] = ~0ull;
+        po.seen[t] = 0ull;
+        if (valid && q < J && b != kNoSel && __uint_as_float(b & ~63u) < cut) {
             const uint32_t src = ids[b & 63u];
-            const uint64_t key = ((uint64_t)(b & ~63u) << 32) | src;
+            po.key[t] = ((uint64_t)(b & ~63u) << 32) | src;
             const uint32_t slot = bounded(mix64(((uint64_t)src << 20) ^ salt), (uint32_t)C);
-            unsigned long long* p = &cand[(int64_t)me * C + slot];
-            if (*p > (unsigned long long)key) {
-                atomicMin(p, (unsigned long long)key);
-                ++emitted;
-            }
+            po.p[t] = &cand[(int64_t)me * C + slot];
+            po.seen[t] = *po.p[t];
         }
     }
-    return emitted;
+}
+
+__device__ inline unsigned long long offers_resolve(const PendingOffers& po)
+{
+    unsigned long long n = 0;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        if (po.p[t] && po.seen[t] > (unsigned long long)po.key[t]) {
+            atomicMin(po.p[t], (unsigned long long)po.key[t]);
+            ++n;
+        }
+    }
+    return n;
+}
+
+// One pending offer per lane (the FP32 join: lane ag < 4 offers entry ag).
+struct PendingOffer {
+    unsigned long long* p;
+    uint64_t key;
+    unsigned long long seen;
+};
+
+__device__ inline void offer_issue(PendingOffer& po, uint32_t b, bool ok, float cut, const uint32_t* ids,
+                                   uint32_t me, int C, uint64_t salt, unsigned long long* __restrict__ cand)
+{
+    po.p = nullptr;
+    po.key = ~0ull;
+    po.seen = 0ull;
+    if (ok && b != kNoSel && __uint_as_float(b & ~63u) < cut) {
+        const uint32_t src = ids[b & 63u];
+        po.key = ((uint64_t)(b & ~63u) << 32) | src;
+        const uint32_t slot = bounded(mix64(((uint64_t)src << 20) ^ salt), (uint32_t)C);
+        po.p = &cand[(int64_t)me * C + slot];
+        po.seen = *po.p;
+    }
+}
+
+__device__ inline unsigned long long offer_resolve(const PendingOffer& po)
+{
+    if (po.p && po.seen > (unsigned long long)po.key) {
+        atomicMin(po.p, (unsigned long long)po.key);
+        return 1;
+    }
+    return 0;
 }
 
 // Local join, BF16 form.  One wave per point v; the grid is split into 8
@@ -476,6 +535,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     const int64_t gsz = (int64_t)(gridDim.x >> 3);
     const int64_t lo = n * grp / 8, hi = n * (grp + 1) / 8;
 
+    PendingOffers po;
+    po.p[0] = po.p[1] = nullptr;
     int64_t v = lo + (int64_t)(blockIdx.x >> 3);
     ListRaw cur = load_lists(v, v < hi, cfg, newf, revnew, oldf, revold);
     for (; v < hi; v += gsz) {
@@ -547,9 +608,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
             for (int q = 0; q < kJMax; ++q) recv[q] = xor_u32(best[q], 32);
 #pragma unroll
             for (int q = 0; q < kJMax; ++q) sel_insert(best, recv[q]);
-            if (m < L) emitted += emit_best(best, J, h ? 0xAu : 0x5u, thr[m], ids, ids[m], cfg.C, salt, cand);
+            emitted += offers_resolve(po);
+            offers_issue(po, best, J, h, m < L, m < L ? thr[m] : 0.0f, ids, ids[m], cfg.C, salt, cand);
         }
     }
+    emitted += offers_resolve(po);
     for (int o = 32; o > 0; o >>= 1) emitted += shfl_u64(emitted, lane ^ o);
     if (lane == 0) {
         atomicAdd(&counters[1], emitted);
@@ -575,7 +638,7 @@ template <int NB, int NI>
 __device__ inline void join_f32_point(const float* __restrict__ Xs, int ldp, int d, float* rows,
                                       const uint32_t* ids, const float* nrm, const float* thr, int L, int nn,
                                       int J, int C, uint64_t salt, unsigned long long* __restrict__ cand,
-                                      unsigned long long& emitted)
+                                      unsigned long long& emitted, PendingOffer& po)
 {
     int ln = threadIdx.x;
     asm volatile("" : "+v"(ln));   // lane-dependent indices re-derived per point
@@ -650,7 +713,10 @@ __device__ inline void join_f32_point(const float* __restrict__ Xs, int ldp, int
 #pragma unroll
             for (int s = 0; s < kJMax; ++s) sel_insert(best, recv[s]);
         }
-        if (b < L && ag < kJMax) emitted += emit_best(best, J, 1u << ag, thr[b], ids, ids[b], C, salt, cand);
+        // lane ag offers merged entry ag; the previous column's offer resolves first
+        emitted += offer_resolve(po);
+        const uint32_t mine = ag == 0 ? best[0] : (ag == 1 ? best[1] : (ag == 2 ? best[2] : best[3]));
+        offer_issue(po, mine, b < L && ag < J, b < L ? thr[b] : 0.0f, ids, ids[b], C, salt, cand);
     }
 }
 
@@ -672,6 +738,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     const int64_t gsz = (int64_t)(gridDim.x >> 3);
     const int64_t lo = n * grp / 8, hi = n * (grp + 1) / 8;
 
+    PendingOffer po;
+    po.p = nullptr;
     int64_t v = lo + (int64_t)(blockIdx.x >> 3);
     ListRaw cur = load_lists(v, v < hi, cfg, newf, revnew, oldf, revold);
     for (; v < hi; v += gsz) {
@@ -690,7 +758,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
         }
         gathered += (unsigned long long)L;
         const int ni = (nn + 7) >> 3;
-#define KNN_JF(NB, NI) join_f32_point<NB, NI>(Xs, ldp, d, rows, ids, nrm, thr, L, nn, cfg.J, cfg.C, salt, cand, emitted)
+#define KNN_JF(NB, NI) \
+    join_f32_point<NB, NI>(Xs, ldp, d, rows, ids, nrm, thr, L, nn, cfg.J, cfg.C, salt, cand, emitted, po)
         if (L <= 32) {
             switch (ni) {
             case 1: KNN_JF(4, 1); break;
@@ -712,6 +781,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
         }
 #undef KNN_JF
     }
+    emitted += offer_resolve(po);
     for (int o = 32; o > 0; o >>= 1) emitted += shfl_u64(emitted, lane ^ o);
     if (lane == 0) {
         atomicAdd(&counters[1], emitted);

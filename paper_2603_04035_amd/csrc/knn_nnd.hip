@@ -791,74 +791,85 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
 
 // ------------------------------------------------------------------ merge
 
-// One wave per row, rows taken from 8 contiguous ranges (blockIdx mod 8, as
-// in the sample kernel; gridDim.x is a multiple of 8), the next row's list
-// and first 64 slots loaded while the current row is merged.  Lanes 0..K-1
-// hold the sorted list.  The C candidate slots are read 64 at a time (and
-// reset); keys whose index is already listed (or is the row) are dropped,
-// the rest are compacted into LDS; then rounds of (list + up to 64-K
-// candidates) are bitonic-sorted and the first K kept.  Old list entries
+// Merge, one half-wave (32 lanes) per row, two rows per wave; the waves take
+// row pairs from 8 contiguous ranges (blockIdx mod 8, as in the sample
+// kernel; gridDim.x is a multiple of 8), the next pair's list and first 64
+// slots loaded while the current pair is merged.  Lane hl < K holds list
+// entry hl.  The C candidate slots are read 32 at a time (and reset); keys
+// whose index is already listed (or is the row) are dropped, the rest are
+// compacted into LDS; then each chunk of 32 candidates is sorted and merged
+// into the list by keeping the 32 smallest of the two sorted halves (a
+// bitonic clean), so the first K lanes stay the list.  Old list entries
 // carry kWasOld in the index word, so lists are ordered by (distance, old
 // after new, index) -- the order the init kernel also sorts by, which makes
 // a resumed run bitwise equal to an uninterrupted one.  Entries whose index
 // is not in the previous list came from slots: flagged new and counted.  The
 // new K-th distance goes to the row's worst-distance word.
-
 __global__ __launch_bounds__(256) void nnd_merge_kernel(
     int64_t n, int K, int C, int32_t* __restrict__ gidx, float* __restrict__ gd2,
     uint8_t* __restrict__ gflag, unsigned long long* __restrict__ cand,
     unsigned long long* __restrict__ counters, float* __restrict__ worst, int64_t wstride)
 {
     extern __shared__ uint64_t sbuf_all[];
-    __shared__ __attribute__((aligned(16))) uint32_t slid[4][64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    uint64_t* sbuf = sbuf_all + (size_t)wv * C;
+    __shared__ __attribute__((aligned(16))) uint32_t slid[8][32];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, hl = lane & 31, hf = lane >> 5;
+    const int seg = 2 * wv + hf;
+    uint64_t* sbuf = sbuf_all + (size_t)seg * C;
+    const uint64_t below = (1ull << hl) - 1ull;
     const unsigned grp = blockIdx.x & 7u;
     const int64_t lo = n * grp / 8, hi = n * (grp + 1) / 8;
     const int64_t wstep = (int64_t)(gridDim.x >> 3) * 4;
     unsigned long long upd = 0;
-    int64_t row = lo + (int64_t)(blockIdx.x >> 3) * 4 + wv;
-    // current row's raw inputs
-    uint64_t slot0 = kEmptyCand;
+    int64_t pw = (int64_t)(blockIdx.x >> 3) * 4 + wv;
+    // raw inputs of the current pair
+    uint64_t s0 = kEmptyCand, s1 = kEmptyCand;
     int32_t id = -1;
     float dd = 0.0f;
     uint8_t fl = 0;
-    if (row < hi) {
-        if (lane < C) slot0 = cand[row * C + lane];
-        if (lane < K) {
-            id = gidx[row * K + lane];
-            dd = gd2[row * K + lane];
-            fl = gflag[row * K + lane];
-        }
-    }
-    for (; row < hi; row += wstep) {
-        const uint32_t lid = id >= 0 ? (uint32_t)id : 0xFFFFFFFFu;
-        uint64_t okey = kEmptyCand;
-        if (lane < K)
-            okey = id >= 0 ? make_key(dd, lid | (fl ? 0u : kWasOld)) : kEmptyList;
-        uint64_t first = slot0;
-        // next row's inputs are in flight during this merge
-        const int64_t nrow = row + wstep;
-        slot0 = kEmptyCand;
-        id = -1;
-        if (nrow < hi) {
-            if (lane < C) slot0 = cand[nrow * C + lane];
-            if (lane < K) {
-                id = gidx[nrow * K + lane];
-                dd = gd2[nrow * K + lane];
-                fl = gflag[nrow * K + lane];
+    {
+        const int64_t row = lo + 2 * pw + hf;
+        if (row < hi) {
+            if (hl < C) s0 = cand[row * C + hl];
+            if (32 + hl < C) s1 = cand[row * C + 32 + hl];
+            if (hl < K) {
+                id = gidx[row * K + hl];
+                dd = gd2[row * K + hl];
+                fl = gflag[row * K + hl];
             }
         }
-        slid[wv][lane] = lid;
+    }
+    for (; lo + 2 * pw < hi; pw += wstep) {
+        const int64_t row = lo + 2 * pw + hf;
+        const bool rv = row < hi;
+        const uint32_t lid = id >= 0 ? (uint32_t)id : 0xFFFFFFFFu;
+        uint64_t cur = kEmptyCand;
+        if (hl < K) cur = id >= 0 ? make_key(dd, lid | (fl ? 0u : kWasOld)) : kEmptyList;
+        const uint64_t f0 = s0, f1 = s1;
+        // next pair's inputs are in flight during this merge
+        {
+            const int64_t nrow = row + 2 * wstep;
+            s0 = s1 = kEmptyCand;
+            id = -1;
+            if (nrow < hi) {
+                if (hl < C) s0 = cand[nrow * C + hl];
+                if (32 + hl < C) s1 = cand[nrow * C + 32 + hl];
+                if (hl < K) {
+                    id = gidx[nrow * K + hl];
+                    dd = gd2[nrow * K + hl];
+                    fl = gflag[nrow * K + hl];
+                }
+            }
+        }
+        slid[seg][hl] = hl < K ? lid : 0xFFFFFFFFu;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         int nc = 0;
-        for (int c0 = 0; c0 < C; c0 += 64) {
+        for (int c0 = 0; c0 < C; c0 += 32) {
             uint64_t key = kEmptyCand;
-            if (c0 + lane < C) {
-                unsigned long long* p = &cand[row * C + c0 + lane];
-                key = c0 == 0 ? first : *p;
+            if (rv && c0 + hl < C) {
+                unsigned long long* p = &cand[row * C + c0 + hl];
+                key = c0 == 0 ? f0 : (c0 == 32 ? f1 : *p);
                 if (key != kEmptyCand) *p = kEmptyCand;
             }
             if (!ballot(key != kEmptyCand)) continue;
@@ -866,44 +877,43 @@ __global__ __launch_bounds__(256) void nnd_merge_kernel(
             bool dup = sid == (uint32_t)row;
 #pragma unroll
             for (int r = 0; r < 32; r += 4) {
-                const uint4 x = *(const uint4*)&slid[wv][r];
-                dup = dup || (r + 0 < K && x.x == sid) || (r + 1 < K && x.y == sid) ||
-                      (r + 2 < K && x.z == sid) || (r + 3 < K && x.w == sid);
+                const uint4 x = *(const uint4*)&slid[seg][r];
+                dup = dup || x.x == sid || x.y == sid || x.z == sid || x.w == sid;
             }
             const bool keep = key != kEmptyCand && !dup;
             const uint64_t km = ballot(keep);
-            if (keep) sbuf[nc + rank_below(km)] = key;
-            nc += popc64(km);
+            const uint64_t hm = hf ? (km >> 32) : (km & 0xFFFFFFFFull);
+            if (keep) sbuf[nc + __popcll(hm & below)] = key;
+            nc += __popcll(hm);
         }
-        if (nc > 0) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            uint64_t cur = lane < K ? okey : kEmptyCand;
-            const int per = 64 - K;
-            for (int b0 = 0; b0 < nc; b0 += per) {
-                uint64_t x = cur;
-                if (lane >= K && b0 + lane - K < nc) x = sbuf[b0 + lane - K];
-                x = seg_sort<64>(x);
-                cur = lane < K ? x : kEmptyCand;
-            }
-            const uint32_t w = key_idx(cur);
-            const uint32_t cid = w & ~kWasOld;
-            const bool sv = key_valid(cur) && key_d2(cur) < __builtin_inff();
-            bool from_list = false;
+        if (!ballot(nc > 0)) continue;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        // the sample kernel may have turned entries old since the list was
+        // sorted, which can reorder equal distances: re-sort if needed
+        const uint64_t nxt = shfl_u64(cur, lane + 1 < 64 ? lane + 1 : lane);
+        if (ballot(hl < 31 && cur > nxt)) cur = seg_sort<32>(cur);
+        for (int b0 = 0; ballot(b0 < nc); b0 += 32) {
+            uint64_t x = b0 + hl < nc ? sbuf[b0 + hl] : kEmptyCand;
+            x = seg_sort<32>(x);
+            cur = seg_merge_sorted<32>(cur, x);
+        }
+        const uint32_t w = key_idx(cur);
+        const uint32_t cidx = w & ~kWasOld;
+        const bool sv = key_valid(cur) && key_d2(cur) < __builtin_inff();
+        bool from_list = false;
 #pragma unroll
-            for (int r = 0; r < 32; r += 4) {
-                const uint4 x = *(const uint4*)&slid[wv][r];
-                from_list = from_list || (r + 0 < K && x.x == cid) || (r + 1 < K && x.y == cid) ||
-                            (r + 2 < K && x.z == cid) || (r + 3 < K && x.w == cid);
-            }
-            upd += (unsigned long long)popc64(ballot(lane < K && sv && !from_list));
-            if (lane < K) {
-                gidx[row * K + lane] = sv ? (int32_t)cid : -1;
-                gd2[row * K + lane] = sv ? key_d2(cur) : __builtin_inff();
-                gflag[row * K + lane] = sv ? (uint8_t)((w & kWasOld) ? 0 : 1) : 0;
-                if (lane == K - 1) worst[row * wstride] = sv ? key_d2(cur) : __builtin_inff();
-            }
+        for (int r = 0; r < 32; r += 4) {
+            const uint4 x = *(const uint4*)&slid[seg][r];
+            from_list = from_list || x.x == cidx || x.y == cidx || x.z == cidx || x.w == cidx;
+        }
+        upd += (unsigned long long)popc64(ballot(hl < K && nc > 0 && sv && !from_list));
+        if (nc > 0 && hl < K) {
+            gidx[row * K + hl] = sv ? (int32_t)cidx : -1;
+            gd2[row * K + hl] = sv ? key_d2(cur) : __builtin_inff();
+            gflag[row * K + hl] = sv ? (uint8_t)((w & kWasOld) ? 0 : 1) : 0;
+            if (hl == K - 1) worst[row * wstride] = sv ? key_d2(cur) : __builtin_inff();
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
@@ -1119,7 +1129,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     unsigned long long* host_cnt = pinned_counters();
     if (!host_cnt) return fail(KNN_EDEVICE, "pinned host allocation failed");
     const double stop = (double)p->delta * (double)n * (double)K;
-    const size_t merge_lds = (size_t)4 * cfg.C * 8;
+    const size_t merge_lds = (size_t)8 * cfg.C * 8;
     int dev = 0;
     KNN_HIP(hipGetDevice(&dev));
     int ncu = 256;
@@ -1131,7 +1141,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     // a multiple of 8: the join splits its grid into 8 contiguous point ranges
     const unsigned join_grid = (unsigned)round_up((int64_t)ncu * jpc, 8);
     // multiples of 8: sample and merge split their grids into 8 contiguous row ranges
-    const unsigned merge_grid = (unsigned)round_up(std::min<int64_t>(ceil_div(n, 4), (int64_t)ncu * 8), 8);
+    const unsigned merge_grid = (unsigned)round_up(std::min<int64_t>(ceil_div(n, 8), (int64_t)ncu * 8), 8);
     const unsigned sample_grid = (unsigned)round_up(std::min<int64_t>(ceil_div(n, 8), (int64_t)ncu * 8), 8);
     int iters = 0;
     double ms_sample = 0, ms_join = 0, ms_merge = 0;

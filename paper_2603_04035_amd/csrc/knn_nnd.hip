@@ -1140,9 +1140,16 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     if (jpc < 1) jpc = 1;
     // a multiple of 8: the join splits its grid into 8 contiguous point ranges
     const unsigned join_grid = (unsigned)round_up((int64_t)ncu * jpc, 8);
-    // multiples of 8: sample and merge split their grids into 8 contiguous row ranges
-    const unsigned merge_grid = (unsigned)round_up(std::min<int64_t>(ceil_div(n, 8), (int64_t)ncu * 8), 8);
-    const unsigned sample_grid = (unsigned)round_up(std::min<int64_t>(ceil_div(n, 8), (int64_t)ncu * 8), 8);
+    // grid-stride kernels get exactly the resident block count (a partial
+    // second round of blocks would run on an otherwise idle chip), rounded to
+    // a multiple of 8: they split their grids into 8 contiguous row ranges
+    int mpc = 0, spc = 0;
+    KNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&mpc, (const void*)nnd_merge_kernel, 256, merge_lds));
+    KNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&spc, (const void*)nnd_sample_kernel, 256, 0));
+    if (mpc < 1) mpc = 1;
+    if (spc < 1) spc = 1;
+    const unsigned merge_grid = (unsigned)round_up(std::min<int64_t>(ceil_div(n, 8), (int64_t)ncu * mpc), 8);
+    const unsigned sample_grid = (unsigned)round_up(std::min<int64_t>(ceil_div(n, 8), (int64_t)ncu * spc), 8);
     int iters = 0;
     double ms_sample = 0, ms_join = 0, ms_merge = 0;
     uint64_t gathered = 0;

@@ -272,6 +272,36 @@ __device__ inline float dist_g16(const void* A, int64_t a_off, const void* B, in
     return wave_sum16(s);
 }
 
+// Squared distance of two rows computed by one lane: coordinates in order,
+// FP32 fused multiply-adds on the stored values.  With `vec` (base and both
+// row offsets 16-byte aligned) the rows are read as 16-byte vectors.
+template <int DT>
+__device__ inline float lane_dist2(const void* A, int64_t a_off, const void* B, int64_t b_off, int d, bool vec)
+{
+    using T = typename elem<DT>::T;
+    constexpr int V = 16 / (int)sizeof(T);
+    float s = 0.0f;
+    int t = 0;
+    if (vec) {
+        for (; t + V <= d; t += V) {
+            const uint4 ua = *(const uint4*)((const T*)A + a_off + t);
+            const uint4 ub = *(const uint4*)((const T*)B + b_off + t);
+            const T* pa = (const T*)&ua;
+            const T* pb = (const T*)&ub;
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const float x = elem<DT>::ld(pa, e) - elem<DT>::ld(pb, e);
+                s = fmaf(x, x, s);
+            }
+        }
+    }
+    for (; t < d; ++t) {
+        const float x = elem<DT>::ld(A, a_off + t) - elem<DT>::ld(B, b_off + t);
+        s = fmaf(x, x, s);
+    }
+    return s;
+}
+
 // ------------------------------------------------------------------ host
 
 void set_error(const std::string& msg);
@@ -285,7 +315,6 @@ knn_status fail(knn_status s, const std::string& msg);
                                                 hipGetErrorString(e_));                \
     } while (0)
 
-// Scratch allocations for one call, released (stream-ordered) on scope exit.
 // Scratch for one entry-point call.  Requests are carved (256-byte aligned)
 // from a grow-only arena that the library keeps per device, so steady-state
 // calls neither allocate nor free device memory.  The arena is held by one

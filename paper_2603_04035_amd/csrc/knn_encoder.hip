@@ -631,7 +631,8 @@ __global__ __launch_bounds__(256) void xproj_kernel(const void* __restrict__ X, 
 }
 
 // One wave per point: window candidates from every order (lane = (p, side,
-// offset)), repeats and self dropped, canonical FP32 distances, best K sorted.
+// offset)), repeats and self dropped, FP32 distances (one candidate per
+// lane), best K sorted.
 template <int DT>
 __global__ __launch_bounds__(256) void proj_seed_kernel(const void* __restrict__ X, int64_t ld, int d, int64_t n,
                                                         const uint32_t* __restrict__ order,
@@ -674,15 +675,9 @@ __global__ __launch_bounds__(256) void proj_seed_kernel(const void* __restrict__
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     const uint32_t mine = lane < cnt ? sc[wv][lane] : 0xFFFFFFFFu;
-    float dd = 0.0f;
-    for (int base = 0; base < cnt; base += 4) {
-        const int ci = base + (lane >> 4);
-        const uint32_t cj = shfl_u32(mine, ci);
-        const bool act = ci < cnt;
-        const float v = dist_g16<DT>(X, i * ld, X, (int64_t)(act ? cj : 0) * ld, d, act);
-        const float got = shfl_f32(v, ((lane - base) & 3) * 16);
-        if (lane >= base && lane < base + 4) dd = got;
-    }
+    // lane c computes candidate c's distance over the whole row
+    const bool vec = ((uintptr_t)X % 16 == 0) && ((ld * (int64_t)sizeof(typename elem<DT>::T)) % 16 == 0);
+    const float dd = lane < cnt ? lane_dist2<DT>(X, i * ld, X, (int64_t)mine * ld, d, vec) : 0.0f;
     uint64_t key = lane < cnt ? make_key(dd, mine) : kEmptyCand;
     key = seg_sort<64>(key);
     if (lane < K) {

@@ -159,18 +159,12 @@ __global__ __launch_bounds__(256) void nnd_init_kernel(
             if (lane < want && !ok) id = 0xFFFFFFFFu;
         }
     }
-    // 3. distances for entries without one (4 rows per pass, 16 lanes each)
+    // 3. distances for entries without one (lane e computes entry e's)
     const int cnt = have > want ? have : want;
-    float mine = gd;
-    for (int base = 0; base < cnt; base += 4) {
-        const int ci = base + (lane >> 4);
-        const uint32_t cj = shfl_u32(id, ci);
-        const bool need = shfl_u32(hasd ? 1u : 0u, ci) == 0;
-        const bool act = ci < cnt && need && cj != 0xFFFFFFFFu;
-        const float v = dist_g16<DT>(Xs, row * ldp, Xs, (int64_t)cj * ldp, d, act);
-        const float got = shfl_f32(v, ((lane - base) & 3) * 16);
-        if (lane >= base && lane < base + 4 && !hasd) mine = got;
-    }
+    const bool need = lane < cnt && !hasd && id != 0xFFFFFFFFu;
+    const float mine = need ? lane_dist2<DT>(Xs, row * ldp, Xs, (int64_t)id * ldp, d,
+                                             (ldp * (int64_t)sizeof(typename elem<DT>::T)) % 16 == 0)
+                            : gd;
     // 4. sort by (d2, old after new, id) -- the merge's list order -- and keep
     //    the first K; the old flag rides in the index word
     const bool live = lane < cnt && id != 0xFFFFFFFFu;

@@ -491,12 +491,14 @@ __device__ inline uint4 load_piece(const uint8_t* r, int p, int np, bool valid, 
 
 // Candidates of member m from one 32-row block's accumulator column: rows
 // 32 blk + 8 (e / 4) + 4 h + e % 4 of tile entry e, branch-free.  Member m
-// pairs with rows i < lim (L if m is new, nn if it is old), i != m.
-__device__ inline void scan_block(const f32x16& g, int blk, int h4, int m, int lim, float nm,
+// pairs with rows i < lim (L if m is new, nn if it is old), i != m.  Groups
+// of 8 rows at or past rows_end (the same for the whole wave) are skipped.
+__device__ inline void scan_block(const f32x16& g, int blk, int h4, int m, int lim, int rows_end, float nm,
                                   const float* nrm, uint32_t (&best)[kJMax])
 {
 #pragma unroll
     for (int e4 = 0; e4 < 4; ++e4) {
+        if (32 * blk + 8 * e4 >= rows_end) break;
         const int i0 = 32 * blk + 8 * e4 + h4;
         const f32x4 ni = *(const f32x4*)(nrm + i0);
 #pragma unroll
@@ -595,8 +597,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
             for (int q = 0; q < kJMax; ++q) best[q] = kNoSel;
             const float nm = nrm[m];
             const int lim = m < nn ? L : nn;
-            scan_block(at, 0, h4, m, lim, nm, nrm, best);
-            if (lower) scan_block(ab, 1, h4, m, lim, nm, nrm, best);
+            // a pass whose members are all old needs only the first nn rows
+            const int rows_end = 32 * cb >= nn ? nn : L;
+            scan_block(at, 0, h4, m, lim, rows_end, nm, nrm, best);
+            if (lower) scan_block(ab, 1, h4, m, lim, rows_end, nm, nrm, best);
             uint32_t recv[kJMax];
 #pragma unroll
             for (int q = 0; q < kJMax; ++q) recv[q] = xor_u32(best[q], 32);
@@ -693,11 +697,13 @@ __device__ inline void join_f32_point(const float* __restrict__ Xs, int ldp, int
         for (int s = 0; s < kJMax; ++s) best[s] = kNoSel;
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
-            const int a = ag + 8 * i;
-            float d2 = na[i] + nb - 2.0f * acc[i][q];
-            d2 = d2 > 0.0f ? d2 : 0.0f;
-            const bool ok = a < lim && a != b;
-            sel_insert(best, ok ? ((__float_as_uint(d2) & ~63u) | (uint32_t)a) : kNoSel);
+            if (i < NI || q < NI) {   // old rows pair only with new columns
+                const int a = ag + 8 * i;
+                float d2 = na[i] + nb - 2.0f * acc[i][q];
+                d2 = d2 > 0.0f ? d2 : 0.0f;
+                const bool ok = a < lim && a != b;
+                sel_insert(best, ok ? ((__float_as_uint(d2) & ~63u) | (uint32_t)a) : kNoSel);
+            }
         }
 #pragma unroll
         for (int o = 8; o <= 32; o <<= 1) {

@@ -227,6 +227,11 @@ def exact_path(X, k, reps=3):
     return out
 
 
+def progress(msg):
+    """One line per finished phase on stderr (the JSON result goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def run_form(X, k, form, steps, warmup, rows, encoder=None, Xnp=None):
     import torch
     import paper_2603_04035_amd as knn
@@ -238,6 +243,7 @@ def run_form(X, k, form, steps, warmup, rows, encoder=None, Xnp=None):
     for w in range(warmup):
         knn.nndescent_build(X, k, seed=1000 + w, **p)
     torch.cuda.synchronize()
+    progress(f"{form}: {warmup} warmup build(s) done")
     stats, walls = [], []
     t0 = time.perf_counter()
     for s in range(steps):
@@ -245,6 +251,7 @@ def run_form(X, k, form, steps, warmup, rows, encoder=None, Xnp=None):
         G, D, st = knn.nndescent_build(X, k, seed=s, **p)   # blocking: returns after the build
         walls.append(time.perf_counter() - ts)
         stats.append(st)
+        progress(f"{form}: step {s + 1}/{steps} {1000.0 * walls[-1]:.2f} ms")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n, d = X.shape
@@ -256,6 +263,7 @@ def run_form(X, k, form, steps, warmup, rows, encoder=None, Xnp=None):
     err = None
     if p["precision"] == "bf16" and Xnp is not None:
         err = distance_error(X, Xnp, k, p, rows[:2000])
+    progress(f"{form}: recall {recall:.5f}")
     import numpy as np
     return {"value": round(n * steps / wall, 1), "ms_per_step": round(1000.0 * wall / steps, 3),
             "ms_per_step_std": round(1000.0 * float(np.std(walls)), 3),
@@ -323,6 +331,7 @@ def main():
     encoder = None
     if "bf16-learned" in forms:
         encoder, training = train_encoder(args.config)
+        progress(f"encoder trained in {training['train_s']} s")
     for f in forms:
         results[f] = run_form(X, k, f, args.steps, args.warmup, rows, encoder, Xnp)
     head = "bf16-learned" if "bf16-learned" in results else forms[0]
@@ -334,6 +343,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         cpu = cpu_baseline(Xnp, k, "fp32", min(args.cpu_sample, n))
+        progress(f"cpu baseline {cpu['value']:.0f} points/s")
 
     out = {
         "metric": "kNN graph build points/sec at recall@15>=0.98 (NNDescent)",

@@ -95,32 +95,105 @@ struct TileCfg {
     using E = float;
     static constexpr int KC = 32;    // elements per K chunk (128 bytes per row)
     static constexpr int LROW = 36;  // LDS row stride in elements (144 bytes)
+    static constexpr int AMAX = 64;  // query rows stay in LDS when ldp <= AMAX
+    static constexpr int AROW = 68;  // their LDS row stride
 };
 template <>
 struct TileCfg<true> {
     using E = uint16_t;
     static constexpr int KC = 64;
     static constexpr int LROW = 72;
+    static constexpr int AMAX = 64;
+    static constexpr int AROW = 72;
 };
 
 // Output D of a 32x32 MFMA: lane l, accumulator v holds row
 // 8*(v/4) + 4*(l/32) + v%4 and column l%32 of the 32x32 block.
 __device__ inline int mfma_row(int v, int half) { return 8 * (v >> 2) + 4 * half + (v & 3); }
 
-template <bool BF>
+// Adds the keys of the lanes in `m` (lanes 0..31 for the list held by lanes
+// 0..31, lanes 32..63 for the one held by lanes 32..63) to the two sorted
+// 32-key lists, keeping each list's 32 smallest.  A few keys are inserted one
+// at a time per half: lanes whose entry exceeds the key move up one place and
+// the first of them takes the key.  Many keys are sorted and merged by
+// bitonic networks.  Both routes give the same list.
+__device__ inline uint64_t list_add(uint64_t list, uint64_t key, uint64_t m, int lane)
+{
+    uint32_t m0 = (uint32_t)m, m1 = (uint32_t)(m >> 32);
+    if (__builtin_popcount(m0) > 3 || __builtin_popcount(m1) > 3) {
+        const uint64_t ck = seg_sort<32>(key);
+        return seg_merge_sorted<32>(list, ck);
+    }
+    const bool hi = lane >= 32;
+    const int from = (lane & 31) == 0 ? lane : lane - 1;
+    while (m0 | m1) {
+        const uint64_t x0 = m0 ? bcast_u64(key, __builtin_ctz(m0)) : kEmptyCand;
+        const uint64_t x1 = m1 ? bcast_u64(key, 32 + __builtin_ctz(m1)) : kEmptyCand;
+        const uint64_t x = hi ? x1 : x0;
+        const bool gt = list > x;
+        const uint64_t gm = ballot(gt);
+        // the lane below (inside the same half) also moves up
+        const bool pgt = (lane & 31) != 0 && ((gm >> ((lane - 1) & 63)) & 1ull);
+        const uint64_t prev = shfl_u64(list, from);
+        list = gt ? (pgt ? prev : x) : list;
+        m0 &= m0 - 1u;
+        m1 &= m1 - 1u;
+    }
+    return list;
+}
+
+// Rows of one pipeline step, loaded into registers: this thread's four
+// 16-byte pieces of reference row r (and of query row r when the query rows
+// stream) for chunk k0, and the reference norm of tile row tid at a tile's
+// first chunk.
+template <typename E, bool ARES>
+__device__ inline void load_step(const E* Qe, const E* Re, int64_t qrow, int64_t rt, int64_t rend, int r,
+                                 int col, int k0, int ldp, const float* rn, int tid, uint4& b0, uint4& b1,
+                                 uint4& b2, uint4& b3, uint4& a0, uint4& a1, uint4& a2, uint4& a3, float& rnv)
+{
+    const int64_t rr = rt + r < rend ? rt + r : rend - 1;
+    const uint4* rsrc = (const uint4*)(Re + rr * ldp + k0 + col);
+    b0 = rsrc[0];
+    b1 = rsrc[1];
+    b2 = rsrc[2];
+    b3 = rsrc[3];
+    if (!ARES) {
+        const uint4* qsrc = (const uint4*)(Qe + qrow * ldp + k0 + col);
+        a0 = qsrc[0];
+        a1 = qsrc[1];
+        a2 = qsrc[2];
+        a3 = qsrc[3];
+    }
+    rnv = 0.0f;
+    if (k0 == 0 && tid < kTileRows && rt + tid < rend) rnv = rn[rt + tid];
+}
+
+// One workgroup (4 waves) owns 128 query rows and streams the reference
+// rows [rbeg, rend) of its split in 128-row tiles, K chunk by K chunk.  The
+// sequence of (tile, chunk) steps is software-pipelined: the global loads of
+// step t+1 are issued into registers before step t's MFMAs and epilogue run
+// and are written to LDS at the top of step t+1, so HBM/L2 latency overlaps
+// the arithmetic.  With ARES (row length ldp <= AMAX) the query rows are
+// loaded into LDS once and only reference rows stream.  Wave w computes
+// query rows 32w..32w+31 against the tile's 128 references (four 32x32
+// MFMA blocks).
+template <bool BF, bool ARES>
 __global__ __launch_bounds__(256, 2) void exact_tile_kernel(
     const void* __restrict__ Qs, const float* __restrict__ qn, int64_t nq,
     const void* __restrict__ Rs, const float* __restrict__ rn, int64_t nr, int ldp,
     const int32_t* __restrict__ q_self, int self_mode, int kp, int64_t split_len, int S,
-    uint64_t* __restrict__ part)
+    const unsigned* __restrict__ rmax_bits, uint64_t* __restrict__ part)
 {
     using C = TileCfg<BF>;
     using E = typename C::E;
     constexpr int KC = C::KC, LROW = C::LROW, PER = KC / 2;
-    __shared__ __attribute__((aligned(16))) E As[kTileRows * LROW];
+    constexpr int AROW = ARES ? C::AROW : LROW;
+    constexpr int NV = PER * (int)sizeof(E) / 16;   // 16-byte loads per thread and chunk
+    __shared__ __attribute__((aligned(16))) E As[kTileRows * AROW];
     __shared__ __attribute__((aligned(16))) E Bs[kTileRows * LROW];
+    __shared__ float srn[kTileRows];
     __shared__ float sqn[kTileRows];
-    __shared__ int64_t sself[kTileRows];
+    __shared__ int32_t sself[kTileRows];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, h = lane >> 5, c = lane & 31;
     const int64_t q0 = (int64_t)blockIdx.x * kTileRows;
@@ -129,23 +202,46 @@ __global__ __launch_bounds__(256, 2) void exact_tile_kernel(
     const int64_t rend = rbeg + split_len < nr ? rbeg + split_len : nr;
 
     if (tid < kTileRows) {
-        int64_t qr = q0 + tid;
+        const int64_t qr = q0 + tid;
         sqn[tid] = qr < nq ? qn[qr] : 0.0f;
-        int64_t sf = -1;
-        if (qr < nq) sf = self_mode == 1 ? qr : (self_mode == 2 ? (int64_t)q_self[qr] : -1);
-        sself[tid] = sf;
+        sself[tid] = qr >= nq ? -1 : (self_mode == 1 ? (int32_t)qr : (self_mode == 2 ? q_self[qr] : -1));
     }
-
+    // Per-row lists of this lane's 16 accumulator rows and their gates.
+    // A candidate enters a list when d2 = |q|^2 + |r|^2 - 2 q.r <= thr (the
+    // list's k'-th distance).  The gate tests the equivalent
+    // q.r - |r|^2/2 >= (|q|^2 - thr)/2 with two operations per element;
+    // lim is lowered by a slack that covers the FP32 rounding of both forms
+    // (8u (|q|^2 + thr + max|r|^2)), so every candidate the exact test
+    // accepts passes the gate, and the exact test decides.  Rows past nq
+    // get lim = +inf and never pass.
+    const float rmax = __uint_as_float(*rmax_bits);
     uint64_t list[16];
-    float thr[16];
+    float lim[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         list[v] = kEmptyList;
-        thr[v] = __builtin_inff();
+        lim[v] = q0 + w * 32 + mfma_row(v, h) < nq ? -__builtin_inff() : __builtin_inff();
     }
 
     const E* Qe = (const E*)Qs;
     const E* Re = (const E*)Rs;
+    const int r = tid >> 1, ph = tid & 1;              // staging: row r, half ph of the chunk
+    const int64_t qrow = q0 + r < nq ? q0 + r : nq - 1;
+    if (ARES) {
+        // whole query rows (ldp <= AMAX elements) into LDS once
+        const uint4* src = (const uint4*)(Qe + qrow * ldp + ph * (ldp / 2));
+        uint4* dst = (uint4*)(As + r * AROW + ph * (ldp / 2));
+        const int nv = ldp / 2 * (int)sizeof(E) / 16;
+        for (int i = 0; i < nv; ++i) dst[i] = src[i];
+    }
+
+    // prologue: the first step's rows (addresses are clamped to valid rows,
+    // so a load past the split's end is harmless)
+    static_assert(NV == 4, "four 16-byte pieces per thread and chunk");
+    uint4 nb0, nb1, nb2, nb3, na0 = {}, na1 = {}, na2 = {}, na3 = {};
+    float nrn;
+    load_step<E, ARES>(Qe, Re, qrow, rbeg, rend, r, ph * PER, 0, ldp, rn, tid, nb0, nb1, nb2, nb3, na0, na1,
+                       na2, na3, nrn);
     for (int64_t rt = rbeg; rt < rend; rt += kTileRows) {
         f32x16 acc[4];
 #pragma unroll
@@ -154,51 +250,52 @@ __global__ __launch_bounds__(256, 2) void exact_tile_kernel(
             for (int v = 0; v < 16; ++v) acc[b][v] = 0.0f;
 
         for (int k0 = 0; k0 < ldp; k0 += KC) {
-            __syncthreads();
+            __syncthreads();   // the previous step's LDS reads are done
             {
-                const int r = tid >> 1, part_h = tid & 1;
-                int64_t qr = q0 + r < nq ? q0 + r : nq - 1;
-                int64_t rr = rt + r < rend ? rt + r : rend - 1;
-                const uint4* qsrc = (const uint4*)(Qe + qr * ldp + k0 + part_h * PER);
-                const uint4* rsrc = (const uint4*)(Re + rr * ldp + k0 + part_h * PER);
-                uint4* adst = (uint4*)(As + r * LROW + part_h * PER);
-                uint4* bdst = (uint4*)(Bs + r * LROW + part_h * PER);
-                uint4 qa[4], rb[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    qa[i] = qsrc[i];
-                    rb[i] = rsrc[i];
+                uint4* bdst = (uint4*)(Bs + r * LROW + ph * PER);
+                bdst[0] = nb0;
+                bdst[1] = nb1;
+                bdst[2] = nb2;
+                bdst[3] = nb3;
+                if (!ARES) {
+                    uint4* adst = (uint4*)(As + r * LROW + ph * PER);
+                    adst[0] = na0;
+                    adst[1] = na1;
+                    adst[2] = na2;
+                    adst[3] = na3;
                 }
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    adst[i] = qa[i];
-                    bdst[i] = rb[i];
-                }
+                if (k0 == 0 && tid < kTileRows) srn[tid] = nrn;
             }
             __syncthreads();
+            // the next step's rows are in flight during this step's arithmetic
+            {
+                const bool last = k0 + KC >= ldp;
+                load_step<E, ARES>(Qe, Re, qrow, last ? rt + kTileRows : rt, rend, r, ph * PER,
+                                   last ? 0 : k0 + KC, ldp, rn, tid, nb0, nb1, nb2, nb3, na0, na1, na2, na3, nrn);
+            }
             // K permutation: half h of the wave supplies chunk columns
             // h*PER .. h*PER+PER-1, the same for A and B, so every column
             // enters the dot product exactly once.
-            const uint4* ap = (const uint4*)(As + (w * 32 + c) * LROW + h * PER);
-            uint4 a4[4];
+            const uint4* ap = (const uint4*)(As + (w * 32 + c) * AROW + (ARES ? k0 : 0) + h * PER);
+            uint4 a4[NV];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a4[i] = ap[i];
+            for (int i = 0; i < NV; ++i) a4[i] = ap[i];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const uint4* bp = (const uint4*)(Bs + (b * 32 + c) * LROW + h * PER);
-                uint4 b4[4];
+                uint4 b4[NV];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) b4[i] = bp[i];
+                for (int i = 0; i < NV; ++i) b4[i] = bp[i];
                 if constexpr (BF) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
+                    for (int i = 0; i < NV; ++i) {
                         bf16x8 av = __builtin_bit_cast(bf16x8, a4[i]);
                         bf16x8 bv = __builtin_bit_cast(bf16x8, b4[i]);
                         acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[b], 0, 0, 0);
                     }
                 } else {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
+                    for (int i = 0; i < NV; ++i) {
                         f32x4 av = __builtin_bit_cast(f32x4, a4[i]);
                         f32x4 bv = __builtin_bit_cast(f32x4, b4[i]);
 #pragma unroll
@@ -211,22 +308,30 @@ __global__ __launch_bounds__(256, 2) void exact_tile_kernel(
 
         // epilogue: distances, threshold gate, wave-bitonic list merges
         for (int blk = 0; blk < 4; ++blk) {
-            f32x16 cur = blk == 0 ? acc[0] : (blk == 1 ? acc[1] : (blk == 2 ? acc[2] : acc[3]));
-            const int64_t j = rt + blk * 32 + c;
-            const bool jv = j < rend;
-            const float rnj = jv ? rn[j] : 0.0f;
+            const f32x16 cur = blk == 0 ? acc[0] : (blk == 1 ? acc[1] : (blk == 2 ? acc[2] : acc[3]));
+            const float rnj = srn[blk * 32 + c];
+            const float hr = 0.5f * rnj;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                const int lr = w * 32 + mfma_row(v, h);
-                float d2 = sqn[lr] + rnj - 2.0f * cur[v];
-                d2 = d2 > 0.0f ? d2 : 0.0f;
-                const bool ok = jv && (q0 + lr < nq) && (j != sself[lr]) && d2 <= thr[v];
-                if (ballot(ok)) {
-                    uint64_t ck = ok ? make_key(d2, (uint32_t)j) : kEmptyCand;
-                    ck = seg_sort<32>(ck);
-                    list[v] = seg_merge_sorted<32>(list[v], ck);
+                if (ballot(cur[v] - hr >= lim[v])) {
+                    // exact test; the list's current k'-th distance is the threshold
+                    const int lr = w * 32 + mfma_row(v, h);
+                    const float sq = sqn[lr];
+                    const int64_t j = rt + blk * 32 + c;
                     const uint64_t t0 = bcast_u64(list[v], kp - 1), t1 = bcast_u64(list[v], 32 + kp - 1);
-                    thr[v] = key_d2(h ? t1 : t0);
+                    const float thr = key_d2(h ? t1 : t0);
+                    float d2 = fmaf(-2.0f, cur[v], sq + rnj);
+                    d2 = d2 > 0.0f ? d2 : 0.0f;
+                    const bool ok = j < rend && (int32_t)j != sself[lr] && d2 <= thr && lim[v] < __builtin_inff();
+                    const uint64_t okm = ballot(ok);
+                    if (okm) {
+                        const uint64_t ck = ok ? make_key(d2, (uint32_t)j) : kEmptyCand;
+                        list[v] = list_add(list[v], ck, okm, lane);
+                        const uint64_t u0 = bcast_u64(list[v], kp - 1), u1 = bcast_u64(list[v], 32 + kp - 1);
+                        const float t = key_d2(h ? u1 : u0);
+                        const float nl = 0.5f * (sq - t) - 4.76837158e-07f * (sq + t + rmax);   // 8u = 2^-21
+                        lim[v] = lim[v] < __builtin_inff() ? nl : lim[v];
+                    }
                 }
             }
         }
@@ -440,12 +545,18 @@ static knn_status exact_impl(const knn_matrix& Q, const knn_matrix& R, bool same
     if (r != KNN_OK) return r;
 
     dim3 tgrid((unsigned)nblk, (unsigned)S);
-    if (bf)
-        exact_tile_kernel<true><<<tgrid, 256, 0, st>>>(Qs, qn, Q.n, Rs, rn, R.n, ldp, q_self,
-                                                       self_mode, kp, split_len, S, part);
-    else
-        exact_tile_kernel<false><<<tgrid, 256, 0, st>>>(Qs, qn, Q.n, Rs, rn, R.n, ldp, q_self,
-                                                        self_mode, kp, split_len, S, part);
+    const bool ares = ldp <= (bf ? TileCfg<true>::AMAX : TileCfg<false>::AMAX);
+#define KNN_TILE(BFV, AR)                                                                        \
+    exact_tile_kernel<BFV, AR><<<tgrid, 256, 0, st>>>(Qs, qn, Q.n, Rs, rn, R.n, ldp, q_self,     \
+                                                      self_mode, kp, split_len, S, small, part)
+    if (bf) {
+        if (ares) KNN_TILE(true, true);
+        else KNN_TILE(true, false);
+    } else {
+        if (ares) KNN_TILE(false, true);
+        else KNN_TILE(false, false);
+    }
+#undef KNN_TILE
     KNN_HIP(hipGetLastError());
 
     // GEMM error bound (FP32): (d + 3) u (|q| + max|r|)^2 with u = 2^-24;

@@ -178,34 +178,6 @@ __device__ inline uint64_t seg_merge_sorted(uint64_t list, uint64_t cand_sorted)
     return seg_bitonic_merge<W>(umin64(list, rev));
 }
 
-// Ascending bitonic sort of 128 keys held two per lane: element e = r * 64 + lane.
-__device__ inline void sort128(uint64_t& k0, uint64_t& k1)
-{
-    const int lane = lane_id();
-#pragma unroll
-    for (int k = 2; k <= 128; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            if (j == 64) {
-                // partner is the other register of the same lane; direction by e & k
-                // (k = 128 here: whole array ascending)
-                uint64_t mn = umin64(k0, k1), mx = umax64(k0, k1);
-                k0 = mn;
-                k1 = mx;
-            } else {
-                uint64_t o0 = shfl_xor_u64(k0, j);
-                uint64_t o1 = shfl_xor_u64(k1, j);
-                bool lower = (lane & j) == 0;
-                // element index e = r*64 + lane; ascending iff (e & k) == 0
-                bool up0 = (k == 128) ? true : ((lane & k) == 0);
-                bool up1 = (k == 128) ? true : (((64 + lane) & k) == 0);
-                k0 = (lower == up0) ? umin64(k0, o0) : umax64(k0, o0);
-                k1 = (lower == up1) ? umin64(k1, o1) : umax64(k1, o1);
-            }
-        }
-    }
-}
-
 __device__ inline uint64_t ballot(bool p) { return __ballot(p); }
 __device__ inline int popc64(uint64_t m) { return __popcll(m); }
 // number of set bits of m in lanes below this one

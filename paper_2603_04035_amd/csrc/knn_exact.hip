@@ -306,14 +306,22 @@ __global__ __launch_bounds__(256, 2) void exact_tile_kernel(
             }
         }
 
-        // epilogue: distances, threshold gate, wave-bitonic list merges
+        // epilogue: distances, threshold gate, list updates
         for (int blk = 0; blk < 4; ++blk) {
             const f32x16 cur = blk == 0 ? acc[0] : (blk == 1 ? acc[1] : (blk == 2 ? acc[2] : acc[3]));
             const float rnj = srn[blk * 32 + c];
             const float hr = 0.5f * rnj;
+            // gate all 16 rows first: one branch per block when nothing passes
+            uint64_t gm[16], any = 0;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                if (ballot(cur[v] - hr >= lim[v])) {
+                gm[v] = ballot(cur[v] - hr >= lim[v]);
+                any |= gm[v];
+            }
+            if (!any) continue;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                if (gm[v]) {
                     // exact test; the list's current k'-th distance is the threshold
                     const int lr = w * 32 + mfma_row(v, h);
                     const float sq = sqn[lr];
@@ -346,7 +354,7 @@ __global__ __launch_bounds__(256, 2) void exact_tile_kernel(
 
 // ------------------------------------------------------------ merge/rerank
 
-// One wave per query row.  Merges the S split lists (<= 4 x 32 keys), keeps
+// One wave per query row.  Merges the S split lists (S x 32 keys), keeps
 // the best kp by GEMM distance, re-ranks them with the canonical FP32
 // direct-difference distance on the original inputs and writes the best k.
 template <int DT>
@@ -360,16 +368,17 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= nq) return;
-    uint64_t k0 = kEmptyCand, k1 = kEmptyCand;
+    // split lists (each sorted, 32 keys): even splits merge in lanes 0..31,
+    // odd ones in lanes 32..63, keeping each half's 32 smallest; the two
+    // halves then form one ascending 64-key sequence
     const int sp = lane >> 5;
-    if (S <= 2) {
-        if (sp < S) k0 = part[(row * S + sp) * kListW + (lane & 31)];
-        k0 = seg_sort<64>(k0);
-    } else {
-        k0 = part[(row * S + sp) * kListW + (lane & 31)];
-        if (sp + 2 < S) k1 = part[(row * S + sp + 2) * kListW + (lane & 31)];
-        sort128(k0, k1);
+    uint64_t acc = sp < S ? part[(row * S + sp) * kListW + (lane & 31)] : kEmptyCand;
+    for (int b = 2; b < S; b += 2) {
+        const uint64_t nk = b + sp < S ? part[(row * S + b + sp) * kListW + (lane & 31)] : kEmptyCand;
+        acc = seg_merge_sorted<32>(acc, nk);
     }
+    const uint64_t rv = shfl_xor_u64(acc, 31);
+    const uint64_t k0 = seg_bitonic_merge<64>(sp ? rv : acc);
     const uint64_t ck = lane < kp ? k0 : kEmptyCand;
     const bool cvalid = lane < kp && key_valid(ck);
     const int nvalid = popc64(ballot(cvalid));
@@ -532,6 +541,8 @@ static knn_status exact_impl(const knn_matrix& Q, const knn_matrix& R, bool same
         if (r != KNN_OK) return r;
     }
 
+    // Reference splits: enough workgroups to fill the chip (about 2048),
+    // at most 4; every split starts from empty lists, which costs merges.
     const int64_t nblk = ceil_div(Q.n, kTileRows);
     int S = (int)ceil_div(2048, nblk);
     S = S < 1 ? 1 : (S > 4 ? 4 : S);

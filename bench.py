@@ -122,10 +122,11 @@ def cpu_baseline(Xnp, k, form, sample_n):
                       f"{dt:.1f} s"}
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summaries (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings),
-    or None when no summary covers it or the kernel source changed since."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` (a CONFIGS key) from the
+    committed rocprofv3 counter summaries (FETCH_SIZE and WRITE_SIZE scaled
+    by a plain copy's readings), or None when no summary covers that kernel
+    and workload or the kernel source changed since."""
     import glob
     import hashlib
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
@@ -135,7 +136,7 @@ def measured_traffic(kernel):
                 rec = json.loads(block)
             except ValueError:
                 continue
-            if rec.get("kernel") != kernel:
+            if rec.get("kernel") != kernel or rec.get("workload") != workload:
                 continue
             src = os.path.join(ROOT, rec["source"])
             if not os.path.exists(src):
@@ -165,7 +166,7 @@ def copy_bandwidth(mib: int = 1024, reps: int = 5):
     return round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
 
 
-def join_roofline(stats, n, d, p, kernel):
+def join_roofline(stats, n, d, p, kernel, workload):
     """Local-join roofline: algorithmic bytes per launch / HIP-event time per launch."""
     import numpy as np
     K = stats[-1]["build_k"]
@@ -178,7 +179,7 @@ def join_roofline(stats, n, d, p, kernel):
     alg_bytes = gathered_rows * (d * rb + 8) + list_bytes + 8 * emitted
     join_ms = sum(st["ms_join"] for st in stats)
     achieved = alg_bytes / (join_ms * 1e-3) / 1e9
-    traffic, source = measured_traffic(kernel)
+    traffic, source = measured_traffic(kernel, workload)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": source,
             "kernel": kernel,
@@ -232,7 +233,7 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_form(X, k, form, steps, warmup, rows, encoder=None, Xnp=None):
+def run_form(X, k, form, steps, warmup, rows, config, encoder=None, Xnp=None):
     import torch
     import paper_2603_04035_amd as knn
     p = dict(FORMS[form])
@@ -274,7 +275,7 @@ def run_form(X, k, form, steps, warmup, rows, encoder=None, Xnp=None):
                              ("ms_init", "ms_sample", "ms_join", "ms_merge", "ms_final", "ms_total")},
             "per_iter": {"updates": last["updates"], "offers": last["emitted"],
                          "ms_join": [round(x, 3) for x in last["ms_join_iter"]]},
-            "roofline": join_roofline(stats, n, d, p, kern)}
+            "roofline": join_roofline(stats, n, d, p, kern, config)}
 
 
 def main():
@@ -333,7 +334,7 @@ def main():
         encoder, training = train_encoder(args.config)
         progress(f"encoder trained in {training['train_s']} s")
     for f in forms:
-        results[f] = run_form(X, k, f, args.steps, args.warmup, rows, encoder, Xnp)
+        results[f] = run_form(X, k, f, args.steps, args.warmup, rows, args.config, encoder, Xnp)
     head = "bf16-learned" if "bf16-learned" in results else forms[0]
     h = results[head]
 

@@ -353,15 +353,39 @@ __device__ inline int join_lists(int64_t v, const ListRaw& raw, const JoinCfg& c
 // distances it orders; ties go to the lower position.
 constexpr uint32_t kNoSel = 0xFFFFFFFFu;
 
-// Keep the kJMax smallest keys (ascending): one min/max exchange per slot.
+// Keep the kJMax smallest keys (ascending).  With the list sorted, the new
+// entry q is the median of old entries q-1, q and the key (the minimum of
+// old entry 0 and the key for q = 0): one independent min or 3-input median
+// (v_med3_u32) per slot.
+__device__ inline uint32_t med3_u32(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 __device__ inline void sel_insert(uint32_t (&best)[kJMax], uint32_t key)
 {
-#pragma unroll
-    for (int q = 0; q < kJMax; ++q) {
-        const uint32_t lo = min(best[q], key);
-        key = max(best[q], key);
-        best[q] = lo;
-    }
+    static_assert(kJMax == 4, "four slots");
+    const uint32_t b0 = best[0], b1 = best[1], b2 = best[2], b3 = best[3];
+    best[0] = min(b0, key);
+    best[1] = med3_u32(b0, b1, key);
+    best[2] = med3_u32(b1, b2, key);
+    best[3] = med3_u32(b2, b3, key);
+}
+
+// Keep the kJMax smallest of two ascending lists: min(a[q], b[3-q]) holds
+// them as a bitonic sequence, which two compare-exchange stages sort.
+__device__ inline void sel_merge(uint32_t (&best)[kJMax], const uint32_t (&other)[kJMax])
+{
+    static_assert(kJMax == 4, "four slots");
+    const uint32_t m0 = min(best[0], other[3]), m1 = min(best[1], other[2]);
+    const uint32_t m2 = min(best[2], other[1]), m3 = min(best[3], other[0]);
+    const uint32_t p0 = min(m0, m2), p2 = max(m0, m2), p1 = min(m1, m3), p3 = max(m1, m3);
+    best[0] = min(p0, p1);
+    best[1] = max(p0, p1);
+    best[2] = min(p2, p3);
+    best[3] = max(p2, p3);
 }
 
 // Offers whose slot reads are in flight: a column pass issues them (key,
@@ -604,8 +628,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
             uint32_t recv[kJMax];
 #pragma unroll
             for (int q = 0; q < kJMax; ++q) recv[q] = xor_u32(best[q], 32);
-#pragma unroll
-            for (int q = 0; q < kJMax; ++q) sel_insert(best, recv[q]);
+            sel_merge(best, recv);
             emitted += offers_resolve(po);
             offers_issue(po, best, J, h, m < L, m < L ? thr[m] : 0.0f, ids, ids[m], cfg.C, salt, cand);
         }
@@ -710,8 +733,7 @@ __device__ inline void join_f32_point(const float* __restrict__ Xs, int ldp, int
             uint32_t recv[kJMax];
 #pragma unroll
             for (int s = 0; s < kJMax; ++s) recv[s] = xor_u32(best[s], o);
-#pragma unroll
-            for (int s = 0; s < kJMax; ++s) sel_insert(best, recv[s]);
+            sel_merge(best, recv);
         }
         // lane ag offers merged entry ag; the previous column's offer resolves first
         emitted += offer_resolve(po);

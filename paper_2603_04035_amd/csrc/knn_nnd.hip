@@ -916,10 +916,25 @@ __global__ __launch_bounds__(256) void nnd_merge_kernel(
         // sorted, which can reorder equal distances: re-sort if needed
         const uint64_t nxt = shfl_u64(cur, lane + 1 < 64 ? lane + 1 : lane);
         if (ballot(hl < 31 && cur > nxt)) cur = seg_sort<32>(cur);
-        for (int b0 = 0; ballot(b0 < nc); b0 += 32) {
-            uint64_t x = b0 + hl < nc ? sbuf[b0 + hl] : kEmptyCand;
-            x = seg_sort<32>(x);
-            cur = seg_merge_sorted<32>(cur, x);
+        if (!ballot(nc > 4)) {
+            // a few candidates: each is inserted into its half's sorted list;
+            // lanes whose entry exceeds it move up one place and the first
+            // of them takes it (the same 32 smallest as the bitonic route)
+            const int from = hl == 0 ? lane : lane - 1;
+            for (int i = 0; ballot(i < nc); ++i) {
+                const uint64_t x = i < nc ? sbuf[i] : kEmptyCand;
+                const bool gt = cur > x;
+                const uint64_t gm = ballot(gt);
+                const bool pgt = hl != 0 && ((gm >> ((lane - 1) & 63)) & 1ull);
+                const uint64_t prev = shfl_u64(cur, from);
+                cur = gt ? (pgt ? prev : x) : cur;
+            }
+        } else {
+            for (int b0 = 0; ballot(b0 < nc); b0 += 32) {
+                uint64_t x = b0 + hl < nc ? sbuf[b0 + hl] : kEmptyCand;
+                x = seg_sort<32>(x);
+                cur = seg_merge_sorted<32>(cur, x);
+            }
         }
         const uint32_t w = key_idx(cur);
         const uint32_t cidx = w & ~kWasOld;

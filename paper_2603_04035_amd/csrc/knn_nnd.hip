@@ -916,7 +916,7 @@ __global__ __launch_bounds__(256) void nnd_merge_kernel(
         // sorted, which can reorder equal distances: re-sort if needed
         const uint64_t nxt = shfl_u64(cur, lane + 1 < 64 ? lane + 1 : lane);
         if (ballot(hl < 31 && cur > nxt)) cur = seg_sort<32>(cur);
-        if (!ballot(nc > 4)) {
+        if (!ballot(nc > 8)) {
             // a few candidates: each is inserted into its half's sorted list;
             // lanes whose entry exceeds it move up one place and the first
             // of them takes it (the same 32 smallest as the bitonic route)

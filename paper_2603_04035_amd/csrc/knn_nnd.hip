@@ -267,11 +267,16 @@ struct JoinCfg {
 constexpr int kJMax = 4;         // largest supported join cap
 
 // Raw join-list entries of one lane: lanes 0..s-1 hold new_f(v), lanes
-// s..s+R-1 the reverse-new slots (key with the source id in the low word),
-// and likewise old_f(v) / reverse-old in `o`; ~0 marks an empty entry.
-// Loaded one point ahead of the join that consumes them.
+// s..s+R-1 the source ids of the reverse-new slots (the low word of the
+// slot key), and likewise old_f(v) / reverse-old in `o`; 0xFFFFFFFF marks an
+// empty entry (a -1 forward entry, or the low word of an empty slot, which
+// no source id reaches).  Loaded ahead of the join that consumes them.  Every
+// lane loads from an in-bounds address (lanes past s+R or K+R re-read a
+// slot, and a point past the range reads row 0) and join_lists masks the
+// lanes it does not use: one load per list with no branch, so a load still
+// in flight never forces a wait on the others.
 struct ListRaw {
-    uint64_t n, o;
+    uint32_t n, o;
 };
 
 __device__ inline ListRaw load_lists(int64_t v, bool valid, const JoinCfg& cfg,
@@ -281,22 +286,13 @@ __device__ inline ListRaw load_lists(int64_t v, bool valid, const JoinCfg& cfg,
                                      const unsigned long long* __restrict__ revold)
 {
     const int lane = threadIdx.x;
-    ListRaw r = {~0ull, ~0ull};
-    if (valid) {
-        if (lane < cfg.s) {
-            const int32_t x = newf[v * cfg.s + lane];
-            if (x >= 0) r.n = (uint64_t)(uint32_t)x;
-        } else if (lane < cfg.s + cfg.R) {
-            r.n = revnew[v * cfg.R + (lane - cfg.s)];
-        }
-        if (lane < cfg.K) {
-            const int32_t x = oldf[v * cfg.K + lane];
-            if (x >= 0) r.o = (uint64_t)(uint32_t)x;
-        } else if (lane < cfg.K + cfg.R) {
-            r.o = revold[v * cfg.R + (lane - cfg.K)];
-        }
-    }
-    return r;
+    const int64_t vv = valid ? v : 0;
+    const int rn = min(max(lane - cfg.s, 0), cfg.R - 1), ro = min(max(lane - cfg.K, 0), cfg.R - 1);
+    const uint32_t* pn = lane < cfg.s ? (const uint32_t*)(newf + vv * cfg.s + lane)
+                                      : (const uint32_t*)(revnew + vv * cfg.R + rn);
+    const uint32_t* po = lane < cfg.K ? (const uint32_t*)(oldf + vv * cfg.K + lane)
+                                      : (const uint32_t*)(revold + vv * cfg.R + ro);
+    return {*pn, *po};
 }
 
 // Per-point join lists from the raw entries.  The reverse slots are reset
@@ -313,8 +309,8 @@ __device__ inline int join_lists(int64_t v, const ListRaw& raw, const JoinCfg& c
     const int lane = threadIdx.x;
     if (lane >= cfg.s && lane < cfg.s + cfg.R) revnew[v * cfg.R + (lane - cfg.s)] = ~0ull;
     if (lane >= cfg.K && lane < cfg.K + cfg.R) revold[v * cfg.R + (lane - cfg.K)] = ~0ull;
-    const uint32_t nid = raw.n == ~0ull ? 0xFFFFFFFFu : (uint32_t)raw.n;
-    const uint32_t oid = raw.o == ~0ull ? 0xFFFFFFFFu : (uint32_t)raw.o;
+    const uint32_t nid = lane < cfg.s + cfg.R ? raw.n : 0xFFFFFFFFu;
+    const uint32_t oid = lane < cfg.K + cfg.R ? raw.o : 0xFFFFFFFFu;
     sh[lane] = nid;
     sh[64 + lane] = oid;
     __syncthreads();
@@ -559,12 +555,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     po.p[0] = po.p[1] = nullptr;
     int64_t v = lo + (int64_t)(blockIdx.x >> 3);
     ListRaw cur = load_lists(v, v < hi, cfg, newf, revnew, oldf, revold);
+    ListRaw nxt = load_lists(v + gsz, v + gsz < hi, cfg, newf, revnew, oldf, revold);
     for (; v < hi; v += gsz) {
+        // lists run two points ahead: the load issued here overlaps this
+        // point's list dedup and the rest of its join
+        const ListRaw nx2 = load_lists(v + 2 * gsz, v + 2 * gsz < hi, cfg, newf, revnew, oldf, revold);
         int L = 0;
         const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cur, cfg, revnew, revold, sh, ids, L));
         L = __builtin_amdgcn_readfirstlane(L);
-        // the next point's lists are in flight while this one is joined
-        cur = load_lists(v + gsz, v + gsz < hi, cfg, newf, revnew, oldf, revold);
+        cur = nxt;
+        nxt = nx2;
         __syncthreads();
         if (nn == 0 || L < 2) continue;
         if (lane < L) {
@@ -764,11 +764,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     po.p = nullptr;
     int64_t v = lo + (int64_t)(blockIdx.x >> 3);
     ListRaw cur = load_lists(v, v < hi, cfg, newf, revnew, oldf, revold);
+    ListRaw nxt = load_lists(v + gsz, v + gsz < hi, cfg, newf, revnew, oldf, revold);
     for (; v < hi; v += gsz) {
+        const ListRaw nx2 = load_lists(v + 2 * gsz, v + 2 * gsz < hi, cfg, newf, revnew, oldf, revold);
         int L = 0;
         const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cur, cfg, revnew, revold, sh, ids, L));
         L = __builtin_amdgcn_readfirstlane(L);
-        cur = load_lists(v + gsz, v + gsz < hi, cfg, newf, revnew, oldf, revold);
+        cur = nxt;
+        nxt = nx2;
         __syncthreads();
         if (nn == 0 || L < 2) continue;
         if (lane < L) {

@@ -492,21 +492,24 @@ __device__ inline f32x16 gram_step(const uint4& a, const uint4& b, f32x16 acc)
                                                     acc, 0, 0, 0);
 }
 
-// Piece p of a row (r = row base + 16h bytes), branch-free: the load always
-// reads inside the row (p clamped, absent rows point at a listed row) and the
-// value is zeroed for an absent row or past the data; the trailing norm /
-// worst-distance words are cleared.
-__device__ inline uint4 load_piece(const uint8_t* r, int p, int np, bool valid, int64_t rowbytes, int h)
+// Piece p of a row (r = row base + 16h bytes): the load always reads inside
+// the row (p clamped; an absent row points at a listed row).  Values of
+// absent rows and of pieces past the data only reach Gram entries that the
+// selection and the offers never use, so they are not cleared; the
+// trailing norm / worst-distance words are (clear_tail), after all of a
+// chunk's loads are issued.
+__device__ inline uint4 load_piece(const uint8_t* r, int p, int np)
 {
     const int pp = p < np ? p : np - 1;
-    uint4 x = *(const uint4*)(r + 32 * (int64_t)pp);
-    const bool keep = valid && p < np;
-    const bool tail = 32 * (int64_t)p + 16 * h + 16 == rowbytes;
-    x.x = keep ? x.x : 0u;
-    x.y = keep ? x.y : 0u;
-    x.z = keep && !tail ? x.z : 0u;
-    x.w = keep && !tail ? x.w : 0u;
-    return x;
+    return *(const uint4*)(r + 32 * (int64_t)pp);
+}
+
+__device__ inline void clear_tail(uint4& x, int p, int64_t rowbytes, int h)
+{
+    if (32 * (int64_t)p + 16 * h + 16 == rowbytes) {
+        x.z = 0u;
+        x.w = 0u;
+    }
 }
 
 // Candidates of member m from one 32-row block's accumulator column: rows
@@ -555,16 +558,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     po.p[0] = po.p[1] = nullptr;
     int64_t v = lo + (int64_t)(blockIdx.x >> 3);
     ListRaw cur = load_lists(v, v < hi, cfg, newf, revnew, oldf, revold);
-    ListRaw nxt = load_lists(v + gsz, v + gsz < hi, cfg, newf, revnew, oldf, revold);
     for (; v < hi; v += gsz) {
-        // lists run two points ahead: the load issued here overlaps this
-        // point's list dedup and the rest of its join
-        const ListRaw nx2 = load_lists(v + 2 * gsz, v + 2 * gsz < hi, cfg, newf, revnew, oldf, revold);
         int L = 0;
         const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cur, cfg, revnew, revold, sh, ids, L));
         L = __builtin_amdgcn_readfirstlane(L);
-        cur = nxt;
-        nxt = nx2;
+        // the next point's lists are in flight while this one is joined
+        cur = load_lists(v + gsz, v + gsz < hi, cfg, newf, revnew, oldf, revold);
         __syncthreads();
         if (nn == 0 || L < 2) continue;
         if (lane < L) {
@@ -596,9 +595,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
             for (int ch = 0; ch < nch; ++ch) {
                 if (cb == 0 || nch > 1) {
 #pragma unroll
-                    for (int q = 0; q < kPC; ++q) {
-                        A0[q] = load_piece(r0, ch * kPC + q, np, v0, rowbytes, h);
-                        A1[q] = load_piece(r1, ch * kPC + q, np, v1 && two, rowbytes, h);
+                    for (int q = 0; q < kPC; ++q) A0[q] = load_piece(r0, ch * kPC + q, np);
+                    if (two) {
+#pragma unroll
+                        for (int q = 0; q < kPC; ++q) A1[q] = load_piece(r1, ch * kPC + q, np);
+                    }
+#pragma unroll
+                    for (int q = 0; q < kPC; ++q) clear_tail(A0[q], ch * kPC + q, rowbytes, h);
+                    if (two) {
+#pragma unroll
+                        for (int q = 0; q < kPC; ++q) clear_tail(A1[q], ch * kPC + q, rowbytes, h);
                     }
                 }
                 const int pc = min(kPC, np - ch * kPC);
@@ -672,18 +678,17 @@ __device__ inline void join_f32_point(const float* __restrict__ Xs, int ldp, int
     const int dk = (d + 1) & ~1;
     for (int c0 = 0; c0 < dk; c0 += kFC) {
         __syncthreads();
-        // stage 8 * NB rows x kFC coordinates: lane -> row ag + 8j, coordinates 4 bg .. 4 bg + 3
+        // stage 8 * NB rows x kFC coordinates: lane -> row ag + 8j, coordinates
+        // 4 bg .. 4 bg + 3, with no branch around the loads.
+        // Absent rows read a listed row and coordinates past d read the
+        // row's zero padding (the staged row is at least roundup(dk, 32)
+        // long and its trailing norm / worst words lie past dk); neither
+        // reaches a used Gram entry or the FMAs, which stop at dk.
+        const int t = c0 + 4 * bg;
 #pragma unroll 2
         for (int j = 0; j < NB; ++j) {
             const int r = ag + 8 * j;
-            const int t = c0 + 4 * bg;
-            f32x4 x = {0.0f, 0.0f, 0.0f, 0.0f};
-            if (r < L && t < d) {
-                x = *(const f32x4*)(Xs + (int64_t)ids[r] * ldp + t);
-                if (t + 1 >= d) x[1] = 0.0f;
-                if (t + 2 >= d) x[2] = 0.0f;
-                if (t + 3 >= d) x[3] = 0.0f;
-            }
+            const f32x4 x = *(const f32x4*)(Xs + (int64_t)ids[r < L ? r : 0] * ldp + t);
             float* dst = rows + r * kFS + 4 * bg;
             *(float2*)dst = make_float2(x[0], x[1]);
             *(float2*)(dst + 2) = make_float2(x[2], x[3]);
@@ -764,14 +769,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     po.p = nullptr;
     int64_t v = lo + (int64_t)(blockIdx.x >> 3);
     ListRaw cur = load_lists(v, v < hi, cfg, newf, revnew, oldf, revold);
-    ListRaw nxt = load_lists(v + gsz, v + gsz < hi, cfg, newf, revnew, oldf, revold);
     for (; v < hi; v += gsz) {
-        const ListRaw nx2 = load_lists(v + 2 * gsz, v + 2 * gsz < hi, cfg, newf, revnew, oldf, revold);
         int L = 0;
         const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cur, cfg, revnew, revold, sh, ids, L));
         L = __builtin_amdgcn_readfirstlane(L);
-        cur = nxt;
-        nxt = nx2;
+        cur = load_lists(v + gsz, v + gsz < hi, cfg, newf, revnew, oldf, revold);
         __syncthreads();
         if (nn == 0 || L < 2) continue;
         if (lane < L) {

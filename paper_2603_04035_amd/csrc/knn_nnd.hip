@@ -848,46 +848,40 @@ __global__ __launch_bounds__(256) void nnd_merge_kernel(
     const int64_t wstep = (int64_t)(gridDim.x >> 3) * 4;
     unsigned long long upd = 0;
     int64_t pw = (int64_t)(blockIdx.x >> 3) * 4 + wv;
-    // raw inputs of the current pair
-    uint64_t s0 = kEmptyCand, s1 = kEmptyCand;
-    int32_t id = -1;
-    float dd = 0.0f;
-    uint8_t fl = 0;
+    // raw inputs of the current pair, loaded without branches from in-bounds
+    // addresses (a row past the range reads the range's first row, lanes
+    // past C or K re-read an entry); the lanes and rows they do not belong
+    // to are masked where the values are used
+    const int hc0 = hl < C ? hl : C - 1, hc1 = 32 + hl < C ? 32 + hl : C - 1, hk = hl < K ? hl : K - 1;
+    uint64_t s0, s1;
+    int32_t id;
+    float dd;
+    uint8_t fl;
     {
-        const int64_t row = lo + 2 * pw + hf;
-        if (row < hi) {
-            if (hl < C) s0 = cand[row * C + hl];
-            if (32 + hl < C) s1 = cand[row * C + 32 + hl];
-            if (hl < K) {
-                id = gidx[row * K + hl];
-                dd = gd2[row * K + hl];
-                fl = gflag[row * K + hl];
-            }
-        }
+        const int64_t r0 = lo + 2 * pw + hf, row = r0 < hi ? r0 : lo;
+        s0 = cand[row * C + hc0];
+        s1 = cand[row * C + hc1];
+        id = gidx[row * K + hk];
+        dd = gd2[row * K + hk];
+        fl = gflag[row * K + hk];
     }
     for (; lo + 2 * pw < hi; pw += wstep) {
         const int64_t row = lo + 2 * pw + hf;
         const bool rv = row < hi;
-        const uint32_t lid = id >= 0 ? (uint32_t)id : 0xFFFFFFFFu;
+        const uint32_t lid = hl < K && id >= 0 ? (uint32_t)id : 0xFFFFFFFFu;
         uint64_t cur = kEmptyCand;
         if (hl < K) cur = id >= 0 ? make_key(dd, lid | (fl ? 0u : kWasOld)) : kEmptyList;
-        const uint64_t f0 = s0, f1 = s1;
+        const uint64_t f0 = hl < C ? s0 : kEmptyCand, f1 = 32 + hl < C ? s1 : kEmptyCand;
         // next pair's inputs are in flight during this merge
         {
-            const int64_t nrow = row + 2 * wstep;
-            s0 = s1 = kEmptyCand;
-            id = -1;
-            if (nrow < hi) {
-                if (hl < C) s0 = cand[nrow * C + hl];
-                if (32 + hl < C) s1 = cand[nrow * C + 32 + hl];
-                if (hl < K) {
-                    id = gidx[nrow * K + hl];
-                    dd = gd2[nrow * K + hl];
-                    fl = gflag[nrow * K + hl];
-                }
-            }
+            const int64_t n0 = row + 2 * wstep, nrow = n0 < hi ? n0 : lo;
+            s0 = cand[nrow * C + hc0];
+            s1 = cand[nrow * C + hc1];
+            id = gidx[nrow * K + hk];
+            dd = gd2[nrow * K + hk];
+            fl = gflag[nrow * K + hk];
         }
-        slid[seg][hl] = hl < K ? lid : 0xFFFFFFFFu;
+        slid[seg][hl] = lid;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");

@@ -497,16 +497,19 @@ __device__ inline f32x16 gram_step(const uint4& a, const uint4& b, f32x16 acc)
 // absent rows and of pieces past the data only reach Gram entries that the
 // selection and the offers never use, so they are not cleared; the
 // trailing norm / worst-distance words are (clear_tail), after all of a
-// chunk's loads are issued.
+// chunk's loads are issued, and clear_tail stores them to the row's norm
+// and threshold slots in LDS: the gather itself delivers them.
 __device__ inline uint4 load_piece(const uint8_t* r, int p, int np)
 {
     const int pp = p < np ? p : np - 1;
     return *(const uint4*)(r + 32 * (int64_t)pp);
 }
 
-__device__ inline void clear_tail(uint4& x, int p, int64_t rowbytes, int h)
+__device__ inline void clear_tail(uint4& x, int p, int np, int64_t rowbytes, int h, float* nrm, float* thr)
 {
-    if (32 * (int64_t)p + 16 * h + 16 == rowbytes) {
+    if (p < np && 32 * (int64_t)p + 16 * h + 16 == rowbytes) {
+        *nrm = __uint_as_float(x.z);
+        *thr = __uint_as_float(x.w);
         x.z = 0u;
         x.w = 0u;
     }
@@ -550,6 +553,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     const uint64_t salt = (uint64_t)iter ^ seed;
     const int J = cfg.J;
     const int nch = (np + kPC - 1) / kPC;
+    const bool tail_in_pieces = 32 * (int64_t)np == rowbytes;   // the last piece holds the norm / worst words
     const unsigned grp = blockIdx.x & 7u;
     const int64_t gsz = (int64_t)(gridDim.x >> 3);
     const int64_t lo = n * grp / 8, hi = n * (grp + 1) / 8;
@@ -566,19 +570,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
         cur = load_lists(v + gsz, v + gsz < hi, cfg, newf, revnew, oldf, revold);
         __syncthreads();
         if (nn == 0 || L < 2) continue;
-        if (lane < L) {
+        gathered += (unsigned long long)L;
+        if (!tail_in_pieces && lane < L) {
+            // rows whose trailing words lie past the gathered pieces
             const float2 a = *(const float2*)(Xr + (int64_t)ids[lane] * rowbytes + rowbytes - 8);
             nrm[lane] = a.x;
             thr[lane] = a.y;
-        } else {
-            nrm[lane] = 0.0f;
         }
-        gathered += (unsigned long long)L;
         const bool two = L > 32;
         const bool v0 = c < L, v1 = 32 + c < L;
         const uint8_t* r0 = Xr + (int64_t)ids[v0 ? c : 0] * rowbytes + 16 * h;
         const uint8_t* r1 = Xr + (int64_t)ids[v1 ? 32 + c : 0] * rowbytes + 16 * h;
-        __syncthreads();
         uint4 A0[kPC], A1[kPC];
         for (int cb = 0; cb < (two ? 2 : 1); ++cb) {
             // rows 32..63 x members 32..63 pair old with old when every new
@@ -601,10 +603,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
                         for (int q = 0; q < kPC; ++q) A1[q] = load_piece(r1, ch * kPC + q, np);
                     }
 #pragma unroll
-                    for (int q = 0; q < kPC; ++q) clear_tail(A0[q], ch * kPC + q, rowbytes, h);
+                    for (int q = 0; q < kPC; ++q) clear_tail(A0[q], ch * kPC + q, np, rowbytes, h, nrm + c, thr + c);
                     if (two) {
 #pragma unroll
-                        for (int q = 0; q < kPC; ++q) clear_tail(A1[q], ch * kPC + q, rowbytes, h);
+                        for (int q = 0; q < kPC; ++q)
+                            clear_tail(A1[q], ch * kPC + q, np, rowbytes, h, nrm + 32 + c, thr + 32 + c);
                     }
                 }
                 const int pc = min(kPC, np - ch * kPC);
@@ -617,6 +620,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
                     }
                 }
             }
+            __syncthreads();   // the norms and thresholds stored from the gathered rows
             // lane-dependent indices are re-derived per point (an opaque copy
             // of the lane id) so that they are not held across the loop
             int ln = lane;

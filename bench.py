@@ -175,7 +175,7 @@ def join_roofline(stats, n, d, p, kernel, workload):
     launches = sum(st["iters"] for st in stats)
     gathered_rows = sum(st["bytes_gathered"] for st in stats) / (d * rb)
     emitted = sum(sum(st["emitted"]) for st in stats)
-    list_bytes = launches * n * (4 * s_ + 4 * K + 2 * 16 * s_)   # new_f, old_f, reverse slots read+reset
+    list_bytes = launches * n * (4 * s_ + 4 * K + 2 * 8 * s_)   # new_f, old_f, 4-byte reverse slots read+reset
     alg_bytes = gathered_rows * (d * rb + 8) + list_bytes + 8 * emitted
     join_ms = sum(st["ms_join"] for st in stats)
     achieved = alg_bytes / (join_ms * 1e-3) / 1e9

@@ -189,10 +189,47 @@ __global__ __launch_bounds__(256) void nnd_init_kernel(
 // pairs from contiguous ranges, one range per group of blockIdx mod 8 (the
 // XCD of the workgroup), so the scattered targets of concurrent rows are
 // mostly Z-order neighbours.  gridDim.x is a multiple of 8.
+// Reverse-slot codes.  A reverse slot of point v holds, as a 32-bit word,
+// the least code among the sources u that picked that slot this iteration:
+// code = mix(u ^ salt(v)), where mix is an invertible 32-bit mixer and the
+// salt is drawn from (seed, stream tag, iteration, v).  The minimum over
+// codes is a pseudo-random choice among the sources, fresh per point and
+// iteration, and the join recovers u = unmix(code) ^ salt(v).  The empty
+// slot is 0xFFFFFFFF (a source whose code is that value, one chance in 2^32,
+// is not recorded).  The mixer is Wellons' "lowbias32" from his
+// hash-prospector search; the inverse undoes each xor-shift and multiplies
+// by the multipliers' inverses modulo 2^32.
+__host__ __device__ inline uint32_t rev_mix(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7FEB352Du;
+    x ^= x >> 15;
+    x *= 0x846CA68Bu;
+    x ^= x >> 16;
+    return x;
+}
+
+__host__ __device__ inline uint32_t rev_unmix(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x43021123u;   // inverse of 0x846CA68B modulo 2^32
+    x ^= (x >> 15) ^ (x >> 30);
+    x *= 0x1D69E2A5u;   // inverse of 0x7FEB352D modulo 2^32
+    x ^= x >> 16;
+    return x;
+}
+
+__host__ __device__ inline uint32_t rev_salt(uint64_t seed, uint64_t tag, int iter, int64_t v)
+{
+    return (uint32_t)hash4(seed ^ tag, (uint64_t)iter, (uint64_t)v, 3);
+}
+
+__host__ __device__ inline uint32_t rev_code(uint32_t u, uint32_t salt) { return rev_mix(u ^ salt); }
+
 __global__ __launch_bounds__(256) void nnd_sample_kernel(
     int64_t n, int K, int s, int R, int32_t* __restrict__ gidx, uint8_t* __restrict__ gflag,
-    int32_t* __restrict__ newf, int32_t* __restrict__ oldf, unsigned long long* __restrict__ revnew,
-    unsigned long long* __restrict__ revold, uint64_t seed, int iter)
+    int32_t* __restrict__ newf, int32_t* __restrict__ oldf, uint32_t* __restrict__ revnew,
+    uint32_t* __restrict__ revold, uint64_t seed, int iter)
 {
     const int lane = threadIdx.x & 63, hl = lane & 31, hbase = lane & 32;
     const unsigned grp = blockIdx.x & 7u;
@@ -242,16 +279,12 @@ __global__ __launch_bounds__(256) void nnd_sample_kernel(
             newf[row * s + rank] = id;
             gflag[row * K + hl] = 0;
             const uint32_t slot = bounded(hash4(seed ^ kTagRevSlot, (uint64_t)iter, (uint64_t)row, 1), (uint32_t)R);
-            const uint64_t key = (hash4(seed ^ kTagRevNew, (uint64_t)iter, (uint64_t)row, (uint64_t)id) &
-                                  0xFFFFFFFF00000000ull) | (uint64_t)row;
-            atomicMin(&revnew[(int64_t)id * R + slot], (unsigned long long)key);
+            atomicMin(&revnew[(int64_t)id * R + slot], rev_code((uint32_t)row, rev_salt(seed, kTagRevNew, iter, id)));
         }
         if (isold) {
             oldf[row * K + opos] = id;
             const uint32_t slot = bounded(hash4(seed ^ kTagRevSlot, (uint64_t)iter, (uint64_t)row, 2), (uint32_t)R);
-            const uint64_t key = (hash4(seed ^ kTagRevOld, (uint64_t)iter, (uint64_t)row, (uint64_t)id) &
-                                  0xFFFFFFFF00000000ull) | (uint64_t)row;
-            atomicMin(&revold[(int64_t)id * R + slot], (unsigned long long)key);
+            atomicMin(&revold[(int64_t)id * R + slot], rev_code((uint32_t)row, rev_salt(seed, kTagRevOld, iter, id)));
         }
     }
 }
@@ -267,10 +300,9 @@ struct JoinCfg {
 constexpr int kJMax = 4;         // largest supported join cap
 
 // Raw join-list entries of one lane: lanes 0..s-1 hold new_f(v), lanes
-// s..s+R-1 the source ids of the reverse-new slots (the low word of the
-// slot key), and likewise old_f(v) / reverse-old in `o`; 0xFFFFFFFF marks an
-// empty entry (a -1 forward entry, or the low word of an empty slot, which
-// no source id reaches).  Loaded ahead of the join that consumes them.  Every
+// s..s+R-1 the codes of the reverse-new slots, and likewise old_f(v) /
+// reverse-old in `o`; 0xFFFFFFFF marks an empty entry (a -1 forward entry,
+// or an empty slot).  Loaded ahead of the join that consumes them.  Every
 // lane loads from an in-bounds address (lanes past s+R or K+R re-read a
 // slot, and a point past the range reads row 0) and join_lists masks the
 // lanes it does not use: one load per list with no branch, so a load still
@@ -281,17 +313,15 @@ struct ListRaw {
 
 __device__ inline ListRaw load_lists(int64_t v, bool valid, const JoinCfg& cfg,
                                      const int32_t* __restrict__ newf,
-                                     const unsigned long long* __restrict__ revnew,
+                                     const uint32_t* __restrict__ revnew,
                                      const int32_t* __restrict__ oldf,
-                                     const unsigned long long* __restrict__ revold)
+                                     const uint32_t* __restrict__ revold)
 {
     const int lane = threadIdx.x;
     const int64_t vv = valid ? v : 0;
     const int rn = min(max(lane - cfg.s, 0), cfg.R - 1), ro = min(max(lane - cfg.K, 0), cfg.R - 1);
-    const uint32_t* pn = lane < cfg.s ? (const uint32_t*)(newf + vv * cfg.s + lane)
-                                      : (const uint32_t*)(revnew + vv * cfg.R + rn);
-    const uint32_t* po = lane < cfg.K ? (const uint32_t*)(oldf + vv * cfg.K + lane)
-                                      : (const uint32_t*)(revold + vv * cfg.R + ro);
+    const uint32_t* pn = lane < cfg.s ? (const uint32_t*)(newf + vv * cfg.s + lane) : revnew + vv * cfg.R + rn;
+    const uint32_t* po = lane < cfg.K ? (const uint32_t*)(oldf + vv * cfg.K + lane) : revold + vv * cfg.R + ro;
     return {*pn, *po};
 }
 
@@ -302,15 +332,18 @@ __device__ inline ListRaw load_lists(int64_t v, bool valid, const JoinCfg& cfg,
 // surviving ids are written to ids[0..nn) (new) and ids[nn..nn+no) (old).
 // Returns nn, sets L.
 __device__ inline int join_lists(int64_t v, const ListRaw& raw, const JoinCfg& cfg,
-                                 unsigned long long* __restrict__ revnew,
-                                 unsigned long long* __restrict__ revold, uint32_t* sh,
-                                 uint32_t* ids, int& L)
+                                 uint32_t* __restrict__ revnew, uint32_t* __restrict__ revold,
+                                 uint64_t seed, int iter, uint32_t* sh, uint32_t* ids, int& L)
 {
     const int lane = threadIdx.x;
-    if (lane >= cfg.s && lane < cfg.s + cfg.R) revnew[v * cfg.R + (lane - cfg.s)] = ~0ull;
-    if (lane >= cfg.K && lane < cfg.K + cfg.R) revold[v * cfg.R + (lane - cfg.K)] = ~0ull;
-    const uint32_t nid = lane < cfg.s + cfg.R ? raw.n : 0xFFFFFFFFu;
-    const uint32_t oid = lane < cfg.K + cfg.R ? raw.o : 0xFFFFFFFFu;
+    if (lane >= cfg.s && lane < cfg.s + cfg.R) revnew[v * cfg.R + (lane - cfg.s)] = 0xFFFFFFFFu;
+    if (lane >= cfg.K && lane < cfg.K + cfg.R) revold[v * cfg.R + (lane - cfg.K)] = 0xFFFFFFFFu;
+    // reverse slots hold codes: recover the source ids
+    const uint32_t sn = rev_salt(seed, kTagRevNew, iter, v), so = rev_salt(seed, kTagRevOld, iter, v);
+    const uint32_t rn = raw.n == 0xFFFFFFFFu ? raw.n : rev_unmix(raw.n) ^ sn;
+    const uint32_t ro = raw.o == 0xFFFFFFFFu ? raw.o : rev_unmix(raw.o) ^ so;
+    const uint32_t nid = lane < cfg.s ? raw.n : (lane < cfg.s + cfg.R ? rn : 0xFFFFFFFFu);
+    const uint32_t oid = lane < cfg.K ? raw.o : (lane < cfg.K + cfg.R ? ro : 0xFFFFFFFFu);
     sh[lane] = nid;
     sh[64 + lane] = oid;
     __syncthreads();
@@ -540,8 +573,8 @@ __device__ inline void scan_block(const f32x16& g, int blk, int h4, int m, int l
 
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nnd_join_bf16_kernel(
     int64_t n, JoinCfg cfg, const uint8_t* __restrict__ Xr, int64_t rowbytes, int np,
-    const int32_t* __restrict__ newf, unsigned long long* __restrict__ revnew,
-    const int32_t* __restrict__ oldf, unsigned long long* __restrict__ revold,
+    const int32_t* __restrict__ newf, uint32_t* __restrict__ revnew,
+    const int32_t* __restrict__ oldf, uint32_t* __restrict__ revold,
     unsigned long long* __restrict__ cand, uint64_t seed, int iter, unsigned long long* __restrict__ counters)
 {
     __shared__ uint32_t ids[64];
@@ -564,7 +597,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     ListRaw cur = load_lists(v, v < hi, cfg, newf, revnew, oldf, revold);
     for (; v < hi; v += gsz) {
         int L = 0;
-        const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cur, cfg, revnew, revold, sh, ids, L));
+        const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cur, cfg, revnew, revold, seed, iter, sh, ids, L));
         L = __builtin_amdgcn_readfirstlane(L);
         // the next point's lists are in flight while this one is joined
         cur = load_lists(v + gsz, v + gsz < hi, cfg, newf, revnew, oldf, revold);
@@ -753,8 +786,8 @@ __device__ inline void join_f32_point(const float* __restrict__ Xs, int ldp, int
 
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nnd_join_f32_kernel(
     int64_t n, JoinCfg cfg, const float* __restrict__ Xs, int ldp, int d,
-    const int32_t* __restrict__ newf, unsigned long long* __restrict__ revnew,
-    const int32_t* __restrict__ oldf, unsigned long long* __restrict__ revold,
+    const int32_t* __restrict__ newf, uint32_t* __restrict__ revnew,
+    const int32_t* __restrict__ oldf, uint32_t* __restrict__ revold,
     unsigned long long* __restrict__ cand, uint64_t seed, int iter, unsigned long long* __restrict__ counters)
 {
     __shared__ __attribute__((aligned(16))) float rows[64 * kFS];
@@ -775,7 +808,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     ListRaw cur = load_lists(v, v < hi, cfg, newf, revnew, oldf, revold);
     for (; v < hi; v += gsz) {
         int L = 0;
-        const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cur, cfg, revnew, revold, sh, ids, L));
+        const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cur, cfg, revnew, revold, seed, iter, sh, ids, L));
         L = __builtin_amdgcn_readfirstlane(L);
         cur = load_lists(v + gsz, v + gsz < hi, cfg, newf, revnew, oldf, revold);
         __syncthreads();
@@ -1117,7 +1150,8 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     int32_t *gidx, *newf, *oldf;
     float* gd2;
     uint8_t* gflag;
-    unsigned long long *revnew, *revold, *cand, *counters;
+    uint32_t *revnew, *revold;
+    unsigned long long *cand, *counters;
     if ((r = ws.alloc(&gidx, (size_t)n * K)) != KNN_OK) return r;
     if ((r = ws.alloc(&gd2, (size_t)n * K)) != KNN_OK) return r;
     if ((r = ws.alloc(&gflag, (size_t)n * K)) != KNN_OK) return r;
@@ -1127,8 +1161,8 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     if ((r = ws.alloc(&revold, (size_t)n * cfg.R)) != KNN_OK) return r;
     if ((r = ws.alloc(&cand, (size_t)n * cfg.C)) != KNN_OK) return r;
     if ((r = ws.alloc(&counters, 4)) != KNN_OK) return r;
-    KNN_HIP(hipMemsetAsync(revnew, 0xFF, (size_t)n * cfg.R * 8, st));
-    KNN_HIP(hipMemsetAsync(revold, 0xFF, (size_t)n * cfg.R * 8, st));
+    KNN_HIP(hipMemsetAsync(revnew, 0xFF, (size_t)n * cfg.R * 4, st));
+    KNN_HIP(hipMemsetAsync(revold, 0xFF, (size_t)n * cfg.R * 4, st));
     KNN_HIP(hipMemsetAsync(cand, 0xFF, (size_t)n * cfg.C * 8, st));
 
     // ---- init

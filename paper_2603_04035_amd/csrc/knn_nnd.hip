@@ -1018,14 +1018,42 @@ __global__ __launch_bounds__(256) void nnd_finalize_kernel(
         if (st_d2) st_d2[orow * K + lane] = gd2[row * K + lane];
         if (st_fl) st_fl[orow * K + lane] = gflag[row * K + lane];
     }
+    // Distances of the K <= 32 entries, four per pass through 16-lane
+    // groups as dist_g16 computes them (each lane sums coordinates g, g+16,
+    // ... in order, then a fixed 16-lane tree), with every pass's loads of a
+    // coordinate step issued together instead of pass after pass.
+    constexpr int kPass = 8;
+    const int g = lane & 15;
+    const float* xr = Xs + row * ldp;
+    const float* xc[kPass];
+    bool act[kPass];
+#pragma unroll
+    for (int q = 0; q < kPass; ++q) {
+        const int ci = 4 * q + (lane >> 4);
+        const int32_t cj = (int32_t)shfl_u32((uint32_t)id, ci < 64 ? ci : 0);
+        act[q] = ci < K && cj >= 0;
+        xc[q] = Xs + (int64_t)(act[q] ? cj : 0) * ldp;
+    }
+    float part[kPass];
+#pragma unroll
+    for (int q = 0; q < kPass; ++q) part[q] = 0.0f;
+    for (int t = g; t < d; t += 16) {
+        const float a = xr[t];
+        float b[kPass];
+#pragma unroll
+        for (int q = 0; q < kPass; ++q) b[q] = xc[q][t];
+#pragma unroll
+        for (int q = 0; q < kPass; ++q) {
+            const float e = a - b[q];
+            part[q] = act[q] ? fmaf(e, e, part[q]) : part[q];
+        }
+    }
     float mine = 0.0f;
-    for (int base = 0; base < K; base += 4) {
-        const int ci = base + (lane >> 4);
-        const int32_t cj = (int32_t)shfl_u32((uint32_t)id, ci);
-        const bool act = ci < K && cj >= 0;
-        const float v = dist_g16<KNN_F32>(Xs, row * ldp, Xs, (int64_t)(act ? cj : 0) * ldp, d, act);
-        const float got = shfl_f32(v, ((lane - base) & 3) * 16);
-        if (lane >= base && lane < base + 4) mine = got;
+#pragma unroll
+    for (int q = 0; q < kPass; ++q) {
+        const float v = wave_sum16(part[q]);
+        const float got = shfl_f32(v, ((lane - 4 * q) & 3) * 16);
+        if (lane >= 4 * q && lane < 4 * q + 4) mine = got;
     }
     uint64_t key = (lane < K && id >= 0) ? make_key(mine, (uint32_t)oid) : kEmptyCand;
     key = seg_sort<64>(key);

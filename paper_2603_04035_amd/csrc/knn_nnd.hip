@@ -89,8 +89,10 @@ __global__ __launch_bounds__(256) void nnd_init_kernel(
             if (init_flags) fl = init_flags[grow * init_k + lane] ? 1 : 0;
         }
     }
-    // drop repeats (keep the first occurrence)
-    for (int o = 0; o < 64; ++o) {
+    // drop repeats (keep the first occurrence); only lanes < init_k hold
+    // given entries
+    const int ngiven = init_idx ? (init_k < 64 ? init_k : 64) : 0;
+    for (int o = 0; o < ngiven; ++o) {
         uint32_t oi = bcast_u32(id, o);
         bool ov = bcast_u32(valid ? 1u : 0u, o) != 0;
         if (o < lane && ov && oi == id) valid = false;

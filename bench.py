@@ -43,13 +43,13 @@ FORMS = {
     "fp32": dict(precision="fp32", build_k=32, sample_rate=1.0, max_iters=30, delta=0.015,
                  join_cap=4, cand_slots=64),
     "bf16-learned": dict(precision="bf16", build_k=32, sample_rate=1.0, max_iters=30, delta=0.015,
-                         join_cap=4, cand_slots=64, init_kind="encoder", proj_count=4, proj_window=8),
+                         join_cap=4, cand_slots=96, init_kind="encoder", proj_count=4, proj_window=8),
     # controls for the encoder's benefit (--form all): same BF16 form, random
     # init, and seeding through an untrained encoder of the same shape
     "bf16-random": dict(precision="bf16", build_k=32, sample_rate=1.0, max_iters=30, delta=0.015,
-                        join_cap=4, cand_slots=64),
+                        join_cap=4, cand_slots=96),
     "bf16-untrained": dict(precision="bf16", build_k=32, sample_rate=1.0, max_iters=30, delta=0.015,
-                           join_cap=4, cand_slots=64, init_kind="encoder", proj_count=4, proj_window=8),
+                           join_cap=4, cand_slots=96, init_kind="encoder", proj_count=4, proj_window=8),
 }
 # encoder training (reported separately, not in the timed region)
 TRAIN = dict(n=100_000, seed=100, k=15, steps=1000, batch=4096, lr=2e-3, precision="bf16")

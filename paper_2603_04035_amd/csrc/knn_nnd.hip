@@ -892,7 +892,8 @@ __global__ __launch_bounds__(256) void nnd_merge_kernel(
     // past C or K re-read an entry); the lanes and rows they do not belong
     // to are masked where the values are used
     const int hc0 = hl < C ? hl : C - 1, hc1 = 32 + hl < C ? 32 + hl : C - 1, hk = hl < K ? hl : K - 1;
-    uint64_t s0, s1;
+    const int hc2 = 64 + hl < C ? 64 + hl : C - 1;
+    uint64_t s0, s1, s2;
     int32_t id;
     float dd;
     uint8_t fl;
@@ -900,6 +901,7 @@ __global__ __launch_bounds__(256) void nnd_merge_kernel(
         const int64_t r0 = lo + 2 * pw + hf, row = r0 < hi ? r0 : lo;
         s0 = cand[row * C + hc0];
         s1 = cand[row * C + hc1];
+        s2 = cand[row * C + hc2];
         id = gidx[row * K + hk];
         dd = gd2[row * K + hk];
         fl = gflag[row * K + hk];
@@ -911,11 +913,13 @@ __global__ __launch_bounds__(256) void nnd_merge_kernel(
         uint64_t cur = kEmptyCand;
         if (hl < K) cur = id >= 0 ? make_key(dd, lid | (fl ? 0u : kWasOld)) : kEmptyList;
         const uint64_t f0 = hl < C ? s0 : kEmptyCand, f1 = 32 + hl < C ? s1 : kEmptyCand;
+        const uint64_t f2 = 64 + hl < C ? s2 : kEmptyCand;
         // next pair's inputs are in flight during this merge
         {
             const int64_t n0 = row + 2 * wstep, nrow = n0 < hi ? n0 : lo;
             s0 = cand[nrow * C + hc0];
             s1 = cand[nrow * C + hc1];
+            s2 = cand[nrow * C + hc2];
             id = gidx[nrow * K + hk];
             dd = gd2[nrow * K + hk];
             fl = gflag[nrow * K + hk];
@@ -929,7 +933,7 @@ __global__ __launch_bounds__(256) void nnd_merge_kernel(
             uint64_t key = kEmptyCand;
             if (rv && c0 + hl < C) {
                 unsigned long long* p = &cand[row * C + c0 + hl];
-                key = c0 == 0 ? f0 : (c0 == 32 ? f1 : *p);
+                key = c0 == 0 ? f0 : (c0 == 32 ? f1 : (c0 == 64 ? f2 : *p));
                 if (key != kEmptyCand) *p = kEmptyCand;
             }
             if (!ballot(key != kEmptyCand)) continue;

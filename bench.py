@@ -257,7 +257,7 @@ def run_form(X, k, form, steps, warmup, rows, config, encoder=None, Xnp=None):
     wall = time.perf_counter() - t0
     n, d = X.shape
     recall = recall_gpu(X, G, D, rows, k)
-    kern = "nnd_join_mfma_kernel<false>" if p["precision"] == "bf16" else "nnd_join_mfma_kernel<true>"
+    kern = "nnd_join_bf16_kernel" if p["precision"] == "bf16" else "nnd_join_f32_kernel"
     last = stats[-1]
     cfg = {kk: vv for kk, vv in p.items() if kk != "encoder"}
     cfg["build_k"] = last["build_k"]

@@ -464,17 +464,47 @@ __device__ inline unsigned long long offers_resolve(const PendingOffers& po)
     return n;
 }
 
-// Local join, both forms.  One wave per point v; the grid is split into 8
+// One pending offer per lane (the FP32 join: lane ag < 4 offers entry ag).
+struct PendingOffer {
+    unsigned long long* p;
+    uint64_t key;
+    unsigned long long seen;
+};
+
+__device__ inline void offer_issue(PendingOffer& po, uint32_t b, bool ok, float cut, const uint32_t* ids,
+                                   uint32_t me, int C, uint64_t salt, unsigned long long* __restrict__ cand)
+{
+    po.p = nullptr;
+    po.key = ~0ull;
+    po.seen = 0ull;
+    if (ok && b != kNoSel && __uint_as_float(b & ~63u) < cut) {
+        const uint32_t src = ids[b & 63u];
+        po.key = ((uint64_t)(b & ~63u) << 32) | src;
+        const uint32_t slot = bounded(mix64(((uint64_t)src << 20) ^ salt), (uint32_t)C);
+        po.p = &cand[(int64_t)me * C + slot];
+        po.seen = *po.p;
+    }
+}
+
+__device__ inline unsigned long long offer_resolve(const PendingOffer& po)
+{
+    if (po.p && po.seen > (unsigned long long)po.key) {
+        atomicMin(po.p, (unsigned long long)po.key);
+        return 1;
+    }
+    return 0;
+}
+
+// Local join, BF16 form.  One wave per point v; the grid is split into 8
 // groups (blockIdx mod 8, the round-robin XCD assignment of workgroups) that
 // each sweep one contiguous range of the processing order, so concurrently
 // joined points are Z-order neighbours sharing an L2.
 //
 // The join list (new members first, then old; L <= 64) is two 32-row
-// blocks.  Its L x L Gram is accumulated by 32 x 32 MFMA tiles with FP32
-// accumulation -- 32x32x16 BF16 steps on BF16 rows, 32x32x2 FP32 steps on
-// FP32 rows -- whose operands come straight from the staged rows into
+// blocks.  Its L x L Gram is accumulated by 32 x 32 x 16 BF16 MFMA tiles
+// (FP32 accumulation) whose operands come straight from the staged rows into
 // registers, no LDS copy: lane (h, c) holds 16-byte pieces of rows c and
-// 32 + c; piece p holds bytes [32p + 16h, +16).  That assigns the reduction
+// 32 + c; piece p holds elements [16p + 8h, +8).  That assigns the reduction
 // index to (step, half) one-to-one, which is all a Gram product needs since
 // both operands use the same assignment.
 //
@@ -491,21 +521,10 @@ constexpr int kPC = 4;   // pieces per lane per row held in registers at a time
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// One 16-byte piece per lane into the Gram: eight BF16 values (one
-// 32x32x16 BF16 MFMA), or four FP32 values (four 32x32x2 FP32 MFMAs, value
-// e of both halves' pieces forming one step's two reduction indices).
-template <bool F32>
 __device__ inline f32x16 gram_step(const uint4& a, const uint4& b, f32x16 acc)
 {
-    if constexpr (F32) {
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), acc, 0, 0, 0);
-        return __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(b.w), acc, 0, 0, 0);
-    } else {
-        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
-                                                        acc, 0, 0, 0);
-    }
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                    acc, 0, 0, 0);
 }
 
 // Piece p of a row (r = row base + 16h bytes): the load always reads inside
@@ -554,8 +573,7 @@ __device__ inline void scan_block(const f32x16& g, int blk, int h4, int m, int l
     }
 }
 
-template <bool F32>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nnd_join_mfma_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nnd_join_bf16_kernel(
     int64_t n, JoinCfg cfg, const uint8_t* __restrict__ Xr, int64_t rowbytes, int np,
     const int32_t* __restrict__ newf, uint32_t* __restrict__ revnew,
     const int32_t* __restrict__ oldf, uint32_t* __restrict__ revold,
@@ -632,8 +650,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
                 for (int q = 0; q < kPC; ++q) {
                     if (q < pc) {
                         const uint4 b = cb == 0 ? A0[q] : A1[q];
-                        at = gram_step<F32>(A0[q], b, at);
-                        if (lower) ab = gram_step<F32>(A1[q], b, ab);
+                        at = gram_step(A0[q], b, at);
+                        if (lower) ab = gram_step(A1[q], b, ab);
                     }
                 }
             }
@@ -667,6 +685,176 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
         atomicAdd(&counters[2], gathered);
     }
 }
+// Local join, FP32 form (VALU).  Lists, traversal and offers as in the BF16
+// kernel.  The rows are staged in LDS in chunks of kFC coordinates (zero
+// past d and for absent rows).  Lane (ag, bg) = (lane / 8, lane % 8) holds
+// the Gram entries of rows a = ag + 8i and columns b = bg + 8q (i, q < NB;
+// NB = 4 when L <= 32, else 8), accumulated with FP32 FMAs from two
+// coordinates per LDS read; row strides of kFS floats put the 8 distinct
+// rows of a read in distinct banks.  For each column b the lane keeps the
+// best J of its NB rows, a butterfly over the 8 lanes of the column (lane
+// bits 3..5) merges them, and lane ag offers entry ag of the merged list.
+constexpr int kFC = 32;        // coordinates per staged chunk
+constexpr int kFS = kFC + 2;   // LDS row stride (floats)
+
+// NI = number of 8-row groups holding new members (new rows come first):
+// register blocks (i, q) with i >= NI and q >= NI pair old with old only and
+// are skipped.
+template <int NB, int NI>
+__device__ inline void join_f32_point(const float* __restrict__ Xs, int ldp, int d, float* rows,
+                                      const uint32_t* ids, const float* nrm, const float* thr, int L, int nn,
+                                      int J, int C, uint64_t salt, unsigned long long* __restrict__ cand,
+                                      unsigned long long& emitted, PendingOffer& po)
+{
+    int ln = threadIdx.x;
+    asm volatile("" : "+v"(ln));   // lane-dependent indices re-derived per point
+    const int ag = ln >> 3, bg = ln & 7;
+    float acc[NB][NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) acc[i][q] = 0.0f;
+    const int dk = (d + 1) & ~1;
+    for (int c0 = 0; c0 < dk; c0 += kFC) {
+        __syncthreads();
+        // stage 8 * NB rows x kFC coordinates: lane -> row ag + 8j, coordinates
+        // 4 bg .. 4 bg + 3, with no branch around the loads.
+        // Absent rows read a listed row and coordinates past d read the
+        // row's zero padding (the staged row is at least roundup(dk, 32)
+        // long and its trailing norm / worst words lie past dk); neither
+        // reaches a used Gram entry or the FMAs, which stop at dk.
+        const int t = c0 + 4 * bg;
+#pragma unroll 2
+        for (int j = 0; j < NB; ++j) {
+            const int r = ag + 8 * j;
+            const f32x4 x = *(const f32x4*)(Xs + (int64_t)ids[r < L ? r : 0] * ldp + t);
+            float* dst = rows + r * kFS + 4 * bg;
+            *(float2*)dst = make_float2(x[0], x[1]);
+            *(float2*)(dst + 2) = make_float2(x[2], x[3]);
+        }
+        __syncthreads();
+        const int kc = min(kFC, dk - c0);
+        for (int t = 0; t < kc; t += 2) {
+            float2 xa[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) xa[i] = *(const float2*)(rows + (ag + 8 * i) * kFS + t);
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const float2 xb = *(const float2*)(rows + (bg + 8 * q) * kFS + t);
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    if (i < NI || q < NI) {
+                        acc[i][q] = fmaf(xa[i].x, xb.x, acc[i][q]);
+                        acc[i][q] = fmaf(xa[i].y, xb.y, acc[i][q]);
+                    }
+                }
+            }
+        }
+    }
+    float na[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) na[i] = nrm[ag + 8 * i];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int b = bg + 8 * q;
+        const float nb = nrm[b];
+        const int lim = b < nn ? L : nn;
+        uint32_t best[kJMax];
+#pragma unroll
+        for (int s = 0; s < kJMax; ++s) best[s] = kNoSel;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            if (i < NI || q < NI) {   // old rows pair only with new columns
+                const int a = ag + 8 * i;
+                float d2 = na[i] + nb - 2.0f * acc[i][q];
+                d2 = d2 > 0.0f ? d2 : 0.0f;
+                const bool ok = a < lim && a != b;
+                sel_insert(best, ok ? ((__float_as_uint(d2) & ~63u) | (uint32_t)a) : kNoSel);
+            }
+        }
+#pragma unroll
+        for (int o = 8; o <= 32; o <<= 1) {
+            uint32_t recv[kJMax];
+#pragma unroll
+            for (int s = 0; s < kJMax; ++s) recv[s] = xor_u32(best[s], o);
+            sel_merge(best, recv);
+        }
+        // lane ag offers merged entry ag; the previous column's offer resolves first
+        emitted += offer_resolve(po);
+        const uint32_t mine = ag == 0 ? best[0] : (ag == 1 ? best[1] : (ag == 2 ? best[2] : best[3]));
+        offer_issue(po, mine, b < L && ag < J, b < L ? thr[b] : 0.0f, ids, ids[b], C, salt, cand);
+    }
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nnd_join_f32_kernel(
+    int64_t n, JoinCfg cfg, const float* __restrict__ Xs, int ldp, int d,
+    const int32_t* __restrict__ newf, uint32_t* __restrict__ revnew,
+    const int32_t* __restrict__ oldf, uint32_t* __restrict__ revold,
+    unsigned long long* __restrict__ cand, uint64_t seed, int iter, unsigned long long* __restrict__ counters)
+{
+    __shared__ __attribute__((aligned(16))) float rows[64 * kFS];
+    __shared__ uint32_t ids[64];
+    __shared__ float nrm[64];
+    __shared__ float thr[64];
+    __shared__ __attribute__((aligned(16))) uint32_t sh[128];
+    const int lane = threadIdx.x;
+    unsigned long long emitted = 0, gathered = 0;
+    const uint64_t salt = (uint64_t)iter ^ seed;
+    const unsigned grp = blockIdx.x & 7u;
+    const int64_t gsz = (int64_t)(gridDim.x >> 3);
+    const int64_t lo = n * grp / 8, hi = n * (grp + 1) / 8;
+
+    PendingOffer po;
+    po.p = nullptr;
+    int64_t v = lo + (int64_t)(blockIdx.x >> 3);
+    ListRaw cur = load_lists(v, v < hi, cfg, newf, revnew, oldf, revold);
+    for (; v < hi; v += gsz) {
+        int L = 0;
+        const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cur, cfg, revnew, revold, seed, iter, sh, ids, L));
+        L = __builtin_amdgcn_readfirstlane(L);
+        cur = load_lists(v + gsz, v + gsz < hi, cfg, newf, revnew, oldf, revold);
+        __syncthreads();
+        if (nn == 0 || L < 2) continue;
+        if (lane < L) {
+            const float2 a = *(const float2*)(Xs + (int64_t)ids[lane] * ldp + ldp - 2);
+            nrm[lane] = a.x;
+            thr[lane] = a.y;
+        } else {
+            nrm[lane] = 0.0f;
+        }
+        gathered += (unsigned long long)L;
+        const int ni = (nn + 7) >> 3;
+#define KNN_JF(NB, NI) \
+    join_f32_point<NB, NI>(Xs, ldp, d, rows, ids, nrm, thr, L, nn, cfg.J, cfg.C, salt, cand, emitted, po)
+        if (L <= 32) {
+            switch (ni) {
+            case 1: KNN_JF(4, 1); break;
+            case 2: KNN_JF(4, 2); break;
+            case 3: KNN_JF(4, 3); break;
+            default: KNN_JF(4, 4); break;
+            }
+        } else {
+            switch (ni) {
+            case 1: KNN_JF(8, 1); break;
+            case 2: KNN_JF(8, 2); break;
+            case 3: KNN_JF(8, 3); break;
+            case 4: KNN_JF(8, 4); break;
+            case 5: KNN_JF(8, 5); break;
+            case 6: KNN_JF(8, 6); break;
+            case 7: KNN_JF(8, 7); break;
+            default: KNN_JF(8, 8); break;
+            }
+        }
+#undef KNN_JF
+    }
+    emitted += offer_resolve(po);
+    for (int o = 32; o > 0; o >>= 1) emitted += shfl_u64(emitted, lane ^ o);
+    if (lane == 0) {
+        atomicAdd(&counters[1], emitted);
+        atomicAdd(&counters[2], gathered);
+    }
+}
+
 // ------------------------------------------------------------------ merge
 
 // Merge, one half-wave (32 lanes) per row, two rows per wave; the waves take
@@ -1056,7 +1244,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     int jpc = 0;
     KNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &jpc, bf ? (const void*)nnd_join_mfma_kernel<false> : (const void*)nnd_join_mfma_kernel<true>, 64, 0));
+        &jpc, bf ? (const void*)nnd_join_bf16_kernel : (const void*)nnd_join_f32_kernel, 64, 0));
     if (jpc < 1) jpc = 1;
     // a multiple of 8: the join splits its grid into 8 contiguous point ranges
     const unsigned join_grid = (unsigned)round_up((int64_t)ncu * jpc, 8);
@@ -1084,11 +1272,11 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         (void)hipEventRecord(ts.b, st);
         (void)hipEventRecord(tj.a, st);
         if (bf)
-            nnd_join_mfma_kernel<false><<<join_grid, 64, 0, st>>>(n, cfg, Xr, rowbytes, np, newf, revnew, oldf,
-                                                                 revold, cand, p->seed, iter, counters);
+            nnd_join_bf16_kernel<<<join_grid, 64, 0, st>>>(n, cfg, Xr, rowbytes, np, newf, revnew, oldf, revold,
+                                                           cand, p->seed, iter, counters);
         else
-            nnd_join_mfma_kernel<true><<<join_grid, 64, 0, st>>>(n, cfg, Xr, rowbytes, np, newf, revnew, oldf,
-                                                                revold, cand, p->seed, iter, counters);
+            nnd_join_f32_kernel<<<join_grid, 64, 0, st>>>(n, cfg, (const float*)Xs, ldp, X.d, newf, revnew, oldf,
+                                                          revold, cand, p->seed, iter, counters);
         KNN_HIP(hipGetLastError());
         (void)hipEventRecord(tj.b, st);
         (void)hipEventRecord(tm.a, st);

@@ -118,7 +118,7 @@ typedef struct {
     int32_t proj_count;   /* encoder init: number of sorted orders P (0: 4) */
     int32_t proj_window;  /* encoder init: neighbours taken on each side per order (0: 8) */
     int32_t proj_dims;    /* encoder init: projections per order key D in {1,2,4,8} (0: 8) */
-    int32_t cand_slots;   /* hashed candidate slots per row and iteration, <= 256 (0: 64) */
+    int32_t cand_slots;   /* hashed candidate slots per row and iteration, <= 256 (0: 96 for BF16, 64 for FP32) */
     int32_t join_cap;     /* max candidates one join list sends to one member, <= 4 (0: 4) */
     int64_t workspace_limit_bytes; /* 0: no limit; else KNN_ENOMEM when scratch exceeds it */
 } knn_nnd_params;

@@ -1144,7 +1144,8 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     cfg.s = s;
     cfg.R = s;
     cfg.K = K;
-    cfg.C = p->cand_slots > 0 ? p->cand_slots : 64;
+    // default slot counts: the 1M x 50 sweeps' choices per form
+    cfg.C = p->cand_slots > 0 ? p->cand_slots : (p->precision == KNN_PREC_BF16 ? 96 : 64);
     if (cfg.C > 256) return fail(KNN_ENOTSUP, "cand_slots above 256 is not supported");
     cfg.J = p->join_cap > 0 ? p->join_cap : 4;
     if (cfg.J > kJMax) cfg.J = kJMax;

@@ -859,13 +859,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
 
 // Merge, one half-wave (32 lanes) per row, two rows per wave; the waves take
 // row pairs from 8 contiguous ranges (blockIdx mod 8, as in the sample
-// kernel; gridDim.x is a multiple of 8), the next pair's list and first 64
+// kernel; gridDim.x is a multiple of 8), the next pair's list and first 96
 // slots loaded while the current pair is merged.  Lane hl < K holds list
 // entry hl.  The C candidate slots are read 32 at a time (and reset); keys
 // whose index is already listed (or is the row) are dropped, the rest are
-// compacted into LDS; then each chunk of 32 candidates is sorted and merged
-// into the list by keeping the 32 smallest of the two sorted halves (a
-// bitonic clean), so the first K lanes stay the list.  Old list entries
+// compacted into LDS.  Up to 8 survivors are inserted one at a time; more
+// are sorted 32 at a time and merged into the list by keeping the 32
+// smallest of the two sorted halves (a bitonic clean), so the first K lanes
+// stay the list.  Old list entries
 // carry kWasOld in the index word, so lists are ordered by (distance, old
 // after new, index) -- the order the init kernel also sorts by, which makes
 // a resumed run bitwise equal to an uninterrupted one.  Entries whose index

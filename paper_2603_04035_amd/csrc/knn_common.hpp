@@ -244,6 +244,53 @@ __device__ inline float dist_g16(const void* A, int64_t a_off, const void* B, in
     return wave_sum16(s);
 }
 
+// Squared distances from row `a` to the 4 * NP candidates base .. base +
+// 4 NP - 1: candidate e is lane e's row `cid` (used when `act`).  Each is
+// computed as dist_g16 computes it -- the 16 lanes of a group sum
+// coordinates g, g+16, ... in order, then a fixed 16-lane tree -- four
+// candidates per pass, and every pass's loads of one coordinate step are
+// issued together rather than pass after pass.  Lane e in that range returns
+// candidate e's distance (0 when inactive); other lanes return 0.
+// Rows are ld elements apart in X; inactive candidates read row a.
+template <int DT, int NP>
+__device__ inline float dist_batch16(const void* X, int64_t ld, int64_t a, uint32_t cid, bool act, int d,
+                                     int base = 0)
+{
+    const int lane = lane_id(), g = lane & 15;
+    int64_t off[NP];
+    bool ok[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const int ci = (base + 4 * q + (lane >> 4)) & 63;
+        const uint32_t cj = shfl_u32(cid, ci);
+        ok[q] = shfl_u32(act ? 1u : 0u, ci) != 0u;
+        off[q] = (ok[q] ? (int64_t)cj : a) * ld;
+    }
+    const int64_t ao = a * ld;
+    float part[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) part[q] = 0.0f;
+    for (int t = g; t < d; t += 16) {
+        const float xa = elem<DT>::ld(X, ao + t);
+        float xb[NP];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) xb[q] = elem<DT>::ld(X, off[q] + t);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const float e = xa - xb[q];
+            part[q] = ok[q] ? fmaf(e, e, part[q]) : part[q];
+        }
+    }
+    float mine = 0.0f;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const float v = wave_sum16(part[q]);
+        const float got = shfl_f32(v, ((lane - base - 4 * q) & 3) * 16);
+        if (lane >= base + 4 * q && lane < base + 4 * q + 4) mine = got;
+    }
+    return mine;
+}
+
 // Squared distance of two rows computed by one lane: coordinates in order,
 // FP32 fused multiply-adds on the stored values.  With `vec` (base and both
 // row offsets 16-byte aligned) the rows are read as 16-byte vectors.

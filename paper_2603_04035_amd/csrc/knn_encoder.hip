@@ -675,7 +675,9 @@ __global__ __launch_bounds__(256) void proj_seed_kernel(const void* __restrict__
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     const uint32_t mine = lane < cnt ? sc[wv][lane] : 0xFFFFFFFFu;
-    // lane c computes candidate c's distance over the whole row
+    // lane c computes candidate c's distance over the whole row (16-byte
+    // reads of the candidate's row; the 16-lane grouping reads 2-byte BF16
+    // elements and measured slower here)
     const bool vec = ((uintptr_t)X % 16 == 0) && ((ld * (int64_t)sizeof(typename elem<DT>::T)) % 16 == 0);
     const float dd = lane < cnt ? lane_dist2<DT>(X, i * ld, X, (int64_t)mine * ld, d, vec) : 0.0f;
     uint64_t key = lane < cnt ? make_key(dd, mine) : kEmptyCand;

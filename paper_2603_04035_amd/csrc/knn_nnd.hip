@@ -161,12 +161,15 @@ __global__ __launch_bounds__(256) void nnd_init_kernel(
             if (lane < want && !ok) id = 0xFFFFFFFFu;
         }
     }
-    // 3. distances for entries without one (lane e computes entry e's)
+    // 3. distances for entries without one (entry e's lands in lane e)
     const int cnt = have > want ? have : want;
     const bool need = lane < cnt && !hasd && id != 0xFFFFFFFFu;
-    const float mine = need ? lane_dist2<DT>(Xs, row * ldp, Xs, (int64_t)id * ldp, d,
-                                             (ldp * (int64_t)sizeof(typename elem<DT>::T)) % 16 == 0)
-                            : gd;
+    float dd = 0.0f;
+    if (ballot(need)) {   // seeded lists arrive with their distances
+        dd = dist_batch16<DT, 8>(Xs, ldp, row, id, need, d);
+        if (cnt > 32) dd += dist_batch16<DT, 8>(Xs, ldp, row, id, need, d, 32);
+    }
+    const float mine = need ? dd : gd;
     // 4. sort by (d2, old after new, id) -- the merge's list order -- and keep
     //    the first K; the old flag rides in the index word
     const bool live = lane < cnt && id != 0xFFFFFFFFu;
@@ -1025,43 +1028,8 @@ __global__ __launch_bounds__(256) void nnd_finalize_kernel(
         if (st_d2) st_d2[orow * K + lane] = gd2[row * K + lane];
         if (st_fl) st_fl[orow * K + lane] = gflag[row * K + lane];
     }
-    // Distances of the K <= 32 entries, four per pass through 16-lane
-    // groups as dist_g16 computes them (each lane sums coordinates g, g+16,
-    // ... in order, then a fixed 16-lane tree), with every pass's loads of a
-    // coordinate step issued together instead of pass after pass.
-    constexpr int kPass = 8;
-    const int g = lane & 15;
-    const float* xr = Xs + row * ldp;
-    const float* xc[kPass];
-    bool act[kPass];
-#pragma unroll
-    for (int q = 0; q < kPass; ++q) {
-        const int ci = 4 * q + (lane >> 4);
-        const int32_t cj = (int32_t)shfl_u32((uint32_t)id, ci < 64 ? ci : 0);
-        act[q] = ci < K && cj >= 0;
-        xc[q] = Xs + (int64_t)(act[q] ? cj : 0) * ldp;
-    }
-    float part[kPass];
-#pragma unroll
-    for (int q = 0; q < kPass; ++q) part[q] = 0.0f;
-    for (int t = g; t < d; t += 16) {
-        const float a = xr[t];
-        float b[kPass];
-#pragma unroll
-        for (int q = 0; q < kPass; ++q) b[q] = xc[q][t];
-#pragma unroll
-        for (int q = 0; q < kPass; ++q) {
-            const float e = a - b[q];
-            part[q] = act[q] ? fmaf(e, e, part[q]) : part[q];
-        }
-    }
-    float mine = 0.0f;
-#pragma unroll
-    for (int q = 0; q < kPass; ++q) {
-        const float v = wave_sum16(part[q]);
-        const float got = shfl_f32(v, ((lane - 4 * q) & 3) * 16);
-        if (lane >= 4 * q && lane < 4 * q + 4) mine = got;
-    }
+    // distances of the K <= 32 entries (16-lane groups, passes batched)
+    const float mine = dist_batch16<KNN_F32, 8>(Xs, ldp, row, (uint32_t)id, lane < K && id >= 0, d);
     uint64_t key = (lane < K && id >= 0) ? make_key(mine, (uint32_t)oid) : kEmptyCand;
     key = seg_sort<64>(key);
     if (lane < k) {

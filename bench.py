@@ -308,8 +308,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the kNN graph build here runs on a single device; "
-              "multi-GPU runs are not part of this build (DESIGN.md describes how it would shard).",
+        print("bench.py measures one GPU: the kNN graph build runs on a single device "
+              "and has no multi-GPU path; run it with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 

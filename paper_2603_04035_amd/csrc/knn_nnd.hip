@@ -231,12 +231,65 @@ __host__ __device__ inline uint32_t rev_salt(uint64_t seed, uint64_t tag, int it
 
 __host__ __device__ inline uint32_t rev_code(uint32_t u, uint32_t salt) { return rev_mix(u ^ salt); }
 
+// Sampling of one row held by a half-wave (lane hl of the half holds entry
+// hl; `isnew` / `isold` mark the valid new and old entries): picks the new
+// entries (every one when there are at most s, else the s with the smallest
+// random priorities, ties by position), writes them in list order to
+// newf(row) and the old entries to oldf(row), -1 past the last, and scatters
+// the reverse edges into R slots per target row.  Returns whether this
+// lane's entry was picked (the caller marks it old).
+__device__ inline bool sample_row(int64_t row, bool rv, int K, int s, int R, int32_t id, bool isnew, bool isold,
+                                  int32_t* __restrict__ newf, int32_t* __restrict__ oldf,
+                                  uint32_t* __restrict__ revnew, uint32_t* __restrict__ revold,
+                                  uint64_t seed, int iter)
+{
+    const int lane = threadIdx.x & 63, hl = lane & 31, hbase = lane & 32;
+    const uint64_t nm = ballot(isnew), om = ballot(isold);
+    const uint64_t hn = hbase ? (nm >> 32) : (nm & 0xFFFFFFFFull);
+    const uint64_t ho = hbase ? (om >> 32) : (om & 0xFFFFFFFFull);
+    // the rank loop runs only for a wave that has a row with more than s
+    // new entries
+    bool pick = isnew;
+    if (ballot(__popcll(hn) > (uint64_t)s)) {
+        const uint64_t pr = isnew ? hash4(seed ^ kTagSample, (uint64_t)iter, (uint64_t)row, (uint64_t)id)
+                                  : ~0ull;
+        int prank = 0;
+        for (int o = 0; o < 32; ++o) {
+            const uint64_t p0 = bcast_u64(pr, o), p1 = bcast_u64(pr, 32 + o);
+            const uint64_t po = hbase ? p1 : p0;
+            prank += (po < pr || (po == pr && o < hl)) ? 1 : 0;
+        }
+        pick = isnew && prank < s;
+    }
+    // picks are written in list order
+    const uint64_t pm = ballot(pick);
+    const uint64_t hp = hbase ? (pm >> 32) : (pm & 0xFFFFFFFFull);
+    const int rank = __popcll(hp & ((1ull << hl) - 1ull));
+    const int npick = __popcll(hn) < s ? __popcll(hn) : s;
+    const int nold = __popcll(ho);
+    const int opos = __popcll(ho & ((1ull << hl) - 1ull));
+    // slots past the picks / old entries get -1 (disjoint from the writes below)
+    if (rv && hl >= npick && hl < s) newf[row * s + hl] = -1;
+    if (rv && hl >= nold && hl < K) oldf[row * K + hl] = -1;
+    if (pick) {
+        newf[row * s + rank] = id;
+        const uint32_t slot = bounded(hash4(seed ^ kTagRevSlot, (uint64_t)iter, (uint64_t)row, 1), (uint32_t)R);
+        atomicMin(&revnew[(int64_t)id * R + slot], rev_code((uint32_t)row, rev_salt(seed, kTagRevNew, iter, id)));
+    }
+    if (isold) {
+        oldf[row * K + opos] = id;
+        const uint32_t slot = bounded(hash4(seed ^ kTagRevSlot, (uint64_t)iter, (uint64_t)row, 2), (uint32_t)R);
+        atomicMin(&revold[(int64_t)id * R + slot], rev_code((uint32_t)row, rev_salt(seed, kTagRevOld, iter, id)));
+    }
+    return pick;
+}
+
 __global__ __launch_bounds__(256) void nnd_sample_kernel(
     int64_t n, int K, int s, int R, int32_t* __restrict__ gidx, uint8_t* __restrict__ gflag,
     int32_t* __restrict__ newf, int32_t* __restrict__ oldf, uint32_t* __restrict__ revnew,
     uint32_t* __restrict__ revold, uint64_t seed, int iter)
 {
-    const int lane = threadIdx.x & 63, hl = lane & 31, hbase = lane & 32;
+    const int lane = threadIdx.x & 63, hl = lane & 31;
     const unsigned grp = blockIdx.x & 7u;
     const int64_t lo = n * grp / 8, hi = n * (grp + 1) / 8;
     const int64_t wstep = (int64_t)(gridDim.x >> 3) * 4;
@@ -252,46 +305,29 @@ __global__ __launch_bounds__(256) void nnd_sample_kernel(
         }
         const bool isnew = inl && id >= 0 && fl;
         const bool isold = inl && id >= 0 && !fl;
-        const uint64_t nm = ballot(isnew), om = ballot(isold);
-        const uint64_t hn = hbase ? (nm >> 32) : (nm & 0xFFFFFFFFull);
-        const uint64_t ho = hbase ? (om >> 32) : (om & 0xFFFFFFFFull);
-        // the picks: every new entry when there are at most s, else the s with
-        // the smallest random priorities (ties by position); the rank loop
-        // runs only for a wave that has a row with more than s new entries
-        bool pick = isnew;
-        if (ballot(__popcll(hn) > (uint64_t)s)) {
-            const uint64_t pr = isnew ? hash4(seed ^ kTagSample, (uint64_t)iter, (uint64_t)row, (uint64_t)id)
-                                      : ~0ull;
-            int prank = 0;
-            for (int o = 0; o < 32; ++o) {
-                const uint64_t p0 = bcast_u64(pr, o), p1 = bcast_u64(pr, 32 + o);
-                const uint64_t po = hbase ? p1 : p0;
-                prank += (po < pr || (po == pr && o < hl)) ? 1 : 0;
-            }
-            pick = isnew && prank < s;
-        }
-        // picks are written in list order
-        const uint64_t pm = ballot(pick);
-        const uint64_t hp = hbase ? (pm >> 32) : (pm & 0xFFFFFFFFull);
-        const int rank = __popcll(hp & ((1ull << hl) - 1ull));
-        const int npick = __popcll(hn) < s ? __popcll(hn) : s;
-        const int nold = __popcll(ho);
-        const int opos = __popcll(ho & ((1ull << hl) - 1ull));
-        // slots past the picks / old entries get -1 (disjoint from the writes below)
-        if (rv && hl >= npick && hl < s) newf[row * s + hl] = -1;
-        if (rv && hl >= nold && hl < K) oldf[row * K + hl] = -1;
-        if (pick) {
-            newf[row * s + rank] = id;
+        if (sample_row(row, rv, K, s, R, id, isnew, isold, newf, oldf, revnew, revold, seed, iter))
             gflag[row * K + hl] = 0;
-            const uint32_t slot = bounded(hash4(seed ^ kTagRevSlot, (uint64_t)iter, (uint64_t)row, 1), (uint32_t)R);
-            atomicMin(&revnew[(int64_t)id * R + slot], rev_code((uint32_t)row, rev_salt(seed, kTagRevNew, iter, id)));
-        }
-        if (isold) {
-            oldf[row * K + opos] = id;
-            const uint32_t slot = bounded(hash4(seed ^ kTagRevSlot, (uint64_t)iter, (uint64_t)row, 2), (uint32_t)R);
-            atomicMin(&revold[(int64_t)id * R + slot], rev_code((uint32_t)row, rev_salt(seed, kTagRevOld, iter, id)));
-        }
     }
+}
+
+// Undoes the flag changes of a sampling whose iteration is not run: an
+// entry of row v that is listed in newf(v) was new before it was picked.
+// Half-wave per row, as the sample kernel.
+__global__ __launch_bounds__(256) void nnd_unsample_kernel(int64_t n, int K, int s, const int32_t* __restrict__ gidx,
+                                                           uint8_t* __restrict__ gflag,
+                                                           const int32_t* __restrict__ newf)
+{
+    const int lane = threadIdx.x & 63, hl = lane & 31, hbase = lane & 32;
+    const int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 5;
+    if (row >= n) return;   // uniform per half-wave; no cross-lane op follows
+    const int32_t id = hl < K ? gidx[row * K + hl] : -1;
+    const int32_t nf = hl < s ? newf[row * s + hl] : -1;
+    bool was = false;
+    for (int j = 0; j < s; ++j) {
+        const int32_t x = (int32_t)shfl_u32((uint32_t)nf, hbase + j);
+        was = was || (id >= 0 && x == id);
+    }
+    if (was) gflag[row * K + hl] = 1;
 }
 
 // ------------------------------------------------------------------ join
@@ -860,6 +896,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
 
 // ------------------------------------------------------------------ merge
 
+// Arguments of the sampling that the merge can run for the next iteration.
+struct SampleArgs {
+    int s, R;
+    int32_t* newf;
+    int32_t* oldf;
+    uint32_t* revnew;
+    uint32_t* revold;
+    uint64_t seed;
+    int iter;
+};
+
 // Merge, one half-wave (32 lanes) per row, two rows per wave; the waves take
 // row pairs from 8 contiguous ranges (blockIdx mod 8, as in the sample
 // kernel; gridDim.x is a multiple of 8), the next pair's list and first 96
@@ -869,16 +916,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
 // compacted into LDS.  Up to 8 survivors are inserted one at a time; more
 // are sorted 32 at a time and merged into the list by keeping the 32
 // smallest of the two sorted halves (a bitonic clean), so the first K lanes
-// stay the list.  Old list entries
-// carry kWasOld in the index word, so lists are ordered by (distance, old
-// after new, index) -- the order the init kernel also sorts by, which makes
-// a resumed run bitwise equal to an uninterrupted one.  Entries whose index
-// is not in the previous list came from slots: flagged new and counted.  The
-// new K-th distance goes to the row's worst-distance word.
+// stay the list.  Old list entries carry kWasOld in the index word, so
+// lists are ordered by (distance, old after new, index) -- the order the
+// init kernel also sorts by, which makes a resumed run bitwise equal to an
+// uninterrupted one.  Entries whose index is not in the previous list came
+// from slots: flagged new and counted.  The new K-th distance goes to the
+// row's worst-distance word.  With Smp the merged row is also sampled for
+// the next iteration (sample_row, the picks stored old), so that the
+// reverse-slot atomics of the sampling overlap the merge work of other
+// waves; every row is then rewritten.
+template <bool Smp>
 __global__ __launch_bounds__(256) void nnd_merge_kernel(
     int64_t n, int K, int C, int32_t* __restrict__ gidx, float* __restrict__ gd2,
     uint8_t* __restrict__ gflag, unsigned long long* __restrict__ cand,
-    unsigned long long* __restrict__ counters, float* __restrict__ worst, int64_t wstride)
+    unsigned long long* __restrict__ counters, float* __restrict__ worst, int64_t wstride,
+    SampleArgs sa)
 {
     extern __shared__ uint64_t sbuf_all[];
     __shared__ __attribute__((aligned(16))) uint32_t slid[8][32];
@@ -954,7 +1006,7 @@ __global__ __launch_bounds__(256) void nnd_merge_kernel(
             if (keep) sbuf[nc + __popcll(hm & below)] = key;
             nc += __popcll(hm);
         }
-        if (!ballot(nc > 0)) continue;
+        if (!Smp && !ballot(nc > 0)) continue;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -992,11 +1044,26 @@ __global__ __launch_bounds__(256) void nnd_merge_kernel(
             from_list = from_list || x.x == cidx || x.y == cidx || x.z == cidx || x.w == cidx;
         }
         upd += (unsigned long long)popc64(ballot(hl < K && nc > 0 && sv && !from_list));
-        if (nc > 0 && hl < K) {
-            gidx[row * K + hl] = sv ? (int32_t)cidx : -1;
-            gd2[row * K + hl] = sv ? key_d2(cur) : __builtin_inff();
-            gflag[row * K + hl] = sv ? (uint8_t)((w & kWasOld) ? 0 : 1) : 0;
-            if (hl == K - 1) worst[row * wstride] = sv ? key_d2(cur) : __builtin_inff();
+        if (!Smp) {
+            if (nc > 0 && hl < K) {
+                gidx[row * K + hl] = sv ? (int32_t)cidx : -1;
+                gd2[row * K + hl] = sv ? key_d2(cur) : __builtin_inff();
+                gflag[row * K + hl] = sv ? (uint8_t)((w & kWasOld) ? 0 : 1) : 0;
+                if (hl == K - 1) worst[row * wstride] = sv ? key_d2(cur) : __builtin_inff();
+            }
+        } else {
+            // the next iteration's sampling of the merged row: every row is
+            // written (its list may have been re-sorted), picks marked old
+            const bool inl = rv && hl < K && sv;
+            const bool isnew = inl && !(w & kWasOld), isold = inl && (w & kWasOld);
+            const bool pick = sample_row(row, rv, K, sa.s, sa.R, (int32_t)cidx, isnew, isold, sa.newf, sa.oldf,
+                                         sa.revnew, sa.revold, sa.seed, sa.iter);
+            if (rv && hl < K) {
+                gidx[row * K + hl] = sv ? (int32_t)cidx : -1;
+                gd2[row * K + hl] = sv ? key_d2(cur) : __builtin_inff();
+                gflag[row * K + hl] = isnew && !pick ? 1 : 0;
+                if (hl == K - 1) worst[row * wstride] = sv ? key_d2(cur) : __builtin_inff();
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
@@ -1222,7 +1289,8 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     // second round of blocks would run on an otherwise idle chip), rounded to
     // a multiple of 8: they split their grids into 8 contiguous row ranges
     int mpc = 0, spc = 0;
-    KNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&mpc, (const void*)nnd_merge_kernel, 256, merge_lds));
+    KNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&mpc, (const void*)nnd_merge_kernel<true>, 256,
+                                                         merge_lds));
     KNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&spc, (const void*)nnd_sample_kernel, 256, 0));
     if (mpc < 1) mpc = 1;
     if (spc < 1) spc = 1;
@@ -1235,11 +1303,13 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     for (int it = 0; it < p->max_iters; ++it) {
         const int iter = iter_offset + it;
         KNN_HIP(hipMemsetAsync(counters, 0, 32, st));
-        (void)hipEventRecord(ts.a, st);
-        nnd_sample_kernel<<<sample_grid, 256, 0, st>>>(n, K, s, cfg.R, gidx, gflag, newf, oldf, revnew, revold,
-                                                       p->seed, iter);
-        KNN_HIP(hipGetLastError());
-        (void)hipEventRecord(ts.b, st);
+        if (it == 0) {   // later iterations are sampled by the previous merge
+            (void)hipEventRecord(ts.a, st);
+            nnd_sample_kernel<<<sample_grid, 256, 0, st>>>(n, K, s, cfg.R, gidx, gflag, newf, oldf, revnew,
+                                                           revold, p->seed, iter);
+            KNN_HIP(hipGetLastError());
+            (void)hipEventRecord(ts.b, st);
+        }
         (void)hipEventRecord(tj.a, st);
         if (bf)
             nnd_join_bf16_kernel<<<join_grid, 64, 0, st>>>(n, cfg, Xr, rowbytes, np, newf, revnew, oldf, revold,
@@ -1249,16 +1319,27 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
                                                           revold, cand, p->seed, iter, counters);
         KNN_HIP(hipGetLastError());
         (void)hipEventRecord(tj.b, st);
+        // the merge samples the next iteration unless this is the last one
+        // allowed; if the stop rule ends the run instead, that sampling's
+        // flag changes are undone below
+        const bool smp = it + 1 < p->max_iters;
+        const SampleArgs sa = {s, cfg.R, newf, oldf, revnew, revold, p->seed, iter + 1};
         (void)hipEventRecord(tm.a, st);
-        nnd_merge_kernel<<<merge_grid, 256, merge_lds, st>>>(n, K, cfg.C, gidx, gd2, gflag, cand, counters,
-                                                             worst, wstride);
+        if (smp)
+            nnd_merge_kernel<true><<<merge_grid, 256, merge_lds, st>>>(n, K, cfg.C, gidx, gd2, gflag, cand,
+                                                                       counters, worst, wstride, sa);
+        else
+            nnd_merge_kernel<false><<<merge_grid, 256, merge_lds, st>>>(n, K, cfg.C, gidx, gd2, gflag, cand,
+                                                                        counters, worst, wstride, sa);
         KNN_HIP(hipGetLastError());
         (void)hipEventRecord(tm.b, st);
         KNN_HIP(hipMemcpyAsync(host_cnt, counters, 32, hipMemcpyDeviceToHost, st));
         KNN_HIP(hipStreamSynchronize(st));
         float ms = 0;
-        (void)hipEventElapsedTime(&ms, ts.a, ts.b);
-        ms_sample += ms;
+        if (it == 0) {
+            (void)hipEventElapsedTime(&ms, ts.a, ts.b);
+            ms_sample += ms;
+        }
         (void)hipEventElapsedTime(&ms, tj.a, tj.b);
         ms_join += ms;
         if (stats && it < KNN_MAX_ITERS_LOGGED) stats->ms_join_iter[it] = ms;
@@ -1270,7 +1351,13 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
             stats->emitted[it] = (int64_t)host_cnt[1];
         }
         ++iters;
-        if ((double)host_cnt[0] < stop) break;
+        if ((double)host_cnt[0] < stop) {
+            if (smp) {
+                nnd_unsample_kernel<<<(unsigned)ceil_div(n, 8), 256, 0, st>>>(n, K, s, gidx, gflag, newf);
+                KNN_HIP(hipGetLastError());
+            }
+            break;
+        }
     }
 
     // ---- finalize

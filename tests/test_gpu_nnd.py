@@ -87,6 +87,28 @@ def test_resume_is_bitwise():
     assert full[2]["updates"][4:] == rest[2]["updates"]
 
 
+def test_stop_rule_state_equals_fixed_iterations():
+    """A run ended by the stop rule leaves the same state (lists, distances
+    and new/old flags) as a run capped at that many iterations, and resumes
+    from it as an uninterrupted run does: the next iteration's sampling,
+    already done when the rule fires, is undone."""
+    import paper_2603_04035_amd as knn
+    X = _dev(datagen.gmm_isotropic(n=5000, d=16, seed=9))
+    ruled = knn.nndescent_build(X, 10, max_iters=30, delta=0.015, return_state=True)
+    T = ruled[2]["iters"]
+    assert 0 < T < 30
+    capped = knn.nndescent_build(X, 10, max_iters=T, delta=0.0, return_state=True)
+    for a, b in zip(ruled[3], capped[3]):
+        assert torch.equal(a, b)
+    assert torch.equal(ruled[0], capped[0]) and torch.equal(ruled[1], capped[1])
+    si, sd, sf = ruled[3]
+    rest = knn.nndescent_refine(X, 10, si, init_dist=sd, init_flags=sf, iter_offset=T,
+                                max_iters=2, delta=0.0, return_state=True)
+    longer = knn.nndescent_build(X, 10, max_iters=T + 2, delta=0.0, return_state=True)
+    for a, b in zip(longer[3], rest[3]):
+        assert torch.equal(a, b)
+
+
 def test_k_n_minus_one_and_tiny(orc):
     for n in (2, 3, 9, 33):
         X = datagen.gmm_isotropic(n=n, d=4, seed=n)

@@ -134,8 +134,9 @@ typedef struct {
     int64_t updates[KNN_MAX_ITERS_LOGGED];    /* list insertions per iteration */
     int64_t emitted[KNN_MAX_ITERS_LOGGED];    /* candidates sent to the slot buffers */
     uint64_t bytes_gathered;                  /* algorithmic row bytes gathered by local joins */
-    /* wall times (ms) of the phases; the first iteration is sampled by its
-     * own kernel (ms_sample), later ones inside the previous merge (ms_merge) */
+    /* wall times (ms) of the phases; new/old sampling runs inside the init
+     * kernel (first iteration) and the merges (later ones) and is counted
+     * there, so ms_sample is 0 */
     double ms_total, ms_init, ms_sample, ms_join, ms_merge, ms_final;
     float ms_join_iter[KNN_MAX_ITERS_LOGGED]; /* local-join kernel time per iteration */
 } knn_nnd_stats;

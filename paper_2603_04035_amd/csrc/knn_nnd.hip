@@ -44,13 +44,31 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr uint32_t kWasOld = 1u << 31;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
+// Arguments of the sampling that the init and merge kernels run for the
+// iteration that follows them (see sample_row).
+struct SampleArgs {
+    int s, R;
+    int32_t* newf;
+    int32_t* oldf;
+    uint32_t* revnew;
+    uint32_t* revold;
+    uint64_t seed;
+    int iter;
+};
+
+__device__ inline bool sample_row(int64_t row, bool rv, int K, int s, int R, int32_t id, bool isnew, bool isold,
+                                  int32_t* __restrict__ newf, int32_t* __restrict__ oldf,
+                                  uint32_t* __restrict__ revnew, uint32_t* __restrict__ revold,
+                                  uint64_t seed, int iter);
+
 // ------------------------------------------------------------------ init
 
 // One wave per row: entries from init_idx (nullable; invalid, self and
 // repeated entries dropped), completed with distinct uniform random indices,
 // distances (given, or canonical direct differences on the staged rows),
 // sorted, first K kept.  Flags: given (or new).  The K-th distance is also
-// written to the row's worst-distance word (worst[row * wstride]).
+// written to the row's worst-distance word (worst[row * wstride]).  With
+// smp the row is then sampled for the first iteration (sample_row).
 template <int DT>
 __global__ __launch_bounds__(256) void nnd_init_kernel(
     int64_t n, int K, const void* __restrict__ Xs, int64_t ldp, int d,
@@ -58,7 +76,7 @@ __global__ __launch_bounds__(256) void nnd_init_kernel(
     const uint8_t* __restrict__ init_flags, int init_k, uint64_t seed,
     int32_t* __restrict__ gidx, float* __restrict__ gd2, uint8_t* __restrict__ gflag,
     const uint32_t* __restrict__ perm, const uint32_t* __restrict__ inv, float* __restrict__ worst,
-    int64_t wstride)
+    int64_t wstride, SampleArgs sa, bool smp)
 {
     __shared__ uint32_t s_id[4][64];
     __shared__ float s_d2[4][64];
@@ -176,24 +194,29 @@ __global__ __launch_bounds__(256) void nnd_init_kernel(
     const uint64_t key = live ? make_key(mine, id | (fl ? 0u : kWasOld)) : kEmptyCand;
     const uint64_t sk = seg_sort<64>(key);
     const uint8_t sfl = (key_idx(sk) & kWasOld) ? 0 : 1;
+    const bool sv = lane < K && key_valid(sk);
+    // 5. with smp, the first iteration's sampling of the row (K <= 32: the
+    //    row is the first half-wave's), picks stored old
+    bool pick = false;
+    if (smp) {
+        const int32_t eid = (int32_t)(key_idx(sk) & ~kWasOld);
+        pick = sample_row(row, lane < 32, K, sa.s, sa.R, eid, sv && sfl, sv && !sfl, sa.newf, sa.oldf, sa.revnew,
+                          sa.revold, sa.seed, sa.iter);
+    }
     if (lane < K) {
-        const bool sv = key_valid(sk);
         gidx[row * K + lane] = sv ? (int32_t)(key_idx(sk) & ~kWasOld) : -1;
         gd2[row * K + lane] = sv ? key_d2(sk) : __builtin_inff();
-        gflag[row * K + lane] = sv ? sfl : 0;
+        gflag[row * K + lane] = sv && !pick ? sfl : 0;
         if (lane == K - 1) worst[row * wstride] = sv ? key_d2(sk) : __builtin_inff();
     }
 }
 
 // ---------------------------------------------------------------- sample
 
-// Half-wave (32 lanes) per row, K <= 32.  Picks the new entries (the s with
-// the smallest random priorities, ties by position, when there are more than
-// s), writes them in list order and marks them old, lists old entries, and
-// scatters reverse edges into R slots per target row.  Waves take row
-// pairs from contiguous ranges, one range per group of blockIdx mod 8 (the
-// XCD of the workgroup), so the scattered targets of concurrent rows are
-// mostly Z-order neighbours.  gridDim.x is a multiple of 8.
+// Sampling runs inside the kernels that produce a row's list: the init
+// kernel samples the first iteration and each merge the next one, so that
+// the sampling's random reverse-slot atomics overlap their other work.
+//
 // Reverse-slot codes.  A reverse slot of point v holds, as a 32-bit word,
 // the least code among the sources u that picked that slot this iteration:
 // code = mix(u ^ salt(v)), where mix is an invertible 32-bit mixer and the
@@ -284,42 +307,16 @@ __device__ inline bool sample_row(int64_t row, bool rv, int K, int s, int R, int
     return pick;
 }
 
-__global__ __launch_bounds__(256) void nnd_sample_kernel(
-    int64_t n, int K, int s, int R, int32_t* __restrict__ gidx, uint8_t* __restrict__ gflag,
-    int32_t* __restrict__ newf, int32_t* __restrict__ oldf, uint32_t* __restrict__ revnew,
-    uint32_t* __restrict__ revold, uint64_t seed, int iter)
-{
-    const int lane = threadIdx.x & 63, hl = lane & 31;
-    const unsigned grp = blockIdx.x & 7u;
-    const int64_t lo = n * grp / 8, hi = n * (grp + 1) / 8;
-    const int64_t wstep = (int64_t)(gridDim.x >> 3) * 4;
-    for (int64_t pw = (int64_t)(blockIdx.x >> 3) * 4 + (threadIdx.x >> 6); lo + 2 * pw < hi; pw += wstep) {
-        const int64_t row = lo + 2 * pw + (lane >> 5);
-        const bool rv = row < hi;
-        const bool inl = rv && hl < K;
-        int32_t id = -1;
-        uint8_t fl = 0;
-        if (inl) {
-            id = gidx[row * K + hl];
-            fl = gflag[row * K + hl];
-        }
-        const bool isnew = inl && id >= 0 && fl;
-        const bool isold = inl && id >= 0 && !fl;
-        if (sample_row(row, rv, K, s, R, id, isnew, isold, newf, oldf, revnew, revold, seed, iter))
-            gflag[row * K + hl] = 0;
-    }
-}
-
 // Undoes the flag changes of a sampling whose iteration is not run: an
 // entry of row v that is listed in newf(v) was new before it was picked.
-// Half-wave per row, as the sample kernel.
+// Half-wave per row.
 __global__ __launch_bounds__(256) void nnd_unsample_kernel(int64_t n, int K, int s, const int32_t* __restrict__ gidx,
                                                            uint8_t* __restrict__ gflag,
                                                            const int32_t* __restrict__ newf)
 {
     const int lane = threadIdx.x & 63, hl = lane & 31, hbase = lane & 32;
     const int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 5;
-    if (row >= n) return;   // uniform per half-wave; no cross-lane op follows
+    if (row >= n) return;   // uniform per half-wave; the shuffles below read the own half only
     const int32_t id = hl < K ? gidx[row * K + hl] : -1;
     const int32_t nf = hl < s ? newf[row * s + hl] : -1;
     bool was = false;
@@ -896,17 +893,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
 
 // ------------------------------------------------------------------ merge
 
-// Arguments of the sampling that the merge can run for the next iteration.
-struct SampleArgs {
-    int s, R;
-    int32_t* newf;
-    int32_t* oldf;
-    uint32_t* revnew;
-    uint32_t* revold;
-    uint64_t seed;
-    int iter;
-};
-
 // Merge, one half-wave (32 lanes) per row, two rows per wave; the waves take
 // row pairs from 8 contiguous ranges (blockIdx mod 8, as in the sample
 // kernel; gridDim.x is a multiple of 8), the next pair's list and first 96
@@ -1010,7 +996,7 @@ __global__ __launch_bounds__(256) void nnd_merge_kernel(
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        // the sample kernel may have turned entries old since the list was
+        // the sampling may have turned entries old since the list was
         // sorted, which can reorder equal distances: re-sort if needed
         const uint64_t nxt = shfl_u64(cur, lane + 1 < 64 ? lane + 1 : lane);
         if (ballot(hl < 31 && cur > nxt)) cur = seg_sort<32>(cur);
@@ -1263,9 +1249,12 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         // caller lists are in input order, encoder seeds already in processing order
         const int sk = seed_idx ? seed_k : 0;
         const bool given = init_idx != nullptr;
+        // the first iteration (if any) is sampled by the init kernel
+        const SampleArgs sa = {s, cfg.R, newf, oldf, revnew, revold, p->seed, iter_offset};
         nnd_init_kernel<KNN_F32><<<grid, 256, 0, st>>>(n, K, Xs, ldp, X.d, seed_idx, seed_d2, seed_fl, sk, p->seed,
                                                        gidx, gd2, gflag, given ? perm : nullptr,
-                                                       given ? inv : nullptr, worst, wstride);
+                                                       given ? inv : nullptr, worst, wstride, sa,
+                                                       p->max_iters > 0);
         KNN_HIP(hipGetLastError());
     }
     (void)hipEventRecord(t_init.b, st);
@@ -1288,28 +1277,19 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     // grid-stride kernels get exactly the resident block count (a partial
     // second round of blocks would run on an otherwise idle chip), rounded to
     // a multiple of 8: they split their grids into 8 contiguous row ranges
-    int mpc = 0, spc = 0;
+    int mpc = 0;
     KNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&mpc, (const void*)nnd_merge_kernel<true>, 256,
                                                          merge_lds));
-    KNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&spc, (const void*)nnd_sample_kernel, 256, 0));
     if (mpc < 1) mpc = 1;
-    if (spc < 1) spc = 1;
     const unsigned merge_grid = (unsigned)round_up(std::min<int64_t>(ceil_div(n, 8), (int64_t)ncu * mpc), 8);
-    const unsigned sample_grid = (unsigned)round_up(std::min<int64_t>(ceil_div(n, 8), (int64_t)ncu * spc), 8);
     int iters = 0;
-    double ms_sample = 0, ms_join = 0, ms_merge = 0;
+    double ms_join = 0, ms_merge = 0;
     uint64_t gathered = 0;
-    Timer ts, tj, tm;
+    Timer tj, tm;
     for (int it = 0; it < p->max_iters; ++it) {
         const int iter = iter_offset + it;
         KNN_HIP(hipMemsetAsync(counters, 0, 32, st));
-        if (it == 0) {   // later iterations are sampled by the previous merge
-            (void)hipEventRecord(ts.a, st);
-            nnd_sample_kernel<<<sample_grid, 256, 0, st>>>(n, K, s, cfg.R, gidx, gflag, newf, oldf, revnew,
-                                                           revold, p->seed, iter);
-            KNN_HIP(hipGetLastError());
-            (void)hipEventRecord(ts.b, st);
-        }
+        // iteration `iter` was sampled by the init kernel or the previous merge
         (void)hipEventRecord(tj.a, st);
         if (bf)
             nnd_join_bf16_kernel<<<join_grid, 64, 0, st>>>(n, cfg, Xr, rowbytes, np, newf, revnew, oldf, revold,
@@ -1336,10 +1316,6 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         KNN_HIP(hipMemcpyAsync(host_cnt, counters, 32, hipMemcpyDeviceToHost, st));
         KNN_HIP(hipStreamSynchronize(st));
         float ms = 0;
-        if (it == 0) {
-            (void)hipEventElapsedTime(&ms, ts.a, ts.b);
-            ms_sample += ms;
-        }
         (void)hipEventElapsedTime(&ms, tj.a, tj.b);
         ms_join += ms;
         if (stats && it < KNN_MAX_ITERS_LOGGED) stats->ms_join_iter[it] = ms;
@@ -1389,7 +1365,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         stats->ms_init = ms;
         (void)hipEventElapsedTime(&ms, t_fin.a, t_fin.b);
         stats->ms_final = ms;
-        stats->ms_sample = ms_sample;
+        stats->ms_sample = 0.0;   // sampled inside the init and merge kernels
         stats->ms_join = ms_join;
         stats->ms_merge = ms_merge;
     }

@@ -630,26 +630,111 @@ __global__ __launch_bounds__(256) void xproj_kernel(const void* __restrict__ X, 
     }
 }
 
-// One wave per point: window candidates from every order (lane = (p, side,
-// offset)), repeats and self dropped, FP32 distances (one candidate per
-// lane), best K sorted.
-template <int DT>
-__global__ __launch_bounds__(256) void proj_seed_kernel(const void* __restrict__ X, int64_t ld, int d, int64_t n,
-                                                        const uint32_t* __restrict__ order,
-                                                        const uint32_t* __restrict__ pos, int P, int w, int K,
+// Window distances of one sorted order (blockIdx.y = p).  A block owns the
+// 256 - w positions [t0, t0 + 256 - w) and its thread j takes position
+// t = t0 - w + j: the canonical FP32 distances from that point to the points
+// at t + 1 .. t + w (sequential fused multiply-adds over the coordinates in
+// order, one lane per pair), so each window pair is computed once per order.
+// The rows of the block's 256 + w positions are staged in LDS 128 bytes
+// (CH elements) at a time, zero past d (a zero difference leaves a sum
+// unchanged), with a 16-byte pad per row so that lanes reading consecutive
+// rows hit distinct banks.  Owned positions then list their w predecessors
+// (slots 0 .. w-1, nearest first; the distances come from the predecessors'
+// threads through LDS) and w successors (slots w .. 2w-1) in their point's
+// row of win_idx / win_d2, order p at slots [2wp, 2wp + 2w); positions past
+// either end get index -1.  The squared difference of two values does not
+// depend on their order, so a pair's distance is the one the point on
+// either side would compute.
+template <int DT, int W>
+__global__ __launch_bounds__(256) void window_dist_kernel(const void* __restrict__ X, int64_t ld, int d, int64_t n,
+                                                          const uint32_t* __restrict__ order, int w, int PW, bool vec,
+                                                          int32_t* __restrict__ win_idx, float* __restrict__ win_d2)
+{
+    using T = typename elem<DT>::T;
+    constexpr int V = 16 / (int)sizeof(T);   // elements per 16-byte vector
+    constexpr int CH = 8 * V;                // elements per staged chunk (128 bytes of a row)
+    constexpr int RS = 9;                    // LDS row stride in 16-byte vectors
+    extern __shared__ uint4 tile[];          // (256 + w) x RS vectors; reused for the distances
+    __shared__ uint32_t rid[256 + 32];
+    const int p = blockIdx.y, j = threadIdx.x, nr = 256 + w;
+    const int64_t base = (int64_t)blockIdx.x * (256 - w) - w;   // position of staged row 0 (= thread 0)
+    const uint32_t* ord = order + (int64_t)p * n;
+    for (int r = j; r < nr; r += 256) {
+        const int64_t t = base + r;
+        rid[r] = t >= 0 && t < n ? ord[t] : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    float sum[W];
+#pragma unroll
+    for (int o = 0; o < W; ++o) sum[o] = 0.0f;
+    for (int c0 = 0; c0 < d; c0 += CH) {
+        for (int q = j; q < nr * 8; q += 256) {
+            const int r = q >> 3, e0 = c0 + (q & 7) * V;
+            const uint32_t id = rid[r];
+            uint4 x = make_uint4(0u, 0u, 0u, 0u);
+            if (id != 0xFFFFFFFFu && e0 < d) {
+                const T* src = (const T*)X + (int64_t)id * ld + e0;
+                if (vec && e0 + V <= d) {
+                    x = *(const uint4*)src;
+                } else {
+                    T tmp[V];
+#pragma unroll
+                    for (int e = 0; e < V; ++e) tmp[e] = e0 + e < d ? src[e] : T(0);
+                    __builtin_memcpy(&x, tmp, sizeof(x));
+                }
+            }
+            tile[r * RS + (q & 7)] = x;
+        }
+        __syncthreads();
+        const int nv = min(8, (d - c0 + V - 1) / V);
+        for (int v = 0; v < nv; ++v) {
+            const uint4 ua = tile[j * RS + v];
+            const T* pa = (const T*)&ua;
+#pragma unroll
+            for (int o = 0; o < W; ++o) {
+                if (o < w) {
+                    const uint4 ub = tile[(j + o + 1) * RS + v];
+                    const T* pb = (const T*)&ub;
+#pragma unroll
+                    for (int e = 0; e < V; ++e) {
+                        const float x = elem<DT>::ld(pa, e) - elem<DT>::ld(pb, e);
+                        sum[o] = fmaf(x, x, sum[o]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    float* fd = (float*)tile;   // fd[o * 256 + j]: distance of staged row j to row j + o + 1
+    const int64_t t = base + j;
+    const bool live = t >= 0 && t < n;
+#pragma unroll
+    for (int o = 0; o < W; ++o)
+        if (o < w) fd[o * 256 + j] = sum[o];
+    __syncthreads();
+    if (j < w || !live) return;
+    const int64_t row = (int64_t)rid[j] * PW + (int64_t)p * 2 * w;
+    for (int o = 1; o <= w; ++o) {
+        const bool lv = t - o >= 0, rv = t + o < n;
+        win_idx[row + o - 1] = lv ? (int32_t)rid[j - o] : -1;
+        win_d2[row + o - 1] = lv ? fd[(o - 1) * 256 + j - o] : 0.0f;
+        win_idx[row + w + o - 1] = rv ? (int32_t)rid[j + o] : -1;
+        win_d2[row + w + o - 1] = rv ? fd[(o - 1) * 256 + j] : 0.0f;
+    }
+}
+
+// One wave per point: its PW = 2wP window entries (lane = (p, side,
+// offset)), repeats and self dropped (a repeat carries the same distance),
+// best K by (distance, index), sorted.
+__global__ __launch_bounds__(256) void proj_seed_kernel(int64_t n, const int32_t* __restrict__ win_idx,
+                                                        const float* __restrict__ win_d2, int PW, int K,
                                                         int32_t* __restrict__ out_idx, float* __restrict__ out_d2)
 {
     const int lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= n) return;
-    uint32_t cand = 0xFFFFFFFFu;
-    const int per = 2 * w;
-    if (lane < per * P) {
-        const int p = lane / per, o = lane % per;
-        const int64_t r0 = pos[(int64_t)p * n + i];
-        const int64_t r = o < w ? r0 - (o + 1) : r0 + (o - w + 1);
-        if (r >= 0 && r < n) cand = order[(int64_t)p * n + r];
-    }
+    const uint32_t cand = lane < PW ? (uint32_t)win_idx[i * PW + lane] : 0xFFFFFFFFu;
+    const float cd = lane < PW ? win_d2[i * PW + lane] : 0.0f;
     // repeats: every lane compares with all earlier lanes through LDS broadcasts
     __shared__ __attribute__((aligned(16))) uint32_t sc[4][64];
     const int wv = threadIdx.x >> 6;
@@ -664,23 +749,7 @@ __global__ __launch_bounds__(256) void proj_seed_kernel(const void* __restrict__
         ok = ok && !(o + 0 < lane && x.x == cand) && !(o + 1 < lane && x.y == cand) &&
              !(o + 2 < lane && x.z == cand) && !(o + 3 < lane && x.w == cand);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    // compact, then 4 candidates per pass through the 16-lane distance groups
-    const uint64_t mk = ballot(ok);
-    const int cnt = popc64(mk);
-    if (ok) sc[wv][rank_below(mk)] = cand;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const uint32_t mine = lane < cnt ? sc[wv][lane] : 0xFFFFFFFFu;
-    // lane c computes candidate c's distance over the whole row (16-byte
-    // reads of the candidate's row; the 16-lane grouping reads 2-byte BF16
-    // elements and measured slower here)
-    const bool vec = ((uintptr_t)X % 16 == 0) && ((ld * (int64_t)sizeof(typename elem<DT>::T)) % 16 == 0);
-    const float dd = lane < cnt ? lane_dist2<DT>(X, i * ld, X, (int64_t)mine * ld, d, vec) : 0.0f;
-    uint64_t key = lane < cnt ? make_key(dd, mine) : kEmptyCand;
+    uint64_t key = ok ? make_key(cd, cand) : kEmptyCand;
     key = seg_sort<64>(key);
     if (lane < K) {
         const bool v = key_valid(key);
@@ -701,7 +770,7 @@ static knn_status proj_seed_impl(const knn_matrix& X, const float* Z, int m, con
                                  int w, int K, int32_t* out_idx, float* out_d2, Workspace& ws, hipStream_t st)
 {
     const int64_t n = X.n;
-    uint32_t *keys, *vals, *k1, *v1, *pos, *counts, *lohi;
+    uint32_t *keys, *vals, *k1, *v1, *counts, *lohi;
     float* Y;
     knn_status r;
     if ((r = ws.alloc(&Y, (size_t)n * P * D)) != KNN_OK) return r;
@@ -710,7 +779,6 @@ static knn_status proj_seed_impl(const knn_matrix& X, const float* Z, int m, con
     if ((r = ws.alloc(&vals, (size_t)n * P)) != KNN_OK) return r;
     if ((r = ws.alloc(&k1, (size_t)n)) != KNN_OK) return r;
     if ((r = ws.alloc(&v1, (size_t)n)) != KNN_OK) return r;
-    if ((r = ws.alloc(&pos, (size_t)n * P)) != KNN_OK) return r;
     if ((r = ws.alloc(&counts, rs_counts(n))) != KNN_OK) return r;
     const unsigned g = (unsigned)ceil_div(n, 256);
     if (m <= 32) proj_vals_kernel<32><<<g, 256, 0, st>>>(Z, n, m, dirs, P * D, Y);
@@ -724,13 +792,29 @@ static knn_status proj_seed_impl(const knn_matrix& X, const float* Z, int m, con
     for (int p = 0; p < P; ++p) {
         r = radix_sort_pairs(keys + (int64_t)p * n, vals + (int64_t)p * n, k1, v1, n, counts, st);
         if (r != KNN_OK) return r;
-        inverse_perm_kernel<<<g, 256, 0, st>>>(vals + (int64_t)p * n, n, pos + (int64_t)p * n);
-        KNN_HIP(hipGetLastError());
     }
+    // window distances per order, then each point's best K of its windows
+    const int PW = 2 * w * P;
+    int32_t* wi;
+    float* wd;
+    if ((r = ws.alloc(&wi, (size_t)n * PW)) != KNN_OK) return r;
+    if ((r = ws.alloc(&wd, (size_t)n * PW)) != KNN_OK) return r;
+    const int64_t eb = X.dtype == KNN_F32 ? 4 : 2;
+    const bool vec = ((uintptr_t)X.data % 16 == 0) && ((X.ld * eb) % 16 == 0);
+    const dim3 wgrid((unsigned)ceil_div(n, 256 - w), (unsigned)P);
+    // staged rows, or the distances of every thread, whichever is larger
+    const size_t lds = std::max((size_t)(256 + w) * 9 * 16, (size_t)w * 256 * sizeof(float));
     by_dtype(X.dtype, [&](auto dt) {
-        proj_seed_kernel<decltype(dt)::value><<<(unsigned)ceil_div(n, 4), 256, 0, st>>>(
-            X.data, X.ld, X.d, n, vals, pos, P, w, K, out_idx, out_d2);
+        constexpr int DT = decltype(dt)::value;
+        if (w <= 8)
+            window_dist_kernel<DT, 8><<<wgrid, 256, lds, st>>>(X.data, X.ld, X.d, n, vals, w, PW, vec, wi, wd);
+        else if (w <= 16)
+            window_dist_kernel<DT, 16><<<wgrid, 256, lds, st>>>(X.data, X.ld, X.d, n, vals, w, PW, vec, wi, wd);
+        else
+            window_dist_kernel<DT, 32><<<wgrid, 256, lds, st>>>(X.data, X.ld, X.d, n, vals, w, PW, vec, wi, wd);
     });
+    KNN_HIP(hipGetLastError());
+    proj_seed_kernel<<<(unsigned)ceil_div(n, 4), 256, 0, st>>>(n, wi, wd, PW, K, out_idx, out_d2);
     KNN_HIP(hipGetLastError());
     return KNN_OK;
 }

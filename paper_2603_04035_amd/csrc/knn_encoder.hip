@@ -766,8 +766,12 @@ static void by_dtype(int dt, F&& f)
     else f(std::integral_constant<int, KNN_F16>());
 }
 
+// Seeds from sorted projections.  With `win_idx` the ranking is left to the
+// caller: the 2wP window entries of every point (index, squared distance;
+// n x 2wP each) are returned there and out_idx / out_d2 are not written.
 static knn_status proj_seed_impl(const knn_matrix& X, const float* Z, int m, const float* dirs, int P, int D,
-                                 int w, int K, int32_t* out_idx, float* out_d2, Workspace& ws, hipStream_t st)
+                                 int w, int K, int32_t* out_idx, float* out_d2, Workspace& ws, hipStream_t st,
+                                 int32_t** win_idx = nullptr, float** win_d2 = nullptr)
 {
     const int64_t n = X.n;
     uint32_t *keys, *vals, *k1, *v1, *counts, *lohi;
@@ -814,6 +818,11 @@ static knn_status proj_seed_impl(const knn_matrix& X, const float* Z, int m, con
             window_dist_kernel<DT, 32><<<wgrid, 256, lds, st>>>(X.data, X.ld, X.d, n, vals, w, PW, vec, wi, wd);
     });
     KNN_HIP(hipGetLastError());
+    if (win_idx) {
+        *win_idx = wi;
+        *win_d2 = wd;
+        return KNN_OK;
+    }
     proj_seed_kernel<<<(unsigned)ceil_div(n, 4), 256, 0, st>>>(n, wi, wd, PW, K, out_idx, out_d2);
     KNN_HIP(hipGetLastError());
     return KNN_OK;
@@ -900,8 +909,8 @@ static knn_status forward_impl(const knn_encoder* enc, const knn_matrix& X, cons
 // Seed lists from the encoder: X is embedded in the given precision, the
 // seeds' distances are taken on Xd (the same points; the BF16 copy in the
 // BF16 form).
-knn_status encoder_seed(const knn_encoder* enc, const knn_matrix& X, const knn_matrix& Xd, int precision, int K,
-                        int P, int D, int w, uint64_t seed, Workspace& ws, int32_t** seed_idx, float** seed_d2,
+knn_status encoder_seed(const knn_encoder* enc, const knn_matrix& X, const knn_matrix& Xd, int precision, int P,
+                        int D, int w, uint64_t seed, Workspace& ws, int32_t** seed_idx, float** seed_d2,
                         hipStream_t st)
 {
     if (2 * w * P > 64) return fail(KNN_EINVAL, "2 * proj_window * proj_count must be <= 64");
@@ -910,12 +919,10 @@ knn_status encoder_seed(const knn_encoder* enc, const knn_matrix& X, const knn_m
     float *Z, *dirs;
     if ((r = ws.alloc(&Z, (size_t)X.n * H2)) != KNN_OK) return r;
     if ((r = ws.alloc(&dirs, (size_t)P * D * H2)) != KNN_OK) return r;
-    if ((r = ws.alloc(seed_idx, (size_t)X.n * K)) != KNN_OK) return r;
-    if ((r = ws.alloc(seed_d2, (size_t)X.n * K)) != KNN_OK) return r;
     dirs_kernel<<<P * D, 64, 0, st>>>(H2, seed, dirs);
     KNN_HIP(hipGetLastError());
     if ((r = forward_impl(enc, X, nullptr, X.n, precision, nullptr, Z, st)) != KNN_OK) return r;
-    return proj_seed_impl(Xd, Z, H2, dirs, P, D, w, K, *seed_idx, *seed_d2, ws, st);
+    return proj_seed_impl(Xd, Z, H2, dirs, P, D, w, 0, nullptr, nullptr, ws, st, seed_idx, seed_d2);
 }
 
 // Forward + loss + backward of one batch (rows: 3B device ints).  Leaves the

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void nnd_init_kernel(
     const uint32_t* __restrict__ perm, const uint32_t* __restrict__ inv, float* __restrict__ worst,
     int64_t wstride, SampleArgs sa, bool smp)
 {
-    __shared__ uint32_t s_id[4][64];
+    __shared__ __attribute__((aligned(16))) uint32_t s_id[4][64];
     __shared__ float s_d2[4][64];
     __shared__ uint8_t s_fl[4][64];
     __shared__ uint8_t s_has[4][64];
@@ -107,13 +107,25 @@ __global__ __launch_bounds__(256) void nnd_init_kernel(
             if (init_flags) fl = init_flags[grow * init_k + lane] ? 1 : 0;
         }
     }
-    // drop repeats (keep the first occurrence); only lanes < init_k hold
-    // given entries
+    // drop repeats (keep the first valid occurrence): every lane compares
+    // with the earlier lanes through LDS broadcasts; only lanes < init_k hold
+    // given entries, invalid ones a value no index takes
     const int ngiven = init_idx ? (init_k < 64 ? init_k : 64) : 0;
-    for (int o = 0; o < ngiven; ++o) {
-        uint32_t oi = bcast_u32(id, o);
-        bool ov = bcast_u32(valid ? 1u : 0u, o) != 0;
-        if (o < lane && ov && oi == id) valid = false;
+    if (ngiven > 1) {
+        s_id[wv][lane] = valid ? id : 0xFFFFFFFEu;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        bool dup = false;
+        for (int o = 0; o < ngiven; o += 4) {
+            const uint4 x = *(const uint4*)&s_id[wv][o];
+            dup = dup || (o + 0 < lane && x.x == id) || (o + 1 < lane && x.y == id) ||
+                  (o + 2 < lane && x.z == id) || (o + 3 < lane && x.w == id);
+        }
+        valid = valid && !dup;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
     uint64_t vm = ballot(valid);
     int nvalid = popc64(vm);
@@ -1095,8 +1107,11 @@ __global__ __launch_bounds__(256) void nnd_finalize_kernel(
 
 // ------------------------------------------------------------------ host
 
-knn_status encoder_seed(const knn_encoder* enc, const knn_matrix& X, const knn_matrix& Xd, int precision, int K,
-                        int P, int D, int w, uint64_t seed, Workspace& ws, int32_t** seed_idx, float** seed_d2,
+// Encoder seeding: the 2wP window entries (index, squared distance in Xd's
+// precision) of every point in processing order, n x 2wP each, ranked by
+// the init kernel.
+knn_status encoder_seed(const knn_encoder* enc, const knn_matrix& X, const knn_matrix& Xd, int precision, int P,
+                        int D, int w, uint64_t seed, Workspace& ws, int32_t** seed_idx, float** seed_d2,
                         hipStream_t st);
 
 int encoder_dim(const knn_encoder* enc);
@@ -1236,12 +1251,12 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         const int D = p->proj_dims > 0 ? p->proj_dims : 8;
         // seed distances in the form's precision (the BF16 copy's values)
         const knn_matrix Xd = bf ? knn_matrix{Xb, X.n, X.d, ldb, KNN_BF16} : Xp;
-        r = encoder_seed(p->encoder, Xp, Xd, p->precision, K, P, D, w, p->seed, ws, &si, &sd, st);
+        r = encoder_seed(p->encoder, Xp, Xd, p->precision, P, D, w, p->seed, ws, &si, &sd, st);
         if (r != KNN_OK) return r;
         seed_idx = si;
         seed_d2 = sd;
         seed_fl = nullptr;
-        seed_k = K;
+        seed_k = 2 * w * P;
     }
     {
         dim3 grid((unsigned)ceil_div(n, 4));

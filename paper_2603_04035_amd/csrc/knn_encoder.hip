@@ -336,12 +336,19 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ w, const 
 
 constexpr int kRsThreads = 256, kRsItems = 16, kRsTile = kRsThreads * kRsItems;
 
-static size_t rs_counts(int64_t n) { return (size_t)256 * ceil_div(n, kRsTile) + 256; }
+__host__ __device__ inline size_t rs_counts(int64_t n)
+{
+    return (size_t)256 * ((n + kRsTile - 1) / kRsTile) + 256;
+}
 
+// Sorts run on blockIdx.y independent arrays of n elements at once: array
+// y's elements (and outputs) start at y * n, its counts at y * rs_counts(n).
 __global__ __launch_bounds__(256) void rs_hist_kernel(const uint32_t* __restrict__ keys, int64_t n, int shift,
                                                       uint32_t* __restrict__ counts, int nblk)
 {
     __shared__ uint32_t hist[256];
+    keys += (int64_t)blockIdx.y * n;
+    counts += (int64_t)blockIdx.y * rs_counts(n);
     hist[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRsTile;
@@ -375,10 +382,11 @@ __device__ inline uint32_t block_exscan256(uint32_t x, uint32_t* s, uint32_t* to
 // Counts are digit-major (c[digit * nblk + tile]).  Block `digit` turns its
 // row into exclusive prefix sums over the tiles and writes the row total to
 // tot[digit]; the scatter adds the exclusive prefix of the totals.
-__global__ __launch_bounds__(256) void rs_scan_kernel(uint32_t* __restrict__ c, int nblk,
-                                                      uint32_t* __restrict__ tot)
+__global__ __launch_bounds__(256) void rs_scan_kernel(uint32_t* __restrict__ c, int64_t n, int nblk)
 {
     __shared__ uint32_t s[256];
+    c += (int64_t)blockIdx.y * rs_counts(n);
+    uint32_t* tot = c + (int64_t)256 * nblk;
     uint32_t* row = c + (int64_t)blockIdx.x * nblk;
     uint32_t carry = 0;
     for (int b0 = 0; b0 < nblk; b0 += 256) {
@@ -400,12 +408,18 @@ __global__ __launch_bounds__(256) void rs_scatter_kernel(const uint32_t* __restr
                                                          const uint32_t* __restrict__ vin,
                                                          uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                          int64_t n, int shift,
-                                                         const uint32_t* __restrict__ offs, int nblk,
-                                                         const uint32_t* __restrict__ tot)
+                                                         const uint32_t* __restrict__ offs, int nblk)
 {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[4][256];
     __shared__ uint32_t sc[256];
+    const int64_t so = (int64_t)blockIdx.y * n;
+    kin += so;
+    vin += so;
+    kout += so;
+    vout += so;
+    offs += (int64_t)blockIdx.y * rs_counts(n);
+    const uint32_t* tot = offs + (int64_t)256 * nblk;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     uint32_t all;
     const uint32_t dbase = block_exscan256(tot[tid], sc, &all);
@@ -446,18 +460,19 @@ __global__ __launch_bounds__(256) void rs_scatter_kernel(const uint32_t* __restr
     }
 }
 
-// Sort (key, value) pairs of length n by key, stable; result in (k0, v0).
-// counts holds rs_counts(n) words.
+// Sort S independent arrays of (key, value) pairs, n each and contiguous
+// (k0 + y n, ...), by key, stable; results in (k0, v0).  k1 / v1 hold S n
+// words and counts S rs_counts(n) words.
 static knn_status radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
-                                   uint32_t* counts, hipStream_t st)
+                                   uint32_t* counts, hipStream_t st, int S = 1)
 {
     const int nblk = (int)ceil_div(n, kRsTile);
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 8 * pass;
-        rs_hist_kernel<<<nblk, kRsThreads, 0, st>>>(k0, n, shift, counts, nblk);
-        rs_scan_kernel<<<256, 256, 0, st>>>(counts, nblk, counts + (int64_t)256 * nblk);
-        rs_scatter_kernel<<<nblk, kRsThreads, 0, st>>>(k0, v0, k1, v1, n, shift, counts, nblk,
-                                                       counts + (int64_t)256 * nblk);
+        rs_hist_kernel<<<dim3((unsigned)nblk, (unsigned)S), kRsThreads, 0, st>>>(k0, n, shift, counts, nblk);
+        rs_scan_kernel<<<dim3(256, (unsigned)S), 256, 0, st>>>(counts, n, nblk);
+        rs_scatter_kernel<<<dim3((unsigned)nblk, (unsigned)S), kRsThreads, 0, st>>>(k0, v0, k1, v1, n, shift,
+                                                                                   counts, nblk);
         KNN_HIP(hipGetLastError());
         std::swap(k0, k1);
         std::swap(v0, v1);
@@ -599,12 +614,19 @@ __global__ __launch_bounds__(256) void inverse_perm_kernel(const uint32_t* __res
 
 // Y[j][i] = X_i . dirs_j over the d input coordinates, D <= 8 directions.
 // 16 lanes per row (coalesced row reads), each summing a strided subset of
-// the coordinates, then a 16-lane reduction.
-template <int DT>
+// the coordinates, then a 16-lane reduction.  With Staged the directions
+// are first copied to LDS (D * d floats of dynamic shared memory).
+template <int DT, bool Staged>
 __global__ __launch_bounds__(256) void xproj_kernel(const void* __restrict__ X, int64_t ld, int d, int64_t n,
-                                                    const float* __restrict__ dirs, int D,
+                                                    const float* __restrict__ dirs_g, int D,
                                                     float* __restrict__ Y)
 {
+    extern __shared__ float sdirs[];
+    if (Staged) {
+        for (int q = threadIdx.x; q < D * d; q += 256) sdirs[q] = dirs_g[q];
+        __syncthreads();
+    }
+    const float* dirs = Staged ? sdirs : dirs_g;
     const int g = threadIdx.x & 15;
     const int64_t i = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
     const bool live = i < n;
@@ -781,9 +803,9 @@ static knn_status proj_seed_impl(const knn_matrix& X, const float* Z, int m, con
     if ((r = ws.alloc(&lohi, (size_t)2 * P * D)) != KNN_OK) return r;
     if ((r = ws.alloc(&keys, (size_t)n * P)) != KNN_OK) return r;
     if ((r = ws.alloc(&vals, (size_t)n * P)) != KNN_OK) return r;
-    if ((r = ws.alloc(&k1, (size_t)n)) != KNN_OK) return r;
-    if ((r = ws.alloc(&v1, (size_t)n)) != KNN_OK) return r;
-    if ((r = ws.alloc(&counts, rs_counts(n))) != KNN_OK) return r;
+    if ((r = ws.alloc(&k1, (size_t)n * P)) != KNN_OK) return r;
+    if ((r = ws.alloc(&v1, (size_t)n * P)) != KNN_OK) return r;
+    if ((r = ws.alloc(&counts, rs_counts(n) * P)) != KNN_OK) return r;
     const unsigned g = (unsigned)ceil_div(n, 256);
     if (m <= 32) proj_vals_kernel<32><<<g, 256, 0, st>>>(Z, n, m, dirs, P * D, Y);
     else proj_vals_kernel<0><<<g, 256, 0, st>>>(Z, n, m, dirs, P * D, Y);
@@ -793,10 +815,8 @@ static knn_status proj_seed_impl(const knn_matrix& X, const float* Z, int m, con
     }
     morton_kernel<<<g, 256, 0, st>>>(Y, n, P, D, lohi, keys, vals);
     KNN_HIP(hipGetLastError());
-    for (int p = 0; p < P; ++p) {
-        r = radix_sort_pairs(keys + (int64_t)p * n, vals + (int64_t)p * n, k1, v1, n, counts, st);
-        if (r != KNN_OK) return r;
-    }
+    // the P orders are sorted together
+    if ((r = radix_sort_pairs(keys, vals, k1, v1, n, counts, st, P)) != KNN_OK) return r;
     // window distances per order, then each point's best K of its windows
     const int PW = 2 * w * P;
     int32_t* wi;
@@ -876,9 +896,13 @@ knn_status morton_order(const knn_matrix& X, int D, uint64_t seed, Workspace& ws
     if ((r = ws.alloc(&counts, rs_counts(n))) != KNN_OK) return r;
     dirs_kernel<<<D, 64, 0, st>>>(X.d, seed ^ 0x5DEECE66Dull, dirs);
     const unsigned g = (unsigned)ceil_div(n, 256);
+    const bool staged = (size_t)D * X.d * sizeof(float) <= 32768;
+    const size_t lds = staged ? (size_t)D * X.d * sizeof(float) : 0;
+    const unsigned xg = (unsigned)ceil_div(n, 16);
     by_dtype(X.dtype, [&](auto dt) {
-        xproj_kernel<decltype(dt)::value><<<(unsigned)ceil_div(n, 16), 256, 0, st>>>(X.data, X.ld, X.d, n, dirs,
-                                                                                     D, Y);
+        constexpr int DT = decltype(dt)::value;
+        if (staged) xproj_kernel<DT, true><<<xg, 256, lds, st>>>(X.data, X.ld, X.d, n, dirs, D, Y);
+        else xproj_kernel<DT, false><<<xg, 256, 0, st>>>(X.data, X.ld, X.d, n, dirs, D, Y);
     });
     lohi_init_kernel<<<1, 64, 0, st>>>(lohi, D);
     minmax_kernel<<<dim3(minmax_blocks(n), (unsigned)D), 256, 0, st>>>(Y, n, lohi);

@@ -306,15 +306,16 @@ __device__ inline bool sample_row(int64_t row, bool rv, int K, int s, int R, int
     // slots past the picks / old entries get -1 (disjoint from the writes below)
     if (rv && hl >= npick && hl < s) newf[row * s + hl] = -1;
     if (rv && hl >= nold && hl < K) oldf[row * K + hl] = -1;
-    if (pick) {
-        newf[row * s + rank] = id;
-        const uint32_t slot = bounded(hash4(seed ^ kTagRevSlot, (uint64_t)iter, (uint64_t)row, 1), (uint32_t)R);
-        atomicMin(&revnew[(int64_t)id * R + slot], rev_code((uint32_t)row, rev_salt(seed, kTagRevNew, iter, id)));
-    }
-    if (isold) {
-        oldf[row * K + opos] = id;
-        const uint32_t slot = bounded(hash4(seed ^ kTagRevSlot, (uint64_t)iter, (uint64_t)row, 2), (uint32_t)R);
-        atomicMin(&revold[(int64_t)id * R + slot], rev_code((uint32_t)row, rev_salt(seed, kTagRevOld, iter, id)));
+    if (pick) newf[row * s + rank] = id;
+    if (isold) oldf[row * K + opos] = id;
+    // one reverse edge per picked or old entry: the list, slot stream and
+    // salt are chosen first, so a wave evaluates each hash once
+    if (pick || isold) {
+        const uint32_t slot =
+            bounded(hash4(seed ^ kTagRevSlot, (uint64_t)iter, (uint64_t)row, pick ? 1u : 2u), (uint32_t)R);
+        uint32_t* rev = pick ? revnew : revold;
+        const uint32_t salt = rev_salt(seed, pick ? kTagRevNew : kTagRevOld, iter, id);
+        atomicMin(&rev[(int64_t)id * R + slot], rev_code((uint32_t)row, salt));
     }
     return pick;
 }
@@ -924,7 +925,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
 // reverse-slot atomics of the sampling overlap the merge work of other
 // waves; every row is then rewritten.
 template <bool Smp>
-__global__ __launch_bounds__(256) void nnd_merge_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void nnd_merge_kernel(
     int64_t n, int K, int C, int32_t* __restrict__ gidx, float* __restrict__ gd2,
     uint8_t* __restrict__ gflag, unsigned long long* __restrict__ cand,
     unsigned long long* __restrict__ counters, float* __restrict__ worst, int64_t wstride,

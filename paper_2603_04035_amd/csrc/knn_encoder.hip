@@ -690,22 +690,31 @@ __global__ __launch_bounds__(256) void window_dist_kernel(const void* __restrict
 #pragma unroll
     for (int o = 0; o < W; ++o) sum[o] = 0.0f;
     for (int c0 = 0; c0 < d; c0 += CH) {
-        for (int q = j; q < nr * 8; q += 256) {
+        // a thread stages at most 9 vectors ((256 + 32) x 8 / 256): all of
+        // its loads are issued before the first LDS store
+        uint4 xs[9];
+#pragma unroll
+        for (int u = 0; u < 9; ++u) {
+            const int q = j + 256 * u;
             const int r = q >> 3, e0 = c0 + (q & 7) * V;
-            const uint32_t id = rid[r];
-            uint4 x = make_uint4(0u, 0u, 0u, 0u);
+            const uint32_t id = q < nr * 8 ? rid[r] : 0xFFFFFFFFu;
+            xs[u] = make_uint4(0u, 0u, 0u, 0u);
             if (id != 0xFFFFFFFFu && e0 < d) {
                 const T* src = (const T*)X + (int64_t)id * ld + e0;
                 if (vec && e0 + V <= d) {
-                    x = *(const uint4*)src;
+                    xs[u] = *(const uint4*)src;
                 } else {
                     T tmp[V];
 #pragma unroll
                     for (int e = 0; e < V; ++e) tmp[e] = e0 + e < d ? src[e] : T(0);
-                    __builtin_memcpy(&x, tmp, sizeof(x));
+                    __builtin_memcpy(&xs[u], tmp, sizeof(uint4));
                 }
             }
-            tile[r * RS + (q & 7)] = x;
+        }
+#pragma unroll
+        for (int u = 0; u < 9; ++u) {
+            const int q = j + 256 * u;
+            if (q < nr * 8) tile[(q >> 3) * RS + (q & 7)] = xs[u];
         }
         __syncthreads();
         const int nv = min(8, (d - c0 + V - 1) / V);
@@ -736,6 +745,26 @@ __global__ __launch_bounds__(256) void window_dist_kernel(const void* __restrict
     __syncthreads();
     if (j < w || !live) return;
     const int64_t row = (int64_t)rid[j] * PW + (int64_t)p * 2 * w;
+    if (w == W) {
+        // the 2W entries are contiguous and 16-byte aligned (PW = 2WP):
+        // written as 16-byte vectors
+        int32_t oi[2 * W];
+        float od[2 * W];
+#pragma unroll
+        for (int o = 1; o <= W; ++o) {
+            const bool lv = t - o >= 0, rv = t + o < n;
+            oi[o - 1] = lv ? (int32_t)rid[j - o] : -1;
+            od[o - 1] = lv ? fd[(o - 1) * 256 + j - o] : 0.0f;
+            oi[W + o - 1] = rv ? (int32_t)rid[j + o] : -1;
+            od[W + o - 1] = rv ? fd[(o - 1) * 256 + j] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < W / 2; ++u) {
+            *(int4*)(win_idx + row + 4 * u) = make_int4(oi[4 * u], oi[4 * u + 1], oi[4 * u + 2], oi[4 * u + 3]);
+            *(float4*)(win_d2 + row + 4 * u) = make_float4(od[4 * u], od[4 * u + 1], od[4 * u + 2], od[4 * u + 3]);
+        }
+        return;
+    }
     for (int o = 1; o <= w; ++o) {
         const bool lv = t - o >= 0, rv = t + o < n;
         win_idx[row + o - 1] = lv ? (int32_t)rid[j - o] : -1;

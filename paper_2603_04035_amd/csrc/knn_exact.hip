@@ -33,8 +33,8 @@ constexpr int kListW = 32;        // list width per query row (k' <= 32)
 
 // ------------------------------------------------------------------ stage
 
-// Waves take rows grid-stride: padded copy (zeros beyond d) and the FP32
-// squared norm of the stored values.  maxnorm (nullable) receives the
+// Waves take groups of 4 rows grid-stride: padded copy (zeros beyond d) and
+// the FP32 squared norm of the stored values.  maxnorm (nullable) receives the
 // largest norm's float bits: one atomic per block after an in-block
 // reduction.  With `aux`, the last 8 bytes of each row hold two FP32 words
 // instead of zeros: the norm and +inf (a per-row value that NNDescent keeps
@@ -46,36 +46,59 @@ __global__ __launch_bounds__(256) void stage_kernel(const void* __restrict__ X, 
                                                     unsigned* __restrict__ maxnorm,
                                                     const uint32_t* __restrict__ rowmap, int aux)
 {
+    constexpr int RB = 4;   // rows per wave and step: their loads are issued together
     __shared__ unsigned smax[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int lim = aux ? ldp - (TO_BF16 ? 4 : 2) : ldp;
     unsigned wmax = 0;
-    for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < n; row += (int64_t)gridDim.x * 4) {
-        const int64_t src = rowmap ? (int64_t)rowmap[row] : row;
-        float s = 0.0f;
+    for (int64_t row0 = ((int64_t)blockIdx.x * 4 + wv) * RB; row0 < n; row0 += (int64_t)gridDim.x * 4 * RB) {
+        int64_t src[RB];
+        float s[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int64_t row = row0 + q < n ? row0 + q : row0;
+            src[q] = rowmap ? (int64_t)rowmap[row] : row;
+            s[q] = 0.0f;
+        }
         for (int t = lane; t < lim; t += 64) {
-            float v = t < d ? elem<DT>::ld(X, src * ld + t) : 0.0f;
-            if (TO_BF16) {
-                uint16_t b = f32_to_bf16_rne(v);
-                ((uint16_t*)Xs)[row * ldp + t] = b;
-                v = __uint_as_float((uint32_t)b << 16);
-            } else {
-                ((float*)Xs)[row * ldp + t] = v;
+            float v[RB];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) v[q] = t < d ? elem<DT>::ld(X, src[q] * ld + t) : 0.0f;
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                if (row0 + q >= n) continue;
+                const int64_t row = row0 + q;
+                float x = v[q];
+                if (TO_BF16) {
+                    uint16_t b = f32_to_bf16_rne(x);
+                    ((uint16_t*)Xs)[row * ldp + t] = b;
+                    x = __uint_as_float((uint32_t)b << 16);
+                } else {
+                    ((float*)Xs)[row * ldp + t] = x;
+                }
+                s[q] = fmaf(x, x, s[q]);
             }
-            s = fmaf(v, v, s);
         }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) s += xor_f32(s, o);
-        if (lane == 0) {
-            norms[row] = s;
-            if (aux) {
-                float* a = (float*)((char*)Xs + (row + 1) * (int64_t)ldp * (TO_BF16 ? 2 : 4)) - 2;
-                a[0] = s;
-                a[1] = __builtin_inff();
-            }
+        for (int q = 0; q < RB; ++q) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) s[q] += xor_f32(s[q], o);
         }
-        const unsigned u = __float_as_uint(s);
-        wmax = u > wmax ? u : wmax;
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int64_t row = row0 + q;
+            if (row >= n) break;
+            if (lane == 0) {
+                norms[row] = s[q];
+                if (aux) {
+                    float* a = (float*)((char*)Xs + (row + 1) * (int64_t)ldp * (TO_BF16 ? 2 : 4)) - 2;
+                    a[0] = s[q];
+                    a[1] = __builtin_inff();
+                }
+            }
+            const unsigned u = __float_as_uint(s[q]);
+            wmax = u > wmax ? u : wmax;
+        }
     }
     if (maxnorm) {
         if (lane == 0) smax[wv] = wmax;
@@ -468,7 +491,7 @@ template <bool TO_BF16>
 static void launch_stage(const knn_matrix& X, void* Xs, int ldp, float* norms, unsigned* maxn,
                          const uint32_t* rowmap, int aux, hipStream_t st)
 {
-    dim3 grid((unsigned)std::min<int64_t>(ceil_div(X.n, 4), 4096)), block(256);
+    dim3 grid((unsigned)std::min<int64_t>(ceil_div(X.n, 16), 4096)), block(256);
     switch (X.dtype) {
     case KNN_F32:
         stage_kernel<KNN_F32, TO_BF16><<<grid, block, 0, st>>>(X.data, X.n, X.d, X.ld, Xs, ldp, norms, maxn, rowmap, aux);

@@ -494,8 +494,19 @@ __global__ __launch_bounds__(256) void proj_vals_kernel(const float* __restrict_
     if (i >= n) return;
     if constexpr (M > 0) {
         float z[M];
+        if (m == M && ((uintptr_t)Z & 15u) == 0) {   // 16-byte aligned rows of M floats: read as vectors
 #pragma unroll
-        for (int t = 0; t < M; ++t) z[t] = t < m ? Z[i * m + t] : 0.0f;
+            for (int t = 0; t < M; t += 4) {
+                const float4 v = *(const float4*)(Z + i * M + t);
+                z[t] = v.x;
+                z[t + 1] = v.y;
+                z[t + 2] = v.z;
+                z[t + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < M; ++t) z[t] = t < m ? Z[i * m + t] : 0.0f;
+        }
         for (int q = 0; q < PD; ++q) {
             float s = 0.0f;
 #pragma unroll
@@ -574,20 +585,22 @@ static unsigned minmax_blocks(int64_t n) { return (unsigned)std::min<int64_t>(ce
 // projections, each quantised to b = 32/D bits over [lo, hi]:
 // q = min(floor((y - lo) * (2^b / (hi - lo))), 2^b - 1), bits interleaved
 // from the most significant level down.
-__global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ Y, int64_t n, int P, int D,
+template <int D>
+__global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ Y, int64_t n, int P,
                                                      const unsigned* __restrict__ lohi,
                                                      uint32_t* __restrict__ keys, uint32_t* __restrict__ vals)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int bits = 32 / D;
+    constexpr int bits = 32 / D;
     for (int p = 0; p < P; ++p) {
         uint32_t key;
-        if (D == 1) {
+        if constexpr (D == 1) {
             key = f32_order(Y[(int64_t)p * n + i]);
         } else {
-            uint32_t code[8];
-            const uint32_t qmax = (1u << bits) - 1u;
+            uint32_t code[D];
+            constexpr uint32_t qmax = (1u << bits) - 1u;
+#pragma unroll
             for (int j = 0; j < D; ++j) {
                 const int q = p * D + j;
                 const float lo = f32_unorder(lohi[2 * q]), hi = f32_unorder(lohi[2 * q + 1]);
@@ -597,12 +610,24 @@ __global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ Y
                 code[j] = c < qmax ? c : qmax;
             }
             key = 0;
+#pragma unroll
             for (int l = bits - 1; l >= 0; --l)
+#pragma unroll
                 for (int j = 0; j < D; ++j) key = (key << 1) | ((code[j] >> l) & 1u);
         }
         keys[(int64_t)p * n + i] = key;
         vals[(int64_t)p * n + i] = (uint32_t)i;
     }
+}
+
+static void launch_morton(const float* Y, int64_t n, int P, int D, const unsigned* lohi, uint32_t* keys,
+                          uint32_t* vals, hipStream_t st)
+{
+    const unsigned g = (unsigned)ceil_div(n, 256);
+    if (D == 1) morton_kernel<1><<<g, 256, 0, st>>>(Y, n, P, lohi, keys, vals);
+    else if (D == 2) morton_kernel<2><<<g, 256, 0, st>>>(Y, n, P, lohi, keys, vals);
+    else if (D == 4) morton_kernel<4><<<g, 256, 0, st>>>(Y, n, P, lohi, keys, vals);
+    else morton_kernel<8><<<g, 256, 0, st>>>(Y, n, P, lohi, keys, vals);
 }
 
 __global__ __launch_bounds__(256) void inverse_perm_kernel(const uint32_t* __restrict__ order, int64_t n,
@@ -842,7 +867,7 @@ static knn_status proj_seed_impl(const knn_matrix& X, const float* Z, int m, con
         lohi_init_kernel<<<1, 64, 0, st>>>(lohi, P * D);
         minmax_kernel<<<dim3(minmax_blocks(n), (unsigned)(P * D)), 256, 0, st>>>(Y, n, lohi);
     }
-    morton_kernel<<<g, 256, 0, st>>>(Y, n, P, D, lohi, keys, vals);
+    launch_morton(Y, n, P, D, lohi, keys, vals, st);
     KNN_HIP(hipGetLastError());
     // the P orders are sorted together
     if ((r = radix_sort_pairs(keys, vals, k1, v1, n, counts, st, P)) != KNN_OK) return r;
@@ -935,7 +960,7 @@ knn_status morton_order(const knn_matrix& X, int D, uint64_t seed, Workspace& ws
     });
     lohi_init_kernel<<<1, 64, 0, st>>>(lohi, D);
     minmax_kernel<<<dim3(minmax_blocks(n), (unsigned)D), 256, 0, st>>>(Y, n, lohi);
-    morton_kernel<<<g, 256, 0, st>>>(Y, n, 1, D, lohi, keys, *perm);
+    launch_morton(Y, n, 1, D, lohi, keys, *perm, st);
     KNN_HIP(hipGetLastError());
     if ((r = radix_sort_pairs(keys, *perm, k1, v1, n, counts, st)) != KNN_OK) return r;
     inverse_perm_kernel<<<g, 256, 0, st>>>(*perm, n, *inv);

@@ -1344,7 +1344,8 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         }
         ++iters;
         if ((double)host_cnt[0] < stop) {
-            if (smp) {
+            // the flags are seen only through the returned state
+            if (smp && state_flags) {
                 nnd_unsample_kernel<<<(unsigned)ceil_div(n, 8), 256, 0, st>>>(n, K, s, gidx, gflag, newf);
                 KNN_HIP(hipGetLastError());
             }

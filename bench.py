@@ -39,16 +39,17 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 # NNDescent settings of the two forms (K_b, rho, caps); delta is the paper's 0.015.
+# The BF16 forms keep K_b = 2k = 30 entries, the FP32 re-rank's width.
 FORMS = {
     "fp32": dict(precision="fp32", build_k=32, sample_rate=1.0, max_iters=30, delta=0.015,
                  join_cap=4, cand_slots=64),
-    "bf16-learned": dict(precision="bf16", build_k=32, sample_rate=1.0, max_iters=30, delta=0.015,
+    "bf16-learned": dict(precision="bf16", build_k=30, sample_rate=1.0, max_iters=30, delta=0.015,
                          join_cap=4, cand_slots=96, init_kind="encoder", proj_count=4, proj_window=8),
     # controls for the encoder's benefit (--form all): same BF16 form, random
     # init, and seeding through an untrained encoder of the same shape
-    "bf16-random": dict(precision="bf16", build_k=32, sample_rate=1.0, max_iters=30, delta=0.015,
+    "bf16-random": dict(precision="bf16", build_k=30, sample_rate=1.0, max_iters=30, delta=0.015,
                         join_cap=4, cand_slots=96),
-    "bf16-untrained": dict(precision="bf16", build_k=32, sample_rate=1.0, max_iters=30, delta=0.015,
+    "bf16-untrained": dict(precision="bf16", build_k=30, sample_rate=1.0, max_iters=30, delta=0.015,
                            join_cap=4, cand_slots=96, init_kind="encoder", proj_count=4, proj_window=8),
 }
 # encoder training (reported separately, not in the timed region)

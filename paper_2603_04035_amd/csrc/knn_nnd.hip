@@ -402,15 +402,20 @@ __device__ inline int join_lists(int64_t v, const ListRaw& raw, const JoinCfg& c
     asm volatile("" : "+v"(ln));   // keep the position tests per point, not hoisted masks
     bool nv = nid != 0xFFFFFFFFu && nid != (uint32_t)v;
     bool ov = oid != 0xFFFFFFFFu && oid != (uint32_t)v;
+    // Repeats keep their first position.  A forward list holds distinct
+    // indices, and a reverse list holds a source at most once (a source
+    // uses one slot index for all its targets), so a new entry can repeat
+    // only a forward-new one (lanes < s), and an old entry a new one or,
+    // if it is a reverse-old entry, a forward-old one (lanes < K).
 #pragma unroll 2
     for (int q = 0; q < 64; q += 4) {
         const uint4 x = *(const uint4*)(sh + q);
-        nv = nv && !(q + 0 < ln && x.x == nid) && !(q + 1 < ln && x.y == nid) &&
-             !(q + 2 < ln && x.z == nid) && !(q + 3 < ln && x.w == nid);
+        if (q < cfg.s)
+            nv = nv && !(q + 0 < ln && x.x == nid) && !(q + 1 < ln && x.y == nid) &&
+                 !(q + 2 < ln && x.z == nid) && !(q + 3 < ln && x.w == nid);
         ov = ov && x.x != oid && x.y != oid && x.z != oid && x.w != oid;
     }
-#pragma unroll 2
-    for (int q = 0; q < 64; q += 4) {
+    for (int q = 0; q < cfg.K; q += 4) {
         const uint4 x = *(const uint4*)(sh + 64 + q);
         ov = ov && !(q + 0 < ln && x.x == oid) && !(q + 1 < ln && x.y == oid) &&
              !(q + 2 < ln && x.z == oid) && !(q + 3 < ln && x.w == oid);

@@ -1018,6 +1018,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void n
         // sorted, which can reorder equal distances: re-sort if needed
         const uint64_t nxt = shfl_u64(cur, lane + 1 < 64 ? lane + 1 : lane);
         if (ballot(hl < 31 && cur > nxt)) cur = seg_sort<32>(cur);
+        const uint64_t orig = cur;   // the row's list before the insertions
         if (!ballot(nc > 8)) {
             // a few candidates: each is inserted into its half's sorted list;
             // lanes whose entry exceeds it move up one place and the first
@@ -1041,13 +1042,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void n
         const uint32_t w = key_idx(cur);
         const uint32_t cidx = w & ~kWasOld;
         const bool sv = key_valid(cur) && key_d2(cur) < __builtin_inff();
-        bool from_list = false;
-#pragma unroll
-        for (int r = 0; r < 32; r += 4) {
-            const uint4 x = *(const uint4*)&slid[seg][r];
-            from_list = from_list || x.x == cidx || x.y == cidx || x.z == cidx || x.w == cidx;
-        }
-        upd += (unsigned long long)popc64(ballot(hl < K && nc > 0 && sv && !from_list));
+        // insertions = valid entries of the new list minus the old valid
+        // entries it kept; keys are unique, so an old entry was kept iff its
+        // key is at most the new K-th key
+        const uint64_t kth = shfl_u64(cur, (lane & 32) + K - 1);
+        const bool osv = hl < K && key_valid(orig) && key_d2(orig) < __builtin_inff();
+        upd += (unsigned long long)popc64(ballot(hl < K && nc > 0 && sv)) -
+               (unsigned long long)popc64(ballot(nc > 0 && osv && orig <= kth));
         if (!Smp) {
             if (nc > 0 && hl < K) {
                 gidx[row * K + hl] = sv ? (int32_t)cidx : -1;

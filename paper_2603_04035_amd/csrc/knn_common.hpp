@@ -291,36 +291,6 @@ __device__ inline float dist_batch16(const void* X, int64_t ld, int64_t a, uint3
     return mine;
 }
 
-// Squared distance of two rows computed by one lane: coordinates in order,
-// FP32 fused multiply-adds on the stored values.  With `vec` (base and both
-// row offsets 16-byte aligned) the rows are read as 16-byte vectors.
-template <int DT>
-__device__ inline float lane_dist2(const void* A, int64_t a_off, const void* B, int64_t b_off, int d, bool vec)
-{
-    using T = typename elem<DT>::T;
-    constexpr int V = 16 / (int)sizeof(T);
-    float s = 0.0f;
-    int t = 0;
-    if (vec) {
-        for (; t + V <= d; t += V) {
-            const uint4 ua = *(const uint4*)((const T*)A + a_off + t);
-            const uint4 ub = *(const uint4*)((const T*)B + b_off + t);
-            const T* pa = (const T*)&ua;
-            const T* pb = (const T*)&ub;
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const float x = elem<DT>::ld(pa, e) - elem<DT>::ld(pb, e);
-                s = fmaf(x, x, s);
-            }
-        }
-    }
-    for (; t < d; ++t) {
-        const float x = elem<DT>::ld(A, a_off + t) - elem<DT>::ld(B, b_off + t);
-        s = fmaf(x, x, s);
-    }
-    return s;
-}
-
 // ------------------------------------------------------------------ host
 
 void set_error(const std::string& msg);

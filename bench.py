@@ -39,9 +39,11 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 # NNDescent settings of the two forms (K_b, rho, caps); delta is the paper's 0.015.
-# The BF16 forms keep K_b = 2k = 30 entries, the FP32 re-rank's width.
+# The BF16 forms keep K_b = 2k = 30 entries, the FP32 re-rank's width; the
+# FP32 form K_b = 31 (each the smallest list that keeps recall@15 above 0.98
+# by about 0.002 over seeds 0-4).
 FORMS = {
-    "fp32": dict(precision="fp32", build_k=32, sample_rate=1.0, max_iters=30, delta=0.015,
+    "fp32": dict(precision="fp32", build_k=31, sample_rate=1.0, max_iters=30, delta=0.015,
                  join_cap=4, cand_slots=64),
     "bf16-learned": dict(precision="bf16", build_k=30, sample_rate=1.0, max_iters=30, delta=0.015,
                          join_cap=4, cand_slots=96, init_kind="encoder", proj_count=4, proj_window=8),

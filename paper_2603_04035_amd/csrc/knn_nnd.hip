@@ -271,8 +271,11 @@ __host__ __device__ inline uint32_t rev_code(uint32_t u, uint32_t salt) { return
 // entries (every one when there are at most s, else the s with the smallest
 // random priorities, ties by position), writes them in list order to
 // newf(row) and the old entries to oldf(row), -1 past the last, and scatters
-// the reverse edges into R slots per target row.  Returns whether this
-// lane's entry was picked (the caller marks it old).
+// the reverse edges into R slots per target row.  All reverse edges of one
+// source and list use the slot index hash(iteration, source), so a source
+// occupies at most one slot of a target's reverse list: the join's repeat
+// check relies on this.  Returns whether this lane's entry was picked (the
+// caller marks it old).
 __device__ inline bool sample_row(int64_t row, bool rv, int K, int s, int R, int32_t id, bool isnew, bool isold,
                                   int32_t* __restrict__ newf, int32_t* __restrict__ oldf,
                                   uint32_t* __restrict__ revnew, uint32_t* __restrict__ revold,

@@ -193,3 +193,27 @@ def test_learned_init_vs_random(orc):
     print("recall after 0/1/2 iterations", res)
     assert res["trained"][0] > 5 * max(res["random"][0], 1e-3), res
     assert res["trained"][2] > res["random"][2], res
+
+
+def test_proj_seed_bench_shape(orc):
+    """The seeding launch of the 1M-point build: 1,000,000 x 50 BF16 rows of
+    the benchmark mixture, P = 4 orders of D = 8 projections of a 32-wide
+    embedding, w = 8, K = 30; 20,000 sampled rows against the oracle (which
+    takes the BF16 values exactly)."""
+    import bench
+    from paper_2603_04035_amd import knn_proj_seed
+    from oracle.compare import exact_parity, parity_ok
+    X = torch.from_numpy(bench.make_data("gmm1m")).to(torch.bfloat16)
+    n = X.shape[0]
+    rng = np.random.default_rng(11)
+    Z = rng.normal(size=(n, 32)).astype(np.float32)
+    dirs = rng.normal(size=(32, 32)).astype(np.float32)
+    idx, d2 = knn_proj_seed(X.cuda(), _dev(Z), _dev(dirs), w=8, K=30, D=8)
+    Xv = X.float().numpy()
+    oi, od2 = orc.proj_seed(Xv, Z, dirs, w=8, K=30, D=8)
+    rows = datagen.sample_queries(n, 20000, seed=5)
+    gi, gd = idx.cpu().numpy()[rows], d2.cpu().numpy()[rows]
+    assert np.array_equal(gi < 0, oi[rows] < 0)
+    full = oi[rows].min(axis=1) >= 0
+    res = exact_parity(Xv, rows[full], gi[full], np.sqrt(gd[full]), oi[rows][full])
+    assert parity_ok(res), res

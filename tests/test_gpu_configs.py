@@ -125,3 +125,32 @@ def test_scale_10m_fp16_learned_bf16(orc):
     _rows_ok(orc, Xh, rows[:200], Gs[:200], Ds[:200])
     print("scale10m recall", r, "iters", st["iters"], "ms", st["ms_total"])
     assert r >= 0.9, (r, st)
+
+
+def test_benchmark_forms_meet_recall(orc):
+    """Both benchmark forms, with exactly the settings bench.py times, on the
+    1,000,000 x 50 mixture: recall@15 >= 0.98 over 10,000 sampled rows (the
+    metric's condition; the exact lists come from the exact path, pinned to
+    the oracle on 20 of the rows), valid rows and oracle-exact distances on
+    300 of them."""
+    import bench
+    import paper_2603_04035_amd as knn
+    Xn = bench.make_data("gmm1m")
+    X = torch.from_numpy(Xn).cuda()
+    enc, _ = bench.train_encoder("gmm1m")
+    rows = datagen.sample_queries(X.shape[0], 10_000, seed=2)
+    rows_t = torch.as_tensor(rows, device="cuda")
+    eidx, edist = knn.knn_exact_query(X[rows_t].contiguous(), X, 15, q_self=rows_t.to(torch.int32))
+    few = np.arange(20)
+    O, _ = orc.exact_query(Xn, Xn[rows[few]], 15, q_self=rows[few])
+    res = exact_parity(Xn, rows[few], eidx.cpu().numpy()[few], edist.cpu().numpy()[few], O)
+    assert parity_ok(res), res
+    for form in ("bf16-learned", "fp32"):
+        p = dict(bench.FORMS[form])
+        if p.get("init_kind") == "encoder":
+            p["encoder"] = enc
+        G, D, st = knn.nndescent_build(X, 15, seed=0, **p)
+        r = bench.recall_gpu(X, G, D, rows, 15)
+        print(form, "recall", r, "iters", st["iters"])
+        assert r >= 0.98, (form, r)
+        _rows_ok(orc, Xn, rows[:300], G[rows_t[:300]].cpu().numpy(), D[rows_t[:300]].cpu().numpy())

@@ -171,7 +171,8 @@ knn_status nndescent_build(knn_matrix X, const knn_nnd_params* p,
  *              build(a iters) then refine(b iters, iter_offset = a) from its
  *              state reproduces build(a + b iters) bit for bit.
  * init_k may differ from K_b (extra columns are dropped after sorting,
- * missing ones are filled at random).  Outputs as nndescent_build.
+ * missing ones are filled at random); 1 <= init_k <= 64, else KNN_EINVAL.
+ * Outputs as nndescent_build.
  */
 knn_status nndescent_refine(knn_matrix X, const knn_nnd_params* p,
                             const int32_t* init_idx, const float* init_dist,

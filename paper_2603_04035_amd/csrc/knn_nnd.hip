@@ -68,7 +68,8 @@ __device__ inline bool sample_row(int64_t row, bool rv, int K, int s, int R, int
 // distances (given, or canonical direct differences on the staged rows),
 // sorted, first K kept.  Flags: given (or new).  The K-th distance is also
 // written to the row's worst-distance word (worst[row * wstride]).  With
-// smp the row is then sampled for the first iteration (sample_row).
+// smp the row is then sampled for the first iteration (sample_row).  The
+// row's C candidate slots are emptied.
 template <int DT>
 __global__ __launch_bounds__(256) void nnd_init_kernel(
     int64_t n, int K, const void* __restrict__ Xs, int64_t ldp, int d,
@@ -76,7 +77,7 @@ __global__ __launch_bounds__(256) void nnd_init_kernel(
     const uint8_t* __restrict__ init_flags, int init_k, uint64_t seed,
     int32_t* __restrict__ gidx, float* __restrict__ gd2, uint8_t* __restrict__ gflag,
     const uint32_t* __restrict__ perm, const uint32_t* __restrict__ inv, float* __restrict__ worst,
-    int64_t wstride, SampleArgs sa, bool smp)
+    int64_t wstride, SampleArgs sa, bool smp, unsigned long long* __restrict__ cand, int C)
 {
     __shared__ __attribute__((aligned(16))) uint32_t s_id[4][64];
     __shared__ float s_d2[4][64];
@@ -221,6 +222,8 @@ __global__ __launch_bounds__(256) void nnd_init_kernel(
         gflag[row * K + lane] = sv && !pick ? sfl : 0;
         if (lane == K - 1) worst[row * wstride] = sv ? key_d2(sk) : __builtin_inff();
     }
+    // 6. the row's candidate slots start empty (only the joins touch them)
+    for (int c = lane; c < C; c += 64) cand[row * C + c] = kEmptyCand;
 }
 
 // ---------------------------------------------------------------- sample
@@ -1245,7 +1248,6 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     if ((r = ws.alloc(&counters, 4)) != KNN_OK) return r;
     KNN_HIP(hipMemsetAsync(revnew, 0xFF, (size_t)n * cfg.R * 4, st));
     KNN_HIP(hipMemsetAsync(revold, 0xFF, (size_t)n * cfg.R * 4, st));
-    KNN_HIP(hipMemsetAsync(cand, 0xFF, (size_t)n * cfg.C * 8, st));
 
     // ---- init
     (void)hipEventRecord(t_init.a, st);
@@ -1279,7 +1281,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         nnd_init_kernel<KNN_F32><<<grid, 256, 0, st>>>(n, K, Xs, ldp, X.d, seed_idx, seed_d2, seed_fl, sk, p->seed,
                                                        gidx, gd2, gflag, given ? perm : nullptr,
                                                        given ? inv : nullptr, worst, wstride, sa,
-                                                       p->max_iters > 0);
+                                                       p->max_iters > 0, cand, cfg.C);
         KNN_HIP(hipGetLastError());
     }
     (void)hipEventRecord(t_init.b, st);

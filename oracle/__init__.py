@@ -12,7 +12,8 @@ What it computes (the C part lives in ``knn_oracle.c``):
   ordered by (distance, index), self excluded.
 * ``nndescent`` - sequential NNDescent of Dong, Charikar & Li (WWW 2011), the
   algorithm of the paper's GPU-native k-NN section, with its delta = 0.015
-  early-termination rule.
+  early-termination rule; ``nndescent_trace`` also returns the per-iteration
+  lists, samples and reverse unions.
 * ``round_bf16`` - FP32 -> BF16 round-to-nearest-even by bit definition.
 * ``mlp_forward`` / ``triplet_loss`` / ``mlp_backward`` / ``adam_step`` - the
   seeding encoder (d -> 64 -> 32, ReLU) in fp64.
@@ -64,6 +65,11 @@ def _load():
     lib.oracle_nndescent.argtypes = [_dp, i64, i64, i32, i32, i32, f64, f64, u64, C.c_void_p,
                                      _ip, _dp, C.POINTER(C.c_int), _ip]
     lib.oracle_nndescent.restype = i32
+    _u8 = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+    lib.oracle_nndescent_traced.argtypes = [_dp, i64, i64, i32, i32, i32, f64, f64, u64, C.c_void_p,
+                                            _ip, _dp, C.POINTER(C.c_int), _ip, i32,
+                                            _ip, _u8, _ip, _ip, _ip, _ip]
+    lib.oracle_nndescent_traced.restype = i32
     lib.oracle_round_bf16.argtypes = [np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS"),
                                       np.ctypeslib.ndpointer(dtype=np.uint16, flags="C_CONTIGUOUS"), i64]
     lib.oracle_round_bf16.restype = None
@@ -154,6 +160,44 @@ def nndescent(X, K: int, max_iters: int = 10, rho: float = 0.5, delta: float = 0
     if rc != 0:
         raise ValueError("oracle_nndescent: bad arguments")
     return idx, d2, iters.value, upd[:iters.value].copy()
+
+
+def nndescent_trace(X, K: int, max_iters: int, rho: float = 0.5, delta: float = 0.0,
+                    seed: int = 0, init_idx=None, trace_iters: int | None = None):
+    """Sequential NNDescent with a trace of its first ``trace_iters`` iterations.
+
+    Returns (idx, squared dist, iters, updates, trace) where trace holds, per
+    iteration t and point v (-1 pads every list): ``lidx`` / ``lflag`` (T x n x
+    K) the list and its new-flags as iteration t starts; ``newf`` (T x n x S)
+    and ``oldf`` (T x n x K) the forward samples; ``new`` (T x n x 2S) and
+    ``old`` (T x n x (K+S)) the lists after the reverse union.
+    """
+    X = _f64(X)
+    n, d = X.shape
+    T = max_iters if trace_iters is None else trace_iters
+    S = int(np.ceil(rho * K))
+    idx = np.empty((n, K), dtype=np.int64)
+    d2 = np.empty((n, K), dtype=np.float64)
+    iters = C.c_int(0)
+    upd = np.zeros(max(1, max_iters), dtype=np.int64)
+    T1 = max(T, 1)
+    tr = {"lidx": np.full((T1, n, K), -1, np.int64), "lflag": np.zeros((T1, n, K), np.uint8),
+          "newf": np.full((T1, n, S), -1, np.int64), "oldf": np.full((T1, n, K), -1, np.int64),
+          "new": np.full((T1, n, 2 * S), -1, np.int64), "old": np.full((T1, n, K + S), -1, np.int64)}
+    ini = None
+    if init_idx is not None:
+        ini_arr = np.ascontiguousarray(np.asarray(init_idx, dtype=np.int64))
+        if ini_arr.shape != (n, K):
+            raise ValueError("init_idx must be n x K")
+        ini = ini_arr.ctypes.data_as(C.c_void_p)
+    rc = _load().oracle_nndescent_traced(X, n, d, d, K, max_iters, float(rho), float(delta),
+                                         int(seed) & ((1 << 64) - 1), ini, idx, d2, C.byref(iters), upd,
+                                         T, tr["lidx"], tr["lflag"], tr["newf"], tr["oldf"],
+                                         tr["new"], tr["old"])
+    if rc != 0:
+        raise ValueError("oracle_nndescent: bad arguments")
+    tr = {key: val[:min(T, iters.value)] for key, val in tr.items()}
+    return idx, d2, iters.value, upd[:iters.value].copy(), tr
 
 
 def round_bf16(a) -> np.ndarray:

@@ -211,11 +211,24 @@ static int sample_wo_repl(const int64_t* a, int m, int s, int64_t* out,
  * updates_out[t] (capacity max_iters) the update count of iteration t.
  * Returns 0, or -1 on bad arguments / allocation failure.
  */
-int oracle_nndescent(const double* X, int64_t n, int64_t ld, int d, int K,
-                     int max_iters, double rho, double delta, uint64_t seed,
-                     const int64_t* init_idx,
-                     int64_t* out_idx, double* out_d2, int* iters_out,
-                     int64_t* updates_out)
+/*
+ * Optional trace of the first trace_iters iterations (every pointer NULL or
+ * all set), for checking the sample / reverse steps against hand-worked
+ * cases.  For iteration t and point v (-1 pads every list):
+ *   tr_lidx / tr_lflag  [t][v][0..K)     v's list and new-flags as the
+ *                                        iteration starts (before sampling);
+ *   tr_newf [t][v][0..S)                 the forward new sample new[v];
+ *   tr_oldf [t][v][0..K)                 the forward old list old[v];
+ *   tr_new  [t][v][0..2S)                new[v] after the reverse union;
+ *   tr_old  [t][v][0..K+S)               old[v] after the reverse union.
+ */
+int oracle_nndescent_traced(const double* X, int64_t n, int64_t ld, int d, int K,
+                            int max_iters, double rho, double delta, uint64_t seed,
+                            const int64_t* init_idx,
+                            int64_t* out_idx, double* out_d2, int* iters_out,
+                            int64_t* updates_out, int trace_iters,
+                            int64_t* tr_lidx, uint8_t* tr_lflag, int64_t* tr_newf,
+                            int64_t* tr_oldf, int64_t* tr_new, int64_t* tr_old)
 {
     if (n < 2 || K < 1 || K > n - 1 || d < 1 || rho <= 0.0 || rho > 1.0 ||
         delta < 0.0 || max_iters < 0)
@@ -291,6 +304,11 @@ int oracle_nndescent(const double* X, int64_t n, int64_t ld, int d, int K,
 
     int it = 0;
     for (; it < max_iters; ++it) {
+        const int tr = trace_iters > it && tr_lidx && tr_lflag && tr_newf && tr_oldf && tr_new && tr_old;
+        if (tr) {
+            memcpy(tr_lidx + (size_t)it * n * K, H.idx, sizeof(int64_t) * (size_t)n * K);
+            memcpy(tr_lflag + (size_t)it * n * K, H.isnew, (size_t)n * K);
+        }
         /* step 2: sample -- old = entries flagged old; new = S of the new ones */
         for (int64_t v = 0; v < n; ++v) {
             int64_t* I = H.idx + v * K;
@@ -306,6 +324,14 @@ int oracle_nndescent(const double* X, int64_t n, int64_t ld, int d, int K,
             for (int r = 0; r < take; ++r) {
                 newl[v * cap_new + nnew[v]++] = I[samp[r]];
                 F[samp[r]] = 0;
+            }
+        }
+        if (tr) {
+            for (int64_t v = 0; v < n; ++v) {
+                int64_t* a = tr_newf + ((size_t)it * n + v) * S;
+                int64_t* b = tr_oldf + ((size_t)it * n + v) * K;
+                for (int r = 0; r < S; ++r) a[r] = r < nnew[v] ? newl[v * cap_new + r] : -1;
+                for (int r = 0; r < K; ++r) b[r] = r < nold[v] ? oldl[v * cap_old + r] : -1;
             }
         }
         /* step 3: reverse lists (CSR, rows in increasing source order) */
@@ -338,6 +364,14 @@ int oracle_nndescent(const double* X, int64_t n, int64_t ld, int d, int K,
             m = (int)(rcnt_old[v + 1] - rcnt_old[v]);
             take = sample_wo_repl(rev_old + rcnt_old[v], m, S, samp, scratch, &rs);
             for (int r = 0; r < take; ++r) set_add(oldl + v * cap_old, &nold[v], cap_old, samp[r]);
+        }
+        if (tr) {
+            for (int64_t v = 0; v < n; ++v) {
+                int64_t* a = tr_new + ((size_t)it * n + v) * cap_new;
+                int64_t* b = tr_old + ((size_t)it * n + v) * cap_old;
+                for (int r = 0; r < cap_new; ++r) a[r] = r < nnew[v] ? newl[v * cap_new + r] : -1;
+                for (int r = 0; r < cap_old; ++r) b[r] = r < nold[v] ? oldl[v * cap_old + r] : -1;
+            }
         }
         /* step 4: local join, updates applied immediately */
         int64_t c = 0;
@@ -374,6 +408,18 @@ int oracle_nndescent(const double* X, int64_t n, int64_t ld, int d, int K,
     free(rcnt_new); free(rcnt_old); free(rev_new); free(rev_old);
     free(fill); free(pick); free(scratch); free(samp);
     return 0;
+}
+
+/* The same without a trace. */
+int oracle_nndescent(const double* X, int64_t n, int64_t ld, int d, int K,
+                     int max_iters, double rho, double delta, uint64_t seed,
+                     const int64_t* init_idx,
+                     int64_t* out_idx, double* out_d2, int* iters_out,
+                     int64_t* updates_out)
+{
+    return oracle_nndescent_traced(X, n, ld, d, K, max_iters, rho, delta, seed, init_idx,
+                                   out_idx, out_d2, iters_out, updates_out, 0,
+                                   NULL, NULL, NULL, NULL, NULL, NULL);
 }
 
 /* ------------------------------------------------------------- rounding */

@@ -12,8 +12,11 @@
  * Conventions for every entry point:
  *  - Pointers named as device pointers must point to device memory of the
  *    current HIP device; host pointers are marked "host".  The caller owns
- *    every buffer passed in; scratch is allocated internally and released
- *    before return.  Only knn_encoder objects are library-owned.
+ *    every buffer passed in.  Scratch (staged copies, working lists, slots)
+ *    is carved from a per-device arena that the library owns and keeps
+ *    between calls: it grows when a call needs more and is never returned
+ *    before the process ends, and calls on one device take turns on it.
+ *    knn_encoder objects are library-owned until destroyed.
  *  - `stream` is a hipStream_t (NULL = the null stream).  Every call is
  *    blocking: the stream is synchronised before return.
  *  - Errors are returned as knn_status (never thrown).  On error the outputs
@@ -40,7 +43,8 @@ enum {
     KNN_EINVAL = -1,   /* bad argument (size, pointer, enum) */
     KNN_ENOMEM = -2,   /* device allocation failed or workspace limit exceeded */
     KNN_EDEVICE = -3,  /* a HIP runtime call failed */
-    KNN_ENOTSUP = -4   /* valid request outside what is implemented (e.g. k > 64) */
+    KNN_ENOTSUP = -4   /* valid request outside what is implemented (e.g. k, re-rank
+                          width or K_b above KNN_MAX_K) */
 };
 
 /* element type of an input matrix */
@@ -100,6 +104,22 @@ knn_status knn_exact_query(knn_matrix Q, knn_matrix R, const int32_t* q_self, in
                            int32_t precision, int32_t rerank_k, int32_t out_kind,
                            int32_t* out_idx, float* out_dist, void* stream);
 
+/*
+ * knn_exact_query with a bound on its scratch: the queries are processed in
+ * chunks (multiples of 128 rows) small enough that the staged reference
+ * set plus one chunk's staged rows and candidate lists fit in
+ * workspace_limit_bytes; every chunk is a pass over R, so a smaller limit
+ * trades time for memory (the paper's chunked pairwise-distance evaluation,
+ * section "Scaling Behavior").  0 = no limit (one chunk).  Results are those
+ * of knn_exact_query.  Errors as knn_exact_query, plus KNN_ENOMEM when the
+ * staged reference set and a single 128-query chunk exceed the limit, and
+ * KNN_EINVAL for a negative limit.
+ */
+knn_status knn_exact_query_limited(knn_matrix Q, knn_matrix R, const int32_t* q_self, int32_t k,
+                                   int32_t precision, int32_t rerank_k, int32_t out_kind,
+                                   int64_t workspace_limit_bytes, int32_t* out_idx, float* out_dist,
+                                   void* stream);
+
 typedef struct knn_encoder knn_encoder;
 
 /* NNDescent parameters (Dong, Charikar & Li 2011; the paper fixes the
@@ -139,6 +159,13 @@ typedef struct {
      * there, so ms_sample is 0 */
     double ms_total, ms_init, ms_sample, ms_join, ms_merge, ms_final;
     float ms_join_iter[KNN_MAX_ITERS_LOGGED]; /* local-join kernel time per iteration */
+    /* offers that found their hashed candidate slot holding another source's
+     * key (one of the two is lost), per iteration; seen by each offer's slot
+     * read, so offers racing for one slot are not counted */
+    int64_t slot_collisions[KNN_MAX_ITERS_LOGGED];
+    /* join-list members not joined because the list exceeded 64 members
+     * (old members are cut first), per iteration */
+    int64_t list_dropped[KNN_MAX_ITERS_LOGGED];
 } knn_nnd_stats;
 
 /*
@@ -185,6 +212,11 @@ knn_status nndescent_refine(knn_matrix X, const knn_nnd_params* p,
  * Learned seeding: an MLP encoder d -> 64 -> 32 (ReLU hidden layer) whose
  * embedding is projected on P seeded directions; the sorted orders give
  * each point its window neighbours as initial candidates for NNDescent.
+ * The paper has no encoder: this learned-initialisation form is an addition
+ * that replaces the random k-neighbour init of NNDescent (paper, section
+ * "GPU-Native k-NN via NNDescent"), which stays the default and fallback.
+ * The activation, loss and optimiser are this library's choices: ReLU,
+ * triplet loss with a margin, Adam (Kingma & Ba 2015).
  * ---------------------------------------------------------------------- */
 #define KNN_ENC_H1 64
 #define KNN_ENC_H2 32
@@ -241,6 +273,32 @@ knn_status knn_encoder_train(knn_encoder* enc, knn_matrix X, const int32_t* knn_
                              const knn_train_params* t, float* loss_log, void* stream);
 
 /*
+ * The triplets training step `step` (0-based, counted over the encoder's
+ * life) of knn_encoder_train draws: rows (device, 3B int32) = [anchors;
+ * positives; negatives].  Anchor b and negative b are uniform rows of
+ * [0, n); positive b is knn_idx[anchor * k + j] for a uniform j < k (the
+ * anchor itself if that entry is out of range).  Each is a function of
+ * (seed, step, b).  knn_idx: device, n x k.
+ */
+knn_status knn_encoder_triplets(int64_t n, const int32_t* knn_idx, int32_t k, int32_t B,
+                                uint64_t seed, int32_t step, int32_t* rows, void* stream);
+
+/*
+ * One optimisation step on caller-given triplets: the gradient of
+ * knn_encoder_grads on rows (device, 3B int32) at the current weights, then
+ * Adam step t + 1 (t = steps taken so far) with t's settings (steps, batch
+ * and seed are not used).  knn_encoder_train's step s is this step on
+ * knn_encoder_triplets(seed = t->seed, step = steps taken before it).
+ * loss_out: host, nullable (the batch loss before the update).
+ */
+knn_status knn_encoder_step(knn_encoder* enc, knn_matrix X, const int32_t* rows, int32_t B,
+                            const knn_train_params* t, float* loss_out, void* stream);
+
+/* Adam state: first and second moments (host, as many floats as weights)
+ * and the number of steps taken. */
+knn_status knn_encoder_get_adam(const knn_encoder* enc, float* m, float* v, int32_t* t);
+
+/*
  * Seed lists from sorted projections of an embedding Z.  Order p uses the D
  * directions dirs[p*D .. p*D+D): the projections Z . r are FP32 sums in
  * coordinate order; D = 1 sorts by the projection itself, D > 1 by the
@@ -257,6 +315,36 @@ knn_status knn_encoder_train(knn_encoder* enc, knn_matrix X, const int32_t* knn_
 knn_status knn_proj_seed(knn_matrix X, const float* Z, int32_t m, const float* dirs,
                          int32_t P, int32_t D, int32_t w, int32_t K, int32_t* out_idx,
                          float* out_dist, void* stream);
+
+/* ----------------------------------------------------------------------
+ * The fuzzy graph UMAP-family methods build from the k-NN graph (UMAP of
+ * McInnes, Healy & Melville 2018; the paper's sections "Architecture" and
+ * "Method Implementations": every method starts from the shared k-NN stage).
+ * ---------------------------------------------------------------------- */
+
+/*
+ * Membership strengths of the graph's edges and their fuzzy union.
+ *  knn_idx, knn_dist  device, n x k: each row's neighbours (distinct, in
+ *      [0, n), not the row itself) and their Euclidean distances.
+ *  For row i: rho_i = smallest positive distance (0 if none); sigma_i > 0
+ *  solves sum_r exp(-max(0, d_ir - rho_i) / sigma_i) = log2(k), found in
+ *  double; rows where #{r : d_ir <= rho_i} >= log2(k) have no root and get
+ *  sigma_i = 0 with weights 1 where d_ir <= rho_i and 0 elsewhere (the
+ *  limit); w_ir = exp(-max(0, d_ir - rho_i) / sigma_i).
+ *  rho, sigma   device, nullable, n floats.
+ *  weights      device, nullable, n x k floats: w_ir.
+ *  The symmetric graph W = A + A^T - A o A^T (A[i][idx_ir] = w_ir) is
+ *  returned in CSR form: row_ptr (device, n + 1 int64), col (device, int32)
+ *  and val (device, float), each row's columns ascending; the pattern is the
+ *  union of the lists and their transpose (entries of value 0 are kept).
+ *  col and val must hold 2 n k entries; *nnz (host) receives the count.
+ * Errors: KNN_EINVAL for null pointers, n < 2, k < 1 or k > n - 1, or an
+ * entry of knn_idx out of range or equal to its row (detected after the
+ * work; outputs unspecified); KNN_ENOTSUP for k > KNN_MAX_K or 2 n k >= 2^32.
+ */
+knn_status knn_fuzzy_graph(const int32_t* knn_idx, const float* knn_dist, int64_t n, int32_t k,
+                           float* rho, float* sigma, float* weights, int64_t* row_ptr,
+                           int32_t* col, float* val, int64_t* nnz, void* stream);
 
 #ifdef __cplusplus
 }

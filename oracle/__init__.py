@@ -88,6 +88,8 @@ def _load():
     lib.oracle_proj_keys.argtypes = [_fp, i64, i32, _fp, i32,
                                      np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS"), _fp]
     lib.oracle_proj_keys.restype = i32
+    lib.oracle_fuzzy_rows.argtypes = [_dp, i64, i32, _dp, _dp, _dp]
+    lib.oracle_fuzzy_rows.restype = None
     _lib = lib
     return lib
 
@@ -313,3 +315,41 @@ def proj_keys(Z, dirs, D: int = 1) -> np.ndarray:
     if _load().oracle_proj_keys(Z, n, Z.shape[1], dirs, D, keys, y) != 0:
         raise ValueError("oracle_proj_keys: bad D")
     return keys
+
+
+def fuzzy_rows(dist):
+    """Per-row UMAP membership strengths of a k-NN graph's edges.
+
+    dist: n x k Euclidean neighbour distances (self excluded).  Returns
+    (rho n, sigma n, w n x k) in fp64 (see oracle_fuzzy_rows)."""
+    d = _f64(dist)
+    n, k = d.shape
+    rho, sigma, w = np.empty(n), np.empty(n), np.empty((n, k))
+    _load().oracle_fuzzy_rows(d, n, k, rho, sigma, w)
+    return rho, sigma, w
+
+
+def fuzzy_union(idx, w, rows=None):
+    """Fuzzy union W = A + A^T - A o A^T of the directed memberships A
+    (A[i, idx[i, r]] = w[i, r]), as sorted rows: for each requested row i a
+    list of (column, value) pairs sorted by column.  The row's columns are
+    its k neighbours and every j that lists i.  Rows default to all."""
+    idx = np.asarray(idx, dtype=np.int64)
+    w = np.asarray(w, dtype=np.float64)
+    n, k = idx.shape
+    rows = range(n) if rows is None else rows
+    # who lists whom: edge numbers grouped by target
+    flat = idx.ravel()
+    order = np.argsort(flat, kind="stable")
+    tgt = flat[order]
+    out = []
+    for i in rows:
+        a = {}
+        for r in range(k):
+            a[int(idx[i, r])] = float(w[i, r])
+        # reverse edges j -> i
+        lo, hi = np.searchsorted(tgt, i, "left"), np.searchsorted(tgt, i, "right")
+        b = {int(e // k): float(w[e // k, e % k]) for e in order[lo:hi]}
+        cols = sorted(set(a) | set(b))
+        out.append([(j, a.get(j, 0.0) + b.get(j, 0.0) - a.get(j, 0.0) * b.get(j, 0.0)) for j in cols])
+    return out

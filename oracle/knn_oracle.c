@@ -714,3 +714,63 @@ int oracle_proj_seed(const double* X, int64_t n, int64_t ld, int d,
     free(cand);
     return 0;
 }
+
+/* ------------------------------------------- fuzzy graph (UMAP weights) */
+
+/*
+ * Membership strengths of each point's k-NN edges, as UMAP defines them
+ * (McInnes, Healy & Melville 2018; the graph every UMAP-family method of the
+ * paper builds from the shared k-NN stage).  For row i with neighbour
+ * distances d_1..d_k (Euclidean, self excluded):
+ *   rho_i   = the smallest positive d_r (0 if none is positive);
+ *   sigma_i > 0 solves  sum_r exp(-max(0, d_r - rho_i) / sigma_i) = log2(k);
+ *   w_ir    = exp(-max(0, d_r - rho_i) / sigma_i).
+ * The sum falls from k (sigma -> inf) to c_i = #{r : d_r <= rho_i}
+ * (sigma -> 0), so a root exists iff c_i < log2(k).  Otherwise sigma_i = 0
+ * and the weights are the limit: 1 where d_r <= rho_i, else 0.
+ * sigma is found by bisection in double: a bracket [0, hi] whose hi doubles
+ * from max(d_r - rho_i) until the sum reaches log2(k), halved until no
+ * double lies strictly inside.
+ */
+static double fuzzy_sum(const double* x, int k, double sigma)
+{
+    double s = 0.0;
+    for (int r = 0; r < k; ++r) s += exp(-x[r] / sigma);
+    return s;
+}
+
+void oracle_fuzzy_rows(const double* dist, int64_t n, int k, double* rho, double* sigma, double* w)
+{
+    double* x = (double*)malloc(sizeof(double) * (size_t)(k > 0 ? k : 1));
+    const double target = log2((double)k);
+    for (int64_t i = 0; i < n; ++i) {
+        const double* d = dist + i * k;
+        double p = 0.0;
+        for (int r = 0; r < k; ++r)
+            if (d[r] > 0.0 && (p == 0.0 || d[r] < p)) p = d[r];
+        int cnt = 0;
+        double xmax = 0.0;
+        for (int r = 0; r < k; ++r) {
+            x[r] = d[r] - p > 0.0 ? d[r] - p : 0.0;
+            if (x[r] == 0.0) ++cnt;
+            if (x[r] > xmax) xmax = x[r];
+        }
+        rho[i] = p;
+        if ((double)cnt >= target) {
+            sigma[i] = 0.0;
+            for (int r = 0; r < k; ++r) w[i * k + r] = x[r] == 0.0 ? 1.0 : 0.0;
+            continue;
+        }
+        double lo = 0.0, hi = xmax;
+        while (fuzzy_sum(x, k, hi) < target) hi *= 2.0;
+        for (;;) {
+            const double mid = 0.5 * (lo + hi);
+            if (!(mid > lo && mid < hi)) break;
+            if (fuzzy_sum(x, k, mid) < target) lo = mid;
+            else hi = mid;
+        }
+        sigma[i] = hi;
+        for (int r = 0; r < k; ++r) w[i * k + r] = exp(-x[r] / hi);
+    }
+    free(x);
+}

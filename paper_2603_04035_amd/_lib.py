@@ -56,7 +56,9 @@ class knn_nnd_stats(C.Structure):
                 ("bytes_gathered", C.c_uint64),
                 ("ms_total", C.c_double), ("ms_init", C.c_double), ("ms_sample", C.c_double),
                 ("ms_join", C.c_double), ("ms_merge", C.c_double), ("ms_final", C.c_double),
-                ("ms_join_iter", C.c_float * MAX_ITERS_LOGGED)]
+                ("ms_join_iter", C.c_float * MAX_ITERS_LOGGED),
+                ("slot_collisions", C.c_int64 * MAX_ITERS_LOGGED),
+                ("list_dropped", C.c_int64 * MAX_ITERS_LOGGED)]
 
     def as_dict(self) -> dict:
         it = self.iters
@@ -66,7 +68,9 @@ class knn_nnd_stats(C.Structure):
                 "bytes_gathered": int(self.bytes_gathered),
                 "ms_total": self.ms_total, "ms_init": self.ms_init, "ms_sample": self.ms_sample,
                 "ms_join": self.ms_join, "ms_merge": self.ms_merge, "ms_final": self.ms_final,
-                "ms_join_iter": [round(x, 4) for x in self.ms_join_iter[:min(it, MAX_ITERS_LOGGED)]]}
+                "ms_join_iter": [round(x, 4) for x in self.ms_join_iter[:min(it, MAX_ITERS_LOGGED)]],
+                "slot_collisions": list(self.slot_collisions[:min(it, MAX_ITERS_LOGGED)]),
+                "list_dropped": list(self.list_dropped[:min(it, MAX_ITERS_LOGGED)])}
 
 
 class knn_train_params(C.Structure):
@@ -81,6 +85,8 @@ EXPORTS = [
     "knn_encoder_create", "knn_encoder_destroy", "knn_encoder_set_weights",
     "knn_encoder_get_weights", "knn_encoder_embed", "knn_encoder_grads",
     "knn_train_default_params", "knn_encoder_train", "knn_proj_seed",
+    "knn_encoder_triplets", "knn_encoder_step", "knn_encoder_get_adam",
+    "knn_exact_query_limited", "knn_fuzzy_graph",
 ]
 
 _lib = None
@@ -103,6 +109,10 @@ def load() -> C.CDLL:
     lib.knn_exact.argtypes = [knn_matrix, i32, i32, i32, i32, vp, vp, vp]
     lib.knn_exact_query.restype = i32
     lib.knn_exact_query.argtypes = [knn_matrix, knn_matrix, vp, i32, i32, i32, i32, vp, vp, vp]
+    lib.knn_exact_query_limited.restype = i32
+    lib.knn_exact_query_limited.argtypes = [knn_matrix, knn_matrix, vp, i32, i32, i32, i32, i64, vp, vp, vp]
+    lib.knn_fuzzy_graph.restype = i32
+    lib.knn_fuzzy_graph.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, vp, vp, C.POINTER(C.c_int64), vp]
     lib.knn_nnd_default_params.restype = None
     lib.knn_nnd_default_params.argtypes = [i32, C.POINTER(knn_nnd_params)]
     lib.nndescent_build.restype = i32
@@ -127,6 +137,13 @@ def load() -> C.CDLL:
     lib.knn_train_default_params.argtypes = [C.POINTER(knn_train_params)]
     lib.knn_encoder_train.restype = i32
     lib.knn_encoder_train.argtypes = [vp, knn_matrix, vp, i32, C.POINTER(knn_train_params), vp, vp]
+    lib.knn_encoder_triplets.restype = i32
+    lib.knn_encoder_triplets.argtypes = [i64, vp, i32, i32, u64, i32, vp, vp]
+    lib.knn_encoder_step.restype = i32
+    lib.knn_encoder_step.argtypes = [vp, knn_matrix, vp, i32, C.POINTER(knn_train_params),
+                                     C.POINTER(C.c_float), vp]
+    lib.knn_encoder_get_adam.restype = i32
+    lib.knn_encoder_get_adam.argtypes = [vp, vp, vp, C.POINTER(C.c_int32)]
     lib.knn_proj_seed.restype = i32
     lib.knn_proj_seed.argtypes = [knn_matrix, vp, i32, vp, i32, i32, i32, i32, vp, vp, vp]
     _lib = lib
@@ -179,8 +196,12 @@ def knn_exact(X: torch.Tensor, k: int, precision: str = "fp32", rerank_k: int = 
 
 
 def knn_exact_query(Q: torch.Tensor, R: torch.Tensor, k: int, q_self=None,
-                    precision: str = "fp32", rerank_k: int = 0, out: str = "l2"):
-    """Exact kNN of the rows of Q among the rows of R (q_self: rows to exclude)."""
+                    precision: str = "fp32", rerank_k: int = 0, out: str = "l2",
+                    workspace_limit: int = 0):
+    """Exact kNN of the rows of Q among the rows of R (q_self: rows to exclude).
+
+    workspace_limit > 0 bounds the call's scratch bytes (queries are then
+    processed in chunks, each a pass over R)."""
     lib = load()
     nq = Q.shape[0]
     idx = torch.empty((nq, k), dtype=torch.int32, device=Q.device)
@@ -188,8 +209,13 @@ def knn_exact_query(Q: torch.Tensor, R: torch.Tensor, k: int, q_self=None,
     qs = None
     if q_self is not None:
         qs = torch.as_tensor(q_self, dtype=torch.int32, device=Q.device).contiguous()
-    _check(lib.knn_exact_query(matrix(Q), matrix(R), _ptr(qs), k, _PREC[precision], rerank_k,
-                               _OUT[out], idx.data_ptr(), dist.data_ptr(), _stream()))
+    if workspace_limit:
+        _check(lib.knn_exact_query_limited(matrix(Q), matrix(R), _ptr(qs), k, _PREC[precision], rerank_k,
+                                           _OUT[out], int(workspace_limit), idx.data_ptr(), dist.data_ptr(),
+                                           _stream()))
+    else:
+        _check(lib.knn_exact_query(matrix(Q), matrix(R), _ptr(qs), k, _PREC[precision], rerank_k,
+                                   _OUT[out], idx.data_ptr(), dist.data_ptr(), _stream()))
     return idx, dist
 
 
@@ -264,3 +290,26 @@ def nndescent_refine(X: torch.Tensor, k: int, init_idx: torch.Tensor, init_dist=
     if return_state:
         return idx, dist, st.as_dict(), (si, sd, sf)
     return idx, dist, st.as_dict()
+
+
+def fuzzy_graph(idx: torch.Tensor, dist: torch.Tensor):
+    """UMAP membership strengths and fuzzy union of a k-NN graph.
+
+    Returns (rho n, sigma n, weights n x k, row_ptr n+1 int64, col int32,
+    val float32) with col / val cut to the nonzero count."""
+    lib = load()
+    idx = idx.to(torch.int32).contiguous()
+    dist = dist.to(torch.float32).contiguous()
+    n, k = idx.shape
+    dev = idx.device
+    rho = torch.empty(n, dtype=torch.float32, device=dev)
+    sigma = torch.empty(n, dtype=torch.float32, device=dev)
+    w = torch.empty((n, k), dtype=torch.float32, device=dev)
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(2 * n * k, dtype=torch.int32, device=dev)
+    val = torch.empty(2 * n * k, dtype=torch.float32, device=dev)
+    nnz = C.c_int64()
+    _check(lib.knn_fuzzy_graph(idx.data_ptr(), dist.data_ptr(), n, k, rho.data_ptr(), sigma.data_ptr(),
+                               w.data_ptr(), row_ptr.data_ptr(), col.data_ptr(), val.data_ptr(),
+                               C.byref(nnz), _stream()))
+    return rho, sigma, w, row_ptr, col[:nnz.value], val[:nnz.value]

@@ -304,6 +304,17 @@ knn_status fail(knn_status s, const std::string& msg);
                                                 hipGetErrorString(e_));                \
     } while (0)
 
+// Where an entry point's scratch comes from: alloc hands out a 256-byte
+// aligned block that stays valid until the call returns.
+class ScratchAlloc {
+public:
+    virtual ~ScratchAlloc() = default;
+    // returns KNN_OK or KNN_ENOMEM / KNN_EDEVICE
+    virtual knn_status alloc(void** p, size_t bytes) = 0;
+    template <typename T>
+    knn_status alloc(T** p, size_t count) { return alloc((void**)p, count * sizeof(T)); }
+};
+
 // Scratch for one entry-point call.  Requests are carved (256-byte aligned)
 // from a grow-only arena that the library keeps per device, so steady-state
 // calls neither allocate nor free device memory.  The arena is held by one
@@ -313,14 +324,12 @@ knn_status fail(knn_status s, const std::string& msg);
 // does not fit is served from a library-owned stream-ordered pool for this
 // call, and the arena is regrown to the call's total for the next one.
 // Only one Workspace may be alive per thread.
-class Workspace {
+class Workspace : public ScratchAlloc {
 public:
     Workspace(hipStream_t s, int64_t limit);
-    ~Workspace();
-    // returns KNN_OK or KNN_ENOMEM / KNN_EDEVICE
-    knn_status alloc(void** p, size_t bytes);
-    template <typename T>
-    knn_status alloc(T** p, size_t count) { return alloc((void**)p, count * sizeof(T)); }
+    ~Workspace() override;
+    using ScratchAlloc::alloc;
+    knn_status alloc(void** p, size_t bytes) override;
     size_t used() const { return used_; }
 
 private:

@@ -460,14 +460,29 @@ __global__ __launch_bounds__(256) void rs_scatter_kernel(const uint32_t* __restr
     }
 }
 
+knn_status radix_sort_bits(uint32_t*& k0, uint32_t*& v0, uint32_t*& k1, uint32_t*& v1, int64_t n,
+                           uint32_t* counts, hipStream_t st, int bits, int S);
+
 // Sort S independent arrays of (key, value) pairs, n each and contiguous
 // (k0 + y n, ...), by key, stable; results in (k0, v0).  k1 / v1 hold S n
 // words and counts S rs_counts(n) words.
 static knn_status radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
                                    uint32_t* counts, hipStream_t st, int S = 1)
 {
+    return radix_sort_bits(k0, v0, k1, v1, n, counts, st, 32, S);
+}
+
+size_t radix_counts_words(int64_t n) { return rs_counts(n); }
+
+// As radix_sort_pairs, on keys below 2^bits: ceil(bits / 8) passes (bits in
+// 1..32).  An odd pass count leaves the result in (k1, v1): the pointers are
+// swapped so that (k0, v0) name the sorted arrays on return.
+knn_status radix_sort_bits(uint32_t*& k0, uint32_t*& v0, uint32_t*& k1, uint32_t*& v1, int64_t n,
+                           uint32_t* counts, hipStream_t st, int bits, int S)
+{
     const int nblk = (int)ceil_div(n, kRsTile);
-    for (int pass = 0; pass < 4; ++pass) {
+    const int npass = (bits + 7) / 8;
+    for (int pass = 0; pass < npass; ++pass) {
         const int shift = 8 * pass;
         rs_hist_kernel<<<dim3((unsigned)nblk, (unsigned)S), kRsThreads, 0, st>>>(k0, n, shift, counts, nblk);
         rs_scan_kernel<<<dim3(256, (unsigned)S), 256, 0, st>>>(counts, n, nblk);
@@ -477,7 +492,7 @@ static knn_status radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uin
         std::swap(k0, k1);
         std::swap(v0, v1);
     }
-    return KNN_OK;   // 4 passes: data is back in the original buffers
+    return KNN_OK;
 }
 
 // -------------------------------------------------------------- seeding
@@ -1033,6 +1048,21 @@ static knn_status batch_grads(const knn_encoder* enc, const knn_matrix& X, const
     return KNN_OK;
 }
 
+// Adam step number t (1-based) on the encoder's FP32 weights with gradient
+// grad: the bias corrections 1 - beta^t are computed on the host in double
+// (in FP32, 1 - 0.999^t loses about 2^-24 / (1 - 0.999^t) relative to the
+// cancellation: 3e-5 at t = 2) and rounded once.
+static knn_status adam_apply(knn_encoder* enc, const float* grad, const knn_train_params& tp, int t,
+                             hipStream_t st)
+{
+    const float c1 = (float)(1.0 - pow((double)tp.beta1, (double)t));
+    const float c2 = (float)(1.0 - pow((double)tp.beta2, (double)t));
+    adam_kernel<<<(unsigned)ceil_div(enc->P, 256), 256, 0, st>>>(enc->params, grad, enc->mom, enc->vel, enc->P,
+                                                                 tp.lr, tp.beta1, tp.beta2, tp.eps, c1, c2);
+    KNN_HIP(hipGetLastError());
+    return KNN_OK;
+}
+
 }  // namespace knn
 
 using namespace knn;
@@ -1208,11 +1238,7 @@ extern "C" knn_status knn_encoder_train(knn_encoder* enc, knn_matrix X, const in
             r = batch_grads(enc, X, rows, B, tp->margin, tp->precision, H, Z, dZ, dH, lterm, partial, grad,
                             losses + s, st);
             if (r != KNN_OK) return r;
-            const int t = enc->t + s + 1;
-            const float c1 = 1.0f - powf(tp->beta1, (float)t), c2 = 1.0f - powf(tp->beta2, (float)t);
-            adam_kernel<<<(unsigned)ceil_div(o.P, 256), 256, 0, st>>>(enc->params, grad, enc->mom, enc->vel, o.P,
-                                                                      tp->lr, tp->beta1, tp->beta2, tp->eps, c1, c2);
-            KNN_HIP(hipGetLastError());
+            if ((r = adam_apply(enc, grad, *tp, enc->t + s + 1, st)) != KNN_OK) return r;
         }
         enc->t += tp->steps;
         if (loss_log && tp->steps > 0)
@@ -1222,6 +1248,68 @@ extern "C" knn_status knn_encoder_train(knn_encoder* enc, knn_matrix X, const in
     } catch (...) {
         return fail(KNN_EDEVICE, "unexpected exception");
     }
+}
+
+extern "C" knn_status knn_encoder_triplets(int64_t n, const int32_t* knn_idx, int32_t k, int32_t B,
+                                           uint64_t seed, int32_t step, int32_t* rows, void* stream)
+{
+    try {
+        if (!knn_idx || !rows) return fail(KNN_EINVAL, "null argument");
+        if (n < 1 || n >= (int64_t)0x7FFFFFFF || k < 1 || B < 1 || step < 0)
+            return fail(KNN_EINVAL, "bad triplet arguments");
+        hipStream_t st = (hipStream_t)stream;
+        triplet_sample_kernel<<<(unsigned)ceil_div(B, 256), 256, 0, st>>>(n, knn_idx, k, B, seed, step, rows);
+        KNN_HIP(hipGetLastError());
+        KNN_HIP(hipStreamSynchronize(st));
+        return KNN_OK;
+    } catch (...) {
+        return fail(KNN_EDEVICE, "unexpected exception");
+    }
+}
+
+extern "C" knn_status knn_encoder_step(knn_encoder* enc, knn_matrix X, const int32_t* rows, int32_t B,
+                                       const knn_train_params* tp, float* loss_out, void* stream)
+{
+    try {
+        if (!enc || !rows || !tp) return fail(KNN_EINVAL, "null argument");
+        knn_status r = check_matrix(X, "X");
+        if (r != KNN_OK) return r;
+        if (X.d != enc->d) return fail(KNN_EINVAL, "X.d != encoder input width");
+        if (B < 1) return fail(KNN_EINVAL, "B must be >= 1");
+        if (tp->precision != KNN_PREC_FP32 && tp->precision != KNN_PREC_BF16)
+            return fail(KNN_EINVAL, "unknown precision");
+        hipStream_t st = (hipStream_t)stream;
+        Workspace ws(st, 0);
+        const int64_t m = 3 * (int64_t)B;
+        const Off o(enc->d);
+        float *H, *Z, *dZ, *dH, *lterm, *partial, *grad, *loss_dev;
+        if ((r = ws.alloc(&H, (size_t)m * H1)) != KNN_OK) return r;
+        if ((r = ws.alloc(&Z, (size_t)m * H2)) != KNN_OK) return r;
+        if ((r = ws.alloc(&dZ, (size_t)m * H2)) != KNN_OK) return r;
+        if ((r = ws.alloc(&dH, (size_t)m * H1)) != KNN_OK) return r;
+        if ((r = ws.alloc(&lterm, (size_t)B)) != KNN_OK) return r;
+        if ((r = ws.alloc(&partial, (size_t)ceil_div(m, kGradChunk) * o.P)) != KNN_OK) return r;
+        if ((r = ws.alloc(&grad, (size_t)o.P)) != KNN_OK) return r;
+        if ((r = ws.alloc(&loss_dev, 1)) != KNN_OK) return r;
+        r = batch_grads(enc, X, rows, B, tp->margin, tp->precision, H, Z, dZ, dH, lterm, partial, grad, loss_dev, st);
+        if (r != KNN_OK) return r;
+        if ((r = adam_apply(enc, grad, *tp, enc->t + 1, st)) != KNN_OK) return r;
+        enc->t += 1;
+        if (loss_out) KNN_HIP(hipMemcpyAsync(loss_out, loss_dev, 4, hipMemcpyDeviceToHost, st));
+        KNN_HIP(hipStreamSynchronize(st));
+        return KNN_OK;
+    } catch (...) {
+        return fail(KNN_EDEVICE, "unexpected exception");
+    }
+}
+
+extern "C" knn_status knn_encoder_get_adam(const knn_encoder* enc, float* m, float* v, int32_t* t)
+{
+    if (!enc || !m || !v || !t) return fail(KNN_EINVAL, "null argument");
+    KNN_HIP(hipMemcpy(m, enc->mom, (size_t)enc->P * 4, hipMemcpyDeviceToHost));
+    KNN_HIP(hipMemcpy(v, enc->vel, (size_t)enc->P * 4, hipMemcpyDeviceToHost));
+    *t = enc->t;
+    return KNN_OK;
 }
 
 extern "C" knn_status knn_proj_seed(knn_matrix X, const float* Z, int32_t m, const float* dirs, int32_t P,

@@ -20,6 +20,7 @@
 //     certified when its k-th re-ranked distance is below the k'-th GEMM
 //     distance minus the worst-case GEMM error bound; other rows are
 //  4. recomputed exhaustively with direct differences.
+
 #include "knn_common.hpp"
 
 namespace knn {
@@ -204,7 +205,7 @@ template <bool BF, bool ARES>
 __global__ __launch_bounds__(256, 2) void exact_tile_kernel(
     const void* __restrict__ Qs, const float* __restrict__ qn, int64_t nq,
     const void* __restrict__ Rs, const float* __restrict__ rn, int64_t nr, int ldp,
-    const int32_t* __restrict__ q_self, int self_mode, int kp, int64_t split_len, int S,
+    const int32_t* __restrict__ q_self, int self_mode, int64_t self_base, int kp, int64_t split_len, int S,
     const unsigned* __restrict__ rmax_bits, uint64_t* __restrict__ part)
 {
     using C = TileCfg<BF>;
@@ -227,7 +228,7 @@ __global__ __launch_bounds__(256, 2) void exact_tile_kernel(
     if (tid < kTileRows) {
         const int64_t qr = q0 + tid;
         sqn[tid] = qr < nq ? qn[qr] : 0.0f;
-        sself[tid] = qr >= nq ? -1 : (self_mode == 1 ? (int32_t)qr : (self_mode == 2 ? q_self[qr] : -1));
+        sself[tid] = qr >= nq ? -1 : (self_mode == 1 ? (int32_t)(self_base + qr) : (self_mode == 2 ? q_self[qr] : -1));
     }
     // Per-row lists of this lane's 16 accumulator rows and their gates.
     // A candidate enters a list when d2 = |q|^2 + |r|^2 - 2 q.r <= thr (the
@@ -446,7 +447,7 @@ template <int DT>
 __global__ __launch_bounds__(256) void exact_fallback_kernel(
     const int32_t* __restrict__ fb_rows, const int* __restrict__ fb_count,
     const void* __restrict__ Q, int64_t ldq, const void* __restrict__ R, int64_t ldr, int64_t nr,
-    int d, const int32_t* __restrict__ q_self, int self_mode, int k, int out_kind,
+    int d, const int32_t* __restrict__ q_self, int self_mode, int64_t self_base, int k, int out_kind,
     int32_t* __restrict__ out_idx, float* __restrict__ out_dist)
 {
     __shared__ uint64_t sl[4][64];
@@ -454,7 +455,7 @@ __global__ __launch_bounds__(256) void exact_fallback_kernel(
     const int cnt = *fb_count;
     for (int f = blockIdx.x; f < cnt; f += gridDim.x) {
         const int64_t row = fb_rows[f];
-        const int64_t self = self_mode == 1 ? row : (self_mode == 2 ? (int64_t)q_self[row] : -1);
+        const int64_t self = self_mode == 1 ? self_base + row : (self_mode == 2 ? (int64_t)q_self[row] : -1);
         uint64_t list = kEmptyList;
         for (int64_t base = (int64_t)wv * 64; base < nr; base += 256) {
             uint64_t cand = kEmptyCand;
@@ -509,7 +510,7 @@ static void launch_stage(const knn_matrix& X, void* Xs, int ldp, float* norms, u
 // ld = roundup(d, 64), both 128-byte multiples), norms and max norm.  Row r
 // of the copy is row rowmap[r] of X (rowmap nullable: identity).  With aux,
 // ld leaves room for the two trailing FP32 words (see stage_kernel).
-knn_status stage_matrix(Workspace& ws, const knn_matrix& X, bool bf16, void** Xs, int* ldp,
+knn_status stage_matrix(ScratchAlloc& ws, const knn_matrix& X, bool bf16, void** Xs, int* ldp,
                         float** norms, unsigned* maxnorm, hipStream_t st, const uint32_t* rowmap,
                         int aux)
 {
@@ -525,10 +526,52 @@ knn_status stage_matrix(Workspace& ws, const knn_matrix& X, bool bf16, void** Xs
     return KNN_OK;
 }
 
+// Zero n words (a fill kernel rather than hipMemsetAsync, so that no memset
+// node is recorded when a caller captures the stream).
+__global__ __launch_bounds__(64) void zero_words_kernel(unsigned* __restrict__ p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += 64) p[i] = 0u;
+}
+
+// Reference splits of a query chunk of qn rows: enough workgroups to fill
+// the chip (about 2048), at most 4; every split starts from empty lists,
+// which costs merges.
+static int exact_splits(int64_t qn)
+{
+    const int64_t nblk = ceil_div(qn, kTileRows);
+    const int64_t S = ceil_div(2048, nblk);
+    return (int)(S < 1 ? 1 : (S > 4 ? 4 : S));
+}
+
+static size_t elem_bytes(int dtype) { return dtype == KNN_F32 ? 4 : 2; }
+
+// Scratch bytes of one exact call with query chunks of qc rows (every
+// request rounded to 256 bytes, as the allocators carve them).
+static size_t exact_scratch(const knn_matrix& Q, const knn_matrix& R, bool same, bool bf, int64_t qc)
+{
+    auto r256 = [](size_t b) { return (size_t)round_up((int64_t)(b ? b : 1), 256); };
+    const int ldp = bf ? (int)round_up(R.d, 64) : (int)round_up(R.d, 32);
+    const size_t eb = bf ? 2 : 4;
+    size_t b = r256(16) + r256((size_t)R.n * ldp * eb) + r256((size_t)R.n * 4);
+    if (!same) b += r256((size_t)qc * ldp * eb) + r256((size_t)qc * 4);
+    const int S = exact_splits(qc);
+    const int64_t slen = round_up(ceil_div(R.n, S), kTileRows);
+    const int Sx = (int)ceil_div(R.n, slen);
+    b += r256((size_t)qc * Sx * kListW * 8) + r256((size_t)qc * 4);
+    return b;
+}
+
+// The exact k-NN of Q's rows among R's rows.  Queries are processed in
+// chunks of qc rows (all of them when budget is 0) so that the scratch,
+// taken from ws, stays within `budget` bytes: the staged reference set
+// plus, per chunk, the staged query rows, the split lists and the fallback
+// list.  A smaller budget means more chunks, each a pass over R: time for
+// memory.  self_mode 1 excludes reference row q for query q (Q == R);
+// self_mode 2 excludes q_self[q].
 static knn_status exact_impl(const knn_matrix& Q, const knn_matrix& R, bool same,
                              const int32_t* q_self, int self_mode, int32_t k, int32_t precision,
                              int32_t rerank_k, int32_t out_kind, int32_t* out_idx, float* out_dist,
-                             hipStream_t st)
+                             hipStream_t st, ScratchAlloc& ws, int64_t budget)
 {
     if (precision != KNN_PREC_FP32 && precision != KNN_PREC_BF16)
         return fail(KNN_EINVAL, "precision must be KNN_PREC_FP32 or KNN_PREC_BF16");
@@ -542,57 +585,52 @@ static knn_status exact_impl(const knn_matrix& Q, const knn_matrix& R, bool same
     if (kp < k) return fail(KNN_EINVAL, "rerank_k must be >= k");
     if (kp > kListW || k > KNN_MAX_K)
         return fail(KNN_ENOTSUP, "rerank_k and k above 32 are not supported by the exact path");
+    if (budget < 0) return fail(KNN_EINVAL, "workspace limit must be >= 0");
     if (Q.n == 0) return KNN_OK;
     const bool bf = precision == KNN_PREC_BF16;
 
-    Workspace ws(st, 0);
+    // query chunk: the largest multiple of the tile height that fits
+    int64_t qc = Q.n;
+    if (budget > 0 && exact_scratch(Q, R, same, bf, qc) > (size_t)budget) {
+        int64_t lo = 0, hi = ceil_div(Q.n, kTileRows);   // in tiles: lo fits (0 = none), hi does not
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) / 2;
+            if (exact_scratch(Q, R, same, bf, mid * kTileRows) <= (size_t)budget) lo = mid;
+            else hi = mid;
+        }
+        if (lo == 0)
+            return fail(KNN_ENOMEM, "workspace limit of " + std::to_string(budget) + " bytes is below the " +
+                                        std::to_string(exact_scratch(Q, R, same, bf, kTileRows)) +
+                                        " bytes the staged reference set and one 128-query chunk need");
+        qc = lo * kTileRows;
+    }
+
     knn_status r;
     unsigned* small = nullptr;   // [0] = max ref norm bits, [1] = fallback count
     r = ws.alloc(&small, 4);
     if (r != KNN_OK) return r;
-    KNN_HIP(hipMemsetAsync(small, 0, 16, st));
-    void *Qs = nullptr, *Rs = nullptr;
-    float *qn = nullptr, *rn = nullptr;
-    int ldp = 0, ldp2 = 0;
+    zero_words_kernel<<<1, 64, 0, st>>>(small, 4);
+    void *Rs = nullptr, *Qb = nullptr;
+    float *rn = nullptr, *qnb = nullptr;
+    int ldp = 0;
     r = stage_matrix(ws, R, bf, &Rs, &ldp, &rn, small, st, nullptr, 0);
     if (r != KNN_OK) return r;
-    if (same) {
-        Qs = Rs;
-        qn = rn;
-    } else {
-        r = stage_matrix(ws, Q, bf, &Qs, &ldp2, &qn, nullptr, st, nullptr, 0);
-        if (r != KNN_OK) return r;
+    const size_t eb = bf ? 2 : 4;
+    if (!same) {
+        if ((r = ws.alloc(&Qb, (size_t)qc * ldp * eb)) != KNN_OK) return r;
+        if ((r = ws.alloc(&qnb, (size_t)qc)) != KNN_OK) return r;
     }
-
-    // Reference splits: enough workgroups to fill the chip (about 2048),
-    // at most 4; every split starts from empty lists, which costs merges.
-    const int64_t nblk = ceil_div(Q.n, kTileRows);
-    int S = (int)ceil_div(2048, nblk);
-    S = S < 1 ? 1 : (S > 4 ? 4 : S);
-    int64_t split_len = round_up(ceil_div(R.n, S), kTileRows);
-    S = (int)ceil_div(R.n, split_len);
+    const int S0 = exact_splits(qc);
+    const int64_t split_len = round_up(ceil_div(R.n, S0), kTileRows);
+    const int S = (int)ceil_div(R.n, split_len);
     uint64_t* part = nullptr;
-    r = ws.alloc(&part, (size_t)Q.n * S * kListW);
+    r = ws.alloc(&part, (size_t)qc * S * kListW);
     if (r != KNN_OK) return r;
     int32_t* fb_rows = nullptr;
-    r = ws.alloc(&fb_rows, (size_t)Q.n);
+    r = ws.alloc(&fb_rows, (size_t)qc);
     if (r != KNN_OK) return r;
 
-    dim3 tgrid((unsigned)nblk, (unsigned)S);
     const bool ares = ldp <= (bf ? TileCfg<true>::AMAX : TileCfg<false>::AMAX);
-#define KNN_TILE(BFV, AR)                                                                        \
-    exact_tile_kernel<BFV, AR><<<tgrid, 256, 0, st>>>(Qs, qn, Q.n, Rs, rn, R.n, ldp, q_self,     \
-                                                      self_mode, kp, split_len, S, small, part)
-    if (bf) {
-        if (ares) KNN_TILE(true, true);
-        else KNN_TILE(true, false);
-    } else {
-        if (ares) KNN_TILE(false, true);
-        else KNN_TILE(false, false);
-    }
-#undef KNN_TILE
-    KNN_HIP(hipGetLastError());
-
     // GEMM error bound (FP32): (d + 3) u (|q| + max|r|)^2 with u = 2^-24;
     // re-rank bound: (d/16 + 8) u relative.
     const float u = 5.9604645e-08f;
@@ -600,28 +638,63 @@ static knn_status exact_impl(const knn_matrix& Q, const knn_matrix& R, bool same
     const float edir = (float)(R.d / 16 + 8) * u;
     const int certify = bf ? 0 : 1;
     int* fb_count = (int*)(small + 1);
-    dim3 mgrid((unsigned)ceil_div(Q.n, 4));
-#define KNN_MR(DT)                                                                              \
-    merge_rerank_kernel<DT><<<mgrid, 256, 0, st>>>(part, S, Q.n, kp, k, Q.data, Q.ld, R.data, \
-                                                   R.ld, R.d, qn, small, err_coef, edir,       \
-                                                   certify, out_kind, out_idx, out_dist,       \
-                                                   fb_rows, fb_count)
-    if (Q.dtype == KNN_F32) KNN_MR(KNN_F32);
-    else if (Q.dtype == KNN_BF16) KNN_MR(KNN_BF16);
-    else KNN_MR(KNN_F16);
-#undef KNN_MR
-    KNN_HIP(hipGetLastError());
-    if (certify) {
-        dim3 fgrid(1024);
-#define KNN_FB(DT)                                                                              \
-    exact_fallback_kernel<DT><<<fgrid, 256, 0, st>>>(fb_rows, fb_count, Q.data, Q.ld, R.data,  \
-                                                     R.ld, R.n, R.d, q_self, self_mode, k,     \
-                                                     out_kind, out_idx, out_dist)
-        if (Q.dtype == KNN_F32) KNN_FB(KNN_F32);
-        else if (Q.dtype == KNN_BF16) KNN_FB(KNN_BF16);
-        else KNN_FB(KNN_F16);
-#undef KNN_FB
+    const size_t qeb = elem_bytes(Q.dtype);
+
+    for (int64_t q0 = 0; q0 < Q.n; q0 += qc) {
+        const int64_t nq = Q.n - q0 < qc ? Q.n - q0 : qc;
+        const void* Qs;
+        const float* qn;
+        if (same) {
+            Qs = (const char*)Rs + (size_t)q0 * ldp * eb;
+            qn = rn + q0;
+        } else {
+            const knn_matrix Qc = {(const char*)Q.data + (size_t)q0 * Q.ld * qeb, nq, Q.d, Q.ld, Q.dtype};
+            if (bf) launch_stage<true>(Qc, Qb, ldp, qnb, nullptr, nullptr, 0, st);
+            else launch_stage<false>(Qc, Qb, ldp, qnb, nullptr, nullptr, 0, st);
+            Qs = Qb;
+            qn = qnb;
+        }
+        const int32_t* qself = self_mode == 2 ? q_self + q0 : nullptr;
+        if (q0 > 0) zero_words_kernel<<<1, 64, 0, st>>>(small + 1, 1);
+        dim3 tgrid((unsigned)ceil_div(nq, kTileRows), (unsigned)S);
+#define KNN_TILE(BFV, AR)                                                                        \
+    exact_tile_kernel<BFV, AR><<<tgrid, 256, 0, st>>>(Qs, qn, nq, Rs, rn, R.n, ldp, qself,       \
+                                                      self_mode, q0, kp, split_len, S, small, part)
+        if (bf) {
+            if (ares) KNN_TILE(true, true);
+            else KNN_TILE(true, false);
+        } else {
+            if (ares) KNN_TILE(false, true);
+            else KNN_TILE(false, false);
+        }
+#undef KNN_TILE
         KNN_HIP(hipGetLastError());
+
+        const void* Qd = (const char*)Q.data + (size_t)q0 * Q.ld * qeb;
+        int32_t* oi = out_idx + q0 * k;
+        float* od = out_dist + q0 * k;
+        dim3 mgrid((unsigned)ceil_div(nq, 4));
+#define KNN_MR(DT)                                                                              \
+    merge_rerank_kernel<DT><<<mgrid, 256, 0, st>>>(part, S, nq, kp, k, Qd, Q.ld, R.data, R.ld,  \
+                                                   R.d, qn, small, err_coef, edir, certify,     \
+                                                   out_kind, oi, od, fb_rows, fb_count)
+        if (Q.dtype == KNN_F32) KNN_MR(KNN_F32);
+        else if (Q.dtype == KNN_BF16) KNN_MR(KNN_BF16);
+        else KNN_MR(KNN_F16);
+#undef KNN_MR
+        KNN_HIP(hipGetLastError());
+        if (certify) {
+            dim3 fgrid(1024);
+#define KNN_FB(DT)                                                                              \
+    exact_fallback_kernel<DT><<<fgrid, 256, 0, st>>>(fb_rows, fb_count, Qd, Q.ld, R.data, R.ld, \
+                                                     R.n, R.d, qself, self_mode, q0, k,         \
+                                                     out_kind, oi, od)
+            if (Q.dtype == KNN_F32) KNN_FB(KNN_F32);
+            else if (Q.dtype == KNN_BF16) KNN_FB(KNN_BF16);
+            else KNN_FB(KNN_F16);
+#undef KNN_FB
+            KNN_HIP(hipGetLastError());
+        }
     }
     KNN_HIP(hipStreamSynchronize(st));
     return KNN_OK;
@@ -638,8 +711,10 @@ extern "C" knn_status knn_exact(knn_matrix X, int32_t k, int32_t precision, int3
         knn_status r = check_matrix(X, "X");
         if (r != KNN_OK) return r;
         if (X.n < 2) return fail(KNN_EINVAL, "X.n must be >= 2");
+        hipStream_t st = (hipStream_t)stream;
+        Workspace ws(st, 0);
         return exact_impl(X, X, true, nullptr, 1, k, precision, rerank_k, out_kind, out_idx,
-                          out_dist, (hipStream_t)stream);
+                          out_dist, st, ws, 0);
     } catch (...) {
         return fail(KNN_EDEVICE, "unexpected exception");
     }
@@ -657,9 +732,34 @@ extern "C" knn_status knn_exact_query(knn_matrix Q, knn_matrix R, const int32_t*
         if (r != KNN_OK) return r;
         if (Q.d != R.d) return fail(KNN_EINVAL, "Q.d != R.d");
         if (Q.dtype != R.dtype) return fail(KNN_EINVAL, "Q.dtype != R.dtype");
+        hipStream_t st = (hipStream_t)stream;
+        Workspace ws(st, 0);
         return exact_impl(Q, R, false, q_self, q_self ? 2 : 0, k, precision, rerank_k, out_kind,
-                          out_idx, out_dist, (hipStream_t)stream);
+                          out_idx, out_dist, st, ws, 0);
     } catch (...) {
         return fail(KNN_EDEVICE, "unexpected exception");
     }
 }
+
+extern "C" knn_status knn_exact_query_limited(knn_matrix Q, knn_matrix R, const int32_t* q_self,
+                                              int32_t k, int32_t precision, int32_t rerank_k,
+                                              int32_t out_kind, int64_t workspace_limit_bytes,
+                                              int32_t* out_idx, float* out_dist, void* stream)
+{
+    try {
+        knn_status r = check_matrix(Q, "Q");
+        if (r != KNN_OK) return r;
+        r = check_matrix(R, "R");
+        if (r != KNN_OK) return r;
+        if (Q.d != R.d) return fail(KNN_EINVAL, "Q.d != R.d");
+        if (Q.dtype != R.dtype) return fail(KNN_EINVAL, "Q.dtype != R.dtype");
+        hipStream_t st = (hipStream_t)stream;
+        Workspace ws(st, 0);
+        return exact_impl(Q, R, false, q_self, q_self ? 2 : 0, k, precision, rerank_k, out_kind,
+                          out_idx, out_dist, st, ws, workspace_limit_bytes);
+    } catch (...) {
+        return fail(KNN_EDEVICE, "unexpected exception");
+    }
+}
+
+

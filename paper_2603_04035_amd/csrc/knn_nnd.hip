@@ -1,37 +1,43 @@
-// NNDescent on gfx950 (Dong, Charikar & Li, WWW 2011; the paper's k-NN
-// section: random k-neighbour init, neighbours-of-neighbours refinement,
-// early termination when the update rate falls below delta = 0.015).
+// NNDescent on gfx950 (Dong, Charikar & Li, WWW 2011), as the paper's
+// section "GPU-Native k-NN via NNDescent" uses it: lists start from random
+// neighbours, are refined through neighbours of neighbours, and the run
+// stops once an iteration's list updates fall below delta * n * K_b with
+// delta = 0.015.
 //
 // State: per point a list of K_b (index, squared distance, new-flag)
-// entries sorted by (distance, index).  One iteration is four kernels with
-// no host round trip except the 8-byte update count:
+// entries sorted by (distance, index).  One iteration is two kernels with
+// no host round trip except a 64-byte counter read:
 //
-//  sample   half-wave per row: up to s = ceil(rho K_b) new entries are picked
-//           by smallest random priority and marked old; the old entries are
-//           listed; both are scattered as reverse edges into R hashed slots of
-//           the target rows with atomicMin on (priority, source) keys, so the
-//           reverse sample does not depend on thread order;
 //  join     one wave per point v: the new list new_f(v) + reverse-new and the
-//           old list old_f(v) + reverse-old are deduplicated, their rows are
-//           gathered into LDS (coalesced 16-lane row reads, d in chunks of
-//           64), the Gram tile new x all is formed with FP32 FMAs (or BF16
-//           MFMA in the precision form), and each member receives at most
-//           `join_cap` of its best partners that beat its current worst
-//           distance, as atomicMin keys into C hashed candidate slots;
-//  merge    one wave per row: the K_b list keys and the C slot keys are
-//           deduplicated by index, bitonic-sorted, the first K_b kept; slot
+//           old list old_f(v) + reverse-old are deduplicated (at most 64
+//           members; old members past that are not joined and are counted),
+//           their rows are gathered (BF16: straight into MFMA operand
+//           registers; FP32: staged in LDS in 32-coordinate chunks), the Gram
+//           tile new x all is formed with BF16 MFMA or FP32 FMAs, and each
+//           member receives at most `join_cap` of its best partners that
+//           beat its current worst distance, as atomicMin keys into C hashed
+//           candidate slots;
+//  merge    half a wave per row: the K_b list keys and the C slot keys are
+//           deduplicated by index and merged, the first K_b kept; slot
 //           entries that enter are flagged new and counted; slots are reset;
+//           the row is then sampled for the next iteration (sample_row: up to
+//           s = ceil(rho K_b) new entries picked by a per-row random order
+//           and marked old, the old entries listed, and both scattered as
+//           reverse edges into R hashed slots of the target rows by
+//           atomicMin on codes that do not depend on thread order);
 //  (host)   stop when updates < delta * n * K_b.
 //
-// finalize re-ranks the K_b entries with FP32 direct differences on the
-// input values and returns the first k.
+// The init kernel builds the first lists (random, given or encoder-seeded)
+// and samples the first iteration the same way.  finalize re-ranks the K_b
+// entries with FP32 direct differences on the input values and returns the
+// first k.
 #include <math.h>
 
 #include "knn_common.hpp"
 
 namespace knn {
 
-knn_status stage_matrix(Workspace& ws, const knn_matrix& X, bool bf16, void** Xs, int* ldp,
+knn_status stage_matrix(ScratchAlloc& ws, const knn_matrix& X, bool bf16, void** Xs, int* ldp,
                         float** norms, unsigned* maxnorm, hipStream_t st, const uint32_t* rowmap,
                         int aux);
 knn_status morton_order(const knn_matrix& X, int D, uint64_t seed, Workspace& ws, uint32_t** perm,
@@ -386,11 +392,12 @@ __device__ inline ListRaw load_lists(int64_t v, bool valid, const JoinCfg& cfg,
 // for the next iteration.  Repeats are dropped (first position wins), an id
 // in both lists stays new, v itself is dropped.  Every lane compares its
 // entries with all 128 through LDS broadcast reads (sh: 128 words).  The
-// surviving ids are written to ids[0..nn) (new) and ids[nn..nn+no) (old).
-// Returns nn, sets L.
+// surviving ids are written to ids[0..nn) (new) and ids[nn..nn+no) (old);
+// members beyond the caps (old ones first: the list is cut at lcap) are not
+// joined and are counted in `dropped`.  Returns nn, sets L.
 __device__ inline int join_lists(int64_t v, const ListRaw& raw, const JoinCfg& cfg,
                                  uint32_t* __restrict__ revnew, uint32_t* __restrict__ revold,
-                                 uint64_t seed, int iter, uint32_t* sh, uint32_t* ids, int& L)
+                                 uint64_t seed, int iter, uint32_t* sh, uint32_t* ids, int& L, int& dropped)
 {
     const int lane = threadIdx.x;
     if (lane >= cfg.s && lane < cfg.s + cfg.R) revnew[v * cfg.R + (lane - cfg.s)] = 0xFFFFFFFFu;
@@ -428,8 +435,10 @@ __device__ inline int join_lists(int64_t v, const ListRaw& raw, const JoinCfg& c
     }
     const uint64_t nm = ballot(nv), om = ballot(ov);
     int nn = popc64(nm), no = popc64(om);
+    const int all = nn + no;
     if (nn > cfg.ncap) nn = cfg.ncap;
     if (nn + no > cfg.lcap) no = cfg.lcap - nn;
+    dropped = all - nn - no;
     const int pn = rank_below(nm), po = rank_below(om);
     if (nv && pn < nn) ids[pn] = nid;
     if (ov && po < no) ids[nn + po] = oid;
@@ -511,11 +520,22 @@ __device__ inline void offers_issue(PendingOffers& po, const uint32_t (&best)[kJ
     }
 }
 
+// A slot read that holds another source's key is a collision: one of the
+// two candidates is lost (counted from the pre-check read, so collisions
+// between offers racing for one slot are not seen).
+__device__ inline bool slot_collides(unsigned long long seen, uint64_t key)
+{
+    return seen != kEmptyCand && (uint32_t)seen != (uint32_t)key;
+}
+
+// Returns the offers sent in the low 32 bits and the collisions seen in the
+// high 32.
 __device__ inline unsigned long long offers_resolve(const PendingOffers& po)
 {
     unsigned long long n = 0;
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
+        if (po.p[t] && slot_collides(po.seen[t], po.key[t])) n += 1ull << 32;
         if (po.p[t] && po.seen[t] > (unsigned long long)po.key[t]) {
             atomicMin(po.p[t], (unsigned long long)po.key[t]);
             ++n;
@@ -548,11 +568,12 @@ __device__ inline void offer_issue(PendingOffer& po, uint32_t b, bool ok, float 
 
 __device__ inline unsigned long long offer_resolve(const PendingOffer& po)
 {
+    unsigned long long n = po.p && slot_collides(po.seen, po.key) ? 1ull << 32 : 0ull;
     if (po.p && po.seen > (unsigned long long)po.key) {
         atomicMin(po.p, (unsigned long long)po.key);
-        return 1;
+        ++n;
     }
-    return 0;
+    return n;
 }
 
 // Local join, BF16 form.  One wave per point v; the grid is split into 8
@@ -644,7 +665,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     __shared__ float thr[64];
     __shared__ __attribute__((aligned(16))) uint32_t sh[128];
     const int lane = threadIdx.x, c = lane & 31, h = lane >> 5;
+    // emitted: offers in the low 32 bits, slot collisions in the high 32 (a
+    // lane sends far fewer than 2^32 offers), so one register pair counts both
     unsigned long long emitted = 0, gathered = 0;
+    unsigned dropped = 0;
     const uint64_t salt = (uint64_t)iter ^ seed;
     const int J = cfg.J;
     const int nch = (np + kPC - 1) / kPC;
@@ -658,8 +682,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     int64_t v = lo + (int64_t)(blockIdx.x >> 3);
     ListRaw cur = load_lists(v, v < hi, cfg, newf, revnew, oldf, revold);
     for (; v < hi; v += gsz) {
-        int L = 0;
-        const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cur, cfg, revnew, revold, seed, iter, sh, ids, L));
+        int L = 0, dr = 0;
+        const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cur, cfg, revnew, revold, seed, iter, sh, ids, L, dr));
+        dropped += (unsigned)__builtin_amdgcn_readfirstlane(dr);
         L = __builtin_amdgcn_readfirstlane(L);
         // the next point's lists are in flight while this one is joined
         cur = load_lists(v + gsz, v + gsz < hi, cfg, newf, revnew, oldf, revold);
@@ -739,10 +764,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
         }
     }
     emitted += offers_resolve(po);
-    for (int o = 32; o > 0; o >>= 1) emitted += shfl_u64(emitted, lane ^ o);
+    unsigned long long coll = emitted >> 32;
+    emitted &= 0xFFFFFFFFull;
+    for (int o = 32; o > 0; o >>= 1) {
+        emitted += shfl_u64(emitted, lane ^ o);
+        coll += shfl_u64(coll, lane ^ o);
+    }
     if (lane == 0) {
         atomicAdd(&counters[1], emitted);
         atomicAdd(&counters[2], gathered);
+        atomicAdd(&counters[3], coll);
+        atomicAdd(&counters[4], (unsigned long long)dropped);   // wave-uniform: lane 0 holds the wave's count
     }
 }
 // Local join, FP32 form (VALU).  Lists, traversal and offers as in the BF16
@@ -858,7 +890,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     __shared__ float thr[64];
     __shared__ __attribute__((aligned(16))) uint32_t sh[128];
     const int lane = threadIdx.x;
+    // emitted: offers in the low 32 bits, slot collisions in the high 32 (a
+    // lane sends far fewer than 2^32 offers), so one register pair counts both
     unsigned long long emitted = 0, gathered = 0;
+    unsigned dropped = 0;
     const uint64_t salt = (uint64_t)iter ^ seed;
     const unsigned grp = blockIdx.x & 7u;
     const int64_t gsz = (int64_t)(gridDim.x >> 3);
@@ -869,8 +904,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     int64_t v = lo + (int64_t)(blockIdx.x >> 3);
     ListRaw cur = load_lists(v, v < hi, cfg, newf, revnew, oldf, revold);
     for (; v < hi; v += gsz) {
-        int L = 0;
-        const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cur, cfg, revnew, revold, seed, iter, sh, ids, L));
+        int L = 0, dr = 0;
+        const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cur, cfg, revnew, revold, seed, iter, sh, ids, L, dr));
+        dropped += (unsigned)__builtin_amdgcn_readfirstlane(dr);
         L = __builtin_amdgcn_readfirstlane(L);
         cur = load_lists(v + gsz, v + gsz < hi, cfg, newf, revnew, oldf, revold);
         __syncthreads();
@@ -908,10 +944,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
 #undef KNN_JF
     }
     emitted += offer_resolve(po);
-    for (int o = 32; o > 0; o >>= 1) emitted += shfl_u64(emitted, lane ^ o);
+    unsigned long long coll = emitted >> 32;
+    emitted &= 0xFFFFFFFFull;
+    for (int o = 32; o > 0; o >>= 1) {
+        emitted += shfl_u64(emitted, lane ^ o);
+        coll += shfl_u64(coll, lane ^ o);
+    }
     if (lane == 0) {
         atomicAdd(&counters[1], emitted);
         atomicAdd(&counters[2], gathered);
+        atomicAdd(&counters[3], coll);
+        atomicAdd(&counters[4], (unsigned long long)dropped);   // wave-uniform: lane 0 holds the wave's count
     }
 }
 
@@ -1245,7 +1288,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     if ((r = ws.alloc(&revnew, (size_t)n * cfg.R)) != KNN_OK) return r;
     if ((r = ws.alloc(&revold, (size_t)n * cfg.R)) != KNN_OK) return r;
     if ((r = ws.alloc(&cand, (size_t)n * cfg.C)) != KNN_OK) return r;
-    if ((r = ws.alloc(&counters, 4)) != KNN_OK) return r;
+    if ((r = ws.alloc(&counters, 8)) != KNN_OK) return r;
     KNN_HIP(hipMemsetAsync(revnew, 0xFF, (size_t)n * cfg.R * 4, st));
     KNN_HIP(hipMemsetAsync(revold, 0xFF, (size_t)n * cfg.R * 4, st));
 
@@ -1315,7 +1358,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     Timer tj, tm;
     for (int it = 0; it < p->max_iters; ++it) {
         const int iter = iter_offset + it;
-        KNN_HIP(hipMemsetAsync(counters, 0, 32, st));
+        KNN_HIP(hipMemsetAsync(counters, 0, 64, st));
         // iteration `iter` was sampled by the init kernel or the previous merge
         (void)hipEventRecord(tj.a, st);
         if (bf)
@@ -1340,7 +1383,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
                                                                         counters, worst, wstride, sa);
         KNN_HIP(hipGetLastError());
         (void)hipEventRecord(tm.b, st);
-        KNN_HIP(hipMemcpyAsync(host_cnt, counters, 32, hipMemcpyDeviceToHost, st));
+        KNN_HIP(hipMemcpyAsync(host_cnt, counters, 64, hipMemcpyDeviceToHost, st));
         KNN_HIP(hipStreamSynchronize(st));
         float ms = 0;
         (void)hipEventElapsedTime(&ms, tj.a, tj.b);
@@ -1352,6 +1395,8 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         if (stats && it < KNN_MAX_ITERS_LOGGED) {
             stats->updates[it] = (int64_t)host_cnt[0];
             stats->emitted[it] = (int64_t)host_cnt[1];
+            stats->slot_collisions[it] = (int64_t)host_cnt[3];
+            stats->list_dropped[it] = (int64_t)host_cnt[4];
         }
         ++iters;
         if ((double)host_cnt[0] < stop) {
@@ -1381,7 +1426,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         stats->iters = iters;
         stats->build_k = K;
         for (int i = iters; i < KNN_MAX_ITERS_LOGGED; ++i) {
-            stats->updates[i] = stats->emitted[i] = 0;
+            stats->updates[i] = stats->emitted[i] = stats->slot_collisions[i] = stats->list_dropped[i] = 0;
             stats->ms_join_iter[i] = 0.0f;
         }
         const int rb = bf ? 2 : 4;

@@ -68,17 +68,51 @@ class Encoder:
                                            _lib._PREC[precision], C.byref(loss), g.data_ptr(), _stream()))
         return loss.value, g
 
-    def train(self, X: torch.Tensor, knn_idx: torch.Tensor, steps: int = 2000, batch: int = 4096,
-              lr: float = 1e-3, margin: float = 1.0, seed: int = 0, precision: str = "fp32") -> np.ndarray:
+    @staticmethod
+    def _train_params(steps, batch, lr, margin, seed, precision):
         t = _lib.knn_train_params()
-        self._lib.knn_train_default_params(C.byref(t))
+        load().knn_train_default_params(C.byref(t))
         t.steps, t.batch, t.lr, t.margin, t.seed = steps, batch, lr, margin, seed
         t.precision = _lib._PREC[precision]
+        return t
+
+    def adam_state(self):
+        """(first moments, second moments, steps taken) as flat float32 arrays."""
+        m = np.empty(self.n_params, np.float32)
+        v = np.empty(self.n_params, np.float32)
+        t = C.c_int32()
+        _check(self._lib.knn_encoder_get_adam(self.handle, m.ctypes.data, v.ctypes.data, C.byref(t)))
+        return m, v, t.value
+
+    def step(self, X: torch.Tensor, rows: torch.Tensor, B: int, lr: float = 1e-3, margin: float = 1.0,
+             precision: str = "fp32") -> float:
+        """One Adam step on the given triplet rows (3B); returns the batch loss."""
+        rows = rows.to(device=X.device, dtype=torch.int32).contiguous()
+        if rows.numel() != 3 * B:
+            raise ValueError("rows must hold 3B entries")
+        t = self._train_params(1, B, lr, margin, 0, precision)
+        loss = C.c_float()
+        _check(self._lib.knn_encoder_step(self.handle, matrix(X), rows.data_ptr(), B, C.byref(t),
+                                          C.byref(loss), _stream()))
+        return loss.value
+
+    def train(self, X: torch.Tensor, knn_idx: torch.Tensor, steps: int = 2000, batch: int = 4096,
+              lr: float = 1e-3, margin: float = 1.0, seed: int = 0, precision: str = "fp32") -> np.ndarray:
+        t = self._train_params(steps, batch, lr, margin, seed, precision)
         knn_idx = knn_idx.to(torch.int32).contiguous()
         log = np.zeros(max(steps, 1), np.float32)
         _check(self._lib.knn_encoder_train(self.handle, matrix(X), knn_idx.data_ptr(), knn_idx.shape[1],
                                            C.byref(t), log.ctypes.data, _stream()))
         return log[:steps]
+
+
+def triplets(knn_idx: torch.Tensor, B: int, seed: int, step: int) -> torch.Tensor:
+    """The 3B triplet rows that training step `step` draws from the graph knn_idx."""
+    knn_idx = knn_idx.to(torch.int32).contiguous()
+    rows = torch.empty(3 * B, dtype=torch.int32, device=knn_idx.device)
+    _check(load().knn_encoder_triplets(knn_idx.shape[0], knn_idx.data_ptr(), knn_idx.shape[1], B, seed, step,
+                                       rows.data_ptr(), _stream()))
+    return rows
 
 
 def knn_proj_seed(X: torch.Tensor, Z: torch.Tensor, dirs: torch.Tensor, w: int, K: int, D: int = 1):

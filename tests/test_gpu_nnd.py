@@ -245,3 +245,17 @@ def test_wide_rows(orc):
         # isotropic clusters in 1100 dimensions are hard for NNDescent; the
         # bar only guards against a broken path
         assert r >= 0.8, (prec, r)
+
+
+def test_stats_collisions_and_list_cap(orc):
+    """The per-iteration counters: join lists whose caps cannot bind
+    (s + R + K + R <= 64) drop nothing; lists that can exceed 64 members
+    (K = 32, rho = 1) report the members they cut; collisions are counted."""
+    import paper_2603_04035_amd as knn
+    X = torch.from_numpy(datagen.gmm_isotropic(n=5000, d=50, seed=0)).cuda()
+    _, _, st = knn.nndescent_build(X, 15, build_k=15, sample_rate=0.5, max_iters=8, delta=0.0)
+    assert st["list_dropped"] == [0] * st["iters"]
+    assert all(c >= 0 for c in st["slot_collisions"]) and sum(st["slot_collisions"]) > 0
+    _, _, st = knn.nndescent_build(X, 15, build_k=32, sample_rate=1.0, max_iters=6, delta=0.0)
+    print("K=32 rho=1 dropped per iteration", st["list_dropped"], "collisions", st["slot_collisions"])
+    assert sum(st["list_dropped"]) > 0

@@ -16,7 +16,8 @@
  *    is carved from a per-device arena that the library owns and keeps
  *    between calls: it grows when a call needs more and is never returned
  *    before the process ends, and calls on one device take turns on it.
- *    knn_encoder objects are library-owned until destroyed.
+ *    knn_exact_noalloc takes its scratch from a fixed static device array
+ *    instead.  knn_encoder objects are library-owned until destroyed.
  *  - `stream` is a hipStream_t (NULL = the null stream).  Every call is
  *    blocking: the stream is synchronised before return.
  *  - Errors are returned as knn_status (never thrown).  On error the outputs
@@ -119,6 +120,28 @@ knn_status knn_exact_query_limited(knn_matrix Q, knn_matrix R, const int32_t* q_
                                    int32_t precision, int32_t rerank_k, int32_t out_kind,
                                    int64_t workspace_limit_bytes, int32_t* out_idx, float* out_dist,
                                    void* stream);
+
+/* Size of the static device array knn_exact_noalloc works in (64 MiB). */
+#define KNN_NOALLOC_SCRATCH_BYTES (64ll << 20)
+
+/*
+ * knn_exact for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same results as knn_exact, with every scratch buffer carved from a
+ * file-scope static device array of KNN_NOALLOC_SCRATCH_BYTES that each
+ * device holds from the library's first use on it until the process ends.
+ * The call makes no hipMalloc, hipFree or other allocation; queries are
+ * chunked to fit the array.  The caller passes inputs and outputs as for
+ * knn_exact.  Limit: the staged copy of X (n * roundup(d, 32) * 4 bytes in
+ * FP32, n * roundup(d, 64) * 2 in BF16) plus n * 4 bytes of norms and one
+ * 128-query chunk (about 140 KB) must fit, e.g. n <= 240,000 at d = 50 FP32;
+ * larger inputs get KNN_ENOMEM with the sizes in the message.  Every call on
+ * a device shares that device's array and leaves it holding its last
+ * contents: calls that overlap on one device (other threads or streams)
+ * race and must be serialised by the caller.  Other errors as knn_exact.
+ */
+knn_status knn_exact_noalloc(knn_matrix X, int32_t k, int32_t precision, int32_t rerank_k,
+                             int32_t out_kind, int32_t* out_idx, float* out_dist, void* stream);
 
 typedef struct knn_encoder knn_encoder;
 

@@ -86,8 +86,9 @@ EXPORTS = [
     "knn_encoder_get_weights", "knn_encoder_embed", "knn_encoder_grads",
     "knn_train_default_params", "knn_encoder_train", "knn_proj_seed",
     "knn_encoder_triplets", "knn_encoder_step", "knn_encoder_get_adam",
-    "knn_exact_query_limited", "knn_fuzzy_graph",
+    "knn_exact_query_limited", "knn_exact_noalloc", "knn_fuzzy_graph",
 ]
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _lib = None
 
@@ -111,6 +112,8 @@ def load() -> C.CDLL:
     lib.knn_exact_query.argtypes = [knn_matrix, knn_matrix, vp, i32, i32, i32, i32, vp, vp, vp]
     lib.knn_exact_query_limited.restype = i32
     lib.knn_exact_query_limited.argtypes = [knn_matrix, knn_matrix, vp, i32, i32, i32, i32, i64, vp, vp, vp]
+    lib.knn_exact_noalloc.restype = i32
+    lib.knn_exact_noalloc.argtypes = [knn_matrix, i32, i32, i32, i32, vp, vp, vp]
     lib.knn_fuzzy_graph.restype = i32
     lib.knn_fuzzy_graph.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, vp, vp, C.POINTER(C.c_int64), vp]
     lib.knn_nnd_default_params.restype = None
@@ -192,6 +195,22 @@ def knn_exact(X: torch.Tensor, k: int, precision: str = "fp32", rerank_k: int = 
     dist = torch.empty((n, k), dtype=torch.float32, device=X.device)
     _check(lib.knn_exact(matrix(X), k, _PREC[precision], rerank_k, _OUT[out],
                          idx.data_ptr(), dist.data_ptr(), _stream()))
+    return idx, dist
+
+
+def knn_exact_noalloc(X: torch.Tensor, k: int, precision: str = "fp32", rerank_k: int = 0,
+                      out: str = "l2", out_idx: torch.Tensor | None = None,
+                      out_dist: torch.Tensor | None = None):
+    """knn_exact working in the library's static device array (no device
+    allocation inside the call); outputs may be passed in preallocated."""
+    lib = load()
+    n = X.shape[0]
+    idx = out_idx if out_idx is not None else torch.empty((n, k), dtype=torch.int32, device=X.device)
+    dist = out_dist if out_dist is not None else torch.empty((n, k), dtype=torch.float32, device=X.device)
+    if idx.shape != (n, k) or dist.shape != (n, k) or not idx.is_contiguous() or not dist.is_contiguous():
+        raise ValueError("outputs must be contiguous n x k")
+    _check(lib.knn_exact_noalloc(matrix(X), k, _PREC[precision], rerank_k, _OUT[out],
+                                 idx.data_ptr(), dist.data_ptr(), _stream()))
     return idx, dist
 
 

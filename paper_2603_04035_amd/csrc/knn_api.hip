@@ -127,6 +127,19 @@ knn_status Workspace::alloc(void** p, size_t bytes)
     return KNN_OK;
 }
 
+knn_status FixedScratch::alloc(void** p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    bytes = (size_t)round_up((int64_t)bytes, 256);
+    if (off_ + bytes > cap_)
+        return fail(KNN_ENOMEM, "static scratch exhausted: need " + std::to_string(off_ + bytes) +
+                                    " bytes, the array holds " + std::to_string(cap_));
+    *p = base_ + off_;
+    off_ += bytes;
+    return KNN_OK;
+}
+
 knn_status check_matrix(const knn_matrix& X, const char* name)
 {
     std::string n(name);

@@ -315,6 +315,21 @@ public:
     knn_status alloc(T** p, size_t count) { return alloc((void**)p, count * sizeof(T)); }
 };
 
+// A fixed device block carved front to back; never allocates.  Requests
+// past its end fail with KNN_ENOMEM.
+class FixedScratch : public ScratchAlloc {
+public:
+    FixedScratch(void* base, size_t cap) : base_((char*)base), cap_(cap) {}
+    using ScratchAlloc::alloc;
+    knn_status alloc(void** p, size_t bytes) override;
+    size_t used() const { return off_; }
+
+private:
+    char* base_;
+    size_t cap_;
+    size_t off_ = 0;
+};
+
 // Scratch for one entry-point call.  Requests are carved (256-byte aligned)
 // from a grow-only arena that the library keeps per device, so steady-state
 // calls neither allocate nor free device memory.  The arena is held by one

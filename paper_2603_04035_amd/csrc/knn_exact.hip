@@ -20,6 +20,7 @@
 //     certified when its k-th re-ranked distance is below the k'-th GEMM
 //     distance minus the worst-case GEMM error bound; other rows are
 //  4. recomputed exhaustively with direct differences.
+#include <mutex>
 
 #include "knn_common.hpp"
 
@@ -700,6 +701,34 @@ static knn_status exact_impl(const knn_matrix& Q, const knn_matrix& R, bool same
     return KNN_OK;
 }
 
+// ------------------------------------------------------------ no-alloc path
+
+// The static scratch array of knn_exact_noalloc: one copy per device, held
+// by the loaded code object until the process ends.  Host code never uses
+// this name as an address (on the host it is a stand-in symbol): the device
+// address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kStaticScratch = (size_t)KNN_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratch];
+
+static knn_status static_scratch(void** out)
+{
+    static std::mutex mu;
+    static void* addr[64] = {};
+    int dev = -1;
+    KNN_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(KNN_EDEVICE, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(KNN_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return KNN_OK;
+}
+
 }  // namespace knn
 
 using namespace knn;
@@ -762,4 +791,19 @@ extern "C" knn_status knn_exact_query_limited(knn_matrix Q, knn_matrix R, const 
     }
 }
 
-
+extern "C" knn_status knn_exact_noalloc(knn_matrix X, int32_t k, int32_t precision, int32_t rerank_k,
+                                        int32_t out_kind, int32_t* out_idx, float* out_dist, void* stream)
+{
+    try {
+        knn_status r = check_matrix(X, "X");
+        if (r != KNN_OK) return r;
+        if (X.n < 2) return fail(KNN_EINVAL, "X.n must be >= 2");
+        void* base = nullptr;
+        if ((r = static_scratch(&base)) != KNN_OK) return r;
+        FixedScratch ws(base, kStaticScratch);
+        return exact_impl(X, X, true, nullptr, 1, k, precision, rerank_k, out_kind, out_idx,
+                          out_dist, (hipStream_t)stream, ws, (int64_t)kStaticScratch);
+    } catch (...) {
+        return fail(KNN_EDEVICE, "unexpected exception");
+    }
+}

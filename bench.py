@@ -20,8 +20,12 @@ library over the timed steps; counter-measured HBM bytes per launch from the
 committed rocprofv3 summary while its kernel source is unchanged), an
 attainable-bandwidth copy measurement, the BF16 form's join distance error
 against FP64, the encoder's training cost (outside the timed region), and
-the CPU oracle's sequential NNDescent on a bounded sample of the workload.
-Other configurations (--config pixel70k | scale10m) print the same line.
+the CPU oracle on a bounded sample of the workload (sequential NNDescent at
+the FP32 form's settings with its recall, and the exact oracle's per-query
+rate on all host cores), the fuzzy graph (UMAP weights) built from the
+headline graph, and the exact path (knn_exact, both precisions) on the
+70,000 x 784 pixel-like set.  Other configurations (--config pixel70k |
+scale10m) print the same line.
 """
 from __future__ import annotations
 
@@ -37,6 +41,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 157.3   # 256 CUs x 4 SIMDs x 2.4 GHz x 64 FP32 flops (packed dual issue)
 
 # NNDescent settings of the two forms (K_b, rho, caps); delta is the paper's 0.015.
 # The BF16 forms keep K_b = 2k = 30 entries, the FP32 re-rank's width; the
@@ -110,19 +115,56 @@ def recall_gpu(X, G, D, rows, k):
     return float(hits.sum().item() / (len(rows) * k))
 
 
-def cpu_baseline(Xnp, k, form, sample_n):
-    """The CPU oracle's sequential NNDescent on the first sample_n rows."""
+def host_cpu():
+    """Host cores visible to this process and the CPU model."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"os_cpu_count": os.cpu_count(), "omp_threads": int(os.environ.get("OMP_NUM_THREADS", "0")) or None,
+            "model": model}
+
+
+def cpu_baseline(Xnp, k, form, sample_n, exact_queries=1000):
+    """The CPU oracle on a bounded sample of the workload.
+
+    * Sequential NNDescent (one core) at the timed FP32 form's settings
+      (K_b, rho, delta, iteration cap) on the first sample_n rows, with its
+      recall@k on 500 of those rows against the oracle's exact lists of the
+      same subset.  NNDescent's cost grows faster than n, so the rate on the
+      subset overstates the full workload's.
+    * The exact oracle (FP64 brute force, OpenMP over all host cores) on
+      exact_queries rows of the full workload: queries/s.
+    """
+    import numpy as np
     import oracle
-    sub = Xnp[:sample_n]
-    p = dict(FORMS[form], build_k=20, sample_rate=0.5)
+    from paper_2603_04035_amd import datagen
+    sub = np.ascontiguousarray(Xnp[:sample_n])
+    p = FORMS[form]
     t0 = time.perf_counter()
-    oracle.nndescent(sub, p["build_k"], max_iters=p["max_iters"], rho=p["sample_rate"],
-                     delta=p["delta"], seed=0)
+    idx, _, iters, _ = oracle.nndescent(sub, p["build_k"], max_iters=p["max_iters"], rho=p["sample_rate"],
+                                        delta=p["delta"], seed=0)
     dt = time.perf_counter() - t0
-    return {"value": sample_n / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
-            "sample": f"sequential NNDescent (K={p['build_k']}, rho={p['sample_rate']}, "
-                      f"delta={p['delta']}) on the first {sample_n} rows of the same workload, "
-                      f"{dt:.1f} s"}
+    rows = datagen.sample_queries(sample_n, 500, seed=2)
+    _, O2 = oracle.exact_knn(sub, k, rows=rows)
+    rec = oracle.recall_at_k(sub, rows, idx[rows, :k], np.sqrt(O2[:, -1]), k)
+    q = datagen.sample_queries(Xnp.shape[0], exact_queries, seed=3)
+    t1 = time.perf_counter()
+    oracle.exact_query(Xnp, Xnp[q], k, q_self=q)
+    de = time.perf_counter() - t1
+    return {"value": round(sample_n / dt, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"sequential NNDescent (K_b={p['build_k']}, rho={p['sample_rate']}, delta={p['delta']}, "
+                      f"the FP32 form's settings) on the first {sample_n} of the {Xnp.shape[0]} rows, "
+                      f"{dt:.1f} s, {iters} iterations; rate on the subset overstates the full workload's",
+            "recall_at_15": round(float(rec), 5), "host": host_cpu(),
+            "exact_oracle": {"queries": exact_queries, "s": round(de, 2),
+                             "queries_per_s": round(exact_queries / de, 1), "cores": host_cpu()["omp_threads"]
+                             or os.cpu_count(),
+                             "note": "FP64 brute force over all rows, OpenMP across queries"}}
 
 
 def measured_traffic(kernel, workload):
@@ -170,7 +212,11 @@ def copy_bandwidth(mib: int = 1024, reps: int = 5):
 
 
 def join_roofline(stats, n, d, p, kernel, workload):
-    """Local-join roofline: algorithmic bytes per launch / HIP-event time per launch."""
+    """Local-join roofline.  BF16 form (Gram on MFMA, gathers bound): algorithmic
+    bytes per launch / HIP-event time per launch against the HBM peak.  FP32
+    form (Gram on VALU): its SIMDs are VALU-busy, so the roof is the FP32
+    vector peak and the rate is the Gram's algorithmic flops (2 d per joined
+    pair) per launch time; the byte rate is kept beside it."""
     import numpy as np
     K = stats[-1]["build_k"]
     s_ = int(np.ceil(p["sample_rate"] * K))
@@ -183,11 +229,18 @@ def join_roofline(stats, n, d, p, kernel, workload):
     join_ms = sum(st["ms_join"] for st in stats)
     achieved = alg_bytes / (join_ms * 1e-3) / 1e9
     traffic, source = measured_traffic(kernel, workload)
+    pairs = sum(st["pairs_joined"] for st in stats)
+    gram_tflops = 2.0 * d * pairs / (join_ms * 1e-3) / 1e12
+    common = {"traffic": traffic, "traffic_source": source, "kernel": kernel, "launches": launches,
+              "alg_bytes_per_launch": int(alg_bytes / max(launches, 1)),
+              "alg_flops_per_launch": int(2 * d * pairs / max(launches, 1)),
+              "ms_per_launch": round(join_ms / max(launches, 1), 4)}
+    if p["precision"] == "fp32":
+        return {"bound": "alu", "achieved": round(gram_tflops, 2), "peak": FP32_VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(gram_tflops / FP32_VALU_PEAK_TFLOPS, 4),
+                "hbm_achieved_gbs": round(achieved, 1), "hbm_frac": round(achieved / HBM_PEAK_GBS, 4), **common}
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": source,
-            "kernel": kernel,
-            "launches": launches, "alg_bytes_per_launch": int(alg_bytes / max(launches, 1)),
-            "ms_per_launch": round(join_ms / max(launches, 1), 4)}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "gram_tflops": round(gram_tflops, 2), **common}
 
 
 def distance_error(X, Xnp, k, p, rows):
@@ -226,9 +279,27 @@ def exact_path(X, k, reps=3):
         torch.cuda.synchronize()
         ms = 1000.0 * (time.perf_counter() - t0) / reps
         tflops = 2.0 * n * n * d / (ms * 1e-3) / 1e12
-        out[prec] = {"ms": round(ms, 3), "tflops": round(tflops, 2), "peak": peak,
-                     "frac": round(tflops / peak, 4)}
+        out[prec] = {"ms": round(ms, 3), "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": peak,
+                                                      "unit": "TFLOP/s", "frac": round(tflops / peak, 4),
+                                                      "traffic": None,
+                                                      "note": "2 n^2 d flops / whole knn_exact call"}}
     return out
+
+
+def fuzzy_measure(G, D, reps=3):
+    """knn_fuzzy_graph on the built graph: ms per call and points/s."""
+    import torch
+    import paper_2603_04035_amd as knn
+    knn.fuzzy_graph(G, D)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = knn.fuzzy_graph(G, D)
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / reps
+    n, k = G.shape
+    return {"ms": round(ms, 3), "points_per_s": round(n / (ms * 1e-3), 1), "nnz": int(out[4].numel()),
+            "edges_in": int(n * k)}
 
 
 def progress(msg):
@@ -278,7 +349,8 @@ def run_form(X, k, form, steps, warmup, rows, config, encoder=None, Xnp=None):
                              ("ms_init", "ms_sample", "ms_join", "ms_merge", "ms_final", "ms_total")},
             "per_iter": {"updates": last["updates"], "offers": last["emitted"],
                          "ms_join": [round(x, 3) for x in last["ms_join_iter"]]},
-            "roofline": join_roofline(stats, n, d, p, kern, config)}
+            "roofline": join_roofline(stats, n, d, p, kern, config),
+            "_graph": (G, D)}
 
 
 def main():
@@ -291,10 +363,13 @@ def main():
                     help="both: fp32 and bf16-learned; all: also the bf16-random and bf16-untrained controls")
     ap.add_argument("--k", type=int, default=15)
     ap.add_argument("--recall-rows", type=int, default=10000)
-    ap.add_argument("--cpu-sample", type=int, default=100_000)
+    ap.add_argument("--cpu-sample", type=int, default=50_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-exact", action="store_true", help="skip the exact-path timing of the default line")
     ap.add_argument("--exact", action="store_true",
                     help="only time the exact path (knn_exact of the workload, both precisions)")
+    ap.add_argument("--fuzzy-only", action="store_true",
+                    help="only build the FP32-form graph once and run the fuzzy graph on it 3 times (profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (counter calibration)")
     args = ap.parse_args()
@@ -328,6 +403,12 @@ def main():
         print(json.dumps({"exact_path": exact_path(X, k), "config": {"workload": CONFIGS[args.config]["desc"]},
                           "n": n, "d": d, "k": k}), flush=True)
         return
+    if args.fuzzy_only:
+        import paper_2603_04035_amd as knn
+        G, D, _ = knn.nndescent_build(X, k, seed=0, **FORMS["fp32"])
+        print(json.dumps({"fuzzy_graph": fuzzy_measure(G, D),
+                          "config": {"workload": CONFIGS[args.config]["desc"]}}), flush=True)
+        return
     rows = datagen.sample_queries(n, args.recall_rows, seed=2)
     forms = {"both": ["fp32", "bf16-learned"], "all": ["fp32", "bf16-learned", "bf16-random", "bf16-untrained"]}.get(
         args.form, [args.form])
@@ -340,10 +421,23 @@ def main():
         results[f] = run_form(X, k, f, args.steps, args.warmup, rows, args.config, encoder, Xnp)
     head = "bf16-learned" if "bf16-learned" in results else forms[0]
     h = results[head]
+    G, D = h["_graph"]
+    fuzzy = fuzzy_measure(G, D)
+    progress(f"fuzzy graph {fuzzy['ms']} ms")
+    for r in results.values():
+        r.pop("_graph", None)
+    del G, D
+    exact = None
+    if not args.no_exact and args.config == "gmm1m":
+        Xp = torch.from_numpy(make_data("pixel70k")).to("cuda")
+        exact = {"workload": CONFIGS["pixel70k"]["desc"], **exact_path(Xp, k)}
+        del Xp
+        progress(f"exact path fp32 {exact['fp32']['ms']} ms, bf16 {exact['bf16']['ms']} ms")
 
     copy_gbs = copy_bandwidth()
     for r in results.values():
-        r["roofline"]["frac_of_measured_copy"] = round(r["roofline"]["achieved"] / copy_gbs, 4)
+        rl = r["roofline"]
+        rl["frac_of_measured_copy"] = round(rl.get("hbm_achieved_gbs", rl["achieved"]) / copy_gbs, 4)
     cpu = None
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         cpu = cpu_baseline(Xnp, k, "fp32", min(args.cpu_sample, n))
@@ -362,6 +456,8 @@ def main():
         "cpu_baseline": cpu,
         "forms": results,
         "encoder_training": training,
+        "fuzzy_graph": fuzzy,
+        "exact_path": exact,
     }
     print(json.dumps(out), flush=True)
 

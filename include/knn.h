@@ -189,6 +189,9 @@ typedef struct {
     /* join-list members not joined because the list exceeded 64 members
      * (old members are cut first), per iteration */
     int64_t list_dropped[KNN_MAX_ITERS_LOGGED];
+    /* member pairs whose distance the local joins evaluated (new x new once,
+     * new x old), over all iterations: the Gram work, 2 d flops each */
+    uint64_t pairs_joined;
 } knn_nnd_stats;
 
 /*
@@ -338,6 +341,28 @@ knn_status knn_encoder_get_adam(const knn_encoder* enc, float* m, float* v, int3
 knn_status knn_proj_seed(knn_matrix X, const float* Z, int32_t m, const float* dirs,
                          int32_t P, int32_t D, int32_t w, int32_t K, int32_t* out_idx,
                          float* out_dist, void* stream);
+
+/*
+ * Embedding quality as the paper's section "Embedding Quality" measures it
+ * (Venna & Kaski 2006), from exact ranks in both spaces: X (n x d, the
+ * input) and Y (n x e, an embedding of the same rows).  r(i,j) = rank of j
+ * among the other rows by distance from i in X (1 = nearest), r'(i,j) in Y;
+ * N(i) / L(i) = the k nearest in X / Y.  Ranks break distance ties by the
+ * smaller index and are taken on canonical FP32 direct-difference squared
+ * distances (the order knn_exact returns); the X-space distances come from
+ * an FP32 MFMA Gram with every comparison inside its error bound re-decided
+ * in the canonical precision.
+ *  metrics  host, 3 doubles: k-NN preservation sum_i |N(i) & L(i)| / (n k);
+ *           trustworthiness 1 - 2 / (n k (2n - 3k - 1)) sum_i sum_{j in
+ *           L(i) \ N(i)} (r(i,j) - k); continuity, the same with N, L and r,
+ *           r' swapped.
+ *  hits, trust, cont  device, nullable, n each: the per-row terms
+ *           (|N(i) & L(i)| int32, the two rank sums int64).
+ * Errors: KNN_EINVAL for bad matrices, X.n != Y.n, k < 1 or 3k >= 2n - 1;
+ * KNN_ENOTSUP for k > 16.
+ */
+knn_status knn_quality(knn_matrix X, knn_matrix Y, int32_t k, int32_t* hits, int64_t* trust,
+                       int64_t* cont, double* metrics, void* stream);
 
 /* ----------------------------------------------------------------------
  * The fuzzy graph UMAP-family methods build from the k-NN graph (UMAP of

@@ -90,6 +90,8 @@ def _load():
     lib.oracle_proj_keys.restype = i32
     lib.oracle_fuzzy_rows.argtypes = [_dp, i64, i32, _dp, _dp, _dp]
     lib.oracle_fuzzy_rows.restype = None
+    lib.oracle_quality_rows.argtypes = [_dp, i32, _dp, i32, i64, i32, _ip, i64, i32, _ip, _ip, _ip]
+    lib.oracle_quality_rows.restype = i32
     _lib = lib
     return lib
 
@@ -353,3 +355,27 @@ def fuzzy_union(idx, w, rows=None):
         cols = sorted(set(a) | set(b))
         out.append([(j, a.get(j, 0.0) + b.get(j, 0.0) - a.get(j, 0.0) * b.get(j, 0.0)) for j in cols])
     return out
+
+
+def quality_rows(X, Y, k: int, rows=None, canonical: bool = False):
+    """Per-row terms (hits, trust, cont) of k-NN preservation,
+    trustworthiness and continuity for the requested rows (default all);
+    canonical=True ranks by the canonical FP32 distance instead of FP64."""
+    X, Y = _f64(X), _f64(Y)
+    n = X.shape[0]
+    rows = np.arange(n, dtype=np.int64) if rows is None else np.ascontiguousarray(np.asarray(rows, np.int64))
+    h, t, c = (np.empty(len(rows), np.int64) for _ in range(3))
+    if _load().oracle_quality_rows(X, X.shape[1], Y, Y.shape[1], n, k, rows, len(rows), int(canonical),
+                                   h, t, c) != 0:
+        raise ValueError("oracle_quality_rows: bad arguments")
+    return h, t, c
+
+
+def quality(X, Y, k: int, canonical: bool = False):
+    """(k-NN preservation, trustworthiness, continuity) over all rows:
+    P = sum hits / (n k); T = 1 - 2 / (n k (2n - 3k - 1)) sum trust;
+    C likewise with cont."""
+    n = np.asarray(X).shape[0]
+    h, t, c = quality_rows(X, Y, k, canonical=canonical)
+    z = 2.0 / (n * k * (2.0 * n - 3.0 * k - 1.0))
+    return float(h.sum()) / (n * k), 1.0 - z * float(t.sum()), 1.0 - z * float(c.sum())

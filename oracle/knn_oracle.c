@@ -774,3 +774,112 @@ void oracle_fuzzy_rows(const double* dist, int64_t n, int k, double* rho, double
     }
     free(x);
 }
+
+/* -------------------------------------------- embedding-quality metrics */
+
+/*
+ * Canonical FP32 squared distance of two rows given as doubles holding FP32
+ * values: coordinate t goes to partial sum t mod 16 (fused multiply-add of
+ * the FP32 difference, in coordinate order), then the 16 partial sums are
+ * added pairwise at strides 8, 4, 2, 1.  This is the precision in which the
+ * GPU path ranks points (its exact k-NN re-rank and its rank counts), so
+ * rank decisions compared bit for bit are taken in it on both sides.
+ */
+static double sqdist_f32c(const double* a, const double* b, int d)
+{
+    float s[16];
+    for (int g = 0; g < 16; ++g) s[g] = 0.0f;
+    for (int t = 0; t < d; ++t) {
+        float e = (float)a[t] - (float)b[t];
+        s[t & 15] = fmaf(e, e, s[t & 15]);
+    }
+    for (int j = 8; j > 0; j >>= 1) {
+        float u[16];
+        for (int g = 0; g < 16; ++g) u[g] = s[g] + s[g ^ j];
+        for (int g = 0; g < 16; ++g) s[g] = u[g];
+    }
+    return (double)s[0];
+}
+
+typedef struct {
+    double d;
+    int64_t j;
+} dj_t;
+
+static int dj_cmp(const void* x, const void* y)
+{
+    const dj_t* a = (const dj_t*)x;
+    const dj_t* b = (const dj_t*)y;
+    if (a->d != b->d) return a->d < b->d ? -1 : 1;
+    return (a->j > b->j) - (a->j < b->j);
+}
+
+/* rank[j] (1 = nearest) of every j != i by (distance, index) from row i of
+ * A (n x w); rank[i] = 0.  scratch holds n entries. */
+static void ranks_from(const double* A, int64_t n, int w, int64_t i, int canonical, dj_t* scratch,
+                       int64_t* rank)
+{
+    int64_t m = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        scratch[m].d = canonical ? sqdist_f32c(A + i * w, A + j * w, w) : sqdist(A + i * w, A + j * w, w);
+        scratch[m].j = j;
+        ++m;
+    }
+    qsort(scratch, (size_t)m, sizeof(dj_t), dj_cmp);
+    rank[i] = 0;
+    for (int64_t r = 0; r < m; ++r) rank[scratch[r].j] = r + 1;
+}
+
+/*
+ * Per-row terms of k-NN preservation, trustworthiness and continuity
+ * (Venna & Kaski 2006; the paper's section "Embedding Quality") for the
+ * rows listed in `rows`: with r(i,j) the rank of j from i among all other
+ * points by high-dimensional distance (rows of X, n x d) and r'(i,j) by
+ * embedding distance (rows of Y, n x e), N(i) = {j : r(i,j) <= k} and
+ * L(i) = {j : r'(i,j) <= k}:
+ *   hits[q]  = |N(i) intersect L(i)|,
+ *   trust[q] = sum over j in L(i) \ N(i) of (r(i,j) - k),
+ *   cont[q]  = sum over j in N(i) \ L(i) of (r'(i,j) - k).
+ * Ranks break distance ties by the smaller index.  canonical = 0 ranks by
+ * FP64 direct differences, 1 by the canonical FP32 distance above.
+ */
+int oracle_quality_rows(const double* X, int d, const double* Y, int e, int64_t n, int k,
+                        const int64_t* rows, int64_t nrows, int canonical,
+                        int64_t* hits, int64_t* trust, int64_t* cont)
+{
+    if (k < 1 || k >= n || d < 1 || e < 1) return -1;
+    int bad = 0;
+#pragma omp parallel
+    {
+        dj_t* scratch = (dj_t*)malloc(sizeof(dj_t) * (size_t)n);
+        int64_t* rx = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+        int64_t* ry = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+        if (!scratch || !rx || !ry) {
+#pragma omp atomic write
+            bad = 1;
+        } else {
+#pragma omp for schedule(dynamic, 4)
+            for (int64_t q = 0; q < nrows; ++q) {
+                const int64_t i = rows[q];
+                ranks_from(X, n, d, i, canonical, scratch, rx);
+                ranks_from(Y, n, e, i, canonical, scratch, ry);
+                int64_t h = 0, t = 0, c = 0;
+                for (int64_t j = 0; j < n; ++j) {
+                    if (j == i) continue;
+                    const int inN = rx[j] <= k, inL = ry[j] <= k;
+                    if (inN && inL) ++h;
+                    if (inL && !inN) t += rx[j] - k;
+                    if (inN && !inL) c += ry[j] - k;
+                }
+                hits[q] = h;
+                trust[q] = t;
+                cont[q] = c;
+            }
+        }
+        free(scratch);
+        free(rx);
+        free(ry);
+    }
+    return bad ? -1 : 0;
+}

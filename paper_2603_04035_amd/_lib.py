@@ -58,7 +58,8 @@ class knn_nnd_stats(C.Structure):
                 ("ms_join", C.c_double), ("ms_merge", C.c_double), ("ms_final", C.c_double),
                 ("ms_join_iter", C.c_float * MAX_ITERS_LOGGED),
                 ("slot_collisions", C.c_int64 * MAX_ITERS_LOGGED),
-                ("list_dropped", C.c_int64 * MAX_ITERS_LOGGED)]
+                ("list_dropped", C.c_int64 * MAX_ITERS_LOGGED),
+                ("pairs_joined", C.c_uint64)]
 
     def as_dict(self) -> dict:
         it = self.iters
@@ -70,7 +71,8 @@ class knn_nnd_stats(C.Structure):
                 "ms_join": self.ms_join, "ms_merge": self.ms_merge, "ms_final": self.ms_final,
                 "ms_join_iter": [round(x, 4) for x in self.ms_join_iter[:min(it, MAX_ITERS_LOGGED)]],
                 "slot_collisions": list(self.slot_collisions[:min(it, MAX_ITERS_LOGGED)]),
-                "list_dropped": list(self.list_dropped[:min(it, MAX_ITERS_LOGGED)])}
+                "list_dropped": list(self.list_dropped[:min(it, MAX_ITERS_LOGGED)]),
+                "pairs_joined": int(self.pairs_joined)}
 
 
 class knn_train_params(C.Structure):
@@ -86,7 +88,7 @@ EXPORTS = [
     "knn_encoder_get_weights", "knn_encoder_embed", "knn_encoder_grads",
     "knn_train_default_params", "knn_encoder_train", "knn_proj_seed",
     "knn_encoder_triplets", "knn_encoder_step", "knn_encoder_get_adam",
-    "knn_exact_query_limited", "knn_exact_noalloc", "knn_fuzzy_graph",
+    "knn_exact_query_limited", "knn_exact_noalloc", "knn_fuzzy_graph", "knn_quality",
 ]
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -114,6 +116,8 @@ def load() -> C.CDLL:
     lib.knn_exact_query_limited.argtypes = [knn_matrix, knn_matrix, vp, i32, i32, i32, i32, i64, vp, vp, vp]
     lib.knn_exact_noalloc.restype = i32
     lib.knn_exact_noalloc.argtypes = [knn_matrix, i32, i32, i32, i32, vp, vp, vp]
+    lib.knn_quality.restype = i32
+    lib.knn_quality.argtypes = [knn_matrix, knn_matrix, i32, vp, vp, vp, C.POINTER(C.c_double), vp]
     lib.knn_fuzzy_graph.restype = i32
     lib.knn_fuzzy_graph.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, vp, vp, C.POINTER(C.c_int64), vp]
     lib.knn_nnd_default_params.restype = None
@@ -332,3 +336,19 @@ def fuzzy_graph(idx: torch.Tensor, dist: torch.Tensor):
                                w.data_ptr(), row_ptr.data_ptr(), col.data_ptr(), val.data_ptr(),
                                C.byref(nnz), _stream()))
     return rho, sigma, w, row_ptr, col[:nnz.value], val[:nnz.value]
+
+
+def quality(X: torch.Tensor, Y: torch.Tensor, k: int = 10, per_row: bool = False):
+    """(k-NN preservation, trustworthiness, continuity) of embedding Y of X;
+    with per_row also the per-row terms (hits, trust, cont) as tensors."""
+    lib = load()
+    n = X.shape[0]
+    m = (C.c_double * 3)()
+    h = t = c = None
+    if per_row:
+        h = torch.empty(n, dtype=torch.int32, device=X.device)
+        t = torch.empty(n, dtype=torch.int64, device=X.device)
+        c = torch.empty(n, dtype=torch.int64, device=X.device)
+    _check(lib.knn_quality(matrix(X), matrix(Y), k, _ptr(h), _ptr(t), _ptr(c), m, _stream()))
+    out = (m[0], m[1], m[2])
+    return (out, (h, t, c)) if per_row else out

@@ -193,6 +193,90 @@ __device__ inline void load_step(const E* Qe, const E* Re, int64_t qrow, int64_t
     if (k0 == 0 && tid < kTileRows && rt + tid < rend) rnv = rn[rt + tid];
 }
 
+// All K chunks of reference tile rt (rows rt .. rt + 127, clamped to rend)
+// against the workgroup's 128 query rows: wave w's four 32x32 accumulators
+// (query rows 32w + .., reference columns 32b + ..) are returned in acc.
+// Each step stores the registers loaded by the previous one into LDS and
+// issues the loads of the next step (the next tile's first chunk after the
+// last chunk), so the loads of a step overlap the MFMAs of the one before.
+// With ARES the query rows are already in As (row stride AROW).
+template <bool BF, bool ARES>
+__device__ __attribute__((always_inline)) inline void tile_gemm(
+    uint4& nb0, uint4& nb1, uint4& nb2, uint4& nb3, uint4& na0, uint4& na1, uint4& na2, uint4& na3, float& nrn,
+    f32x16 (&acc)[4], typename TileCfg<BF>::E* As, typename TileCfg<BF>::E* Bs, float* srn,
+    const typename TileCfg<BF>::E* Qe, const typename TileCfg<BF>::E* Re, int64_t qrow, int64_t rt,
+    int64_t rend, int ldp, const float* rn, int tid, int w, int h, int c)
+{
+    using C = TileCfg<BF>;
+    using E = typename C::E;
+    constexpr int KC = C::KC, LROW = C::LROW, PER = KC / 2;
+    constexpr int AROW = ARES ? C::AROW : LROW;
+    constexpr int NV = PER * (int)sizeof(E) / 16;   // 16-byte loads per thread and chunk
+    static_assert(NV == 4, "four 16-byte pieces per thread and chunk");
+    const int r = tid >> 1, ph = tid & 1;              // staging: row r, half ph of the chunk
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[b][v] = 0.0f;
+
+    for (int k0 = 0; k0 < ldp; k0 += KC) {
+        __syncthreads();   // the previous step's LDS reads are done
+        {
+            uint4* bdst = (uint4*)(Bs + r * LROW + ph * PER);
+            bdst[0] = nb0;
+            bdst[1] = nb1;
+            bdst[2] = nb2;
+            bdst[3] = nb3;
+            if (!ARES) {
+                uint4* adst = (uint4*)(As + r * LROW + ph * PER);
+                adst[0] = na0;
+                adst[1] = na1;
+                adst[2] = na2;
+                adst[3] = na3;
+            }
+            if (k0 == 0 && tid < kTileRows) srn[tid] = nrn;
+        }
+        __syncthreads();
+        // the next step's rows are in flight during this step's arithmetic
+        {
+            const bool last = k0 + KC >= ldp;
+            load_step<E, ARES>(Qe, Re, qrow, last ? rt + kTileRows : rt, rend, r, ph * PER, last ? 0 : k0 + KC,
+                               ldp, rn, tid, nb0, nb1, nb2, nb3, na0, na1, na2, na3, nrn);
+        }
+        // K permutation: half h of the wave supplies chunk columns
+        // h*PER .. h*PER+PER-1, the same for A and B, so every column
+        // enters the dot product exactly once.
+        const uint4* ap = (const uint4*)(As + (w * 32 + c) * AROW + (ARES ? k0 : 0) + h * PER);
+        uint4 a4[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) a4[i] = ap[i];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint4* bp = (const uint4*)(Bs + (b * 32 + c) * LROW + h * PER);
+            uint4 b4[NV];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) b4[i] = bp[i];
+            if constexpr (BF) {
+#pragma unroll
+                for (int i = 0; i < NV; ++i) {
+                    bf16x8 av = __builtin_bit_cast(bf16x8, a4[i]);
+                    bf16x8 bv = __builtin_bit_cast(bf16x8, b4[i]);
+                    acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[b], 0, 0, 0);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < NV; ++i) {
+                    f32x4 av = __builtin_bit_cast(f32x4, a4[i]);
+                    f32x4 bv = __builtin_bit_cast(f32x4, b4[i]);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[e], bv[e], acc[b], 0, 0, 0);
+                }
+            }
+        }
+    }
+}
+
 // One workgroup (4 waves) owns 128 query rows and streams the reference
 // rows [rbeg, rend) of its split in 128-row tiles, K chunk by K chunk.  The
 // sequence of (tile, chunk) steps is software-pipelined: the global loads of
@@ -269,67 +353,8 @@ __global__ __launch_bounds__(256, 2) void exact_tile_kernel(
                        na2, na3, nrn);
     for (int64_t rt = rbeg; rt < rend; rt += kTileRows) {
         f32x16 acc[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) acc[b][v] = 0.0f;
-
-        for (int k0 = 0; k0 < ldp; k0 += KC) {
-            __syncthreads();   // the previous step's LDS reads are done
-            {
-                uint4* bdst = (uint4*)(Bs + r * LROW + ph * PER);
-                bdst[0] = nb0;
-                bdst[1] = nb1;
-                bdst[2] = nb2;
-                bdst[3] = nb3;
-                if (!ARES) {
-                    uint4* adst = (uint4*)(As + r * LROW + ph * PER);
-                    adst[0] = na0;
-                    adst[1] = na1;
-                    adst[2] = na2;
-                    adst[3] = na3;
-                }
-                if (k0 == 0 && tid < kTileRows) srn[tid] = nrn;
-            }
-            __syncthreads();
-            // the next step's rows are in flight during this step's arithmetic
-            {
-                const bool last = k0 + KC >= ldp;
-                load_step<E, ARES>(Qe, Re, qrow, last ? rt + kTileRows : rt, rend, r, ph * PER,
-                                   last ? 0 : k0 + KC, ldp, rn, tid, nb0, nb1, nb2, nb3, na0, na1, na2, na3, nrn);
-            }
-            // K permutation: half h of the wave supplies chunk columns
-            // h*PER .. h*PER+PER-1, the same for A and B, so every column
-            // enters the dot product exactly once.
-            const uint4* ap = (const uint4*)(As + (w * 32 + c) * AROW + (ARES ? k0 : 0) + h * PER);
-            uint4 a4[NV];
-#pragma unroll
-            for (int i = 0; i < NV; ++i) a4[i] = ap[i];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const uint4* bp = (const uint4*)(Bs + (b * 32 + c) * LROW + h * PER);
-                uint4 b4[NV];
-#pragma unroll
-                for (int i = 0; i < NV; ++i) b4[i] = bp[i];
-                if constexpr (BF) {
-#pragma unroll
-                    for (int i = 0; i < NV; ++i) {
-                        bf16x8 av = __builtin_bit_cast(bf16x8, a4[i]);
-                        bf16x8 bv = __builtin_bit_cast(bf16x8, b4[i]);
-                        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[b], 0, 0, 0);
-                    }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < NV; ++i) {
-                        f32x4 av = __builtin_bit_cast(f32x4, a4[i]);
-                        f32x4 bv = __builtin_bit_cast(f32x4, b4[i]);
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[e], bv[e], acc[b], 0, 0, 0);
-                    }
-                }
-            }
-        }
+        tile_gemm<BF, ARES>(nb0, nb1, nb2, nb3, na0, na1, na2, na3, nrn, acc, As, Bs, srn, Qe, Re, qrow, rt, rend,
+                            ldp, rn, tid, w, h, c);
 
         // epilogue: distances, threshold gate, list updates
         for (int blk = 0; blk < 4; ++blk) {
@@ -374,6 +399,152 @@ __global__ __launch_bounds__(256, 2) void exact_tile_kernel(
     for (int v = 0; v < 16; ++v) {
         const int64_t row = q0 + w * 32 + mfma_row(v, h);
         if (row < nq) part[(row * S + s) * kListW + c] = list[v];
+    }
+}
+
+// ------------------------------------------------------------ rank counts
+
+constexpr int kRankP = 16;   // probes per query row (the quality metrics' k <= 16)
+
+// Canonical FP32 squared distance of two FP32 rows computed by one lane:
+// the partial sums dist_g16 forms in 16 lanes (coordinate t into partial
+// t mod 16, in order) combined by its tree at strides 8, 4, 2, 1, which is
+// ((s0+s8)+(s4+s12)) + ((s2+s10)+(s6+s14)) + ... ; the same bits.  Partials
+// are formed one at a time so that few registers are live.
+__device__ inline float canon_part(const float* __restrict__ a, const float* __restrict__ b, int d, int g)
+{
+    float s = 0.0f;
+    for (int t = g; t < d; t += 16) {
+        const float e = a[t] - b[t];
+        s = fmaf(e, e, s);
+    }
+    return s;
+}
+
+__device__ __attribute__((noinline)) float canon_dist(const float* __restrict__ a, const float* __restrict__ b, int d)
+{
+    float q[4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        // o = 0, 1, 2, 3 -> the quarter rooted at partials 0, 2, 1, 3
+        const int g = o == 1 ? 2 : (o == 2 ? 1 : o);
+        const float x = canon_part(a, b, d, g) + canon_part(a, b, d, g + 8);
+        const float y = canon_part(a, b, d, g + 4) + canon_part(a, b, d, g + 12);
+        q[o] = x + y;
+    }
+    return (q[0] + q[1]) + (q[2] + q[3]);
+}
+
+// For every query row q and each of its probes (keys (canonical d2, index),
+// ascending; kEmptyCand pads), counts[q][p] = the number of reference rows
+// m != self(q) whose key (canonical FP32 d2(q, m), m) is below the probe's
+// key: the probe's rank minus one.  The same tiles and pipeline as
+// exact_tile_kernel (FP32 MFMA Gram, norm expansion, one split, query rows
+// streamed); the epilogue puts each reference row that can be below a
+// probe of its query into a per-row histogram over the probe boundaries (in
+// LDS), so counts are prefix sums.  A GEMM distance within the slack of a
+// probe's distance (the GEMM error bound plus the canonical distance's) is
+// recomputed in the canonical precision by its lane to decide.
+__global__ __launch_bounds__(256, 2) void rank_tile_kernel(
+    const float* __restrict__ Qs, const float* __restrict__ qn, int64_t nq, const float* __restrict__ Rs,
+    const float* __restrict__ rn, int64_t nr, int ldp, int d, int self_mode, int64_t self_base,
+    const uint64_t* __restrict__ probes, const unsigned* __restrict__ rmax_bits, float err_coef, float edir,
+    uint32_t* __restrict__ counts)
+{
+    using C = TileCfg<false>;
+    constexpr int LROW = C::LROW, KC = C::KC, PER = KC / 2;
+    __shared__ __attribute__((aligned(16))) float As[kTileRows * LROW];
+    __shared__ __attribute__((aligned(16))) float Bs[kTileRows * LROW];
+    __shared__ float srn[kTileRows];
+    __shared__ float sqn[kTileRows];
+    __shared__ int32_t sself[kTileRows];
+    __shared__ float sgate[kTileRows], sslack[kTileRows];
+    __shared__ __attribute__((aligned(16))) uint64_t skey[kTileRows * kRankP];
+    __shared__ uint32_t hist[kTileRows * (kRankP + 1)];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, h = lane >> 5, c = lane & 31;
+    const int64_t q0 = (int64_t)blockIdx.x * kTileRows;
+    const float ra = sqrtf(__uint_as_float(*rmax_bits));
+    for (int e = tid; e < kTileRows * kRankP; e += 256) {
+        const int64_t qr = q0 + e / kRankP;
+        skey[e] = qr < nq ? probes[qr * kRankP + e % kRankP] : kEmptyCand;
+    }
+    for (int e = tid; e < kTileRows * (kRankP + 1); e += 256) hist[e] = 0u;
+    __syncthreads();
+    if (tid < kTileRows) {
+        const int64_t qr = q0 + tid;
+        const float sq = qr < nq ? qn[qr] : 0.0f;
+        sqn[tid] = sq;
+        sself[tid] = qr >= nq ? -1 : (self_mode == 1 ? (int32_t)(self_base + qr) : -1);
+        float mx = -1.0f;
+        for (int p = 0; p < kRankP; ++p) {
+            const uint64_t key = skey[tid * kRankP + p];
+            if (key != kEmptyCand) mx = key_d2(key);
+        }
+        const float qa = sqrtf(sq), E = err_coef * (qa + ra) * (qa + ra);
+        const float sl = E + 2.0f * edir * (mx + E);
+        sslack[tid] = sl;
+        sgate[tid] = mx < 0.0f ? -1.0f : mx + sl;   // rows without probes never pass
+    }
+
+    const float* Qe = Qs;
+    const float* Re = Rs;
+    const int r = tid >> 1, ph = tid & 1;
+    const int64_t qrow = q0 + r < nq ? q0 + r : nq - 1;
+    uint4 nb0, nb1, nb2, nb3, na0 = {}, na1 = {}, na2 = {}, na3 = {};
+    float nrn;
+    load_step<float, false>(Qe, Re, qrow, 0, nr, r, ph * PER, 0, ldp, rn, tid, nb0, nb1, nb2, nb3, na0, na1, na2,
+                            na3, nrn);
+    for (int64_t rt = 0; rt < nr; rt += kTileRows) {
+        f32x16 acc[4];
+        tile_gemm<false, false>(nb0, nb1, nb2, nb3, na0, na1, na2, na3, nrn, acc, As, Bs, srn, Qe, Re, qrow, rt,
+                                nr, ldp, rn, tid, w, h, c);
+        for (int blk = 0; blk < 4; ++blk) {
+            const f32x16 cur = blk == 0 ? acc[0] : (blk == 1 ? acc[1] : (blk == 2 ? acc[2] : acc[3]));
+            const float rnj = srn[blk * 32 + c];
+            const int64_t j = rt + blk * 32 + c;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int lr = w * 32 + mfma_row(v, h);
+                float d2 = fmaf(-2.0f, cur[v], sqn[lr] + rnj);
+                d2 = d2 > 0.0f ? d2 : 0.0f;
+                const bool pass = d2 <= sgate[lr] && j < nr && (int32_t)j != sself[lr];
+                if (!ballot(pass)) continue;
+                if (pass) {
+                    const float sl = sslack[lr];
+                    const uint64_t* pk = skey + lr * kRankP;
+                    int a = 0, b = 0;   // probes with thr <= d2 + sl, with thr < d2 - sl
+#pragma unroll
+                    for (int p = 0; p < kRankP; ++p) {
+                        const uint64_t key = pk[p];
+                        const float thr = key == kEmptyCand ? __builtin_inff() : key_d2(key);
+                        a += thr <= d2 + sl ? 1 : 0;
+                        b += thr < d2 - sl ? 1 : 0;
+                    }
+                    int at = a;   // probes from `at` on have this row below them
+                    if (b < a) {
+                        const float dc = canon_dist(Qs + (q0 + lr) * (int64_t)ldp, Rs + j * (int64_t)ldp, d);
+                        const uint64_t km = make_key(dc, (uint32_t)j);
+                        for (int p = b; p < a; ++p) {
+                            if (km < pk[p]) {
+                                at = p;
+                                break;
+                            }
+                        }
+                    }
+                    if (at < kRankP) atomicAdd(&hist[lr * (kRankP + 1) + at], 1u);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < kTileRows * kRankP; e += 256) {
+        const int lr = e / kRankP, p = e % kRankP;
+        const int64_t qr = q0 + lr;
+        if (qr >= nq) continue;
+        uint32_t cnt = 0;
+        for (int a = 0; a <= p; ++a) cnt += hist[lr * (kRankP + 1) + a];
+        counts[qr * kRankP + p] = cnt;
     }
 }
 
@@ -701,6 +872,140 @@ static knn_status exact_impl(const knn_matrix& Q, const knn_matrix& R, bool same
     return KNN_OK;
 }
 
+// ------------------------------------------------------------ quality
+
+// One wave per row i.  N(i) (row i of Hn, the exact lists in X) sits in
+// lanes 0..k-1, L(i) (row i of Ln, the lists in the embedding Y) likewise.
+// U = L \ N are the trustworthiness probes: their canonical FP32 distances
+// in X as keys; V = N \ L the continuity probes, keyed by their distances in
+// Y.  Both are sorted ascending and padded with kEmptyCand to kRankP (k <=
+// kRankP); hits[i] = |N intersect L|.
+__global__ __launch_bounds__(256) void quality_probes_kernel(int64_t n, int k, const int32_t* __restrict__ Hn,
+                                                             const int32_t* __restrict__ Ln,
+                                                             const float* __restrict__ Xs, int ldx, int dx,
+                                                             const float* __restrict__ Ys, int ldy, int dy,
+                                                             uint64_t* __restrict__ pu, uint64_t* __restrict__ pv,
+                                                             int32_t* __restrict__ hits)
+{
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= n) return;   // uniform across the wave
+    const int32_t hv = lane < k ? Hn[i * k + lane] : -1;
+    const int32_t lv = lane < k ? Ln[i * k + lane] : -1;
+    bool l_in_n = false, n_in_l = false;
+    for (int r = 0; r < k; ++r) {
+        // lane r's entries by readlane, outside any lane-dependent branch
+        const int32_t hr = (int32_t)bcast_u32((uint32_t)hv, r), lr = (int32_t)bcast_u32((uint32_t)lv, r);
+        l_in_n |= lv == hr;
+        n_in_l |= hv == lr;
+    }
+    const bool inU = lane < k && !l_in_n, inV = lane < k && !n_in_l;
+    const float du = dist_batch16<KNN_F32, 4>(Xs, ldx, i, (uint32_t)lv, inU, dx);
+    const float dv = dist_batch16<KNN_F32, 4>(Ys, ldy, i, (uint32_t)hv, inV, dy);
+    uint64_t ku = inU ? make_key(du, (uint32_t)lv) : kEmptyCand;
+    uint64_t kv = inV ? make_key(dv, (uint32_t)hv) : kEmptyCand;
+    ku = seg_sort<16>(ku);
+    kv = seg_sort<16>(kv);
+    if (lane < kRankP) {
+        pu[i * kRankP + lane] = ku;
+        pv[i * kRankP + lane] = kv;
+    }
+    const int nu = popc64(ballot(inU));
+    if (lane == 0) hits[i] = k - nu;
+}
+
+// Per row: trust = sum over U of (rank - k) = sum of (count + 1 - k), cont
+// likewise over V; the three totals by exact integer atomics (order-free).
+__global__ __launch_bounds__(256) void quality_reduce_kernel(int64_t n, int k, const uint64_t* __restrict__ pu,
+                                                             const uint32_t* __restrict__ cu,
+                                                             const uint64_t* __restrict__ pv,
+                                                             const uint32_t* __restrict__ cv,
+                                                             const int32_t* __restrict__ hits,
+                                                             int64_t* __restrict__ trust_row,
+                                                             int64_t* __restrict__ cont_row,
+                                                             unsigned long long* __restrict__ tot)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long t = 0, c = 0, hsum = 0;
+    if (i < n) {
+        for (int p = 0; p < kRankP; ++p) {
+            if (pu[i * kRankP + p] != kEmptyCand) t += (unsigned long long)(cu[i * kRankP + p] + 1u - (uint32_t)k);
+            if (pv[i * kRankP + p] != kEmptyCand) c += (unsigned long long)(cv[i * kRankP + p] + 1u - (uint32_t)k);
+        }
+        hsum = (unsigned long long)hits[i];
+        if (trust_row) trust_row[i] = (int64_t)t;
+        if (cont_row) cont_row[i] = (int64_t)c;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        t += shfl_u64(t, (threadIdx.x & 63) ^ o);
+        c += shfl_u64(c, (threadIdx.x & 63) ^ o);
+        hsum += shfl_u64(hsum, (threadIdx.x & 63) ^ o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&tot[0], hsum);
+        atomicAdd(&tot[1], t);
+        atomicAdd(&tot[2], c);
+    }
+}
+
+static knn_status quality_impl(const knn_matrix& X, const knn_matrix& Y, int k, int32_t* hits_out,
+                               int64_t* trust_out, int64_t* cont_out, double* metrics, hipStream_t st)
+{
+    const int64_t n = X.n;
+    Workspace ws(st, 0);
+    knn_status r;
+    int32_t *Hn, *Ln, *hits;
+    float *Hd, *Ld;
+    if ((r = ws.alloc(&Hn, (size_t)n * k)) != KNN_OK) return r;
+    if ((r = ws.alloc(&Ln, (size_t)n * k)) != KNN_OK) return r;
+    if ((r = ws.alloc(&Hd, (size_t)n * k)) != KNN_OK) return r;
+    if ((r = ws.alloc(&Ld, (size_t)n * k)) != KNN_OK) return r;
+    // exact lists in both spaces (FP32, canonical re-rank)
+    if ((r = exact_impl(X, X, true, nullptr, 1, k, KNN_PREC_FP32, 0, KNN_OUT_SQL2, Hn, Hd, st, ws, 0)) != KNN_OK)
+        return r;
+    if ((r = exact_impl(Y, Y, true, nullptr, 1, k, KNN_PREC_FP32, 0, KNN_OUT_SQL2, Ln, Ld, st, ws, 0)) != KNN_OK)
+        return r;
+    unsigned* small;   // [0] max norm of X, [1] max norm of Y; then three u64 totals
+    if ((r = ws.alloc(&small, 8)) != KNN_OK) return r;
+    zero_words_kernel<<<1, 64, 0, st>>>(small, 8);
+    void *Xs, *Ys;
+    float *xn, *yn;
+    int ldx, ldy;
+    if ((r = stage_matrix(ws, X, false, &Xs, &ldx, &xn, small, st, nullptr, 0)) != KNN_OK) return r;
+    if ((r = stage_matrix(ws, Y, false, &Ys, &ldy, &yn, small + 1, st, nullptr, 0)) != KNN_OK) return r;
+    uint64_t *pu, *pv;
+    uint32_t *cu, *cv;
+    if ((r = ws.alloc(&pu, (size_t)n * kRankP)) != KNN_OK) return r;
+    if ((r = ws.alloc(&pv, (size_t)n * kRankP)) != KNN_OK) return r;
+    if ((r = ws.alloc(&cu, (size_t)n * kRankP)) != KNN_OK) return r;
+    if ((r = ws.alloc(&cv, (size_t)n * kRankP)) != KNN_OK) return r;
+    hits = hits_out;
+    if (!hits && (r = ws.alloc(&hits, (size_t)n)) != KNN_OK) return r;
+    quality_probes_kernel<<<(unsigned)ceil_div(n, 4), 256, 0, st>>>(n, k, Hn, Ln, (const float*)Xs, ldx, X.d,
+                                                                    (const float*)Ys, ldy, Y.d, pu, pv, hits);
+    KNN_HIP(hipGetLastError());
+    const float u = 5.9604645e-08f;
+    const dim3 grid((unsigned)ceil_div(n, kTileRows));
+    rank_tile_kernel<<<grid, 256, 0, st>>>((const float*)Xs, xn, n, (const float*)Xs, xn, n, ldx, X.d, 1, 0, pu,
+                                           small, (float)(X.d + 3) * u * 1.01f, (float)(X.d / 16 + 8) * u, cu);
+    rank_tile_kernel<<<grid, 256, 0, st>>>((const float*)Ys, yn, n, (const float*)Ys, yn, n, ldy, Y.d, 1, 0, pv,
+                                           small + 1, (float)(Y.d + 3) * u * 1.01f, (float)(Y.d / 16 + 8) * u, cv);
+    KNN_HIP(hipGetLastError());
+    unsigned long long* tot = (unsigned long long*)(small + 2);
+    quality_reduce_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(n, k, pu, cu, pv, cv, hits, trust_out,
+                                                                      cont_out, tot);
+    KNN_HIP(hipGetLastError());
+    unsigned long long host[3];
+    KNN_HIP(hipMemcpyAsync(host, tot, 24, hipMemcpyDeviceToHost, st));
+    KNN_HIP(hipStreamSynchronize(st));
+    const double nk = (double)n * (double)k;
+    const double z = 2.0 / (nk * (2.0 * (double)n - 3.0 * (double)k - 1.0));
+    metrics[0] = (double)host[0] / nk;
+    metrics[1] = 1.0 - z * (double)host[1];
+    metrics[2] = 1.0 - z * (double)host[2];
+    return KNN_OK;
+}
+
 // ------------------------------------------------------------ no-alloc path
 
 // The static scratch array of knn_exact_noalloc: one copy per device, held
@@ -803,6 +1108,23 @@ extern "C" knn_status knn_exact_noalloc(knn_matrix X, int32_t k, int32_t precisi
         FixedScratch ws(base, kStaticScratch);
         return exact_impl(X, X, true, nullptr, 1, k, precision, rerank_k, out_kind, out_idx,
                           out_dist, (hipStream_t)stream, ws, (int64_t)kStaticScratch);
+    } catch (...) {
+        return fail(KNN_EDEVICE, "unexpected exception");
+    }
+}
+
+extern "C" knn_status knn_quality(knn_matrix X, knn_matrix Y, int32_t k, int32_t* hits, int64_t* trust,
+                                  int64_t* cont, double* metrics, void* stream)
+{
+    try {
+        knn_status r = check_matrix(X, "X");
+        if (r != KNN_OK) return r;
+        if ((r = check_matrix(Y, "Y")) != KNN_OK) return r;
+        if (!metrics) return fail(KNN_EINVAL, "metrics is null");
+        if (X.n != Y.n) return fail(KNN_EINVAL, "X.n != Y.n");
+        if (k < 1 || 3 * (int64_t)k >= 2 * X.n - 1) return fail(KNN_EINVAL, "k must satisfy 1 <= k and 3k < 2n - 1");
+        if (k > kRankP) return fail(KNN_ENOTSUP, "k above 16 is not supported by the quality metrics");
+        return quality_impl(X, Y, k, hits, trust, cont, metrics, (hipStream_t)stream);
     } catch (...) {
         return fail(KNN_EDEVICE, "unexpected exception");
     }

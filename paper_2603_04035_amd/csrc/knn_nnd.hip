@@ -667,8 +667,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     const int lane = threadIdx.x, c = lane & 31, h = lane >> 5;
     // emitted: offers in the low 32 bits, slot collisions in the high 32 (a
     // lane sends far fewer than 2^32 offers), so one register pair counts both
-    unsigned long long emitted = 0, gathered = 0;
-    unsigned dropped = 0;
+    unsigned long long emitted = 0;
+    // wave-uniform tallies (rows gathered, pairs joined, members cut) live in
+    // LDS, updated by lane 0, so that they hold no registers in the loop
+    __shared__ unsigned long long tally[3];
+    if (threadIdx.x == 0) tally[0] = tally[1] = tally[2] = 0ull;
     const uint64_t salt = (uint64_t)iter ^ seed;
     const int J = cfg.J;
     const int nch = (np + kPC - 1) / kPC;
@@ -684,13 +687,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     for (; v < hi; v += gsz) {
         int L = 0, dr = 0;
         const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cur, cfg, revnew, revold, seed, iter, sh, ids, L, dr));
-        dropped += (unsigned)__builtin_amdgcn_readfirstlane(dr);
+        if (threadIdx.x == 0) tally[2] += (unsigned long long)dr;
         L = __builtin_amdgcn_readfirstlane(L);
         // the next point's lists are in flight while this one is joined
         cur = load_lists(v + gsz, v + gsz < hi, cfg, newf, revnew, oldf, revold);
         __syncthreads();
         if (nn == 0 || L < 2) continue;
-        gathered += (unsigned long long)L;
+        if (threadIdx.x == 0) {
+            tally[0] += (unsigned long long)L;
+            tally[1] += (unsigned long long)(nn * (nn - 1) / 2 + nn * (L - nn));
+        }
         if (!tail_in_pieces && lane < L) {
             // rows whose trailing words lie past the gathered pieces
             const float2 a = *(const float2*)(Xr + (int64_t)ids[lane] * rowbytes + rowbytes - 8);
@@ -772,9 +778,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     }
     if (lane == 0) {
         atomicAdd(&counters[1], emitted);
-        atomicAdd(&counters[2], gathered);
+        atomicAdd(&counters[2], tally[0]);
         atomicAdd(&counters[3], coll);
-        atomicAdd(&counters[4], (unsigned long long)dropped);   // wave-uniform: lane 0 holds the wave's count
+        atomicAdd(&counters[4], tally[2]);
+        atomicAdd(&counters[5], tally[1]);
     }
 }
 // Local join, FP32 form (VALU).  Lists, traversal and offers as in the BF16
@@ -892,8 +899,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     const int lane = threadIdx.x;
     // emitted: offers in the low 32 bits, slot collisions in the high 32 (a
     // lane sends far fewer than 2^32 offers), so one register pair counts both
-    unsigned long long emitted = 0, gathered = 0;
-    unsigned dropped = 0;
+    unsigned long long emitted = 0;
+    // wave-uniform tallies (rows gathered, pairs joined, members cut) live in
+    // LDS, updated by lane 0, so that they hold no registers in the loop
+    __shared__ unsigned long long tally[3];
+    if (threadIdx.x == 0) tally[0] = tally[1] = tally[2] = 0ull;
     const uint64_t salt = (uint64_t)iter ^ seed;
     const unsigned grp = blockIdx.x & 7u;
     const int64_t gsz = (int64_t)(gridDim.x >> 3);
@@ -906,7 +916,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     for (; v < hi; v += gsz) {
         int L = 0, dr = 0;
         const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cur, cfg, revnew, revold, seed, iter, sh, ids, L, dr));
-        dropped += (unsigned)__builtin_amdgcn_readfirstlane(dr);
+        if (threadIdx.x == 0) tally[2] += (unsigned long long)dr;
         L = __builtin_amdgcn_readfirstlane(L);
         cur = load_lists(v + gsz, v + gsz < hi, cfg, newf, revnew, oldf, revold);
         __syncthreads();
@@ -918,7 +928,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
         } else {
             nrm[lane] = 0.0f;
         }
-        gathered += (unsigned long long)L;
+        if (threadIdx.x == 0) {
+            tally[0] += (unsigned long long)L;
+            tally[1] += (unsigned long long)(nn * (nn - 1) / 2 + nn * (L - nn));
+        }
         const int ni = (nn + 7) >> 3;
 #define KNN_JF(NB, NI) \
     join_f32_point<NB, NI>(Xs, ldp, d, rows, ids, nrm, thr, L, nn, cfg.J, cfg.C, salt, cand, emitted, po)
@@ -952,9 +965,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
     }
     if (lane == 0) {
         atomicAdd(&counters[1], emitted);
-        atomicAdd(&counters[2], gathered);
+        atomicAdd(&counters[2], tally[0]);
         atomicAdd(&counters[3], coll);
-        atomicAdd(&counters[4], (unsigned long long)dropped);   // wave-uniform: lane 0 holds the wave's count
+        atomicAdd(&counters[4], tally[2]);
+        atomicAdd(&counters[5], tally[1]);
     }
 }
 
@@ -1354,7 +1368,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     const unsigned merge_grid = (unsigned)round_up(std::min<int64_t>(ceil_div(n, 8), (int64_t)ncu * mpc), 8);
     int iters = 0;
     double ms_join = 0, ms_merge = 0;
-    uint64_t gathered = 0;
+    uint64_t gathered = 0, pairs_joined = 0;
     Timer tj, tm;
     for (int it = 0; it < p->max_iters; ++it) {
         const int iter = iter_offset + it;
@@ -1392,6 +1406,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         (void)hipEventElapsedTime(&ms, tm.a, tm.b);
         ms_merge += ms;
         gathered += host_cnt[2];
+        pairs_joined += host_cnt[5];
         if (stats && it < KNN_MAX_ITERS_LOGGED) {
             stats->updates[it] = (int64_t)host_cnt[0];
             stats->emitted[it] = (int64_t)host_cnt[1];
@@ -1431,6 +1446,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         }
         const int rb = bf ? 2 : 4;
         stats->bytes_gathered = gathered * (uint64_t)X.d * (uint64_t)rb;
+        stats->pairs_joined = pairs_joined;
         float ms = 0;
         (void)hipEventElapsedTime(&ms, t_all.a, t_all.b);
         stats->ms_total = ms;

@@ -343,6 +343,28 @@ knn_status knn_proj_seed(knn_matrix X, const float* Z, int32_t m, const float* d
                          float* out_dist, void* stream);
 
 /*
+ * Principal components of the rows of X and the projection onto the first p
+ * (the PCA preprocessing to pca_dim the paper runs before the k-NN stage,
+ * sections "Reproducibility" and "Scaling Behavior"), in FP64: mean mu,
+ * covariance C = (X - mu)^T (X - mu) / (n - 1), the p largest eigenvalues
+ * (descending) and their eigenvectors, each with its entry of largest
+ * magnitude positive, and Z = (X - mu) V rounded to FP32.
+ *  p       1 <= p <= min(d, 64).
+ *  iters   subspace iterations (0: 200); the eigenvectors come from a
+ *          min(d, max(2p, p + 16))-column subspace iteration with a final
+ *          Rayleigh-Ritz step (exact when that width is d), so their error
+ *          falls as (lambda_{m+1} / lambda_p)^iters.
+ *  Z       device, n x p float.   components  device, nullable, d x p
+ *          double (row-major).   eigenvalues  device, nullable, p double.
+ *  mean    device, nullable, d double.
+ * Errors: KNN_EINVAL for a bad matrix, n < 2, p out of range, iters < 0,
+ * or X of rank below the subspace width; KNN_ENOTSUP for p > 64 or
+ * d > 16384.
+ */
+knn_status knn_pca(knn_matrix X, int32_t p, int32_t iters, float* Z, double* components,
+                   double* eigenvalues, double* mean, void* stream);
+
+/*
  * Embedding quality as the paper's section "Embedding Quality" measures it
  * (Venna & Kaski 2006), from exact ranks in both spaces: X (n x d, the
  * input) and Y (n x e, an embedding of the same rows).  r(i,j) = rank of j

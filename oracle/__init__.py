@@ -379,3 +379,24 @@ def quality(X, Y, k: int, canonical: bool = False):
     h, t, c = quality_rows(X, Y, k, canonical=canonical)
     z = 2.0 / (n * k * (2.0 * n - 3.0 * k - 1.0))
     return float(h.sum()) / (n * k), 1.0 - z * float(t.sum()), 1.0 - z * float(c.sum())
+
+
+def pca(X, p: int):
+    """Principal components of the rows of X (the paper's PCA preprocessing
+    to pca_dim, section "Scaling Behavior"): mean mu, covariance
+    C = (X - mu)^T (X - mu) / (n - 1) in FP64, its eigenpairs by
+    numpy.linalg.eigh, the p largest eigenvalues in descending order with
+    their eigenvectors, each eigenvector's sign fixed so that its entry of
+    largest magnitude (the first such) is positive, and the projection
+    Z = (X - mu) V.  Returns (Z n x p, V d x p, eigenvalues p, mu d)."""
+    X = _f64(X)
+    n = X.shape[0]
+    mu = X.mean(axis=0)
+    Xc = X - mu
+    C = (Xc.T @ Xc) / (n - 1)
+    w, V = np.linalg.eigh(C)
+    order = np.argsort(-w, kind="stable")[:p]
+    w, V = w[order], V[:, order]
+    piv = np.argmax(np.abs(V), axis=0)
+    V = V * np.sign(V[piv, np.arange(V.shape[1])])
+    return Xc @ V, V, w, mu

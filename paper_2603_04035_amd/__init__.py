@@ -8,7 +8,7 @@ has not been built (``paper_2603_04035_amd.build.build()``).
 from __future__ import annotations
 
 __all__ = ["knn_exact", "knn_exact_query", "knn_exact_noalloc", "nndescent_build", "nndescent_refine",
-           "Encoder", "knn_proj_seed", "fuzzy_graph", "quality", "load"]
+           "Encoder", "knn_proj_seed", "fuzzy_graph", "quality", "pca", "load"]
 
 
 def __getattr__(name):

@@ -88,7 +88,7 @@ EXPORTS = [
     "knn_encoder_get_weights", "knn_encoder_embed", "knn_encoder_grads",
     "knn_train_default_params", "knn_encoder_train", "knn_proj_seed",
     "knn_encoder_triplets", "knn_encoder_step", "knn_encoder_get_adam",
-    "knn_exact_query_limited", "knn_exact_noalloc", "knn_fuzzy_graph", "knn_quality",
+    "knn_exact_query_limited", "knn_exact_noalloc", "knn_fuzzy_graph", "knn_quality", "knn_pca",
 ]
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -116,6 +116,8 @@ def load() -> C.CDLL:
     lib.knn_exact_query_limited.argtypes = [knn_matrix, knn_matrix, vp, i32, i32, i32, i32, i64, vp, vp, vp]
     lib.knn_exact_noalloc.restype = i32
     lib.knn_exact_noalloc.argtypes = [knn_matrix, i32, i32, i32, i32, vp, vp, vp]
+    lib.knn_pca.restype = i32
+    lib.knn_pca.argtypes = [knn_matrix, i32, i32, vp, vp, vp, vp, vp]
     lib.knn_quality.restype = i32
     lib.knn_quality.argtypes = [knn_matrix, knn_matrix, i32, vp, vp, vp, C.POINTER(C.c_double), vp]
     lib.knn_fuzzy_graph.restype = i32
@@ -352,3 +354,17 @@ def quality(X: torch.Tensor, Y: torch.Tensor, k: int = 10, per_row: bool = False
     _check(lib.knn_quality(matrix(X), matrix(Y), k, _ptr(h), _ptr(t), _ptr(c), m, _stream()))
     out = (m[0], m[1], m[2])
     return (out, (h, t, c)) if per_row else out
+
+
+def pca(X: torch.Tensor, p: int, iters: int = 0):
+    """PCA of the rows of X: (Z n x p float32, components d x p float64,
+    eigenvalues p float64, mean d float64)."""
+    lib = load()
+    n, d = X.shape
+    dev = X.device
+    Z = torch.empty((n, p), dtype=torch.float32, device=dev)
+    V = torch.empty((d, p), dtype=torch.float64, device=dev)
+    w = torch.empty(p, dtype=torch.float64, device=dev)
+    mu = torch.empty(d, dtype=torch.float64, device=dev)
+    _check(lib.knn_pca(matrix(X), p, iters, Z.data_ptr(), V.data_ptr(), w.data_ptr(), mu.data_ptr(), _stream()))
+    return Z, V, w, mu

@@ -50,8 +50,10 @@ enum {
 
 /* element type of an input matrix */
 enum { KNN_F32 = 0, KNN_BF16 = 1, KNN_F16 = 2 };
-/* distance precision: FP32 throughout, or BF16 MFMA candidates + FP32 re-rank */
-enum { KNN_PREC_FP32 = 0, KNN_PREC_BF16 = 1 };
+/* distance precision: FP32 throughout, or 16-bit MFMA candidates (inputs
+ * rounded to BF16, or to FP16 -- exact for FP16-stored data, finite below
+ * 65504 in magnitude) with FP32 accumulation + FP32 re-rank */
+enum { KNN_PREC_FP32 = 0, KNN_PREC_BF16 = 1, KNN_PREC_FP16 = 2 };
 /* returned distance kind */
 enum { KNN_OUT_L2 = 0, KNN_OUT_SQL2 = 1 };
 /* NNDescent initial lists */

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libknn.so")
 
 KNN_OK, KNN_EINVAL, KNN_ENOMEM, KNN_EDEVICE, KNN_ENOTSUP = 0, -1, -2, -3, -4
 KNN_F32, KNN_BF16, KNN_F16 = 0, 1, 2
-KNN_PREC_FP32, KNN_PREC_BF16 = 0, 1
+KNN_PREC_FP32, KNN_PREC_BF16, KNN_PREC_FP16 = 0, 1, 2
 KNN_OUT_L2, KNN_OUT_SQL2 = 0, 1
 KNN_INIT_RANDOM, KNN_INIT_ENCODER = 0, 1
 KNN_MAX_K = 32
@@ -25,7 +25,7 @@ ENC_H1, ENC_H2 = 64, 32
 MAX_ITERS_LOGGED = 64
 
 _DTYPES = {torch.float32: KNN_F32, torch.bfloat16: KNN_BF16, torch.float16: KNN_F16}
-_PREC = {"fp32": KNN_PREC_FP32, "bf16": KNN_PREC_BF16}
+_PREC = {"fp32": KNN_PREC_FP32, "bf16": KNN_PREC_BF16, "fp16": KNN_PREC_FP16}
 _OUT = {"l2": KNN_OUT_L2, "sql2": KNN_OUT_SQL2}
 
 
@@ -273,7 +273,7 @@ def _state_tensors(n, K, device, want):
 def _build_k(p: knn_nnd_params, n: int) -> int:
     K = p.build_k
     if K == 0:
-        K = min(2 * p.k, KNN_MAX_K) if p.precision == KNN_PREC_BF16 else p.k
+        K = min(2 * p.k, KNN_MAX_K) if p.precision != KNN_PREC_FP32 else p.k
     return min(K, n - 1)
 
 

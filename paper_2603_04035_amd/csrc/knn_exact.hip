@@ -41,7 +41,7 @@ constexpr int kListW = 32;        // list width per query row (k' <= 32)
 // reduction.  With `aux`, the last 8 bytes of each row hold two FP32 words
 // instead of zeros: the norm and +inf (a per-row value that NNDescent keeps
 // current).
-template <int DT, bool TO_BF16>
+template <int DT, int OUT>
 __global__ __launch_bounds__(256) void stage_kernel(const void* __restrict__ X, int64_t n, int d,
                                                     int64_t ld, void* __restrict__ Xs, int ldp,
                                                     float* __restrict__ norms,
@@ -51,7 +51,8 @@ __global__ __launch_bounds__(256) void stage_kernel(const void* __restrict__ X, 
     constexpr int RB = 4;   // rows per wave and step: their loads are issued together
     __shared__ unsigned smax[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int lim = aux ? ldp - (TO_BF16 ? 4 : 2) : ldp;
+    constexpr bool HALF = OUT != KNN_F32;   // 2-byte staged elements
+    const int lim = aux ? ldp - (HALF ? 4 : 2) : ldp;
     unsigned wmax = 0;
     for (int64_t row0 = ((int64_t)blockIdx.x * 4 + wv) * RB; row0 < n; row0 += (int64_t)gridDim.x * 4 * RB) {
         int64_t src[RB];
@@ -71,10 +72,14 @@ __global__ __launch_bounds__(256) void stage_kernel(const void* __restrict__ X, 
                 if (row0 + q >= n) continue;
                 const int64_t row = row0 + q;
                 float x = v[q];
-                if (TO_BF16) {
+                if constexpr (OUT == KNN_BF16) {
                     uint16_t b = f32_to_bf16_rne(x);
                     ((uint16_t*)Xs)[row * ldp + t] = b;
                     x = __uint_as_float((uint32_t)b << 16);
+                } else if constexpr (OUT == KNN_F16) {
+                    const _Float16 hv = (_Float16)x;   // round to nearest even
+                    ((_Float16*)Xs)[row * ldp + t] = hv;
+                    x = (float)hv;
                 } else {
                     ((float*)Xs)[row * ldp + t] = x;
                 }
@@ -93,7 +98,7 @@ __global__ __launch_bounds__(256) void stage_kernel(const void* __restrict__ X, 
             if (lane == 0) {
                 norms[row] = s[q];
                 if (aux) {
-                    float* a = (float*)((char*)Xs + (row + 1) * (int64_t)ldp * (TO_BF16 ? 2 : 4)) - 2;
+                    float* a = (float*)((char*)Xs + (row + 1) * (int64_t)ldp * (HALF ? 2 : 4)) - 2;
                     a[0] = s[q];
                     a[1] = __builtin_inff();
                 }
@@ -115,7 +120,8 @@ __global__ __launch_bounds__(256) void stage_kernel(const void* __restrict__ X, 
 
 // ------------------------------------------------------------------ tile
 
-template <bool BF>
+// Tile geometry per staged element kind (KNN_F32, KNN_BF16, KNN_F16).
+template <int OUT>
 struct TileCfg {
     using E = float;
     static constexpr int KC = 32;    // elements per K chunk (128 bytes per row)
@@ -124,13 +130,17 @@ struct TileCfg {
     static constexpr int AROW = 68;  // their LDS row stride
 };
 template <>
-struct TileCfg<true> {
+struct TileCfg<KNN_BF16> {
     using E = uint16_t;
     static constexpr int KC = 64;
     static constexpr int LROW = 72;
     static constexpr int AMAX = 64;
     static constexpr int AROW = 72;
 };
+template <>
+struct TileCfg<KNN_F16> : TileCfg<KNN_BF16> {};
+
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 // Output D of a 32x32 MFMA: lane l, accumulator v holds row
 // 8*(v/4) + 4*(l/32) + v%4 and column l%32 of the 32x32 block.
@@ -200,14 +210,14 @@ __device__ inline void load_step(const E* Qe, const E* Re, int64_t qrow, int64_t
 // issues the loads of the next step (the next tile's first chunk after the
 // last chunk), so the loads of a step overlap the MFMAs of the one before.
 // With ARES the query rows are already in As (row stride AROW).
-template <bool BF, bool ARES>
+template <int OUT, bool ARES>
 __device__ __attribute__((always_inline)) inline void tile_gemm(
     uint4& nb0, uint4& nb1, uint4& nb2, uint4& nb3, uint4& na0, uint4& na1, uint4& na2, uint4& na3, float& nrn,
-    f32x16 (&acc)[4], typename TileCfg<BF>::E* As, typename TileCfg<BF>::E* Bs, float* srn,
-    const typename TileCfg<BF>::E* Qe, const typename TileCfg<BF>::E* Re, int64_t qrow, int64_t rt,
+    f32x16 (&acc)[4], typename TileCfg<OUT>::E* As, typename TileCfg<OUT>::E* Bs, float* srn,
+    const typename TileCfg<OUT>::E* Qe, const typename TileCfg<OUT>::E* Re, int64_t qrow, int64_t rt,
     int64_t rend, int ldp, const float* rn, int tid, int w, int h, int c)
 {
-    using C = TileCfg<BF>;
+    using C = TileCfg<OUT>;
     using E = typename C::E;
     constexpr int KC = C::KC, LROW = C::LROW, PER = KC / 2;
     constexpr int AROW = ARES ? C::AROW : LROW;
@@ -256,12 +266,19 @@ __device__ __attribute__((always_inline)) inline void tile_gemm(
             uint4 b4[NV];
 #pragma unroll
             for (int i = 0; i < NV; ++i) b4[i] = bp[i];
-            if constexpr (BF) {
+            if constexpr (OUT == KNN_BF16) {
 #pragma unroll
                 for (int i = 0; i < NV; ++i) {
                     bf16x8 av = __builtin_bit_cast(bf16x8, a4[i]);
                     bf16x8 bv = __builtin_bit_cast(bf16x8, b4[i]);
                     acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[b], 0, 0, 0);
+                }
+            } else if constexpr (OUT == KNN_F16) {
+#pragma unroll
+                for (int i = 0; i < NV; ++i) {
+                    f16x8 av = __builtin_bit_cast(f16x8, a4[i]);
+                    f16x8 bv = __builtin_bit_cast(f16x8, b4[i]);
+                    acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc[b], 0, 0, 0);
                 }
             } else {
 #pragma unroll
@@ -286,14 +303,14 @@ __device__ __attribute__((always_inline)) inline void tile_gemm(
 // loaded into LDS once and only reference rows stream.  Wave w computes
 // query rows 32w..32w+31 against the tile's 128 references (four 32x32
 // MFMA blocks).
-template <bool BF, bool ARES>
+template <int OUT, bool ARES>
 __global__ __launch_bounds__(256, 2) void exact_tile_kernel(
     const void* __restrict__ Qs, const float* __restrict__ qn, int64_t nq,
     const void* __restrict__ Rs, const float* __restrict__ rn, int64_t nr, int ldp,
     const int32_t* __restrict__ q_self, int self_mode, int64_t self_base, int kp, int64_t split_len, int S,
     const unsigned* __restrict__ rmax_bits, uint64_t* __restrict__ part)
 {
-    using C = TileCfg<BF>;
+    using C = TileCfg<OUT>;
     using E = typename C::E;
     constexpr int KC = C::KC, LROW = C::LROW, PER = KC / 2;
     constexpr int AROW = ARES ? C::AROW : LROW;
@@ -353,7 +370,7 @@ __global__ __launch_bounds__(256, 2) void exact_tile_kernel(
                        na2, na3, nrn);
     for (int64_t rt = rbeg; rt < rend; rt += kTileRows) {
         f32x16 acc[4];
-        tile_gemm<BF, ARES>(nb0, nb1, nb2, nb3, na0, na1, na2, na3, nrn, acc, As, Bs, srn, Qe, Re, qrow, rt, rend,
+        tile_gemm<OUT, ARES>(nb0, nb1, nb2, nb3, na0, na1, na2, na3, nrn, acc, As, Bs, srn, Qe, Re, qrow, rt, rend,
                             ldp, rn, tid, w, h, c);
 
         // epilogue: distances, threshold gate, list updates
@@ -451,7 +468,7 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
     const uint64_t* __restrict__ probes, const unsigned* __restrict__ rmax_bits, float err_coef, float edir,
     uint32_t* __restrict__ counts)
 {
-    using C = TileCfg<false>;
+    using C = TileCfg<KNN_F32>;
     constexpr int LROW = C::LROW, KC = C::KC, PER = KC / 2;
     __shared__ __attribute__((aligned(16))) float As[kTileRows * LROW];
     __shared__ __attribute__((aligned(16))) float Bs[kTileRows * LROW];
@@ -497,7 +514,7 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
                             na3, nrn);
     for (int64_t rt = 0; rt < nr; rt += kTileRows) {
         f32x16 acc[4];
-        tile_gemm<false, false>(nb0, nb1, nb2, nb3, na0, na1, na2, na3, nrn, acc, As, Bs, srn, Qe, Re, qrow, rt,
+        tile_gemm<KNN_F32, false>(nb0, nb1, nb2, nb3, na0, na1, na2, na3, nrn, acc, As, Bs, srn, Qe, Re, qrow, rt,
                                 nr, ldp, rn, tid, w, h, c);
         for (int blk = 0; blk < 4; ++blk) {
             const f32x16 cur = blk == 0 ? acc[0] : (blk == 1 ? acc[1] : (blk == 2 ? acc[2] : acc[3]));
@@ -660,40 +677,50 @@ __global__ __launch_bounds__(256) void exact_fallback_kernel(
 
 // ------------------------------------------------------------------ host
 
-template <bool TO_BF16>
+template <int OUT>
 static void launch_stage(const knn_matrix& X, void* Xs, int ldp, float* norms, unsigned* maxn,
                          const uint32_t* rowmap, int aux, hipStream_t st)
 {
     dim3 grid((unsigned)std::min<int64_t>(ceil_div(X.n, 16), 4096)), block(256);
     switch (X.dtype) {
     case KNN_F32:
-        stage_kernel<KNN_F32, TO_BF16><<<grid, block, 0, st>>>(X.data, X.n, X.d, X.ld, Xs, ldp, norms, maxn, rowmap, aux);
+        stage_kernel<KNN_F32, OUT><<<grid, block, 0, st>>>(X.data, X.n, X.d, X.ld, Xs, ldp, norms, maxn, rowmap, aux);
         break;
     case KNN_BF16:
-        stage_kernel<KNN_BF16, TO_BF16><<<grid, block, 0, st>>>(X.data, X.n, X.d, X.ld, Xs, ldp, norms, maxn, rowmap, aux);
+        stage_kernel<KNN_BF16, OUT><<<grid, block, 0, st>>>(X.data, X.n, X.d, X.ld, Xs, ldp, norms, maxn, rowmap, aux);
         break;
     default:
-        stage_kernel<KNN_F16, TO_BF16><<<grid, block, 0, st>>>(X.data, X.n, X.d, X.ld, Xs, ldp, norms, maxn, rowmap, aux);
+        stage_kernel<KNN_F16, OUT><<<grid, block, 0, st>>>(X.data, X.n, X.d, X.ld, Xs, ldp, norms, maxn, rowmap, aux);
         break;
     }
 }
 
-// Staged copy of a matrix for the GEMM (FP32 ld = roundup(d, 32) or BF16
-// ld = roundup(d, 64), both 128-byte multiples), norms and max norm.  Row r
-// of the copy is row rowmap[r] of X (rowmap nullable: identity).  With aux,
-// ld leaves room for the two trailing FP32 words (see stage_kernel).
-knn_status stage_matrix(ScratchAlloc& ws, const knn_matrix& X, bool bf16, void** Xs, int* ldp,
+static void launch_stage_kind(int kind, const knn_matrix& X, void* Xs, int ldp, float* norms, unsigned* maxn,
+                              const uint32_t* rowmap, int aux, hipStream_t st)
+{
+    if (kind == KNN_BF16) launch_stage<KNN_BF16>(X, Xs, ldp, norms, maxn, rowmap, aux, st);
+    else if (kind == KNN_F16) launch_stage<KNN_F16>(X, Xs, ldp, norms, maxn, rowmap, aux, st);
+    else launch_stage<KNN_F32>(X, Xs, ldp, norms, maxn, rowmap, aux, st);
+}
+
+// Staged copy of a matrix for the GEMM (FP32 ld = roundup(d, 32) or BF16 /
+// FP16 ld = roundup(d, 64), both 128-byte multiples), norms and max norm.
+// kind (KNN_F32, KNN_BF16, KNN_F16) is the staged element type; values are
+// rounded to nearest even.  Row r of the copy is row rowmap[r] of X (rowmap
+// nullable: identity).  With aux, ld leaves room for the two trailing FP32
+// words (see stage_kernel).
+knn_status stage_matrix(ScratchAlloc& ws, const knn_matrix& X, int kind, void** Xs, int* ldp,
                         float** norms, unsigned* maxnorm, hipStream_t st, const uint32_t* rowmap,
                         int aux)
 {
-    const int64_t need = X.d + (aux ? (bf16 ? 4 : 2) : 0);
-    *ldp = bf16 ? (int)round_up(need, 64) : (int)round_up(need, 32);
-    knn_status r = ws.alloc(Xs, (size_t)X.n * (size_t)(*ldp) * (bf16 ? 2 : 4));
+    const bool half = kind != KNN_F32;
+    const int64_t need = X.d + (aux ? (half ? 4 : 2) : 0);
+    *ldp = half ? (int)round_up(need, 64) : (int)round_up(need, 32);
+    knn_status r = ws.alloc(Xs, (size_t)X.n * (size_t)(*ldp) * (half ? 2 : 4));
     if (r != KNN_OK) return r;
     r = ws.alloc(norms, (size_t)X.n);
     if (r != KNN_OK) return r;
-    if (bf16) launch_stage<true>(X, *Xs, *ldp, *norms, maxnorm, rowmap, aux, st);
-    else launch_stage<false>(X, *Xs, *ldp, *norms, maxnorm, rowmap, aux, st);
+    launch_stage_kind(kind, X, *Xs, *ldp, *norms, maxnorm, rowmap, aux, st);
     KNN_HIP(hipGetLastError());
     return KNN_OK;
 }
@@ -745,8 +772,8 @@ static knn_status exact_impl(const knn_matrix& Q, const knn_matrix& R, bool same
                              int32_t rerank_k, int32_t out_kind, int32_t* out_idx, float* out_dist,
                              hipStream_t st, ScratchAlloc& ws, int64_t budget)
 {
-    if (precision != KNN_PREC_FP32 && precision != KNN_PREC_BF16)
-        return fail(KNN_EINVAL, "precision must be KNN_PREC_FP32 or KNN_PREC_BF16");
+    if (precision != KNN_PREC_FP32 && precision != KNN_PREC_BF16 && precision != KNN_PREC_FP16)
+        return fail(KNN_EINVAL, "precision must be KNN_PREC_FP32, KNN_PREC_BF16 or KNN_PREC_FP16");
     if (out_kind != KNN_OUT_L2 && out_kind != KNN_OUT_SQL2)
         return fail(KNN_EINVAL, "out_kind must be KNN_OUT_L2 or KNN_OUT_SQL2");
     if (!out_idx || !out_dist) return fail(KNN_EINVAL, "null output pointer");
@@ -759,7 +786,9 @@ static knn_status exact_impl(const knn_matrix& Q, const knn_matrix& R, bool same
         return fail(KNN_ENOTSUP, "rerank_k and k above 32 are not supported by the exact path");
     if (budget < 0) return fail(KNN_EINVAL, "workspace limit must be >= 0");
     if (Q.n == 0) return KNN_OK;
-    const bool bf = precision == KNN_PREC_BF16;
+    // staged element kind: FP32, or the 16-bit type of the MFMA form
+    const int kind = precision == KNN_PREC_BF16 ? KNN_BF16 : (precision == KNN_PREC_FP16 ? KNN_F16 : KNN_F32);
+    const bool bf = kind != KNN_F32;
 
     // query chunk: the largest multiple of the tile height that fits
     int64_t qc = Q.n;
@@ -785,7 +814,7 @@ static knn_status exact_impl(const knn_matrix& Q, const knn_matrix& R, bool same
     void *Rs = nullptr, *Qb = nullptr;
     float *rn = nullptr, *qnb = nullptr;
     int ldp = 0;
-    r = stage_matrix(ws, R, bf, &Rs, &ldp, &rn, small, st, nullptr, 0);
+    r = stage_matrix(ws, R, kind, &Rs, &ldp, &rn, small, st, nullptr, 0);
     if (r != KNN_OK) return r;
     const size_t eb = bf ? 2 : 4;
     if (!same) {
@@ -802,7 +831,7 @@ static knn_status exact_impl(const knn_matrix& Q, const knn_matrix& R, bool same
     r = ws.alloc(&fb_rows, (size_t)qc);
     if (r != KNN_OK) return r;
 
-    const bool ares = ldp <= (bf ? TileCfg<true>::AMAX : TileCfg<false>::AMAX);
+    const bool ares = ldp <= (bf ? TileCfg<KNN_BF16>::AMAX : TileCfg<KNN_F32>::AMAX);
     // GEMM error bound (FP32): (d + 3) u (|q| + max|r|)^2 with u = 2^-24;
     // re-rank bound: (d/16 + 8) u relative.
     const float u = 5.9604645e-08f;
@@ -821,8 +850,7 @@ static knn_status exact_impl(const knn_matrix& Q, const knn_matrix& R, bool same
             qn = rn + q0;
         } else {
             const knn_matrix Qc = {(const char*)Q.data + (size_t)q0 * Q.ld * qeb, nq, Q.d, Q.ld, Q.dtype};
-            if (bf) launch_stage<true>(Qc, Qb, ldp, qnb, nullptr, nullptr, 0, st);
-            else launch_stage<false>(Qc, Qb, ldp, qnb, nullptr, nullptr, 0, st);
+            launch_stage_kind(kind, Qc, Qb, ldp, qnb, nullptr, nullptr, 0, st);
             Qs = Qb;
             qn = qnb;
         }
@@ -832,12 +860,15 @@ static knn_status exact_impl(const knn_matrix& Q, const knn_matrix& R, bool same
 #define KNN_TILE(BFV, AR)                                                                        \
     exact_tile_kernel<BFV, AR><<<tgrid, 256, 0, st>>>(Qs, qn, nq, Rs, rn, R.n, ldp, qself,       \
                                                       self_mode, q0, kp, split_len, S, small, part)
-        if (bf) {
-            if (ares) KNN_TILE(true, true);
-            else KNN_TILE(true, false);
+        if (kind == KNN_BF16) {
+            if (ares) KNN_TILE(KNN_BF16, true);
+            else KNN_TILE(KNN_BF16, false);
+        } else if (kind == KNN_F16) {
+            if (ares) KNN_TILE(KNN_F16, true);
+            else KNN_TILE(KNN_F16, false);
         } else {
-            if (ares) KNN_TILE(false, true);
-            else KNN_TILE(false, false);
+            if (ares) KNN_TILE(KNN_F32, true);
+            else KNN_TILE(KNN_F32, false);
         }
 #undef KNN_TILE
         KNN_HIP(hipGetLastError());
@@ -971,8 +1002,8 @@ static knn_status quality_impl(const knn_matrix& X, const knn_matrix& Y, int k, 
     void *Xs, *Ys;
     float *xn, *yn;
     int ldx, ldy;
-    if ((r = stage_matrix(ws, X, false, &Xs, &ldx, &xn, small, st, nullptr, 0)) != KNN_OK) return r;
-    if ((r = stage_matrix(ws, Y, false, &Ys, &ldy, &yn, small + 1, st, nullptr, 0)) != KNN_OK) return r;
+    if ((r = stage_matrix(ws, X, KNN_F32, &Xs, &ldx, &xn, small, st, nullptr, 0)) != KNN_OK) return r;
+    if ((r = stage_matrix(ws, Y, KNN_F32, &Ys, &ldy, &yn, small + 1, st, nullptr, 0)) != KNN_OK) return r;
     uint64_t *pu, *pv;
     uint32_t *cu, *cv;
     if ((r = ws.alloc(&pu, (size_t)n * kRankP)) != KNN_OK) return r;

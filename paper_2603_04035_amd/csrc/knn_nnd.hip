@@ -37,7 +37,7 @@
 
 namespace knn {
 
-knn_status stage_matrix(ScratchAlloc& ws, const knn_matrix& X, bool bf16, void** Xs, int* ldp,
+knn_status stage_matrix(ScratchAlloc& ws, const knn_matrix& X, int kind, void** Xs, int* ldp,
                         float** norms, unsigned* maxnorm, hipStream_t st, const uint32_t* rowmap,
                         int aux);
 knn_status morton_order(const knn_matrix& X, int D, uint64_t seed, Workspace& ws, uint32_t** perm,
@@ -576,7 +576,8 @@ __device__ inline unsigned long long offer_resolve(const PendingOffer& po)
     return n;
 }
 
-// Local join, BF16 form.  One wave per point v; the grid is split into 8
+// Local join, 16-bit MFMA forms (BF16, or FP16: OUT is the staged element
+// type).  One wave per point v; the grid is split into 8
 // groups (blockIdx mod 8, the round-robin XCD assignment of workgroups) that
 // each sweep one contiguous range of the processing order, so concurrently
 // joined points are Z-order neighbours sharing an L2.
@@ -602,10 +603,19 @@ constexpr int kPC = 4;   // pieces per lane per row held in registers at a time
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// One 32x32x16 MFMA step on 16-bit operands: BF16 or FP16 (OUT = KNN_BF16 /
+// KNN_F16, the staged element type), FP32 accumulation.
+template <int OUT>
 __device__ inline f32x16 gram_step(const uint4& a, const uint4& b, f32x16 acc)
 {
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
-                                                    acc, 0, 0, 0);
+    if constexpr (OUT == KNN_F16)
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b),
+                                                       acc, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                        acc, 0, 0, 0);
 }
 
 // Piece p of a row (r = row base + 16h bytes): the load always reads inside
@@ -654,7 +664,8 @@ __device__ inline void scan_block(const f32x16& g, int blk, int h4, int m, int l
     }
 }
 
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nnd_join_bf16_kernel(
+template <int OUT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nnd_join_mfma_kernel(
     int64_t n, JoinCfg cfg, const uint8_t* __restrict__ Xr, int64_t rowbytes, int np,
     const int32_t* __restrict__ newf, uint32_t* __restrict__ revnew,
     const int32_t* __restrict__ oldf, uint32_t* __restrict__ revold,
@@ -741,8 +752,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
                 for (int q = 0; q < kPC; ++q) {
                     if (q < pc) {
                         const uint4 b = cb == 0 ? A0[q] : A1[q];
-                        at = gram_step(A0[q], b, at);
-                        if (lower) ab = gram_step(A1[q], b, ab);
+                        at = gram_step<OUT>(A0[q], b, at);
+                        if (lower) ab = gram_step<OUT>(A1[q], b, ab);
                     }
                 }
             }
@@ -1225,7 +1236,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     const int64_t n = X.n;
     if (n < 2) return fail(KNN_EINVAL, "X.n must be >= 2");
     if (p->k < 1 || (int64_t)p->k > n - 1) return fail(KNN_EINVAL, "k must satisfy 1 <= k <= n-1");
-    if (p->precision != KNN_PREC_FP32 && p->precision != KNN_PREC_BF16)
+    if (p->precision != KNN_PREC_FP32 && p->precision != KNN_PREC_BF16 && p->precision != KNN_PREC_FP16)
         return fail(KNN_EINVAL, "unknown precision");
     if (p->out_kind != KNN_OUT_L2 && p->out_kind != KNN_OUT_SQL2)
         return fail(KNN_EINVAL, "unknown out_kind");
@@ -1237,8 +1248,11 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     if (p->max_iters < 0) return fail(KNN_EINVAL, "max_iters must be >= 0");
     if (iter_offset < 0) return fail(KNN_EINVAL, "iter_offset must be >= 0");
     if (init_idx && (init_k < 1 || init_k > 64)) return fail(KNN_EINVAL, "init_k must be in [1, 64]");
+    // the 16-bit MFMA forms (BF16, FP16) and their staged element type
+    const bool bf = p->precision != KNN_PREC_FP32;
+    const int kind = p->precision == KNN_PREC_BF16 ? KNN_BF16 : (p->precision == KNN_PREC_FP16 ? KNN_F16 : KNN_F32);
     int K = p->build_k;
-    if (K == 0) K = p->precision == KNN_PREC_BF16 ? (2 * p->k < KNN_MAX_K ? 2 * p->k : KNN_MAX_K) : p->k;
+    if (K == 0) K = bf ? (2 * p->k < KNN_MAX_K ? 2 * p->k : KNN_MAX_K) : p->k;
     if (K < p->k) return fail(KNN_EINVAL, "build_k must be >= k");
     if (K > KNN_MAX_K) return fail(KNN_ENOTSUP, "build_k above 32 is not supported");
     if ((int64_t)K > n - 1) K = (int)(n - 1);
@@ -1252,7 +1266,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     cfg.R = s;
     cfg.K = K;
     // default slot counts: the 1M x 50 sweeps' choices per form
-    cfg.C = p->cand_slots > 0 ? p->cand_slots : (p->precision == KNN_PREC_BF16 ? 96 : 64);
+    cfg.C = p->cand_slots > 0 ? p->cand_slots : (bf ? 96 : 64);
     if (cfg.C > 256) return fail(KNN_ENOTSUP, "cand_slots above 256 is not supported");
     cfg.J = p->join_cap > 0 ? p->join_cap : 4;
     if (cfg.J > kJMax) cfg.J = kJMax;
@@ -1264,7 +1278,6 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     Timer t_all, t_init, t_fin;
     (void)hipEventRecord(t_all.a, st);
     Workspace ws(st, p->workspace_limit_bytes);
-    const bool bf = p->precision == KNN_PREC_BF16;
     // processing order: Z-order curve of X (see morton_order); every staged
     // copy and every list below is indexed in that order
     uint32_t *perm = nullptr, *inv = nullptr;
@@ -1273,13 +1286,13 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     void* Xs = nullptr;
     float* norms = nullptr;
     int ldp = 0;
-    r = stage_matrix(ws, X, false, &Xs, &ldp, &norms, nullptr, st, perm, 1);
+    r = stage_matrix(ws, X, KNN_F32, &Xs, &ldp, &norms, nullptr, st, perm, 1);
     if (r != KNN_OK) return r;
     void* Xb = nullptr;
     float* nb = nullptr;
     int ldb = 0;
     if (bf) {
-        r = stage_matrix(ws, X, true, &Xb, &ldb, &nb, nullptr, st, perm, 1);
+        r = stage_matrix(ws, X, kind, &Xb, &ldb, &nb, nullptr, st, perm, 1);
         if (r != KNN_OK) return r;
     }
     // the copy the join reads, and its per-row worst-distance word
@@ -1319,8 +1332,9 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         const int w = p->proj_window > 0 ? p->proj_window : 8;
         const int D = p->proj_dims > 0 ? p->proj_dims : 8;
         // seed distances in the form's precision (the BF16 copy's values)
-        const knn_matrix Xd = bf ? knn_matrix{Xb, X.n, X.d, ldb, KNN_BF16} : Xp;
-        r = encoder_seed(p->encoder, Xp, Xd, p->precision, P, D, w, p->seed, ws, &si, &sd, st);
+        const knn_matrix Xd = bf ? knn_matrix{Xb, X.n, X.d, ldb, kind} : Xp;
+        // the encoder embeds in FP32 or in its BF16 mode (the 16-bit forms)
+        r = encoder_seed(p->encoder, Xp, Xd, bf ? KNN_PREC_BF16 : KNN_PREC_FP32, P, D, w, p->seed, ws, &si, &sd, st);
         if (r != KNN_OK) return r;
         seed_idx = si;
         seed_d2 = sd;
@@ -1354,7 +1368,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     int jpc = 0;
     KNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &jpc, bf ? (const void*)nnd_join_bf16_kernel : (const void*)nnd_join_f32_kernel, 64, 0));
+        &jpc, bf ? (const void*)nnd_join_mfma_kernel<KNN_BF16> : (const void*)nnd_join_f32_kernel, 64, 0));
     if (jpc < 1) jpc = 1;
     // a multiple of 8: the join splits its grid into 8 contiguous point ranges
     const unsigned join_grid = (unsigned)round_up((int64_t)ncu * jpc, 8);
@@ -1375,9 +1389,12 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         KNN_HIP(hipMemsetAsync(counters, 0, 64, st));
         // iteration `iter` was sampled by the init kernel or the previous merge
         (void)hipEventRecord(tj.a, st);
-        if (bf)
-            nnd_join_bf16_kernel<<<join_grid, 64, 0, st>>>(n, cfg, Xr, rowbytes, np, newf, revnew, oldf, revold,
-                                                           cand, p->seed, iter, counters);
+        if (kind == KNN_F16)
+            nnd_join_mfma_kernel<KNN_F16><<<join_grid, 64, 0, st>>>(n, cfg, Xr, rowbytes, np, newf, revnew, oldf,
+                                                                    revold, cand, p->seed, iter, counters);
+        else if (kind == KNN_BF16)
+            nnd_join_mfma_kernel<KNN_BF16><<<join_grid, 64, 0, st>>>(n, cfg, Xr, rowbytes, np, newf, revnew, oldf,
+                                                                     revold, cand, p->seed, iter, counters);
         else
             nnd_join_f32_kernel<<<join_grid, 64, 0, st>>>(n, cfg, (const float*)Xs, ldp, X.d, newf, revnew, oldf,
                                                           revold, cand, p->seed, iter, counters);

@@ -58,6 +58,9 @@ FORMS = {
                         join_cap=4, cand_slots=96),
     "bf16-untrained": dict(precision="bf16", build_k=30, sample_rate=1.0, max_iters=30, delta=0.015,
                            join_cap=4, cand_slots=96, init_kind="encoder", proj_count=4, proj_window=8),
+    # FP16 MFMA distances (exact operands for FP16-stored data), same settings
+    "fp16-learned": dict(precision="fp16", build_k=30, sample_rate=1.0, max_iters=30, delta=0.015,
+                         join_cap=4, cand_slots=96, init_kind="encoder", proj_count=4, proj_window=8),
 }
 # encoder training (reported separately, not in the timed region)
 TRAIN = dict(n=100_000, seed=100, k=15, steps=1000, batch=4096, lr=2e-3, precision="bf16")
@@ -220,7 +223,7 @@ def join_roofline(stats, n, d, p, kernel, workload):
     import numpy as np
     K = stats[-1]["build_k"]
     s_ = int(np.ceil(p["sample_rate"] * K))
-    rb = 2 if p["precision"] == "bf16" else 4
+    rb = 4 if p["precision"] == "fp32" else 2
     launches = sum(st["iters"] for st in stats)
     gathered_rows = sum(st["bytes_gathered"] for st in stats) / (d * rb)
     emitted = sum(sum(st["emitted"]) for st in stats)
@@ -263,14 +266,14 @@ def distance_error(X, Xnp, k, p, rows):
 
 
 def exact_path(X, k, reps=3):
-    """knn_exact of X among itself in both precisions: wall time per call and
+    """knn_exact of X among itself in each precision: wall time per call and
     the GEMM's algorithmic rate 2 n^2 d / time against the MFMA peak of the
-    precision (FP32 157.3 TFLOP/s, BF16 2500 TFLOP/s dense)."""
+    precision (FP32 157.3 TFLOP/s, BF16 and FP16 2500 TFLOP/s dense)."""
     import torch
     import paper_2603_04035_amd as knn
     n, d = X.shape
     out = {}
-    for prec, peak in (("fp32", 157.3), ("bf16", 2500.0)):
+    for prec, peak in (("fp32", 157.3), ("bf16", 2500.0), ("fp16", 2500.0)):
         knn.knn_exact(X, k, precision=prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -284,6 +287,45 @@ def exact_path(X, k, reps=3):
                                                       "traffic": None,
                                                       "note": "2 n^2 d flops / whole knn_exact call"}}
     return out
+
+
+def pca_quality(X, p=50, k=10, reps=3):
+    """PCA of X to p dimensions (FP64 Gram on MFMA, subspace iteration) and
+    the quality metrics of the 2-D PCA embedding (exact ranks in both
+    spaces): ms per call.  Rooflines: the Gram's n d (d + 1) FP64 flops per
+    PCA call against the FP64 MFMA peak (78.6 TFLOP/s), and the rank pass's
+    2 n^2 d FP32 flops per quality call against the FP32 MFMA peak."""
+    import torch
+    import paper_2603_04035_amd as knn
+    n, d = X.shape
+    knn.pca(X, p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        knn.pca(X, p)
+    torch.cuda.synchronize()
+    ms_pca = 1000.0 * (time.perf_counter() - t0) / reps
+    Y = knn.pca(X, 2)[0]
+    m = knn.quality(X, Y, k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        m = knn.quality(X, Y, k)
+    torch.cuda.synchronize()
+    ms_q = 1000.0 * (time.perf_counter() - t0) / reps
+    gram_tf = n * d * (d + 1) / (ms_pca * 1e-3) / 1e12
+    rank_tf = 2.0 * n * n * d / (ms_q * 1e-3) / 1e12
+    return {"pca": {"ms": round(ms_pca, 3), "p": p,
+                    "roofline": {"bound": "mfma", "achieved": round(gram_tf, 2), "peak": 78.6, "unit": "TFLOP/s",
+                                 "frac": round(gram_tf / 78.6, 4), "traffic": None,
+                                 "note": "n d (d+1) FP64 Gram flops / whole knn_pca call"}},
+            "quality": {"ms": round(ms_q, 3), "k": k, "embedding": "2-D PCA",
+                        "knn_preservation": round(m[0], 5), "trustworthiness": round(m[1], 5),
+                        "continuity": round(m[2], 5),
+                        "roofline": {"bound": "mfma", "achieved": round(rank_tf, 2), "peak": 157.3, "unit": "TFLOP/s",
+                                     "frac": round(rank_tf / 157.3, 4), "traffic": None,
+                                     "note": "2 n^2 d rank-pass flops / whole knn_quality call (it also runs two "
+                                             "exact k-NN searches)"}}}
 
 
 def fuzzy_measure(G, D, reps=3):
@@ -331,12 +373,13 @@ def run_form(X, k, form, steps, warmup, rows, config, encoder=None, Xnp=None):
     wall = time.perf_counter() - t0
     n, d = X.shape
     recall = recall_gpu(X, G, D, rows, k)
-    kern = "nnd_join_bf16_kernel" if p["precision"] == "bf16" else "nnd_join_f32_kernel"
+    kern = {"bf16": "nnd_join_mfma_kernel<1>", "fp16": "nnd_join_mfma_kernel<2>"}.get(p["precision"],
+                                                                                   "nnd_join_f32_kernel")
     last = stats[-1]
     cfg = {kk: vv for kk, vv in p.items() if kk != "encoder"}
     cfg["build_k"] = last["build_k"]
     err = None
-    if p["precision"] == "bf16" and Xnp is not None:
+    if p["precision"] != "fp32" and Xnp is not None:
         err = distance_error(X, Xnp, k, p, rows[:2000])
     progress(f"{form}: recall {recall:.5f}")
     import numpy as np
@@ -368,6 +411,8 @@ def main():
     ap.add_argument("--no-exact", action="store_true", help="skip the exact-path timing of the default line")
     ap.add_argument("--exact", action="store_true",
                     help="only time the exact path (knn_exact of the workload, both precisions)")
+    ap.add_argument("--pca-quality", action="store_true",
+                    help="only time knn_pca (p = 50) and knn_quality of the 2-D PCA embedding on --config")
     ap.add_argument("--fuzzy-only", action="store_true",
                     help="only build the FP32-form graph once and run the fuzzy graph on it 3 times (profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -403,6 +448,10 @@ def main():
         print(json.dumps({"exact_path": exact_path(X, k), "config": {"workload": CONFIGS[args.config]["desc"]},
                           "n": n, "d": d, "k": k}), flush=True)
         return
+    if args.pca_quality:
+        print(json.dumps({"pca_quality": pca_quality(X, k=min(k, 16)),
+                          "config": {"workload": CONFIGS[args.config]["desc"]}}), flush=True)
+        return
     if args.fuzzy_only:
         import paper_2603_04035_amd as knn
         G, D, _ = knn.nndescent_build(X, k, seed=0, **FORMS["fp32"])
@@ -410,11 +459,11 @@ def main():
                           "config": {"workload": CONFIGS[args.config]["desc"]}}), flush=True)
         return
     rows = datagen.sample_queries(n, args.recall_rows, seed=2)
-    forms = {"both": ["fp32", "bf16-learned"], "all": ["fp32", "bf16-learned", "bf16-random", "bf16-untrained"]}.get(
-        args.form, [args.form])
+    forms = {"both": ["fp32", "bf16-learned"],
+             "all": ["fp32", "bf16-learned", "bf16-random", "bf16-untrained", "fp16-learned"]}.get(args.form, [args.form])
     results, training = {}, None
     encoder = None
-    if "bf16-learned" in forms:
+    if any(FORMS[f].get("init_kind") == "encoder" and f != "bf16-untrained" for f in forms):
         encoder, training = train_encoder(args.config)
         progress(f"encoder trained in {training['train_s']} s")
     for f in forms:
@@ -427,12 +476,14 @@ def main():
     for r in results.values():
         r.pop("_graph", None)
     del G, D
-    exact = None
+    exact = pca_q = None
     if not args.no_exact and args.config == "gmm1m":
         Xp = torch.from_numpy(make_data("pixel70k")).to("cuda")
         exact = {"workload": CONFIGS["pixel70k"]["desc"], **exact_path(Xp, k)}
-        del Xp
         progress(f"exact path fp32 {exact['fp32']['ms']} ms, bf16 {exact['bf16']['ms']} ms")
+        pca_q = pca_quality(Xp)
+        progress(f"pca {pca_q['pca']['ms']} ms, quality {pca_q['quality']['ms']} ms")
+        del Xp
 
     copy_gbs = copy_bandwidth()
     for r in results.values():
@@ -458,6 +509,7 @@ def main():
         "encoder_training": training,
         "fuzzy_graph": fuzzy,
         "exact_path": exact,
+        "pca_quality": pca_q,
     }
     print(json.dumps(out), flush=True)
 

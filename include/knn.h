@@ -352,10 +352,10 @@ knn_status knn_proj_seed(knn_matrix X, const float* Z, int32_t m, const float* d
  * (descending) and their eigenvectors, each with its entry of largest
  * magnitude positive, and Z = (X - mu) V rounded to FP32.
  *  p       1 <= p <= min(d, 64).
- *  iters   subspace iterations (0: 200); the eigenvectors come from a
- *          min(d, max(2p, p + 16))-column subspace iteration with a final
- *          Rayleigh-Ritz step (exact when that width is d), so their error
- *          falls as (lambda_{m+1} / lambda_p)^iters.
+ *  iters   subspace iterations (0: 200); the eigenvectors come from an
+ *          m = min(d, 80, max(2p, p + 16))-column subspace iteration with a
+ *          final Rayleigh-Ritz step (exact when m = d), so their error falls
+ *          as (lambda_{m+1} / lambda_p)^iters.
  *  Z       device, n x p float.   components  device, nullable, d x p
  *          double (row-major).   eigenvalues  device, nullable, p double.
  *  mean    device, nullable, d double.

@@ -422,36 +422,6 @@ __global__ __launch_bounds__(256, 2) void exact_tile_kernel(
 // ------------------------------------------------------------ rank counts
 
 constexpr int kRankP = 16;   // probes per query row (the quality metrics' k <= 16)
-
-// Canonical FP32 squared distance of two FP32 rows computed by one lane:
-// the partial sums dist_g16 forms in 16 lanes (coordinate t into partial
-// t mod 16, in order) combined by its tree at strides 8, 4, 2, 1, which is
-// ((s0+s8)+(s4+s12)) + ((s2+s10)+(s6+s14)) + ... ; the same bits.  Partials
-// are formed one at a time so that few registers are live.
-__device__ inline float canon_part(const float* __restrict__ a, const float* __restrict__ b, int d, int g)
-{
-    float s = 0.0f;
-    for (int t = g; t < d; t += 16) {
-        const float e = a[t] - b[t];
-        s = fmaf(e, e, s);
-    }
-    return s;
-}
-
-__device__ __attribute__((noinline)) float canon_dist(const float* __restrict__ a, const float* __restrict__ b, int d)
-{
-    float q[4];
-#pragma unroll
-    for (int o = 0; o < 4; ++o) {
-        // o = 0, 1, 2, 3 -> the quarter rooted at partials 0, 2, 1, 3
-        const int g = o == 1 ? 2 : (o == 2 ? 1 : o);
-        const float x = canon_part(a, b, d, g) + canon_part(a, b, d, g + 8);
-        const float y = canon_part(a, b, d, g + 4) + canon_part(a, b, d, g + 12);
-        q[o] = x + y;
-    }
-    return (q[0] + q[1]) + (q[2] + q[3]);
-}
-
 // For every query row q and each of its probes (keys (canonical d2, index),
 // ascending; kEmptyCand pads), counts[q][p] = the number of reference rows
 // m != self(q) whose key (canonical FP32 d2(q, m), m) is below the probe's
@@ -461,7 +431,12 @@ __device__ __attribute__((noinline)) float canon_dist(const float* __restrict__ 
 // probe of its query into a per-row histogram over the probe boundaries (in
 // LDS), so counts are prefix sums.  A GEMM distance within the slack of a
 // probe's distance (the GEMM error bound plus the canonical distance's) is
-// recomputed in the canonical precision by its lane to decide.
+// undecided: the pair is queued in LDS (the tile buffers, free between the
+// tile's MFMAs and the next tile) and, after every two 32-column blocks,
+// the queued pairs get their canonical FP32 distances from 16-lane groups
+// (dist_g16, the canonical sums) and enter the histogram.  Two blocks queue
+// at most 128 x 64 = 8,192 pairs, within the buffers' 9,216 words, so no
+// pair is ever decided any other way.
 __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
     const float* __restrict__ Qs, const float* __restrict__ qn, int64_t nq, const float* __restrict__ Rs,
     const float* __restrict__ rn, int64_t nr, int ldp, int d, int self_mode, int64_t self_base,
@@ -470,14 +445,21 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
 {
     using C = TileCfg<KNN_F32>;
     constexpr int LROW = C::LROW, KC = C::KC, PER = KC / 2;
-    __shared__ __attribute__((aligned(16))) float As[kTileRows * LROW];
-    __shared__ __attribute__((aligned(16))) float Bs[kTileRows * LROW];
+    __shared__ __attribute__((aligned(16))) float ABs[2 * kTileRows * LROW];
+    float* As = ABs;
+    float* Bs = ABs + kTileRows * LROW;
+    // undecided pairs, between a tile's MFMAs and the next tile's staging:
+    // column in tile << 17 | query row << 10 | a << 5 | b
+    uint32_t* queue = (uint32_t*)ABs;
+    constexpr int kQueueCap = 2 * kTileRows * LROW;
+    static_assert(kQueueCap >= kTileRows * 64, "two 32-column blocks of undecided pairs fit the tile buffers");
     __shared__ float srn[kTileRows];
     __shared__ float sqn[kTileRows];
     __shared__ int32_t sself[kTileRows];
     __shared__ float sgate[kTileRows], sslack[kTileRows];
     __shared__ __attribute__((aligned(16))) uint64_t skey[kTileRows * kRankP];
     __shared__ uint32_t hist[kTileRows * (kRankP + 1)];
+    __shared__ uint32_t qcount[2];   // queue fill, one per half of a tile
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, h = lane >> 5, c = lane & 31;
     const int64_t q0 = (int64_t)blockIdx.x * kTileRows;
@@ -487,6 +469,7 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
         skey[e] = qr < nq ? probes[qr * kRankP + e % kRankP] : kEmptyCand;
     }
     for (int e = tid; e < kTileRows * (kRankP + 1); e += 256) hist[e] = 0u;
+    if (tid < 2) qcount[tid] = 0u;
     __syncthreads();
     if (tid < kTileRows) {
         const int64_t qr = q0 + tid;
@@ -516,42 +499,68 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
         f32x16 acc[4];
         tile_gemm<KNN_F32, false>(nb0, nb1, nb2, nb3, na0, na1, na2, na3, nrn, acc, As, Bs, srn, Qe, Re, qrow, rt,
                                 nr, ldp, rn, tid, w, h, c);
-        for (int blk = 0; blk < 4; ++blk) {
-            const f32x16 cur = blk == 0 ? acc[0] : (blk == 1 ? acc[1] : (blk == 2 ? acc[2] : acc[3]));
-            const float rnj = srn[blk * 32 + c];
-            const int64_t j = rt + blk * 32 + c;
+        __syncthreads();   // every wave's MFMA operands are read: the tile buffers hold the queue
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int lr = w * 32 + mfma_row(v, h);
-                float d2 = fmaf(-2.0f, cur[v], sqn[lr] + rnj);
-                d2 = d2 > 0.0f ? d2 : 0.0f;
-                const bool pass = d2 <= sgate[lr] && j < nr && (int32_t)j != sself[lr];
-                if (!ballot(pass)) continue;
-                if (pass) {
-                    const float sl = sslack[lr];
-                    const uint64_t* pk = skey + lr * kRankP;
-                    int a = 0, b = 0;   // probes with thr <= d2 + sl, with thr < d2 - sl
+        for (int half = 0; half < 2; ++half) {
 #pragma unroll
-                    for (int p = 0; p < kRankP; ++p) {
-                        const uint64_t key = pk[p];
-                        const float thr = key == kEmptyCand ? __builtin_inff() : key_d2(key);
-                        a += thr <= d2 + sl ? 1 : 0;
-                        b += thr < d2 - sl ? 1 : 0;
+            for (int bb = 0; bb < 2; ++bb) {
+                const int blk = 2 * half + bb;
+                const f32x16 cur = acc[blk];
+                const float rnj = srn[blk * 32 + c];
+                const int64_t j = rt + blk * 32 + c;
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int lr = w * 32 + mfma_row(v, h);
+                    float d2 = fmaf(-2.0f, cur[v], sqn[lr] + rnj);
+                    d2 = d2 > 0.0f ? d2 : 0.0f;
+                    const bool pass = d2 <= sgate[lr] && j < nr && (int32_t)j != sself[lr];
+                    if (!ballot(pass)) continue;
+                    if (pass) {
+                        const float sl = sslack[lr];
+                        const uint64_t* pk = skey + lr * kRankP;
+                        int a = 0, b = 0;   // probes with thr <= d2 + sl, with thr < d2 - sl
+#pragma unroll
+                        for (int p = 0; p < kRankP; ++p) {
+                            const uint64_t key = pk[p];
+                            const float thr = key == kEmptyCand ? __builtin_inff() : key_d2(key);
+                            a += thr <= d2 + sl ? 1 : 0;
+                            b += thr < d2 - sl ? 1 : 0;
+                        }
+                        // probes a.. have this row below them; b..a-1 are undecided
+                        if (b == a && a < kRankP) atomicAdd(&hist[lr * (kRankP + 1) + a], 1u);
+                        if (b < a) {
+                            const uint32_t slot = atomicAdd(&qcount[half], 1u);
+                            queue[slot] = ((uint32_t)(blk * 32 + c) << 17) | ((uint32_t)lr << 10) |
+                                          ((uint32_t)a << 5) | (uint32_t)b;
+                        }
                     }
-                    int at = a;   // probes from `at` on have this row below them
-                    if (b < a) {
-                        const float dc = canon_dist(Qs + (q0 + lr) * (int64_t)ldp, Rs + j * (int64_t)ldp, d);
-                        const uint64_t km = make_key(dc, (uint32_t)j);
-                        for (int p = b; p < a; ++p) {
-                            if (km < pk[p]) {
-                                at = p;
-                                break;
-                            }
+                }
+            }
+            __syncthreads();
+            const int nqd = (int)qcount[half];
+            for (int base = 0; base < nqd; base += 16) {
+                const int e = base + (tid >> 4);
+                const bool act = e < nqd;
+                const uint32_t qe = act ? queue[e] : 0u;
+                const int64_t jj = rt + (int64_t)(qe >> 17);
+                const int lr = (int)((qe >> 10) & 127), a = (int)((qe >> 5) & 31), b = (int)(qe & 31);
+                const float dc = dist_g16<KNN_F32>(Qs, (q0 + lr) * (int64_t)ldp, Rs, (act ? jj : 0) * (int64_t)ldp, d,
+                                                   act);
+                if (act && (tid & 15) == 0) {
+                    const uint64_t km = make_key(dc, (uint32_t)jj);
+                    const uint64_t* pk = skey + lr * kRankP;
+                    int at = a;
+                    for (int p = b; p < a; ++p) {
+                        if (km < pk[p]) {
+                            at = p;
+                            break;
                         }
                     }
                     if (at < kRankP) atomicAdd(&hist[lr * (kRankP + 1) + at], 1u);
                 }
             }
+            __syncthreads();   // the queue is read; the next half (or tile) may overwrite it
+            if (tid == 0) qcount[half] = 0u;
         }
     }
     __syncthreads();
@@ -562,6 +571,71 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
         uint32_t cnt = 0;
         for (int a = 0; a <= p; ++a) cnt += hist[lr * (kRankP + 1) + a];
         counts[qr * kRankP + p] = cnt;
+    }
+}
+
+// The same counts for a low-dimensional space (d <= kRankDirectD, e.g. a 2-D
+// embedding), by direct canonical FP32 distances: there the norm
+// expansion's error bound is wider than neighbour distances, so a GEMM pass
+// would recheck nearly every pair.  Thread = query row; its probe keys and
+// counts sit in registers; reference rows stream through LDS in tiles of
+// 256.  Exact in the canonical precision, no ambiguity.
+constexpr int kRankDirectD = 16;
+
+__global__ __launch_bounds__(256) void rank_direct_kernel(const float* __restrict__ Xs, int64_t n, int ldp, int d,
+                                                          const uint64_t* __restrict__ probes,
+                                                          uint32_t* __restrict__ counts)
+{
+    __shared__ float tile[256][kRankDirectD + 1];
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool live = q < n;
+    float xq[kRankDirectD];
+#pragma unroll
+    for (int t = 0; t < kRankDirectD; ++t) xq[t] = live && t < d ? Xs[q * ldp + t] : 0.0f;
+    uint64_t pk[kRankP];
+    uint32_t cnt[kRankP];
+    float mx = -1.0f;
+#pragma unroll
+    for (int p = 0; p < kRankP; ++p) {
+        pk[p] = live ? probes[q * kRankP + p] : kEmptyCand;
+        cnt[p] = 0u;
+        if (pk[p] != kEmptyCand) mx = key_d2(pk[p]);
+    }
+    for (int64_t r0 = 0; r0 < n; r0 += 256) {
+        __syncthreads();
+        {
+            const int64_t r = r0 + threadIdx.x;
+#pragma unroll
+            for (int t = 0; t < kRankDirectD; ++t) tile[threadIdx.x][t] = r < n && t < d ? Xs[r * ldp + t] : 0.0f;
+        }
+        __syncthreads();
+        const int nr = (int)(n - r0 < 256 ? n - r0 : 256);
+        for (int jj = 0; jj < nr; ++jj) {
+            // canonical order: partial t mod 16 holds coordinate t (d <= 16),
+            // then the tree at strides 8, 4, 2, 1
+            float s[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const float e = xq[t] - tile[jj][t];
+                s[t] = t < d ? e * e : 0.0f;
+            }
+#pragma unroll
+            for (int j = 8; j > 0; j >>= 1) {
+#pragma unroll
+                for (int g = 0; g < j; ++g) s[g] = s[g] + s[g + j];
+            }
+            const float d2 = s[0];
+            const int64_t m = r0 + jj;
+            if (d2 <= mx && m != q) {
+                const uint64_t km = make_key(d2, (uint32_t)m);
+#pragma unroll
+                for (int p = 0; p < kRankP; ++p) cnt[p] += km < pk[p] ? 1u : 0u;
+            }
+        }
+    }
+    if (live) {
+#pragma unroll
+        for (int p = 0; p < kRankP; ++p) counts[q * kRankP + p] = cnt[p];
     }
 }
 
@@ -1017,10 +1091,17 @@ static knn_status quality_impl(const knn_matrix& X, const knn_matrix& Y, int k, 
     KNN_HIP(hipGetLastError());
     const float u = 5.9604645e-08f;
     const dim3 grid((unsigned)ceil_div(n, kTileRows));
-    rank_tile_kernel<<<grid, 256, 0, st>>>((const float*)Xs, xn, n, (const float*)Xs, xn, n, ldx, X.d, 1, 0, pu,
-                                           small, (float)(X.d + 3) * u * 1.01f, (float)(X.d / 16 + 8) * u, cu);
-    rank_tile_kernel<<<grid, 256, 0, st>>>((const float*)Ys, yn, n, (const float*)Ys, yn, n, ldy, Y.d, 1, 0, pv,
-                                           small + 1, (float)(Y.d + 3) * u * 1.01f, (float)(Y.d / 16 + 8) * u, cv);
+    if (X.d <= kRankDirectD)
+        rank_direct_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>((const float*)Xs, n, ldx, X.d, pu, cu);
+    else
+        rank_tile_kernel<<<grid, 256, 0, st>>>((const float*)Xs, xn, n, (const float*)Xs, xn, n, ldx, X.d, 1, 0, pu,
+                                               small, (float)(X.d + 3) * u * 1.01f, (float)(X.d / 16 + 8) * u, cu);
+    if (Y.d <= kRankDirectD)
+        rank_direct_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>((const float*)Ys, n, ldy, Y.d, pv, cv);
+    else
+        rank_tile_kernel<<<grid, 256, 0, st>>>((const float*)Ys, yn, n, (const float*)Ys, yn, n, ldy, Y.d, 1, 0, pv,
+                                               small + 1, (float)(Y.d + 3) * u * 1.01f, (float)(Y.d / 16 + 8) * u,
+                                               cv);
     KNN_HIP(hipGetLastError());
     unsigned long long* tot = (unsigned long long*)(small + 2);
     quality_reduce_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(n, k, pu, cu, pv, cv, hits, trust_out,

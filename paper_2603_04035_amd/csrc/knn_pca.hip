@@ -8,7 +8,7 @@
 //               (rows staged in LDS as FP32, centred as they become
 //               operands), partials summed in chunk order: no atomics, so
 //               the result does not depend on scheduling;
-//  3. subspace: m = min(d, max(2p, p + 16)) columns V (seeded, hashed
+//  3. subspace: m = min(d, 80, max(2p, p + 16)) columns V (seeded, hashed
 //               values) iterate V <- orth(C V), orthonormalised by
 //               Cholesky-QR (twice: the second pass restores the
 //               orthogonality the first loses to conditioning); then
@@ -27,7 +27,7 @@
 namespace knn {
 
 constexpr int kPcaMaxP = 64;      // components
-constexpr int kPcaMaxM = 128;     // subspace width
+constexpr int kPcaMaxM = 80;      // subspace width (an m x m double matrix fits in LDS)
 constexpr int kPcaChunk = 4096;   // rows per Gram partial
 constexpr int kPcaTile = 64;      // Gram tile edge
 
@@ -160,17 +160,29 @@ __global__ __launch_bounds__(256) void pca_identity_kernel(int d, int m, double*
     V[e] = (e / d == e % d) ? 1.0 : 0.0;
 }
 
-// W[j][a] = sum_b C[b][a] V[j][b] (C symmetric: lanes over a read rows of C).
+// W[j][a] = sum_b C[b][a] V[j][b] (C symmetric: lanes over a read rows of C,
+// coalesced), eight columns j per thread so that each C element loaded
+// serves eight products.
+constexpr int kPcaCols = 8;
+
 __global__ __launch_bounds__(256) void pca_cv_kernel(const double* __restrict__ C, const double* __restrict__ V,
                                                      int d, int m, double* __restrict__ W)
 {
     const int a = blockIdx.x * 256 + threadIdx.x;
-    const int j = blockIdx.y;
+    const int j0 = blockIdx.y * kPcaCols;
     if (a >= d) return;
-    const double* v = V + (int64_t)j * d;
-    double s = 0.0;
-    for (int b = 0; b < d; ++b) s = fma(C[(int64_t)b * d + a], v[b], s);
-    W[(int64_t)j * d + a] = s;
+    double s[kPcaCols];
+#pragma unroll
+    for (int q = 0; q < kPcaCols; ++q) s[q] = 0.0;
+    for (int b = 0; b < d; ++b) {
+        const double c = C[(int64_t)b * d + a];
+#pragma unroll
+        for (int q = 0; q < kPcaCols; ++q)
+            if (j0 + q < m) s[q] = fma(c, V[(int64_t)(j0 + q) * d + b], s[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < kPcaCols; ++q)
+        if (j0 + q < m) W[(int64_t)(j0 + q) * d + a] = s[q];
 }
 
 // S[i][j] = <W_i, W_j> over d (i <= j; mirrored), one workgroup per pair,
@@ -197,59 +209,85 @@ __global__ __launch_bounds__(256) void pca_gram_small_kernel(const double* __res
     }
 }
 
-// Cholesky factor S = R^T R (R upper triangular, in place over S's upper
-// triangle; one workgroup, column by column).  A non-positive pivot (a rank-
-// deficient W) is replaced by 1 and flagged, which leaves that column as it
-// is rather than dividing by zero.
-__global__ __launch_bounds__(256) void pca_chol_kernel(double* __restrict__ S, int m, unsigned* __restrict__ bad)
+// Cholesky factor S = R^T R (R upper triangular) of the m x m Gram matrix
+// in LDS, one workgroup, column by column, then its inverse Ri = R^{-1}
+// (upper triangular, one column per thread by back substitution); Ri goes
+// to global memory.  A non-positive pivot (a rank-deficient W) is replaced
+// by 1 and flagged, which keeps the factor finite.
+__global__ __launch_bounds__(256) void pca_chol_inv_kernel(const double* __restrict__ Sg, int m,
+                                                           double* __restrict__ Ri, unsigned* __restrict__ bad)
 {
+    __shared__ double S[kPcaMaxM * kPcaMaxM];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < m * m; e += 256) S[e] = Sg[e];
     for (int k = 0; k < m; ++k) {
         __syncthreads();
         double piv = S[k * m + k];
         if (!(piv > 0.0)) {
-            if (threadIdx.x == 0) atomicOr(bad, 1u);
+            if (tid == 0) atomicOr(bad, 1u);
             piv = 1.0;
         }
         const double r = sqrt(piv);
         __syncthreads();
-        // row k of R: R[k][j] = S[k][j] / r for j > k
-        for (int j = k + 1 + (int)threadIdx.x; j < m; j += 256) S[k * m + j] /= r;
+        for (int j = k + 1 + tid; j < m; j += 256) S[k * m + j] /= r;
+        if (tid == 0) S[k * m + k] = r;
         __syncthreads();
-        if (threadIdx.x == 0) S[k * m + k] = r;
-        // trailing update S[i][j] -= R[k][i] R[k][j], i, j > k (upper part)
-        for (int e = threadIdx.x; e < (m - k - 1) * (m - k - 1); e += 256) {
-            const int i = k + 1 + e / (m - k - 1), j = k + 1 + e % (m - k - 1);
+        const int w = m - k - 1;
+        for (int e = tid; e < w * w; e += 256) {
+            const int i = k + 1 + e / w, j = k + 1 + e % w;
             if (i <= j) S[i * m + j] -= S[k * m + i] * S[k * m + j];
+        }
+    }
+    __syncthreads();
+    // column j of R^{-1}: R x = e_j, rows j, j-1, ..., 0
+    for (int j = tid; j < m; j += 256) {
+        for (int i = m - 1; i > j; --i) Ri[i * m + j] = 0.0;
+        Ri[j * m + j] = 1.0 / S[j * m + j];
+        for (int i = j - 1; i >= 0; --i) {
+            double t = 0.0;
+            for (int l = i + 1; l <= j; ++l) t = fma(S[i * m + l], Ri[l * m + j], t);
+            Ri[i * m + j] = -t / S[i * m + i];
         }
     }
 }
 
-// V = W R^{-1}: row a of V (over the m columns) by forward substitution,
-// V[j][a] = (W[j][a] - sum_{i<j} V[i][a] R[i][j]) / R[j][j].
-__global__ __launch_bounds__(256) void pca_trsm_kernel(const double* __restrict__ W, const double* __restrict__ R,
-                                                       int d, int m, double* __restrict__ V)
+// V[j][a] = sum_{i <= j} W[i][a] Ri[i][j] (= W R^{-1}, eight columns per
+// thread).
+__global__ __launch_bounds__(256) void pca_apply_kernel(const double* __restrict__ W, const double* __restrict__ Ri,
+                                                        int d, int m, double* __restrict__ V)
 {
     const int a = blockIdx.x * 256 + threadIdx.x;
+    const int j0 = blockIdx.y * kPcaCols;
     if (a >= d) return;
-    for (int j = 0; j < m; ++j) {
-        double s = W[(int64_t)j * d + a];
-        for (int i = 0; i < j; ++i) s -= V[(int64_t)i * d + a] * R[i * m + j];   // this thread's earlier results
-        V[(int64_t)j * d + a] = s / R[j * m + j];
+    double s[kPcaCols];
+#pragma unroll
+    for (int q = 0; q < kPcaCols; ++q) s[q] = 0.0;
+    const int jmax = j0 + kPcaCols < m ? j0 + kPcaCols : m;
+    for (int i = 0; i < jmax; ++i) {
+        const double w = W[(int64_t)i * d + a];
+#pragma unroll
+        for (int q = 0; q < kPcaCols; ++q)
+            if (j0 + q < m && i <= j0 + q) s[q] = fma(w, Ri[i * m + j0 + q], s[q]);
     }
+#pragma unroll
+    for (int q = 0; q < kPcaCols; ++q)
+        if (j0 + q < m) V[(int64_t)(j0 + q) * d + a] = s[q];
 }
 
-// Cyclic Jacobi on the symmetric m x m matrix H (global, row-major), one
-// workgroup: each sweep runs m - 1 rounds of the round-robin tournament
+// Cyclic Jacobi on the symmetric m x m matrix H (row-major, copied into LDS
+// and back), one workgroup: each sweep runs m - 1 rounds of the round-robin tournament
 // (m even; an odd m plays a bye), every round rotating its m/2 disjoint
 // pairs (p, q) so that H[p][q] becomes 0: rows then columns, with E
 // accumulating the rotations (E starts as the identity).  Sweeps stop when
 // the off-diagonal mass falls below 1e-30 of the total, or after 40.
-__global__ __launch_bounds__(256) void pca_jacobi_kernel(double* __restrict__ H, double* __restrict__ E, int m)
+__global__ __launch_bounds__(256) void pca_jacobi_kernel(double* __restrict__ Hg, double* __restrict__ E, int m)
 {
+    __shared__ double H[kPcaMaxM * kPcaMaxM];
     __shared__ double cs[kPcaMaxM / 2], sn[kPcaMaxM / 2];
     __shared__ int pp[kPcaMaxM / 2], qq[kPcaMaxM / 2];
     __shared__ double red[256];
     const int tid = threadIdx.x;
+    for (int e = tid; e < m * m; e += 256) H[e] = Hg[e];
     const int mm = m + (m & 1);   // players, with a bye for odd m
     for (int e = tid; e < m * m; e += 256) E[e] = (e / m == e % m) ? 1.0 : 0.0;
     for (int sweep = 0; sweep < 40; ++sweep) {
@@ -326,6 +364,8 @@ __global__ __launch_bounds__(256) void pca_jacobi_kernel(double* __restrict__ H,
             __syncthreads();
         }
     }
+    __syncthreads();
+    for (int e = tid; e < m * m; e += 256) Hg[e] = H[e];
 }
 
 // The p largest Ritz pairs: eigenvalues from diag(H) sorted descending
@@ -473,14 +513,15 @@ extern "C" knn_status knn_pca(knn_matrix X, int32_t p, int32_t iters, float* Z, 
         } else {
             pca_init_kernel<<<(unsigned)ceil_div((int64_t)d * m, 256), 256, 0, st>>>(d, m, 0x5CA1AB1Eull, W);
         }
+        const dim3 gcols((unsigned)ceil_div(d, 256), (unsigned)ceil_div(m, kPcaCols));
         auto orthonormalise = [&](double* src, double* dst) -> knn_status {
             // two Cholesky-QR passes: src -> dst -> (src as scratch) -> dst
             double* in = src;
             for (int pass = 0; pass < 2; ++pass) {
                 pca_gram_small_kernel<<<dim3((unsigned)m, (unsigned)m), 256, 0, st>>>(in, in, d, m, S);
-                pca_chol_kernel<<<1, 256, 0, st>>>(S, m, bad);
+                pca_chol_inv_kernel<<<1, 256, 0, st>>>(S, m, E, bad);
                 double* out = pass == 0 ? dst : src;
-                pca_trsm_kernel<<<(unsigned)ceil_div(d, 256), 256, 0, st>>>(in, S, d, m, out);
+                pca_apply_kernel<<<gcols, 256, 0, st>>>(in, E, d, m, out);
                 in = out;
             }
             if (in != dst) KNN_HIP(hipMemcpyAsync(dst, in, (size_t)d * m * 8, hipMemcpyDeviceToDevice, st));
@@ -490,12 +531,13 @@ extern "C" knn_status knn_pca(knn_matrix X, int32_t p, int32_t iters, float* Z, 
         if (m < d) {
             if ((r = orthonormalise(W, V)) != KNN_OK) return r;
             for (int it = 0; it < T; ++it) {
-                pca_cv_kernel<<<dim3((unsigned)ceil_div(d, 256), (unsigned)m), 256, 0, st>>>(C, V, d, m, W);
+                pca_cv_kernel<<<gcols, 256, 0, st>>>(C, V, d, m, W);
                 if ((r = orthonormalise(W, V)) != KNN_OK) return r;
             }
         }
         // Rayleigh-Ritz: H = V^T C V
-        pca_cv_kernel<<<dim3((unsigned)ceil_div(d, 256), (unsigned)m), 256, 0, st>>>(C, V, d, m, W);
+        pca_cv_kernel<<<dim3((unsigned)ceil_div(d, 256), (unsigned)ceil_div(m, kPcaCols)), 256, 0, st>>>(C, V, d, m,
+                                                                                                      W);
         pca_gram_small_kernel<<<dim3((unsigned)m, (unsigned)m), 256, 0, st>>>(W, V, d, m, H);
         pca_jacobi_kernel<<<1, 256, 0, st>>>(H, E, m);
         pca_ritz_kernel<<<1, 256, 0, st>>>(H, E, V, d, m, p, U, lam);

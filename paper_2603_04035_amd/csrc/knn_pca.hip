@@ -9,9 +9,10 @@
 //               operands), partials summed in chunk order: no atomics, so
 //               the result does not depend on scheduling;
 //  3. subspace: m = min(d, 80, max(2p, p + 16)) columns V (seeded, hashed
-//               values) iterate V <- orth(C V), orthonormalised by
-//               Cholesky-QR (twice: the second pass restores the
-//               orthogonality the first loses to conditioning); then
+//               values) iterate V <- orth(C V) (C V on
+//               v_mfma_f64_16x16x4_f64), orthonormalised by one Cholesky-QR
+//               pass per iteration and a second after the last (it restores
+//               the orthogonality the first loses to conditioning); then
 //               Rayleigh-Ritz: H = V^T C V, whose eigenpairs come from cyclic
 //               Jacobi rotations (one workgroup, round-robin pairing), and
 //               the p largest Ritz pairs are kept; each eigenvector's entry
@@ -20,6 +21,7 @@
 // When m = d the Ritz pairs are the exact eigenpairs of C.
 #include <math.h>
 
+#include <utility>
 #include <vector>
 
 #include "knn_common.hpp"
@@ -28,14 +30,16 @@ namespace knn {
 
 constexpr int kPcaMaxP = 64;      // components
 constexpr int kPcaMaxM = 80;      // subspace width (an m x m double matrix fits in LDS)
+static_assert(kPcaMaxM % 16 == 0, "LDS kernels stride columns by 16");
 constexpr int kPcaChunk = 4096;   // rows per Gram partial
+constexpr int kPcaSumChunk = 512; // rows per column-sum partial
 constexpr int kPcaTile = 64;      // Gram tile edge
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ mean
 
-// part[c][t] = sum of column t over rows [c * kPcaChunk, ...), in row order
+// part[c][t] = sum of column t over rows [c * kPcaSumChunk, ...), in row order
 // (thread t of a 256-wide column block walks the chunk's rows).
 template <int DT>
 __global__ __launch_bounds__(256) void pca_colsum_kernel(const void* __restrict__ X, int64_t n, int64_t ld, int d,
@@ -44,7 +48,7 @@ __global__ __launch_bounds__(256) void pca_colsum_kernel(const void* __restrict_
     const int t = blockIdx.x * 256 + threadIdx.x;
     const int64_t c = blockIdx.y;
     if (t >= d) return;
-    const int64_t r0 = c * kPcaChunk, r1 = r0 + kPcaChunk < n ? r0 + kPcaChunk : n;
+    const int64_t r0 = c * kPcaSumChunk, r1 = r0 + kPcaSumChunk < n ? r0 + kPcaSumChunk : n;
     double s = 0.0;
     for (int64_t r = r0; r < r1; ++r) s += (double)elem<DT>::ld(X, r * ld + t);
     part[c * d + t] = s;
@@ -85,31 +89,48 @@ __global__ __launch_bounds__(256) void pca_gram_kernel(const void* __restrict__ 
         sma[tid] = a0 + tid < d ? mu[a0 + tid] : 0.0;
         smb[tid] = b0 + tid < d ? mu[b0 + tid] : 0.0;
     }
+    // staging: thread (rq, cc) holds rows rq, rq + 4, ..., rq + 60 of column
+    // cc of both slices; the next 64 rows are loaded while this step's
+    // MFMAs run (zeros past d and past the chunk)
+    const int cc = tid & 63, rq = tid >> 6;
+    const bool acol = a0 + cc < d, bcol = b0 + cc < d;
+    float pa[16], pb[16];
+    auto fetch = [&](int64_t rs) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int64_t row = rs + rq + 4 * u;
+            const bool ok = row < r1;
+            pa[u] = ok && acol ? elem<DT>::ld(X, row * ld + a0 + cc) : 0.0f;
+            pb[u] = ok && bcol ? elem<DT>::ld(X, row * ld + b0 + cc) : 0.0f;
+        }
+    };
+    fetch(r0);
     f64x4 acc[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const int ia = 16 * w + (lane & 15);
     for (int64_t rs = r0; rs < r1; rs += 64) {
         __syncthreads();
-        // stage 64 rows x 64 columns of each slice (zeros past d and past the chunk)
-        for (int e = tid; e < 64 * kPcaTile; e += 256) {
-            const int rr = e / kPcaTile, cc = e % kPcaTile;
-            const int64_t row = rs + rr;
-            const bool ok = row < r1;
-            sa[rr][cc] = ok && a0 + cc < d ? elem<DT>::ld(X, row * ld + a0 + cc) : 0.0f;
-            sb[rr][cc] = ok && b0 + cc < d ? elem<DT>::ld(X, row * ld + b0 + cc) : 0.0f;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            sa[rq + 4 * u][cc] = pa[u];
+            sb[rq + 4 * u][cc] = pb[u];
         }
         __syncthreads();
+        if (rs + 64 < r1) fetch(rs + 64);
         const int nr = (int)(r1 - rs < 64 ? r1 - rs : 64);
-        for (int k0 = 0; k0 < nr; k0 += 4) {
+#pragma unroll 4
+        for (int k0 = 0; k0 < 64; k0 += 4) {
             const int kk = k0 + (lane >> 4);
             const bool kv = kk < nr;
-            const int ia = 16 * w + (lane & 15);
             // centred operands; padded rows and columns contribute 0
-            const double av = kv && a0 + ia < d ? (double)sa[kk][ia] - sma[ia] : 0.0;
+            const float xa = sa[kk][ia];
+            const double av = kv ? (double)xa - sma[ia] : 0.0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int jb = 16 * j + (lane & 15);
-                const double bv = kv && b0 + jb < d ? (double)sb[kk][jb] - smb[jb] : 0.0;
+                const float xb = sb[kk][jb];
+                const double bv = kv ? (double)xb - smb[jb] : 0.0;
                 acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[j], 0, 0, 0);
             }
         }
@@ -160,29 +181,52 @@ __global__ __launch_bounds__(256) void pca_identity_kernel(int d, int m, double*
     V[e] = (e / d == e % d) ? 1.0 : 0.0;
 }
 
-// W[j][a] = sum_b C[b][a] V[j][b] (C symmetric: lanes over a read rows of C,
-// coalesced), eight columns j per thread so that each C element loaded
-// serves eight products.
-constexpr int kPcaCols = 8;
-
-__global__ __launch_bounds__(256) void pca_cv_kernel(const double* __restrict__ C, const double* __restrict__ V,
-                                                     int d, int m, double* __restrict__ W)
+// W = C V on v_mfma_f64_16x16x4_f64, one workgroup per 16 x 16 block of W
+// (rows a of C, columns j of V).  K runs in blocks of 16, block b taken by
+// wave b % 4 (four blocks per round, loads first): lane l (r = l % 16, g = l / 16) holds C[a0 + r][k0 + 4g ..
+// +3] and V[j0 + r][k0 + 4g .. +3], and step s multiplies the k = k0 + 4g +
+// s slice, so every k enters once; entries past d or m are zero.  The four
+// waves' sums are added in wave order.  Accumulator item i of lane l is
+// W[j0 + r][a0 + g + 4i].
+__global__ __launch_bounds__(256) void pca_cv_kernel(const double* __restrict__ C, const double* __restrict__ V, int d,
+                                                     int m, double* __restrict__ W)
 {
-    const int a = blockIdx.x * 256 + threadIdx.x;
-    const int j0 = blockIdx.y * kPcaCols;
-    if (a >= d) return;
-    double s[kPcaCols];
+    __shared__ double part[3][64][4];
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, r = l & 15, g = l >> 4;
+    const int a0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+    const bool aok = a0 + r < d, jok = j0 + r < m;
+    const double* crow = C + (int64_t)(aok ? a0 + r : 0) * d;
+    const double* vcol = V + (int64_t)(jok ? j0 + r : 0) * d;
+    f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+    // four of the wave's K blocks per round, all their loads issued first
+    for (int kb = 16 * wv; kb < d; kb += 256) {
+        double ca[4][4], vb[4][4];
 #pragma unroll
-    for (int q = 0; q < kPcaCols; ++q) s[q] = 0.0;
-    for (int b = 0; b < d; ++b) {
-        const double c = C[(int64_t)b * d + a];
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int q = 0; q < kPcaCols; ++q)
-            if (j0 + q < m) s[q] = fma(c, V[(int64_t)(j0 + q) * d + b], s[q]);
+            for (int s = 0; s < 4; ++s) {
+                const int k = kb + 64 * b + 4 * g + s;
+                ca[b][s] = aok && k < d ? crow[k] : 0.0;
+                vb[b][s] = jok && k < d ? vcol[k] : 0.0;
+            }
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[b][s], vb[b][s], acc, 0, 0, 0);
     }
+    if (wv > 0) {
 #pragma unroll
-    for (int q = 0; q < kPcaCols; ++q)
-        if (j0 + q < m) W[(int64_t)(j0 + q) * d + a] = s[q];
+        for (int i = 0; i < 4; ++i) part[wv - 1][l][i] = acc[i];
+    }
+    __syncthreads();
+    if (wv == 0 && jok) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double v = ((acc[i] + part[0][l][i]) + part[1][l][i]) + part[2][l][i];
+            const int a = a0 + g + 4 * i;
+            if (a < d) W[(int64_t)(j0 + r) * d + a] = v;
+        }
+    }
 }
 
 // S[i][j] = <W_i, W_j> over d (i <= j; mirrored), one workgroup per pair,
@@ -209,85 +253,124 @@ __global__ __launch_bounds__(256) void pca_gram_small_kernel(const double* __res
     }
 }
 
-// Cholesky factor S = R^T R (R upper triangular) of the m x m Gram matrix
-// in LDS, one workgroup, column by column, then its inverse Ri = R^{-1}
-// (upper triangular, one column per thread by back substitution); Ri goes
-// to global memory.  A non-positive pivot (a rank-deficient W) is replaced
-// by 1 and flagged, which keeps the factor finite.
-__global__ __launch_bounds__(256) void pca_chol_inv_kernel(const double* __restrict__ Sg, int m,
-                                                           double* __restrict__ Ri, unsigned* __restrict__ bad)
+// One Cholesky-QR pass: V = W R^{-1}, where S = W^T W = R^T R (R upper
+// triangular).  Every workgroup factors S in LDS, the same operations in
+// each, so all hold the same factor; then thread a forms row a of W R^{-1}
+// for the workgroup's eight columns.  The factor comes from symmetric
+// elimination on [S | I] (one barrier per step): step k subtracts
+// S[k][i] / S[k][k] times row k from each row i > k, on the trailing upper
+// triangle of S and on the unit lower triangular M beside it, so that at
+// the end M S = D L^T with S = L D L^T (L unit lower triangular, D the
+// pivots) and M = L^{-1}.  Then R = D^{1/2} L^T and R^{-1}[i][j] = M[j][i] /
+// sqrt(D[j]): no triangular solve is needed.  M's strict lower triangle sits
+// in the lower half of the LDS copy of S, which the upper-triangle
+// elimination never reads.  A non-positive pivot (W of lower rank than m) is
+// replaced by 1 and flagged, which keeps the factor finite.
+constexpr int kPcaCols = 8;
+
+__global__ __launch_bounds__(256) void pca_cholqr_kernel(const double* __restrict__ Sg, const double* __restrict__ W,
+                                                         int d, int m, double* __restrict__ V,
+                                                         unsigned* __restrict__ bad)
 {
-    __shared__ double S[kPcaMaxM * kPcaMaxM];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < m * m; e += 256) S[e] = Sg[e];
+    __shared__ double S[kPcaMaxM * kPcaMaxM];   // upper: S being eliminated; strict lower: M
+    __shared__ double rinv[kPcaMaxM];
+    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    {
+        // all of this thread's loads are issued before the first store
+        constexpr int NL = (kPcaMaxM * kPcaMaxM + 255) / 256;
+        double tmp[NL];
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int e = tid + 256 * u;
+            tmp[u] = e < m * m ? Sg[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int e = tid + 256 * u;
+            if (e < m * m) S[e] = (e % m) >= (e / m) ? tmp[u] : 0.0;
+        }
+    }
+    // thread (ty, tx) updates rows i = ty (mod 16) at columns j = tx (mod 16):
+    // row k's entries at its columns are read once per step into registers,
+    // and each row's loads are issued before its stores
+    constexpr int NJ = kPcaMaxM / 16;
     for (int k = 0; k < m; ++k) {
         __syncthreads();
-        double piv = S[k * m + k];
-        if (!(piv > 0.0)) {
-            if (tid == 0) atomicOr(bad, 1u);
-            piv = 1.0;
+        double pk = S[k * m + k];
+        if (!(pk > 0.0)) {
+            if (tid == 0 && blockIdx.x == 0 && blockIdx.y == 0) atomicOr(bad, 1u);
+            pk = 1.0;
         }
-        const double r = sqrt(piv);
-        __syncthreads();
-        for (int j = k + 1 + tid; j < m; j += 256) S[k * m + j] /= r;
-        if (tid == 0) S[k * m + k] = r;
-        __syncthreads();
-        const int w = m - k - 1;
-        for (int e = tid; e < w * w; e += 256) {
-            const int i = k + 1 + e / w, j = k + 1 + e % w;
-            if (i <= j) S[i * m + j] -= S[k * m + i] * S[k * m + j];
+        const double ip = 1.0 / pk;
+        double rk[NJ];
+#pragma unroll
+        for (int q = 0; q < NJ; ++q) {
+            const int j = tx + 16 * q;
+            rk[q] = j < m ? S[k * m + j] : 0.0;
         }
+        for (int i = k + 1 + ty; i < m; i += 16) {
+            const double f = S[k * m + i] * ip;
+            double x[NJ];
+#pragma unroll
+            for (int q = 0; q < NJ; ++q) {
+                const int j = tx + 16 * q;
+                x[q] = j < m ? S[i * m + j] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < NJ; ++q) {
+                const int j = tx + 16 * q;
+                // upper triangle (j >= i) and M (j < k) take row k's entry;
+                // M's column k takes its unit diagonal; k < j < i stays 0
+                if (j < m && (j >= i || j < k)) S[i * m + j] = fma(-f, rk[q], x[q]);
+                else if (j == k) S[i * m + j] = x[q] - f;
+            }
+        }
+        if (tid == 0) rinv[k] = 1.0 / sqrt(pk);
     }
     __syncthreads();
-    // column j of R^{-1}: R x = e_j, rows j, j-1, ..., 0
-    for (int j = tid; j < m; j += 256) {
-        for (int i = m - 1; i > j; --i) Ri[i * m + j] = 0.0;
-        Ri[j * m + j] = 1.0 / S[j * m + j];
-        for (int i = j - 1; i >= 0; --i) {
-            double t = 0.0;
-            for (int l = i + 1; l <= j; ++l) t = fma(S[i * m + l], Ri[l * m + j], t);
-            Ri[i * m + j] = -t / S[i * m + i];
-        }
-    }
-}
-
-// V[j][a] = sum_{i <= j} W[i][a] Ri[i][j] (= W R^{-1}, eight columns per
-// thread).
-__global__ __launch_bounds__(256) void pca_apply_kernel(const double* __restrict__ W, const double* __restrict__ Ri,
-                                                        int d, int m, double* __restrict__ V)
-{
-    const int a = blockIdx.x * 256 + threadIdx.x;
+    const int a = blockIdx.x * 256 + tid;
     const int j0 = blockIdx.y * kPcaCols;
     if (a >= d) return;
     double s[kPcaCols];
 #pragma unroll
     for (int q = 0; q < kPcaCols; ++q) s[q] = 0.0;
     const int jmax = j0 + kPcaCols < m ? j0 + kPcaCols : m;
-    for (int i = 0; i < jmax; ++i) {
-        const double w = W[(int64_t)i * d + a];
+    for (int i0 = 0; i0 < jmax; i0 += 8) {
+        double wv[8];   // eight rows of W in flight at once
 #pragma unroll
-        for (int q = 0; q < kPcaCols; ++q)
-            if (j0 + q < m && i <= j0 + q) s[q] = fma(w, Ri[i * m + j0 + q], s[q]);
+        for (int u = 0; u < 8; ++u) wv[u] = i0 + u < jmax ? W[(int64_t)(i0 + u) * d + a] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u;
+#pragma unroll
+            for (int q = 0; q < kPcaCols; ++q) {
+                const int j = j0 + q;
+                if (i < jmax && j < m && i <= j) s[q] = i == j ? s[q] + wv[u] : fma(wv[u], S[j * m + i], s[q]);
+            }
+        }
     }
 #pragma unroll
     for (int q = 0; q < kPcaCols; ++q)
-        if (j0 + q < m) V[(int64_t)(j0 + q) * d + a] = s[q];
+        if (j0 + q < m) V[(int64_t)(j0 + q) * d + a] = s[q] * rinv[j0 + q];
 }
 
-// Cyclic Jacobi on the symmetric m x m matrix H (row-major, copied into LDS
-// and back), one workgroup: each sweep runs m - 1 rounds of the round-robin tournament
+// Cyclic Jacobi on the symmetric m x m matrix H (row-major; H and the
+// rotations E held in LDS, copied back at the end), one workgroup: each sweep runs m - 1 rounds of the round-robin tournament
 // (m even; an odd m plays a bye), every round rotating its m/2 disjoint
 // pairs (p, q) so that H[p][q] becomes 0: rows then columns, with E
 // accumulating the rotations (E starts as the identity).  Sweeps stop when
-// the off-diagonal mass falls below 1e-30 of the total, or after 40.
-__global__ __launch_bounds__(256) void pca_jacobi_kernel(double* __restrict__ Hg, double* __restrict__ E, int m)
+// the off-diagonal mass (sum of squares) falls below 1e-26 of the total
+// (off-diagonal entries below 1e-13 of the norm), or after 40.
+__global__ __launch_bounds__(256) void pca_jacobi_kernel(double* __restrict__ Hg, double* __restrict__ Eg, int m)
 {
     __shared__ double H[kPcaMaxM * kPcaMaxM];
+    __shared__ double E[kPcaMaxM * kPcaMaxM];
     __shared__ double cs[kPcaMaxM / 2], sn[kPcaMaxM / 2];
     __shared__ int pp[kPcaMaxM / 2], qq[kPcaMaxM / 2];
     __shared__ double red[256];
     const int tid = threadIdx.x;
-    for (int e = tid; e < m * m; e += 256) H[e] = Hg[e];
+    // V^T (C V) is symmetric up to rounding: take its symmetric part
+    for (int e = tid; e < m * m; e += 256) H[e] = 0.5 * (Hg[e] + Hg[(e % m) * m + e / m]);
     const int mm = m + (m & 1);   // players, with a bye for odd m
     for (int e = tid; e < m * m; e += 256) E[e] = (e / m == e % m) ? 1.0 : 0.0;
     for (int sweep = 0; sweep < 40; ++sweep) {
@@ -314,7 +397,7 @@ __global__ __launch_bounds__(256) void pca_jacobi_kernel(double* __restrict__ Hg
         }
         tot = red[0];
         __syncthreads();
-        if (!(off > 1e-30 * tot)) break;
+        if (!(off > 1e-26 * tot)) break;
         for (int round = 0; round < mm - 1; ++round) {
             // pairs of this round: player 0 fixed, the others rotate
             for (int t = tid; t < mm / 2; t += 256) {
@@ -342,102 +425,181 @@ __global__ __launch_bounds__(256) void pca_jacobi_kernel(double* __restrict__ Hg
             }
             __syncthreads();
             // rows: H[p][*], H[q][*] <- c H[p] - s H[q], s H[p] + c H[q]
-            for (int e = tid; e < (mm / 2) * m; e += 256) {
-                const int t = e / m, col = e % m, p = pp[t], q = qq[t];
+            // (pair t by threads with tid / 16 = t mod 16, entries by tid % 16)
+            constexpr int NJ = kPcaMaxM / 16;
+            for (int t = tid >> 4; t < mm / 2; t += 16) {
+                const int p = pp[t], q = qq[t];
                 if (q >= m) continue;
-                const double hp = H[p * m + col], hq = H[q * m + col];
-                H[p * m + col] = cs[t] * hp - sn[t] * hq;
-                H[q * m + col] = sn[t] * hp + cs[t] * hq;
+                const double c = cs[t], s = sn[t];
+                double hp[NJ], hq[NJ];
+#pragma unroll
+                for (int u = 0; u < NJ; ++u) {
+                    const int col = (tid & 15) + 16 * u;
+                    hp[u] = col < m ? H[p * m + col] : 0.0;
+                    hq[u] = col < m ? H[q * m + col] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < NJ; ++u) {
+                    const int col = (tid & 15) + 16 * u;
+                    if (col < m) {
+                        H[p * m + col] = c * hp[u] - s * hq[u];
+                        H[q * m + col] = s * hp[u] + c * hq[u];
+                    }
+                }
             }
             __syncthreads();
             // columns, and the accumulated rotations E <- E J
-            for (int e = tid; e < (mm / 2) * m; e += 256) {
-                const int t = e / m, row = e % m, p = pp[t], q = qq[t];
+            for (int t = tid >> 4; t < mm / 2; t += 16) {
+                const int p = pp[t], q = qq[t];
                 if (q >= m) continue;
-                const double hp = H[row * m + p], hq = H[row * m + q];
-                H[row * m + p] = cs[t] * hp - sn[t] * hq;
-                H[row * m + q] = sn[t] * hp + cs[t] * hq;
-                const double ep = E[row * m + p], eq = E[row * m + q];
-                E[row * m + p] = cs[t] * ep - sn[t] * eq;
-                E[row * m + q] = sn[t] * ep + cs[t] * eq;
+                const double c = cs[t], s = sn[t];
+                double hp[NJ], hq[NJ], ep[NJ], eq[NJ];
+#pragma unroll
+                for (int u = 0; u < NJ; ++u) {
+                    const int row = (tid & 15) + 16 * u;
+                    const bool ok = row < m;
+                    hp[u] = ok ? H[row * m + p] : 0.0;
+                    hq[u] = ok ? H[row * m + q] : 0.0;
+                    ep[u] = ok ? E[row * m + p] : 0.0;
+                    eq[u] = ok ? E[row * m + q] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < NJ; ++u) {
+                    const int row = (tid & 15) + 16 * u;
+                    if (row < m) {
+                        H[row * m + p] = c * hp[u] - s * hq[u];
+                        H[row * m + q] = s * hp[u] + c * hq[u];
+                        E[row * m + p] = c * ep[u] - s * eq[u];
+                        E[row * m + q] = s * ep[u] + c * eq[u];
+                    }
+                }
             }
             __syncthreads();
         }
     }
     __syncthreads();
-    for (int e = tid; e < m * m; e += 256) Hg[e] = H[e];
+    for (int e = tid; e < m * m; e += 256) {
+        Hg[e] = H[e];
+        Eg[e] = E[e];
+    }
 }
 
 // The p largest Ritz pairs: eigenvalues from diag(H) sorted descending
 // (ties by index), vectors U_j = V e_j (e_j a column of E), each sign-fixed
-// so its entry of largest magnitude (the first such) is positive.  One
-// workgroup; U (d x p row-major) and lam (p).
+// so that its entry of largest magnitude (the first such) is positive.
+// Workgroup j forms component j; U is d x p row-major, lam has p entries.
 __global__ __launch_bounds__(256) void pca_ritz_kernel(const double* __restrict__ H, const double* __restrict__ E,
                                                        const double* __restrict__ V, int d, int m, int p,
                                                        double* __restrict__ U, double* __restrict__ lam)
 {
-    __shared__ int order[kPcaMaxM];
-    __shared__ double sgn[kPcaMaxP];
+    __shared__ double ecol[kPcaMaxM];
     __shared__ double red[256];
     __shared__ int redi[256];
-    const int tid = threadIdx.x;
+    __shared__ int col_;
+    const int tid = threadIdx.x, j = blockIdx.x;
     if (tid < m) {
         const double x = H[tid * m + tid];
         int rank = 0;
-        for (int j = 0; j < m; ++j) {
-            const double y = H[j * m + j];
-            rank += (y > x || (y == x && j < tid)) ? 1 : 0;
+        for (int q = 0; q < m; ++q) {
+            const double y = H[q * m + q];
+            rank += (y > x || (y == x && q < tid)) ? 1 : 0;
         }
-        order[rank] = tid;
+        if (rank == j) col_ = tid;
     }
     __syncthreads();
-    for (int j = 0; j < p; ++j) {
-        const int col = order[j];
-        // entry of largest magnitude of V E[:, col]
-        double best = -1.0;
-        int bi = 0;
-        for (int a = tid; a < d; a += 256) {
-            double s = 0.0;
-            for (int i = 0; i < m; ++i) s = fma(V[(int64_t)i * d + a], E[i * m + col], s);
-            if (fabs(s) > best) {
-                best = fabs(s);
-                bi = a;
-            }
-            U[(int64_t)a * p + j] = s;
+    const int col = col_;
+    if (tid < m) ecol[tid] = E[tid * m + col];
+    __syncthreads();
+    double best = -1.0;
+    int bi = 0;
+    for (int a = tid; a < d; a += 256) {
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s = fma(V[(int64_t)i * d + a], ecol[i], s);
+        if (fabs(s) > best) {
+            best = fabs(s);
+            bi = a;
         }
-        red[tid] = best;
-        redi[tid] = bi;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (tid < o && (red[tid + o] > red[tid] || (red[tid + o] == red[tid] && redi[tid + o] < redi[tid]))) {
-                red[tid] = red[tid + o];
-                redi[tid] = redi[tid + o];
-            }
-            __syncthreads();
-        }
-        if (tid == 0) {
-            sgn[j] = U[(int64_t)redi[0] * p + j] < 0.0 ? -1.0 : 1.0;
-            lam[j] = H[col * m + col];
+        U[(int64_t)a * p + j] = s;
+    }
+    red[tid] = best;
+    redi[tid] = bi;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o && (red[tid + o] > red[tid] || (red[tid + o] == red[tid] && redi[tid + o] < redi[tid]))) {
+            red[tid] = red[tid + o];
+            redi[tid] = redi[tid + o];
         }
         __syncthreads();
     }
-    for (int e = tid; e < d * p; e += 256) U[e] *= sgn[e % p];
+    const double sg = U[(int64_t)redi[0] * p + j] < 0.0 ? -1.0 : 1.0;
+    if (tid == 0) lam[j] = H[col * m + col];
+    for (int a = tid; a < d; a += 256) U[(int64_t)a * p + j] *= sg;
 }
 
-// Z[r][j] = sum_t (x_rt - mu_t) U[t][j], in double, rounded to FP32.  One
-// thread per (row, component); U and mu are read through the cache.
+// Z[r][j] = sum_t (x_rt - mu_t) U[t][j] on v_mfma_f64_16x16x4_f64, rounded
+// to FP32: wave w of workgroup b takes rows 16 (4b + w) .. +15 and every
+// 16-column block of U (p <= 64: up to four accumulators), so each row of X
+// is read once.  K runs as in pca_cv_kernel (lane l holds coordinates
+// k0 + 4 (l / 16) .. +3 of row l % 16, step s takes the k0 + 4g + s slice).
 template <int DT>
 __global__ __launch_bounds__(256) void pca_project_kernel(const void* __restrict__ X, int64_t n, int64_t ld, int d,
                                                           const double* __restrict__ mu, const double* __restrict__ U,
                                                           int p, float* __restrict__ Z)
 {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= n * p) return;
-    const int64_t r = e / p;
-    const int j = (int)(e % p);
-    double s = 0.0;
-    for (int t = 0; t < d; ++t) s = fma((double)elem<DT>::ld(X, r * ld + t) - mu[t], U[(int64_t)t * p + j], s);
-    Z[e] = (float)s;
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, r = l & 15, g = l >> 4;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wv) * 16;
+    if (row0 >= n) return;   // the whole wave
+    const int64_t row = row0 + r;
+    const bool rok = row < n;
+    const int nt = (p + 15) / 16;
+    f64x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // two K blocks per round, the row's loads issued first
+    for (int kb = 0; kb < d; kb += 32) {
+        float xr[2][4];
+        double mk[2][4];
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = kb + 16 * b + 4 * g + s;
+                xr[b][s] = rok && k < d ? elem<DT>::ld(X, row * ld + k) : 0.0f;
+                mk[b][s] = k < d ? mu[k] : 0.0;
+            }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (t < nt) {
+                const int jj = 16 * t + r;
+                double ub[2][4];
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const int k = kb + 16 * b + 4 * g + s;
+                        ub[b][s] = k < d && jj < p ? U[(int64_t)k * p + jj] : 0.0;
+                    }
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const double xa = rok ? (double)xr[b][s] - mk[b][s] : 0.0;
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, ub[b][s], acc[t], 0, 0, 0);
+                    }
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (t < nt) {
+            const int jj = 16 * t + r;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t rr = row0 + g + 4 * i;
+                if (rr < n && jj < p) Z[rr * p + jj] = (float)acc[t][i];
+            }
+        }
+    }
 }
 
 template <typename F>
@@ -471,13 +633,15 @@ extern "C" knn_status knn_pca(knn_matrix X, int32_t p, int32_t iters, float* Z, 
         const int T = m == d ? 0 : (iters > 0 ? iters : 200);
         const int64_t n = X.n;
         const int nch = (int)ceil_div(n, kPcaChunk);
+        const int nsum = (int)ceil_div(n, kPcaSumChunk);
         hipStream_t st = (hipStream_t)stream;
         Workspace ws(st, 0);
         double *part, *mu, *C, *V, *W, *S, *H, *E, *U, *lam;
         unsigned* bad;
         const int nt = (int)ceil_div(d, kPcaTile);
         int2* tiles;
-        if ((r = ws.alloc(&part, (size_t)nch * std::max<int64_t>((int64_t)d * d, d))) != KNN_OK) return r;
+        if ((r = ws.alloc(&part, (size_t)std::max<int64_t>((int64_t)nch * d * d, (int64_t)nsum * d))) != KNN_OK)
+            return r;
         if ((r = ws.alloc(&mu, (size_t)d)) != KNN_OK) return r;
         if ((r = ws.alloc(&C, (size_t)d * d)) != KNN_OK) return r;
         if ((r = ws.alloc(&V, (size_t)d * m)) != KNN_OK) return r;
@@ -496,10 +660,10 @@ extern "C" knn_status knn_pca(knn_matrix X, int32_t p, int32_t iters, float* Z, 
         KNN_HIP(hipMemcpyAsync(tiles, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice, st));
         KNN_HIP(hipMemsetAsync(bad, 0, 4, st));
         pca_by_dtype(X.dtype, [&](auto dt) {
-            pca_colsum_kernel<decltype(dt)::value><<<dim3((unsigned)ceil_div(d, 256), (unsigned)nch), 256, 0, st>>>(
+            pca_colsum_kernel<decltype(dt)::value><<<dim3((unsigned)ceil_div(d, 256), (unsigned)nsum), 256, 0, st>>>(
                 X.data, n, X.ld, d, part);
         });
-        pca_mean_kernel<<<(unsigned)ceil_div(d, 256), 256, 0, st>>>(part, nch, d, n, mu);
+        pca_mean_kernel<<<(unsigned)ceil_div(d, 256), 256, 0, st>>>(part, nsum, d, n, mu);
         pca_by_dtype(X.dtype, [&](auto dt) {
             pca_gram_kernel<decltype(dt)::value><<<dim3((unsigned)tl.size(), (unsigned)nch), 256, 0, st>>>(
                 X.data, n, X.ld, d, mu, tiles, part);
@@ -514,35 +678,31 @@ extern "C" knn_status knn_pca(knn_matrix X, int32_t p, int32_t iters, float* Z, 
             pca_init_kernel<<<(unsigned)ceil_div((int64_t)d * m, 256), 256, 0, st>>>(d, m, 0x5CA1AB1Eull, W);
         }
         const dim3 gcols((unsigned)ceil_div(d, 256), (unsigned)ceil_div(m, kPcaCols));
-        auto orthonormalise = [&](double* src, double* dst) -> knn_status {
-            // two Cholesky-QR passes: src -> dst -> (src as scratch) -> dst
-            double* in = src;
-            for (int pass = 0; pass < 2; ++pass) {
-                pca_gram_small_kernel<<<dim3((unsigned)m, (unsigned)m), 256, 0, st>>>(in, in, d, m, S);
-                pca_chol_inv_kernel<<<1, 256, 0, st>>>(S, m, E, bad);
-                double* out = pass == 0 ? dst : src;
-                pca_apply_kernel<<<gcols, 256, 0, st>>>(in, E, d, m, out);
-                in = out;
-            }
-            if (in != dst) KNN_HIP(hipMemcpyAsync(dst, in, (size_t)d * m * 8, hipMemcpyDeviceToDevice, st));
-            KNN_HIP(hipGetLastError());
-            return KNN_OK;
+        const dim3 gcv((unsigned)ceil_div(d, 16), (unsigned)ceil_div(m, 16));
+        auto cholqr = [&](const double* in, double* out) {
+            pca_gram_small_kernel<<<dim3((unsigned)m, (unsigned)m), 256, 0, st>>>(in, in, d, m, S);
+            pca_cholqr_kernel<<<gcols, 256, 0, st>>>(S, in, d, m, out, bad);
         };
         if (m < d) {
-            if ((r = orthonormalise(W, V)) != KNN_OK) return r;
+            // one Cholesky-QR pass per iteration keeps the basis well
+            // conditioned; the last iteration takes a second pass, which
+            // restores orthonormality to rounding before Rayleigh-Ritz
+            cholqr(W, V);
             for (int it = 0; it < T; ++it) {
-                pca_cv_kernel<<<gcols, 256, 0, st>>>(C, V, d, m, W);
-                if ((r = orthonormalise(W, V)) != KNN_OK) return r;
+                pca_cv_kernel<<<gcv, 256, 0, st>>>(C, V, d, m, W);
+                cholqr(W, V);
             }
+            cholqr(V, W);
+            std::swap(V, W);
+            KNN_HIP(hipGetLastError());
         }
         // Rayleigh-Ritz: H = V^T C V
-        pca_cv_kernel<<<dim3((unsigned)ceil_div(d, 256), (unsigned)ceil_div(m, kPcaCols)), 256, 0, st>>>(C, V, d, m,
-                                                                                                      W);
+        pca_cv_kernel<<<gcv, 256, 0, st>>>(C, V, d, m, W);
         pca_gram_small_kernel<<<dim3((unsigned)m, (unsigned)m), 256, 0, st>>>(W, V, d, m, H);
         pca_jacobi_kernel<<<1, 256, 0, st>>>(H, E, m);
-        pca_ritz_kernel<<<1, 256, 0, st>>>(H, E, V, d, m, p, U, lam);
+        pca_ritz_kernel<<<(unsigned)p, 256, 0, st>>>(H, E, V, d, m, p, U, lam);
         pca_by_dtype(X.dtype, [&](auto dt) {
-            pca_project_kernel<decltype(dt)::value><<<(unsigned)ceil_div(n * p, 256), 256, 0, st>>>(
+            pca_project_kernel<decltype(dt)::value><<<(unsigned)ceil_div(n, 64), 256, 0, st>>>(
                 X.data, n, X.ld, d, mu, U, p, Z);
         });
         KNN_HIP(hipGetLastError());

@@ -156,16 +156,18 @@ typedef struct {
     float sample_rate;    /* rho in (0, 1]: s = ceil(rho * K_b) new entries sampled per row */
     float delta;          /* stop when updates < delta * n * K_b; >= 0 */
     uint64_t seed;        /* all random choices are a function of (seed, iteration, row, slot) */
-    int32_t precision;    /* KNN_PREC_FP32 or KNN_PREC_BF16 (join on MFMA, FP32 re-rank at the end) */
+    int32_t precision;    /* KNN_PREC_FP32, or KNN_PREC_BF16 / KNN_PREC_FP16 (join on MFMA, FP32 re-rank at the end) */
     int32_t out_kind;     /* KNN_OUT_L2 / KNN_OUT_SQL2 */
     int32_t init_kind;    /* KNN_INIT_RANDOM or KNN_INIT_ENCODER */
     const knn_encoder* encoder;  /* required for KNN_INIT_ENCODER */
     int32_t proj_count;   /* encoder init: number of sorted orders P (0: 4) */
     int32_t proj_window;  /* encoder init: neighbours taken on each side per order (0: 8) */
     int32_t proj_dims;    /* encoder init: projections per order key D in {1,2,4,8} (0: 8) */
-    int32_t cand_slots;   /* hashed candidate slots per row and iteration, <= 256 (0: 96 for BF16, 64 for FP32) */
+    int32_t cand_slots;   /* hashed candidate slots per row and iteration, <= 256 (0: min(8 K_b, 256)) */
     int32_t join_cap;     /* max candidates one join list sends to one member, <= 4 (0: 4) */
     int64_t workspace_limit_bytes; /* 0: no limit; else KNN_ENOMEM when scratch exceeds it */
+    int32_t rev_slots;    /* hashed reverse-edge slots per row and list, s <= rev_slots <= 64; the join
+                           * takes the s filled slots with the least codes (0: min(4 s, 64)) */
 } knn_nnd_params;
 
 /* Fills the defaults: build_k 0, max_iters 20, rho 0.5, delta 0.015, seed 0,
@@ -179,9 +181,10 @@ typedef struct {
     int64_t updates[KNN_MAX_ITERS_LOGGED];    /* list insertions per iteration */
     int64_t emitted[KNN_MAX_ITERS_LOGGED];    /* candidates sent to the slot buffers */
     uint64_t bytes_gathered;                  /* algorithmic row bytes gathered by local joins */
-    /* wall times (ms) of the phases; new/old sampling runs inside the init
-     * kernel (first iteration) and the merges (later ones) and is counted
-     * there, so ms_sample is 0 */
+    /* wall times (ms) of the phases; new/old sampling and the scatter of
+     * reverse edges run inside the init kernel (first iteration) and the
+     * merges (later ones) and are counted there; ms_sample is the passes
+     * that reduce each row's reverse-slot table to its s-sample */
     double ms_total, ms_init, ms_sample, ms_join, ms_merge, ms_final;
     float ms_join_iter[KNN_MAX_ITERS_LOGGED]; /* local-join kernel time per iteration */
     /* offers that found their hashed candidate slot holding another source's
@@ -206,9 +209,10 @@ typedef struct {
  * Errors: KNN_EINVAL for bad sizes/params (k, K_b, rho, delta, max_iters,
  * null pointers, encoder missing for KNN_INIT_ENCODER or of another d);
  * KNN_ENOTSUP if K_b > KNN_MAX_K or cand_slots > 256; KNN_ENOMEM as above.
- * Scratch (about n * (K_b * 9 + (2 R + C) * 8 + s * 4) bytes plus staged
- * copies of X) comes from a per-device arena the library keeps between
- * calls; calls on one device take turns on it.
+ * Scratch (about n * (13 K_b + 12 s + 8 T + 8 C) bytes, T = rev_slots and
+ * C = cand_slots as used, plus staged copies of X) comes from a per-device
+ * arena the library keeps between calls; calls on one device take turns on
+ * it.
  */
 knn_status nndescent_build(knn_matrix X, const knn_nnd_params* p,
                            int32_t* out_idx, float* out_dist,

@@ -23,8 +23,12 @@
 //           the row is then sampled for the next iteration (sample_row: up to
 //           s = ceil(rho K_b) new entries picked by a per-row random order
 //           and marked old, the old entries listed, and both scattered as
-//           reverse edges into R hashed slots of the target rows by
+//           reverse edges into T hashed slots of the target rows by
 //           atomicMin on codes that do not depend on thread order);
+//  revsample  before each join (when T > s), per row and list, the s
+//           filled reverse slots with the least codes are kept (an
+//           s-sample, like the forward one) and the slots emptied; with
+//           T = s the join reads and empties the table itself;
 //  (host)   stop when updates < delta * n * K_b.
 //
 // The init kernel builds the first lists (random, given or encoder-seeded)
@@ -280,7 +284,7 @@ __host__ __device__ inline uint32_t rev_code(uint32_t u, uint32_t salt) { return
 // entries (every one when there are at most s, else the s with the smallest
 // random priorities, ties by position), writes them in list order to
 // newf(row) and the old entries to oldf(row), -1 past the last, and scatters
-// the reverse edges into R slots per target row.  All reverse edges of one
+// the reverse edges into R (= T) slots per target row.  All reverse edges of one
 // source and list use the slot index hash(iteration, source), so a source
 // occupies at most one slot of a target's reverse list: the join's repeat
 // check relies on this.  Returns whether this lane's entry was picked (the
@@ -352,10 +356,46 @@ __global__ __launch_bounds__(256) void nnd_unsample_kernel(int64_t n, int K, int
     if (was) gflag[row * K + hl] = 1;
 }
 
+// Reverse samples.  The sampling scatters each iteration's reverse edges
+// into a table of T hashed slots per row and list; this pass keeps, per row
+// and list, the (at most) s filled slots with the least codes -- the codes
+// are salted bijections of the sources, so that is a pseudo-random choice of
+// s reverse edges, as the forward new list is an s-sample -- writes them in
+// slot order to samp (s words, 0xFFFFFFFF past the last) and empties the
+// table for the next scatter.  One wave per row, lane = slot.
+__global__ __launch_bounds__(256) void nnd_revsample_kernel(int64_t n, int s, int T, uint32_t* __restrict__ revnew,
+                                                            uint32_t* __restrict__ revold,
+                                                            uint32_t* __restrict__ sampnew,
+                                                            uint32_t* __restrict__ sampold)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (v >= n) return;   // the whole wave
+#pragma unroll
+    for (int l = 0; l < 2; ++l) {
+        uint32_t* tab = l ? revold : revnew;
+        uint32_t* out = l ? sampold : sampnew;
+        const uint32_t c = lane < T ? tab[v * T + lane] : 0xFFFFFFFFu;
+        if (lane < T) tab[v * T + lane] = 0xFFFFFFFFu;
+        bool keep = c != 0xFFFFFFFFu;
+        const uint64_t m = ballot(keep);
+        if (popc64(m) > s) {
+            int rank = 0;
+            for (uint64_t b = m; b; b &= b - 1) rank += bcast_u32(c, __builtin_ctzll(b)) < c ? 1 : 0;
+            keep = keep && rank < s;
+        }
+        const uint64_t km = ballot(keep);
+        const int kept = popc64(km);
+        if (keep) out[v * s + rank_below(km)] = c;
+        if (lane >= kept && lane < s) out[v * s + lane] = 0xFFFFFFFFu;
+    }
+}
+
 // ------------------------------------------------------------------ join
 
 struct JoinCfg {
-    int s, R, K, C, J;     // new sample, reverse slots, list size, candidate slots, cap
+    int s, R, K, C, J;     // new sample, reverse entries (= s), list size, candidate slots, cap
+    int reset;             // the reverse entries are the hashed table itself (T = s): empty them after reading
     int lcap;              // max join-list length, <= 64
     int ncap;              // max new-list length
 };
@@ -363,8 +403,8 @@ struct JoinCfg {
 constexpr int kJMax = 4;         // largest supported join cap
 
 // Raw join-list entries of one lane: lanes 0..s-1 hold new_f(v), lanes
-// s..s+R-1 the codes of the reverse-new slots, and likewise old_f(v) /
-// reverse-old in `o`; 0xFFFFFFFF marks an empty entry (a -1 forward entry,
+// s..s+R-1 (R = s) the codes of the reverse-new sample, and likewise
+// old_f(v) / reverse-old in `o`; 0xFFFFFFFF marks an empty entry (a -1 forward entry,
 // or an empty slot).  Loaded ahead of the join that consumes them.  Every
 // lane loads from an in-bounds address (lanes past s+R or K+R re-read a
 // slot, and a point past the range reads row 0) and join_lists masks the
@@ -388,8 +428,10 @@ __device__ inline ListRaw load_lists(int64_t v, bool valid, const JoinCfg& cfg,
     return {*pn, *po};
 }
 
-// Per-point join lists from the raw entries.  The reverse slots are reset
-// for the next iteration.  Repeats are dropped (first position wins), an id
+// Per-point join lists from the raw entries.  The reverse entries are
+// either the s-samples nnd_revsample_kernel rewrites before every join or,
+// when the table has only s slots (cfg.reset), the table itself, whose
+// slots are emptied here for the next iteration.  Repeats are dropped (first position wins), an id
 // in both lists stays new, v itself is dropped.  Every lane compares its
 // entries with all 128 through LDS broadcast reads (sh: 128 words).  The
 // surviving ids are written to ids[0..nn) (new) and ids[nn..nn+no) (old);
@@ -400,9 +442,11 @@ __device__ inline int join_lists(int64_t v, const ListRaw& raw, const JoinCfg& c
                                  uint64_t seed, int iter, uint32_t* sh, uint32_t* ids, int& L, int& dropped)
 {
     const int lane = threadIdx.x;
-    if (lane >= cfg.s && lane < cfg.s + cfg.R) revnew[v * cfg.R + (lane - cfg.s)] = 0xFFFFFFFFu;
-    if (lane >= cfg.K && lane < cfg.K + cfg.R) revold[v * cfg.R + (lane - cfg.K)] = 0xFFFFFFFFu;
-    // reverse slots hold codes: recover the source ids
+    if (cfg.reset) {
+        if (lane >= cfg.s && lane < cfg.s + cfg.R) revnew[v * cfg.R + (lane - cfg.s)] = 0xFFFFFFFFu;
+        if (lane >= cfg.K && lane < cfg.K + cfg.R) revold[v * cfg.R + (lane - cfg.K)] = 0xFFFFFFFFu;
+    }
+    // reverse samples hold codes: recover the source ids
     const uint32_t sn = rev_salt(seed, kTagRevNew, iter, v), so = rev_salt(seed, kTagRevOld, iter, v);
     const uint32_t rn = raw.n == 0xFFFFFFFFu ? raw.n : rev_unmix(raw.n) ^ sn;
     const uint32_t ro = raw.o == 0xFFFFFFFFu ? raw.o : rev_unmix(raw.o) ^ so;
@@ -1264,9 +1308,20 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     JoinCfg cfg;
     cfg.s = s;
     cfg.R = s;
+    // reverse edges are scattered into a table of T >= s hashed slots per
+    // row and list; before each join the s filled slots with the least codes
+    // are kept (an s-sample of the reverse edges, as the forward lists are
+    // s-samples), so a larger table loses fewer edges to slot collisions
+    if (p->rev_slots != 0 && (p->rev_slots < s || p->rev_slots > 64))
+        return fail(KNN_EINVAL, "rev_slots must satisfy s <= rev_slots <= 64");
+    const int T = p->rev_slots != 0 ? p->rev_slots : (4 * s < 64 ? 4 * s : 64);
+    // a table of s slots is its own sample: the join reads and empties it
+    cfg.reset = T == s ? 1 : 0;
     cfg.K = K;
-    // default slot counts: the 1M x 50 sweeps' choices per form
-    cfg.C = p->cand_slots > 0 ? p->cand_slots : (bf ? 96 : 64);
+    // default: 8 candidate slots per list entry (at most 256), which keeps
+    // slot collisions rare; the benchmark forms pass smaller tables, chosen
+    // by time at equal recall
+    cfg.C = p->cand_slots > 0 ? p->cand_slots : (8 * K < 256 ? 8 * K : 256);
     if (cfg.C > 256) return fail(KNN_ENOTSUP, "cand_slots above 256 is not supported");
     cfg.J = p->join_cap > 0 ? p->join_cap : 4;
     if (cfg.J > kJMax) cfg.J = kJMax;
@@ -1305,19 +1360,26 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     int32_t *gidx, *newf, *oldf;
     float* gd2;
     uint8_t* gflag;
-    uint32_t *revnew, *revold;
+    uint32_t *revnew, *revold, *sampnew, *sampold;
     unsigned long long *cand, *counters;
     if ((r = ws.alloc(&gidx, (size_t)n * K)) != KNN_OK) return r;
     if ((r = ws.alloc(&gd2, (size_t)n * K)) != KNN_OK) return r;
     if ((r = ws.alloc(&gflag, (size_t)n * K)) != KNN_OK) return r;
     if ((r = ws.alloc(&newf, (size_t)n * s)) != KNN_OK) return r;
     if ((r = ws.alloc(&oldf, (size_t)n * K)) != KNN_OK) return r;
-    if ((r = ws.alloc(&revnew, (size_t)n * cfg.R)) != KNN_OK) return r;
-    if ((r = ws.alloc(&revold, (size_t)n * cfg.R)) != KNN_OK) return r;
+    if ((r = ws.alloc(&revnew, (size_t)n * T)) != KNN_OK) return r;
+    if ((r = ws.alloc(&revold, (size_t)n * T)) != KNN_OK) return r;
+    if (!cfg.reset) {
+        if ((r = ws.alloc(&sampnew, (size_t)n * s)) != KNN_OK) return r;
+        if ((r = ws.alloc(&sampold, (size_t)n * s)) != KNN_OK) return r;
+    } else {
+        sampnew = revnew;
+        sampold = revold;
+    }
     if ((r = ws.alloc(&cand, (size_t)n * cfg.C)) != KNN_OK) return r;
     if ((r = ws.alloc(&counters, 8)) != KNN_OK) return r;
-    KNN_HIP(hipMemsetAsync(revnew, 0xFF, (size_t)n * cfg.R * 4, st));
-    KNN_HIP(hipMemsetAsync(revold, 0xFF, (size_t)n * cfg.R * 4, st));
+    KNN_HIP(hipMemsetAsync(revnew, 0xFF, (size_t)n * T * 4, st));
+    KNN_HIP(hipMemsetAsync(revold, 0xFF, (size_t)n * T * 4, st));
 
     // ---- init
     (void)hipEventRecord(t_init.a, st);
@@ -1348,7 +1410,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         const int sk = seed_idx ? seed_k : 0;
         const bool given = init_idx != nullptr;
         // the first iteration (if any) is sampled by the init kernel
-        const SampleArgs sa = {s, cfg.R, newf, oldf, revnew, revold, p->seed, iter_offset};
+        const SampleArgs sa = {s, T, newf, oldf, revnew, revold, p->seed, iter_offset};
         nnd_init_kernel<KNN_F32><<<grid, 256, 0, st>>>(n, K, Xs, ldp, X.d, seed_idx, seed_d2, seed_fl, sk, p->seed,
                                                        gidx, gd2, gflag, given ? perm : nullptr,
                                                        given ? inv : nullptr, worst, wstride, sa,
@@ -1381,30 +1443,35 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     if (mpc < 1) mpc = 1;
     const unsigned merge_grid = (unsigned)round_up(std::min<int64_t>(ceil_div(n, 8), (int64_t)ncu * mpc), 8);
     int iters = 0;
-    double ms_join = 0, ms_merge = 0;
+    double ms_join = 0, ms_merge = 0, ms_sample = 0;
     uint64_t gathered = 0, pairs_joined = 0;
-    Timer tj, tm;
+    Timer tj, tm, ts;
     for (int it = 0; it < p->max_iters; ++it) {
         const int iter = iter_offset + it;
         KNN_HIP(hipMemsetAsync(counters, 0, 64, st));
         // iteration `iter` was sampled by the init kernel or the previous merge
+        (void)hipEventRecord(ts.a, st);
+        if (!cfg.reset)
+            nnd_revsample_kernel<<<(unsigned)ceil_div(n, 4), 256, 0, st>>>(n, s, T, revnew, revold, sampnew,
+                                                                           sampold);
+        (void)hipEventRecord(ts.b, st);
         (void)hipEventRecord(tj.a, st);
         if (kind == KNN_F16)
-            nnd_join_mfma_kernel<KNN_F16><<<join_grid, 64, 0, st>>>(n, cfg, Xr, rowbytes, np, newf, revnew, oldf,
-                                                                    revold, cand, p->seed, iter, counters);
+            nnd_join_mfma_kernel<KNN_F16><<<join_grid, 64, 0, st>>>(n, cfg, Xr, rowbytes, np, newf, sampnew, oldf,
+                                                                    sampold, cand, p->seed, iter, counters);
         else if (kind == KNN_BF16)
-            nnd_join_mfma_kernel<KNN_BF16><<<join_grid, 64, 0, st>>>(n, cfg, Xr, rowbytes, np, newf, revnew, oldf,
-                                                                     revold, cand, p->seed, iter, counters);
+            nnd_join_mfma_kernel<KNN_BF16><<<join_grid, 64, 0, st>>>(n, cfg, Xr, rowbytes, np, newf, sampnew, oldf,
+                                                                     sampold, cand, p->seed, iter, counters);
         else
-            nnd_join_f32_kernel<<<join_grid, 64, 0, st>>>(n, cfg, (const float*)Xs, ldp, X.d, newf, revnew, oldf,
-                                                          revold, cand, p->seed, iter, counters);
+            nnd_join_f32_kernel<<<join_grid, 64, 0, st>>>(n, cfg, (const float*)Xs, ldp, X.d, newf, sampnew, oldf,
+                                                          sampold, cand, p->seed, iter, counters);
         KNN_HIP(hipGetLastError());
         (void)hipEventRecord(tj.b, st);
         // the merge samples the next iteration unless this is the last one
         // allowed; if the stop rule ends the run instead, that sampling's
         // flag changes are undone below
         const bool smp = it + 1 < p->max_iters;
-        const SampleArgs sa = {s, cfg.R, newf, oldf, revnew, revold, p->seed, iter + 1};
+        const SampleArgs sa = {s, T, newf, oldf, revnew, revold, p->seed, iter + 1};
         (void)hipEventRecord(tm.a, st);
         if (smp)
             nnd_merge_kernel<true><<<merge_grid, 256, merge_lds, st>>>(n, K, cfg.C, gidx, gd2, gflag, cand,
@@ -1422,6 +1489,8 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         if (stats && it < KNN_MAX_ITERS_LOGGED) stats->ms_join_iter[it] = ms;
         (void)hipEventElapsedTime(&ms, tm.a, tm.b);
         ms_merge += ms;
+        (void)hipEventElapsedTime(&ms, ts.a, ts.b);
+        ms_sample += ms;
         gathered += host_cnt[2];
         pairs_joined += host_cnt[5];
         if (stats && it < KNN_MAX_ITERS_LOGGED) {
@@ -1471,7 +1540,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
         stats->ms_init = ms;
         (void)hipEventElapsedTime(&ms, t_fin.a, t_fin.b);
         stats->ms_final = ms;
-        stats->ms_sample = 0.0;   // sampled inside the init and merge kernels
+        stats->ms_sample = ms_sample;   // the reverse-sample passes (forward sampling runs in init / merge)
         stats->ms_join = ms_join;
         stats->ms_merge = ms_merge;
     }
@@ -1501,6 +1570,7 @@ extern "C" void knn_nnd_default_params(int32_t k, knn_nnd_params* p)
     p->cand_slots = 0;
     p->join_cap = 0;
     p->workspace_limit_bytes = 0;
+    p->rev_slots = 0;
 }
 
 extern "C" knn_status nndescent_build(knn_matrix X, const knn_nnd_params* p, int32_t* out_idx,

@@ -61,7 +61,10 @@ def test_pixel70k_fp32_nndescent(orc):
     _, O2 = orc.exact_knn(X, 15, rows=rows)
     r = orc.recall_at_k(X, rows, G, np.sqrt(O2[:, -1]), 15)
     print("pixel70k fp32 recall", r, "oracle", gold["oracle_recall_at_15"], "iters", st["iters"])
-    assert r >= gold["oracle_recall_at_15"] - 0.06, (r, gold)
+    # the GPU's approximations (at most join_cap = 4 partners per member
+    # and join list, join lists cut at 64 members: list_dropped counts them,
+    # hashed candidate slots) cost 0.023 here (0.810 against 0.833)
+    assert r >= gold["oracle_recall_at_15"] - 0.03, (r, gold)
 
 
 def test_pixel70k_bf16_storage_precision_form(orc):
@@ -97,7 +100,7 @@ def test_pixel70k_bf16_storage_precision_form(orc):
     vs_orig = _rel_err_stats(sd[ok].astype(np.float64), orc.pair_d2(X32, a, b))
     print("pixel70k bf16 form recall", r, "iters", st["iters"], "err vs stored", vs_stored,
           "err vs original", vs_orig)
-    assert r >= 0.7, r
+    assert r >= 0.76, r   # measured 0.788
     assert vs_stored["p99"] <= 1e-3, vs_stored
     assert vs_orig["p99"] <= 5e-2, vs_orig
 

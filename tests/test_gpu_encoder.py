@@ -1,7 +1,8 @@
 """Learned seeding on the GPU: encoder forward/backward against the FP64 CPU
 oracle, the stable radix sort + window seeding against the oracle's
-sorted-projection seeding, and the gain of a trained encoder over random
-init (recall after the same number of NNDescent iterations)."""
+sorted-projection seeding, and the gain of encoder seeding (trained or
+untrained) over random init (recall after the same number of NNDescent
+iterations)."""
 import numpy as np
 import pytest
 import torch
@@ -170,7 +171,16 @@ def test_learned_init_vs_random(orc):
     """Train on a 20K sample of the mixture (exact graph from knn_exact), seed a
     held-out 100K set through Z-order windows of the embedding, and compare
     recall after 0, 1 and 2 NNDescent iterations with random init and with an
-    untrained encoder (same settings).  The seeds must beat random lists."""
+    untrained encoder of the same shape (same settings).
+
+    What this shows, and what it does not: both encoder-seeded starts beat
+    random lists by far (the sorted-projection seeding is what gains), but
+    training does not beat the untrained encoder here -- a random ReLU map
+    already preserves enough locality for the Z-order windows, and the
+    measured recall of the trained seeds is within 0.03 of the untrained
+    ones (slightly below on this mixture).  The test asserts exactly that:
+    the seeds' advantage over random init, and training costing no more
+    than 0.03 of recall against the untrained map at every iteration."""
     import paper_2603_04035_amd as knn
     from paper_2603_04035_amd import Encoder
     Xt = _dev(datagen.gmm_anisotropic(n=20000, d=50, comps=50, seed=0 + 100))
@@ -191,8 +201,10 @@ def test_learned_init_vs_random(orc):
             res[name].append(round(orc.recall_at_k(Xe_np, rows, G.cpu().numpy()[rows],
                                                    np.sqrt(O2[:, -1]), 15), 4))
     print("recall after 0/1/2 iterations", res)
-    assert res["trained"][0] > 5 * max(res["random"][0], 1e-3), res
-    assert res["trained"][2] > res["random"][2], res
+    for name in ("trained", "untrained"):
+        assert res[name][0] > 5 * max(res["random"][0], 1e-3), res
+        assert res[name][2] > 5 * res["random"][2], res
+    assert all(t >= u - 0.03 for t, u in zip(res["trained"], res["untrained"])), res
 
 
 def test_proj_seed_bench_shape(orc):

@@ -40,15 +40,29 @@ def _check_rows(orc, X, G, D, rel=1e-5):
 
 
 def test_config1_recall(orc):
-    """5,000 x 50 isotropic mixture, k = 15, K_b = 15, rho = 0.5, 8 iterations."""
+    """5,000 x 50 isotropic mixture, k = 15, K_b = 15, rho = 0.5, at most 8
+    iterations, algorithm seeds 0-4, against the sequential oracle NNDescent
+    at the same settings and seeds (tests/golden/config1_nnd.json, written by
+    make_config1_nnd.py).  The GPU batches each iteration's updates, which
+    by itself changes nothing (the join lists are fixed at the iteration's
+    start in both); what it approximates is (a) each member takes at most
+    join_cap = 4 of its best partners from one join list (recall by cap
+    1 / 2 / 3 / 4 measured at 0.823 / 0.906 / 0.933 / 0.942) and (b) hashed
+    candidate slots can collide.  Bar: the oracle's mean minus 0.01."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config1_nnd.json")))
     X = datagen.gmm_isotropic(n=5000, d=50, seed=0)
-    G, D, st = _build(X, 15, max_iters=8, sample_rate=0.5)
-    G, D = G.cpu().numpy(), D.cpu().numpy()
-    _check_rows(orc, X, G, D)
     _, O2 = orc.exact_knn(X, 15)
-    r = orc.recall_at_k(X, np.arange(5000), G, np.sqrt(O2[:, -1]), 15)
-    print("config1 recall", r, st)
-    assert r >= 0.90, (r, st)
+    rs = []
+    for seed in gold["seeds"]:
+        G, D, st = _build(X, 15, max_iters=8, sample_rate=0.5, seed=seed)
+        G, D = G.cpu().numpy(), D.cpu().numpy()
+        _check_rows(orc, X, G, D)
+        rs.append(orc.recall_at_k(X, np.arange(5000), G, np.sqrt(O2[:, -1]), 15))
+    print("config1 recall per seed", rs, "mean", np.mean(rs), "oracle", gold["oracle_recall_at_15"],
+          "mean", gold["oracle_recall_mean"], "iters", st["iters"])
+    assert np.mean(rs) >= gold["oracle_recall_mean"] - 0.01, (rs, gold)
 
 
 def test_recall_improves_with_iterations(orc):
@@ -227,7 +241,9 @@ def test_pixel_like_high_dim(orc):
         assert not np.any(G[rows] == rows[:, None])
         r = orc.recall_at_k(X, rows, G[rows], np.sqrt(O2[:, -1]), 15)
         print("pixel", prec, r, st["iters"])
-        assert r >= 0.5, (prec, r)
+        # defaults: K_b = 15 (FP32) / 30 (BF16), rho = 0.5, 10 iterations;
+        # measured 0.666 / 0.911 (deterministic for the fixed seed)
+        assert r >= {"fp32": 0.64, "bf16": 0.89}[prec], (prec, r)
 
 
 def test_wide_rows(orc):
@@ -242,18 +258,18 @@ def test_wide_rows(orc):
         _, O2 = orc.exact_knn(X, 10, rows=rows)
         r = orc.recall_at_k(X, rows, G.cpu().numpy()[rows], np.sqrt(O2[:, -1]), 10)
         print("wide", prec, r, st["iters"])
-        # isotropic clusters in 1100 dimensions are hard for NNDescent; the
-        # bar only guards against a broken path
-        assert r >= 0.8, (prec, r)
+        # measured 0.911 (FP32, K_b = 10) / 0.998 (BF16, K_b = 20)
+        assert r >= {"fp32": 0.89, "bf16": 0.99}[prec], (prec, r)
 
 
 def test_stats_collisions_and_list_cap(orc):
     """The per-iteration counters: join lists whose caps cannot bind
-    (s + R + K + R <= 64) drop nothing; lists that can exceed 64 members
-    (K = 32, rho = 1) report the members they cut; collisions are counted."""
+    (2 s + K + s <= 64) drop nothing; lists that can exceed 64 members
+    (K = 32, rho = 1) report the members they cut; collisions are counted
+    (64 candidate slots for 15-entry lists)."""
     import paper_2603_04035_amd as knn
     X = torch.from_numpy(datagen.gmm_isotropic(n=5000, d=50, seed=0)).cuda()
-    _, _, st = knn.nndescent_build(X, 15, build_k=15, sample_rate=0.5, max_iters=8, delta=0.0)
+    _, _, st = knn.nndescent_build(X, 15, build_k=15, sample_rate=0.5, max_iters=8, delta=0.0, cand_slots=64)
     assert st["list_dropped"] == [0] * st["iters"]
     assert all(c >= 0 for c in st["slot_collisions"]) and sum(st["slot_collisions"]) > 0
     _, _, st = knn.nndescent_build(X, 15, build_k=32, sample_rate=1.0, max_iters=6, delta=0.0)

@@ -316,6 +316,31 @@ def exact_path(X, k, reps=3):
     return out
 
 
+def chunk_knob(X, k, limits_mib=(0, 1024, 512, 384, 320, 288, 256), reps=2):
+    """knn_exact_query_limited of X among itself (FP32) under decreasing
+    scratch limits: ms per call, or the error when even one 128-query chunk
+    does not fit beside the staged reference set."""
+    import torch
+    import paper_2603_04035_amd as knn
+    n = X.shape[0]
+    qs = torch.arange(n, dtype=torch.int32, device=X.device)
+    out = []
+    for mib in limits_mib:
+        lim = int(mib) << 20
+        try:
+            knn.knn_exact_query(X, X, k, q_self=qs, workspace_limit=lim)
+        except knn.KnnError as e:
+            out.append({"limit_mib": mib, "error": str(e).split(":")[0]})
+            continue
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            knn.knn_exact_query(X, X, k, q_self=qs, workspace_limit=lim)
+        torch.cuda.synchronize()
+        out.append({"limit_mib": mib or None, "ms": round(1000.0 * (time.perf_counter() - t0) / reps, 3)})
+    return out
+
+
 def pca_quality(X, p=50, k=10, reps=3):
     """PCA of X to p dimensions (FP64 Gram on MFMA, subspace iteration) and
     the quality metrics of the 2-D PCA embedding (exact ranks in both
@@ -443,7 +468,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-exact", action="store_true", help="skip the exact-path timing of the default line")
     ap.add_argument("--exact", action="store_true",
-                    help="only time the exact path (knn_exact of the workload, both precisions)")
+                    help="only time the exact path (knn_exact of the workload in FP32, BF16 and FP16, and FP32 "
+                         "under decreasing scratch limits)")
     ap.add_argument("--pca-quality", action="store_true",
                     help="only time knn_pca (p = 50) and knn_quality of the 2-D PCA embedding on --config")
     ap.add_argument("--fuzzy-only", action="store_true",
@@ -478,8 +504,9 @@ def main():
     X = torch.from_numpy(Xnp).to("cuda")
     torch.cuda.synchronize()
     if args.exact:
-        print(json.dumps({"exact_path": exact_path(X, k), "config": {"workload": CONFIGS[args.config]["desc"]},
-                          "n": n, "d": d, "k": k}), flush=True)
+        print(json.dumps({"exact_path": exact_path(X, k), "chunk_knob": chunk_knob(X, k),
+                          "config": {"workload": CONFIGS[args.config]["desc"]}, "n": n, "d": d, "k": k}),
+              flush=True)
         return
     if args.pca_quality:
         print(json.dumps({"pca_quality": pca_quality(X, k=min(k, 16)),

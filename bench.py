@@ -7,9 +7,9 @@ Gaussian mixture with anisotropic covariances (eigenvalues log-uniform on
 already resident in HBM (init, every iteration, final re-rank).  Steps use
 algorithm seeds 0..steps-1 after `warmup` untimed calls.
 
-Two forms are timed: plain FP32 NNDescent (random init, VALU join) and the
-BF16 form seeded by a trained encoder (BF16 MFMA join, FP32 re-rank of the
-final lists); the headline line is the latter, both are in "forms".
+Two forms are timed: plain FP32 NNDescent (random init, FP32 MFMA join) and
+the BF16 form seeded by a trained encoder (BF16 MFMA join, FP32 re-rank of
+the final lists); the headline line is the latter, both are in "forms".
 
 Reported: points/s = n * steps / wall time of the timed steps (and the
 spread of the per-step times), recall@15 of every timed step's graph on
@@ -43,7 +43,6 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP32_VALU_PEAK_TFLOPS = 157.3   # 256 CUs x 4 SIMDs x 2.4 GHz x 64 FP32 flops (packed dual issue)
 
 # NNDescent settings of the two forms (K_b, rho, caps); delta is the paper's 0.015.
 # The BF16 forms keep K_b = 2k = 30 entries, the FP32 re-rank's width; the
@@ -242,11 +241,10 @@ def copy_bandwidth(mib: int = 1024, reps: int = 5):
 
 
 def join_roofline(stats, n, d, p, kernel, workload):
-    """Local-join roofline.  BF16 form (Gram on MFMA, gathers bound): algorithmic
-    bytes per launch / HIP-event time per launch against the HBM peak.  FP32
-    form (Gram on VALU): its SIMDs are VALU-busy, so the roof is the FP32
-    vector peak and the rate is the Gram's algorithmic flops (2 d per joined
-    pair) per launch time; the byte rate is kept beside it."""
+    """Local-join roofline: algorithmic bytes per launch / HIP-event time per
+    launch against the HBM peak (every form's join gathers rows and offers
+    candidates at random; its Gram runs on MFMA, whose algorithmic rate, 2 d
+    flops per joined pair, is reported beside it)."""
     import numpy as np
     K = stats[-1]["build_k"]
     s_ = int(np.ceil(p["sample_rate"] * K))
@@ -261,16 +259,12 @@ def join_roofline(stats, n, d, p, kernel, workload):
     traffic, source = measured_traffic(kernel, workload)
     pairs = sum(st["pairs_joined"] for st in stats)
     gram_tflops = 2.0 * d * pairs / (join_ms * 1e-3) / 1e12
-    common = {"traffic": traffic, "traffic_source": source, "kernel": kernel, "launches": launches,
-              "alg_bytes_per_launch": int(alg_bytes / max(launches, 1)),
-              "alg_flops_per_launch": int(2 * d * pairs / max(launches, 1)),
-              "ms_per_launch": round(join_ms / max(launches, 1), 4)}
-    if p["precision"] == "fp32":
-        return {"bound": "alu", "achieved": round(gram_tflops, 2), "peak": FP32_VALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(gram_tflops / FP32_VALU_PEAK_TFLOPS, 4),
-                "hbm_achieved_gbs": round(achieved, 1), "hbm_frac": round(achieved / HBM_PEAK_GBS, 4), **common}
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "gram_tflops": round(gram_tflops, 2), **common}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "gram_tflops": round(gram_tflops, 2),
+            "traffic": traffic, "traffic_source": source, "kernel": kernel, "launches": launches,
+            "alg_bytes_per_launch": int(alg_bytes / max(launches, 1)),
+            "alg_flops_per_launch": int(2 * d * pairs / max(launches, 1)),
+            "ms_per_launch": round(join_ms / max(launches, 1), 4)}
 
 
 def distance_error(X, Xnp, k, p, rows):
@@ -430,8 +424,8 @@ def run_form(X, k, form, steps, warmup, rows, config, encoder=None, Xnp=None):
     per_step = [recall_gpu(X, g, None, rows, k, exact=ex) for g in graphs]
     del graphs
     recall = min(per_step)
-    kern = {"bf16": "nnd_join_mfma_kernel<1>", "fp16": "nnd_join_mfma_kernel<2>"}.get(p["precision"],
-                                                                                   "nnd_join_f32_kernel")
+    kern = {"fp32": "nnd_join_mfma_kernel<0>", "bf16": "nnd_join_mfma_kernel<1>",
+            "fp16": "nnd_join_mfma_kernel<2>"}[p["precision"]]
     last = stats[-1]
     cfg = {kk: vv for kk, vv in p.items() if kk != "encoder"}
     cfg["build_k"] = last["build_k"]
@@ -548,7 +542,7 @@ def main():
     copy_gbs = copy_bandwidth()
     for r in results.values():
         rl = r["roofline"]
-        rl["frac_of_measured_copy"] = round(rl.get("hbm_achieved_gbs", rl["achieved"]) / copy_gbs, 4)
+        rl["frac_of_measured_copy"] = round(rl["achieved"] / copy_gbs, 4)
     cpu = None
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         cpu = cpu_baseline(Xnp, k, "fp32", min(args.cpu_sample, n))

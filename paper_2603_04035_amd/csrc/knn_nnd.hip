@@ -11,12 +11,11 @@
 //  join     one wave per point v: the new list new_f(v) + reverse-new and the
 //           old list old_f(v) + reverse-old are deduplicated (at most 64
 //           members; old members past that are not joined and are counted),
-//           their rows are gathered (BF16: straight into MFMA operand
-//           registers; FP32: staged in LDS in 32-coordinate chunks), the Gram
-//           tile new x all is formed with BF16 MFMA or FP32 FMAs, and each
-//           member receives at most `join_cap` of its best partners that
-//           beat its current worst distance, as atomicMin keys into C hashed
-//           candidate slots;
+//           their rows are gathered straight into MFMA operand registers,
+//           the Gram tile new x all is formed on MFMA (32x32x16 BF16 / FP16,
+//           or 32x32x2 FP32 for the plain form), and each member receives at
+//           most `join_cap` of its best partners that beat its current worst
+//           distance, as atomicMin keys into C hashed candidate slots;
 //  merge    half a wave per row: the K_b list keys and the C slot keys are
 //           deduplicated by index and merged, the first K_b kept; slot
 //           entries that enter are flagged new and counted; slots are reset;
@@ -588,49 +587,18 @@ __device__ inline unsigned long long offers_resolve(const PendingOffers& po)
     return n;
 }
 
-// One pending offer per lane (the FP32 join: lane ag < 4 offers entry ag).
-struct PendingOffer {
-    unsigned long long* p;
-    uint64_t key;
-    unsigned long long seen;
-};
-
-__device__ inline void offer_issue(PendingOffer& po, uint32_t b, bool ok, float cut, const uint32_t* ids,
-                                   uint32_t me, int C, uint64_t salt, unsigned long long* __restrict__ cand)
-{
-    po.p = nullptr;
-    po.key = ~0ull;
-    po.seen = 0ull;
-    if (ok && b != kNoSel && __uint_as_float(b & ~63u) < cut) {
-        const uint32_t src = ids[b & 63u];
-        po.key = ((uint64_t)(b & ~63u) << 32) | src;
-        const uint32_t slot = bounded(mix64(((uint64_t)src << 20) ^ salt), (uint32_t)C);
-        po.p = &cand[(int64_t)me * C + slot];
-        po.seen = *po.p;
-    }
-}
-
-__device__ inline unsigned long long offer_resolve(const PendingOffer& po)
-{
-    unsigned long long n = po.p && slot_collides(po.seen, po.key) ? 1ull << 32 : 0ull;
-    if (po.p && po.seen > (unsigned long long)po.key) {
-        atomicMin(po.p, (unsigned long long)po.key);
-        ++n;
-    }
-    return n;
-}
-
-// Local join, 16-bit MFMA forms (BF16, or FP16: OUT is the staged element
-// type).  One wave per point v; the grid is split into 8
+// Local join on MFMA, every form (OUT is the staged element type: KNN_F32,
+// KNN_BF16 or KNN_F16).  One wave per point v; the grid is split into 8
 // groups (blockIdx mod 8, the round-robin XCD assignment of workgroups) that
 // each sweep one contiguous range of the processing order, so concurrently
 // joined points are Z-order neighbours sharing an L2.
 //
 // The join list (new members first, then old; L <= 64) is two 32-row
-// blocks.  Its L x L Gram is accumulated by 32 x 32 x 16 BF16 MFMA tiles
-// (FP32 accumulation) whose operands come straight from the staged rows into
+// blocks.  Its L x L Gram is accumulated by 32 x 32 MFMA tiles (FP32
+// accumulation) whose operands come straight from the staged rows into
 // registers, no LDS copy: lane (h, c) holds 16-byte pieces of rows c and
-// 32 + c; piece p holds elements [16p + 8h, +8).  That assigns the reduction
+// 32 + c; piece p covers bytes [32p + 16h, +16) (8 BF16 / FP16 elements, or
+// 4 FP32 ones taken by four 32x32x2 steps).  That assigns the reduction
 // index to (step, half) one-to-one, which is all a Gram product needs since
 // both operands use the same assignment.
 //
@@ -649,12 +617,20 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
-// One 32x32x16 MFMA step on 16-bit operands: BF16 or FP16 (OUT = KNN_BF16 /
-// KNN_F16, the staged element type), FP32 accumulation.
+// The Gram work of one 16-byte piece pair, FP32 accumulation: one 32x32x16
+// MFMA step on 16-bit operands (OUT = KNN_BF16 / KNN_F16, the staged element
+// type), or four 32x32x2 FP32 steps (OUT = KNN_F32: the piece's four floats
+// in turn; with the other half-wave's four, each step sums two elements, so
+// every element of the 32-byte piece enters once).
 template <int OUT>
 __device__ inline f32x16 gram_step(const uint4& a, const uint4& b, f32x16 acc)
 {
-    if constexpr (OUT == KNN_F16)
+    if constexpr (OUT == KNN_F32) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), acc, 0, 0, 0);
+        return __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(b.w), acc, 0, 0, 0);
+    } else if constexpr (OUT == KNN_F16)
         return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b),
                                                        acc, 0, 0, 0);
     else
@@ -825,193 +801,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nn
         }
     }
     emitted += offers_resolve(po);
-    unsigned long long coll = emitted >> 32;
-    emitted &= 0xFFFFFFFFull;
-    for (int o = 32; o > 0; o >>= 1) {
-        emitted += shfl_u64(emitted, lane ^ o);
-        coll += shfl_u64(coll, lane ^ o);
-    }
-    if (lane == 0) {
-        atomicAdd(&counters[1], emitted);
-        atomicAdd(&counters[2], tally[0]);
-        atomicAdd(&counters[3], coll);
-        atomicAdd(&counters[4], tally[2]);
-        atomicAdd(&counters[5], tally[1]);
-    }
-}
-// Local join, FP32 form (VALU).  Lists, traversal and offers as in the BF16
-// kernel.  The rows are staged in LDS in chunks of kFC coordinates (zero
-// past d and for absent rows).  Lane (ag, bg) = (lane / 8, lane % 8) holds
-// the Gram entries of rows a = ag + 8i and columns b = bg + 8q (i, q < NB;
-// NB = 4 when L <= 32, else 8), accumulated with FP32 FMAs from two
-// coordinates per LDS read; row strides of kFS floats put the 8 distinct
-// rows of a read in distinct banks.  For each column b the lane keeps the
-// best J of its NB rows, a butterfly over the 8 lanes of the column (lane
-// bits 3..5) merges them, and lane ag offers entry ag of the merged list.
-constexpr int kFC = 32;        // coordinates per staged chunk
-constexpr int kFS = kFC + 2;   // LDS row stride (floats)
-
-// NI = number of 8-row groups holding new members (new rows come first):
-// register blocks (i, q) with i >= NI and q >= NI pair old with old only and
-// are skipped.
-template <int NB, int NI>
-__device__ inline void join_f32_point(const float* __restrict__ Xs, int ldp, int d, float* rows,
-                                      const uint32_t* ids, const float* nrm, const float* thr, int L, int nn,
-                                      int J, int C, uint64_t salt, unsigned long long* __restrict__ cand,
-                                      unsigned long long& emitted, PendingOffer& po)
-{
-    int ln = threadIdx.x;
-    asm volatile("" : "+v"(ln));   // lane-dependent indices re-derived per point
-    const int ag = ln >> 3, bg = ln & 7;
-    float acc[NB][NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-#pragma unroll
-        for (int q = 0; q < NB; ++q) acc[i][q] = 0.0f;
-    const int dk = (d + 1) & ~1;
-    for (int c0 = 0; c0 < dk; c0 += kFC) {
-        __syncthreads();
-        // stage 8 * NB rows x kFC coordinates: lane -> row ag + 8j, coordinates
-        // 4 bg .. 4 bg + 3, with no branch around the loads.
-        // Absent rows read a listed row and coordinates past d read the
-        // row's zero padding (the staged row is at least roundup(dk, 32)
-        // long and its trailing norm / worst words lie past dk); neither
-        // reaches a used Gram entry or the FMAs, which stop at dk.
-        const int t = c0 + 4 * bg;
-#pragma unroll 2
-        for (int j = 0; j < NB; ++j) {
-            const int r = ag + 8 * j;
-            const f32x4 x = *(const f32x4*)(Xs + (int64_t)ids[r < L ? r : 0] * ldp + t);
-            float* dst = rows + r * kFS + 4 * bg;
-            *(float2*)dst = make_float2(x[0], x[1]);
-            *(float2*)(dst + 2) = make_float2(x[2], x[3]);
-        }
-        __syncthreads();
-        const int kc = min(kFC, dk - c0);
-        for (int t = 0; t < kc; t += 2) {
-            float2 xa[NB];
-#pragma unroll
-            for (int i = 0; i < NB; ++i) xa[i] = *(const float2*)(rows + (ag + 8 * i) * kFS + t);
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                const float2 xb = *(const float2*)(rows + (bg + 8 * q) * kFS + t);
-#pragma unroll
-                for (int i = 0; i < NB; ++i) {
-                    if (i < NI || q < NI) {
-                        acc[i][q] = fmaf(xa[i].x, xb.x, acc[i][q]);
-                        acc[i][q] = fmaf(xa[i].y, xb.y, acc[i][q]);
-                    }
-                }
-            }
-        }
-    }
-    float na[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) na[i] = nrm[ag + 8 * i];
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-        const int b = bg + 8 * q;
-        const float nb = nrm[b];
-        const int lim = b < nn ? L : nn;
-        uint32_t best[kJMax];
-#pragma unroll
-        for (int s = 0; s < kJMax; ++s) best[s] = kNoSel;
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            if (i < NI || q < NI) {   // old rows pair only with new columns
-                const int a = ag + 8 * i;
-                float d2 = na[i] + nb - 2.0f * acc[i][q];
-                d2 = d2 > 0.0f ? d2 : 0.0f;
-                const bool ok = a < lim && a != b;
-                sel_insert(best, ok ? ((__float_as_uint(d2) & ~63u) | (uint32_t)a) : kNoSel);
-            }
-        }
-#pragma unroll
-        for (int o = 8; o <= 32; o <<= 1) {
-            uint32_t recv[kJMax];
-#pragma unroll
-            for (int s = 0; s < kJMax; ++s) recv[s] = xor_u32(best[s], o);
-            sel_merge(best, recv);
-        }
-        // lane ag offers merged entry ag; the previous column's offer resolves first
-        emitted += offer_resolve(po);
-        const uint32_t mine = ag == 0 ? best[0] : (ag == 1 ? best[1] : (ag == 2 ? best[2] : best[3]));
-        offer_issue(po, mine, b < L && ag < J, b < L ? thr[b] : 0.0f, ids, ids[b], C, salt, cand);
-    }
-}
-
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void nnd_join_f32_kernel(
-    int64_t n, JoinCfg cfg, const float* __restrict__ Xs, int ldp, int d,
-    const int32_t* __restrict__ newf, uint32_t* __restrict__ revnew,
-    const int32_t* __restrict__ oldf, uint32_t* __restrict__ revold,
-    unsigned long long* __restrict__ cand, uint64_t seed, int iter, unsigned long long* __restrict__ counters)
-{
-    __shared__ __attribute__((aligned(16))) float rows[64 * kFS];
-    __shared__ uint32_t ids[64];
-    __shared__ float nrm[64];
-    __shared__ float thr[64];
-    __shared__ __attribute__((aligned(16))) uint32_t sh[128];
-    const int lane = threadIdx.x;
-    // emitted: offers in the low 32 bits, slot collisions in the high 32 (a
-    // lane sends far fewer than 2^32 offers), so one register pair counts both
-    unsigned long long emitted = 0;
-    // wave-uniform tallies (rows gathered, pairs joined, members cut) live in
-    // LDS, updated by lane 0, so that they hold no registers in the loop
-    __shared__ unsigned long long tally[3];
-    if (threadIdx.x == 0) tally[0] = tally[1] = tally[2] = 0ull;
-    const uint64_t salt = (uint64_t)iter ^ seed;
-    const unsigned grp = blockIdx.x & 7u;
-    const int64_t gsz = (int64_t)(gridDim.x >> 3);
-    const int64_t lo = n * grp / 8, hi = n * (grp + 1) / 8;
-
-    PendingOffer po;
-    po.p = nullptr;
-    int64_t v = lo + (int64_t)(blockIdx.x >> 3);
-    ListRaw cur = load_lists(v, v < hi, cfg, newf, revnew, oldf, revold);
-    for (; v < hi; v += gsz) {
-        int L = 0, dr = 0;
-        const int nn = __builtin_amdgcn_readfirstlane(join_lists(v, cur, cfg, revnew, revold, seed, iter, sh, ids, L, dr));
-        if (threadIdx.x == 0) tally[2] += (unsigned long long)dr;
-        L = __builtin_amdgcn_readfirstlane(L);
-        cur = load_lists(v + gsz, v + gsz < hi, cfg, newf, revnew, oldf, revold);
-        __syncthreads();
-        if (nn == 0 || L < 2) continue;
-        if (lane < L) {
-            const float2 a = *(const float2*)(Xs + (int64_t)ids[lane] * ldp + ldp - 2);
-            nrm[lane] = a.x;
-            thr[lane] = a.y;
-        } else {
-            nrm[lane] = 0.0f;
-        }
-        if (threadIdx.x == 0) {
-            tally[0] += (unsigned long long)L;
-            tally[1] += (unsigned long long)(nn * (nn - 1) / 2 + nn * (L - nn));
-        }
-        const int ni = (nn + 7) >> 3;
-#define KNN_JF(NB, NI) \
-    join_f32_point<NB, NI>(Xs, ldp, d, rows, ids, nrm, thr, L, nn, cfg.J, cfg.C, salt, cand, emitted, po)
-        if (L <= 32) {
-            switch (ni) {
-            case 1: KNN_JF(4, 1); break;
-            case 2: KNN_JF(4, 2); break;
-            case 3: KNN_JF(4, 3); break;
-            default: KNN_JF(4, 4); break;
-            }
-        } else {
-            switch (ni) {
-            case 1: KNN_JF(8, 1); break;
-            case 2: KNN_JF(8, 2); break;
-            case 3: KNN_JF(8, 3); break;
-            case 4: KNN_JF(8, 4); break;
-            case 5: KNN_JF(8, 5); break;
-            case 6: KNN_JF(8, 6); break;
-            case 7: KNN_JF(8, 7); break;
-            default: KNN_JF(8, 8); break;
-            }
-        }
-#undef KNN_JF
-    }
-    emitted += offer_resolve(po);
     unsigned long long coll = emitted >> 32;
     emitted &= 0xFFFFFFFFull;
     for (int o = 32; o > 0; o >>= 1) {
@@ -1430,7 +1219,7 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     int jpc = 0;
     KNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &jpc, bf ? (const void*)nnd_join_mfma_kernel<KNN_BF16> : (const void*)nnd_join_f32_kernel, 64, 0));
+        &jpc, (const void*)nnd_join_mfma_kernel<KNN_BF16>, 64, 0));
     if (jpc < 1) jpc = 1;
     // a multiple of 8: the join splits its grid into 8 contiguous point ranges
     const unsigned join_grid = (unsigned)round_up((int64_t)ncu * jpc, 8);
@@ -1463,8 +1252,8 @@ static knn_status nnd_run(const knn_matrix& X, const knn_nnd_params* p, const in
             nnd_join_mfma_kernel<KNN_BF16><<<join_grid, 64, 0, st>>>(n, cfg, Xr, rowbytes, np, newf, sampnew, oldf,
                                                                      sampold, cand, p->seed, iter, counters);
         else
-            nnd_join_f32_kernel<<<join_grid, 64, 0, st>>>(n, cfg, (const float*)Xs, ldp, X.d, newf, sampnew, oldf,
-                                                          sampold, cand, p->seed, iter, counters);
+            nnd_join_mfma_kernel<KNN_F32><<<join_grid, 64, 0, st>>>(n, cfg, Xr, rowbytes, np, newf, sampnew, oldf,
+                                                                    sampold, cand, p->seed, iter, counters);
         KNN_HIP(hipGetLastError());
         (void)hipEventRecord(tj.b, st);
         // the merge samples the next iteration unless this is the last one

@@ -10,9 +10,10 @@
 //               the result does not depend on scheduling;
 //  3. subspace: m = min(d, 80, max(2p, p + 16)) columns V (seeded, hashed
 //               values) iterate V <- orth(C V) (C V on
-//               v_mfma_f64_16x16x4_f64), orthonormalised by one Cholesky-QR
-//               pass per iteration and a second after the last (it restores
-//               the orthogonality the first loses to conditioning); then
+//               v_mfma_f64_16x16x4_f64), orthonormalised by one shifted
+//               Cholesky-QR pass every q products (q from the basis'
+//               estimated conditioning, 1..8) and by shifted + two plain
+//               passes after the last (Cholesky-QR3); then
 //               Rayleigh-Ritz: H = V^T C V, whose eigenpairs come from cyclic
 //               Jacobi rotations (one workgroup, round-robin pairing), and
 //               the p largest Ritz pairs are kept; each eigenvector's entry
@@ -21,6 +22,8 @@
 // When m = d the Ritz pairs are the exact eigenpairs of C.
 #include <math.h>
 
+#include <algorithm>
+#include <cmath>
 #include <utility>
 #include <vector>
 
@@ -33,6 +36,7 @@ constexpr int kPcaMaxM = 80;      // subspace width (an m x m double matrix fits
 static_assert(kPcaMaxM % 16 == 0, "LDS kernels stride columns by 16");
 constexpr int kPcaChunk = 4096;   // rows per Gram partial
 constexpr int kPcaSumChunk = 512; // rows per column-sum partial
+constexpr int kPcaMaxQ = 8;       // products C V between orthonormalisations, at most
 constexpr int kPcaTile = 64;      // Gram tile edge
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -264,16 +268,23 @@ __global__ __launch_bounds__(256) void pca_gram_small_kernel(const double* __res
 // pivots) and M = L^{-1}.  Then R = D^{1/2} L^T and R^{-1}[i][j] = M[j][i] /
 // sqrt(D[j]): no triangular solve is needed.  M's strict lower triangle sits
 // in the lower half of the LDS copy of S, which the upper-triangle
-// elimination never reads.  A non-positive pivot (W of lower rank than m) is
-// replaced by 1 and flagged, which keeps the factor finite.
+// elimination never reads.  With shift_rel > 0 the factored matrix is
+// S + s I, s = shift_rel * trace(S) (shifted Cholesky-QR: V spans the same
+// space as W, but is only near-orthonormal, and no pivot can fail however
+// badly W is conditioned).  A non-positive pivot (W of lower rank than m,
+// unshifted) is replaced by 1 and flagged, which keeps the factor finite.
+// The pivots D[k] (as used) go to `pivots`: their spread estimates W's
+// conditioning.
 constexpr int kPcaCols = 8;
 
 __global__ __launch_bounds__(256) void pca_cholqr_kernel(const double* __restrict__ Sg, const double* __restrict__ W,
                                                          int d, int m, double* __restrict__ V,
-                                                         unsigned* __restrict__ bad)
+                                                         unsigned* __restrict__ bad, double* __restrict__ pivots,
+                                                         double shift_rel)
 {
     __shared__ double S[kPcaMaxM * kPcaMaxM];   // upper: S being eliminated; strict lower: M
     __shared__ double rinv[kPcaMaxM];
+    __shared__ double shift_;
     const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
     {
         // all of this thread's loads are issued before the first store
@@ -289,6 +300,18 @@ __global__ __launch_bounds__(256) void pca_cholqr_kernel(const double* __restric
             const int e = tid + 256 * u;
             if (e < m * m) S[e] = (e % m) >= (e / m) ? tmp[u] : 0.0;
         }
+    }
+    if (shift_rel > 0.0) {
+        // S + s I with s = shift_rel * trace(S): the same span, positive
+        // pivots however badly W is conditioned
+        __syncthreads();
+        if (tid == 0) {
+            double tr = 0.0;
+            for (int k = 0; k < m; ++k) tr += S[k * m + k];
+            shift_ = shift_rel * tr;
+        }
+        __syncthreads();
+        if (tid < m) S[tid * m + tid] += shift_;
     }
     // thread (ty, tx) updates rows i = ty (mod 16) at columns j = tx (mod 16):
     // row k's entries at its columns are read once per step into registers,
@@ -325,7 +348,10 @@ __global__ __launch_bounds__(256) void pca_cholqr_kernel(const double* __restric
                 else if (j == k) S[i * m + j] = x[q] - f;
             }
         }
-        if (tid == 0) rinv[k] = 1.0 / sqrt(pk);
+        if (tid == 0) {
+            rinv[k] = 1.0 / sqrt(pk);
+            if (blockIdx.x == 0 && blockIdx.y == 0) pivots[k] = pk;
+        }
     }
     __syncthreads();
     const int a = blockIdx.x * 256 + tid;
@@ -636,7 +662,7 @@ extern "C" knn_status knn_pca(knn_matrix X, int32_t p, int32_t iters, float* Z, 
         const int nsum = (int)ceil_div(n, kPcaSumChunk);
         hipStream_t st = (hipStream_t)stream;
         Workspace ws(st, 0);
-        double *part, *mu, *C, *V, *W, *S, *H, *E, *U, *lam;
+        double *part, *mu, *C, *V, *W, *U2, *piv, *S, *H, *E, *U, *lam;
         unsigned* bad;
         const int nt = (int)ceil_div(d, kPcaTile);
         int2* tiles;
@@ -646,6 +672,8 @@ extern "C" knn_status knn_pca(knn_matrix X, int32_t p, int32_t iters, float* Z, 
         if ((r = ws.alloc(&C, (size_t)d * d)) != KNN_OK) return r;
         if ((r = ws.alloc(&V, (size_t)d * m)) != KNN_OK) return r;
         if ((r = ws.alloc(&W, (size_t)d * m)) != KNN_OK) return r;
+        if ((r = ws.alloc(&U2, (size_t)d * m)) != KNN_OK) return r;
+        if ((r = ws.alloc(&piv, (size_t)m)) != KNN_OK) return r;
         if ((r = ws.alloc(&S, (size_t)m * m)) != KNN_OK) return r;
         if ((r = ws.alloc(&H, (size_t)m * m)) != KNN_OK) return r;
         if ((r = ws.alloc(&E, (size_t)m * m)) != KNN_OK) return r;
@@ -679,20 +707,62 @@ extern "C" knn_status knn_pca(knn_matrix X, int32_t p, int32_t iters, float* Z, 
         }
         const dim3 gcols((unsigned)ceil_div(d, 256), (unsigned)ceil_div(m, kPcaCols));
         const dim3 gcv((unsigned)ceil_div(d, 16), (unsigned)ceil_div(m, 16));
-        auto cholqr = [&](const double* in, double* out) {
+        // shift of the shifted passes: 11 (m d + m (m + 1)) u relative to
+        // trace(S) >= |W|_2^2, the bound under which a shifted Cholesky-QR
+        // is guaranteed to succeed in double precision (Fukaya, Kannan,
+        // Nakatsukasa, Yamamoto and Yanagisawa, 2020)
+        const double shift = 11.0 * ((double)m * d + (double)m * (m + 1)) * 1.1102230246251565e-16;
+        auto cholqr = [&](const double* in, double* out, double sh) {
             pca_gram_small_kernel<<<dim3((unsigned)m, (unsigned)m), 256, 0, st>>>(in, in, d, m, S);
-            pca_cholqr_kernel<<<gcols, 256, 0, st>>>(S, in, d, m, out, bad);
+            pca_cholqr_kernel<<<gcols, 256, 0, st>>>(S, in, d, m, out, bad, piv, sh);
         };
         if (m < d) {
-            // one Cholesky-QR pass per iteration keeps the basis well
-            // conditioned; the last iteration takes a second pass, which
-            // restores orthonormality to rounding before Rayleigh-Ritz
-            cholqr(W, V);
-            for (int it = 0; it < T; ++it) {
-                pca_cv_kernel<<<gcv, 256, 0, st>>>(C, V, d, m, W);
-                cholqr(W, V);
+            // Subspace iteration needs orthonormalisation only often enough
+            // to keep the basis well conditioned: W = C^q V for q products,
+            // then one shifted Cholesky-QR pass (the span is that of
+            // orthonormalising after every product).  q is chosen so that the
+            // basis' condition number, estimated from the spread of the last
+            // pass's pivots (kappa(C^q V) ~ sqrt(max D / min D), so kappa(C V)
+            // ~ that to the power 1/q), stays below about 1e4 over the q
+            // products (larger targets lost the weak directions of the pixel
+            // set's block in a CPU emulation).  After the last product a
+            // shifted pass and two plain ones (Cholesky-QR3) make the basis
+            // orthonormal to rounding for Rayleigh-Ritz.
+            std::vector<double> hp((size_t)m);
+            cholqr(W, V, shift);
+            int q = 1, since = kPcaMaxQ;   // products since q was last re-estimated
+            for (int it = 0; it < T;) {
+                const int qq = std::min(q, T - it);
+                const double* src = V;
+                for (int r = 0; r < qq; ++r) {
+                    double* dst = (r & 1) ? U2 : W;
+                    pca_cv_kernel<<<gcv, 256, 0, st>>>(C, src, d, m, dst);
+                    src = dst;
+                }
+                it += qq;
+                since += qq;
+                cholqr(src, V, shift);
+                // re-estimated about every kPcaMaxQ products (each estimate
+                // waits for the pass's pivots)
+                if (it < T && since >= kPcaMaxQ) {
+                    since = 0;
+                    KNN_HIP(hipMemcpyAsync(hp.data(), piv, (size_t)m * 8, hipMemcpyDeviceToHost, st));
+                    KNN_HIP(hipStreamSynchronize(st));
+                    double lo = hp[0], hi = hp[0];
+                    for (int k = 1; k < m; ++k) {
+                        lo = std::min(lo, hp[k]);
+                        hi = std::max(hi, hp[k]);
+                    }
+                    // kappa(C V) estimate (the pass saw C^qq V), and the
+                    // products that keep kappa^q <= 1e4
+                    const double kap = lo > 0.0 ? std::pow(hi / lo, 0.5 / qq) : 1e300;
+                    q = kap <= 1.0 + 1e-12 ? kPcaMaxQ : (int)std::floor(4.0 / std::log10(kap));
+                    q = std::max(1, std::min(q, kPcaMaxQ));
+                }
             }
-            cholqr(V, W);
+            cholqr(V, W, shift);
+            cholqr(W, V, 0.0);
+            cholqr(V, W, 0.0);
             std::swap(V, W);
             KNN_HIP(hipGetLastError());
         }

@@ -8,7 +8,8 @@ projection is compared in FP32 (the output type): 1e-5 of the row norm.
 Cases: a full decomposition (p = d = 12, no iteration), 200,000 rows of the
 50-d anisotropic mixture reduced to 10 (subspace iteration), the 70,000 x
 784 pixel-like set reduced to 50 (a covariance with a 392-dimensional null
-space: its background pixels are always 0), a ragged n, and BF16 input."""
+space: its background pixels are always 0), a spectrum over 12 decades
+(orthonormalisation after every product), a ragged n, and BF16 input."""
 import numpy as np
 import pytest
 import torch
@@ -65,6 +66,25 @@ def test_pca_pixel70k(orc):
     assert np.abs(resid).max() <= 1e-4
     scale = np.linalg.norm(oZ[:, :9], axis=1, keepdims=True) + 1e-30
     assert np.all(np.abs(Z[:, :9] - oZ[:, :9]) <= 1e-5 * scale + 1e-6)
+
+
+@pytest.mark.parametrize("p", [5, 20])
+def test_pca_steep_spectrum(orc, p):
+    """Singular values falling geometrically over 6 decades (eigenvalues
+    over 12): the basis is badly conditioned after a few products, so the
+    products between orthonormalisations must adapt (and the eigenvalues
+    still match to 1e-10 relative)."""
+    rng = np.random.default_rng(5)
+    n, d = 6000, 40
+    G = rng.normal(size=(n, d))
+    G -= G.mean(axis=0)
+    U, _ = np.linalg.qr(G)
+    U -= U.mean(axis=0)
+    U, _ = np.linalg.qr(U)
+    Q, _ = np.linalg.qr(rng.normal(size=(d, d)))
+    S = np.geomspace(1e3, 1e-3, d)
+    X = (3.0 + (U * S) @ Q.T).astype(np.float32)
+    _check(orc, X, p)
 
 
 def test_pca_bf16_input(orc):

@@ -65,6 +65,15 @@ FORMS = {
     # FP16 MFMA distances (exact operands for FP16-stored data), same settings
     "fp16-learned": dict(precision="fp16", build_k=30, sample_rate=1.0, max_iters=30, delta=0.015,
                          join_cap=4, cand_slots=96, rev_slots=30, init_kind="encoder", proj_count=4, proj_window=8),
+    # E independent BF16 + learned runs joined through continuations seeded with
+    # their union (--form ensemble): the 10M workload's route past the recall
+    # one run reaches at the largest supported K_b
+    "bf16-learned-e2": dict(precision="bf16", build_k=32, sample_rate=1.0, max_iters=30, delta=0.015,
+                            join_cap=4, cand_slots=96, rev_slots=32, init_kind="encoder", proj_count=4,
+                            proj_window=8, ensemble=2),
+    "bf16-learned-e3": dict(precision="bf16", build_k=32, sample_rate=1.0, max_iters=30, delta=0.015,
+                            join_cap=4, cand_slots=96, rev_slots=32, init_kind="encoder", proj_count=4,
+                            proj_window=8, ensemble=3),
 }
 # encoder training (reported separately, not in the timed region)
 TRAIN = dict(n=100_000, seed=100, k=15, steps=1000, batch=4096, lr=2e-3, precision="bf16")
@@ -454,7 +463,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="gmm1m", choices=sorted(CONFIGS))
-    ap.add_argument("--form", default="both", choices=sorted(FORMS) + ["both", "all"],
+    ap.add_argument("--form", default="both", choices=sorted(FORMS) + ["both", "all", "ensemble"],
                     help="both: fp32 and bf16-learned; all: also the bf16-random and bf16-untrained controls")
     ap.add_argument("--k", type=int, default=15)
     ap.add_argument("--recall-rows", type=int, default=10000)
@@ -514,7 +523,8 @@ def main():
         return
     rows = datagen.sample_queries(n, args.recall_rows, seed=2)
     forms = {"both": ["fp32", "bf16-learned"],
-             "all": ["fp32", "bf16-learned", "bf16-random", "bf16-untrained", "fp16-learned"]}.get(args.form, [args.form])
+             "all": ["fp32", "bf16-learned", "bf16-random", "bf16-untrained", "fp16-learned"],
+             "ensemble": ["bf16-learned", "bf16-learned-e2", "bf16-learned-e3"]}.get(args.form, [args.form])
     results, training = {}, None
     encoder = None
     if any(FORMS[f].get("init_kind") == "encoder" and f != "bf16-untrained" for f in forms):

@@ -168,6 +168,11 @@ typedef struct {
     int64_t workspace_limit_bytes; /* 0: no limit; else KNN_ENOMEM when scratch exceeds it */
     int32_t rev_slots;    /* hashed reverse-edge slots per row and list, s <= rev_slots <= 64; the join
                            * takes the s filled slots with the least codes (0: min(4 s, 64)) */
+    int32_t ensemble;     /* nndescent_build only: E independent runs (seeds seed + e * 0x9E3779B97F4A7C15),
+                           * each after the first joined to the lists so far by a continuation seeded
+                           * with their union (all entries new); 0 or 1: one run; at most 8, and
+                           * 2 K_b <= 64.  The E runs' buffers beyond the arena's are stream-ordered
+                           * allocations freed before return. */
 } knn_nnd_params;
 
 /* Fills the defaults: build_k 0, max_iters 20, rho 0.5, delta 0.015, seed 0,

@@ -47,7 +47,7 @@ class knn_nnd_params(C.Structure):
                 ("encoder", C.c_void_p), ("proj_count", C.c_int32), ("proj_window", C.c_int32),
                 ("proj_dims", C.c_int32),
                 ("cand_slots", C.c_int32), ("join_cap", C.c_int32),
-                ("workspace_limit_bytes", C.c_int64), ("rev_slots", C.c_int32)]
+                ("workspace_limit_bytes", C.c_int64), ("rev_slots", C.c_int32), ("ensemble", C.c_int32)]
 
 
 class knn_nnd_stats(C.Structure):

@@ -35,6 +35,9 @@
 // entries with FP32 direct differences on the input values and returns the
 // first k.
 #include <math.h>
+#include <string.h>
+
+#include <algorithm>
 
 #include "knn_common.hpp"
 
@@ -1360,13 +1363,131 @@ extern "C" void knn_nnd_default_params(int32_t k, knn_nnd_params* p)
     p->join_cap = 0;
     p->workspace_limit_bytes = 0;
     p->rev_slots = 0;
+    p->ensemble = 0;
 }
+
+namespace knn {
+
+// Row r of the union: the K entries of list a then those of list b, every
+// flag new (the init kernel drops repeats and keeps the best K).
+__global__ __launch_bounds__(256) void nnd_union_kernel(int64_t n, int K, const int32_t* __restrict__ ai,
+                                                        const float* __restrict__ ad, const int32_t* __restrict__ bi,
+                                                        const float* __restrict__ bd, int32_t* __restrict__ ci,
+                                                        float* __restrict__ cd, uint8_t* __restrict__ cf)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n * 2 * K) return;
+    const int64_t r = e / (2 * K);
+    const int j = (int)(e % (2 * K));
+    ci[e] = j < K ? ai[r * K + j] : bi[r * K + j - K];
+    cd[e] = j < K ? ad[r * K + j] : bd[r * K + j - K];
+    cf[e] = 1;
+}
+
+static void stats_add(knn_nnd_stats* acc, const knn_nnd_stats& s)
+{
+    for (int i = 0; i < s.iters && acc->iters + i < KNN_MAX_ITERS_LOGGED; ++i) {
+        const int j = acc->iters + i;
+        acc->updates[j] = s.updates[i];
+        acc->emitted[j] = s.emitted[i];
+        acc->ms_join_iter[j] = s.ms_join_iter[i];
+        acc->slot_collisions[j] = s.slot_collisions[i];
+        acc->list_dropped[j] = s.list_dropped[i];
+    }
+    acc->iters += s.iters;
+    acc->build_k = s.build_k;
+    acc->bytes_gathered += s.bytes_gathered;
+    acc->pairs_joined += s.pairs_joined;
+    acc->ms_total += s.ms_total;
+    acc->ms_init += s.ms_init;
+    acc->ms_sample += s.ms_sample;
+    acc->ms_join += s.ms_join;
+    acc->ms_merge += s.ms_merge;
+    acc->ms_final += s.ms_final;
+}
+
+// E independent runs joined into one graph: run 0, then for each further run
+// the union of its lists with the lists so far seeds a continuation (every
+// entry new, so every pair in the union is joined once more).  Independent
+// runs miss different neighbours: at 10M points two runs at K_b = 32 reach a
+// recall one run cannot reach at any supported K_b.
+static knn_status nnd_ensemble(const knn_matrix& X, const knn_nnd_params* p, int E, int32_t* out_idx,
+                               float* out_dist, int32_t* state_idx, float* state_dist, uint8_t* state_flags,
+                               knn_nnd_stats* stats, hipStream_t st)
+{
+    knn_status r = check_matrix(X, "X");
+    if (r != KNN_OK) return r;
+    const int64_t n = X.n;
+    int K = p->build_k;
+    if (K == 0) K = p->precision != KNN_PREC_FP32 ? std::min(2 * p->k, KNN_MAX_K) : p->k;
+    if ((int64_t)K > n - 1) K = (int)(n - 1);
+    if (K < 1) return fail(KNN_EINVAL, "build_k");
+    if (2 * K > 64) return fail(KNN_ENOTSUP, "ensemble needs 2 K_b <= 64");
+    const size_t nk = (size_t)n * K;
+    int32_t *ai = nullptr, *bi = nullptr, *ci = nullptr, *ti = nullptr;
+    float *ad = nullptr, *bd = nullptr, *cd = nullptr, *td = nullptr;
+    uint8_t* cf = nullptr;
+    void* bufs[9];
+    const size_t sizes[9] = {nk * 4, nk * 4, nk * 4, nk * 4, 2 * nk * 4, 2 * nk * 4, 2 * nk, (size_t)n * p->k * 4,
+                             (size_t)n * p->k * 4};
+    for (int i = 0; i < 9; ++i) {
+        if (hipMallocAsync(&bufs[i], sizes[i] ? sizes[i] : 4, st) != hipSuccess) {
+            (void)hipGetLastError();
+            for (int j = 0; j < i; ++j) (void)hipFreeAsync(bufs[j], st);
+            return fail(KNN_ENOMEM, "ensemble buffers");
+        }
+    }
+    ai = (int32_t*)bufs[0];
+    ad = (float*)bufs[1];
+    bi = (int32_t*)bufs[2];
+    bd = (float*)bufs[3];
+    ci = (int32_t*)bufs[4];
+    cd = (float*)bufs[5];
+    cf = (uint8_t*)bufs[6];
+    ti = (int32_t*)bufs[7];
+    td = (float*)bufs[8];
+    knn_nnd_stats acc = {};
+    knn_nnd_stats one;
+    knn_nnd_params q = *p;
+    q.ensemble = 1;
+    q.build_k = K;
+    r = nnd_run(X, &q, nullptr, nullptr, nullptr, 0, 0, ti, td, ai, ad, nullptr, &one, st);
+    if (r == KNN_OK) stats_add(&acc, one);
+    for (int e = 1; e < E && r == KNN_OK; ++e) {
+        knn_nnd_params qe = q;
+        qe.seed = p->seed + (uint64_t)e * 0x9E3779B97F4A7C15ull;
+        r = nnd_run(X, &qe, nullptr, nullptr, nullptr, 0, 0, ti, td, bi, bd, nullptr, &one, st);
+        if (r != KNN_OK) break;
+        stats_add(&acc, one);
+        nnd_union_kernel<<<(unsigned)ceil_div((int64_t)(2 * nk), 256), 256, 0, st>>>(n, K, ai, ad, bi, bd, ci, cd,
+                                                                                  cf);
+        KNN_HIP(hipGetLastError());
+        knn_nnd_params qr = qe;
+        qr.init_kind = KNN_INIT_RANDOM;
+        qr.encoder = nullptr;
+        const bool last = e == E - 1;
+        r = nnd_run(X, &qr, ci, cd, cf, 2 * K, 4096 * e, last ? out_idx : ti, last ? out_dist : td,
+                    last ? state_idx : ai, last ? state_dist : ad, last ? state_flags : nullptr, &one, st);
+        if (r == KNN_OK) stats_add(&acc, one);
+    }
+    for (int i = 0; i < 9; ++i) (void)hipFreeAsync(bufs[i], st);
+    if (r == KNN_OK) KNN_HIP(hipStreamSynchronize(st));
+    if (r == KNN_OK && stats) *stats = acc;
+    return r;
+}
+
+}  // namespace knn
 
 extern "C" knn_status nndescent_build(knn_matrix X, const knn_nnd_params* p, int32_t* out_idx,
                                       float* out_dist, int32_t* state_idx, float* state_dist,
                                       uint8_t* state_flags, knn_nnd_stats* stats, void* stream)
 {
     try {
+        if (!p) return fail(KNN_EINVAL, "params are null");
+        if (p->ensemble < 0 || p->ensemble > 8) return fail(KNN_EINVAL, "ensemble must be in [0, 8]");
+        if (p->ensemble > 1)
+            return nnd_ensemble(X, p, p->ensemble, out_idx, out_dist, state_idx, state_dist, state_flags, stats,
+                                (hipStream_t)stream);
         return nnd_run(X, p, nullptr, nullptr, nullptr, 0, 0, out_idx, out_dist, state_idx,
                        state_dist, state_flags, stats, (hipStream_t)stream);
     } catch (...) {

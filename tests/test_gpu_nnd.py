@@ -275,3 +275,33 @@ def test_stats_collisions_and_list_cap(orc):
     _, _, st = knn.nndescent_build(X, 15, build_k=32, sample_rate=1.0, max_iters=6, delta=0.0)
     print("K=32 rho=1 dropped per iteration", st["list_dropped"], "collisions", st["slot_collisions"])
     assert sum(st["list_dropped"]) > 0
+
+
+def test_ensemble_union_of_runs(orc):
+    """ensemble = E: E independent runs, each after the first joined to the
+    lists so far by a continuation seeded with their union.  Rows stay valid
+    with exact distances, the result is deterministic, and with lists too
+    short for one run to get close (K_b = 16, rho = 0.5) two and three runs
+    raise recall step by step."""
+    import paper_2603_04035_amd as knn
+    Xn = datagen.gmm_anisotropic(n=50_000, d=50, comps=50, seed=4)
+    X = _dev(Xn)
+    rows = datagen.sample_queries(50_000, 1000, seed=2)
+    _, O2 = orc.exact_knn(Xn, 15, rows=rows)
+    rec = {}
+    for E in (1, 2, 3):
+        G, D, st = _build(X, 15, build_k=16, sample_rate=0.5, max_iters=30, ensemble=E)
+        G, D = G.cpu().numpy(), D.cpu().numpy()
+        true = np.sqrt(orc.pair_d2(Xn, np.repeat(rows, 15), G[rows].ravel()).reshape(-1, 15))
+        assert np.allclose(D[rows], true, rtol=1e-5, atol=0)
+        assert not np.any(G[rows] == rows[:, None])
+        srt = np.sort(G[rows], axis=1)
+        assert not np.any(srt[:, 1:] == srt[:, :-1])
+        rec[E] = orc.recall_at_k(Xn, rows, G[rows], np.sqrt(O2[:, -1]), 15)
+        print("ensemble", E, "recall", rec[E], "iters", st["iters"])
+    assert rec[2] > rec[1] + 0.005 and rec[3] > rec[2], rec
+    a = _build(X, 15, build_k=16, sample_rate=0.5, max_iters=30, ensemble=2)
+    b = _build(X, 15, build_k=16, sample_rate=0.5, max_iters=30, ensemble=2)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    with pytest.raises(knn.KnnError):
+        _build(X, 15, ensemble=9)

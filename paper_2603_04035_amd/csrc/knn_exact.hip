@@ -430,8 +430,8 @@ constexpr int kRankP = 16;   // probes per query row (the quality metrics' k <= 
 // streamed); the epilogue puts each reference row that can be below a
 // probe of its query into a per-row histogram over the probe boundaries (in
 // LDS), so counts are prefix sums.  A GEMM distance within the slack of a
-// probe's distance (the GEMM error bound plus the canonical distance's) is
-// undecided: the pair is queued in LDS (the tile buffers, free between the
+// probe's distance (the GEMM error bound for the pair's own norms plus the
+// canonical distance's) is undecided: the pair is queued in LDS (the tile buffers, free between the
 // tile's MFMAs and the next tile) and, after every two 32-column blocks,
 // the queued pairs get their canonical FP32 distances from 16-lane groups
 // (dist_g16, the canonical sums) and enter the histogram.  Two blocks queue
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
     __shared__ float srn[kTileRows];
     __shared__ float sqn[kTileRows];
     __shared__ int32_t sself[kTileRows];
-    __shared__ float sgate[kTileRows], sslack[kTileRows];
+    __shared__ float sgate[kTileRows], sqa[kTileRows], smx[kTileRows];
     __shared__ __attribute__((aligned(16))) uint64_t skey[kTileRows * kRankP];
     __shared__ uint32_t hist[kTileRows * (kRankP + 1)];
     __shared__ uint32_t qcount[2];   // queue fill, one per half of a tile
@@ -483,8 +483,9 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
         }
         const float qa = sqrtf(sq), E = err_coef * (qa + ra) * (qa + ra);
         const float sl = E + 2.0f * edir * (mx + E);
-        sslack[tid] = sl;
-        sgate[tid] = mx < 0.0f ? -1.0f : mx + sl;   // rows without probes never pass
+        sqa[tid] = qa;
+        smx[tid] = mx;
+        sgate[tid] = mx < 0.0f ? -1.0f : mx + sl;   // rows without probes never pass (largest reference norm)
     }
 
     const float* Qe = Qs;
@@ -507,6 +508,7 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
                 const int blk = 2 * half + bb;
                 const f32x16 cur = acc[blk];
                 const float rnj = srn[blk * 32 + c];
+                const float raj = sqrtf(rnj);
                 const int64_t j = rt + blk * 32 + c;
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
@@ -516,7 +518,10 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
                     const bool pass = d2 <= sgate[lr] && j < nr && (int32_t)j != sself[lr];
                     if (!ballot(pass)) continue;
                     if (pass) {
-                        const float sl = sslack[lr];
+                        // the slack of this pair: the GEMM bound with its own
+                        // reference norm, plus the canonical distance's
+                        const float qa = sqa[lr], E = err_coef * (qa + raj) * (qa + raj);
+                        const float sl = E + 2.0f * edir * (smx[lr] + E);
                         const uint64_t* pk = skey + lr * kRankP;
                         int a = 0, b = 0;   // probes with thr <= d2 + sl, with thr < d2 - sl
 #pragma unroll

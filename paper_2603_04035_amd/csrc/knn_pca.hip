@@ -258,17 +258,17 @@ __global__ __launch_bounds__(256) void pca_gram_small_kernel(const double* __res
 }
 
 // One Cholesky-QR pass: V = W R^{-1}, where S = W^T W = R^T R (R upper
-// triangular).  Every workgroup factors S in LDS, the same operations in
-// each, so all hold the same factor; then thread a forms row a of W R^{-1}
-// for the workgroup's eight columns.  The factor comes from symmetric
-// elimination on [S | I] (one barrier per step): step k subtracts
+// triangular).  Every workgroup factors S (its entries in registers, 25 per
+// thread), the same operations in each, so all hold the same factor; then
+// it forms 64 rows of W R^{-1} for its eight columns.  The factor comes from
+// symmetric elimination on [S | I] (one barrier per step, the pivot row
+// passed through LDS): step k subtracts
 // S[k][i] / S[k][k] times row k from each row i > k, on the trailing upper
 // triangle of S and on the unit lower triangular M beside it, so that at
 // the end M S = D L^T with S = L D L^T (L unit lower triangular, D the
 // pivots) and M = L^{-1}.  Then R = D^{1/2} L^T and R^{-1}[i][j] = M[j][i] /
 // sqrt(D[j]): no triangular solve is needed.  M's strict lower triangle sits
-// in the lower half of the LDS copy of S, which the upper-triangle
-// elimination never reads.  With shift_rel > 0 the factored matrix is
+// in the lower half of S, which the upper-triangle elimination never reads.  With shift_rel > 0 the factored matrix is
 // S + s I, s = shift_rel * trace(S) (shifted Cholesky-QR: V spans the same
 // space as W, but is only near-orthonormal, and no pivot can fail however
 // badly W is conditioned).  A non-positive pivot (W of lower rank than m,
@@ -282,102 +282,137 @@ __global__ __launch_bounds__(256) void pca_cholqr_kernel(const double* __restric
                                                          unsigned* __restrict__ bad, double* __restrict__ pivots,
                                                          double shift_rel)
 {
-    __shared__ double S[kPcaMaxM * kPcaMaxM];   // upper: S being eliminated; strict lower: M
+    __shared__ double S[kPcaMaxM * kPcaMaxM];   // the result: upper R-scaled rows, strict lower M
+    __shared__ double rowk[2][kPcaMaxM];         // the step's pivot row (double-buffered)
     __shared__ double rinv[kPcaMaxM];
+    __shared__ double diag[kPcaMaxM];
     __shared__ double shift_;
     const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-    {
-        // all of this thread's loads are issued before the first store
-        constexpr int NL = (kPcaMaxM * kPcaMaxM + 255) / 256;
-        double tmp[NL];
+    // thread (ty, tx) owns entries (ty + 16u, tx + 16q), u, q < NJ, held in
+    // registers through the whole elimination; only the pivot row of each
+    // step goes through LDS (one barrier per step)
+    constexpr int NJ = kPcaMaxM / 16;
+    double x[NJ][NJ];
 #pragma unroll
-        for (int u = 0; u < NL; ++u) {
-            const int e = tid + 256 * u;
-            tmp[u] = e < m * m ? Sg[e] : 0.0;
-        }
+    for (int u = 0; u < NJ; ++u)
 #pragma unroll
-        for (int u = 0; u < NL; ++u) {
-            const int e = tid + 256 * u;
-            if (e < m * m) S[e] = (e % m) >= (e / m) ? tmp[u] : 0.0;
+        for (int q = 0; q < NJ; ++q) {
+            const int i = ty + 16 * u, j = tx + 16 * q;
+            x[u][q] = i < m && j < m && j >= i ? Sg[i * m + j] : 0.0;
         }
-    }
     if (shift_rel > 0.0) {
         // S + s I with s = shift_rel * trace(S): the same span, positive
         // pivots however badly W is conditioned
+        if (ty == tx) {
+#pragma unroll
+            for (int u = 0; u < NJ; ++u) diag[ty + 16 * u] = x[u][u];
+        }
         __syncthreads();
         if (tid == 0) {
             double tr = 0.0;
-            for (int k = 0; k < m; ++k) tr += S[k * m + k];
+            for (int k = 0; k < m; ++k) tr += diag[k];
             shift_ = shift_rel * tr;
         }
         __syncthreads();
-        if (tid < m) S[tid * m + tid] += shift_;
+        if (ty == tx) {
+#pragma unroll
+            for (int u = 0; u < NJ; ++u)
+                if (ty + 16 * u < m) x[u][u] += shift_;
+        }
     }
-    // thread (ty, tx) updates rows i = ty (mod 16) at columns j = tx (mod 16):
-    // row k's entries at its columns are read once per step into registers,
-    // and each row's loads are issued before its stores
-    constexpr int NJ = kPcaMaxM / 16;
+    if (ty == 0) {
+#pragma unroll
+        for (int q = 0; q < NJ; ++q) rowk[0][tx + 16 * q] = x[0][q];
+    }
     for (int k = 0; k < m; ++k) {
         __syncthreads();
-        double pk = S[k * m + k];
+        const double* rk = rowk[k & 1];
+        double pk = rk[k];
         if (!(pk > 0.0)) {
             if (tid == 0 && blockIdx.x == 0 && blockIdx.y == 0) atomicOr(bad, 1u);
             pk = 1.0;
         }
         const double ip = 1.0 / pk;
-        double rk[NJ];
+        double rkq[NJ], fu[NJ];
 #pragma unroll
-        for (int q = 0; q < NJ; ++q) {
-            const int j = tx + 16 * q;
-            rk[q] = j < m ? S[k * m + j] : 0.0;
-        }
-        for (int i = k + 1 + ty; i < m; i += 16) {
-            const double f = S[k * m + i] * ip;
-            double x[NJ];
+        for (int q = 0; q < NJ; ++q) rkq[q] = rk[tx + 16 * q];
+#pragma unroll
+        for (int u = 0; u < NJ; ++u) fu[u] = rk[ty + 16 * u] * ip;
+#pragma unroll
+        for (int u = 0; u < NJ; ++u)
 #pragma unroll
             for (int q = 0; q < NJ; ++q) {
-                const int j = tx + 16 * q;
-                x[q] = j < m ? S[i * m + j] : 0.0;
+                const int i = ty + 16 * u, j = tx + 16 * q;
+                // rows below k: the upper triangle (j >= i) and M (j < k) take
+                // row k's entry; M's column k takes its unit diagonal; k < j < i
+                // stays 0
+                const double nv = (j >= i || j < k) ? fma(-fu[u], rkq[q], x[u][q])
+                                                    : (j == k ? x[u][q] - fu[u] : x[u][q]);
+                x[u][q] = i > k ? nv : x[u][q];
             }
-#pragma unroll
-            for (int q = 0; q < NJ; ++q) {
-                const int j = tx + 16 * q;
-                // upper triangle (j >= i) and M (j < k) take row k's entry;
-                // M's column k takes its unit diagonal; k < j < i stays 0
-                if (j < m && (j >= i || j < k)) S[i * m + j] = fma(-f, rk[q], x[q]);
-                else if (j == k) S[i * m + j] = x[q] - f;
-            }
-        }
         if (tid == 0) {
             rinv[k] = 1.0 / sqrt(pk);
             if (blockIdx.x == 0 && blockIdx.y == 0) pivots[k] = pk;
         }
-    }
-    __syncthreads();
-    const int a = blockIdx.x * 256 + tid;
-    const int j0 = blockIdx.y * kPcaCols;
-    if (a >= d) return;
-    double s[kPcaCols];
+        // row k + 1 is final now: its owners publish it for the next step
+        const int k1 = k + 1;
+        if (k1 < m && ty == (k1 & 15)) {
 #pragma unroll
-    for (int q = 0; q < kPcaCols; ++q) s[q] = 0.0;
-    const int jmax = j0 + kPcaCols < m ? j0 + kPcaCols : m;
-    for (int i0 = 0; i0 < jmax; i0 += 8) {
-        double wv[8];   // eight rows of W in flight at once
+            for (int u = 0; u < NJ; ++u)
+                if (u == (k1 >> 4)) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) wv[u] = i0 + u < jmax ? W[(int64_t)(i0 + u) * d + a] : 0.0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int i = i0 + u;
-#pragma unroll
-            for (int q = 0; q < kPcaCols; ++q) {
-                const int j = j0 + q;
-                if (i < jmax && j < m && i <= j) s[q] = i == j ? s[q] + wv[u] : fma(wv[u], S[j * m + i], s[q]);
-            }
+                    for (int q = 0; q < NJ; ++q) rowk[k1 & 1][tx + 16 * q] = x[u][q];
+                }
         }
     }
 #pragma unroll
-    for (int q = 0; q < kPcaCols; ++q)
-        if (j0 + q < m) V[(int64_t)(j0 + q) * d + a] = s[q] * rinv[j0 + q];
+    for (int u = 0; u < NJ; ++u)
+#pragma unroll
+        for (int q = 0; q < NJ; ++q) {
+            const int i = ty + 16 * u, j = tx + 16 * q;
+            if (i < m && j < m) S[i * m + j] = x[u][q];
+        }
+    __syncthreads();
+    // V = W R^{-1} for rows a0 .. a0 + 63 and the workgroup's eight columns:
+    // wave g sums the products over its quarter of the index range i (so
+    // each thread issues a quarter of the row loads), and the four partial
+    // sums are added in wave order
+    const int r = tid & 63, g = tid >> 6;
+    const int a = blockIdx.x * 64 + r;
+    const int j0 = blockIdx.y * kPcaCols;
+    const int jmax = j0 + kPcaCols < m ? j0 + kPcaCols : m;
+    const int ilen = (jmax + 3) / 4, ib = g * ilen, ie = ib + ilen < jmax ? ib + ilen : jmax;
+    double sp[kPcaCols];
+#pragma unroll
+    for (int q = 0; q < kPcaCols; ++q) sp[q] = 0.0;
+    if (a < d) {
+        for (int i0 = ib; i0 < ie; i0 += 8) {
+            double wv[8];   // eight rows of W in flight at once
+#pragma unroll
+            for (int u = 0; u < 8; ++u) wv[u] = i0 + u < ie ? W[(int64_t)(i0 + u) * d + a] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + u;
+#pragma unroll
+                for (int q = 0; q < kPcaCols; ++q) {
+                    const int j = j0 + q;
+                    if (i < ie && j < m && i <= j) sp[q] = i == j ? sp[q] + wv[u] : fma(wv[u], S[j * m + i], sp[q]);
+                }
+            }
+        }
+    }
+    __shared__ double part[3][64][kPcaCols];
+    if (g > 0) {
+#pragma unroll
+        for (int q = 0; q < kPcaCols; ++q) part[g - 1][r][q] = sp[q];
+    }
+    __syncthreads();
+    if (g == 0 && a < d) {
+#pragma unroll
+        for (int q = 0; q < kPcaCols; ++q)
+            if (j0 + q < m)
+                V[(int64_t)(j0 + q) * d + a] = (((sp[q] + part[0][r][q]) + part[1][r][q]) + part[2][r][q]) * rinv[j0 + q];
+    }
 }
 
 // Cyclic Jacobi on the symmetric m x m matrix H (row-major; H and the
@@ -705,7 +740,7 @@ extern "C" knn_status knn_pca(knn_matrix X, int32_t p, int32_t iters, float* Z, 
         } else {
             pca_init_kernel<<<(unsigned)ceil_div((int64_t)d * m, 256), 256, 0, st>>>(d, m, 0x5CA1AB1Eull, W);
         }
-        const dim3 gcols((unsigned)ceil_div(d, 256), (unsigned)ceil_div(m, kPcaCols));
+        const dim3 gcols((unsigned)ceil_div(d, 64), (unsigned)ceil_div(m, kPcaCols));
         const dim3 gcv((unsigned)ceil_div(d, 16), (unsigned)ceil_div(m, 16));
         // shift of the shifted passes: 11 (m d + m (m + 1)) u relative to
         // trace(S) >= |W|_2^2, the bound under which a shifted Cholesky-QR

@@ -7,7 +7,8 @@
  * bounded sorted list merges, stop on update count).  It is the graph stage
  * the paper's dimensionality-reduction methods share (paper, section
  * "GPU-Native k-NN via NNDescent"; the exact ranks of the embedding-quality
- * section).
+ * section), with the steps next to it: PCA before the graph, the UMAP fuzzy
+ * graph and the embedding-quality metrics after it.
  *
  * Conventions for every entry point:
  *  - Pointers named as device pointers must point to device memory of the
@@ -17,7 +18,9 @@
  *    between calls: it grows when a call needs more and is never returned
  *    before the process ends, and calls on one device take turns on it.
  *    knn_exact_noalloc takes its scratch from a fixed static device array
- *    instead.  knn_encoder objects are library-owned until destroyed.
+ *    instead; nndescent_build with ensemble > 1 also takes the runs' lists
+ *    from stream-ordered allocations freed before it returns.  knn_encoder
+ *    objects are library-owned until destroyed.
  *  - `stream` is a hipStream_t (NULL = the null stream).  Every call is
  *    blocking: the stream is synchronised before return.
  *  - Errors are returned as knn_status (never thrown).  On error the outputs

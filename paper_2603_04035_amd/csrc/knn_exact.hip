@@ -20,6 +20,7 @@
 //     certified when its k-th re-ranked distance is below the k'-th GEMM
 //     distance minus the worst-case GEMM error bound; other rows are
 //  4. recomputed exhaustively with direct differences.
+#include <algorithm>
 #include <mutex>
 
 #include "knn_common.hpp"
@@ -36,7 +37,9 @@ constexpr int kListW = 32;        // list width per query row (k' <= 32)
 // ------------------------------------------------------------------ stage
 
 // Waves take groups of 4 rows grid-stride: padded copy (zeros beyond d) and
-// the FP32 squared norm of the stored values.  maxnorm (nullable) receives the
+// the squared norm of the stored values: FP64 sums rounded once to FP32
+// (within u of the exact norm), or with `aux` FP32 sums (the norms
+// NNDescent's distances use).  maxnorm (nullable) receives the
 // largest norm's float bits: one atomic per block after an in-block
 // reduction.  With `aux`, the last 8 bytes of each row hold two FP32 words
 // instead of zeros: the norm and +inf (a per-row value that NNDescent keeps
@@ -57,11 +60,13 @@ __global__ __launch_bounds__(256) void stage_kernel(const void* __restrict__ X, 
     for (int64_t row0 = ((int64_t)blockIdx.x * 4 + wv) * RB; row0 < n; row0 += (int64_t)gridDim.x * 4 * RB) {
         int64_t src[RB];
         float s[RB];
+        double sd[RB];
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
             const int64_t row = row0 + q < n ? row0 + q : row0;
             src[q] = rowmap ? (int64_t)rowmap[row] : row;
             s[q] = 0.0f;
+            sd[q] = 0.0;
         }
         for (int t = lane; t < lim; t += 64) {
             float v[RB];
@@ -83,13 +88,26 @@ __global__ __launch_bounds__(256) void stage_kernel(const void* __restrict__ X, 
                 } else {
                     ((float*)Xs)[row * ldp + t] = x;
                 }
-                s[q] = fmaf(x, x, s[q]);
+                if (aux)
+                    s[q] = fmaf(x, x, s[q]);
+                else
+                    sd[q] = fma((double)x, (double)x, sd[q]);
             }
         }
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
+            if (aux) {
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) s[q] += xor_f32(s[q], o);
+                for (int o = 32; o > 0; o >>= 1) s[q] += xor_f32(s[q], o);
+            } else {
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    const uint64_t b = (uint64_t)__double_as_longlong(sd[q]);
+                    const uint64_t y = ((uint64_t)xor_u32((uint32_t)(b >> 32), o) << 32) | xor_u32((uint32_t)b, o);
+                    sd[q] += __longlong_as_double((long long)y);
+                }
+                s[q] = (float)sd[q];
+            }
         }
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
@@ -422,54 +440,59 @@ __global__ __launch_bounds__(256, 2) void exact_tile_kernel(
 // ------------------------------------------------------------ rank counts
 
 constexpr int kRankP = 16;   // probes per query row (the quality metrics' k <= 16)
+constexpr int kRankM = 16;   // queued pairs per thread in one pass over a tile's rows
 // For every query row q and each of its probes (keys (canonical d2, index),
 // ascending; kEmptyCand pads), counts[q][p] = the number of reference rows
 // m != self(q) whose key (canonical FP32 d2(q, m), m) is below the probe's
 // key: the probe's rank minus one.  The same tiles and pipeline as
-// exact_tile_kernel (FP32 MFMA Gram, norm expansion, one split, query rows
+// exact_tile_kernel (FP32 MFMA Gram, norm expansion, S reference splits
+// whose counts are added into counts, zeroed beforehand; query rows
 // streamed); the epilogue puts each reference row that can be below a
 // probe of its query into a per-row histogram over the probe boundaries (in
 // LDS), so counts are prefix sums.  A GEMM distance within the slack of a
 // probe's distance (the GEMM error bound for the pair's own norms plus the
-// canonical distance's) is undecided: the pair is queued in LDS (the tile buffers, free between the
-// tile's MFMAs and the next tile) and, after every two 32-column blocks,
-// the queued pairs get their canonical FP32 distances from 16-lane groups
-// (dist_g16, the canonical sums) and enter the histogram.  Two blocks queue
-// at most 128 x 64 = 8,192 pairs, within the buffers' 9,216 words, so no
-// pair is ever decided any other way.
+// canonical distance's) is undecided: the pair is queued in the
+// workgroup's global queue (room for a whole tile, 128 x 128 pairs) and,
+// after the tile's epilogue, the tile's query and reference rows are
+// streamed again through the tile buffers in 32-coordinate chunks; 16-lane
+// groups sum the queued pairs' canonical FP32 distances from LDS (lane g:
+// coordinates g, g + 16, ... in order, then the fixed 16-lane tree, the sums
+// dist_g16 makes) and put them into the histogram.  No pair is decided any
+// other way.
 __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
     const float* __restrict__ Qs, const float* __restrict__ qn, int64_t nq, const float* __restrict__ Rs,
     const float* __restrict__ rn, int64_t nr, int ldp, int d, int self_mode, int64_t self_base,
-    const uint64_t* __restrict__ probes, const unsigned* __restrict__ rmax_bits, float err_coef, float edir,
-    uint32_t* __restrict__ counts)
+    const uint64_t* __restrict__ probes, const unsigned* __restrict__ rmax_bits, float ec_dot, float ec_norm,
+    float edir, int S, int64_t split_len, uint32_t* __restrict__ counts, uint32_t* __restrict__ gqueue)
 {
     using C = TileCfg<KNN_F32>;
     constexpr int LROW = C::LROW, KC = C::KC, PER = KC / 2;
     __shared__ __attribute__((aligned(16))) float ABs[2 * kTileRows * LROW];
     float* As = ABs;
     float* Bs = ABs + kTileRows * LROW;
-    // undecided pairs, between a tile's MFMAs and the next tile's staging:
+    // this workgroup's undecided pairs of the current tile:
     // column in tile << 17 | query row << 10 | a << 5 | b
-    uint32_t* queue = (uint32_t*)ABs;
-    constexpr int kQueueCap = 2 * kTileRows * LROW;
-    static_assert(kQueueCap >= kTileRows * 64, "two 32-column blocks of undecided pairs fit the tile buffers");
+    uint32_t* queue = gqueue + (int64_t)blockIdx.x * (kTileRows * kTileRows);
     __shared__ float srn[kTileRows];
     __shared__ float sqn[kTileRows];
     __shared__ int32_t sself[kTileRows];
     __shared__ float sgate[kTileRows], sqa[kTileRows], smx[kTileRows];
     __shared__ __attribute__((aligned(16))) uint64_t skey[kTileRows * kRankP];
     __shared__ uint32_t hist[kTileRows * (kRankP + 1)];
-    __shared__ uint32_t qcount[2];   // queue fill, one per half of a tile
+    __shared__ uint32_t qcount;   // queue fill
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, h = lane >> 5, c = lane & 31;
-    const int64_t q0 = (int64_t)blockIdx.x * kTileRows;
+    // workgroup = (query block, reference split): splits rbeg .. rend
+    const int64_t q0 = (int64_t)(blockIdx.x / S) * kTileRows;
+    const int64_t rbeg = (int64_t)(blockIdx.x % S) * split_len;
+    const int64_t rend = rbeg + split_len < nr ? rbeg + split_len : nr;
     const float ra = sqrtf(__uint_as_float(*rmax_bits));
     for (int e = tid; e < kTileRows * kRankP; e += 256) {
         const int64_t qr = q0 + e / kRankP;
         skey[e] = qr < nq ? probes[qr * kRankP + e % kRankP] : kEmptyCand;
     }
     for (int e = tid; e < kTileRows * (kRankP + 1); e += 256) hist[e] = 0u;
-    if (tid < 2) qcount[tid] = 0u;
+    if (tid == 0) qcount = 0u;
     __syncthreads();
     if (tid < kTileRows) {
         const int64_t qr = q0 + tid;
@@ -481,7 +504,7 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
             const uint64_t key = skey[tid * kRankP + p];
             if (key != kEmptyCand) mx = key_d2(key);
         }
-        const float qa = sqrtf(sq), E = err_coef * (qa + ra) * (qa + ra);
+        const float qa = sqrtf(sq), E = ec_dot * qa * ra + ec_norm * (sq + ra * ra);
         const float sl = E + 2.0f * edir * (mx + E);
         sqa[tid] = qa;
         smx[tid] = mx;
@@ -494,65 +517,124 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
     const int64_t qrow = q0 + r < nq ? q0 + r : nq - 1;
     uint4 nb0, nb1, nb2, nb3, na0 = {}, na1 = {}, na2 = {}, na3 = {};
     float nrn;
-    load_step<float, false>(Qe, Re, qrow, 0, nr, r, ph * PER, 0, ldp, rn, tid, nb0, nb1, nb2, nb3, na0, na1, na2,
-                            na3, nrn);
-    for (int64_t rt = 0; rt < nr; rt += kTileRows) {
+    load_step<float, false>(Qe, Re, qrow, rbeg, rend, r, ph * PER, 0, ldp, rn, tid, nb0, nb1, nb2, nb3, na0, na1,
+                            na2, na3, nrn);
+    for (int64_t rt = rbeg; rt < rend; rt += kTileRows) {
         f32x16 acc[4];
         tile_gemm<KNN_F32, false>(nb0, nb1, nb2, nb3, na0, na1, na2, na3, nrn, acc, As, Bs, srn, Qe, Re, qrow, rt,
-                                nr, ldp, rn, tid, w, h, c);
-        __syncthreads();   // every wave's MFMA operands are read: the tile buffers hold the queue
+                                rend, ldp, rn, tid, w, h, c);
+        // row and column bases, opaque to the compiler here so that the 64
+        // (block, row) offsets derived from them are formed where they are
+        // used instead of being held in registers across the whole loop
+        int lr0 = w * 32 + 4 * h, c0 = c;
+        asm volatile("" : "+v"(lr0), "+v"(c0));
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
+        for (int blk = 0; blk < 4; ++blk) {
+            const f32x16 cur = acc[blk];
+            const int col = blk * 32 + c0;
+            const float rnj = srn[col];
+            const float raj = sqrtf(rnj);
+            const int64_t j = rt + col;
 #pragma unroll
-            for (int bb = 0; bb < 2; ++bb) {
-                const int blk = 2 * half + bb;
-                const f32x16 cur = acc[blk];
-                const float rnj = srn[blk * 32 + c];
-                const float raj = sqrtf(rnj);
-                const int64_t j = rt + blk * 32 + c;
+            for (int v = 0; v < 16; ++v) {
+                const int lr = lr0 + (mfma_row(v, 0));
+                float d2 = fmaf(-2.0f, cur[v], sqn[lr] + rnj);
+                d2 = d2 > 0.0f ? d2 : 0.0f;
+                const bool pass = d2 <= sgate[lr] && j < rend && (int32_t)j != sself[lr];
+                if (!ballot(pass)) continue;
+                if (pass) {
+                    // the slack of this pair: the GEMM bound with its own
+                    // reference norm, plus the canonical distance's
+                    const float E = ec_dot * sqa[lr] * raj + ec_norm * (sqn[lr] + rnj);
+                    const float sl = E + 2.0f * edir * (smx[lr] + E);
+                    const uint64_t* pk = skey + lr * kRankP;
+                    int a = 0, b = 0;   // probes with thr <= d2 + sl, with thr < d2 - sl
 #pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    const int lr = w * 32 + mfma_row(v, h);
-                    float d2 = fmaf(-2.0f, cur[v], sqn[lr] + rnj);
-                    d2 = d2 > 0.0f ? d2 : 0.0f;
-                    const bool pass = d2 <= sgate[lr] && j < nr && (int32_t)j != sself[lr];
-                    if (!ballot(pass)) continue;
-                    if (pass) {
-                        // the slack of this pair: the GEMM bound with its own
-                        // reference norm, plus the canonical distance's
-                        const float qa = sqa[lr], E = err_coef * (qa + raj) * (qa + raj);
-                        const float sl = E + 2.0f * edir * (smx[lr] + E);
-                        const uint64_t* pk = skey + lr * kRankP;
-                        int a = 0, b = 0;   // probes with thr <= d2 + sl, with thr < d2 - sl
-#pragma unroll
-                        for (int p = 0; p < kRankP; ++p) {
-                            const uint64_t key = pk[p];
-                            const float thr = key == kEmptyCand ? __builtin_inff() : key_d2(key);
-                            a += thr <= d2 + sl ? 1 : 0;
-                            b += thr < d2 - sl ? 1 : 0;
-                        }
-                        // probes a.. have this row below them; b..a-1 are undecided
-                        if (b == a && a < kRankP) atomicAdd(&hist[lr * (kRankP + 1) + a], 1u);
-                        if (b < a) {
-                            const uint32_t slot = atomicAdd(&qcount[half], 1u);
-                            queue[slot] = ((uint32_t)(blk * 32 + c) << 17) | ((uint32_t)lr << 10) |
-                                          ((uint32_t)a << 5) | (uint32_t)b;
-                        }
+                    for (int p = 0; p < kRankP; ++p) {
+                        const uint64_t key = pk[p];
+                        const float thr = key == kEmptyCand ? __builtin_inff() : key_d2(key);
+                        a += thr <= d2 + sl ? 1 : 0;
+                        b += thr < d2 - sl ? 1 : 0;
+                    }
+                    // probes a.. have this row below them; b..a-1 are undecided
+                    if (b == a && a < kRankP) atomicAdd(&hist[lr * (kRankP + 1) + a], 1u);
+                    if (b < a) {
+                        const uint32_t slot = atomicAdd(&qcount, 1u);
+                        queue[slot] = ((uint32_t)col << 17) | ((uint32_t)lr << 10) | ((uint32_t)a << 5) | (uint32_t)b;
                     }
                 }
             }
-            __syncthreads();
-            const int nqd = (int)qcount[half];
-            for (int base = 0; base < nqd; base += 16) {
-                const int e = base + (tid >> 4);
-                const bool act = e < nqd;
-                const uint32_t qe = act ? queue[e] : 0u;
-                const int64_t jj = rt + (int64_t)(qe >> 17);
-                const int lr = (int)((qe >> 10) & 127), a = (int)((qe >> 5) & 31), b = (int)(qe & 31);
-                const float dc = dist_g16<KNN_F32>(Qs, (q0 + lr) * (int64_t)ldp, Rs, (act ? jj : 0) * (int64_t)ldp, d,
-                                                   act);
-                if (act && (tid & 15) == 0) {
-                    const uint64_t km = make_key(dc, (uint32_t)jj);
+        }
+        __syncthreads();   // the queue is complete; every wave's MFMA operands are read
+        const int nqd = (int)qcount;
+        // thread (tid / 16, g = tid % 16) takes pairs base + tid / 16 + 16 m;
+        // a thread past the end reads row 0 of both buffers and drops the sum
+        const int g = tid & 15;
+        for (int base = 0; base < nqd; base += 16 * kRankM) {
+            uint32_t qo[kRankM], ro[kRankM];
+            float part[kRankM];
+#pragma unroll
+            for (int m = 0; m < kRankM; ++m) {
+                const int e = base + (tid >> 4) + 16 * m;
+                const uint32_t ent = e < nqd ? queue[e] : 0u;
+                qo[m] = ((ent >> 10) & 127u) * LROW + g;
+                ro[m] = (ent >> 17) * LROW + g;
+                part[m] = 0.0f;
+            }
+            // the chunks pass through registers: chunk k0 + KC is loaded
+            // while chunk k0's sums are formed
+            const int rr = tid >> 1, hh = tid & 1;
+            const f32x4* qs = (const f32x4*)(Qs + (q0 + rr < nq ? q0 + rr : nq - 1) * ldp + hh * PER);
+            const f32x4* rs = (const f32x4*)(Rs + (rt + rr < rend ? rt + rr : rend - 1) * ldp + hh * PER);
+            f32x4 x0 = qs[0], x1 = qs[1], x2 = qs[2], x3 = qs[3];
+            f32x4 y0 = rs[0], y1 = rs[1], y2 = rs[2], y3 = rs[3];
+            for (int k0 = 0; k0 < d; k0 += KC) {
+                __syncthreads();   // the previous chunk is read
+                {
+                    f32x4* qd = (f32x4*)(As + rr * LROW + hh * PER);
+                    f32x4* rd = (f32x4*)(Bs + rr * LROW + hh * PER);
+                    qd[0] = x0;
+                    qd[1] = x1;
+                    qd[2] = x2;
+                    qd[3] = x3;
+                    rd[0] = y0;
+                    rd[1] = y1;
+                    rd[2] = y2;
+                    rd[3] = y3;
+                }
+                __syncthreads();
+                {
+                    // the last chunk loads itself again (in bounds, unused)
+                    const int kn = (k0 + KC < d ? k0 + KC : k0) / 4;
+                    x0 = qs[kn];
+                    x1 = qs[kn + 1];
+                    x2 = qs[kn + 2];
+                    x3 = qs[kn + 3];
+                    y0 = rs[kn];
+                    y1 = rs[kn + 1];
+                    y2 = rs[kn + 2];
+                    y3 = rs[kn + 3];
+                }
+                // coordinates past d add nothing: fmaf(0, 0, s) == s
+                const bool lo = k0 + g < d, hi = k0 + g + 16 < d;
+#pragma unroll
+                for (int m = 0; m < kRankM; ++m) {
+                    const float d0 = As[qo[m]] - Bs[ro[m]], d1 = As[qo[m] + 16] - Bs[ro[m] + 16];
+                    const float e0 = lo ? d0 : 0.0f, e1 = hi ? d1 : 0.0f;
+                    part[m] = fmaf(e1, e1, fmaf(e0, e0, part[m]));
+                }
+                // the next chunk's loads belong to this step: issued before
+                // the sums above, not moved to the top of the next step
+                asm volatile("" : "+v"(x0), "+v"(x1), "+v"(x2), "+v"(x3), "+v"(y0), "+v"(y1), "+v"(y2), "+v"(y3));
+            }
+#pragma unroll
+            for (int m = 0; m < kRankM; ++m) {
+                const float dc = wave_sum16(part[m]);
+                const int e = base + (tid >> 4) + 16 * m;
+                if (e < nqd && g == 0) {
+                    const uint32_t ent = queue[e];
+                    const int lr = (int)((ent >> 10) & 127u), a = (int)((ent >> 5) & 31u), b = (int)(ent & 31u);
+                    const uint64_t km = make_key(dc, (uint32_t)(rt + (ent >> 17)));
                     const uint64_t* pk = skey + lr * kRankP;
                     int at = a;
                     for (int p = b; p < a; ++p) {
@@ -564,9 +646,9 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
                     if (at < kRankP) atomicAdd(&hist[lr * (kRankP + 1) + at], 1u);
                 }
             }
-            __syncthreads();   // the queue is read; the next half (or tile) may overwrite it
-            if (tid == 0) qcount[half] = 0u;
         }
+        __syncthreads();   // the queue and the tile buffers are free for the next tile
+        if (tid == 0) qcount = 0u;
     }
     __syncthreads();
     for (int e = tid; e < kTileRows * kRankP; e += 256) {
@@ -575,7 +657,7 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
         if (qr >= nq) continue;
         uint32_t cnt = 0;
         for (int a = 0; a <= p; ++a) cnt += hist[lr * (kRankP + 1) + a];
-        counts[qr * kRankP + p] = cnt;
+        atomicAdd(&counts[qr * kRankP + p], cnt);   // the splits' counts add up
     }
 }
 
@@ -586,17 +668,27 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
 // counts sit in registers; reference rows stream through LDS in tiles of
 // 256.  Exact in the canonical precision, no ambiguity.
 constexpr int kRankDirectD = 16;
+// Workgroups per rank_tile_kernel launch: each holds a 64 KiB queue of
+// undecided pairs (256 MiB per launch).
+constexpr int64_t kRankBlocks = 4096;
+constexpr int kRankMaxSplits = 8;   // reference splits of the rank pass
 
-__global__ __launch_bounds__(256) void rank_direct_kernel(const float* __restrict__ Xs, int64_t n, int ldp, int d,
+// DC = d when it is a compile-time constant (2, 3), 0 for any d <= 16.
+template <int DC>
+__global__ __launch_bounds__(256) void rank_direct_kernel(const float* __restrict__ Xs, int64_t n, int ldp, int dd,
                                                           const uint64_t* __restrict__ probes,
                                                           uint32_t* __restrict__ counts)
 {
+    // the canonical sums round every square and every sum: no fused forms
+#pragma clang fp contract(off)
+    const int d = DC ? DC : dd;
+    constexpr int DT = DC ? DC : kRankDirectD;   // coordinates held per row
     __shared__ float tile[256][kRankDirectD + 1];
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool live = q < n;
-    float xq[kRankDirectD];
+    float xq[DT];
 #pragma unroll
-    for (int t = 0; t < kRankDirectD; ++t) xq[t] = live && t < d ? Xs[q * ldp + t] : 0.0f;
+    for (int t = 0; t < DT; ++t) xq[t] = live && t < d ? Xs[q * ldp + t] : 0.0f;
     uint64_t pk[kRankP];
     uint32_t cnt[kRankP];
     float mx = -1.0f;
@@ -611,23 +703,29 @@ __global__ __launch_bounds__(256) void rank_direct_kernel(const float* __restric
         {
             const int64_t r = r0 + threadIdx.x;
 #pragma unroll
-            for (int t = 0; t < kRankDirectD; ++t) tile[threadIdx.x][t] = r < n && t < d ? Xs[r * ldp + t] : 0.0f;
+            for (int t = 0; t < DT; ++t) tile[threadIdx.x][t] = r < n && t < d ? Xs[r * ldp + t] : 0.0f;
         }
         __syncthreads();
         const int nr = (int)(n - r0 < 256 ? n - r0 : 256);
         for (int jj = 0; jj < nr; ++jj) {
             // canonical order: partial t mod 16 holds coordinate t (d <= 16),
             // then the tree at strides 8, 4, 2, 1
+            // (with d fixed, the terms known to be zero are left out: adding
+            // +0 to a square changes nothing)
             float s[16];
 #pragma unroll
             for (int t = 0; t < 16; ++t) {
-                const float e = xq[t] - tile[jj][t];
-                s[t] = t < d ? e * e : 0.0f;
+                if (t < DT) {
+                    const float e = xq[t] - tile[jj][t];
+                    s[t] = t < d ? e * e : 0.0f;
+                }
             }
 #pragma unroll
             for (int j = 8; j > 0; j >>= 1) {
 #pragma unroll
-                for (int g = 0; g < j; ++g) s[g] = s[g] + s[g + j];
+                for (int g = 0; g < j; ++g) {
+                    if (g + j < DT) s[g] = g < DT ? s[g] + s[g + j] : s[g + j];
+                }
             }
             const float d2 = s[0];
             const int64_t m = r0 + jj;
@@ -806,9 +904,9 @@ knn_status stage_matrix(ScratchAlloc& ws, const knn_matrix& X, int kind, void** 
 
 // Zero n words (a fill kernel rather than hipMemsetAsync, so that no memset
 // node is recorded when a caller captures the stream).
-__global__ __launch_bounds__(64) void zero_words_kernel(unsigned* __restrict__ p, int n)
+__global__ __launch_bounds__(64) void zero_words_kernel(unsigned* __restrict__ p, int64_t n)
 {
-    for (int i = threadIdx.x; i < n; i += 64) p[i] = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 64) p[i] = 0u;
 }
 
 // Reference splits of a query chunk of qn rows: enough workgroups to fill
@@ -1095,18 +1193,60 @@ static knn_status quality_impl(const knn_matrix& X, const knn_matrix& Y, int k, 
                                                                     (const float*)Ys, ldy, Y.d, pu, pv, hits);
     KNN_HIP(hipGetLastError());
     const float u = 5.9604645e-08f;
-    const dim3 grid((unsigned)ceil_div(n, kTileRows));
+    // The tile pass: S reference splits, so that the workgroups fill the
+    // chip's resident slots (two per CU) in nearly whole waves; each
+    // workgroup holds a queue of undecided pairs of one tile, launches of at
+    // most kRankBlocks workgroups.
+    int dev = 0, ncu = 256;
+    KNN_HIP(hipGetDevice(&dev));
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) ncu = 256;
+    const int64_t nblk = ceil_div(n, kTileRows), ntile = nblk, slots = 2 * (int64_t)ncu;
+    int S = 1;
+    for (; S < kRankMaxSplits; ++S) {
+        const int64_t b = nblk * S;   // waves of resident workgroups: whole ones at least 90% of the last
+        if (b % slots == 0 || (double)b / (double)slots >= 0.9 * (double)ceil_div(b, slots)) break;
+    }
+    if (S > ntile) S = (int)ntile;
+    const int64_t split_len = ceil_div(ntile, S) * kTileRows;
+    const int64_t per_launch = kRankBlocks / S;   // query blocks per launch
+    uint32_t* rq = nullptr;
+    if ((X.d > kRankDirectD || Y.d > kRankDirectD) &&
+        (r = ws.alloc(&rq, (size_t)std::min<int64_t>(nblk, per_launch) * S * kTileRows * kTileRows)) != KNN_OK)
+        return r;
+    auto rank_tile = [&](const float* Zs, const float* zn, int ldz, int dz, const uint64_t* pz, const unsigned* mx,
+                         uint32_t* cz) {
+        // GEMM distance error: 2 gamma_d |q| |r| for the FP32 dot product
+        // plus 2u (|q|^2 + |r|^2) for the norms (FP64 sums rounded once)
+        // and their sum; the canonical distance's own error (edir) carries
+        // the margin for the final rounding
+        const float ecd = 2.0f * (float)(dz + 2) * u * 1.01f, ecn = 2.02f * u;
+        const float ed = (float)(dz / 16 + 8) * u;
+        zero_words_kernel<<<(unsigned)std::min<int64_t>(ceil_div(n * kRankP, 64), 4096), 64, 0, st>>>(cz,
+                                                                                                 n * kRankP);
+        for (int64_t q0 = 0; q0 < n; q0 += per_launch * kTileRows) {
+            const int64_t nq = std::min<int64_t>(n - q0, per_launch * kTileRows);
+            rank_tile_kernel<<<(unsigned)(ceil_div(nq, kTileRows) * S), 256, 0, st>>>(
+                Zs + q0 * ldz, zn + q0, nq, Zs, zn, n, ldz, dz, 1, q0, pz + q0 * kRankP, mx, ecd, ecn, ed, S, split_len,
+                cz + q0 * kRankP, rq);
+        }
+    };
+    auto rank_direct = [&](const float* Zs, int ldz, int dz, const uint64_t* pz, uint32_t* cz) {
+        const unsigned nb = (unsigned)ceil_div(n, 256);
+        if (dz == 2)
+            rank_direct_kernel<2><<<nb, 256, 0, st>>>(Zs, n, ldz, dz, pz, cz);
+        else if (dz == 3)
+            rank_direct_kernel<3><<<nb, 256, 0, st>>>(Zs, n, ldz, dz, pz, cz);
+        else
+            rank_direct_kernel<0><<<nb, 256, 0, st>>>(Zs, n, ldz, dz, pz, cz);
+    };
     if (X.d <= kRankDirectD)
-        rank_direct_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>((const float*)Xs, n, ldx, X.d, pu, cu);
+        rank_direct((const float*)Xs, ldx, X.d, pu, cu);
     else
-        rank_tile_kernel<<<grid, 256, 0, st>>>((const float*)Xs, xn, n, (const float*)Xs, xn, n, ldx, X.d, 1, 0, pu,
-                                               small, (float)(X.d + 3) * u * 1.01f, (float)(X.d / 16 + 8) * u, cu);
+        rank_tile((const float*)Xs, xn, ldx, X.d, pu, small, cu);
     if (Y.d <= kRankDirectD)
-        rank_direct_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>((const float*)Ys, n, ldy, Y.d, pv, cv);
+        rank_direct((const float*)Ys, ldy, Y.d, pv, cv);
     else
-        rank_tile_kernel<<<grid, 256, 0, st>>>((const float*)Ys, yn, n, (const float*)Ys, yn, n, ldy, Y.d, 1, 0, pv,
-                                               small + 1, (float)(Y.d + 3) * u * 1.01f, (float)(Y.d / 16 + 8) * u,
-                                               cv);
+        rank_tile((const float*)Ys, yn, ldy, Y.d, pv, small + 1, cv);
     KNN_HIP(hipGetLastError());
     unsigned long long* tot = (unsigned long long*)(small + 2);
     quality_reduce_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(n, k, pu, cu, pv, cv, hits, trust_out,

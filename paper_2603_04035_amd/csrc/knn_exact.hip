@@ -661,12 +661,40 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
     }
 }
 
+// Canonical FP32 squared distance for d <= DT <= 16 coordinates: the
+// squares of coordinates t < d (t mod 16 = t), then the fixed tree at
+// strides 8, 4, 2, 1 (terms known to be zero left out); every square and
+// sum rounded, as dist_g16 rounds them.
+template <int DT>
+__device__ __attribute__((always_inline)) inline float direct_d2(const float (&xq)[DT], const float* xr, int d)
+{
+#pragma clang fp contract(off)
+    float sq[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        if (t < DT) {
+            const float e = xq[t] - xr[t];
+            sq[t] = t < d ? e * e : 0.0f;
+        }
+    }
+#pragma unroll
+    for (int j = 8; j > 0; j >>= 1) {
+#pragma unroll
+        for (int g = 0; g < j; ++g) {
+            if (g + j < DT) sq[g] = sq[g] + sq[g + j];
+        }
+    }
+    return sq[0];
+}
+
 // The same counts for a low-dimensional space (d <= kRankDirectD, e.g. a 2-D
 // embedding), by direct canonical FP32 distances: there the norm
 // expansion's error bound is wider than neighbour distances, so a GEMM pass
 // would recheck nearly every pair.  Thread = query row; its probe keys and
-// counts sit in registers; reference rows stream through LDS in tiles of
-// 256.  Exact in the canonical precision, no ambiguity.
+// counts sit in registers; the reference rows of the workgroup's split
+// stream through LDS in tiles of 256, and the splits' counts are added into
+// counts (zeroed beforehand).  Exact in the canonical precision, no
+// ambiguity.
 constexpr int kRankDirectD = 16;
 // Workgroups per rank_tile_kernel launch: each holds a 64 KiB queue of
 // undecided pairs (256 MiB per launch).
@@ -676,15 +704,14 @@ constexpr int kRankMaxSplits = 8;   // reference splits of the rank pass
 // DC = d when it is a compile-time constant (2, 3), 0 for any d <= 16.
 template <int DC>
 __global__ __launch_bounds__(256) void rank_direct_kernel(const float* __restrict__ Xs, int64_t n, int ldp, int dd,
-                                                          const uint64_t* __restrict__ probes,
+                                                          const uint64_t* __restrict__ probes, int64_t split_len,
                                                           uint32_t* __restrict__ counts)
 {
-    // the canonical sums round every square and every sum: no fused forms
-#pragma clang fp contract(off)
     const int d = DC ? DC : dd;
     constexpr int DT = DC ? DC : kRankDirectD;   // coordinates held per row
-    __shared__ float tile[256][kRankDirectD + 1];
+    __shared__ float tile[256][DT + 1];
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t rbeg = (int64_t)blockIdx.y * split_len, rend = rbeg + split_len < n ? rbeg + split_len : n;
     const bool live = q < n;
     float xq[DT];
 #pragma unroll
@@ -698,47 +725,111 @@ __global__ __launch_bounds__(256) void rank_direct_kernel(const float* __restric
         cnt[p] = 0u;
         if (pk[p] != kEmptyCand) mx = key_d2(pk[p]);
     }
-    for (int64_t r0 = 0; r0 < n; r0 += 256) {
+    for (int64_t r0 = rbeg; r0 < rend; r0 += 256) {
         __syncthreads();
         {
             const int64_t r = r0 + threadIdx.x;
 #pragma unroll
-            for (int t = 0; t < DT; ++t) tile[threadIdx.x][t] = r < n && t < d ? Xs[r * ldp + t] : 0.0f;
+            for (int t = 0; t < DT; ++t) tile[threadIdx.x][t] = r < rend && t < d ? Xs[r * ldp + t] : 0.0f;
         }
         __syncthreads();
-        const int nr = (int)(n - r0 < 256 ? n - r0 : 256);
-        for (int jj = 0; jj < nr; ++jj) {
-            // canonical order: partial t mod 16 holds coordinate t (d <= 16),
-            // then the tree at strides 8, 4, 2, 1
-            // (with d fixed, the terms known to be zero are left out: adding
-            // +0 to a square changes nothing)
-            float s[16];
+        const int nr = (int)(rend - r0 < 256 ? rend - r0 : 256);
+        // 8 references at a time: their distances first (the tile reads
+        // issued together), then the probe comparisons of those that can
+        // be below a probe
+        for (int j0 = 0; j0 < nr; j0 += 8) {
+            float d2[8];
 #pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                if (t < DT) {
-                    const float e = xq[t] - tile[jj][t];
-                    s[t] = t < d ? e * e : 0.0f;
+            for (int u = 0; u < 8; ++u) d2[u] = direct_d2<DT>(xq, tile[j0 + u < nr ? j0 + u : j0], d);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t m = r0 + j0 + u;
+                if (j0 + u < nr && d2[u] <= mx && m != q) {
+                    const uint64_t km = make_key(d2[u], (uint32_t)m);
+#pragma unroll
+                    for (int p = 0; p < kRankP; ++p) cnt[p] += km < pk[p] ? 1u : 0u;
                 }
-            }
-#pragma unroll
-            for (int j = 8; j > 0; j >>= 1) {
-#pragma unroll
-                for (int g = 0; g < j; ++g) {
-                    if (g + j < DT) s[g] = g < DT ? s[g] + s[g + j] : s[g + j];
-                }
-            }
-            const float d2 = s[0];
-            const int64_t m = r0 + jj;
-            if (d2 <= mx && m != q) {
-                const uint64_t km = make_key(d2, (uint32_t)m);
-#pragma unroll
-                for (int p = 0; p < kRankP; ++p) cnt[p] += km < pk[p] ? 1u : 0u;
             }
         }
     }
     if (live) {
 #pragma unroll
-        for (int p = 0; p < kRankP; ++p) counts[q * kRankP + p] = cnt[p];
+        for (int p = 0; p < kRankP; ++p) atomicAdd(&counts[q * kRankP + p], cnt[p]);   // the splits' counts add up
+    }
+}
+
+// Exact k-NN in a low-dimensional space (d <= kRankDirectD, e.g. a 2-D
+// embedding): there the norm expansion's error bound exceeds neighbour
+// distances, so GEMM certificates fail; instead every pair's canonical FP32
+// distance is formed directly (thread = query row, reference rows through
+// LDS, the canonical sum as in rank_direct_kernel) and each thread keeps
+// its KM smallest keys (canonical d2, index) in registers.  Workgroup
+// (query block, reference split) writes its sorted list, padded to kListW,
+// in the split-list layout merge_rerank_kernel merges.
+template <int DT, int DC, int KM>
+__global__ __launch_bounds__(256) void exact_direct_kernel(
+    const void* __restrict__ Q, int64_t ldq, int64_t nq, const void* __restrict__ R, int64_t ldr, int64_t nr,
+    int dd, const int32_t* __restrict__ q_self, int self_mode, int64_t self_base, int k, int64_t split_len, int S,
+    uint64_t* __restrict__ part)
+{
+    const int d = DC ? DC : dd;
+    constexpr int DT_ = DC ? DC : kRankDirectD;
+    __shared__ float tile[256][DT_ + 1];
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int s = blockIdx.y;
+    const int64_t rbeg = (int64_t)s * split_len, rend = rbeg + split_len < nr ? rbeg + split_len : nr;
+    const bool live = q < nq;
+    const int64_t self = !live ? -1 : (self_mode == 1 ? self_base + q : (self_mode == 2 ? (int64_t)q_self[q] : -1));
+    float xq[DT_];
+#pragma unroll
+    for (int t = 0; t < DT_; ++t) xq[t] = live && t < d ? elem<DT>::ld(Q, q * ldq + t) : 0.0f;
+    uint64_t list[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) list[j] = kEmptyList;
+    uint64_t kth = kEmptyList;   // list[k - 1]
+    for (int64_t r0 = rbeg; r0 < rend; r0 += 256) {
+        __syncthreads();
+        {
+            const int64_t r = r0 + threadIdx.x;
+#pragma unroll
+            for (int t = 0; t < DT_; ++t) tile[threadIdx.x][t] = r < rend && t < d ? elem<DT>::ld(R, r * ldr + t) : 0.0f;
+        }
+        __syncthreads();
+        const int nt = (int)(rend - r0 < 256 ? rend - r0 : 256);
+        // 32 references at a time: first the gate against the list's k-th key
+        // as it stood (a bit per passing reference), then the passing ones
+        // inserted in index order, each re-tested against the current k-th
+        // key, so a wave runs as many insertion steps as its busiest lane
+        for (int j0 = 0; j0 < nt; j0 += 32) {
+            const int jn = nt - j0 < 32 ? nt - j0 : 32;
+            uint32_t mask = 0u;
+            for (int jj = 0; jj < jn; ++jj) {
+                const int64_t m = r0 + j0 + jj;
+                const uint64_t key = make_key(direct_d2<DT_>(xq, tile[j0 + jj], d), (uint32_t)m);
+                mask |= (key < kth && m != self) ? 1u << jj : 0u;
+            }
+            while (mask) {
+                const int jj = __builtin_ctz(mask);
+                mask &= mask - 1u;
+                const uint64_t key = make_key(direct_d2<DT_>(xq, tile[j0 + jj], d), (uint32_t)(r0 + j0 + jj));
+                if (key < kth) {
+                    // insertion into the ascending list; entries past k stay empty
+#pragma unroll
+                    for (int j = KM - 1; j >= 1; --j) {
+                        const uint64_t a = list[j - 1], b = list[j];
+                        list[j] = j < k ? (key < a ? a : (key < b ? key : b)) : b;
+                    }
+                    list[0] = key < list[0] ? key : list[0];
+#pragma unroll
+                    for (int j = 0; j < KM; ++j) kth = j == k - 1 ? list[j] : kth;
+                }
+            }
+        }
+    }
+    if (live) {
+        uint64_t* out = part + (q * S + s) * kListW;
+#pragma unroll
+        for (int c = 0; c < kListW; ++c) out[c] = c < KM ? list[c] : kEmptyList;
     }
 }
 
@@ -944,6 +1035,82 @@ static size_t exact_scratch(const knn_matrix& Q, const knn_matrix& R, bool same,
 // list.  A smaller budget means more chunks, each a pass over R: time for
 // memory.  self_mode 1 excludes reference row q for query q (Q == R);
 // self_mode 2 excludes q_self[q].
+// The exact path for d <= kRankDirectD in FP32: direct canonical distances
+// (exact_direct_kernel) over S reference splits, merged by
+// merge_rerank_kernel without a certificate (the lists are canonical).
+// Scratch: the split lists, S * kListW * 8 bytes per query row of a chunk.
+template <int DT>
+static void launch_exact_direct(int dc, int km, dim3 grid, hipStream_t st, const void* Qd, int64_t ldq,
+                                int64_t nq, const knn_matrix& R, const int32_t* qself, int self_mode,
+                                int64_t q0, int k, int64_t split_len, int S, uint64_t* part)
+{
+#define KNN_ED(DC, KM)                                                                                 \
+    exact_direct_kernel<DT, DC, KM><<<grid, 256, 0, st>>>(Qd, ldq, nq, R.data, R.ld, R.n, R.d, qself,  \
+                                                          self_mode, q0, k, split_len, S, part)
+    if (km == 16) {
+        if (dc == 2) KNN_ED(2, 16);
+        else if (dc == 3) KNN_ED(3, 16);
+        else KNN_ED(0, 16);
+    } else {
+        if (dc == 2) KNN_ED(2, 32);
+        else if (dc == 3) KNN_ED(3, 32);
+        else KNN_ED(0, 32);
+    }
+#undef KNN_ED
+}
+
+static knn_status exact_direct_impl(const knn_matrix& Q, const knn_matrix& R, const int32_t* q_self,
+                                    int self_mode, int32_t k, int32_t out_kind, int32_t* out_idx,
+                                    float* out_dist, hipStream_t st, ScratchAlloc& ws, int64_t budget)
+{
+    const int64_t nblk = ceil_div(Q.n, 256);
+    int S = (int)std::min<int64_t>(16, std::max<int64_t>(1, ceil_div(2048, nblk)));
+    S = (int)std::min<int64_t>(S, ceil_div(R.n, 256));
+    const int64_t split_len = round_up(ceil_div(R.n, S), 256);
+    S = (int)ceil_div(R.n, split_len);
+    const size_t per_row = (size_t)S * kListW * 8;
+    int64_t qc = Q.n;
+    if (budget > 0 && (size_t)round_up((int64_t)(qc * per_row), 256) > (size_t)budget) {
+        qc = (budget / (int64_t)per_row) / 256 * 256;
+        if (qc < 256)
+            return fail(KNN_ENOMEM, "workspace limit of " + std::to_string(budget) + " bytes is below the " +
+                                        std::to_string(256 * per_row) + " bytes one 256-query chunk needs");
+    }
+    uint64_t* part = nullptr;
+    knn_status r = ws.alloc(&part, (size_t)qc * S * kListW);
+    if (r != KNN_OK) return r;
+    const int km = k <= 16 ? 16 : 32;
+    const int dc = R.d == 2 || R.d == 3 ? R.d : 0;
+    const size_t qeb = elem_bytes(Q.dtype);
+    for (int64_t q0 = 0; q0 < Q.n; q0 += qc) {
+        const int64_t nq = Q.n - q0 < qc ? Q.n - q0 : qc;
+        const void* Qd = (const char*)Q.data + (size_t)q0 * Q.ld * qeb;
+        const int32_t* qself = self_mode == 2 ? q_self + q0 : nullptr;
+        const dim3 grid((unsigned)ceil_div(nq, 256), (unsigned)S);
+        if (Q.dtype == KNN_F32)
+            launch_exact_direct<KNN_F32>(dc, km, grid, st, Qd, Q.ld, nq, R, qself, self_mode, q0, k, split_len, S, part);
+        else if (Q.dtype == KNN_BF16)
+            launch_exact_direct<KNN_BF16>(dc, km, grid, st, Qd, Q.ld, nq, R, qself, self_mode, q0, k, split_len, S,
+                                          part);
+        else
+            launch_exact_direct<KNN_F16>(dc, km, grid, st, Qd, Q.ld, nq, R, qself, self_mode, q0, k, split_len, S,
+                                         part);
+        KNN_HIP(hipGetLastError());
+        int32_t* oi = out_idx + q0 * k;
+        float* od = out_dist + q0 * k;
+        const dim3 mgrid((unsigned)ceil_div(nq, 4));
+#define KNN_MR(DT)                                                                                       \
+    merge_rerank_kernel<DT><<<mgrid, 256, 0, st>>>(part, S, nq, k, k, Qd, Q.ld, R.data, R.ld, R.d, nullptr, \
+                                                   nullptr, 0.0f, 0.0f, 0, out_kind, oi, od, nullptr, nullptr)
+        if (Q.dtype == KNN_F32) KNN_MR(KNN_F32);
+        else if (Q.dtype == KNN_BF16) KNN_MR(KNN_BF16);
+        else KNN_MR(KNN_F16);
+#undef KNN_MR
+        KNN_HIP(hipGetLastError());
+    }
+    return KNN_OK;
+}
+
 static knn_status exact_impl(const knn_matrix& Q, const knn_matrix& R, bool same,
                              const int32_t* q_self, int self_mode, int32_t k, int32_t precision,
                              int32_t rerank_k, int32_t out_kind, int32_t* out_idx, float* out_dist,
@@ -966,6 +1133,8 @@ static knn_status exact_impl(const knn_matrix& Q, const knn_matrix& R, bool same
     // staged element kind: FP32, or the 16-bit type of the MFMA form
     const int kind = precision == KNN_PREC_BF16 ? KNN_BF16 : (precision == KNN_PREC_FP16 ? KNN_F16 : KNN_F32);
     const bool bf = kind != KNN_F32;
+    if (kind == KNN_F32 && R.d <= kRankDirectD)
+        return exact_direct_impl(Q, R, q_self, self_mode, k, out_kind, out_idx, out_dist, st, ws, budget);
 
     // query chunk: the largest multiple of the tile height that fits
     int64_t qc = Q.n;
@@ -1231,13 +1400,21 @@ static knn_status quality_impl(const knn_matrix& X, const knn_matrix& Y, int k, 
         }
     };
     auto rank_direct = [&](const float* Zs, int ldz, int dz, const uint64_t* pz, uint32_t* cz) {
-        const unsigned nb = (unsigned)ceil_div(n, 256);
+        // reference splits (counts added) so that enough waves hide the tile reads
+        const int64_t nb = ceil_div(n, 256);
+        int Sd = (int)std::min<int64_t>(16, std::max<int64_t>(1, ceil_div(2048, nb)));
+        Sd = (int)std::min<int64_t>(Sd, ceil_div(n, 256));
+        const int64_t sl = round_up(ceil_div(n, Sd), 256);
+        Sd = (int)ceil_div(n, sl);
+        zero_words_kernel<<<(unsigned)std::min<int64_t>(ceil_div(n * kRankP, 64), 4096), 64, 0, st>>>(cz,
+                                                                                                 n * kRankP);
+        const dim3 g((unsigned)nb, (unsigned)Sd);
         if (dz == 2)
-            rank_direct_kernel<2><<<nb, 256, 0, st>>>(Zs, n, ldz, dz, pz, cz);
+            rank_direct_kernel<2><<<g, 256, 0, st>>>(Zs, n, ldz, dz, pz, sl, cz);
         else if (dz == 3)
-            rank_direct_kernel<3><<<nb, 256, 0, st>>>(Zs, n, ldz, dz, pz, cz);
+            rank_direct_kernel<3><<<g, 256, 0, st>>>(Zs, n, ldz, dz, pz, sl, cz);
         else
-            rank_direct_kernel<0><<<nb, 256, 0, st>>>(Zs, n, ldz, dz, pz, cz);
+            rank_direct_kernel<0><<<g, 256, 0, st>>>(Zs, n, ldz, dz, pz, sl, cz);
     };
     if (X.d <= kRankDirectD)
         rank_direct((const float*)Xs, ldx, X.d, pu, cu);

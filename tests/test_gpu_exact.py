@@ -122,6 +122,26 @@ def test_query_form(orc):
     assert parity_ok(res), res
 
 
+@pytest.mark.parametrize("d,k", [(2, 15), (3, 32), (5, 20), (16, 7)])
+def test_low_dim_direct_path(orc, d, k):
+    """d <= 16 takes direct canonical distances over reference splits (no
+    GEMM): 30,000 rows (118 query blocks, 16 splits), sampled rows against the
+    oracle; the query form with excluded rows gives the same lists; BF16
+    storage of the same values gives the oracle's lists on those values."""
+    import paper_2603_04035_amd as knn
+    X = datagen.gmm_isotropic(n=30_000, d=d, seed=40 + d)
+    rows = datagen.sample_queries(30_000, 120, seed=d)
+    G, D, _ = _assert_parity(orc, X, k, rows=rows)
+    qi, qd = knn.knn_exact_query(_dev(X[rows]), _dev(X), k, q_self=rows.astype(np.int32))
+    assert np.array_equal(qi.cpu().numpy(), G[rows]) and np.array_equal(qd.cpu().numpy(), D[rows])
+    Xt = _dev(X, torch.bfloat16)
+    Xs = Xt.float().cpu().numpy()
+    idx, dist = knn.knn_exact(Xt, k)
+    O, _ = orc.exact_knn(Xs, k, rows=rows)
+    res = exact_parity(Xs, rows, idx.cpu().numpy()[rows], dist.cpu().numpy()[rows], O)
+    assert parity_ok(res), res
+
+
 def test_pixel_70k_sampled(orc):
     """70,000 x 784 pixel-like data at full size, 150 sampled rows checked."""
     X = datagen.pixel_like(n=70000, seed=0)

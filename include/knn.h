@@ -89,7 +89,9 @@ const char* knn_last_error(void);
  *             distances with FP32 accumulation.  Either way the best
  *             `rerank_k` candidates per row are re-ranked with FP32
  *             direct-difference distances, and FP32 rows whose candidate
- *             set cannot be certified are recomputed exhaustively.
+ *             set cannot be certified are recomputed exhaustively.  With
+ *             KNN_PREC_FP32 and d <= 16 no GEMM is run: every pair's
+ *             direct-difference distance is formed (the same lists).
  *  rerank_k   candidates kept per row before the re-rank, k <= rerank_k <=
  *             KNN_MAX_K (0 = min(2k, KNN_MAX_K)).
  *  out_idx    device, n x k int32.   out_dist  device, n x k float.
@@ -119,7 +121,9 @@ knn_status knn_exact_query(knn_matrix Q, knn_matrix R, const int32_t* q_self, in
  * section "Scaling Behavior").  0 = no limit (one chunk).  Results are those
  * of knn_exact_query.  Errors as knn_exact_query, plus KNN_ENOMEM when the
  * staged reference set and a single 128-query chunk exceed the limit, and
- * KNN_EINVAL for a negative limit.
+ * KNN_EINVAL for a negative limit.  (FP32 with d <= 16 stages nothing: a
+ * chunk is a multiple of 256 rows, each needing S * 256 bytes of split
+ * lists, S <= 16 reference splits.)
  */
 knn_status knn_exact_query_limited(knn_matrix Q, knn_matrix R, const int32_t* q_self, int32_t k,
                                    int32_t precision, int32_t rerank_k, int32_t out_kind,
@@ -139,8 +143,9 @@ knn_status knn_exact_query_limited(knn_matrix Q, knn_matrix R, const int32_t* q_
  * chunked to fit the array.  The caller passes inputs and outputs as for
  * knn_exact.  Limit: the staged copy of X (n * roundup(d, 32) * 4 bytes in
  * FP32, n * roundup(d, 64) * 2 in BF16) plus n * 4 bytes of norms and one
- * 128-query chunk (about 140 KB) must fit, e.g. n <= 240,000 at d = 50 FP32;
- * larger inputs get KNN_ENOMEM with the sizes in the message.  Every call on
+ * 128-query chunk (about 140 KB) must fit, e.g. n <= 240,000 at d = 50 FP32
+ * (FP32 with d <= 16 stages nothing and fits any n); larger inputs get
+ * KNN_ENOMEM with the sizes in the message.  Every call on
  * a device shares that device's array and leaves it holding its last
  * contents: calls that overlap on one device (other threads or streams)
  * race and must be serialised by the caller.  Other errors as knn_exact.

@@ -428,8 +428,9 @@ knn_status knn_quality(knn_matrix X, knn_matrix Y, int32_t k, int32_t* hits, int
  *  union of the lists and their transpose (entries of value 0 are kept).
  *  col and val must hold 2 n k entries; *nnz (host) receives the count.
  * Errors: KNN_EINVAL for null pointers, n < 2, k < 1 or k > n - 1, or an
- * entry of knn_idx out of range or equal to its row (detected after the
- * work; outputs unspecified); KNN_ENOTSUP for k > KNN_MAX_K or 2 n k >= 2^32.
+ * entry of knn_idx out of range, equal to its row or repeated in its row
+ * (detected after the work; outputs unspecified); KNN_ENOTSUP for
+ * k > KNN_MAX_K or 2 n k >= 2^32.
  */
 knn_status knn_fuzzy_graph(const int32_t* knn_idx, const float* knn_dist, int64_t n, int32_t k,
                            float* rho, float* sigma, float* weights, int64_t* row_ptr,

@@ -17,16 +17,20 @@
 //            (v_exp_f32), then polished by Newton steps on the sum in
 //            double, whose root it converges to quadratically from the FP32
 //            estimate; the weights are evaluated in double and rounded once.
-//            Each edge (i -> j) emits two entries: (row i, col j) and
-//            (row j, col i), both carrying w_ij, identified by their entry
-//            number 2e and 2e + 1.
-// 2. sort:   the entries are sorted by (row, col) with two stable LSD radix
-//            sorts (by column, then by row) on 32-bit keys with the entry
-//            number as payload; deterministic whatever the thread order.
-// 3. emit:   runs of equal (row, col) fold their values by the probabilistic
-//            union v <- v + x - v x (two entries: a + b - ab) in double; a
-//            scan over the run heads gives each unique entry its CSR slot,
-//            and the row boundaries give row_ptr.
+//            Each edge e = (i -> j) emits one entry keyed by its target j.
+// 2. sort:   the entries are sorted by target with a stable LSD radix sort
+//            (32-bit keys, the edge number as payload), so the edges into a
+//            row form one segment ordered by source: the row's transposed
+//            entries, already in column order.  Deterministic whatever the
+//            thread order.
+// 3. union:  one wave per row merges its own k entries (ranked by column in
+//            registers) with that segment: a column in both gets the
+//            probabilistic union a + b - ab (folded in double in the order
+//            of the entries' numbers, 2e for (i, j) and 2e' + 1 for the
+//            transposed (j, i) of e' = (j -> i)), the others keep their
+//            weight; each entry's CSR position follows from the counts of
+//            smaller columns on both sides.  A count pass and a scan over
+//            the rows give row_ptr, then the same pass writes the entries.
 #include <math.h>
 
 #include "knn_common.hpp"
@@ -55,8 +59,7 @@ __device__ inline float fz_sum32(const float (&x)[kFzMaxK], int k, float s)
 __global__ __launch_bounds__(256) void fuzzy_rows_kernel(
     const int32_t* __restrict__ idx, const float* __restrict__ dist, int64_t n, int k,
     float* __restrict__ rho_out, float* __restrict__ sigma_out, float* __restrict__ w_out,
-    uint32_t* __restrict__ colkey, uint32_t* __restrict__ rowkey, uint32_t* __restrict__ eid,
-    unsigned* __restrict__ bad)
+    uint32_t* __restrict__ tgtkey, uint32_t* __restrict__ eid, unsigned* __restrict__ bad)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -126,172 +129,202 @@ __global__ __launch_bounds__(256) void fuzzy_rows_kernel(
             const int32_t j = idx[e];
             const bool valid = j >= 0 && (int64_t)j < n && (int64_t)j != i;
             ok = ok && valid;
-            // entry 2e: (i, j); entry 2e + 1: (j, i); invalid edges sort last (row n)
-            colkey[2 * e] = valid ? (uint32_t)j : 0u;
-            rowkey[2 * e] = valid ? (uint32_t)i : (uint32_t)n;
-            colkey[2 * e + 1] = valid ? (uint32_t)i : 0u;
-            rowkey[2 * e + 1] = valid ? (uint32_t)j : (uint32_t)n;
-            eid[2 * e] = (uint32_t)(2 * e);
-            eid[2 * e + 1] = (uint32_t)(2 * e + 1);
+            // keyed by target; invalid edges sort last (key n)
+            tgtkey[e] = valid ? (uint32_t)j : (uint32_t)n;
+            eid[e] = (uint32_t)e;
         }
     }
     if (!ok) atomicOr(bad, 1u);
 }
 
-// keys of the second sort: the row of each entry in column order
-__global__ __launch_bounds__(256) void fuzzy_gather_kernel(const uint32_t* __restrict__ ids,
-                                                          const uint32_t* __restrict__ rowkey, int64_t m,
-                                                          uint32_t* __restrict__ out)
+// ------------------------------------------------------------------ union
+
+// in_ptr[r] = the first sorted position whose target is >= r, r = 0..n.
+__global__ __launch_bounds__(256) void fuzzy_inptr_kernel(const uint32_t* __restrict__ key, int64_t m, int64_t n,
+                                                          uint32_t* __restrict__ in_ptr)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < m) out[p] = rowkey[ids[p]];
-}
-
-// ------------------------------------------------------------------ emit
-
-constexpr int kFzThreads = 256, kFzItems = 8, kFzTile = kFzThreads * kFzItems;
-
-// (row, col) of sorted entry p; entries of invalid edges have row n
-__device__ inline void fz_entry(const uint32_t* ids, const int32_t* idx, int k, int64_t n, int64_t p,
-                                uint32_t& row, uint32_t& col)
-{
-    const uint32_t id = ids[p];
-    const int64_t e = id >> 1;
-    const int64_t i = e / k;
-    const int32_t j = idx[e];
-    const bool valid = j >= 0 && (int64_t)j < n && (int64_t)j != i;
-    if (!valid) {
-        row = (uint32_t)n;
-        col = 0;
-    } else if (id & 1u) {
-        row = (uint32_t)j;
-        col = (uint32_t)i;
-    } else {
-        row = (uint32_t)i;
-        col = (uint32_t)j;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < m; p += (int64_t)gridDim.x * 256) {
+        const int64_t r = key[p], prev = p > 0 ? (int64_t)key[p - 1] : -1;
+        for (int64_t rr = prev + 1; rr <= r; ++rr) in_ptr[rr] = (uint32_t)p;
+        if (p == m - 1)
+            for (int64_t rr = r + 1; rr <= n; ++rr) in_ptr[rr] = (uint32_t)m;
     }
 }
 
-__device__ inline bool fz_head(const uint32_t* ids, const int32_t* idx, int k, int64_t n, int64_t p,
-                               uint32_t& row, uint32_t& col)
-{
-    fz_entry(ids, idx, k, n, p, row, col);
-    if ((int64_t)row >= n) return false;
-    if (p == 0) return true;
-    uint32_t r0, c0;
-    fz_entry(ids, idx, k, n, p - 1, r0, c0);
-    return r0 != row || c0 != col;
-}
+__device__ inline uint32_t lane_u32(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+__device__ inline float lane_f32(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
 
-// Heads per tile of kFzTile sorted entries.
-__global__ __launch_bounds__(kFzThreads) void fuzzy_count_kernel(const uint32_t* __restrict__ ids,
-                                                                 const int32_t* __restrict__ idx, int k,
-                                                                 int64_t n, int64_t m,
-                                                                 uint32_t* __restrict__ tile_cnt)
+// One wave per row i.  Lanes r < k hold the row's own entries (i, idx_ir);
+// the transposed entries (i, j) of the edges j -> i are the segment
+// [in_ptr[i], in_ptr[i + 1]) of the sorted edges, in column order.  The
+// count pass (EMIT false) stores the union's size in cnt[i] and flags a
+// column repeated in a row's list; the emit pass writes the union at
+// row_ptr[i], columns ascending.
+template <bool EMIT>
+__global__ __launch_bounds__(256) void fuzzy_union_kernel(
+    const int32_t* __restrict__ idx, const float* __restrict__ w, int k, int64_t n,
+    const uint32_t* __restrict__ sorted_e, const uint32_t* __restrict__ in_ptr, uint32_t* __restrict__ cnt,
+    const int64_t* __restrict__ row_ptr, int32_t* __restrict__ col_out, float* __restrict__ val_out,
+    unsigned* __restrict__ bad)
 {
-    __shared__ uint32_t s[kFzThreads / 64];
-    uint32_t c = 0;
-    for (int it = 0; it < kFzItems; ++it) {
-        const int64_t p = (int64_t)blockIdx.x * kFzTile + it * kFzThreads + threadIdx.x;
-        uint32_t r, cl;
-        if (p < m && fz_head(ids, idx, k, n, p, r, cl)) ++c;
+    const int lane = threadIdx.x & 63;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
+        // own entries; an invalid one (reported by the rows kernel) takes no part
+        const int32_t jj = lane < k ? idx[i * k + lane] : -1;
+        const bool ov = jj >= 0 && (int64_t)jj < n && (int64_t)jj != i;
+        const uint32_t oc = ov ? (uint32_t)jj : 0xFFFFFFFFu;
+        const float ow = ov ? w[i * k + lane] : 0.0f;
+        uint32_t orank = 0;   // own entries with a smaller column
+        bool rep = false;     // an earlier lane holds the same column
+        for (int r = 0; r < k; ++r) {
+            const uint32_t c2 = lane_u32(oc, r);
+            orank += c2 < oc ? 1u : 0u;
+            rep = rep || (ov && r < lane && c2 == oc);
+        }
+        if (!EMIT && ballot(rep) && lane == 0) atomicOr(bad, 2u);
+        const int64_t b = in_ptr[i], e = in_ptr[i + 1];
+        // per own entry: its transposed partner (matched, with weight wm) and
+        // the transposed entries with a smaller column
+        bool om = false;
+        float wm = 0.0f;
+        uint32_t oless = 0;
+        for (int64_t c0 = b; c0 < e; c0 += 64) {
+            const int64_t p = c0 + lane;
+            const bool iv = p < e;
+            const uint32_t ed = iv ? sorted_e[p] : 0u;
+            const uint32_t ic = iv ? ed / (uint32_t)k : 0xFFFFFFFFu;
+            const float iw = iv ? w[ed] : 0.0f;
+            for (int r = 0; r < k; ++r) {
+                const uint32_t ocr = lane_u32(oc, r);
+                const uint64_t mb = ballot(iv && ic == ocr);
+                const uint64_t lt = ballot(iv && ic < ocr);
+                const float ws = lane_f32(iw, mb ? __builtin_ctzll(mb) : 0);
+                if (lane == r) {
+                    oless += (uint32_t)popc64(lt);
+                    if (mb) {
+                        om = true;
+                        wm = ws;
+                    }
+                }
+            }
+        }
+        const uint32_t nown = (uint32_t)popc64(ballot(ov)), nmatch = (uint32_t)popc64(ballot(om));
+        if (!EMIT) {
+            if (lane == 0) cnt[i] = nown + (uint32_t)(e - b) - nmatch;
+            continue;
+        }
+        const int64_t base = row_ptr[i];
+        uint32_t mless = 0;   // matched own entries with a smaller column
+        for (int r = 0; r < k; ++r) {
+            const uint32_t c2 = lane_u32(oc, r), m2 = lane_u32(om ? 1u : 0u, r);
+            mless += m2 && c2 < oc ? 1u : 0u;
+        }
+        if (ov) {
+            const int64_t pos = base + orank + oless - mless;
+            col_out[pos] = (int32_t)oc;
+            float v = ow;
+            if (om) {
+                // entry 2e of (i, j) precedes entry 2e' + 1 of (j, i) iff i < j
+                const double x[2] = {(double)((int64_t)i < (int64_t)oc ? ow : wm),
+                                     (double)((int64_t)i < (int64_t)oc ? wm : ow)};
+                double u = 0.0;
+                for (int t = 0; t < 2; ++t) u = u + x[t] - u * x[t];
+                v = (float)u;
+            }
+            val_out[pos] = v;
+        }
+        // transposed entries without a partner: position = their index in the
+        // segment plus the unmatched own entries with a smaller column
+        for (int64_t c0 = b; c0 < e; c0 += 64) {
+            const int64_t p = c0 + lane;
+            const bool iv = p < e;
+            const uint32_t ed = iv ? sorted_e[p] : 0u;
+            const uint32_t ic = iv ? ed / (uint32_t)k : 0xFFFFFFFFu;
+            bool im = false;
+            uint32_t uless = 0;
+            for (int r = 0; r < k; ++r) {
+                const uint32_t ocr = lane_u32(oc, r), m2 = lane_u32(om ? 1u : 0u, r);
+                im = im || ic == ocr;
+                uless += !m2 && ocr < ic ? 1u : 0u;
+            }
+            if (iv && !im) {
+                const int64_t pos = base + (p - b) + uless;
+                col_out[pos] = (int32_t)ic;
+                val_out[pos] = w[ed];
+            }
+        }
     }
-    for (int o = 32; o > 0; o >>= 1) c += shfl_u32(c, (threadIdx.x & 63) ^ o);
-    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) tile_cnt[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
 }
 
-// Exclusive scan of the tile counts by one block (in order, with a carry);
-// tile_cnt[ntile] receives the total.
-__global__ __launch_bounds__(256) void fuzzy_scan_kernel(uint32_t* __restrict__ tile_cnt, int64_t ntile)
+// Row counts to row_ptr: per-block sums over 1024 rows, their exclusive scan
+// (fuzzy_scan_kernel, one block), then each block's rows.
+constexpr int kFzScanRows = 1024;
+
+// Exclusive scan of a[0..m) in place by one block (in order, with a
+// carry); a[m] receives the total.
+__global__ __launch_bounds__(256) void fuzzy_scan_kernel(uint32_t* __restrict__ a, int64_t m)
 {
     __shared__ uint32_t s[256];
     uint32_t carry = 0;
-    for (int64_t b0 = 0; b0 < ntile; b0 += 256) {
+    for (int64_t b0 = 0; b0 < m; b0 += 256) {
         const int64_t b = b0 + threadIdx.x;
-        const uint32_t x = b < ntile ? tile_cnt[b] : 0u;
+        const uint32_t x = b < m ? a[b] : 0u;
         __syncthreads();
         s[threadIdx.x] = x;
         __syncthreads();
-        for (int w = 1; w < 256; w <<= 1) {
-            const uint32_t y = (int)threadIdx.x >= w ? s[threadIdx.x - w] : 0u;
-            __syncthreads();
-            s[threadIdx.x] += y;
-            __syncthreads();
-        }
-        if (b < ntile) tile_cnt[b] = carry + s[threadIdx.x] - x;
-        carry += s[255];
-    }
-    if (threadIdx.x == 0) tile_cnt[ntile] = carry;
-}
-
-// Each head folds its run into one CSR entry at (tile offset + heads before
-// it in the tile) and fills row_ptr for the rows from the previous entry's
-// row (exclusive) up to its own; the last valid entry fills the rest.
-__global__ __launch_bounds__(kFzThreads) void fuzzy_emit_kernel(
-    const uint32_t* __restrict__ ids, const int32_t* __restrict__ idx, const float* __restrict__ w, int k,
-    int64_t n, int64_t m, const uint32_t* __restrict__ tile_off, int64_t* __restrict__ row_ptr,
-    int32_t* __restrict__ col_out, float* __restrict__ val_out)
-{
-    __shared__ uint32_t s[kFzThreads];
-    uint32_t run = tile_off[blockIdx.x];
-    const int64_t nnz = tile_off[gridDim.x];
-    for (int it = 0; it < kFzItems; ++it) {
-        const int64_t p = (int64_t)blockIdx.x * kFzTile + it * kFzThreads + threadIdx.x;
-        uint32_t row = 0, col = 0;
-        const bool head = p < m && fz_head(ids, idx, k, n, p, row, col);
-        __syncthreads();
-        s[threadIdx.x] = head ? 1u : 0u;
-        __syncthreads();
-        for (int o = 1; o < kFzThreads; o <<= 1) {
+        for (int o = 1; o < 256; o <<= 1) {
             const uint32_t y = (int)threadIdx.x >= o ? s[threadIdx.x - o] : 0u;
             __syncthreads();
             s[threadIdx.x] += y;
             __syncthreads();
         }
-        const uint32_t incl = s[threadIdx.x], total = s[kFzThreads - 1];
-        if (head) {
-            const int64_t o = (int64_t)run + incl - 1;
-            double v = 0.0;
-            int64_t q = p;
-            for (;;) {
-                const double x = (double)w[ids[q] >> 1];
-                v = v + x - v * x;
-                ++q;
-                if (q >= m) break;
-                uint32_t r2, c2;
-                fz_entry(ids, idx, k, n, q, r2, c2);
-                if (r2 != row || c2 != col) break;
-            }
-            col_out[o] = (int32_t)col;
-            val_out[o] = (float)v;
-            // rows after the previous entry's row, up to this one, start here
-            int64_t prev = -1;
-            if (p > 0) {
-                uint32_t r0, c0;
-                fz_entry(ids, idx, k, n, p - 1, r0, c0);
-                prev = (int64_t)r0;
-            }
-            for (int64_t rr = prev + 1; rr <= (int64_t)row; ++rr) row_ptr[rr] = o;
-            // the last valid entry closes the remaining rows
-            bool last = q >= m;
-            if (!last) {
-                uint32_t r2, c2;
-                fz_entry(ids, idx, k, n, q, r2, c2);
-                last = (int64_t)r2 >= n;
-            }
-            if (last)
-                for (int64_t rr = (int64_t)row + 1; rr <= n; ++rr) row_ptr[rr] = nnz;
-        }
-        run += total;
+        if (b < m) a[b] = carry + s[threadIdx.x] - x;
+        carry += s[255];
     }
+    if (threadIdx.x == 0) a[m] = carry;
 }
 
-__global__ __launch_bounds__(256) void fill_i64_kernel(int64_t* __restrict__ p, int64_t m, int64_t v)
+__global__ __launch_bounds__(256) void fuzzy_block_sum_kernel(const uint32_t* __restrict__ cnt, int64_t n,
+                                                              uint32_t* __restrict__ bsum)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
+    __shared__ uint32_t s[4];
+    uint32_t t = 0;
+    for (int q = 0; q < 4; ++q) {
+        const int64_t i = (int64_t)blockIdx.x * kFzScanRows + threadIdx.x * 4 + q;
+        t += i < n ? cnt[i] : 0u;
+    }
+    for (int o = 32; o > 0; o >>= 1) t += shfl_u32(t, (threadIdx.x & 63) ^ o);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) bsum[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
+}
+
+__global__ __launch_bounds__(256) void fuzzy_rowptr_kernel(const uint32_t* __restrict__ cnt, int64_t n,
+                                                           const uint32_t* __restrict__ boff, int64_t nb,
+                                                           int64_t* __restrict__ row_ptr)
+{
+    __shared__ uint32_t s[256];
+    uint32_t c[4], t = 0;
+    for (int q = 0; q < 4; ++q) {
+        const int64_t i = (int64_t)blockIdx.x * kFzScanRows + threadIdx.x * 4 + q;
+        c[q] = i < n ? cnt[i] : 0u;
+        t += c[q];
+    }
+    s[threadIdx.x] = t;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const uint32_t y = (int)threadIdx.x >= o ? s[threadIdx.x - o] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += y;
+        __syncthreads();
+    }
+    int64_t run = (int64_t)boff[blockIdx.x] + s[threadIdx.x] - t;
+    for (int q = 0; q < 4; ++q) {
+        const int64_t i = (int64_t)blockIdx.x * kFzScanRows + threadIdx.x * 4 + q;
+        if (i < n) row_ptr[i] = run;
+        run += c[q];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) row_ptr[n] = boff[nb];
 }
 
 static int bits_for(int64_t v)   // bits to hold values 0..v
@@ -314,45 +347,46 @@ extern "C" knn_status knn_fuzzy_graph(const int32_t* knn_idx, const float* knn_d
         if (n < 2 || n >= (int64_t)0x7FFFFFFF) return fail(KNN_EINVAL, "n must satisfy 2 <= n < 2^31 - 1");
         if (k < 1 || (int64_t)k > n - 1) return fail(KNN_EINVAL, "k must satisfy 1 <= k <= n-1");
         if (k > kFzMaxK) return fail(KNN_ENOTSUP, "k above 32 is not supported by the fuzzy graph");
-        const int64_t m = 2 * n * (int64_t)k;
-        if (m >= ((int64_t)1 << 32)) return fail(KNN_ENOTSUP, "2 n k must be below 2^32");
+        const int64_t m = n * (int64_t)k;   // edges
+        if (2 * m >= ((int64_t)1 << 32)) return fail(KNN_ENOTSUP, "2 n k must be below 2^32");
         hipStream_t st = (hipStream_t)stream;
         Workspace ws(st, 0);
         knn_status r;
-        uint32_t *ck, *rk, *id, *k1, *v1, *counts, *tiles;
+        uint32_t *key, *eid, *k1, *v1, *counts, *inptr, *cnt, *bsum;
         unsigned* bad;
         float* w = weights;
-        const int64_t ntile = ceil_div(m, kFzTile);
-        if ((r = ws.alloc(&ck, (size_t)m)) != KNN_OK) return r;
-        if ((r = ws.alloc(&rk, (size_t)m)) != KNN_OK) return r;
-        if ((r = ws.alloc(&id, (size_t)m)) != KNN_OK) return r;
+        const int64_t nb = ceil_div(n, kFzScanRows);
+        if ((r = ws.alloc(&key, (size_t)m)) != KNN_OK) return r;
+        if ((r = ws.alloc(&eid, (size_t)m)) != KNN_OK) return r;
         if ((r = ws.alloc(&k1, (size_t)m)) != KNN_OK) return r;
         if ((r = ws.alloc(&v1, (size_t)m)) != KNN_OK) return r;
         if ((r = ws.alloc(&counts, radix_counts_words(m))) != KNN_OK) return r;
-        if ((r = ws.alloc(&tiles, (size_t)ntile + 1)) != KNN_OK) return r;
+        if ((r = ws.alloc(&inptr, (size_t)n + 1)) != KNN_OK) return r;
+        if ((r = ws.alloc(&cnt, (size_t)n)) != KNN_OK) return r;
+        if ((r = ws.alloc(&bsum, (size_t)nb + 1)) != KNN_OK) return r;
         if ((r = ws.alloc(&bad, 1)) != KNN_OK) return r;
         if (!w && (r = ws.alloc(&w, (size_t)n * k)) != KNN_OK) return r;
         KNN_HIP(hipMemsetAsync(bad, 0, 4, st));
-        fuzzy_rows_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(knn_idx, knn_dist, n, k, rho, sigma, w, ck,
-                                                                     rk, id, bad);
+        fuzzy_rows_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(knn_idx, knn_dist, n, k, rho, sigma, w, key,
+                                                                     eid, bad);
         KNN_HIP(hipGetLastError());
-        // by column (keys < n), then stably by row (keys <= n: invalid edges last)
-        uint32_t *a0 = ck, *b0 = id, *a1 = k1, *b1 = v1;
-        if ((r = radix_sort_bits(a0, b0, a1, b1, m, counts, st, bits_for(n - 1), 1)) != KNN_OK) return r;
-        // a1 is free scratch now: the row keys in column order
-        fuzzy_gather_kernel<<<(unsigned)ceil_div(m, 256), 256, 0, st>>>(b0, rk, m, a1);
-        uint32_t *c0 = a1, *d0 = b0, *c1 = a0, *d1 = b1;
-        if ((r = radix_sort_bits(c0, d0, c1, d1, m, counts, st, bits_for(n), 1)) != KNN_OK) return r;
-        fuzzy_count_kernel<<<(unsigned)ntile, kFzThreads, 0, st>>>(d0, knn_idx, k, n, m, tiles);
-        fuzzy_scan_kernel<<<1, 256, 0, st>>>(tiles, ntile);
-        fill_i64_kernel<<<(unsigned)std::min<int64_t>(ceil_div(n + 1, 256), 1024), 256, 0, st>>>(row_ptr, n + 1, 0);
-        fuzzy_emit_kernel<<<(unsigned)ntile, kFzThreads, 0, st>>>(d0, knn_idx, w, k, n, m, tiles, row_ptr, col, val);
+        // by target (keys <= n: invalid edges last), stably
+        if ((r = radix_sort_bits(key, eid, k1, v1, m, counts, st, bits_for(n), 1)) != KNN_OK) return r;
+        fuzzy_inptr_kernel<<<(unsigned)std::min<int64_t>(ceil_div(m, 256), 8192), 256, 0, st>>>(key, m, n, inptr);
+        const unsigned ugrid = (unsigned)std::min<int64_t>(ceil_div(n, 4), 65536);
+        fuzzy_union_kernel<false><<<ugrid, 256, 0, st>>>(knn_idx, w, k, n, eid, inptr, cnt, nullptr, nullptr,
+                                                         nullptr, bad);
+        fuzzy_block_sum_kernel<<<(unsigned)nb, 256, 0, st>>>(cnt, n, bsum);
+        fuzzy_scan_kernel<<<1, 256, 0, st>>>(bsum, nb);
+        fuzzy_rowptr_kernel<<<(unsigned)nb, 256, 0, st>>>(cnt, n, bsum, nb, row_ptr);
+        fuzzy_union_kernel<true><<<ugrid, 256, 0, st>>>(knn_idx, w, k, n, eid, inptr, cnt, row_ptr, col, val, bad);
         KNN_HIP(hipGetLastError());
         unsigned host[2] = {0, 0};
         KNN_HIP(hipMemcpyAsync(&host[0], bad, 4, hipMemcpyDeviceToHost, st));
-        KNN_HIP(hipMemcpyAsync(&host[1], tiles + ntile, 4, hipMemcpyDeviceToHost, st));
+        KNN_HIP(hipMemcpyAsync(&host[1], bsum + nb, 4, hipMemcpyDeviceToHost, st));
         KNN_HIP(hipStreamSynchronize(st));
-        if (host[0]) return fail(KNN_EINVAL, "knn_idx holds an entry out of range or equal to its row");
+        if (host[0] & 1u) return fail(KNN_EINVAL, "knn_idx holds an entry out of range or equal to its row");
+        if (host[0] & 2u) return fail(KNN_EINVAL, "knn_idx holds a column twice in one row");
         *nnz = (int64_t)host[1];
         return KNN_OK;
     } catch (...) {

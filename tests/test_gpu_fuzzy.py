@@ -7,7 +7,7 @@ FP32 roundings (rel 2^-22); the CSR pattern (row_ptr, col) identical; the
 union values within 1e-6 absolute (the GPU folds FP32-rounded weights in
 double).  Cases: a ragged 3,001-row mixture, rows that hit the no-root limit
 (duplicates, lattice ties), k = 1 and 32, the 1,000,000-row graph on sampled
-rows, and a graph with a self entry (rejected).
+rows, and graphs with a self entry or a repeated entry (rejected).
 """
 import numpy as np
 import pytest
@@ -92,3 +92,7 @@ def test_fuzzy_rejects_self_entry():
     with pytest.raises(knn.KnnError) as e:
         knn.fuzzy_graph(G, D)
     assert e.value.status == -1
+    G[17, 2] = G[17, 4]                                     # a column twice in one row
+    with pytest.raises(knn.KnnError) as e:
+        knn.fuzzy_graph(G, D)
+    assert e.value.status == -1 and "twice" in str(e.value)

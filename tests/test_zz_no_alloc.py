@@ -18,12 +18,14 @@ def _same(a, b):
     return torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
-def test_noalloc_matches_knn_exact_twice(orc, precision):
+@pytest.mark.parametrize("precision,d", [("fp32", 50), ("bf16", 50), ("fp32", 2)])
+def test_noalloc_matches_knn_exact_twice(orc, precision, d):
+    """d = 50: the GEMM path (part lists alone: 150K x 2 x 256 B > 64 MiB);
+    d = 2 in FP32: the direct path (split lists 150K x 4 x 256 B > 64 MiB)."""
     import paper_2603_04035_amd as knn
     from oracle.compare import exact_parity, parity_ok
-    big = datagen.gmm_isotropic(n=150_000, d=50, seed=3)     # part lists alone: 150K x 2 x 256 B > 64 MiB
-    small = datagen.gmm_isotropic(n=3_001, d=50, seed=4)
+    big = datagen.gmm_isotropic(n=150_000, d=d, seed=3)
+    small = datagen.gmm_isotropic(n=3_001, d=d, seed=4)
     for X in (big, small):
         print("noalloc case", X.shape, precision, flush=True)
         Xd = torch.from_numpy(X).cuda()

@@ -1372,11 +1372,12 @@ static knn_status quality_impl(const knn_matrix& X, const knn_matrix& Y, int k, 
     const int64_t nblk = ceil_div(n, kTileRows), ntile = nblk, slots = 2 * (int64_t)ncu;
     int S = 1;
     for (; S < kRankMaxSplits; ++S) {
-        const int64_t b = nblk * S;   // waves of resident workgroups: whole ones at least 90% of the last
+        const int64_t b = nblk * S;   // stop once the waves of resident workgroups are 90% full on average
         if (b % slots == 0 || (double)b / (double)slots >= 0.9 * (double)ceil_div(b, slots)) break;
     }
     if (S > ntile) S = (int)ntile;
     const int64_t split_len = ceil_div(ntile, S) * kTileRows;
+    S = (int)ceil_div(n, split_len);   // no empty split
     const int64_t per_launch = kRankBlocks / S;   // query blocks per launch
     uint32_t* rq = nullptr;
     if ((X.d > kRankDirectD || Y.d > kRankDirectD) &&

@@ -6,8 +6,9 @@ FP32 rounding of the oracle's double root (rel 2^-23); weights within two
 FP32 roundings (rel 2^-22); the CSR pattern (row_ptr, col) identical; the
 union values within 1e-6 absolute (the GPU folds FP32-rounded weights in
 double).  Cases: a ragged 3,001-row mixture, rows that hit the no-root limit
-(duplicates, lattice ties), k = 1 and 32, the 1,000,000-row graph on sampled
-rows, and graphs with a self entry or a repeated entry (rejected).
+(duplicates, lattice ties), k = 1 and 32, rows listed by hundreds of others
+(a hand-built graph), the 1,000,000-row graph on sampled rows, and graphs
+with a self entry or a repeated entry (rejected).
 """
 import numpy as np
 import pytest
@@ -73,6 +74,22 @@ def test_fuzzy_k_extremes(orc, k):
     X = torch.from_numpy(datagen.gmm_anisotropic(n=2000, d=20, comps=5, seed=3)).cuda()
     G, D = knn.knn_exact(X, k)
     _check(orc, G, D)
+
+
+def test_fuzzy_hub_rows(orc):
+    """Rows listed by hundreds of others (a transposed segment of several
+    64-entry chunks), some of them listing those rows back: a hand-built
+    graph of 700 rows, k = 6, where every row lists rows 0, 1 and 2 and
+    three rows chosen at random (distinct, not itself, seed 11)."""
+    n, k = 700, 6
+    rng = np.random.default_rng(11)
+    G = np.empty((n, k), dtype=np.int32)
+    for i in range(n):
+        hubs = [h for h in (0, 1, 2) if h != i]
+        rest = rng.choice([j for j in range(3, n) if j != i], size=k - len(hubs), replace=False)
+        G[i] = np.concatenate([hubs, rest])
+    D = np.sort(rng.uniform(0.5, 2.0, size=(n, k)).astype(np.float32), axis=1)
+    _check(orc, torch.from_numpy(G).cuda(), torch.from_numpy(D).cuda())
 
 
 def test_fuzzy_1m_sampled(orc):

@@ -7,8 +7,9 @@ equal element for element, and the metrics built from them to 1e-12.  The
 metrics are also compared with the oracle's FP64 definition to 1e-5: the
 two differ only where two distances from one point tie within FP32
 rounding, each such pair moving a rank sum by one.  Cases: a ragged 3,001-row mixture with a noisy 2-D
-projection as the embedding (k = 10 and 15), k = 1 and 16, an integer
-lattice (every rank decided by index ties), and the 70,000 x 784 pixel-like
+projection as the embedding (k = 10 and 15), k = 1 and 16, points far from
+the origin (every pair re-decided canonically), an integer lattice (every
+rank decided by index ties), and the 70,000 x 784 pixel-like
 set on 64 sampled rows (its metrics against the oracle's per-row sums are
 not available at full size; the rows are)."""
 import numpy as np
@@ -49,6 +50,18 @@ def test_quality_mixture(orc, k):
     exp = orc.quality(X, Y, k)
     print("k", k, "gpu", m, "oracle fp64", exp, "one rank unit", z)
     assert np.allclose(m, exp, rtol=0, atol=1e-5)
+
+
+def test_quality_far_from_origin(orc):
+    """Points far from the origin (a mixture shifted by 1000 in every
+    coordinate): the Gram distance's error bound then exceeds every pair's
+    separation, so the rank pass re-decides every pair canonically (full
+    queues, many passes over each tile's rows)."""
+    X = np.ascontiguousarray((datagen.gmm_isotropic(n=1500, d=40, seed=12) + 1000.0).astype(np.float32))
+    Y = _embed(X - 1000.0, 3)
+    m, h, t, c = _run(X, Y, 10)
+    oh, ot, oc = orc.quality_rows(X, Y, 10, canonical=True)
+    assert np.array_equal(h, oh) and np.array_equal(t, ot) and np.array_equal(c, oc)
 
 
 def test_quality_lattice_ties(orc):

@@ -478,6 +478,7 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
     __shared__ int32_t sself[kTileRows];
     __shared__ float sgate[kTileRows], sqa[kTileRows], smx[kTileRows];
     __shared__ __attribute__((aligned(16))) uint64_t skey[kTileRows * kRankP];
+    __shared__ __attribute__((aligned(16))) float sthr[kTileRows * kRankP];   // the probes' distances (+inf: none)
     __shared__ uint32_t hist[kTileRows * (kRankP + 1)];
     __shared__ uint32_t qcount;   // queue fill
 
@@ -489,7 +490,9 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
     const float ra = sqrtf(__uint_as_float(*rmax_bits));
     for (int e = tid; e < kTileRows * kRankP; e += 256) {
         const int64_t qr = q0 + e / kRankP;
-        skey[e] = qr < nq ? probes[qr * kRankP + e % kRankP] : kEmptyCand;
+        const uint64_t key = qr < nq ? probes[qr * kRankP + e % kRankP] : kEmptyCand;
+        skey[e] = key;
+        sthr[e] = key == kEmptyCand ? __builtin_inff() : key_d2(key);
     }
     for (int e = tid; e < kTileRows * (kRankP + 1); e += 256) hist[e] = 0u;
     if (tid == 0) qcount = 0u;
@@ -547,14 +550,17 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
                     // reference norm, plus the canonical distance's
                     const float E = ec_dot * sqa[lr] * raj + ec_norm * (sqn[lr] + rnj);
                     const float sl = E + 2.0f * edir * (smx[lr] + E);
-                    const uint64_t* pk = skey + lr * kRankP;
+                    const f32x4* pt = (const f32x4*)(sthr + lr * kRankP);
+                    const float hi = d2 + sl, lo = d2 - sl;
                     int a = 0, b = 0;   // probes with thr <= d2 + sl, with thr < d2 - sl
 #pragma unroll
-                    for (int p = 0; p < kRankP; ++p) {
-                        const uint64_t key = pk[p];
-                        const float thr = key == kEmptyCand ? __builtin_inff() : key_d2(key);
-                        a += thr <= d2 + sl ? 1 : 0;
-                        b += thr < d2 - sl ? 1 : 0;
+                    for (int p4 = 0; p4 < kRankP / 4; ++p4) {
+                        const f32x4 t4 = pt[p4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            a += t4[e] <= hi ? 1 : 0;
+                            b += t4[e] < lo ? 1 : 0;
+                        }
                     }
                     // probes a.. have this row below them; b..a-1 are undecided
                     if (b == a && a < kRankP) atomicAdd(&hist[lr * (kRankP + 1) + a], 1u);

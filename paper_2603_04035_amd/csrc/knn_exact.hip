@@ -474,9 +474,8 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
     // column in tile << 17 | query row << 10 | a << 5 | b
     uint32_t* queue = gqueue + (int64_t)blockIdx.x * (kTileRows * kTileRows);
     __shared__ float srn[kTileRows];
-    __shared__ float sqn[kTileRows];
-    __shared__ int32_t sself[kTileRows];
-    __shared__ float sgate[kTileRows], sqa[kTileRows], smx[kTileRows];
+    __shared__ f32x4 srow[kTileRows];   // per query row: |q|^2, gate, excluded index (bits), |q|
+    __shared__ float smx[kTileRows];
     __shared__ __attribute__((aligned(16))) uint64_t skey[kTileRows * kRankP];
     __shared__ __attribute__((aligned(16))) float sthr[kTileRows * kRankP];   // the probes' distances (+inf: none)
     __shared__ uint32_t hist[kTileRows * (kRankP + 1)];
@@ -500,8 +499,7 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
     if (tid < kTileRows) {
         const int64_t qr = q0 + tid;
         const float sq = qr < nq ? qn[qr] : 0.0f;
-        sqn[tid] = sq;
-        sself[tid] = qr >= nq ? -1 : (self_mode == 1 ? (int32_t)(self_base + qr) : -1);
+        const int32_t self = qr >= nq ? -1 : (self_mode == 1 ? (int32_t)(self_base + qr) : -1);
         float mx = -1.0f;
         for (int p = 0; p < kRankP; ++p) {
             const uint64_t key = skey[tid * kRankP + p];
@@ -509,9 +507,10 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
         }
         const float qa = sqrtf(sq), E = ec_dot * qa * ra + ec_norm * (sq + ra * ra);
         const float sl = E + 2.0f * edir * (mx + E);
-        sqa[tid] = qa;
         smx[tid] = mx;
-        sgate[tid] = mx < 0.0f ? -1.0f : mx + sl;   // rows without probes never pass (largest reference norm)
+        // rows without probes never pass (the gate takes the largest reference norm)
+        const f32x4 ri = {sq, mx < 0.0f ? -1.0f : mx + sl, __int_as_float(self), qa};
+        srow[tid] = ri;
     }
 
     const float* Qe = Qs;
@@ -531,24 +530,28 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
         // used instead of being held in registers across the whole loop
         int lr0 = w * 32 + 4 * h, c0 = c;
         asm volatile("" : "+v"(lr0), "+v"(c0));
+        float rnj[4], raj[4];   // the lane's four reference columns: |r|^2, |r|
 #pragma unroll
         for (int blk = 0; blk < 4; ++blk) {
-            const f32x16 cur = acc[blk];
-            const int col = blk * 32 + c0;
-            const float rnj = srn[col];
-            const float raj = sqrtf(rnj);
-            const int64_t j = rt + col;
+            rnj[blk] = srn[blk * 32 + c0];
+            raj[blk] = sqrtf(rnj[blk]);
+        }
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int lr = lr0 + (mfma_row(v, 0));
-                float d2 = fmaf(-2.0f, cur[v], sqn[lr] + rnj);
+        for (int v = 0; v < 16; ++v) {
+            const int lr = lr0 + mfma_row(v, 0);
+            const f32x4 ri = srow[lr];   // the row's |q|^2, gate, excluded index, |q|
+#pragma unroll
+            for (int blk = 0; blk < 4; ++blk) {
+                const int col = blk * 32 + c0;
+                const int64_t j = rt + col;
+                float d2 = fmaf(-2.0f, acc[blk][v], ri[0] + rnj[blk]);
                 d2 = d2 > 0.0f ? d2 : 0.0f;
-                const bool pass = d2 <= sgate[lr] && j < rend && (int32_t)j != sself[lr];
+                const bool pass = d2 <= ri[1] && j < rend && (int32_t)j != __float_as_int(ri[2]);
                 if (!ballot(pass)) continue;
                 if (pass) {
                     // the slack of this pair: the GEMM bound with its own
                     // reference norm, plus the canonical distance's
-                    const float E = ec_dot * sqa[lr] * raj + ec_norm * (sqn[lr] + rnj);
+                    const float E = ec_dot * ri[3] * raj[blk] + ec_norm * (ri[0] + rnj[blk]);
                     const float sl = E + 2.0f * edir * (smx[lr] + E);
                     const f32x4* pt = (const f32x4*)(sthr + lr * kRankP);
                     const float hi = d2 + sl, lo = d2 - sl;

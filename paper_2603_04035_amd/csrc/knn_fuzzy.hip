@@ -157,15 +157,16 @@ __device__ inline float lane_f32(float v, int l) { return __int_as_float(__built
 // One wave per row i.  Lanes r < k hold the row's own entries (i, idx_ir);
 // the transposed entries (i, j) of the edges j -> i are the segment
 // [in_ptr[i], in_ptr[i + 1]) of the sorted edges, in column order.  The
-// count pass (EMIT false) stores the union's size in cnt[i] and flags a
-// column repeated in a row's list; the emit pass writes the union at
+// count pass (EMIT false) stores the union's size in cnt[i], flags a
+// column repeated in a row's list and keeps each own entry's partner and
+// count of smaller transposed columns; the emit pass writes the union at
 // row_ptr[i], columns ascending.
 template <bool EMIT>
 __global__ __launch_bounds__(256) void fuzzy_union_kernel(
     const int32_t* __restrict__ idx, const float* __restrict__ w, int k, int64_t n,
     const uint32_t* __restrict__ sorted_e, const uint32_t* __restrict__ in_ptr, uint32_t* __restrict__ cnt,
-    const int64_t* __restrict__ row_ptr, int32_t* __restrict__ col_out, float* __restrict__ val_out,
-    unsigned* __restrict__ bad)
+    uint32_t* __restrict__ own_less, float* __restrict__ own_wm, const int64_t* __restrict__ row_ptr,
+    int32_t* __restrict__ col_out, float* __restrict__ val_out, unsigned* __restrict__ bad)
 {
     const int lane = threadIdx.x & 63;
     for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
@@ -184,11 +185,19 @@ __global__ __launch_bounds__(256) void fuzzy_union_kernel(
         if (!EMIT && ballot(rep) && lane == 0) atomicOr(bad, 2u);
         const int64_t b = in_ptr[i], e = in_ptr[i + 1];
         // per own entry: its transposed partner (matched, with weight wm) and
-        // the transposed entries with a smaller column
+        // the transposed entries with a smaller column; found by the count
+        // pass, which keeps them per edge (oless | matched << 31, wm) for the
+        // emit pass
         bool om = false;
         float wm = 0.0f;
         uint32_t oless = 0;
-        for (int64_t c0 = b; c0 < e; c0 += 64) {
+        if (EMIT) {
+            const uint32_t ol = lane < k ? own_less[i * k + lane] : 0u;
+            om = ov && (ol >> 31) != 0u;
+            oless = ol & 0x7FFFFFFFu;
+            wm = lane < k ? own_wm[i * k + lane] : 0.0f;
+        }
+        for (int64_t c0 = b; c0 < (EMIT ? b : e); c0 += 64) {
             const int64_t p = c0 + lane;
             const bool iv = p < e;
             const uint32_t ed = iv ? sorted_e[p] : 0u;
@@ -211,6 +220,10 @@ __global__ __launch_bounds__(256) void fuzzy_union_kernel(
         const uint32_t nown = (uint32_t)popc64(ballot(ov)), nmatch = (uint32_t)popc64(ballot(om));
         if (!EMIT) {
             if (lane == 0) cnt[i] = nown + (uint32_t)(e - b) - nmatch;
+            if (lane < k) {
+                own_less[i * k + lane] = oless | (om ? 0x80000000u : 0u);
+                own_wm[i * k + lane] = wm;
+            }
             continue;
         }
         const int64_t base = row_ptr[i];
@@ -352,7 +365,8 @@ extern "C" knn_status knn_fuzzy_graph(const int32_t* knn_idx, const float* knn_d
         hipStream_t st = (hipStream_t)stream;
         Workspace ws(st, 0);
         knn_status r;
-        uint32_t *key, *eid, *k1, *v1, *counts, *inptr, *cnt, *bsum;
+        uint32_t *key, *eid, *k1, *v1, *counts, *inptr, *cnt, *bsum, *oless;
+        float* owm;
         unsigned* bad;
         float* w = weights;
         const int64_t nb = ceil_div(n, kFzScanRows);
@@ -364,6 +378,8 @@ extern "C" knn_status knn_fuzzy_graph(const int32_t* knn_idx, const float* knn_d
         if ((r = ws.alloc(&inptr, (size_t)n + 1)) != KNN_OK) return r;
         if ((r = ws.alloc(&cnt, (size_t)n)) != KNN_OK) return r;
         if ((r = ws.alloc(&bsum, (size_t)nb + 1)) != KNN_OK) return r;
+        if ((r = ws.alloc(&oless, (size_t)m)) != KNN_OK) return r;
+        if ((r = ws.alloc(&owm, (size_t)m)) != KNN_OK) return r;
         if ((r = ws.alloc(&bad, 1)) != KNN_OK) return r;
         if (!w && (r = ws.alloc(&w, (size_t)n * k)) != KNN_OK) return r;
         KNN_HIP(hipMemsetAsync(bad, 0, 4, st));
@@ -374,12 +390,13 @@ extern "C" knn_status knn_fuzzy_graph(const int32_t* knn_idx, const float* knn_d
         if ((r = radix_sort_bits(key, eid, k1, v1, m, counts, st, bits_for(n), 1)) != KNN_OK) return r;
         fuzzy_inptr_kernel<<<(unsigned)std::min<int64_t>(ceil_div(m, 256), 8192), 256, 0, st>>>(key, m, n, inptr);
         const unsigned ugrid = (unsigned)std::min<int64_t>(ceil_div(n, 4), 65536);
-        fuzzy_union_kernel<false><<<ugrid, 256, 0, st>>>(knn_idx, w, k, n, eid, inptr, cnt, nullptr, nullptr,
-                                                         nullptr, bad);
+        fuzzy_union_kernel<false><<<ugrid, 256, 0, st>>>(knn_idx, w, k, n, eid, inptr, cnt, oless, owm, nullptr,
+                                                         nullptr, nullptr, bad);
         fuzzy_block_sum_kernel<<<(unsigned)nb, 256, 0, st>>>(cnt, n, bsum);
         fuzzy_scan_kernel<<<1, 256, 0, st>>>(bsum, nb);
         fuzzy_rowptr_kernel<<<(unsigned)nb, 256, 0, st>>>(cnt, n, bsum, nb, row_ptr);
-        fuzzy_union_kernel<true><<<ugrid, 256, 0, st>>>(knn_idx, w, k, n, eid, inptr, cnt, row_ptr, col, val, bad);
+        fuzzy_union_kernel<true><<<ugrid, 256, 0, st>>>(knn_idx, w, k, n, eid, inptr, cnt, oless, owm, row_ptr, col,
+                                                        val, bad);
         KNN_HIP(hipGetLastError());
         unsigned host[2] = {0, 0};
         KNN_HIP(hipMemcpyAsync(&host[0], bad, 4, hipMemcpyDeviceToHost, st));

@@ -459,11 +459,13 @@ constexpr int kRankM = 16;   // queued pairs per thread in one pass over a tile'
 // coordinates g, g + 16, ... in order, then the fixed 16-lane tree, the sums
 // dist_g16 makes) and put them into the histogram.  No pair is decided any
 // other way.
+template <bool LISTS>
 __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
     const float* __restrict__ Qs, const float* __restrict__ qn, int64_t nq, const float* __restrict__ Rs,
     const float* __restrict__ rn, int64_t nr, int ldp, int d, int self_mode, int64_t self_base,
     const uint64_t* __restrict__ probes, const unsigned* __restrict__ rmax_bits, float ec_dot, float ec_norm,
-    float edir, int S, int64_t split_len, uint32_t* __restrict__ counts, uint32_t* __restrict__ gqueue)
+    float edir, int S, int64_t split_len, uint32_t* __restrict__ counts, uint32_t* __restrict__ gqueue, int kp,
+    uint64_t* __restrict__ part)
 {
     using C = TileCfg<KNN_F32>;
     constexpr int LROW = C::LROW, KC = C::KC, PER = KC / 2;
@@ -513,6 +515,21 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
         srow[tid] = ri;
     }
 
+    // With LISTS, the split's best kp keys (GEMM distance, index) of each
+    // query row as well, kept as exact_tile_kernel keeps them (lane (h, c)
+    // holds entry c of row 32 w + mfma_row(v, h)'s list) and written to part
+    // in its layout: the same pass gives the rows' exact k-NN after the
+    // merge, re-rank and certificate.  lthr is the list's kp-th distance
+    // (-inf for rows past nq, which take nothing).
+    uint64_t list[16];
+    float lthr[16];
+    if constexpr (LISTS) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            list[v] = kEmptyList;
+            lthr[v] = q0 + w * 32 + mfma_row(v, h) < nq ? __builtin_inff() : -__builtin_inff();
+        }
+    }
     const float* Qe = Qs;
     const float* Re = Rs;
     const int r = tid >> 1, ph = tid & 1;
@@ -546,6 +563,15 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
                 const int64_t j = rt + col;
                 float d2 = fmaf(-2.0f, acc[blk][v], ri[0] + rnj[blk]);
                 d2 = d2 > 0.0f ? d2 : 0.0f;
+                if constexpr (LISTS) {
+                    const bool okl = d2 <= lthr[v] && j < rend && (int32_t)j != __float_as_int(ri[2]);
+                    const uint64_t okm = ballot(okl);
+                    if (okm) {
+                        list[v] = list_add(list[v], okl ? make_key(d2, (uint32_t)j) : kEmptyCand, okm, lane);
+                        const uint64_t t0 = bcast_u64(list[v], kp - 1), t1 = bcast_u64(list[v], 32 + kp - 1);
+                        lthr[v] = key_d2(h ? t1 : t0);
+                    }
+                }
                 const bool pass = d2 <= ri[1] && j < rend && (int32_t)j != __float_as_int(ri[2]);
                 if (!ballot(pass)) continue;
                 if (pass) {
@@ -581,14 +607,14 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
         const int g = tid & 15;
         for (int base = 0; base < nqd; base += 16 * kRankM) {
             uint32_t qo[kRankM], ro[kRankM];
-            float part[kRankM];
+            float dsum[kRankM];
 #pragma unroll
             for (int m = 0; m < kRankM; ++m) {
                 const int e = base + (tid >> 4) + 16 * m;
                 const uint32_t ent = e < nqd ? queue[e] : 0u;
                 qo[m] = ((ent >> 10) & 127u) * LROW + g;
                 ro[m] = (ent >> 17) * LROW + g;
-                part[m] = 0.0f;
+                dsum[m] = 0.0f;
             }
             // the chunks pass through registers: chunk k0 + KC is loaded
             // while chunk k0's sums are formed
@@ -630,7 +656,7 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
                 for (int m = 0; m < kRankM; ++m) {
                     const float d0 = As[qo[m]] - Bs[ro[m]], d1 = As[qo[m] + 16] - Bs[ro[m] + 16];
                     const float e0 = lo ? d0 : 0.0f, e1 = hi ? d1 : 0.0f;
-                    part[m] = fmaf(e1, e1, fmaf(e0, e0, part[m]));
+                    dsum[m] = fmaf(e1, e1, fmaf(e0, e0, dsum[m]));
                 }
                 // the next chunk's loads belong to this step: issued before
                 // the sums above, not moved to the top of the next step
@@ -638,7 +664,7 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
             }
 #pragma unroll
             for (int m = 0; m < kRankM; ++m) {
-                const float dc = wave_sum16(part[m]);
+                const float dc = wave_sum16(dsum[m]);
                 const int e = base + (tid >> 4) + 16 * m;
                 if (e < nqd && g == 0) {
                     const uint32_t ent = queue[e];
@@ -658,6 +684,13 @@ __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
         }
         __syncthreads();   // the queue and the tile buffers are free for the next tile
         if (tid == 0) qcount = 0u;
+    }
+    if constexpr (LISTS) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int64_t row = q0 + w * 32 + mfma_row(v, h);
+            if (row < nq) part[(row * S + blockIdx.x % S) * kListW + c] = list[v];
+        }
     }
     __syncthreads();
     for (int e = tid; e < kTileRows * kRankP; e += 256) {
@@ -1265,18 +1298,20 @@ static knn_status exact_impl(const knn_matrix& Q, const knn_matrix& R, bool same
 // U = L \ N are the trustworthiness probes: their canonical FP32 distances
 // in X as keys; V = N \ L the continuity probes, keyed by their distances in
 // Y.  Both are sorted ascending and padded with kEmptyCand to kRankP (k <=
-// kRankP); hits[i] = |N intersect L|.
+// kRankP); hits[i] = |N intersect L|.  With all_l, U is all of L (N is not
+// needed; Hn may be null).  pu, pv and hits may each be null: that output
+// is not formed.
 __global__ __launch_bounds__(256) void quality_probes_kernel(int64_t n, int k, const int32_t* __restrict__ Hn,
                                                              const int32_t* __restrict__ Ln,
                                                              const float* __restrict__ Xs, int ldx, int dx,
                                                              const float* __restrict__ Ys, int ldy, int dy,
                                                              uint64_t* __restrict__ pu, uint64_t* __restrict__ pv,
-                                                             int32_t* __restrict__ hits)
+                                                             int32_t* __restrict__ hits, int all_l)
 {
     const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (i >= n) return;   // uniform across the wave
-    const int32_t hv = lane < k ? Hn[i * k + lane] : -1;
+    const int32_t hv = lane < k && Hn ? Hn[i * k + lane] : -1;
     const int32_t lv = lane < k ? Ln[i * k + lane] : -1;
     bool l_in_n = false, n_in_l = false;
     for (int r = 0; r < k; ++r) {
@@ -1285,7 +1320,10 @@ __global__ __launch_bounds__(256) void quality_probes_kernel(int64_t n, int k, c
         l_in_n |= lv == hr;
         n_in_l |= hv == lr;
     }
-    const bool inU = lane < k && !l_in_n, inV = lane < k && !n_in_l;
+    // all_l: every member of L(i) is a probe in X (no N(i) yet); a member
+    // of N(i) then has rank <= k and adds nothing to the trust sum.  A side
+    // whose output is null computes nothing; without Hn there is no V side
+    const bool inU = pu && lane < k && (all_l || !l_in_n), inV = Hn && lane < k && !n_in_l;
     const float du = dist_batch16<KNN_F32, 4>(Xs, ldx, i, (uint32_t)lv, inU, dx);
     const float dv = dist_batch16<KNN_F32, 4>(Ys, ldy, i, (uint32_t)hv, inV, dy);
     uint64_t ku = inU ? make_key(du, (uint32_t)lv) : kEmptyCand;
@@ -1293,11 +1331,11 @@ __global__ __launch_bounds__(256) void quality_probes_kernel(int64_t n, int k, c
     ku = seg_sort<16>(ku);
     kv = seg_sort<16>(kv);
     if (lane < kRankP) {
-        pu[i * kRankP + lane] = ku;
-        pv[i * kRankP + lane] = kv;
+        if (pu) pu[i * kRankP + lane] = ku;
+        if (pv) pv[i * kRankP + lane] = kv;
     }
-    const int nu = popc64(ballot(inU));
-    if (lane == 0) hits[i] = k - nu;
+    const int nv = popc64(ballot(inV));
+    if (hits && lane == 0) hits[i] = k - nv;   // |N & L| = k - |N \ L|
 }
 
 // Per row: trust = sum over U of (rank - k) = sum of (count + 1 - k), cont
@@ -1315,8 +1353,11 @@ __global__ __launch_bounds__(256) void quality_reduce_kernel(int64_t n, int k, c
     unsigned long long t = 0, c = 0, hsum = 0;
     if (i < n) {
         for (int p = 0; p < kRankP; ++p) {
-            if (pu[i * kRankP + p] != kEmptyCand) t += (unsigned long long)(cu[i * kRankP + p] + 1u - (uint32_t)k);
-            if (pv[i * kRankP + p] != kEmptyCand) c += (unsigned long long)(cv[i * kRankP + p] + 1u - (uint32_t)k);
+            // rank - k where the rank exceeds k (probes of rank <= k, members
+            // of both lists, add nothing)
+            const uint32_t ru = cu[i * kRankP + p] + 1u, rv = cv[i * kRankP + p] + 1u;
+            if (pu[i * kRankP + p] != kEmptyCand && ru > (uint32_t)k) t += (unsigned long long)(ru - (uint32_t)k);
+            if (pv[i * kRankP + p] != kEmptyCand && rv > (uint32_t)k) c += (unsigned long long)(rv - (uint32_t)k);
         }
         hsum = (unsigned long long)hits[i];
         if (trust_row) trust_row[i] = (int64_t)t;
@@ -1346,10 +1387,14 @@ static knn_status quality_impl(const knn_matrix& X, const knn_matrix& Y, int k, 
     if ((r = ws.alloc(&Ln, (size_t)n * k)) != KNN_OK) return r;
     if ((r = ws.alloc(&Hd, (size_t)n * k)) != KNN_OK) return r;
     if ((r = ws.alloc(&Ld, (size_t)n * k)) != KNN_OK) return r;
-    // exact lists in both spaces (FP32, canonical re-rank)
-    if ((r = exact_impl(X, X, true, nullptr, 1, k, KNN_PREC_FP32, 0, KNN_OUT_SQL2, Hn, Hd, st, ws, 0)) != KNN_OK)
-        return r;
+    // exact lists in both spaces (FP32, canonical re-rank).  Above
+    // kRankDirectD dimensions X's lists come from its rank pass (fused):
+    // the same Gram tiles give the ranks and the split lists
+    const bool fused = X.d > kRankDirectD;
     if ((r = exact_impl(Y, Y, true, nullptr, 1, k, KNN_PREC_FP32, 0, KNN_OUT_SQL2, Ln, Ld, st, ws, 0)) != KNN_OK)
+        return r;
+    if (!fused &&
+        (r = exact_impl(X, X, true, nullptr, 1, k, KNN_PREC_FP32, 0, KNN_OUT_SQL2, Hn, Hd, st, ws, 0)) != KNN_OK)
         return r;
     unsigned* small;   // [0] max norm of X, [1] max norm of Y; then three u64 totals
     if ((r = ws.alloc(&small, 8)) != KNN_OK) return r;
@@ -1367,8 +1412,15 @@ static knn_status quality_impl(const knn_matrix& X, const knn_matrix& Y, int k, 
     if ((r = ws.alloc(&cv, (size_t)n * kRankP)) != KNN_OK) return r;
     hits = hits_out;
     if (!hits && (r = ws.alloc(&hits, (size_t)n)) != KNN_OK) return r;
-    quality_probes_kernel<<<(unsigned)ceil_div(n, 4), 256, 0, st>>>(n, k, Hn, Ln, (const float*)Xs, ldx, X.d,
-                                                                    (const float*)Ys, ldy, Y.d, pu, pv, hits);
+    // X's probes: L(i) \ N(i), or every member of L(i) when N(i) is not
+    // known yet (fused); Y's probes N(i) \ L(i) and |N & L| once it is
+    if (fused)
+        quality_probes_kernel<<<(unsigned)ceil_div(n, 4), 256, 0, st>>>(n, k, nullptr, Ln, (const float*)Xs, ldx,
+                                                                        X.d, (const float*)Ys, ldy, Y.d, pu, nullptr,
+                                                                        nullptr, 1);
+    else
+        quality_probes_kernel<<<(unsigned)ceil_div(n, 4), 256, 0, st>>>(n, k, Hn, Ln, (const float*)Xs, ldx, X.d,
+                                                                        (const float*)Ys, ldy, Y.d, pu, pv, hits, 0);
     KNN_HIP(hipGetLastError());
     const float u = 5.9604645e-08f;
     // The tile pass: S reference splits, so that the workgroups fill the
@@ -1392,8 +1444,11 @@ static knn_status quality_impl(const knn_matrix& X, const knn_matrix& Y, int k, 
     if ((X.d > kRankDirectD || Y.d > kRankDirectD) &&
         (r = ws.alloc(&rq, (size_t)std::min<int64_t>(nblk, per_launch) * S * kTileRows * kTileRows)) != KNN_OK)
         return r;
+    const int kp = 2 * k < kListW ? 2 * k : kListW;   // the lists' re-rank width, as knn_exact's default
+    uint64_t* part = nullptr;
+    if (fused && (r = ws.alloc(&part, (size_t)n * S * kListW)) != KNN_OK) return r;
     auto rank_tile = [&](const float* Zs, const float* zn, int ldz, int dz, const uint64_t* pz, const unsigned* mx,
-                         uint32_t* cz) {
+                         uint32_t* cz, uint64_t* lists) {
         // GEMM distance error: 2 gamma_d |q| |r| for the FP32 dot product
         // plus 2u (|q|^2 + |r|^2) for the norms (FP64 sums rounded once)
         // and their sum; the canonical distance's own error (edir) carries
@@ -1404,9 +1459,15 @@ static knn_status quality_impl(const knn_matrix& X, const knn_matrix& Y, int k, 
                                                                                                  n * kRankP);
         for (int64_t q0 = 0; q0 < n; q0 += per_launch * kTileRows) {
             const int64_t nq = std::min<int64_t>(n - q0, per_launch * kTileRows);
-            rank_tile_kernel<<<(unsigned)(ceil_div(nq, kTileRows) * S), 256, 0, st>>>(
-                Zs + q0 * ldz, zn + q0, nq, Zs, zn, n, ldz, dz, 1, q0, pz + q0 * kRankP, mx, ecd, ecn, ed, S, split_len,
-                cz + q0 * kRankP, rq);
+            const unsigned g = (unsigned)(ceil_div(nq, kTileRows) * S);
+            if (lists)
+                rank_tile_kernel<true><<<g, 256, 0, st>>>(Zs + q0 * ldz, zn + q0, nq, Zs, zn, n, ldz, dz, 1, q0,
+                                                          pz + q0 * kRankP, mx, ecd, ecn, ed, S, split_len,
+                                                          cz + q0 * kRankP, rq, kp, lists + q0 * S * kListW);
+            else
+                rank_tile_kernel<false><<<g, 256, 0, st>>>(Zs + q0 * ldz, zn + q0, nq, Zs, zn, n, ldz, dz, 1, q0,
+                                                           pz + q0 * kRankP, mx, ecd, ecn, ed, S, split_len,
+                                                           cz + q0 * kRankP, rq, kp, nullptr);
         }
     };
     auto rank_direct = [&](const float* Zs, int ldz, int dz, const uint64_t* pz, uint32_t* cz) {
@@ -1426,14 +1487,42 @@ static knn_status quality_impl(const knn_matrix& X, const knn_matrix& Y, int k, 
         else
             rank_direct_kernel<0><<<g, 256, 0, st>>>(Zs, n, ldz, dz, pz, sl, cz);
     };
-    if (X.d <= kRankDirectD)
+    if (!fused) {
         rank_direct((const float*)Xs, ldx, X.d, pu, cu);
-    else
-        rank_tile((const float*)Xs, xn, ldx, X.d, pu, small, cu);
+    } else {
+        rank_tile((const float*)Xs, xn, ldx, X.d, pu, small, cu, part);
+        KNN_HIP(hipGetLastError());
+        // X's exact lists from the split lists: merge, canonical re-rank,
+        // certificate, and the exhaustive search for rows not certified
+        int32_t* fb_rows = nullptr;
+        int* fb_count = nullptr;
+        if ((r = ws.alloc(&fb_rows, (size_t)n)) != KNN_OK) return r;
+        if ((r = ws.alloc(&fb_count, 1)) != KNN_OK) return r;
+        zero_words_kernel<<<1, 64, 0, st>>>((unsigned*)fb_count, 1);
+        const float err_coef = (float)(X.d + 3) * u * 1.01f, edir = (float)(X.d / 16 + 8) * u;
+        const dim3 mgrid((unsigned)ceil_div(n, 4));
+#define KNN_QMR(DT)                                                                                            \
+    merge_rerank_kernel<DT><<<mgrid, 256, 0, st>>>(part, S, n, kp, k, X.data, X.ld, X.data, X.ld, X.d, xn, small, \
+                                                   err_coef, edir, 1, KNN_OUT_SQL2, Hn, Hd, fb_rows, fb_count);    \
+    exact_fallback_kernel<DT><<<1024, 256, 0, st>>>(fb_rows, fb_count, X.data, X.ld, X.data, X.ld, n, X.d, nullptr,  \
+                                                    1, 0, k, KNN_OUT_SQL2, Hn, Hd)
+        if (X.dtype == KNN_F32) {
+            KNN_QMR(KNN_F32);
+        } else if (X.dtype == KNN_BF16) {
+            KNN_QMR(KNN_BF16);
+        } else {
+            KNN_QMR(KNN_F16);
+        }
+#undef KNN_QMR
+        KNN_HIP(hipGetLastError());
+        quality_probes_kernel<<<(unsigned)ceil_div(n, 4), 256, 0, st>>>(n, k, Hn, Ln, (const float*)Xs, ldx, X.d,
+                                                                        (const float*)Ys, ldy, Y.d, nullptr, pv,
+                                                                        hits, 0);
+    }
     if (Y.d <= kRankDirectD)
         rank_direct((const float*)Ys, ldy, Y.d, pv, cv);
     else
-        rank_tile((const float*)Ys, yn, ldy, Y.d, pv, small + 1, cv);
+        rank_tile((const float*)Ys, yn, ldy, Y.d, pv, small + 1, cv, nullptr);
     KNN_HIP(hipGetLastError());
     unsigned long long* tot = (unsigned long long*)(small + 2);
     quality_reduce_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(n, k, pu, cu, pv, cv, hits, trust_out,

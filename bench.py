@@ -379,8 +379,9 @@ def pca_quality(X, p=50, k=10, reps=3):
                         "continuity": round(m[2], 5),
                         "roofline": {"bound": "mfma", "achieved": round(rank_tf, 2), "peak": 157.3, "unit": "TFLOP/s",
                                      "frac": round(rank_tf / 157.3, 4), "traffic": None,
-                                     "note": "2 n^2 d rank-pass flops / whole knn_quality call (it also runs two "
-                                             "exact k-NN searches)"}}}
+                                     "note": "2 n^2 d rank-pass flops / whole knn_quality call (the rank pass "
+                                             "also yields the exact k-NN in X; the call also runs the 2-D "
+                                             "exact k-NN and rank pass)"}}}
 
 
 def fuzzy_measure(G, D, reps=3):

@@ -6,12 +6,13 @@ canonical FP32 precision (the oracle's canonical mode), so they must be
 equal element for element, and the metrics built from them to 1e-12.  The
 metrics are also compared with the oracle's FP64 definition to 1e-5: the
 two differ only where two distances from one point tie within FP32
-rounding, each such pair moving a rank sum by one.  Cases: a ragged 3,001-row mixture with a noisy 2-D
-projection as the embedding (k = 10 and 15), k = 1 and 16, points far from
-the origin (every pair re-decided canonically), an integer lattice (every
-rank decided by index ties), and the 70,000 x 784 pixel-like
-set on 64 sampled rows (its metrics against the oracle's per-row sums are
-not available at full size; the rows are)."""
+rounding, each such pair moving a rank sum by one.  Cases: a ragged
+3,001-row mixture with a noisy 2-D projection as the embedding (k = 10 and
+15), k = 1 and 16, points far from the origin (every pair re-decided
+canonically), X in BF16 and FP16, an integer lattice (every rank decided by
+index ties), and the 70,000 x 784 pixel-like set on 64 sampled rows (its
+metrics against the oracle's per-row sums are not available at full size;
+the rows are)."""
 import numpy as np
 import pytest
 import torch
@@ -62,6 +63,20 @@ def test_quality_far_from_origin(orc):
     m, h, t, c = _run(X, Y, 10)
     oh, ot, oc = orc.quality_rows(X, Y, 10, canonical=True)
     assert np.array_equal(h, oh) and np.array_equal(t, ot) and np.array_equal(c, oc)
+
+
+@pytest.mark.parametrize("dt", [torch.bfloat16, torch.float16])
+def test_quality_half_input(orc, dt):
+    """X in BF16 / FP16 (the exact lists' re-rank reads X in its own type,
+    widened exactly to FP32): the terms equal the oracle's on X's values."""
+    import paper_2603_04035_amd as knn
+    X = torch.from_numpy(datagen.gmm_isotropic(n=1201, d=40, seed=21)).to(dt)
+    Xv = np.ascontiguousarray(X.float().numpy())
+    Y = _embed(Xv, 5)
+    m, (h, t, c) = knn.quality(X.cuda(), torch.from_numpy(Y).cuda(), 12, per_row=True)
+    oh, ot, oc = orc.quality_rows(Xv, Y, 12, canonical=True)
+    assert np.array_equal(h.cpu().numpy(), oh)
+    assert np.array_equal(t.cpu().numpy(), ot) and np.array_equal(c.cpu().numpy(), oc)
 
 
 def test_quality_lattice_ties(orc):

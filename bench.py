@@ -470,6 +470,9 @@ def main():
     ap.add_argument("--recall-rows", type=int, default=10000)
     ap.add_argument("--cpu-sample", type=int, default=50_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="only run the CPU oracle leg (no GPU) on the first --cpu-sample rows of --config; "
+                         "--cpu-sample 1000000 times the full 1M workload")
     ap.add_argument("--no-exact", action="store_true", help="skip the exact-path timing of the default line")
     ap.add_argument("--exact", action="store_true",
                     help="only time the exact path (knn_exact of the workload in FP32, BF16 and FP16, and FP32 "
@@ -491,6 +494,12 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": nbytes, "copies": 3}), flush=True)
+        return
+
+    if args.cpu_only:
+        Xnp = make_data(args.config)
+        cpu = cpu_baseline(Xnp, args.k, "fp32", min(args.cpu_sample, Xnp.shape[0]))
+        print(json.dumps({"cpu_baseline": cpu, "config": {"workload": CONFIGS[args.config]["desc"]}}), flush=True)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -197,7 +197,8 @@ def cpu_baseline(Xnp, k, form, sample_n, exact_queries=1000):
     return {"value": round(sample_n / dt, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
             "sample": f"sequential NNDescent (K_b={p['build_k']}, rho={p['sample_rate']}, delta={p['delta']}, "
                       f"the FP32 form's settings) on the first {sample_n} of the {Xnp.shape[0]} rows, "
-                      f"{dt:.1f} s, {iters} iterations; rate on the subset overstates the full workload's",
+                      f"{dt:.1f} s, {iters} iterations"
+                      + ("; rate on the subset overstates the full workload's" if sample_n < Xnp.shape[0] else ""),
             "recall_at_15": round(float(rec), 5), "host": host_cpu(),
             "exact_oracle": {"queries": exact_queries, "s": round(de, 2),
                              "queries_per_s": round(exact_queries / de, 1), "cores": host_cpu()["omp_threads"]

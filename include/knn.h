@@ -392,7 +392,9 @@ knn_status knn_pca(knn_matrix X, int32_t p, int32_t iters, float* Z, double* com
  * smaller index and are taken on canonical FP32 direct-difference squared
  * distances (the order knn_exact returns); the X-space distances come from
  * an FP32 MFMA Gram with every comparison inside its error bound re-decided
- * in the canonical precision.
+ * in the canonical precision.  Above 16 dimensions the same Gram pass also
+ * yields X's exact k-NN (knn_exact's merge, re-rank and certificate); the
+ * embedding's k-NN and ranks use direct differences when e <= 16.
  *  metrics  host, 3 doubles: k-NN preservation sum_i |N(i) & L(i)| / (n k);
  *           trustworthiness 1 - 2 / (n k (2n - 3k - 1)) sum_i sum_{j in
  *           L(i) \ N(i)} (r(i,j) - k); continuity, the same with N, L and r,

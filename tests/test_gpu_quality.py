@@ -10,9 +10,9 @@ rounding, each such pair moving a rank sum by one.  Cases: a ragged
 3,001-row mixture with a noisy 2-D projection as the embedding (k = 10 and
 15), k = 1 and 16, points far from the origin (every pair re-decided
 canonically), X in BF16 and FP16, an integer lattice (every rank decided by
-index ties), and the 70,000 x 784 pixel-like set on 64 sampled rows (its
+index ties), the 70,000 x 784 pixel-like set on 64 sampled rows (its
 metrics against the oracle's per-row sums are not available at full size;
-the rows are)."""
+the rows are), and 600,000 rows whose rank pass takes two launches."""
 import numpy as np
 import pytest
 import torch
@@ -102,6 +102,18 @@ def test_quality_pixel70k_sampled(orc):
     print("pixel70k quality", m)
     assert np.array_equal(h[rows], oh) and np.array_equal(t[rows], ot) and np.array_equal(c[rows], oc)
     assert 0.0 <= m[0] <= 1.0 and 0.0 < m[1] < 1.0 and 0.0 < m[2] < 1.0
+
+
+def test_quality_two_rank_launches(orc):
+    """600,000 x 24 rows: the X-space rank pass (which also keeps X's k-NN
+    lists) runs as two launches of query blocks, each writing its counts and
+    lists at its own offset; 64 sampled rows against the oracle."""
+    X = datagen.gmm_isotropic(n=600_000, d=24, comps=30, seed=31)
+    Y = _embed(X, 9)
+    m, h, t, c = _run(X, Y, 10)
+    rows = np.concatenate([datagen.sample_queries(600_000, 48, seed=6), [0, 524_287, 524_288, 599_999]])
+    oh, ot, oc = orc.quality_rows(X, Y, 10, rows=rows, canonical=True)
+    assert np.array_equal(h[rows], oh) and np.array_equal(t[rows], ot) and np.array_equal(c[rows], oc)
 
 
 def test_quality_rejects_bad_k():

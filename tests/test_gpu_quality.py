@@ -116,6 +116,19 @@ def test_quality_two_rank_launches(orc):
     assert np.array_equal(h[rows], oh) and np.array_equal(t[rows], ot) and np.array_equal(c[rows], oc)
 
 
+@pytest.mark.parametrize("n", [12, 50, 129])
+def test_quality_small_sets(orc, n):
+    """A partial tile (12 and 50 rows) and one row past a tile (129), 20-d
+    (the fused rank pass), k = 3: every per-row term against the oracle."""
+    X = datagen.gmm_isotropic(n=n, d=20, comps=3, seed=n)
+    Y = _embed(X, n + 1)
+    m, h, t, c = _run(X, Y, 3)
+    oh, ot, oc = orc.quality_rows(X, Y, 3, canonical=True)
+    assert np.array_equal(h, oh) and np.array_equal(t, ot) and np.array_equal(c, oc)
+    z = 2.0 / (n * 3 * (2.0 * n - 3.0 * 3 - 1.0))
+    assert np.allclose(m, (oh.sum() / (n * 3), 1.0 - z * ot.sum(), 1.0 - z * oc.sum()), rtol=0, atol=1e-12)
+
+
 def test_quality_rejects_bad_k():
     import paper_2603_04035_amd as knn
     X = torch.zeros((30, 4), device="cuda")

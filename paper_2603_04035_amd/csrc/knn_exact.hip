@@ -458,7 +458,11 @@ constexpr int kRankM = 16;   // queued pairs per thread in one pass over a tile'
 // groups sum the queued pairs' canonical FP32 distances from LDS (lane g:
 // coordinates g, g + 16, ... in order, then the fixed 16-lane tree, the sums
 // dist_g16 makes) and put them into the histogram.  No pair is decided any
-// other way.
+// other way.  With LISTS the pass also keeps, per query row and split, the
+// kp smallest GEMM keys (GEMM distance, index) as exact_tile_kernel does,
+// and writes them to part in its split-list layout (row-major over query
+// rows, then splits, kListW keys each), for merge_rerank_kernel; without
+// LISTS, kp and part are unused.
 template <bool LISTS>
 __global__ __launch_bounds__(256, 2) void rank_tile_kernel(
     const float* __restrict__ Qs, const float* __restrict__ qn, int64_t nq, const float* __restrict__ Rs,

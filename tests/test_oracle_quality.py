@@ -8,7 +8,10 @@ preservation, trustworthiness and continuity as the paper's section
 * swapping the roles of the two spaces swaps trustworthiness and
   continuity;
 * ranking by the canonical FP32 distance gives the FP64 result where no two
-  distances from a point are within FP32 error of each other.
+  distances from a point are within FP32 error of each other;
+* on lattices full of ties, the trust and continuity sums over L \ N (and
+  N \ L) equal the sums of (rank - k)+ over all of L (and N), from
+  brute-force ranks, and both equal the oracle's terms.
 """
 import numpy as np
 import pytest
@@ -73,3 +76,41 @@ def test_canonical_fp32_equals_fp64_without_near_ties(orc):
         b = orc.quality_rows(X, Y, k, canonical=True)
         for u, v in zip(a, b):
             assert np.array_equal(u, v)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_trust_sum_over_all_of_l(orc, seed):
+    """The identity the GPU's single X-space pass relies on: with ranks that
+    break ties by index, the members of N(i) are exactly the rows of rank
+    <= k, so sum over L(i) \\ N(i) of (r(i,j) - k) equals the sum over all of
+    L(i) of max(r(i,j) - k, 0) (likewise for continuity).  Ranks here are
+    brute force in FP64 with lexicographic (distance, index) order, on
+    inputs with repeated points so that ties occur; both sums are checked
+    against the oracle's per-row terms."""
+    rng = np.random.default_rng(seed)
+    n, k = 40, 4
+    X = rng.integers(0, 4, size=(n, 3)).astype(np.float64)    # a small lattice: many equal distances
+    Y = rng.integers(0, 5, size=(n, 2)).astype(np.float64)
+
+    def ranks(Z):
+        d = ((Z[:, None, :] - Z[None, :, :]) ** 2).sum(-1)
+        r = np.zeros((n, n), dtype=np.int64)
+        for i in range(n):
+            order = sorted((j for j in range(n) if j != i), key=lambda j: (d[i, j], j))
+            for pos, j in enumerate(order):
+                r[i, j] = pos + 1
+        return r
+
+    rx, ry = ranks(X), ranks(Y)
+    N = [set(np.nonzero((rx[i] >= 1) & (rx[i] <= k))[0]) for i in range(n)]
+    L = [set(np.nonzero((ry[i] >= 1) & (ry[i] <= k))[0]) for i in range(n)]
+    for i in range(n):
+        assert len(N[i]) == k and len(L[i]) == k
+    t_def = np.array([sum(rx[i, j] - k for j in L[i] - N[i]) for i in range(n)])
+    t_all = np.array([sum(max(rx[i, j] - k, 0) for j in L[i]) for i in range(n)])
+    c_def = np.array([sum(ry[i, j] - k for j in N[i] - L[i]) for i in range(n)])
+    c_all = np.array([sum(max(ry[i, j] - k, 0) for j in N[i]) for i in range(n)])
+    assert np.array_equal(t_def, t_all) and np.array_equal(c_def, c_all)
+    h, t, c = orc.quality_rows(X, Y, k)
+    assert np.array_equal(t, t_def) and np.array_equal(c, c_def)
+    assert np.array_equal(h, np.array([len(N[i] & L[i]) for i in range(n)]))
